@@ -1,0 +1,202 @@
+/*
+ * posetx — fast zeta and Möbius transforms on posets, MI355X (gfx950) native.
+ *
+ * C ABI of the library libposetx.so.  The operations follow Pegolotti,
+ * Seifert and Püschel, "Fast Möbius and Zeta Transforms":
+ *
+ *   zeta      g(x) = Σ_{y ⪯ x} f(y)                    (Theorem 1, Corollary 1, §2.2)
+ *   mobius    f(x) = Σ_{y ⪯ x} μ(y, x) g(y),  i.e. f = Z^{-1} g   (Theorem 1)
+ *   adjoints  Z^T and M^T = (Z^T)^{-1}: the same transforms on the dual order
+ *
+ * computed through the factorisation Z = U V of §3: V is the chain-wise
+ * prefix sum over a chain decomposition (Definition 1, §2.3) and U gathers,
+ * for every element x and chain j, the prefix of chain j ending at
+ * niv_j(x), the highest element of chain j below x (§2.4).  The Möbius
+ * transform solves U y' = g by substitution and then takes the first
+ * difference along every chain (V^{-1}, §3 and §4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - The poset is a DAG in CSR form: indices[indptr[u] .. indptr[u+1]) are the
+ *    children of u; an edge u -> v means v ⪯ u (§2.1).  Duplicate edges and
+ *    transitive edges are allowed, self-loops and cycles are errors.  The DAG
+ *    need not be connected.
+ *  - Function matrices are [n, B] row-major in NODE order: element (x, b) of a
+ *    matrix with leading dimension ld (in elements, ld >= B) sits at
+ *    ptr[x * ld + b].  They are DEVICE pointers on the poset's device and stay
+ *    owned by the caller.
+ *  - dtype PX_I64 computes in two's-complement int64 with wrap-around
+ *    (exact modulo 2^64); PX_F32 computes in float32 with compensated chain
+ *    scans and float64 accumulation of the gathered terms; PX_F64 in float64.
+ *  - Compute calls are asynchronous on `stream` (a hipStream_t, NULL = the
+ *    null stream) unless stated otherwise.  Argument errors are reported
+ *    synchronously; launch errors as PX_EHIP.  The poset handle owns a device
+ *    workspace that grows on demand (hipMalloc); call px_reserve() first to
+ *    keep later calls allocation-free, e.g. before HIP graph capture.  Calls
+ *    on one handle must be ordered (same stream or explicit synchronisation):
+ *    they share that workspace.
+ *  - Every call returns a px_status; px_last_error() gives a thread-local
+ *    message for the last failure on the calling thread.  No C++ exception
+ *    crosses this interface.
+ */
+#ifndef POSETX_H
+#define POSETX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct px_poset px_poset;
+typedef struct px_batch px_batch;
+
+typedef enum { PX_I64 = 0, PX_F32 = 1, PX_F64 = 2 } px_dtype;
+
+typedef enum {
+  PX_OK = 0,
+  PX_EINVAL = 1,        /* bad argument: sizes, ranges, self-loop, malformed chains   */
+  PX_ECYCLE = 2,        /* the edge list has a directed cycle                         */
+  PX_ECHAIN = 3,        /* a planted chain is not totally ordered by the DAG          */
+  PX_ENOMEM = 4,        /* host or device allocation failed                           */
+  PX_EHIP = 5,          /* a HIP runtime call or kernel launch failed                 */
+  PX_EUNSUPPORTED = 6,  /* operation not available for this handle or dtype           */
+  PX_ENONFINITE = 7,    /* refinement met a NaN or Inf residual                       */
+  PX_ENOTCONV = 8       /* refinement did not reach the tolerance                     */
+} px_status;
+
+/* px_poset_build flags */
+#define PX_BUILD_HOST_ONLY 0x1u      /* preprocess on the host only: no device buffers, no compute  */
+#define PX_BUILD_NO_ADJOINT 0x2u     /* skip the up-niv map and its levels (adjoints unavailable)   */
+#define PX_BUILD_LEVELS_MIRSKY 0x4u  /* schedule Möbius over Mirsky antichains (§4, Alg. 5/6)       */
+
+typedef struct {
+  int64_t n;              /* elements                                                   */
+  int64_t k;              /* chains in the decomposition                                */
+  int64_t edges;          /* CSR edges                                                  */
+  int64_t nnz_niv;        /* finite entries of niv, own chain included (nnz(N), §2.4)   */
+  int64_t nnz_niv_up;     /* the same for the up-niv map of the dual order             */
+  int64_t max_chain;      /* longest chain of the decomposition                         */
+  int64_t levels_down;    /* levels scheduling the Möbius solve                         */
+  int64_t levels_up;      /* levels scheduling the adjoint Möbius solve                 */
+  int64_t mirsky_levels;  /* length of the longest chain of the poset (Mirsky, §4)      */
+  int64_t udep_levels;    /* levels of the U-solve dependency DAG                       */
+  int64_t device_bytes;   /* device memory held by the handle, workspace excluded       */
+  int32_t chains_planted; /* 1 if the caller supplied the chains                        */
+  int32_t device;
+  double t_validate, t_chains, t_niv, t_levels, t_upload;  /* preprocessing seconds      */
+} px_info;
+
+typedef struct {
+  int32_t iterations;     /* refinement steps taken                                      */
+  int32_t nonfinite;      /* 1 if a residual held NaN or Inf                             */
+  double residual;        /* max over columns of ||g - zeta(f)||_inf / ||g||_inf (float64) */
+} px_refine_report;
+
+/*
+ * Build a poset handle (one-time preprocessing, §4: chain decomposition,
+ * niv map by the recursion of Theorem 5, levels; then upload).
+ *   n          elements, 0 <= n < 2^31
+ *   indptr     host, n+1 entries, indptr[0] = 0, non-decreasing
+ *   indices    host, indptr[n] entries in [0, n)
+ *   chain_of   host, n entries or NULL.  With chain_pos: a planted chain
+ *   chain_pos  decomposition, chain_of[x] in [0, k), positions 0..len-1 of
+ *              each chain used exactly once, position 0 the minimal element.
+ *              It is validated (PX_ECHAIN if a chain is not totally ordered).
+ *              NULL: chains come from a maximum matching on the edges
+ *              (Alg. 1, Hopcroft-Karp), a minimum path cover of the DAG.
+ *   flags      PX_BUILD_* bits
+ *   device     HIP device ordinal (ignored with PX_BUILD_HOST_ONLY)
+ *   out        receives the handle; free it with px_poset_free
+ * Host arrays are copied.  Synchronous.
+ */
+px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indices,
+                         const int32_t* chain_of, const int32_t* chain_pos, uint32_t flags,
+                         int device, px_poset** out);
+px_status px_poset_free(px_poset* p);
+px_status px_poset_info(const px_poset* p, px_info* out);
+
+/* Host copies of the preprocessing products, in NODE order (for inspection and tests).
+ *   chains: chain_of[n], chain_pos[n]
+ *   niv:    out[n * k]; out[x*k + j] = node id of niv_j(x), or -1 (the paper's ∞);
+ *           up != 0 gives the dual map: the lowest element of chain j above x.
+ *   levels: level[n] of every node in the Möbius schedule (up != 0: adjoint schedule). */
+px_status px_poset_chains(const px_poset* p, int32_t* chain_of, int32_t* chain_pos);
+px_status px_poset_niv(const px_poset* p, int up, int32_t* out);
+px_status px_poset_levels(const px_poset* p, int up, int32_t* level);
+
+/* Grow the workspace for dtype and B right-hand sides now, so that later calls with
+ * at most B columns allocate nothing.  Synchronous. */
+px_status px_reserve(px_poset* p, int dtype, int64_t B);
+
+/*
+ * g = Z f  (fast zeta transform, §3 Eq. zeta-fast / Alg. 3): chain-wise prefix sums
+ * followed by the niv gather-reduce.  f, g: device [n, B] with leading dims ldf, ldg.
+ * f == g (same pointer and ld) is allowed.  B >= 1.
+ */
+px_status px_zeta(px_poset* p, int dtype, const void* f, int64_t ldf, void* g, int64_t ldg,
+                  int64_t B, void* stream);
+
+/* out = Z^T w: chain-wise suffix sums and the up-niv gather (zeta on the dual order).
+ * Requires a handle built without PX_BUILD_NO_ADJOINT. */
+px_status px_zeta_adjoint(px_poset* p, int dtype, const void* w, int64_t ldw, void* out,
+                          int64_t ldo, int64_t B, void* stream);
+
+/*
+ * f = M g = Z^{-1} g  (fast Möbius transform, §3 and Alg. 4): level-scheduled solve
+ * of U y' = g, then f = V^{-1} y' (first difference along every chain).
+ *   PX_I64: exact; max_refine and tol are ignored.
+ *   PX_F64: float64 solve; no refinement.
+ *   PX_F32: float32 solve, then up to max_refine steps of iterative refinement
+ *           r = g - zeta(f) in float64, f += M r (float32 solve).  tol > 0 stops
+ *           early once ||r||_inf <= tol * ||g||_inf for every column; this check
+ *           synchronises the stream each step.  tol <= 0 runs exactly max_refine
+ *           steps with no host synchronisation.
+ *   rep        NULL or receives the refinement report; non-NULL synchronises.
+ * g and f must not overlap.  Returns PX_ENONFINITE if a residual is not finite, and
+ * PX_ENOTCONV if tol > 0 was not reached within max_refine steps (f is still written).
+ */
+px_status px_mobius(px_poset* p, int dtype, const void* g, int64_t ldg, void* f, int64_t ldf,
+                    int64_t B, int max_refine, double tol, void* stream, px_refine_report* rep);
+
+/* out = M^T v = (Z^T)^{-1} v: the Möbius transform of the dual order, same contract as
+ * px_mobius.  Requires a handle built without PX_BUILD_NO_ADJOINT. */
+px_status px_mobius_adjoint(px_poset* p, int dtype, const void* v, int64_t ldv, void* out,
+                            int64_t ldo, int64_t B, int max_refine, double tol, void* stream,
+                            px_refine_report* rep);
+
+/*
+ * Batches of independent posets of uneven size (all on one device).  A batch
+ * function matrix stacks the posets' [n_i, B] matrices in order: rows
+ * [o_i, o_i + n_i) belong to poset i, o_i = n_0 + ... + n_{i-1}.  Each batched
+ * call runs every poset in one launch per phase.  The batch keeps its own
+ * device copy of the posets' maps; the poset handles may be freed afterwards.
+ */
+px_status px_batch_build(int count, px_poset* const* posets, px_batch** out);
+px_status px_batch_free(px_batch* b);
+px_status px_batch_reserve(px_batch* b, int dtype, int64_t B);
+px_status px_batch_rows(const px_batch* b, int64_t* total_rows);
+px_status px_zeta_batched(px_batch* b, int dtype, const void* f, int64_t ldf, void* g,
+                          int64_t ldg, int64_t B, void* stream);
+px_status px_zeta_adjoint_batched(px_batch* b, int dtype, const void* w, int64_t ldw, void* out,
+                                  int64_t ldo, int64_t B, void* stream);
+
+/* Optional per-kernel timing.  px_profile(1) resets the totals and starts recording a
+ * pair of HIP events on the launch stream around every kernel launch of every handle;
+ * px_profile(0) stops.  px_profile_read synchronises on the recorded events and returns,
+ * for each of the first nphases phases, the summed milliseconds and the launch count.
+ * Phase names: px_profile_phase_name(i) (scan_reduce, scan_carry, scan_apply, gather,
+ * usolve_level, chain_diff, absmax).  Not for use under HIP graph capture. */
+px_status px_profile(int on);
+px_status px_profile_read(double* ms, int64_t* count, int nphases);
+const char* px_profile_phase_name(int i);
+
+/* Thread-local message of the last failure on this thread ("" if none). */
+const char* px_last_error(void);
+const char* px_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POSETX_H */

@@ -1,0 +1,721 @@
+// C ABI of libposetx (declared in include/posetx.h): poset handles, device
+// upload, workspaces and the drivers that sequence the kernels of one
+// transform on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "posetx.h"
+#include "prep.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+px_status fail(px_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Makes `dev` current for the scope of a call and restores the caller's device.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+template <typename T>
+hipError_t upload(T** dst, const T* src, size_t count, int64_t& bytes) {
+  *dst = nullptr;
+  if (count == 0) return hipSuccess;
+  hipError_t e = hipMalloc((void**)dst, count * sizeof(T));
+  if (e != hipSuccess) return e;
+  bytes += count * sizeof(T);
+  return hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+}
+
+size_t elem_size(int dtype) { return dtype == PX_F32 ? 4 : 8; }
+px::ElemType etype(int dtype) { return dtype == PX_I64 ? px::E_I64 : dtype == PX_F32 ? px::E_F32 : px::E_F64; }
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Grow-only device workspace.
+struct Workspace {
+  void* p = nullptr;
+  size_t bytes = 0;
+  px_status ensure(size_t need) {
+    if (need <= bytes) return PX_OK;
+    if (p) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(p);
+      p = nullptr;
+      bytes = 0;
+    }
+    if (hipMalloc(&p, need) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      return fail(PX_ENOMEM, "device workspace allocation of " + std::to_string(need) + " bytes failed");
+    }
+    bytes = need;
+    return PX_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+// Tile offsets of the chain scan for each of the 7 tile heights.
+void seg_tables(const std::vector<int32_t>& chain_off, std::vector<int32_t>& segoff, int64_t ntiles[7]) {
+  const int64_t nc = (int64_t)chain_off.size() - 1;
+  segoff.assign(7 * (nc + 1), 0);
+  for (int i = 0; i < 7; ++i) {
+    const int64_t seg = px::seg_rows(1 << i);
+    int32_t* so = &segoff[i * (nc + 1)];
+    for (int64_t c = 0; c < nc; ++c) {
+      int64_t len = chain_off[c + 1] - chain_off[c];
+      so[c + 1] = so[c] + (int32_t)((len + seg - 1) / seg);
+    }
+    ntiles[i] = so[nc];
+  }
+}
+
+struct Layout {
+  size_t y = 0, p64 = 0, r64 = 0, aux = 0, stats = 0, total = 0;
+};
+
+// Workspace layout of one call: a [n, B] matrix of the working type (P or Y),
+// for float32 refinement two float64 [n, B] matrices (P64 and the residual),
+// the scan's tile states and the refinement statistics.
+Layout layout(int64_t n, int64_t B, int dtype, bool refine, int64_t ntiles) {
+  Layout L;
+  size_t o = 0;
+  L.y = o;
+  o = align256(o + (size_t)n * B * elem_size(dtype));
+  if (refine) {
+    L.p64 = o;
+    o = align256(o + (size_t)n * B * 8);
+    L.r64 = o;
+    o = align256(o + (size_t)n * B * 8);
+  }
+  L.aux = o;
+  o = align256(o + (size_t)ntiles * B * 16 * 2);
+  L.stats = o;
+  o = align256(o + (size_t)(2 * B + 1) * 8);
+  L.total = o;
+  return L;
+}
+
+px_status hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return PX_OK;
+  return fail(PX_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Opt-in per-kernel timing with HIP events recorded on the launch stream
+// (px_profile / px_profile_read).  Off by default: then it costs one branch.
+namespace prof {
+enum Phase { SCAN_REDUCE = 0, SCAN_CARRY, SCAN_APPLY, GATHER, USOLVE, CHAIN_DIFF, ABSMAX, NPH };
+const char* const kNames[NPH] = {"scan_reduce", "scan_carry", "scan_apply", "gather",
+                                 "usolve_level", "chain_diff", "absmax"};
+std::mutex mu;
+std::atomic<bool> on{false};
+struct Rec {
+  int ph;
+  hipEvent_t a, b;
+};
+std::vector<Rec> pending;
+double ms[NPH];
+int64_t cnt[NPH];
+
+void drain() {
+  for (Rec& r : pending) {
+    float t = 0;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+      ms[r.ph] += t;
+      cnt[r.ph] += 1;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  pending.clear();
+}
+
+struct Scope {
+  int ph;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Scope(int p, hipStream_t st) : ph(p), s(st) {
+    if (on && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+  }
+  ~Scope() {
+    if (!a) return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) != hipSuccess) return;
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(mu);
+    pending.push_back({ph, a, b});
+  }
+};
+}  // namespace prof
+
+hipError_t run_scan(const px::DevPoset& d, int dir, px::ElemType tin, const void* x, int64_t ldx, px::ElemType tout,
+                    void* P, int64_t B, void* aux, int64_t nt, hipStream_t s) {
+  hipError_t e;
+  {
+    prof::Scope sc(prof::SCAN_REDUCE, s);
+    e = px::launch_chain_scan_phase(0, d, dir, tin, x, ldx, tout, P, B, aux, nt, s);
+  }
+  if (e != hipSuccess) return e;
+  {
+    prof::Scope sc(prof::SCAN_CARRY, s);
+    e = px::launch_chain_scan_phase(1, d, dir, tin, x, ldx, tout, P, B, aux, nt, s);
+  }
+  if (e != hipSuccess) return e;
+  prof::Scope sc(prof::SCAN_APPLY, s);
+  return px::launch_chain_scan_phase(2, d, dir, tin, x, ldx, tout, P, B, aux, nt, s);
+}
+
+hipError_t run_gather(const px::DevPoset& d, bool up, px::ElemType tp, const void* P, int64_t B, px::ElemType tout,
+                      void* out, int64_t ldo, px::ElemType tres, const void* resid, int64_t ldr, hipStream_t s) {
+  prof::Scope sc(prof::GATHER, s);
+  return px::launch_gather(d, up, tp, P, B, tout, out, ldo, tres, resid, ldr, s);
+}
+
+hipError_t run_chain_diff(const px::DevPoset& d, int dir, px::ElemType ty, const void* Y, int64_t B,
+                          px::ElemType tout, void* out, int64_t ldo, bool acc, hipStream_t s) {
+  prof::Scope sc(prof::CHAIN_DIFF, s);
+  return px::launch_chain_diff(d, dir, ty, Y, B, tout, out, ldo, acc, s);
+}
+
+}  // namespace
+
+struct px_poset {
+  px::Prep prep;
+  int device = 0;
+  bool host_only = false, has_up = false, mirsky = false;
+  int32_t *d_node_of_row = nullptr, *d_chain_of_row = nullptr, *d_chain_off = nullptr, *d_niv = nullptr,
+          *d_niv_up = nullptr, *d_lev_down = nullptr, *d_lev_up = nullptr, *d_segoff = nullptr;
+  int64_t ntiles[7] = {0, 0, 0, 0, 0, 0, 0};
+  px::DevPoset dp;
+  Workspace ws;
+  int64_t device_bytes = 0;
+  double t_upload = 0;
+};
+
+struct px_batch {
+  int device = 0;
+  int count = 0;
+  int64_t rows = 0;
+  bool has_up = false;
+  int32_t *d_node_of_row = nullptr, *d_chain_of_row = nullptr, *d_chain_off = nullptr, *d_niv = nullptr,
+          *d_niv_up = nullptr, *d_segoff = nullptr, *d_poset_of_row = nullptr, *d_k = nullptr, *d_row_off = nullptr;
+  int64_t* d_niv_off = nullptr;
+  int64_t ntiles[7] = {0, 0, 0, 0, 0, 0, 0};
+  px::DevPoset dp;
+  Workspace ws;
+};
+
+namespace {
+
+void free_poset_device(px_poset* p) {
+  int32_t* bufs[] = {p->d_node_of_row, p->d_chain_of_row, p->d_chain_off, p->d_niv,
+                     p->d_niv_up,      p->d_lev_down,     p->d_lev_up,    p->d_segoff};
+  for (int32_t* b : bufs)
+    if (b) (void)hipFree(b);
+  p->ws.release();
+}
+
+px_status check_matrix_args(int64_t n, int dtype, const void* a, int64_t lda, const void* b, int64_t ldb,
+                            int64_t B) {
+  if (dtype != PX_I64 && dtype != PX_F32 && dtype != PX_F64) return fail(PX_EINVAL, "unknown dtype");
+  if (B < 1) return fail(PX_EINVAL, "B must be >= 1");
+  if (B > (int64_t)65535 * 64) return fail(PX_EINVAL, "B too large");
+  if (lda < B || ldb < B) return fail(PX_EINVAL, "leading dimension smaller than B");
+  if (n > 0 && (!a || !b)) return fail(PX_EINVAL, "null function matrix");
+  return PX_OK;
+}
+
+// Level-scheduled solve U y' = g (Alg. 4, first loop; Alg. 5 schedule), one
+// launch per level so that every level sees the previous one complete.
+hipError_t solve_levels(const px_poset* p, bool up, px::ElemType tin, const void* g, int64_t ldg, px::ElemType ty,
+                        void* Y, int64_t B, hipStream_t s) {
+  const std::vector<int32_t>& ptr = up ? p->prep.lev_up_ptr : p->prep.lev_down_ptr;
+  const int32_t* rows = up ? p->d_lev_up : p->d_lev_down;
+  for (size_t l = 0; l + 1 < ptr.size(); ++l) {
+    prof::Scope sc(prof::USOLVE, s);
+    hipError_t e = px::launch_usolve_level(p->dp, up, rows + ptr[l], ptr[l + 1] - ptr[l], tin, g, ldg, ty, Y, B, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+px_status zeta_impl(px_poset* p, bool up, int dtype, const void* f, int64_t ldf, void* g, int64_t ldg, int64_t B,
+                    void* stream) {
+  if (!p) return fail(PX_EINVAL, "null poset");
+  if (p->host_only) return fail(PX_EUNSUPPORTED, "poset was built with PX_BUILD_HOST_ONLY");
+  if (up && !p->has_up) return fail(PX_EUNSUPPORTED, "poset was built with PX_BUILD_NO_ADJOINT");
+  px_status st = check_matrix_args(p->prep.n, dtype, f, ldf, g, ldg, B);
+  if (st != PX_OK) return st;
+  if (p->prep.n == 0) return PX_OK;
+  DeviceGuard dg(p->device);
+  if (!dg.ok) return fail(PX_EHIP, "hipSetDevice failed");
+  const int cw = px::col_width(B);
+  const int64_t nt = p->ntiles[px::seg_index(cw)];
+  Layout L = layout(p->prep.n, B, dtype, false, nt);
+  if ((st = p->ws.ensure(L.total)) != PX_OK) return st;
+  char* w = (char*)p->ws.p;
+  hipStream_t s = (hipStream_t)stream;
+  const px::ElemType T = etype(dtype);
+  hipError_t e = run_scan(p->dp, up ? -1 : 1, T, f, ldf, T, w + L.y, B, w + L.aux, nt, s);
+  if (e == hipSuccess) e = run_gather(p->dp, up, T, w + L.y, B, T, g, ldg, T, nullptr, 0, s);
+  return hip_status(e, "zeta launch");
+}
+
+px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ldg, void* f, int64_t ldf, int64_t B,
+                      int max_refine, double tol, void* stream, px_refine_report* rep) {
+  if (!p) return fail(PX_EINVAL, "null poset");
+  if (p->host_only) return fail(PX_EUNSUPPORTED, "poset was built with PX_BUILD_HOST_ONLY");
+  if (up && !p->has_up) return fail(PX_EUNSUPPORTED, "poset was built with PX_BUILD_NO_ADJOINT");
+  px_status st = check_matrix_args(p->prep.n, dtype, g, ldg, f, ldf, B);
+  if (st != PX_OK) return st;
+  if (max_refine < 0) return fail(PX_EINVAL, "max_refine must be >= 0");
+  const int64_t n = p->prep.n;
+  if (rep) *rep = px_refine_report{0, 0, 0.0};
+  if (n == 0) return PX_OK;
+  {
+    const char* gb = (const char*)g;
+    const char* fb = (const char*)f;
+    const size_t es = elem_size(dtype);
+    const char* ge = gb + ((n - 1) * ldg + B) * es;
+    const char* fe = fb + ((n - 1) * ldf + B) * es;
+    if (gb < fe && fb < ge) return fail(PX_EINVAL, "g and f must not overlap");
+  }
+  DeviceGuard dg(p->device);
+  if (!dg.ok) return fail(PX_EHIP, "hipSetDevice failed");
+  const bool refine = dtype == PX_F32;
+  const int cw = px::col_width(B);
+  const int64_t nt = p->ntiles[px::seg_index(cw)];
+  Layout L = layout(n, B, dtype, refine, nt);
+  if ((st = p->ws.ensure(L.total)) != PX_OK) return st;
+  char* w = (char*)p->ws.p;
+  hipStream_t s = (hipStream_t)stream;
+  const px::ElemType T = etype(dtype);
+  const int dir = up ? -1 : 1;
+  hipError_t e = solve_levels(p, up, T, g, ldg, T, w + L.y, B, s);
+  if (e == hipSuccess) e = run_chain_diff(p->dp, dir, T, w + L.y, B, T, f, ldf, false, s);
+  if (e != hipSuccess) return hip_status(e, "mobius launch");
+  if (!refine) return PX_OK;
+
+  const bool check = tol > 0 || rep;
+  double* r64 = (double*)(w + L.r64);
+  uint64_t* dstats = (uint64_t*)(w + L.stats);
+  std::vector<uint64_t> hstats(2 * B + 1);
+  // r = g - zeta(f) in float64; returns the normwise residual ratio (max over columns)
+  auto residual = [&](double& ratio, bool& nonfinite) -> px_status {
+    hipError_t e2 = run_scan(p->dp, dir, px::E_F32, f, ldf, px::E_F64, w + L.p64, B, w + L.aux, nt, s);
+    if (e2 == hipSuccess)
+      e2 = run_gather(p->dp, up, px::E_F64, w + L.p64, B, px::E_F64, r64, B, px::E_F32, g, ldg, s);
+    if (e2 != hipSuccess) return hip_status(e2, "residual launch");
+    if (!check) return PX_OK;
+    {
+      prof::Scope sc(prof::ABSMAX, s);
+      e2 = px::launch_absmax(n, B, r64, px::E_F32, g, ldg, dstats, s);
+    }
+    if (e2 == hipSuccess) e2 = hipMemcpyAsync(hstats.data(), dstats, hstats.size() * 8, hipMemcpyDeviceToHost, s);
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+    if (e2 != hipSuccess) return hip_status(e2, "residual statistics");
+    nonfinite = hstats[2 * B] != 0;
+    ratio = 0;
+    for (int64_t c = 0; c < B; ++c) {
+      double rn, gn;
+      std::memcpy(&rn, &hstats[c], 8);
+      std::memcpy(&gn, &hstats[B + c], 8);
+      ratio = std::max(ratio, gn > 0 ? rn / gn : rn);
+    }
+    return PX_OK;
+  };
+  int it = 0;
+  double ratio = 0;
+  bool nonfinite = false, converged = false;
+  for (; it < max_refine; ++it) {
+    if ((st = residual(ratio, nonfinite)) != PX_OK) return st;
+    if (check) {
+      if (nonfinite) break;
+      if (tol > 0 && ratio <= tol) {
+        converged = true;
+        break;
+      }
+    }
+    e = solve_levels(p, up, px::E_F64, r64, B, px::E_F32, w + L.y, B, s);
+    if (e == hipSuccess) e = run_chain_diff(p->dp, dir, px::E_F32, w + L.y, B, px::E_F32, f, ldf, true, s);
+    if (e != hipSuccess) return hip_status(e, "refinement launch");
+  }
+  if (check && !converged && !nonfinite) {
+    if ((st = residual(ratio, nonfinite)) != PX_OK) return st;
+    converged = tol > 0 && ratio <= tol;
+  }
+  if (rep) {
+    rep->iterations = it;
+    rep->nonfinite = nonfinite ? 1 : 0;
+    rep->residual = ratio;
+  }
+  if (nonfinite) return fail(PX_ENONFINITE, "refinement residual is not finite");
+  if (tol > 0 && !converged)
+    return fail(PX_ENOTCONV, "refinement stopped at residual " + std::to_string(ratio) + " > tol");
+  return PX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* px_last_error(void) { return g_err.c_str(); }
+
+px_status px_profile(int on) {
+  std::lock_guard<std::mutex> lk(prof::mu);
+  prof::drain();
+  for (int i = 0; i < prof::NPH; ++i) {
+    prof::ms[i] = 0;
+    prof::cnt[i] = 0;
+  }
+  prof::on = on != 0;
+  return PX_OK;
+}
+
+px_status px_profile_read(double* ms, int64_t* count, int nphases) {
+  if (nphases < 0 || (nphases > 0 && (!ms || !count))) return fail(PX_EINVAL, "bad profile buffers");
+  std::lock_guard<std::mutex> lk(prof::mu);
+  prof::drain();
+  for (int i = 0; i < nphases && i < prof::NPH; ++i) {
+    ms[i] = prof::ms[i];
+    count[i] = prof::cnt[i];
+  }
+  return PX_OK;
+}
+
+const char* px_profile_phase_name(int i) { return (i >= 0 && i < prof::NPH) ? prof::kNames[i] : ""; }
+const char* px_version(void) { return "posetx 0.1 (gfx950)"; }
+
+px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indices, const int32_t* chain_of,
+                         const int32_t* chain_pos, uint32_t flags, int device, px_poset** out) {
+  if (!out) return fail(PX_EINVAL, "null output handle");
+  *out = nullptr;
+  px_poset* p = new (std::nothrow) px_poset();
+  if (!p) return fail(PX_ENOMEM, "host allocation failed");
+  p->host_only = flags & PX_BUILD_HOST_ONLY;
+  p->has_up = !(flags & PX_BUILD_NO_ADJOINT);
+  p->mirsky = flags & PX_BUILD_LEVELS_MIRSKY;
+  p->device = device;
+  std::string msg;
+  int rc;
+  try {
+    rc = px::preprocess(n, indptr, indices, chain_of, chain_pos, p->has_up, p->mirsky, p->prep, msg);
+  } catch (const std::bad_alloc&) {
+    rc = PX_ENOMEM;
+    msg = "host allocation failed during preprocessing";
+  }
+  if (rc != PX_OK) {
+    delete p;
+    return fail((px_status)rc, msg);
+  }
+  std::vector<int32_t> segoff;
+  seg_tables(p->prep.chain_off, segoff, p->ntiles);
+  if (!p->host_only && n > 0) {
+    double t0 = now_s();
+    DeviceGuard dg(device);
+    if (!dg.ok) {
+      delete p;
+      return fail(PX_EHIP, "hipSetDevice(" + std::to_string(device) + ") failed");
+    }
+    const px::Prep& P = p->prep;
+    int64_t& b = p->device_bytes;
+    hipError_t e = upload(&p->d_node_of_row, P.node_of_row.data(), P.node_of_row.size(), b);
+    if (e == hipSuccess) e = upload(&p->d_chain_of_row, P.chain_of_row.data(), P.chain_of_row.size(), b);
+    if (e == hipSuccess) e = upload(&p->d_chain_off, P.chain_off.data(), P.chain_off.size(), b);
+    if (e == hipSuccess) e = upload(&p->d_niv, P.niv.data(), P.niv.size(), b);
+    if (e == hipSuccess && p->has_up) e = upload(&p->d_niv_up, P.niv_up.data(), P.niv_up.size(), b);
+    if (e == hipSuccess) e = upload(&p->d_lev_down, P.lev_down_rows.data(), P.lev_down_rows.size(), b);
+    if (e == hipSuccess && p->has_up) e = upload(&p->d_lev_up, P.lev_up_rows.data(), P.lev_up_rows.size(), b);
+    if (e == hipSuccess) e = upload(&p->d_segoff, segoff.data(), segoff.size(), b);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      free_poset_device(p);
+      delete p;
+      return fail(e == hipErrorOutOfMemory ? PX_ENOMEM : PX_EHIP,
+                  std::string("device upload failed: ") + hipGetErrorString(e));
+    }
+    p->t_upload = now_s() - t0;
+  }
+  px::DevPoset& d = p->dp;
+  d.n = (int32_t)n;
+  d.k = (int32_t)p->prep.k;
+  d.nchains = (int32_t)p->prep.k;
+  d.node_of_row = p->d_node_of_row;
+  d.chain_of_row = p->d_chain_of_row;
+  d.chain_off = p->d_chain_off;
+  d.niv = p->d_niv;
+  d.niv_up = p->d_niv_up;
+  d.segoff = p->d_segoff;
+  *out = p;
+  return PX_OK;
+}
+
+px_status px_poset_free(px_poset* p) {
+  if (!p) return PX_OK;
+  if (!p->host_only) {
+    DeviceGuard dg(p->device);
+    free_poset_device(p);
+  }
+  delete p;
+  return PX_OK;
+}
+
+px_status px_poset_info(const px_poset* p, px_info* o) {
+  if (!p || !o) return fail(PX_EINVAL, "null argument");
+  const px::Prep& P = p->prep;
+  o->n = P.n;
+  o->k = P.k;
+  o->edges = P.edges;
+  o->nnz_niv = P.nnz_niv;
+  o->nnz_niv_up = P.nnz_niv_up;
+  o->max_chain = P.max_chain;
+  o->levels_down = (int64_t)P.lev_down_ptr.size() - 1;
+  o->levels_up = (int64_t)P.lev_up_ptr.size() - 1;
+  o->mirsky_levels = P.mirsky;
+  o->udep_levels = P.udep;
+  o->device_bytes = p->device_bytes;
+  o->chains_planted = P.planted ? 1 : 0;
+  o->device = p->device;
+  o->t_validate = P.t_validate;
+  o->t_chains = P.t_chains;
+  o->t_niv = P.t_niv;
+  o->t_levels = P.t_levels;
+  o->t_upload = p->t_upload;
+  return PX_OK;
+}
+
+px_status px_poset_chains(const px_poset* p, int32_t* chain_of, int32_t* chain_pos) {
+  if (!p || (p->prep.n > 0 && (!chain_of || !chain_pos))) return fail(PX_EINVAL, "null argument");
+  std::copy(p->prep.chain_of.begin(), p->prep.chain_of.end(), chain_of);
+  std::copy(p->prep.chain_pos.begin(), p->prep.chain_pos.end(), chain_pos);
+  return PX_OK;
+}
+
+px_status px_poset_niv(const px_poset* p, int up, int32_t* out) {
+  if (!p || (p->prep.n > 0 && !out)) return fail(PX_EINVAL, "null argument");
+  if (up && !p->has_up) return fail(PX_EUNSUPPORTED, "poset was built with PX_BUILD_NO_ADJOINT");
+  const px::Prep& P = p->prep;
+  const std::vector<int32_t>& nv = up ? P.niv_up : P.niv;
+  for (int64_t x = 0; x < P.n; ++x) {
+    const int32_t* R = &nv[(size_t)P.row_of_node[x] * P.k];
+    for (int64_t j = 0; j < P.k; ++j) out[x * P.k + j] = R[j] >= 0 ? P.node_of_row[R[j]] : -1;
+  }
+  return PX_OK;
+}
+
+px_status px_poset_levels(const px_poset* p, int up, int32_t* level) {
+  if (!p || (p->prep.n > 0 && !level)) return fail(PX_EINVAL, "null argument");
+  if (up && !p->has_up) return fail(PX_EUNSUPPORTED, "poset was built with PX_BUILD_NO_ADJOINT");
+  const px::Prep& P = p->prep;
+  const std::vector<int32_t>& lev = up ? P.lev_up : P.lev_down;
+  for (int64_t x = 0; x < P.n; ++x) level[x] = lev[P.row_of_node[x]];
+  return PX_OK;
+}
+
+px_status px_reserve(px_poset* p, int dtype, int64_t B) {
+  if (!p) return fail(PX_EINVAL, "null poset");
+  if (p->host_only) return fail(PX_EUNSUPPORTED, "poset was built with PX_BUILD_HOST_ONLY");
+  if (dtype != PX_I64 && dtype != PX_F32 && dtype != PX_F64) return fail(PX_EINVAL, "unknown dtype");
+  if (B < 1) return fail(PX_EINVAL, "B must be >= 1");
+  DeviceGuard dg(p->device);
+  const int64_t nt = p->ntiles[px::seg_index(px::col_width(B))];
+  return p->ws.ensure(layout(p->prep.n, B, dtype, dtype == PX_F32, nt).total);
+}
+
+px_status px_zeta(px_poset* p, int dtype, const void* f, int64_t ldf, void* g, int64_t ldg, int64_t B, void* stream) {
+  return zeta_impl(p, false, dtype, f, ldf, g, ldg, B, stream);
+}
+
+px_status px_zeta_adjoint(px_poset* p, int dtype, const void* w, int64_t ldw, void* out, int64_t ldo, int64_t B,
+                          void* stream) {
+  return zeta_impl(p, true, dtype, w, ldw, out, ldo, B, stream);
+}
+
+px_status px_mobius(px_poset* p, int dtype, const void* g, int64_t ldg, void* f, int64_t ldf, int64_t B,
+                    int max_refine, double tol, void* stream, px_refine_report* rep) {
+  return mobius_impl(p, false, dtype, g, ldg, f, ldf, B, max_refine, tol, stream, rep);
+}
+
+px_status px_mobius_adjoint(px_poset* p, int dtype, const void* v, int64_t ldv, void* out, int64_t ldo, int64_t B,
+                            int max_refine, double tol, void* stream, px_refine_report* rep) {
+  return mobius_impl(p, true, dtype, v, ldv, out, ldo, B, max_refine, tol, stream, rep);
+}
+
+// ------------------------------------------------------------------- batches
+px_status px_batch_build(int count, px_poset* const* posets, px_batch** out) {
+  if (!out || count < 1 || !posets) return fail(PX_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  const int dev = posets[0] ? posets[0]->device : 0;
+  bool has_up = true;
+  for (int i = 0; i < count; ++i) {
+    if (!posets[i]) return fail(PX_EINVAL, "null poset in batch");
+    if (posets[i]->host_only) return fail(PX_EUNSUPPORTED, "host-only poset in batch");
+    if (posets[i]->device != dev) return fail(PX_EINVAL, "posets of a batch must share a device");
+    has_up = has_up && posets[i]->has_up;
+  }
+  px_batch* b = new (std::nothrow) px_batch();
+  if (!b) return fail(PX_ENOMEM, "host allocation failed");
+  b->device = dev;
+  b->count = count;
+  b->has_up = has_up;
+  std::vector<int32_t> node_of_row, chain_of_row, chain_off(1, 0), poset_of_row, kk(count), row_off(count + 1, 0);
+  std::vector<int64_t> niv_off(count + 1, 0);
+  int64_t rows = 0, chains = 0;
+  for (int i = 0; i < count; ++i) {
+    const px::Prep& P = posets[i]->prep;
+    row_off[i] = (int32_t)rows;
+    niv_off[i + 1] = niv_off[i] + P.n * P.k;
+    kk[i] = (int32_t)P.k;
+    rows += P.n;
+    chains += P.k;
+  }
+  if (rows >= INT32_MAX) {
+    delete b;
+    return fail(PX_EINVAL, "batch has too many rows");
+  }
+  row_off[count] = (int32_t)rows;
+  b->rows = rows;
+  node_of_row.resize(rows);
+  chain_of_row.resize(rows);
+  poset_of_row.resize(rows);
+  chain_off.reserve(chains + 1);
+  std::vector<int32_t> niv((size_t)niv_off[count]), niv_up(has_up ? (size_t)niv_off[count] : 0);
+  int32_t cbase = 0;
+  for (int i = 0; i < count; ++i) {
+    const px::Prep& P = posets[i]->prep;
+    const int32_t o = row_off[i];
+    for (int64_t r = 0; r < P.n; ++r) {
+      node_of_row[o + r] = o + P.node_of_row[r];
+      chain_of_row[o + r] = cbase + P.chain_of_row[r];
+      poset_of_row[o + r] = i;
+    }
+    for (int64_t c = 0; c < P.k; ++c) chain_off.push_back(o + P.chain_off[c + 1]);
+    for (size_t e = 0; e < P.niv.size(); ++e) niv[niv_off[i] + e] = P.niv[e] >= 0 ? P.niv[e] + o : -1;
+    if (has_up)
+      for (size_t e = 0; e < P.niv_up.size(); ++e) niv_up[niv_off[i] + e] = P.niv_up[e] >= 0 ? P.niv_up[e] + o : -1;
+    cbase += (int32_t)P.k;
+  }
+  std::vector<int32_t> segoff;
+  seg_tables(chain_off, segoff, b->ntiles);
+  DeviceGuard dg(dev);
+  int64_t bytes = 0;
+  hipError_t e = upload(&b->d_node_of_row, node_of_row.data(), node_of_row.size(), bytes);
+  if (e == hipSuccess) e = upload(&b->d_chain_of_row, chain_of_row.data(), chain_of_row.size(), bytes);
+  if (e == hipSuccess) e = upload(&b->d_chain_off, chain_off.data(), chain_off.size(), bytes);
+  if (e == hipSuccess) e = upload(&b->d_niv, niv.data(), niv.size(), bytes);
+  if (e == hipSuccess && has_up) e = upload(&b->d_niv_up, niv_up.data(), niv_up.size(), bytes);
+  if (e == hipSuccess) e = upload(&b->d_segoff, segoff.data(), segoff.size(), bytes);
+  if (e == hipSuccess) e = upload(&b->d_poset_of_row, poset_of_row.data(), poset_of_row.size(), bytes);
+  if (e == hipSuccess) e = upload(&b->d_k, kk.data(), kk.size(), bytes);
+  if (e == hipSuccess) e = upload(&b->d_row_off, row_off.data(), row_off.size(), bytes);
+  if (e == hipSuccess) e = upload(&b->d_niv_off, niv_off.data(), niv_off.size(), bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    px_batch_free(b);
+    return fail(e == hipErrorOutOfMemory ? PX_ENOMEM : PX_EHIP, std::string("batch upload failed: ") + hipGetErrorString(e));
+  }
+  px::DevPoset& d = b->dp;
+  d.n = (int32_t)rows;
+  d.k = 0;
+  d.nchains = (int32_t)chains;
+  d.node_of_row = b->d_node_of_row;
+  d.chain_of_row = b->d_chain_of_row;
+  d.chain_off = b->d_chain_off;
+  d.niv = b->d_niv;
+  d.niv_up = b->d_niv_up;
+  d.segoff = b->d_segoff;
+  d.niv_off = b->d_niv_off;
+  d.poset_of_row = b->d_poset_of_row;
+  d.k_of_poset = b->d_k;
+  d.row_off = b->d_row_off;
+  *out = b;
+  return PX_OK;
+}
+
+px_status px_batch_free(px_batch* b) {
+  if (!b) return PX_OK;
+  DeviceGuard dg(b->device);
+  int32_t* bufs[] = {b->d_node_of_row, b->d_chain_of_row, b->d_chain_off, b->d_niv,  b->d_niv_up,
+                     b->d_segoff,      b->d_poset_of_row,  b->d_k,         b->d_row_off};
+  for (int32_t* q : bufs)
+    if (q) (void)hipFree(q);
+  if (b->d_niv_off) (void)hipFree(b->d_niv_off);
+  b->ws.release();
+  delete b;
+  return PX_OK;
+}
+
+px_status px_batch_rows(const px_batch* b, int64_t* total_rows) {
+  if (!b || !total_rows) return fail(PX_EINVAL, "null argument");
+  *total_rows = b->rows;
+  return PX_OK;
+}
+
+px_status px_batch_reserve(px_batch* b, int dtype, int64_t B) {
+  if (!b) return fail(PX_EINVAL, "null batch");
+  if (dtype != PX_I64 && dtype != PX_F32 && dtype != PX_F64) return fail(PX_EINVAL, "unknown dtype");
+  if (B < 1) return fail(PX_EINVAL, "B must be >= 1");
+  DeviceGuard dg(b->device);
+  const int64_t nt = b->ntiles[px::seg_index(px::col_width(B))];
+  return b->ws.ensure(layout(b->rows, B, dtype, false, nt).total);
+}
+
+static px_status batch_zeta(px_batch* b, bool up, int dtype, const void* f, int64_t ldf, void* g, int64_t ldg,
+                            int64_t B, void* stream) {
+  if (!b) return fail(PX_EINVAL, "null batch");
+  if (up && !b->has_up) return fail(PX_EUNSUPPORTED, "a poset of the batch was built with PX_BUILD_NO_ADJOINT");
+  px_status st = check_matrix_args(b->rows, dtype, f, ldf, g, ldg, B);
+  if (st != PX_OK) return st;
+  DeviceGuard dg(b->device);
+  if (!dg.ok) return fail(PX_EHIP, "hipSetDevice failed");
+  const int64_t nt = b->ntiles[px::seg_index(px::col_width(B))];
+  Layout L = layout(b->rows, B, dtype, false, nt);
+  if ((st = b->ws.ensure(L.total)) != PX_OK) return st;
+  char* w = (char*)b->ws.p;
+  hipStream_t s = (hipStream_t)stream;
+  const px::ElemType T = etype(dtype);
+  hipError_t e = run_scan(b->dp, up ? -1 : 1, T, f, ldf, T, w + L.y, B, w + L.aux, nt, s);
+  if (e == hipSuccess) e = run_gather(b->dp, up, T, w + L.y, B, T, g, ldg, T, nullptr, 0, s);
+  return hip_status(e, "batched zeta launch");
+}
+
+px_status px_zeta_batched(px_batch* b, int dtype, const void* f, int64_t ldf, void* g, int64_t ldg, int64_t B,
+                          void* stream) {
+  return batch_zeta(b, false, dtype, f, ldf, g, ldg, B, stream);
+}
+
+px_status px_zeta_adjoint_batched(px_batch* b, int dtype, const void* w, int64_t ldw, void* out, int64_t ldo,
+                                  int64_t B, void* stream) {
+  return batch_zeta(b, true, dtype, w, ldw, out, ldo, B, stream);
+}
+
+}  // extern "C"

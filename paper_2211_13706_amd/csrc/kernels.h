@@ -1,0 +1,74 @@
+// Launchers of the gfx950 kernels of the transforms (internal interface).
+//
+// Row = position in the chain-major renumbering: chain c owns rows
+// [chain_off[c], chain_off[c+1]), bottom element first.  Device matrices P / Y
+// are [n, B] chain-major and dense; user matrices are in node order with a
+// leading dimension and are addressed through node_of_row.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace px {
+
+enum ElemType { E_I64 = 0, E_F32 = 1, E_F64 = 2 };
+
+// Static description of one poset (or a batch of posets) on the device.
+struct DevPoset {
+  int32_t n = 0, k = 0;           // for a batch: total rows; k = 0 (per-poset k)
+  const int32_t* node_of_row = nullptr;
+  const int32_t* chain_of_row = nullptr;
+  const int32_t* chain_off = nullptr;   // chains+1
+  int32_t nchains = 0;
+  const int32_t* niv = nullptr;         // [n*k] or, for a batch, at niv_off[poset]
+  const int32_t* niv_up = nullptr;
+  const int32_t* segoff = nullptr;      // [7][nchains+1] tile offsets per tile height
+  // batch only
+  const int64_t* niv_off = nullptr;     // element offset of each poset's niv block
+  const int32_t* poset_of_row = nullptr;
+  const int32_t* k_of_poset = nullptr;
+  const int32_t* row_off = nullptr;     // first row of each poset
+};
+
+// Column tile width used by every kernel for B right-hand sides, and the
+// scan tile height derived from it.
+int col_width(int64_t B);
+int seg_index(int cw);     // 0..6
+int seg_rows(int cw);      // rows of one scan tile
+
+// Chain scan V x (forward, dir=+1, prefix from the bottom) or V^T x (dir=-1,
+// suffix from the top), three deterministic phases.  x is node order
+// (ld ldx, element type tin); P is chain-major dense [n, B] of type tout.
+// Scan state: compensated float for E_F32 -> E_F32, compensated double when
+// tout is E_F64, wrapping uint64 for E_I64.  aux must hold 2 * ntiles * B *
+// 16 bytes.
+// phase: 0 = tile totals, 1 = carries, 2 = scan and write (run in this order).
+hipError_t launch_chain_scan_phase(int phase, const DevPoset& d, int dir, ElemType tin, const void* x,
+                                   int64_t ldx, ElemType tout, void* P, int64_t B, void* aux,
+                                   int64_t ntiles, hipStream_t s);
+
+// Gather-reduce U c: out[node(r)] = Σ_j P[nv[r][j]] over finite entries.  With
+// resid != nullptr (float64 P only): out = resid[node] - Σ (residual of a
+// refinement step; resid has element type tres, leading dim ldr).
+hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P, int64_t B,
+                         ElemType tout, void* out, int64_t ldo, ElemType tres, const void* resid,
+                         int64_t ldr, hipStream_t s);
+
+// One level of the solve U y' = g: for the rows lev_rows[0..cnt),
+// Y[r] = g[node(r)] - Σ_{j: nv[r][j] != r} Y[nv[r][j]].
+hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_rows, int64_t cnt,
+                               ElemType tin, const void* g, int64_t ldg, ElemType ty, void* Y,
+                               int64_t B, hipStream_t s);
+
+// y = V^{-1} y' (dir=+1: minus the element below in the chain; dir=-1: minus the
+// element above).  accumulate: out += result instead of out = result.
+hipError_t launch_chain_diff(const DevPoset& d, int dir, ElemType ty, const void* Y, int64_t B,
+                             ElemType tout, void* out, int64_t ldo, bool accumulate, hipStream_t s);
+
+// Per-column max|r| (float64 [n, B], ld B) and max|g| (type tg, ld ldg) plus a
+// non-finite flag into stats[2*B + 1] (as uint64 bit patterns / 0-1).
+hipError_t launch_absmax(int64_t n, int64_t B, const double* r, ElemType tg, const void* g,
+                         int64_t ldg, uint64_t* stats, hipStream_t s);
+
+}  // namespace px

@@ -1,0 +1,485 @@
+// gfx950 kernels of the fast zeta / Möbius transforms.
+//
+// The transforms factor as Z = U V (§3): V sums every chain from the bottom
+// up to each element (a prefix scan along chain-major rows), U gathers for
+// every element x the chain prefixes ending at niv_j(x) (§2.4, Eq.
+// zeta-fast).  The Möbius transform solves U y' = g by substitution,
+// level by level, then applies V^{-1}, one subtraction per element (§3, Alg. 4).
+//
+// Thread layout shared by all kernels: a 256-thread workgroup covers `cw`
+// consecutive right-hand-side columns (lanes) times 256/cw rows, so that the
+// lanes of a wavefront read contiguous bytes of a row; B is padded to cw.
+// Everything here is a scan or an integer-indexed gather: VALU + HBM work, no
+// MFMA.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace px {
+
+constexpr int WG = 256;
+constexpr int RPT = 16;  // rows per thread in a scan tile
+
+int col_width(int64_t B) {
+  int cw = 1;
+  while (cw < B && cw < 64) cw <<= 1;
+  return cw;
+}
+int seg_index(int cw) {
+  int i = 0;
+  while ((1 << i) < cw) ++i;
+  return i;
+}
+int seg_rows(int cw) { return (WG / cw) * RPT; }
+
+namespace {
+
+// ------------------------------------------------------------------ scan state
+// Wrapping 64-bit integer sum (two's complement modulo 2^64).
+struct StateI {
+  uint64_t s;
+  __device__ void zero() { s = 0; }
+  __device__ void add(uint64_t x) { s += x; }
+  __device__ void combine(const StateI& o) { s += o.s; }
+  __device__ uint64_t value() const { return s; }
+};
+
+// Compensated floating-point sum: s + e carries the running total, and each
+// addition's rounding error (TwoSum, Knuth) is accumulated in e
+// (Kahan-Babuska-Neumaier).  Order-independent combination lets tiles be
+// summed in parallel.  No multiplications, so contraction cannot change it.
+template <typename F>
+struct StateF {
+  F s, e;
+  __device__ void zero() { s = F(0); e = F(0); }
+  __device__ void add(F x) {
+    F t = s + x;
+    F bp = t - s;
+    F err = (s - (t - bp)) + (x - bp);
+    s = t;
+    e += err;
+  }
+  __device__ void combine(const StateF& o) {
+    F t = s + o.s;
+    F bp = t - s;
+    F err = (s - (t - bp)) + (o.s - bp);
+    s = t;
+    e += o.e + err;
+  }
+  __device__ F value() const { return s + e; }
+};
+
+template <typename Tin, typename Tout> struct ScanTraits;
+template <> struct ScanTraits<int64_t, int64_t> {
+  using St = StateI;
+  __device__ static uint64_t in(int64_t x) { return (uint64_t)x; }
+  __device__ static int64_t out(uint64_t v) { return (int64_t)v; }
+};
+template <> struct ScanTraits<float, float> {
+  using St = StateF<float>;
+  __device__ static float in(float x) { return x; }
+  __device__ static float out(float v) { return v; }
+};
+template <> struct ScanTraits<double, double> {
+  using St = StateF<double>;
+  __device__ static double in(double x) { return x; }
+  __device__ static double out(double v) { return v; }
+};
+template <> struct ScanTraits<float, double> {
+  using St = StateF<double>;
+  __device__ static double in(float x) { return (double)x; }
+  __device__ static double out(double v) { return v; }
+};
+
+__device__ inline int find_chain(const int32_t* so, int nchains, int t) {
+  int lo = 0, hi = nchains;  // so[lo] <= t < so[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (so[mid] <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Phase 1: per tile and column, the compensated total of the tile's rows.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw, const Tin* __restrict__ x,
+                                                    int64_t ldx, int64_t B,
+                                                    typename ScanTraits<Tin, Tout>::St* __restrict__ A) {
+  using Tr = ScanTraits<Tin, Tout>;
+  using St = typename Tr::St;
+  __shared__ St sm[WG];
+  const int t = blockIdx.x;
+  const int32_t* so = d.segoff + (int64_t)segi * (d.nchains + 1);
+  const int c = find_chain(so, d.nchains, t);
+  const int seg = (WG / cw) * RPT;
+  const int64_t base = d.chain_off[c] + (int64_t)(t - so[c]) * seg;
+  const int64_t end = d.chain_off[c + 1];
+  const int lane = threadIdx.x % cw, rg = threadIdx.x / cw;
+  const int64_t col = (int64_t)blockIdx.y * cw + lane;
+  St st;
+  st.zero();
+  if (col < B) {
+    const int64_t r0 = base + (int64_t)rg * RPT;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      int64_t r = r0 + i;
+      if (r < end) st.add(Tr::in(x[(int64_t)d.node_of_row[r] * ldx + col]));
+    }
+  }
+  sm[threadIdx.x] = st;
+  __syncthreads();
+  if (rg == 0 && col < B) {
+    St tot = sm[lane];
+    for (int g = 1; g < WG / cw; ++g) tot.combine(sm[g * cw + lane]);
+    A[(int64_t)t * B + col] = tot;
+  }
+}
+
+// Phase 2: exclusive scan of the tile totals along every chain, per column.
+template <typename St>
+__global__ __launch_bounds__(WG) void k_scan_carry(DevPoset d, int segi, int dir, int64_t B,
+                                                   const St* __restrict__ A, St* __restrict__ C) {
+  const int64_t idx = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (idx >= (int64_t)d.nchains * B) return;
+  const int c = (int)(idx / B);
+  const int64_t col = idx % B;
+  const int32_t* so = d.segoff + (int64_t)segi * (d.nchains + 1);
+  St carry;
+  carry.zero();
+  if (dir > 0) {
+    for (int t = so[c]; t < so[c + 1]; ++t) {
+      C[(int64_t)t * B + col] = carry;
+      carry.combine(A[(int64_t)t * B + col]);
+    }
+  } else {
+    for (int t = so[c + 1] - 1; t >= so[c]; --t) {
+      C[(int64_t)t * B + col] = carry;
+      carry.combine(A[(int64_t)t * B + col]);
+    }
+  }
+}
+
+// Phase 3: scan inside the tile from its carry; write P chain-major.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw, int dir, const Tin* __restrict__ x,
+                                                   int64_t ldx, int64_t B,
+                                                   const typename ScanTraits<Tin, Tout>::St* __restrict__ C,
+                                                   Tout* __restrict__ P) {
+  using Tr = ScanTraits<Tin, Tout>;
+  using St = typename Tr::St;
+  using Tv = decltype(Tr::in(Tin()));
+  __shared__ St sm[WG];
+  const int t = blockIdx.x;
+  const int32_t* so = d.segoff + (int64_t)segi * (d.nchains + 1);
+  const int c = find_chain(so, d.nchains, t);
+  const int RG = WG / cw;
+  const int seg = RG * RPT;
+  const int64_t base = d.chain_off[c] + (int64_t)(t - so[c]) * seg;
+  const int64_t end = d.chain_off[c + 1];
+  const int lane = threadIdx.x % cw, rg = threadIdx.x / cw;
+  const int64_t col = (int64_t)blockIdx.y * cw + lane;
+  const int64_t r0 = base + (int64_t)rg * RPT;
+  Tv v[RPT];
+  St loc;
+  loc.zero();
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    int64_t r = r0 + i;
+    v[i] = (col < B && r < end) ? Tr::in(x[(int64_t)d.node_of_row[r] * ldx + col]) : Tv(0);
+  }
+  if (dir > 0) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) loc.add(v[i]);
+  } else {
+#pragma unroll
+    for (int i = RPT - 1; i >= 0; --i) loc.add(v[i]);
+  }
+  sm[threadIdx.x] = loc;
+  __syncthreads();
+  if (col >= B) return;
+  St st = C[(int64_t)t * B + col];
+  if (dir > 0) {
+    for (int g = 0; g < rg; ++g) st.combine(sm[g * cw + lane]);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      st.add(v[i]);
+      int64_t r = r0 + i;
+      if (r < end) P[r * B + col] = Tr::out(st.value());
+    }
+  } else {
+    for (int g = RG - 1; g > rg; --g) st.combine(sm[g * cw + lane]);
+#pragma unroll
+    for (int i = RPT - 1; i >= 0; --i) {
+      st.add(v[i]);
+      int64_t r = r0 + i;
+      if (r < end) P[r * B + col] = Tr::out(st.value());
+    }
+  }
+}
+
+// ------------------------------------------------------------ gather-reduce
+template <typename T> struct Wide;
+template <> struct Wide<int64_t> { using W = uint64_t; };
+template <> struct Wide<float> { using W = double; };
+template <> struct Wide<double> { using W = double; };
+
+template <typename TP, typename Tout, typename Tres, bool RESID>
+__global__ __launch_bounds__(WG) void k_gather(DevPoset d, const int32_t* __restrict__ nv, int cw,
+                                               const TP* __restrict__ P, int64_t B, Tout* __restrict__ out,
+                                               int64_t ldo, const Tres* __restrict__ res, int64_t ldr) {
+  using W = typename Wide<TP>::W;
+  const int RG = WG / cw;
+  const int64_t r = (int64_t)blockIdx.x * RG + threadIdx.x / cw;
+  const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
+  if (r >= d.n || col >= B) return;
+  const int k = d.k;
+  const int32_t* nr = nv + r * k;
+  W acc = W(0);
+  for (int j = 0; j < k; ++j) {
+    const int32_t t = nr[j];
+    if (t >= 0) acc += (W)P[(int64_t)t * B + col];
+  }
+  const int64_t node = d.node_of_row[r];
+  if constexpr (RESID) {
+    out[node * ldo + col] = (Tout)((double)res[node * ldr + col] - (double)acc);
+  } else {
+    out[node * ldo + col] = (Tout)acc;
+  }
+}
+
+// Batched gather over many posets of different width: row r belongs to
+// poset p = poset_of_row[r] whose niv block (k_p entries per row, global row
+// ids) starts at niv_off[p].
+template <typename TP, typename Tout>
+__global__ __launch_bounds__(WG) void k_gather_batched(DevPoset d, const int32_t* __restrict__ nv, int cw,
+                                                       const TP* __restrict__ P, int64_t B,
+                                                       Tout* __restrict__ out, int64_t ldo) {
+  using W = typename Wide<TP>::W;
+  const int RG = WG / cw;
+  const int64_t r = (int64_t)blockIdx.x * RG + threadIdx.x / cw;
+  const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
+  if (r >= d.n || col >= B) return;
+  const int p = d.poset_of_row[r];
+  const int k = d.k_of_poset[p];
+  const int32_t* nr = nv + d.niv_off[p] + (r - d.row_off[p]) * k;
+  W acc = W(0);
+  for (int j = 0; j < k; ++j) {
+    const int32_t t = nr[j];
+    if (t >= 0) acc += (W)P[(int64_t)t * B + col];
+  }
+  out[(int64_t)d.node_of_row[r] * ldo + col] = (Tout)acc;
+}
+
+// ------------------------------------------------------------- U-solve level
+template <typename Tin, typename TY>
+__global__ __launch_bounds__(WG) void k_usolve(DevPoset d, const int32_t* __restrict__ nv,
+                                               const int32_t* __restrict__ rows, int64_t cnt, int cw,
+                                               const Tin* __restrict__ g, int64_t ldg, TY* __restrict__ Y,
+                                               int64_t B) {
+  using W = typename Wide<TY>::W;
+  const int RG = WG / cw;
+  const int64_t i = (int64_t)blockIdx.x * RG + threadIdx.x / cw;
+  const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
+  if (i >= cnt || col >= B) return;
+  const int64_t r = rows[i];
+  const int64_t node = d.node_of_row[r];
+  W acc = (W)g[node * ldg + col];
+  const int32_t* nr = nv + r * d.k;
+  for (int j = 0; j < d.k; ++j) {
+    const int32_t t = nr[j];
+    if (t >= 0 && t != r) acc -= (W)Y[(int64_t)t * B + col];
+  }
+  Y[r * B + col] = (TY)acc;
+}
+
+// ------------------------------------------------------------ chain difference
+template <typename TY, typename Tout>
+__global__ __launch_bounds__(WG) void k_chain_diff(DevPoset d, int dir, int cw, const TY* __restrict__ Y, int64_t B,
+                                                   Tout* __restrict__ out, int64_t ldo, int accumulate) {
+  using W = typename Wide<TY>::W;
+  const int RG = WG / cw;
+  const int64_t r = (int64_t)blockIdx.x * RG + threadIdx.x / cw;
+  const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
+  if (r >= d.n || col >= B) return;
+  const int c = d.chain_of_row[r];
+  W v = (W)Y[r * B + col];
+  if (dir > 0) {
+    if (r > d.chain_off[c]) v -= (W)Y[(r - 1) * B + col];
+  } else {
+    if (r + 1 < d.chain_off[c + 1]) v -= (W)Y[(r + 1) * B + col];
+  }
+  const int64_t node = d.node_of_row[r];
+  Tout* o = out + node * ldo + col;
+  if (accumulate) *o = (Tout)((W)*o + v);
+  else *o = (Tout)v;
+}
+
+// --------------------------------------------------------------- statistics
+template <typename TG>
+__global__ __launch_bounds__(WG) void k_absmax(int64_t n, int64_t B, const double* __restrict__ r,
+                                               const TG* __restrict__ g, int64_t ldg, uint64_t* stats) {
+  const int64_t total = n * B;
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < total; i += (int64_t)gridDim.x * WG) {
+    const int64_t x = i / B, col = i % B;
+    double a = fabs(r[i]);
+    double b = fabs((double)g[x * ldg + col]);
+    if (!isfinite(a) || !isfinite(b)) {
+      atomicMax((unsigned long long*)&stats[2 * B], 1ull);
+      continue;
+    }
+    atomicMax((unsigned long long*)&stats[col], (unsigned long long)__double_as_longlong(a));
+    atomicMax((unsigned long long*)&stats[B + col], (unsigned long long)__double_as_longlong(b));
+  }
+}
+
+__global__ void k_fill_u64(uint64_t* p, int64_t cnt, uint64_t v) {
+  int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i < cnt) p[i] = v;
+}
+
+inline dim3 grid2(int64_t rows, int cw, int64_t B) {
+  const int64_t RG = WG / cw;
+  return dim3((unsigned)((rows + RG - 1) / RG), (unsigned)((B + cw - 1) / cw));
+}
+
+template <typename Tin, typename Tout>
+hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int64_t ldx, void* P, int64_t B,
+                      void* aux, int64_t ntiles, hipStream_t s) {
+  using St = typename ScanTraits<Tin, Tout>::St;
+  const int cw = col_width(B);
+  const int segi = seg_index(cw);
+  St* A = (St*)aux;
+  St* C = A + ntiles * B;
+  dim3 g((unsigned)ntiles, (unsigned)((B + cw - 1) / cw));
+  if (phase == 0) {
+    hipLaunchKernelGGL((k_scan_reduce<Tin, Tout>), g, dim3(WG), 0, s, d, segi, cw, (const Tin*)x, ldx, B, A);
+  } else if (phase == 1) {
+    const int64_t nc = (int64_t)d.nchains * B;
+    hipLaunchKernelGGL((k_scan_carry<St>), dim3((unsigned)((nc + WG - 1) / WG)), dim3(WG), 0, s, d, segi, dir, B,
+                       (const St*)A, C);
+  } else {
+    hipLaunchKernelGGL((k_scan_apply<Tin, Tout>), g, dim3(WG), 0, s, d, segi, cw, dir, (const Tin*)x, ldx, B,
+                       (const St*)C, (Tout*)P);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_chain_scan_phase(int phase, const DevPoset& d, int dir, ElemType tin, const void* x, int64_t ldx,
+                                   ElemType tout, void* P, int64_t B, void* aux, int64_t ntiles, hipStream_t s) {
+  if (d.n == 0 || ntiles == 0) return hipSuccess;
+  if (tin == E_I64 && tout == E_I64) return scan_typed<int64_t, int64_t>(phase, d, dir, x, ldx, P, B, aux, ntiles, s);
+  if (tin == E_F32 && tout == E_F32) return scan_typed<float, float>(phase, d, dir, x, ldx, P, B, aux, ntiles, s);
+  if (tin == E_F64 && tout == E_F64) return scan_typed<double, double>(phase, d, dir, x, ldx, P, B, aux, ntiles, s);
+  if (tin == E_F32 && tout == E_F64) return scan_typed<float, double>(phase, d, dir, x, ldx, P, B, aux, ntiles, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P, int64_t B, ElemType tout,
+                         void* out, int64_t ldo, ElemType tres, const void* resid, int64_t ldr, hipStream_t s) {
+  if (d.n == 0) return hipSuccess;
+  const int cw = col_width(B);
+  const dim3 g = grid2(d.n, cw, B);
+  const int32_t* nv = up ? d.niv_up : d.niv;
+  if (resid) {
+    if (tp != E_F64 || tout != E_F64) return hipErrorInvalidValue;
+    if (tres == E_F32)
+      hipLaunchKernelGGL((k_gather<double, double, float, true>), g, dim3(WG), 0, s, d, nv, cw, (const double*)P, B,
+                         (double*)out, ldo, (const float*)resid, ldr);
+    else if (tres == E_F64)
+      hipLaunchKernelGGL((k_gather<double, double, double, true>), g, dim3(WG), 0, s, d, nv, cw, (const double*)P,
+                         B, (double*)out, ldo, (const double*)resid, ldr);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+  if (d.poset_of_row) {
+    if (tp == E_F32 && tout == E_F32)
+      hipLaunchKernelGGL((k_gather_batched<float, float>), g, dim3(WG), 0, s, d, nv, cw, (const float*)P, B,
+                         (float*)out, ldo);
+    else if (tp == E_F64 && tout == E_F64)
+      hipLaunchKernelGGL((k_gather_batched<double, double>), g, dim3(WG), 0, s, d, nv, cw, (const double*)P, B,
+                         (double*)out, ldo);
+    else if (tp == E_I64 && tout == E_I64)
+      hipLaunchKernelGGL((k_gather_batched<int64_t, int64_t>), g, dim3(WG), 0, s, d, nv, cw, (const int64_t*)P,
+                         B, (int64_t*)out, ldo);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+  if (tp == E_I64 && tout == E_I64)
+    hipLaunchKernelGGL((k_gather<int64_t, int64_t, int64_t, false>), g, dim3(WG), 0, s, d, nv, cw,
+                       (const int64_t*)P, B, (int64_t*)out, ldo, (const int64_t*)nullptr, 0);
+  else if (tp == E_F32 && tout == E_F32)
+    hipLaunchKernelGGL((k_gather<float, float, float, false>), g, dim3(WG), 0, s, d, nv, cw, (const float*)P, B,
+                       (float*)out, ldo, (const float*)nullptr, 0);
+  else if (tp == E_F64 && tout == E_F64)
+    hipLaunchKernelGGL((k_gather<double, double, double, false>), g, dim3(WG), 0, s, d, nv, cw, (const double*)P,
+                       B, (double*)out, ldo, (const double*)nullptr, 0);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_rows, int64_t cnt, ElemType tin,
+                               const void* g, int64_t ldg, ElemType ty, void* Y, int64_t B, hipStream_t s) {
+  if (cnt == 0) return hipSuccess;
+  const int cw = col_width(B);
+  const dim3 gr = grid2(cnt, cw, B);
+  const int32_t* nv = up ? d.niv_up : d.niv;
+  if (tin == E_I64 && ty == E_I64)
+    hipLaunchKernelGGL((k_usolve<int64_t, int64_t>), gr, dim3(WG), 0, s, d, nv, lev_rows, cnt, cw,
+                       (const int64_t*)g, ldg, (int64_t*)Y, B);
+  else if (tin == E_F32 && ty == E_F32)
+    hipLaunchKernelGGL((k_usolve<float, float>), gr, dim3(WG), 0, s, d, nv, lev_rows, cnt, cw, (const float*)g,
+                       ldg, (float*)Y, B);
+  else if (tin == E_F64 && ty == E_F32)
+    hipLaunchKernelGGL((k_usolve<double, float>), gr, dim3(WG), 0, s, d, nv, lev_rows, cnt, cw, (const double*)g,
+                       ldg, (float*)Y, B);
+  else if (tin == E_F64 && ty == E_F64)
+    hipLaunchKernelGGL((k_usolve<double, double>), gr, dim3(WG), 0, s, d, nv, lev_rows, cnt, cw,
+                       (const double*)g, ldg, (double*)Y, B);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_chain_diff(const DevPoset& d, int dir, ElemType ty, const void* Y, int64_t B, ElemType tout,
+                             void* out, int64_t ldo, bool accumulate, hipStream_t s) {
+  if (d.n == 0) return hipSuccess;
+  const int cw = col_width(B);
+  const dim3 g = grid2(d.n, cw, B);
+  if (ty == E_I64 && tout == E_I64)
+    hipLaunchKernelGGL((k_chain_diff<int64_t, int64_t>), g, dim3(WG), 0, s, d, dir, cw, (const int64_t*)Y, B,
+                       (int64_t*)out, ldo, (int)accumulate);
+  else if (ty == E_F32 && tout == E_F32)
+    hipLaunchKernelGGL((k_chain_diff<float, float>), g, dim3(WG), 0, s, d, dir, cw, (const float*)Y, B,
+                       (float*)out, ldo, (int)accumulate);
+  else if (ty == E_F64 && tout == E_F64)
+    hipLaunchKernelGGL((k_chain_diff<double, double>), g, dim3(WG), 0, s, d, dir, cw, (const double*)Y, B,
+                       (double*)out, ldo, (int)accumulate);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax(int64_t n, int64_t B, const double* r, ElemType tg, const void* g, int64_t ldg,
+                         uint64_t* stats, hipStream_t s) {
+  const int64_t cnt = 2 * B + 1;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((cnt + WG - 1) / WG)), dim3(WG), 0, s, stats, cnt, (uint64_t)0);
+  if (n == 0) return hipGetLastError();
+  int64_t blocks = (n * B + WG - 1) / WG;
+  if (blocks > 4096) blocks = 4096;
+  if (tg == E_F32)
+    hipLaunchKernelGGL((k_absmax<float>), dim3((unsigned)blocks), dim3(WG), 0, s, n, B, r, (const float*)g, ldg,
+                       stats);
+  else if (tg == E_F64)
+    hipLaunchKernelGGL((k_absmax<double>), dim3((unsigned)blocks), dim3(WG), 0, s, n, B, r, (const double*)g, ldg,
+                       stats);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace px

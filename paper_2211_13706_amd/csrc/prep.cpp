@@ -1,0 +1,343 @@
+// One-time host preprocessing of a poset; see prep.h.
+#include "prep.h"
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstring>
+
+#include "posetx.h"
+
+namespace px {
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Parent lists (reversed CSR) of the child lists.
+void reverse_csr(int64_t n, const int64_t* indptr, const int32_t* indices, std::vector<int64_t>& rptr,
+                 std::vector<int32_t>& ridx) {
+  rptr.assign(n + 1, 0);
+  const int64_t m = indptr[n];
+  for (int64_t e = 0; e < m; ++e) rptr[indices[e] + 1]++;
+  for (int64_t i = 0; i < n; ++i) rptr[i + 1] += rptr[i];
+  ridx.resize(m);
+  std::vector<int64_t> fill(rptr.begin(), rptr.end() - 1);
+  for (int64_t u = 0; u < n; ++u)
+    for (int64_t e = indptr[u]; e < indptr[u + 1]; ++e) ridx[fill[indices[e]]++] = (int32_t)u;
+}
+
+// Maximum matching of the bipartite graph with an edge (v1, u2) per DAG edge v -> u
+// (Alg. 1): Hopcroft-Karp with iterative searches.  next[v] = u when matched.
+void hopcroft_karp(int64_t n, const int64_t* indptr, const int32_t* indices, std::vector<int32_t>& matchL,
+                   std::vector<int32_t>& matchR) {
+  matchL.assign(n, -1);
+  matchR.assign(n, -1);
+  for (int64_t v = 0; v < n; ++v)  // greedy start
+    for (int64_t e = indptr[v]; e < indptr[v + 1]; ++e)
+      if (matchR[indices[e]] < 0) {
+        matchL[v] = indices[e];
+        matchR[indices[e]] = (int32_t)v;
+        break;
+      }
+  const int32_t INF = INT32_MAX;
+  std::vector<int32_t> dist(n), queue(n), stack, via;
+  std::vector<int64_t> it(n);
+  for (;;) {
+    int64_t qh = 0, qt = 0;
+    for (int64_t v = 0; v < n; ++v) {
+      if (matchL[v] < 0) {
+        dist[v] = 0;
+        queue[qt++] = (int32_t)v;
+      } else {
+        dist[v] = INF;
+      }
+    }
+    bool found = false;
+    while (qh < qt) {
+      int32_t v = queue[qh++];
+      for (int64_t e = indptr[v]; e < indptr[v + 1]; ++e) {
+        int32_t w = matchR[indices[e]];
+        if (w < 0) {
+          found = true;
+        } else if (dist[w] == INF) {
+          dist[w] = dist[v] + 1;
+          queue[qt++] = w;
+        }
+      }
+    }
+    if (!found) break;
+    for (int64_t v = 0; v < n; ++v) it[v] = indptr[v];
+    for (int64_t s = 0; s < n; ++s) {
+      if (matchL[s] >= 0) continue;
+      stack.assign(1, (int32_t)s);
+      via.clear();
+      while (!stack.empty()) {
+        int32_t x = stack.back();
+        if (it[x] == indptr[x + 1]) {
+          dist[x] = INF;
+          stack.pop_back();
+          if (!via.empty()) via.pop_back();
+          continue;
+        }
+        int32_t u = indices[it[x]++];
+        int32_t w = matchR[u];
+        if (w < 0) {
+          via.push_back(u);
+          for (size_t d = stack.size(); d-- > 0;) {
+            matchL[stack[d]] = via[d];
+            matchR[via[d]] = stack[d];
+          }
+          break;
+        }
+        if (dist[w] == dist[x] + 1) {
+          via.push_back(u);
+          stack.push_back(w);
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const int32_t* chain_of,
+               const int32_t* chain_pos, bool want_up, bool mirsky_schedule, Prep& P, std::string& msg) {
+  double t0 = now_s();
+  if (n < 0 || n >= INT32_MAX) {
+    msg = "n out of range";
+    return PX_EINVAL;
+  }
+  if (n > 0 && (!indptr || (!indices && indptr[n] > 0))) {
+    msg = "null CSR array";
+    return PX_EINVAL;
+  }
+  if ((chain_of == nullptr) != (chain_pos == nullptr)) {
+    msg = "chain_of and chain_pos must both be given or both be NULL";
+    return PX_EINVAL;
+  }
+  P = Prep();
+  P.n = n;
+  if (n == 0) {
+    P.chain_off.assign(1, 0);
+    P.lev_down_ptr.assign(1, 0);
+    P.lev_up_ptr.assign(1, 0);
+    return PX_OK;
+  }
+  if (indptr[0] != 0) {
+    msg = "indptr[0] must be 0";
+    return PX_EINVAL;
+  }
+  for (int64_t u = 0; u < n; ++u)
+    if (indptr[u + 1] < indptr[u]) {
+      msg = "indptr is not non-decreasing";
+      return PX_EINVAL;
+    }
+  const int64_t m = indptr[n];
+  P.edges = m;
+  for (int64_t u = 0; u < n; ++u)
+    for (int64_t e = indptr[u]; e < indptr[u + 1]; ++e) {
+      int32_t v = indices[e];
+      if (v < 0 || v >= n) {
+        msg = "edge target out of range at edge " + std::to_string(e);
+        return PX_EINVAL;
+      }
+      if (v == u) {
+        msg = "self-loop at node " + std::to_string(u);
+        return PX_EINVAL;
+      }
+    }
+
+  // Topological order, children before parents (Kahn; leaves first as in Alg. 6).
+  std::vector<int64_t> rptr;
+  std::vector<int32_t> ridx;
+  reverse_csr(n, indptr, indices, rptr, ridx);
+  std::vector<int32_t> order;
+  order.reserve(n);
+  std::vector<int64_t> outdeg(n);
+  for (int64_t u = 0; u < n; ++u) {
+    outdeg[u] = indptr[u + 1] - indptr[u];
+    if (outdeg[u] == 0) order.push_back((int32_t)u);
+  }
+  std::vector<int32_t> mir(n, 0);  // longest path down to a leaf (Mirsky level)
+  for (size_t h = 0; h < order.size(); ++h) {
+    int32_t v = order[h];
+    for (int64_t e = rptr[v]; e < rptr[v + 1]; ++e) {
+      int32_t p = ridx[e];
+      mir[p] = std::max(mir[p], mir[v] + 1);
+      if (--outdeg[p] == 0) order.push_back(p);
+    }
+  }
+  if ((int64_t)order.size() != n) {
+    msg = "the graph has a directed cycle";
+    return PX_ECYCLE;
+  }
+  for (int64_t v = 0; v < n; ++v) P.mirsky = std::max<int64_t>(P.mirsky, mir[v] + 1);
+  double t1 = now_s();
+  P.t_validate = t1 - t0;
+
+  // Chain decomposition (Definition 1): planted or by maximum matching (Alg. 1).
+  P.chain_of.resize(n);
+  P.chain_pos.resize(n);
+  if (chain_of) {
+    P.planted = true;
+    int64_t k = 0;
+    for (int64_t x = 0; x < n; ++x) {
+      if (chain_of[x] < 0 || chain_pos[x] < 0) {
+        msg = "negative chain id or position at node " + std::to_string(x);
+        return PX_EINVAL;
+      }
+      k = std::max<int64_t>(k, (int64_t)chain_of[x] + 1);
+    }
+    P.k = k;
+    std::copy(chain_of, chain_of + n, P.chain_of.begin());
+    std::copy(chain_pos, chain_pos + n, P.chain_pos.begin());
+  } else {
+    std::vector<int32_t> matchL, matchR;
+    hopcroft_karp(n, indptr, indices, matchL, matchR);
+    int32_t k = 0;
+    std::vector<int32_t> path;
+    for (int64_t top = 0; top < n; ++top) {
+      if (matchR[top] >= 0) continue;  // someone's successor: not a chain top
+      path.clear();
+      for (int32_t x = (int32_t)top; x >= 0; x = matchL[x]) path.push_back(x);
+      for (size_t i = 0; i < path.size(); ++i) {
+        P.chain_of[path[i]] = k;
+        P.chain_pos[path[i]] = (int32_t)(path.size() - 1 - i);
+      }
+      ++k;
+    }
+    P.k = k;
+  }
+  const int64_t k = P.k;
+  P.chain_off.assign(k + 1, 0);
+  for (int64_t x = 0; x < n; ++x) P.chain_off[P.chain_of[x] + 1]++;
+  for (int64_t c = 0; c < k; ++c) {
+    P.max_chain = std::max<int64_t>(P.max_chain, P.chain_off[c + 1]);
+    P.chain_off[c + 1] += P.chain_off[c];
+  }
+  P.row_of_node.resize(n);
+  P.node_of_row.assign(n, -1);
+  P.chain_of_row.resize(n);
+  for (int64_t x = 0; x < n; ++x) {
+    int32_t c = P.chain_of[x];
+    int64_t len = P.chain_off[c + 1] - P.chain_off[c];
+    if (P.chain_pos[x] >= len) {
+      msg = "chain position out of range at node " + std::to_string(x);
+      return PX_EINVAL;
+    }
+    int32_t r = P.chain_off[c] + P.chain_pos[x];
+    if (P.node_of_row[r] >= 0) {
+      msg = "chain " + std::to_string(c) + " uses position " + std::to_string(P.chain_pos[x]) + " twice";
+      return PX_EINVAL;
+    }
+    P.node_of_row[r] = (int32_t)x;
+    P.row_of_node[x] = r;
+    P.chain_of_row[r] = c;
+  }
+  double t2 = now_s();
+  P.t_chains = t2 - t1;
+
+  // niv by the recursion of Theorem 5 over rows in chain-major order.  Within a
+  // chain, rows grow with the position, so the highest element of chain j below x
+  // is the largest row of chain j reachable from x: a row-wise max over the
+  // children, and x itself on its own chain.  The own-chain entry before x is
+  // inserted must be the row just below x: this checks planted chains.
+  P.niv.assign((size_t)n * k, -1);
+  for (int64_t h = 0; h < n; ++h) {
+    int32_t x = order[h];
+    int32_t r = P.row_of_node[x];
+    int32_t* R = &P.niv[(size_t)r * k];
+    for (int64_t e = indptr[x]; e < indptr[x + 1]; ++e) {
+      const int32_t* Rz = &P.niv[(size_t)P.row_of_node[indices[e]] * k];
+      for (int64_t j = 0; j < k; ++j) R[j] = std::max(R[j], Rz[j]);
+    }
+    int32_t c = P.chain_of[x];
+    int32_t expect = P.chain_pos[x] > 0 ? r - 1 : -1;
+    if (R[c] != expect) {
+      msg = "chain " + std::to_string(c) + " is not totally ordered at position " +
+            std::to_string(P.chain_pos[x]) + " (node " + std::to_string(x) + ")";
+      return PX_ECHAIN;
+    }
+    R[c] = r;
+  }
+  for (size_t i = 0; i < P.niv.size(); ++i) P.nnz_niv += P.niv[i] >= 0;
+  if (want_up) {
+    // Dual order: the lowest element of chain j above x is a row-wise min over parents.
+    P.niv_up.assign((size_t)n * k, INT32_MAX);
+    for (int64_t h = n; h-- > 0;) {
+      int32_t x = order[h];
+      int32_t r = P.row_of_node[x];
+      int32_t* R = &P.niv_up[(size_t)r * k];
+      for (int64_t e = rptr[x]; e < rptr[x + 1]; ++e) {
+        const int32_t* Rp = &P.niv_up[(size_t)P.row_of_node[ridx[e]] * k];
+        for (int64_t j = 0; j < k; ++j) R[j] = std::min(R[j], Rp[j]);
+      }
+      R[P.chain_of[x]] = r;
+    }
+    for (size_t i = 0; i < P.niv_up.size(); ++i) {
+      if (P.niv_up[i] == INT32_MAX) P.niv_up[i] = -1;
+      P.nnz_niv_up += P.niv_up[i] >= 0;
+    }
+  }
+  double t3 = now_s();
+  P.t_niv = t3 - t2;
+
+  // Level schedules.  U-dependency levels: the solve at x reads the rows
+  // niv_j(x), j != id(x), all strictly below x, so level(x) = 1 + the largest
+  // level among them.  Mirsky levels (§4) are the longest path to a leaf.
+  auto bucket = [n](const std::vector<int32_t>& lev, std::vector<int32_t>& ptr, std::vector<int32_t>& rows) {
+    int32_t L = 0;
+    for (int64_t r = 0; r < n; ++r) L = std::max(L, lev[r] + 1);
+    ptr.assign(L + 1, 0);
+    for (int64_t r = 0; r < n; ++r) ptr[lev[r] + 1]++;
+    for (int32_t l = 0; l < L; ++l) ptr[l + 1] += ptr[l];
+    rows.resize(n);
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (int64_t r = 0; r < n; ++r) rows[fill[lev[r]]++] = (int32_t)r;
+  };
+  auto udep_levels = [&](const std::vector<int32_t>& nv, bool up, std::vector<int32_t>& lev) {
+    lev.assign(n, 0);
+    for (int64_t h = 0; h < n; ++h) {
+      int32_t x = order[up ? n - 1 - h : h];
+      int32_t r = P.row_of_node[x];
+      const int32_t* R = &nv[(size_t)r * k];
+      int32_t l = 0;
+      for (int64_t j = 0; j < k; ++j)
+        if (R[j] >= 0 && R[j] != r) l = std::max(l, lev[R[j]] + 1);
+      lev[r] = l;
+    }
+  };
+  std::vector<int32_t> ud;
+  udep_levels(P.niv, false, ud);
+  for (int64_t r = 0; r < n; ++r) P.udep = std::max<int64_t>(P.udep, ud[r] + 1);
+  if (mirsky_schedule) {
+    P.lev_down.resize(n);
+    for (int64_t x = 0; x < n; ++x) P.lev_down[P.row_of_node[x]] = mir[x];
+  } else {
+    P.lev_down.swap(ud);
+  }
+  bucket(P.lev_down, P.lev_down_ptr, P.lev_down_rows);
+  if (want_up) {
+    if (mirsky_schedule) {
+      std::vector<int32_t> comir(n, 0);  // longest path up to a root
+      for (int64_t h = n; h-- > 0;) {
+        int32_t x = order[h];
+        for (int64_t e = indptr[x]; e < indptr[x + 1]; ++e)
+          comir[indices[e]] = std::max(comir[indices[e]], comir[x] + 1);
+      }
+      P.lev_up.resize(n);
+      for (int64_t x = 0; x < n; ++x) P.lev_up[P.row_of_node[x]] = comir[x];
+    } else {
+      udep_levels(P.niv_up, true, P.lev_up);
+    }
+    bucket(P.lev_up, P.lev_up_ptr, P.lev_up_rows);
+  } else {
+    P.lev_up_ptr.assign(1, 0);
+  }
+  P.t_levels = now_s() - t3;
+  return PX_OK;
+}
+
+}  // namespace px

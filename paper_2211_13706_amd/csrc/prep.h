@@ -1,0 +1,35 @@
+// Host-side, one-time preprocessing of a poset (§2.3-§2.4 and §4 of the paper):
+// validation, topological order, chain decomposition, chain-major renumbering,
+// the niv map and its dual, and the level schedules of the Möbius solves.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace px {
+
+struct Prep {
+  int64_t n = 0, k = 0, edges = 0;
+  bool planted = false;
+  std::vector<int32_t> chain_of, chain_pos;       // per node
+  std::vector<int32_t> chain_off;                 // k+1 row offsets of the chains
+  std::vector<int32_t> row_of_node, node_of_row;  // chain-major renumbering
+  std::vector<int32_t> chain_of_row;              // per row
+  // niv[r*k + j]: row of the highest element of chain j below row r, or -1.
+  std::vector<int32_t> niv;
+  // niv_up[r*k + j]: row of the lowest element of chain j above row r, or -1.
+  std::vector<int32_t> niv_up;
+  // level schedules: rows of level l are lev_rows[lev_ptr[l] .. lev_ptr[l+1])
+  std::vector<int32_t> lev_down, lev_up;          // level per row
+  std::vector<int32_t> lev_down_ptr, lev_down_rows, lev_up_ptr, lev_up_rows;
+  int64_t nnz_niv = 0, nnz_niv_up = 0, max_chain = 0, mirsky = 0, udep = 0;
+  double t_validate = 0, t_chains = 0, t_niv = 0, t_levels = 0;
+};
+
+// Returns a px_status value; on failure `msg` says why.
+int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const int32_t* chain_of,
+               const int32_t* chain_pos, bool want_up, bool mirsky_schedule, Prep& out,
+               std::string& msg);
+
+}  // namespace px

@@ -1,0 +1,238 @@
+"""Python binding of the posetx C ABI: poset handles and the four transforms.
+
+Function matrices are torch tensors on the poset's GPU, shape [n, B] with
+unit column stride (rows may be padded: the row stride is passed as the
+leading dimension).  PyTorch only provides device memory and the current
+stream; all computation runs in libposetx.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+
+_DTYPES = None
+
+
+def _dtype_code(t) -> int:
+    global _DTYPES
+    import torch
+    if _DTYPES is None:
+        _DTYPES = {torch.int64: _lib.PX_I64, torch.float32: _lib.PX_F32, torch.float64: _lib.PX_F64}
+    try:
+        return _DTYPES[t.dtype]
+    except KeyError:
+        raise TypeError(f"unsupported dtype {t.dtype}; use int64, float32 or float64") from None
+
+
+def _as_matrix(t, name):
+    if t.dim() == 1:
+        t = t.unsqueeze(1)
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be [n] or [n, B]")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (the library has no CPU path)")
+    if t.stride(1) != 1 and t.shape[1] > 1:
+        t = t.contiguous()
+    return t
+
+
+def _ld(t):
+    return max(int(t.stride(0)), int(t.shape[1])) if t.shape[0] > 1 else int(t.shape[1])
+
+
+def _stream(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+class Poset:
+    """A preprocessed poset on one GPU (px_poset_build)."""
+
+    def __init__(self, handle, n, device):
+        self._h = handle
+        self.n = int(n)
+        self.device = device
+        self.info = self.info_dict()
+        self.k = int(self.info["k"])
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            try:
+                _lib.lib().px_poset_free(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def free(self):
+        self.__del__()
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("poset handle was freed")
+        return self._h
+
+    def info_dict(self) -> dict:
+        info = _lib.Info()
+        _lib.check(_lib.lib().px_poset_info(self.handle, ctypes.byref(info)), "px_poset_info")
+        return info.as_dict()
+
+    def chains(self):
+        co = np.empty(self.n, np.int32)
+        cp = np.empty(self.n, np.int32)
+        _lib.check(_lib.lib().px_poset_chains(self.handle, co.ctypes.data, cp.ctypes.data), "px_poset_chains")
+        return co, cp
+
+    def niv(self, up: bool = False) -> np.ndarray:
+        out = np.empty((self.n, self.k), np.int32)
+        _lib.check(_lib.lib().px_poset_niv(self.handle, int(up), out.ctypes.data), "px_poset_niv")
+        return out
+
+    def levels(self, up: bool = False) -> np.ndarray:
+        out = np.empty(self.n, np.int32)
+        _lib.check(_lib.lib().px_poset_levels(self.handle, int(up), out.ctypes.data), "px_poset_levels")
+        return out
+
+    def reserve(self, dtype, B: int):
+        import torch
+        code = {torch.int64: 0, torch.float32: 1, torch.float64: 2}[dtype]
+        _lib.check(_lib.lib().px_reserve(self.handle, code, int(B)), "px_reserve")
+
+
+def poset_build(n, indptr, indices, chain_of=None, chain_pos=None, flags: int = 0, device: int = 0) -> Poset:
+    """Preprocess a DAG given as CSR child lists (px_poset_build)."""
+    indptr = np.ascontiguousarray(indptr, dtype=np.int64)
+    indices = np.ascontiguousarray(indices, dtype=np.int32)
+    if indptr.shape != (int(n) + 1,):
+        raise ValueError("indptr must have n+1 entries")
+    co = cp = None
+    if chain_of is not None:
+        co = np.ascontiguousarray(chain_of, dtype=np.int32)
+        cp = np.ascontiguousarray(chain_pos, dtype=np.int32)
+        if co.shape != (int(n),) or cp.shape != (int(n),):
+            raise ValueError("chain_of and chain_pos must have n entries")
+    h = ctypes.c_void_p()
+    _lib.check(_lib.lib().px_poset_build(
+        int(n), indptr.ctypes.data, indices.ctypes.data if indices.size else None,
+        None if co is None else co.ctypes.data, None if cp is None else cp.ctypes.data,
+        int(flags), int(device), ctypes.byref(h)), "px_poset_build")
+    return Poset(h, n, device)
+
+
+def _transform(fn_name, P, x, out):
+    import torch
+    x = _as_matrix(x, "input")
+    if x.shape[0] != P.n:
+        raise ValueError(f"input has {x.shape[0]} rows, poset has {P.n}")
+    if out is None:
+        out = torch.empty_like(x, memory_format=torch.contiguous_format)
+    out2 = out if out.dim() == 2 else out.unsqueeze(1)
+    if out2.shape != x.shape or out2.dtype != x.dtype or out2.stride(1) != 1 and out2.shape[1] > 1:
+        raise ValueError("out must match the input's shape and dtype, with unit column stride")
+    code = _dtype_code(x)
+    fn = getattr(_lib.lib(), fn_name)
+    _lib.check(fn(P.handle, code, ctypes.c_void_p(x.data_ptr()), _ld(x), ctypes.c_void_p(out2.data_ptr()),
+                  _ld(out2), int(x.shape[1]), _stream(x)), fn_name)
+    return out
+
+
+def zeta(P: Poset, f, out=None):
+    """g = Z f (px_zeta)."""
+    return _transform("px_zeta", P, f, out)
+
+
+def zeta_adjoint(P: Poset, w, out=None):
+    """Z^T w (px_zeta_adjoint)."""
+    return _transform("px_zeta_adjoint", P, w, out)
+
+
+def _mobius(fn_name, P, g, out, max_refine, tol, report):
+    import torch
+    g = _as_matrix(g, "input")
+    if g.shape[0] != P.n:
+        raise ValueError(f"input has {g.shape[0]} rows, poset has {P.n}")
+    if out is None:
+        out = torch.empty_like(g, memory_format=torch.contiguous_format)
+    out2 = out if out.dim() == 2 else out.unsqueeze(1)
+    rep = _lib.RefineReport() if report else None
+    code = _dtype_code(g)
+    fn = getattr(_lib.lib(), fn_name)
+    _lib.check(fn(P.handle, code, ctypes.c_void_p(g.data_ptr()), _ld(g), ctypes.c_void_p(out2.data_ptr()),
+                  _ld(out2), int(g.shape[1]), int(max_refine), float(tol), _stream(g),
+                  ctypes.byref(rep) if rep is not None else None), fn_name)
+    return (out, rep.as_dict()) if report else out
+
+
+def mobius(P: Poset, g, out=None, max_refine: int = 3, tol: float = 0.0, report: bool = False):
+    """f = M g = Z^{-1} g (px_mobius).  float32 uses float64-residual refinement."""
+    return _mobius("px_mobius", P, g, out, max_refine, tol, report)
+
+
+def mobius_adjoint(P: Poset, v, out=None, max_refine: int = 3, tol: float = 0.0, report: bool = False):
+    """M^T v (px_mobius_adjoint)."""
+    return _mobius("px_mobius_adjoint", P, v, out, max_refine, tol, report)
+
+
+class Batch:
+    """Many posets run together (px_batch_build); matrices stack the posets' rows."""
+
+    def __init__(self, posets):
+        self.posets = list(posets)
+        arr = (ctypes.c_void_p * len(self.posets))(*[p.handle for p in self.posets])
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().px_batch_build(len(self.posets), arr, ctypes.byref(h)), "px_batch_build")
+        self._h = h
+        rows = ctypes.c_int64()
+        _lib.check(_lib.lib().px_batch_rows(h, ctypes.byref(rows)), "px_batch_rows")
+        self.rows = rows.value
+        self.offsets = np.concatenate([[0], np.cumsum([p.n for p in self.posets])]).astype(np.int64)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            try:
+                _lib.lib().px_batch_free(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("batch handle was freed")
+        return self._h
+
+    def reserve(self, dtype, B: int):
+        import torch
+        code = {torch.int64: 0, torch.float32: 1, torch.float64: 2}[dtype]
+        _lib.check(_lib.lib().px_batch_reserve(self.handle, code, int(B)), "px_batch_reserve")
+
+
+def batch_build(posets) -> Batch:
+    return Batch(posets)
+
+
+def _batched(fn_name, b, x, out):
+    import torch
+    x = _as_matrix(x, "input")
+    if x.shape[0] != b.rows:
+        raise ValueError(f"input has {x.shape[0]} rows, batch has {b.rows}")
+    if out is None:
+        out = torch.empty_like(x, memory_format=torch.contiguous_format)
+    fn = getattr(_lib.lib(), fn_name)
+    _lib.check(fn(b.handle, _dtype_code(x), ctypes.c_void_p(x.data_ptr()), _ld(x), ctypes.c_void_p(out.data_ptr()),
+                  _ld(out), int(x.shape[1]), _stream(x)), fn_name)
+    return out
+
+
+def zeta_batched(b: Batch, f, out=None):
+    return _batched("px_zeta_batched", b, f, out)
+
+
+def zeta_adjoint_batched(b: Batch, w, out=None):
+    return _batched("px_zeta_adjoint_batched", b, w, out)

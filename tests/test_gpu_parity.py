@@ -1,0 +1,356 @@
+"""GPU parity of the HIP path against the CPU oracle (run on an MI355X).
+
+Every case builds a seeded poset, runs the library through the C ABI
+(paper_2211_13706_amd, ctypes) and compares with the oracle computed from the
+same seeded inputs:
+  int64   bit-exact (wrap-around modulo 2**64);
+  float64 normwise relative error <= 1e-12;
+  float32 zeta: componentwise |g_hat - g| <= 3 u32 (Z|f|)(x), u32 = 2**-24
+          (compensated chain scan: each chain prefix within ~u32 of its exact
+          value; the k prefixes are added in float64; one final rounding), and
+          normwise per column <= 1e-5;
+  float32 Möbius after float64-residual refinement: normwise per column <= 1e-5
+          on the well-posed cases (grid, small posets).
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def px():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2211_13706_amd as px
+    px.lib()
+    return px
+
+
+def dev():
+    import torch
+    return torch.device("cuda:0")
+
+
+def T(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev())
+
+
+def H(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def build(px, p, planted=True, **kw):
+    return px.poset_build(p.n, p.indptr, p.indices, p.chain_of if planted else None,
+                          p.chain_pos if planted else None, device=0, **kw)
+
+
+def rel(a, b):
+    """Normwise relative error per column, max over columns."""
+    a = np.asarray(a, np.float64); b = np.asarray(b, np.float64)
+    den = np.maximum(np.abs(b).max(axis=0), 1e-300)
+    return float((np.abs(a - b).max(axis=0) / den).max())
+
+
+def check_f32_zeta(got, want, zabs):
+    got = np.asarray(got, np.float64)
+    assert (np.abs(got - want) <= 3 * U32 * zabs + 1e-30).all(), float((np.abs(got - want) / (zabs + 1e-30)).max())
+    assert rel(got, want) <= 1e-5
+
+
+# ------------------------------------------------------------- worked example
+@pytest.mark.parametrize("kind", ["int", "f32", "f64"])
+def test_worked_example_all_transforms(px, kind):
+    p = W.worked_example()
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = build(px, p)
+    f = W.functions(12, 3, "int", seed=7, lo=-50, hi=50)
+    if kind != "int":
+        f = f.astype(np.float32 if kind == "f32" else np.float64)
+    fi = f.astype(np.int64)
+    assert np.array_equal(H(px.zeta(P, T(f))).astype(np.int64), O.zeta(R, fi))
+    assert np.array_equal(H(px.zeta_adjoint(P, T(f))).astype(np.int64), O.zeta_adjoint(R, fi))
+    assert np.array_equal(H(px.mobius(P, T(f))).astype(np.int64), O.mobius(R, fi))
+    assert np.array_equal(H(px.mobius_adjoint(P, T(f))).astype(np.int64), O.mobius_adjoint(R, fi))
+
+
+# ---------------------------------------------------- config-0 shaped, int64
+@pytest.fixture(scope="module")
+def cfg0():
+    p = W.chain_poset(2000, 16, 4, seed=0)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    return p, R
+
+
+@pytest.mark.parametrize("B,ld", [(1, 1), (3, 5), (64, 64)])
+def test_cfg0_int64_bit_exact(px, cfg0, B, ld):
+    p, R = cfg0
+    P = build(px, p)
+    f = W.functions(p.n, B, "int", seed=1, lo=-100, hi=100)
+    fp = np.zeros((p.n, ld), np.int64); fp[:, :B] = f
+    ft = T(fp)[:, :B]
+    g = H(px.zeta(P, ft))
+    assert np.array_equal(g, O.zeta(R, f))
+    assert np.array_equal(H(px.mobius(P, T(g))), f)
+    assert np.array_equal(H(px.zeta_adjoint(P, ft)), O.zeta_adjoint(R, f))
+    # Möbius of an arbitrary g (not a zeta image): substitution oracle, exact mod 2**64
+    gr = W.functions(p.n, B, "int", seed=3, lo=-1000, hi=1000)
+    assert np.array_equal(H(px.mobius(P, T(gr))), O.mobius_by_substitution(R, gr))
+    assert np.array_equal(H(px.mobius_adjoint(P, T(gr))), O.mobius_adjoint_by_substitution(R, gr))
+
+
+def test_int64_wraparound(px, cfg0):
+    p, R = cfg0
+    P = build(px, p)
+    f = W.functions(p.n, 2, "int", seed=4, lo=-(2**62), hi=2**62)
+    g = H(px.zeta(P, T(f)))
+    assert np.array_equal(g, O.zeta(R, f))
+    assert np.array_equal(H(px.mobius(P, T(g))), f)
+
+
+def test_results_independent_of_decomposition_and_schedule(px, cfg0):
+    """Planted chains, matching chains, Mirsky and U-dependency schedules agree exactly."""
+    p, R = cfg0
+    f = T(W.functions(p.n, 4, "int", seed=5, lo=-100, hi=100))
+    ff = T(W.functions(p.n, 4, "normal", seed=5))
+    outs = []
+    for planted, flags in ((True, 0), (False, 0), (True, px.PX_BUILD_LEVELS_MIRSKY)):
+        P = build(px, p, planted=planted, flags=flags)
+        outs.append((H(px.zeta(P, f)), H(px.mobius(P, f)), H(px.mobius_adjoint(P, f)),
+                     H(px.mobius(P, ff, max_refine=0)), P.k))
+    for o in outs[1:]:
+        for a, b in zip(outs[0][:3], o[:3]):
+            assert np.array_equal(a, b)
+    # same chains, different schedule: the per-element float arithmetic is identical
+    assert np.array_equal(outs[0][3], outs[2][3])
+
+
+# ------------------------------------------------------------ float accuracy
+@pytest.mark.parametrize("B", [1, 5, 16, 64])
+def test_f32_zeta_tolerance(px, cfg0, B):
+    p, R = cfg0
+    P = build(px, p)
+    f = W.functions(p.n, B, "normal", seed=11 + B)
+    want = O.zeta(R, f, exact=False)
+    zabs = O.zeta(R, np.abs(f).astype(np.float64), exact=False)
+    check_f32_zeta(H(px.zeta(P, T(f))), want, zabs)
+    wantT = O.zeta_adjoint(R, f, exact=False)
+    zabsT = O.zeta_adjoint(R, np.abs(f).astype(np.float64), exact=False)
+    check_f32_zeta(H(px.zeta_adjoint(P, T(f))), wantT, zabsT)
+
+
+def test_f64_zeta_and_mobius(px, cfg0):
+    p, R = cfg0
+    P = build(px, p)
+    f = W.functions(p.n, 8, "normal64", seed=12)
+    g = H(px.zeta(P, T(f)))
+    assert rel(g, O.zeta(R, f, exact=False)) <= 1e-12
+    assert rel(H(px.zeta_adjoint(P, T(f))), O.zeta_adjoint(R, f, exact=False)) <= 1e-12
+    # Möbius on a zeta image returns f (well-posed: the data are consistent)
+    assert rel(H(px.mobius(P, T(g))), f) <= 1e-9
+
+
+def test_f32_mobius_refined_small_poset(px):
+    """g = Z f with integer f is exact in float32, so M g = f exactly is the target."""
+    p = W.chain_poset(1500, 12, 3, seed=21)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = build(px, p)
+    f = W.functions(p.n, 8, "int", seed=22, lo=-100, hi=100)
+    g32 = O.zeta(R, f).astype(np.float32)
+    got, rep = px.mobius(P, T(g32), max_refine=8, tol=1e-8, report=True)
+    assert rel(H(got), f) <= 1e-5, rep
+    assert not rep["nonfinite"]
+    v32 = O.zeta_adjoint(R, f).astype(np.float32)
+    gotT, repT = px.mobius_adjoint(P, T(v32), max_refine=8, tol=1e-8, report=True)
+    assert rel(H(gotT), f) <= 1e-5, repT
+
+
+# ------------------------------------------------------------ special cases
+@pytest.mark.parametrize("B", [1, 64])
+def test_chain_prefix_sum_and_difference(px, B):
+    p = W.chain_only(5000, seed=2)
+    P = build(px, p)
+    order = np.argsort(p.chain_pos)
+    f = W.functions(p.n, B, "int", seed=3, lo=-9, hi=9)
+    g = H(px.zeta(P, T(f)))
+    assert np.array_equal(g[order], np.cumsum(f[order], axis=0))
+    a = H(px.zeta_adjoint(P, T(f)))
+    assert np.array_equal(a[order], np.cumsum(f[order][::-1], axis=0)[::-1])
+    m = H(px.mobius(P, T(f)))
+    fo = f[order]
+    assert np.array_equal(m[order], fo - np.vstack([np.zeros((1, B), np.int64), fo[:-1]]))
+    ff = W.functions(p.n, B, "normal", seed=4)
+    gf = H(px.zeta(P, T(ff))).astype(np.float64)
+    ex = np.cumsum(ff[order].astype(np.float64), axis=0)
+    exabs = np.cumsum(np.abs(ff[order]).astype(np.float64), axis=0)
+    check_f32_zeta(gf[order], ex, exabs)
+
+
+def test_antichain_identity(px):
+    p = W.antichain(3000)
+    P = build(px, p, planted=False)
+    assert P.k == 3000
+    f = W.functions(p.n, 3, "normal", seed=5)
+    assert np.array_equal(H(px.zeta(P, T(f))), f)
+    assert np.array_equal(H(px.mobius(P, T(f), max_refine=0)), f)
+
+
+def test_boolean_lattice_yates(px):
+    m = 10
+    p = W.boolean_lattice(m)
+    P = build(px, p, planted=False)
+    assert P.k == 252
+    f = W.functions(p.n, 4, "int", seed=6, lo=-9, hi=9)
+    want = f.copy()
+    for e in range(m):
+        bit = 1 << e
+        idx = np.nonzero(np.arange(p.n) & bit)[0]
+        want[idx] += want[idx ^ bit]
+    g = H(px.zeta(P, T(f)))
+    assert np.array_equal(g, want)
+    assert np.array_equal(H(px.mobius(P, T(g))), f)
+    # μ(S,T) = (-1)^{|T \ S|}: Möbius of the indicator of the empty set's zeta column
+    pc = np.array([bin(v).count("1") for v in range(p.n)])
+    e0 = np.zeros((p.n, 1), np.int64); e0[p.n - 1] = 1        # f = delta at the full set
+    mt = H(px.mobius_adjoint(P, T(e0)))[:, 0]                  # M^T e_full = μ(·, full)
+    assert np.array_equal(mt, 1 - 2 * ((m - pc) % 2))
+
+
+def _grid_closed_forms(g3):
+    h, w, B = g3.shape
+    pad = np.zeros((h + 1, w + 1, B), g3.dtype); pad[1:, 1:] = g3
+    return pad[1:, 1:] - pad[:-1, 1:] - pad[1:, :-1] + pad[:-1, :-1]
+
+
+def test_grid_config2_int64(px):
+    h, w = 4096, 64
+    p = W.grid_poset(h, w)
+    P = build(px, p)
+    assert P.info["udep_levels"] == 64
+    f = W.functions(p.n, 16, "int", seed=8, lo=-1000, hi=1000)
+    g = H(px.zeta(P, T(f)))
+    assert np.array_equal(g.reshape(h, w, 16), f.reshape(h, w, 16).cumsum(0).cumsum(1))
+    assert np.array_equal(H(px.mobius(P, T(g))), f)
+    gr = W.functions(p.n, 16, "int", seed=9, lo=-1000, hi=1000)
+    assert np.array_equal(H(px.mobius(P, T(gr))).reshape(h, w, 16), _grid_closed_forms(gr.reshape(h, w, 16)))
+
+
+def test_grid_config2_f32_refined(px):
+    h, w, B = 4096, 64, 16
+    p = W.grid_poset(h, w)
+    P = build(px, p)
+    g = W.functions(p.n, B, "uniform", seed=10, lo=-1.0, hi=1.0)
+    want = _grid_closed_forms(g.astype(np.float64).reshape(h, w, B)).reshape(p.n, B)
+    got, rep = px.mobius(P, T(g), max_refine=5, tol=1e-7, report=True)
+    assert rel(H(got), want) <= 1e-5, rep
+    plain = H(px.mobius(P, T(g), max_refine=0))
+    got64 = H(px.mobius(P, T(g.astype(np.float64))))
+    assert rel(got64, want) <= 1e-12
+    print(f"grid f32 Möbius: plain err {rel(plain, want):.2e}, refined {rel(H(got), want):.2e}, {rep}")
+
+
+# ------------------------------------------------------- full-size, sampled
+@pytest.fixture(scope="module")
+def cfg1():
+    p = W.chain_poset(1 << 20, 64, 3, seed=1)
+    rng = np.random.default_rng(17)
+    nodes = np.concatenate([rng.choice(p.n, 6, replace=False), [int(np.argmax(p.chain_pos)), 0]])
+    return p, nodes
+
+
+def test_config1_f32_zeta_sampled(px, cfg1):
+    p, nodes = cfg1
+    P = build(px, p)
+    f = W.functions(p.n, 64, "normal", seed=2)
+    g = H(px.zeta(P, T(f)))[nodes]
+    want = O.zeta_at(p.n, p.indptr, p.indices, f, nodes)
+    zabs = O.zeta_at(p.n, p.indptr, p.indices, np.abs(f), nodes)
+    check_f32_zeta(g, want, zabs)
+
+
+def test_config1_int64_zeta_sampled_and_roundtrip(px, cfg1):
+    p, nodes = cfg1
+    P = build(px, p)
+    f = W.functions(p.n, 64, "int", seed=3, lo=-1000, hi=1000)
+    ft = T(f)
+    g = px.zeta(P, ft)
+    assert np.array_equal(H(g)[nodes], O.zeta_at(p.n, p.indptr, p.indices, f, nodes))
+    # Möbius(zeta(f)) = f exactly at every element (Corollary 1), at full size
+    assert np.array_equal(H(px.mobius(P, g)), f)
+    a = H(px.zeta_adjoint(P, ft))[nodes]
+    assert np.array_equal(a, O.zeta_adjoint_at(p.n, p.indptr, p.indices, f, nodes))
+    assert np.array_equal(H(px.mobius_adjoint(P, px.zeta_adjoint(P, ft))), f)
+
+
+# ----------------------------------------------------------------- autograd
+def test_autograd_gradcheck_and_dense_transpose(px):
+    import torch
+    from paper_2211_13706_amd.autograd import mobius_fn, zeta_fn
+    p = W.chain_poset(60, 5, 3, seed=30)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = build(px, p)
+    f = torch.randn(p.n, 3, dtype=torch.float64, device=dev(), requires_grad=True)
+    assert torch.autograd.gradcheck(lambda x: zeta_fn(P, x), (f,), eps=1e-6, atol=1e-7)
+    assert torch.autograd.gradcheck(lambda x: mobius_fn(P, x), (f,), eps=1e-6, atol=1e-7)
+    # the Jacobian of zeta is the dense closure Z; its transpose is what backward applies
+    w = torch.randn(p.n, 3, dtype=torch.float64, device=dev())
+    y = zeta_fn(P, f)
+    (gf,) = torch.autograd.grad((y * w).sum(), f)
+    assert np.allclose(H(gf), R.astype(np.float64).T @ H(w), rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------------------ batched
+def test_batched_zeta_and_adjoint(px):
+    import torch
+    from paper_2211_13706_amd.autograd import batch_zeta_fn
+    posets = W.batched_posets(16, seed=40, nmin=100, nmax=1500)
+    Ps = [build(px, q) for q in posets]
+    b = px.batch_build(Ps)
+    f = W.functions(b.rows, 8, "int", seed=41, lo=-100, hi=100)
+    g = H(px.zeta_batched(b, T(f)))
+    a = H(px.zeta_adjoint_batched(b, T(f)))
+    for i, q in enumerate(posets):
+        s, e = b.offsets[i], b.offsets[i + 1]
+        R = O.reachability(q.n, q.indptr, q.indices)
+        assert np.array_equal(g[s:e], O.zeta(R, f[s:e]))
+        assert np.array_equal(a[s:e], O.zeta_adjoint(R, f[s:e]))
+    # autograd through the batch: loss = Σ w·ζ(f), gradient = Z^T w per poset
+    ff = torch.randn(b.rows, 8, dtype=torch.float32, device=dev(), requires_grad=True)
+    w = torch.randn(b.rows, 8, dtype=torch.float32, device=dev())
+    (batch_zeta_fn(b, ff) * w).sum().backward()
+    grad = H(ff.grad).astype(np.float64)
+    for i, q in enumerate(posets[:4]):
+        s, e = b.offsets[i], b.offsets[i + 1]
+        R = O.reachability(q.n, q.indptr, q.indices)
+        want = R.astype(np.float64).T @ H(w)[s:e].astype(np.float64)
+        zabs = R.astype(np.float64).T @ np.abs(H(w)[s:e]).astype(np.float64)
+        assert (np.abs(grad[s:e] - want) <= 3 * U32 * zabs + 1e-30).all()
+
+
+# ------------------------------------------------------------ error handling
+def test_argument_errors_and_nonfinite(px, cfg0):
+    import torch
+    p, _ = cfg0
+    P = build(px, p)
+    f = T(W.functions(p.n, 4, "normal", seed=1))
+    with pytest.raises(px.PosetxError) as e:
+        px.mobius(P, f, out=f)
+    assert e.value.name == "PX_EINVAL"
+    with pytest.raises(ValueError):
+        px.zeta(P, f[:10])
+    c = W.chain_only(4)
+    Pc = build(px, c)
+    g = T(np.array([[3e38], [-3e38], [3e38], [-3e38]], np.float32))
+    with pytest.raises(px.PosetxError) as e:
+        px.mobius(Pc, g, max_refine=2, tol=1e-6)
+    assert e.value.name == "PX_ENONFINITE"
+    torch.cuda.synchronize()

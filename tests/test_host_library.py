@@ -1,0 +1,187 @@
+"""CPU tests of the C-ABI library: it loads, exports what include/posetx.h declares,
+and its host preprocessing (chains, niv, up-niv, levels, validation) matches the
+oracle's definitions.  No compute calls: these run without a GPU."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def px():
+    import paper_2211_13706_amd as px
+    from paper_2211_13706_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2211_13706_amd.build import build
+        build()
+    px.lib()
+    return px
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "posetx.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(px_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(px):
+    from paper_2211_13706_amd import _lib
+    declared = _declared_functions()
+    assert len(declared) >= 20
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), f"{name} declared in posetx.h but not exported"
+    assert sorted(_lib.EXPORTS) == declared
+
+
+def _host(px, p, **kw):
+    return px.poset_build(p.n, p.indptr, p.indices, p.chain_of if kw.get("planted", True) else None,
+                          p.chain_pos if kw.get("planted", True) else None,
+                          flags=px.PX_BUILD_HOST_ONLY | kw.get("flags", 0))
+
+
+def _check_against_closure(px, P, p, R):
+    co, cp = P.chains()
+    k = P.k
+    # chains are totally ordered, positions 0..len-1
+    for c in range(k):
+        nodes = np.nonzero(co == c)[0]
+        nodes = nodes[np.argsort(cp[nodes])]
+        assert list(cp[nodes]) == list(range(nodes.size))
+        assert R[nodes[1:], nodes[:-1]].all()
+    niv = P.niv()
+    assert np.array_equal(niv, O.niv_from_closure(R, co, cp, k))
+    # up-niv is niv of the dual order, lowest element above: read it off R^T
+    RT = np.ascontiguousarray(R.T)
+    up = P.niv(up=True)
+    want = np.full_like(up, -1)
+    for x in range(p.n):
+        above = np.nonzero(RT[x])[0]
+        for j in range(k):
+            cand = above[co[above] == j]
+            if cand.size:
+                want[x, j] = cand[np.argmin(cp[cand])]
+    assert np.array_equal(up, want)
+    # schedules: every U-solve dependency lies on a strictly lower level
+    for upflag, nv in ((False, niv), (True, up)):
+        lev = P.levels(up=upflag)
+        for x in range(p.n):
+            deps = [t for j, t in enumerate(nv[x]) if t >= 0 and j != co[x]]
+            assert all(lev[t] < lev[x] for t in deps)
+    info = P.info
+    assert info["nnz_niv"] == int((niv >= 0).sum())
+    assert info["mirsky_levels"] == O.mirsky_levels(R).max() + 1
+
+
+@pytest.mark.parametrize("case", ["example", "cfg0", "lattice6", "grid", "random"])
+@pytest.mark.parametrize("planted", [True, False])
+def test_preprocessing_matches_closure(px, case, planted):
+    p = {"example": W.worked_example, "cfg0": lambda: W.chain_poset(600, 16, 4, seed=0),
+         "lattice6": lambda: W.boolean_lattice(6), "grid": lambda: W.grid_poset(20, 7),
+         "random": lambda: W.random_small_dag(90, 0.08, 3)}[case]()
+    if planted and p.chain_of is None:
+        pytest.skip("no planted chains for this poset")
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = _host(px, p, planted=planted)
+    if planted:
+        assert P.k == p.k_planted
+    _check_against_closure(px, P, p, R)
+
+
+def test_matching_chains_reach_width(px):
+    """Alg. 1 on the cover graph of the worked example and a Boolean lattice gives the width."""
+    P = _host(px, W.worked_example(), planted=False)
+    assert P.k == 4
+    P = _host(px, W.boolean_lattice(10), planted=False)
+    assert P.k == 252            # C(10, 5), Sperner / Dilworth
+
+
+def test_mirsky_schedule_flag(px):
+    p = W.worked_example()
+    P = _host(px, p, flags=px.PX_BUILD_LEVELS_MIRSKY)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    assert np.array_equal(P.levels(), O.mirsky_levels(R))
+    assert P.info["levels_down"] == 5
+
+
+def _err(px, fn):
+    with pytest.raises(px.PosetxError) as ei:
+        fn()
+    return ei.value.name
+
+
+def test_rejects_bad_input(px):
+    p = W.worked_example()
+    # cycle: add an edge from a minimal element back up to the top
+    src, dst = p.edges()
+    src2 = np.concatenate([src, [11]]); dst2 = np.concatenate([dst, [0]])
+    order = np.argsort(src2, kind="stable")
+    indptr = np.zeros(13, np.int64); np.cumsum(np.bincount(src2, minlength=12), out=indptr[1:])
+    assert _err(px, lambda: px.poset_build(12, indptr, dst2[order], flags=px.PX_BUILD_HOST_ONLY)) == "PX_ECYCLE"
+    # self-loop
+    ind = p.indices.copy(); ind[0] = 0
+    assert _err(px, lambda: px.poset_build(12, p.indptr, ind, flags=px.PX_BUILD_HOST_ONLY)) == "PX_EINVAL"
+    # out-of-range target
+    ind = p.indices.copy(); ind[1] = 99
+    assert _err(px, lambda: px.poset_build(12, p.indptr, ind, flags=px.PX_BUILD_HOST_ONLY)) == "PX_EINVAL"
+    # planted chain that is not totally ordered: swap two incomparable elements' chains
+    co, cp = p.chain_of.copy(), p.chain_pos.copy()
+    co[[4, 5]] = co[[5, 4]]; cp[[4, 5]] = cp[[5, 4]]     # x5 and x6 are incomparable
+    assert _err(px, lambda: px.poset_build(12, p.indptr, p.indices, co, cp,
+                                           flags=px.PX_BUILD_HOST_ONLY)) == "PX_ECHAIN"
+    # reversed chain order
+    cp2 = p.chain_pos.copy()
+    c0 = np.nonzero(p.chain_of == 0)[0]; cp2[c0] = cp2[c0].max() - cp2[c0]
+    assert _err(px, lambda: px.poset_build(12, p.indptr, p.indices, p.chain_of, cp2,
+                                           flags=px.PX_BUILD_HOST_ONLY)) == "PX_ECHAIN"
+    # duplicate chain position
+    cp3 = p.chain_pos.copy(); cp3[c0[0]] = cp3[c0[1]]
+    assert _err(px, lambda: px.poset_build(12, p.indptr, p.indices, p.chain_of, cp3,
+                                           flags=px.PX_BUILD_HOST_ONLY)) == "PX_EINVAL"
+
+
+def test_empty_and_trivial_posets(px):
+    P = px.poset_build(0, np.zeros(1, np.int64), np.zeros(0, np.int32), flags=px.PX_BUILD_HOST_ONLY)
+    assert P.k == 0 and P.n == 0
+    P = _host(px, W.antichain(7), planted=False)
+    assert P.k == 7 and P.info["levels_down"] == 1
+    assert (P.niv() == np.where(np.eye(7, dtype=bool), np.arange(7)[:, None], -1)).all()
+
+
+def test_duplicate_and_transitive_edges(px):
+    p = W.worked_example()
+    src, dst = p.edges()
+    # add duplicates and the transitive edge x1 -> x12
+    src2 = np.concatenate([src, src[:5], [0]]); dst2 = np.concatenate([dst, dst[:5], [11]])
+    order = np.argsort(src2, kind="stable")
+    indptr = np.zeros(13, np.int64); np.cumsum(np.bincount(src2, minlength=12), out=indptr[1:])
+    P = px.poset_build(12, indptr, dst2[order], p.chain_of, p.chain_pos, flags=px.PX_BUILD_HOST_ONLY)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    assert np.array_equal(P.niv(), O.niv_from_closure(R, p.chain_of, p.chain_pos, 4))
+
+
+def test_config1_preprocessing_scale(px):
+    """The n = 2^20, k = 64 poset preprocesses on the host in seconds; niv invariants hold."""
+    p = W.chain_poset(1 << 16, 64, 3, seed=1)
+    P = _host(px, p)
+    info = P.info
+    assert info["k"] == 64 and info["max_chain"] == 1024
+    niv = P.niv()
+    co, cp = P.chains()
+    # own chain entry is the element itself (Theorem 5, second case)
+    assert (niv[np.arange(p.n), co] == np.arange(p.n)).all()
+    # niv is monotone along every chain: x below y implies out(x) ⊆ out(y)
+    for c in range(0, 64, 16):
+        nodes = np.nonzero(co == c)[0]
+        nodes = nodes[np.argsort(cp[nodes])]
+        pos = np.where(niv[nodes] >= 0, cp[np.maximum(niv[nodes], 0)], -1)
+        assert (np.diff(pos, axis=0) >= 0).all()
+    assert info["udep_levels"] < info["mirsky_levels"]
