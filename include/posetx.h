@@ -88,9 +88,11 @@ typedef struct {
 } px_info;
 
 typedef struct {
-  int32_t iterations;     /* refinement steps taken                                      */
-  int32_t nonfinite;      /* 1 if a residual held NaN or Inf                             */
-  double residual;        /* max over columns of ||g - zeta(f)||_inf / ||g||_inf (float64) */
+  int32_t iterations;     /* refinement steps taken                                        */
+  int32_t nonfinite;      /* 1 if a correction, the iterate or the residual held NaN or Inf */
+  double residual;        /* max over columns of ||g - zeta(f)||_inf / ||g||_inf, float64,
+                             for the returned f (normwise backward error)                  */
+  double correction;      /* max over columns of ||delta||_inf / ||f||_inf of the last step */
 } px_refine_report;
 
 /*
@@ -147,14 +149,18 @@ px_status px_zeta_adjoint(px_poset* p, int dtype, const void* w, int64_t ldw, vo
  * of U y' = g, then f = V^{-1} y' (first difference along every chain).
  *   PX_I64: exact; max_refine and tol are ignored.
  *   PX_F64: float64 solve; no refinement.
- *   PX_F32: float32 solve, then up to max_refine steps of iterative refinement
- *           r = g - zeta(f) in float64, f += M r (float32 solve).  tol > 0 stops
- *           early once ||r||_inf <= tol * ||g||_inf for every column; this check
- *           synchronises the stream each step.  tol <= 0 runs exactly max_refine
- *           steps with no host synchronisation.
- *   rep        NULL or receives the refinement report; non-NULL synchronises.
- * g and f must not overlap.  Returns PX_ENONFINITE if a residual is not finite, and
- * PX_ENOTCONV if tol > 0 was not reached within max_refine steps (f is still written).
+ *   PX_F32: float32 solve, then up to max_refine steps of iterative refinement:
+ *           r = g - zeta(f) with zeta applied in float64, delta = M r (float32
+ *           solve), f += delta.  tol > 0 stops early once every column has
+ *           ||delta||_inf <= tol * ||f||_inf (a forward-error test: the residual
+ *           itself is floored by the float32 rounding of f summed over down-sets);
+ *           this check synchronises the stream each step.  tol <= 0 runs exactly
+ *           max_refine steps with no host synchronisation.
+ *   rep        NULL or receives the refinement report (computes the final residual;
+ *              synchronises).
+ * g and f must not overlap.  Returns PX_ENONFINITE if a correction or the iterate is
+ * not finite, and PX_ENOTCONV if tol > 0 and max_refine > 0 and the correction test
+ * was not met within max_refine steps (f is still written).
  */
 px_status px_mobius(px_poset* p, int dtype, const void* g, int64_t ldg, void* f, int64_t ldf,
                     int64_t B, int max_refine, double tol, void* stream, px_refine_report* rep);

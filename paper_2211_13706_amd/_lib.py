@@ -48,10 +48,12 @@ class Info(ctypes.Structure):
 
 
 class RefineReport(ctypes.Structure):
-    _fields_ = [("iterations", ctypes.c_int32), ("nonfinite", ctypes.c_int32), ("residual", ctypes.c_double)]
+    _fields_ = [("iterations", ctypes.c_int32), ("nonfinite", ctypes.c_int32), ("residual", ctypes.c_double),
+                ("correction", ctypes.c_double)]
 
     def as_dict(self):
-        return {"iterations": self.iterations, "nonfinite": bool(self.nonfinite), "residual": self.residual}
+        return {"iterations": self.iterations, "nonfinite": bool(self.nonfinite), "residual": self.residual,
+                "correction": self.correction}
 
 
 def _declare(lib):

@@ -99,6 +99,29 @@ void seg_tables(const std::vector<int32_t>& chain_off, std::vector<int32_t>& seg
   }
 }
 
+// Runs of `T` rows along every chain for the walking gather, ordered by the
+// relative height of the run inside its chain (ties by chain), so that the
+// waves resident together cover one height band of every chain.
+constexpr int kWalkT = 128;
+std::vector<int32_t> walk_table(const std::vector<int32_t>& chain_off, int T) {
+  struct Run {
+    double h;
+    int32_t c, r0;
+  };
+  std::vector<Run> runs;
+  const int64_t nc = (int64_t)chain_off.size() - 1;
+  for (int64_t c = 0; c < nc; ++c) {
+    const int64_t len = chain_off[c + 1] - chain_off[c];
+    const int64_t nq = (len + T - 1) / T;
+    for (int64_t q = 0; q < nq; ++q)
+      runs.push_back({(q + 0.5) / (double)nq, (int32_t)c, (int32_t)(chain_off[c] + q * T)});
+  }
+  std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) { return a.h < b.h; });
+  std::vector<int32_t> out(runs.size());
+  for (size_t i = 0; i < runs.size(); ++i) out[i] = runs[i].r0;
+  return out;
+}
+
 struct Layout {
   size_t y = 0, p64 = 0, r64 = 0, aux = 0, stats = 0, total = 0;
 };
@@ -201,9 +224,9 @@ hipError_t run_gather(const px::DevPoset& d, bool up, px::ElemType tp, const voi
 }
 
 hipError_t run_chain_diff(const px::DevPoset& d, int dir, px::ElemType ty, const void* Y, int64_t B,
-                          px::ElemType tout, void* out, int64_t ldo, bool acc, hipStream_t s) {
+                          px::ElemType tout, void* out, int64_t ldo, bool acc, uint64_t* stats, hipStream_t s) {
   prof::Scope sc(prof::CHAIN_DIFF, s);
-  return px::launch_chain_diff(d, dir, ty, Y, B, tout, out, ldo, acc, s);
+  return px::launch_chain_diff(d, dir, ty, Y, B, tout, out, ldo, acc, stats, s);
 }
 
 }  // namespace
@@ -213,8 +236,10 @@ struct px_poset {
   int device = 0;
   bool host_only = false, has_up = false, mirsky = false;
   int32_t *d_node_of_row = nullptr, *d_chain_of_row = nullptr, *d_chain_off = nullptr, *d_niv = nullptr,
-          *d_niv_up = nullptr, *d_lev_down = nullptr, *d_lev_up = nullptr, *d_segoff = nullptr;
+          *d_niv_up = nullptr, *d_lev_down = nullptr, *d_lev_up = nullptr, *d_segoff = nullptr,
+          *d_walk = nullptr;
   int64_t ntiles[7] = {0, 0, 0, 0, 0, 0, 0};
+  int32_t nwalk = 0;
   px::DevPoset dp;
   Workspace ws;
   int64_t device_bytes = 0;
@@ -237,8 +262,8 @@ struct px_batch {
 namespace {
 
 void free_poset_device(px_poset* p) {
-  int32_t* bufs[] = {p->d_node_of_row, p->d_chain_of_row, p->d_chain_off, p->d_niv,
-                     p->d_niv_up,      p->d_lev_down,     p->d_lev_up,    p->d_segoff};
+  int32_t* bufs[] = {p->d_node_of_row, p->d_chain_of_row, p->d_chain_off, p->d_niv, p->d_niv_up,
+                     p->d_lev_down,     p->d_lev_up,       p->d_segoff,    p->d_walk};
   for (int32_t* b : bufs)
     if (b) (void)hipFree(b);
   p->ws.release();
@@ -299,7 +324,7 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   if (st != PX_OK) return st;
   if (max_refine < 0) return fail(PX_EINVAL, "max_refine must be >= 0");
   const int64_t n = p->prep.n;
-  if (rep) *rep = px_refine_report{0, 0, 0.0};
+  if (rep) *rep = px_refine_report{0, 0, 0.0, 0.0};
   if (n == 0) return PX_OK;
   {
     const char* gb = (const char*)g;
@@ -321,7 +346,7 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   const px::ElemType T = etype(dtype);
   const int dir = up ? -1 : 1;
   hipError_t e = solve_levels(p, up, T, g, ldg, T, w + L.y, B, s);
-  if (e == hipSuccess) e = run_chain_diff(p->dp, dir, T, w + L.y, B, T, f, ldf, false, s);
+  if (e == hipSuccess) e = run_chain_diff(p->dp, dir, T, w + L.y, B, T, f, ldf, false, nullptr, s);
   if (e != hipSuccess) return hip_status(e, "mobius launch");
   if (!refine) return PX_OK;
 
@@ -329,58 +354,65 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   double* r64 = (double*)(w + L.r64);
   uint64_t* dstats = (uint64_t*)(w + L.stats);
   std::vector<uint64_t> hstats(2 * B + 1);
-  // r = g - zeta(f) in float64; returns the normwise residual ratio (max over columns)
-  auto residual = [&](double& ratio, bool& nonfinite) -> px_status {
-    hipError_t e2 = run_scan(p->dp, dir, px::E_F32, f, ldf, px::E_F64, w + L.p64, B, w + L.aux, nt, s);
-    if (e2 == hipSuccess)
-      e2 = run_gather(p->dp, up, px::E_F64, w + L.p64, B, px::E_F64, r64, B, px::E_F32, g, ldg, s);
-    if (e2 != hipSuccess) return hip_status(e2, "residual launch");
-    if (!check) return PX_OK;
-    {
-      prof::Scope sc(prof::ABSMAX, s);
-      e2 = px::launch_absmax(n, B, r64, px::E_F32, g, ldg, dstats, s);
-    }
-    if (e2 == hipSuccess) e2 = hipMemcpyAsync(hstats.data(), dstats, hstats.size() * 8, hipMemcpyDeviceToHost, s);
+  // Largest over columns of stats[col] / stats[B + col] (float64 bit patterns).
+  auto read_ratio = [&](double& ratio, bool& nonfinite) -> px_status {
+    hipError_t e2 = hipMemcpyAsync(hstats.data(), dstats, hstats.size() * 8, hipMemcpyDeviceToHost, s);
     if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
-    if (e2 != hipSuccess) return hip_status(e2, "residual statistics");
-    nonfinite = hstats[2 * B] != 0;
+    if (e2 != hipSuccess) return hip_status(e2, "refinement statistics");
+    nonfinite = nonfinite || hstats[2 * B] != 0;
     ratio = 0;
     for (int64_t c = 0; c < B; ++c) {
-      double rn, gn;
-      std::memcpy(&rn, &hstats[c], 8);
-      std::memcpy(&gn, &hstats[B + c], 8);
-      ratio = std::max(ratio, gn > 0 ? rn / gn : rn);
+      double num, den;
+      std::memcpy(&num, &hstats[c], 8);
+      std::memcpy(&den, &hstats[B + c], 8);
+      ratio = std::max(ratio, den > 0 ? num / den : num);
     }
     return PX_OK;
   };
+  // r = g - zeta(f), zeta applied in float64 to the float32 iterate.
+  auto residual = [&]() -> hipError_t {
+    hipError_t e2 = run_scan(p->dp, dir, px::E_F32, f, ldf, px::E_F64, w + L.p64, B, w + L.aux, nt, s);
+    if (e2 == hipSuccess)
+      e2 = run_gather(p->dp, up, px::E_F64, w + L.p64, B, px::E_F64, r64, B, px::E_F32, g, ldg, s);
+    return e2;
+  };
   int it = 0;
-  double ratio = 0;
+  double corr = 0, resid = 0;
   bool nonfinite = false, converged = false;
-  for (; it < max_refine; ++it) {
-    if ((st = residual(ratio, nonfinite)) != PX_OK) return st;
+  while (it < max_refine) {
+    e = residual();
+    if (e == hipSuccess) e = solve_levels(p, up, px::E_F64, r64, B, px::E_F32, w + L.y, B, s);
+    if (e == hipSuccess)
+      e = run_chain_diff(p->dp, dir, px::E_F32, w + L.y, B, px::E_F32, f, ldf, true, check ? dstats : nullptr, s);
+    if (e != hipSuccess) return hip_status(e, "refinement launch");
+    ++it;
     if (check) {
+      // stop on the size of the correction relative to the iterate (forward error)
+      if ((st = read_ratio(corr, nonfinite)) != PX_OK) return st;
       if (nonfinite) break;
-      if (tol > 0 && ratio <= tol) {
+      if (tol > 0 && corr <= tol) {
         converged = true;
         break;
       }
     }
-    e = solve_levels(p, up, px::E_F64, r64, B, px::E_F32, w + L.y, B, s);
-    if (e == hipSuccess) e = run_chain_diff(p->dp, dir, px::E_F32, w + L.y, B, px::E_F32, f, ldf, true, s);
-    if (e != hipSuccess) return hip_status(e, "refinement launch");
-  }
-  if (check && !converged && !nonfinite) {
-    if ((st = residual(ratio, nonfinite)) != PX_OK) return st;
-    converged = tol > 0 && ratio <= tol;
   }
   if (rep) {
+    // normwise backward error of the returned f
+    e = residual();
+    if (e == hipSuccess) {
+      prof::Scope sc(prof::ABSMAX, s);
+      e = px::launch_absmax(n, B, r64, px::E_F32, g, ldg, dstats, s);
+    }
+    if (e != hipSuccess) return hip_status(e, "residual statistics");
+    if ((st = read_ratio(resid, nonfinite)) != PX_OK) return st;
     rep->iterations = it;
     rep->nonfinite = nonfinite ? 1 : 0;
-    rep->residual = ratio;
+    rep->residual = resid;
+    rep->correction = corr;
   }
-  if (nonfinite) return fail(PX_ENONFINITE, "refinement residual is not finite");
-  if (tol > 0 && !converged)
-    return fail(PX_ENOTCONV, "refinement stopped at residual " + std::to_string(ratio) + " > tol");
+  if (nonfinite) return fail(PX_ENONFINITE, "refinement met a non-finite value");
+  if (tol > 0 && max_refine > 0 && !converged)
+    return fail(PX_ENOTCONV, "refinement stopped with correction " + std::to_string(corr) + " > tol");
   return PX_OK;
 }
 
@@ -456,6 +488,11 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
     if (e == hipSuccess) e = upload(&p->d_lev_down, P.lev_down_rows.data(), P.lev_down_rows.size(), b);
     if (e == hipSuccess && p->has_up) e = upload(&p->d_lev_up, P.lev_up_rows.data(), P.lev_up_rows.size(), b);
     if (e == hipSuccess) e = upload(&p->d_segoff, segoff.data(), segoff.size(), b);
+    if (e == hipSuccess) {
+      std::vector<int32_t> wt = walk_table(P.chain_off, kWalkT);
+      p->nwalk = (int32_t)wt.size();
+      e = upload(&p->d_walk, wt.data(), wt.size(), b);
+    }
     if (e != hipSuccess) {
       (void)hipGetLastError();
       free_poset_device(p);
@@ -475,6 +512,9 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
   d.niv = p->d_niv;
   d.niv_up = p->d_niv_up;
   d.segoff = p->d_segoff;
+  d.walk = p->d_walk;
+  d.nwalk = p->nwalk;
+  d.walk_T = kWalkT;
   *out = p;
   return PX_OK;
 }

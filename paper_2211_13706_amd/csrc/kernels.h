@@ -24,6 +24,10 @@ struct DevPoset {
   const int32_t* niv = nullptr;         // [n*k] or, for a batch, at niv_off[poset]
   const int32_t* niv_up = nullptr;
   const int32_t* segoff = nullptr;      // [7][nchains+1] tile offsets per tile height
+  // walk segments of the gather: first row of each run of walk_T rows of one
+  // chain, ordered by relative height (single posets only)
+  const int32_t* walk = nullptr;
+  int32_t nwalk = 0, walk_T = 0;
   // batch only
   const int64_t* niv_off = nullptr;     // element offset of each poset's niv block
   const int32_t* poset_of_row = nullptr;
@@ -63,8 +67,11 @@ hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_ro
 
 // y = V^{-1} y' (dir=+1: minus the element below in the chain; dir=-1: minus the
 // element above).  accumulate: out += result instead of out = result.
+// stats (nullable, float32/float64 only): 2B+1 uint64 words that receive the
+// per-column max |correction|, max |result| and a non-finite flag.
 hipError_t launch_chain_diff(const DevPoset& d, int dir, ElemType ty, const void* Y, int64_t B,
-                             ElemType tout, void* out, int64_t ldo, bool accumulate, hipStream_t s);
+                             ElemType tout, void* out, int64_t ldo, bool accumulate, uint64_t* stats,
+                             hipStream_t s);
 
 // Per-column max|r| (float64 [n, B], ld B) and max|g| (type tg, ld ldg) plus a
 // non-finite flag into stats[2*B + 1] (as uint64 bit patterns / 0-1).

@@ -13,6 +13,8 @@
 // MFMA.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace px {
@@ -116,16 +118,21 @@ __global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw
   const int64_t end = d.chain_off[c + 1];
   const int lane = threadIdx.x % cw, rg = threadIdx.x / cw;
   const int64_t col = (int64_t)blockIdx.y * cw + lane;
+  const int64_t colc = col < B ? col : 0;
+  const int64_t r0 = base + (int64_t)rg * RPT;
+  // row indices first, then every load unconditionally (rows clamped into the
+  // chain, columns into the matrix), so that all RPT loads are in flight together
+  int32_t nodes[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) nodes[i] = d.node_of_row[min(r0 + i, end - 1)];
+  Tin v[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) v[i] = x[(int64_t)nodes[i] * ldx + colc];
   St st;
   st.zero();
-  if (col < B) {
-    const int64_t r0 = base + (int64_t)rg * RPT;
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      int64_t r = r0 + i;
-      if (r < end) st.add(Tr::in(x[(int64_t)d.node_of_row[r] * ldx + col]));
-    }
-  }
+  for (int i = 0; i < RPT; ++i)
+    if (r0 + i < end) st.add(Tr::in(v[i]));
   sm[threadIdx.x] = st;
   __syncthreads();
   if (rg == 0 && col < B) {
@@ -146,15 +153,24 @@ __global__ __launch_bounds__(WG) void k_scan_carry(DevPoset d, int segi, int dir
   const int32_t* so = d.segoff + (int64_t)segi * (d.nchains + 1);
   St carry;
   carry.zero();
-  if (dir > 0) {
-    for (int t = so[c]; t < so[c + 1]; ++t) {
-      C[(int64_t)t * B + col] = carry;
-      carry.combine(A[(int64_t)t * B + col]);
+  const int t0 = so[c], t1 = so[c + 1];
+  constexpr int CH = 16;  // tile totals loaded per round trip
+  for (int base = 0; base < t1 - t0; base += CH) {
+    St a[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = min(base + u, t1 - t0 - 1);
+      const int t = dir > 0 ? t0 + i : t1 - 1 - i;
+      a[u] = A[(int64_t)t * B + col];
     }
-  } else {
-    for (int t = so[c + 1] - 1; t >= so[c]; --t) {
-      C[(int64_t)t * B + col] = carry;
-      carry.combine(A[(int64_t)t * B + col]);
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = base + u;
+      if (i < t1 - t0) {
+        const int t = dir > 0 ? t0 + i : t1 - 1 - i;
+        C[(int64_t)t * B + col] = carry;
+        carry.combine(a[u]);
+      }
     }
   }
 }
@@ -179,14 +195,18 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw,
   const int lane = threadIdx.x % cw, rg = threadIdx.x / cw;
   const int64_t col = (int64_t)blockIdx.y * cw + lane;
   const int64_t r0 = base + (int64_t)rg * RPT;
+  const int64_t colc = col < B ? col : 0;
+  int32_t nodes[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) nodes[i] = d.node_of_row[min(r0 + i, end - 1)];
+  Tin raw[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) raw[i] = x[(int64_t)nodes[i] * ldx + colc];
   Tv v[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) v[i] = (r0 + i < end) ? Tr::in(raw[i]) : Tv(0);
   St loc;
   loc.zero();
-#pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    int64_t r = r0 + i;
-    v[i] = (col < B && r < end) ? Tr::in(x[(int64_t)d.node_of_row[r] * ldx + col]) : Tv(0);
-  }
   if (dir > 0) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) loc.add(v[i]);
@@ -223,6 +243,8 @@ template <> struct Wide<int64_t> { using W = uint64_t; };
 template <> struct Wide<float> { using W = double; };
 template <> struct Wide<double> { using W = double; };
 
+__device__ inline double fmax_(double a, double b) { return a > b ? a : b; }
+
 template <typename TP, typename Tout, typename Tres, bool RESID>
 __global__ __launch_bounds__(WG) void k_gather(DevPoset d, const int32_t* __restrict__ nv, int cw,
                                                const TP* __restrict__ P, int64_t B, Tout* __restrict__ out,
@@ -244,6 +266,96 @@ __global__ __launch_bounds__(WG) void k_gather(DevPoset d, const int32_t* __rest
     out[node * ldo + col] = (Tout)((double)res[node * ldr + col] - (double)acc);
   } else {
     out[node * ldo + col] = (Tout)acc;
+  }
+}
+
+// Gather-reduce by walking chains.  Along a chain the niv rows change little
+// from one element to the next (x below y implies out(x) ⊆ out(y), Theorem 4),
+// so a wavefront walks `walk_T` consecutive rows of one chain with its 64
+// lanes on 64 right-hand-side columns and keeps the running sum
+//   acc(r) = Σ_{j != own chain} P[nv[r][j]]
+// in float64 (exact int64 wrap for integers): a full gather for the first row,
+// then for each later row only the entries j whose niv changed contribute
+// P[new] - P[old].  The own chain's entry is the row itself, so
+// out(r) = acc(r) + P[r].  The changed entries are found with one ballot over
+// the niv row held one entry per lane (k <= 64); up to 4 changes are gathered
+// in parallel.  Segments are ordered by relative height so that concurrently
+// resident waves gather from nearby P rows.
+template <typename TP>
+__global__ __launch_bounds__(WG) void k_gather_walk(DevPoset d, const int32_t* __restrict__ nv,
+                                                    const TP* __restrict__ P, int64_t B, TP* __restrict__ out,
+                                                    int64_t ldo) {
+  using W = typename Wide<TP>::W;
+  const int lane = threadIdx.x & 63;
+  const int64_t ncb = (B + 63) >> 6;
+  const int64_t gw = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+  if (gw >= (int64_t)d.nwalk * ncb) return;
+  const int64_t seg = gw / ncb;
+  const int64_t col = (gw % ncb) * 64 + lane;
+  const bool colok = col < B;
+  const int64_t colc = colok ? col : 0;
+  const int r0 = d.walk[seg];
+  const int c = d.chain_of_row[r0];
+  const int r1 = min(r0 + d.walk_T, d.chain_off[c + 1]);
+  const int k = d.k;
+  const uint64_t notown = ~(1ull << c);
+
+  // first row: the full gather, 16 loads in flight
+  int cur = lane < k ? nv[(int64_t)r0 * k + lane] : -1;
+  W acc = W(0);
+  for (int j0 = 0; j0 < k; j0 += 16) {
+    TP v[16];
+    bool ok[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int j = j0 + u;
+      const int t = __builtin_amdgcn_readlane(cur, j & 63);
+      ok[u] = j < k && j != c && t >= 0;
+      v[u] = P[(int64_t)(ok[u] ? t : r0) * B + colc];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (ok[u]) acc += (W)v[u];
+  }
+
+  int prev = cur;
+  for (int r = r0; r < r1; r += 8) {
+    int nvc[8];
+    TP po[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int rr = min(r + u, r1 - 1);
+      nvc[u] = lane < k ? nv[(int64_t)rr * k + lane] : -1;
+      po[u] = P[(int64_t)rr * B + colc];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (r + u >= r1) break;
+      uint64_t m = __ballot(nvc[u] != prev) & notown;
+      while (m) {
+        TP vn[4], vo[4];
+        bool okn[4], oko[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bool has = m != 0;
+          const int j = has ? (int)__builtin_ctzll(m) : 0;
+          m &= m - 1;
+          const int tn = __builtin_amdgcn_readlane(nvc[u], j);
+          const int to = __builtin_amdgcn_readlane(prev, j);
+          okn[q] = has && tn >= 0;
+          oko[q] = has && to >= 0;
+          vn[q] = P[(int64_t)(okn[q] ? tn : r0) * B + colc];
+          vo[q] = P[(int64_t)(oko[q] ? to : r0) * B + colc];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (okn[q]) acc += (W)vn[q];
+          if (oko[q]) acc -= (W)vo[q];
+        }
+      }
+      prev = nvc[u];
+      if (colok) out[(int64_t)d.node_of_row[r + u] * ldo + col] = (TP)(acc + (W)po[u]);
+    }
   }
 }
 
@@ -293,25 +405,59 @@ __global__ __launch_bounds__(WG) void k_usolve(DevPoset d, const int32_t* __rest
 }
 
 // ------------------------------------------------------------ chain difference
+// With stats != nullptr (refinement, accumulate mode): per column the largest
+// |correction| into stats[col], the largest |updated value| into stats[B+col]
+// (float64 bit patterns, non-negative so integer max orders them), and a
+// non-finite flag into stats[2B]; reduced over the workgroup's rows in LDS
+// first, one atomic per column per workgroup.
 template <typename TY, typename Tout>
 __global__ __launch_bounds__(WG) void k_chain_diff(DevPoset d, int dir, int cw, const TY* __restrict__ Y, int64_t B,
-                                                   Tout* __restrict__ out, int64_t ldo, int accumulate) {
+                                                   Tout* __restrict__ out, int64_t ldo, int accumulate,
+                                                   uint64_t* __restrict__ stats) {
   using W = typename Wide<TY>::W;
   const int RG = WG / cw;
   const int64_t r = (int64_t)blockIdx.x * RG + threadIdx.x / cw;
   const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
-  if (r >= d.n || col >= B) return;
-  const int c = d.chain_of_row[r];
-  W v = (W)Y[r * B + col];
-  if (dir > 0) {
-    if (r > d.chain_off[c]) v -= (W)Y[(r - 1) * B + col];
-  } else {
-    if (r + 1 < d.chain_off[c + 1]) v -= (W)Y[(r + 1) * B + col];
+  const bool active = r < d.n && col < B;
+  double dmax = 0, fmax = 0;
+  bool bad = false;
+  if (active) {
+    const int c = d.chain_of_row[r];
+    W v = (W)Y[r * B + col];
+    if (dir > 0) {
+      if (r > d.chain_off[c]) v -= (W)Y[(r - 1) * B + col];
+    } else {
+      if (r + 1 < d.chain_off[c + 1]) v -= (W)Y[(r + 1) * B + col];
+    }
+    const int64_t node = d.node_of_row[r];
+    Tout* o = out + node * ldo + col;
+    Tout nv = accumulate ? (Tout)((W)*o + v) : (Tout)v;
+    *o = nv;
+    if constexpr (std::is_floating_point<W>::value) {
+      dmax = fabs((double)v);
+      fmax = fabs((double)nv);
+      bad = !isfinite(dmax) || !isfinite(fmax);
+    }
   }
-  const int64_t node = d.node_of_row[r];
-  Tout* o = out + node * ldo + col;
-  if (accumulate) *o = (Tout)((W)*o + v);
-  else *o = (Tout)v;
+  if (!stats) return;
+  __shared__ double sd[WG], sf[WG];
+  __shared__ int sb;
+  if (threadIdx.x == 0) sb = 0;
+  __syncthreads();
+  sd[threadIdx.x] = bad ? 0.0 : dmax;
+  sf[threadIdx.x] = bad ? 0.0 : fmax;
+  if (bad) sb = 1;
+  __syncthreads();
+  if (threadIdx.x < cw && col < B) {
+    double a = 0, b = 0;
+    for (int g = 0; g < RG; ++g) {
+      a = fmax_(a, sd[g * cw + threadIdx.x]);
+      b = fmax_(b, sf[g * cw + threadIdx.x]);
+    }
+    atomicMax((unsigned long long*)&stats[col], (unsigned long long)__double_as_longlong(a));
+    atomicMax((unsigned long long*)&stats[B + col], (unsigned long long)__double_as_longlong(b));
+  }
+  if (threadIdx.x == 0 && sb) atomicMax((unsigned long long*)&stats[2 * B], 1ull);
 }
 
 // --------------------------------------------------------------- statistics
@@ -408,6 +554,18 @@ hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P,
       return hipErrorInvalidValue;
     return hipGetLastError();
   }
+  if (d.walk && d.k <= 64 && B >= 32 && tp == tout) {
+    const int64_t waves = (int64_t)d.nwalk * ((B + 63) / 64);
+    const dim3 gw((unsigned)((waves + (WG / 64) - 1) / (WG / 64)));
+    if (tp == E_F32)
+      hipLaunchKernelGGL((k_gather_walk<float>), gw, dim3(WG), 0, s, d, nv, (const float*)P, B, (float*)out, ldo);
+    else if (tp == E_F64)
+      hipLaunchKernelGGL((k_gather_walk<double>), gw, dim3(WG), 0, s, d, nv, (const double*)P, B, (double*)out, ldo);
+    else
+      hipLaunchKernelGGL((k_gather_walk<int64_t>), gw, dim3(WG), 0, s, d, nv, (const int64_t*)P, B, (int64_t*)out,
+                         ldo);
+    return hipGetLastError();
+  }
   if (tp == E_I64 && tout == E_I64)
     hipLaunchKernelGGL((k_gather<int64_t, int64_t, int64_t, false>), g, dim3(WG), 0, s, d, nv, cw,
                        (const int64_t*)P, B, (int64_t*)out, ldo, (const int64_t*)nullptr, 0);
@@ -446,19 +604,23 @@ hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_ro
 }
 
 hipError_t launch_chain_diff(const DevPoset& d, int dir, ElemType ty, const void* Y, int64_t B, ElemType tout,
-                             void* out, int64_t ldo, bool accumulate, hipStream_t s) {
+                             void* out, int64_t ldo, bool accumulate, uint64_t* stats, hipStream_t s) {
   if (d.n == 0) return hipSuccess;
   const int cw = col_width(B);
   const dim3 g = grid2(d.n, cw, B);
+  if (stats) {
+    const int64_t cnt = 2 * B + 1;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((cnt + WG - 1) / WG)), dim3(WG), 0, s, stats, cnt, (uint64_t)0);
+  }
   if (ty == E_I64 && tout == E_I64)
     hipLaunchKernelGGL((k_chain_diff<int64_t, int64_t>), g, dim3(WG), 0, s, d, dir, cw, (const int64_t*)Y, B,
-                       (int64_t*)out, ldo, (int)accumulate);
+                       (int64_t*)out, ldo, (int)accumulate, stats);
   else if (ty == E_F32 && tout == E_F32)
     hipLaunchKernelGGL((k_chain_diff<float, float>), g, dim3(WG), 0, s, d, dir, cw, (const float*)Y, B,
-                       (float*)out, ldo, (int)accumulate);
+                       (float*)out, ldo, (int)accumulate, stats);
   else if (ty == E_F64 && tout == E_F64)
     hipLaunchKernelGGL((k_chain_diff<double, double>), g, dim3(WG), 0, s, d, dir, cw, (const double*)Y, B,
-                       (double*)out, ldo, (int)accumulate);
+                       (double*)out, ldo, (int)accumulate, stats);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -250,8 +250,9 @@ def test_grid_config2_f32_refined(px):
     P = build(px, p)
     g = W.functions(p.n, B, "uniform", seed=10, lo=-1.0, hi=1.0)
     want = _grid_closed_forms(g.astype(np.float64).reshape(h, w, B)).reshape(p.n, B)
-    got, rep = px.mobius(P, T(g), max_refine=5, tol=1e-7, report=True)
+    got, rep = px.mobius(P, T(g), max_refine=6, tol=1e-6, report=True)
     assert rel(H(got), want) <= 1e-5, rep
+    assert rep["correction"] <= 1e-6 and not rep["nonfinite"]
     plain = H(px.mobius(P, T(g), max_refine=0))
     got64 = H(px.mobius(P, T(g.astype(np.float64))))
     assert rel(got64, want) <= 1e-12
