@@ -42,9 +42,20 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(phase: str, n: int, k: int, B: int, s: int) -> int:
-    """Compulsory HBM bytes of one launch: every array the kernel must touch, once."""
-    if phase == "gather":        # read P, read niv, read node_of_row, write g
+def algorithmic_bytes(phase: str, n: int, k: int, B: int, s: int, info: dict) -> int:
+    """Compulsory bytes of one launch of each kernel (every array touched once).
+
+    walk_events: the change events (8 B), the first niv row of every run (4k B),
+    the P rows the method must gather (one per event and k-1 per run start) and
+    the snapshots it stores; re-reads of a chain's previous P row are not counted.
+    walk_combine: P, the snapshots, node_of_row and snap_of_row, and g.
+    """
+    runs, ev, snaps = info.get("walk_runs", 0), info.get("walk_events", 0), info.get("walk_snapshots", 0)
+    if phase == "walk_events":
+        return ev * 8 + runs * (k * 4 + 16) + (ev + runs * (k - 1)) * B * s + snaps * B * s
+    if phase == "walk_combine":
+        return n * B * s + snaps * B * s + 8 * n + n * B * s
+    if phase == "gather":        # one thread per row: read P, niv, node_of_row, write g
         return n * B * s + n * k * 4 + n * 4 + n * B * s
     if phase == "scan_apply":    # read f, read node_of_row, write P
         return n * B * s + n * 4 + n * B * s
@@ -53,7 +64,7 @@ def algorithmic_bytes(phase: str, n: int, k: int, B: int, s: int) -> int:
     return 0
 
 
-def profile_read(lib, nph=7):
+def profile_read(lib, nph=9):
     import ctypes
     ms = (ctypes.c_double * nph)()
     cnt = (ctypes.c_int64 * nph)()
@@ -147,14 +158,14 @@ def main():
     ms_step = dt * 1e3 / args.steps
     value = p.n * B / (dt / args.steps)
     phases = {}
-    for name in ("scan_reduce", "scan_carry", "scan_apply", "gather"):
+    for name in ("scan_reduce", "scan_carry", "scan_apply", "gather", "walk_events", "walk_combine"):
         ms, cnt = prof[name]
         if cnt:
             avg = ms / cnt
-            byt = algorithmic_bytes(name, p.n, P.k, B, 4)
+            byt = algorithmic_bytes(name, p.n, P.k, B, 4, P.info)
             phases[name] = {"avg_ms": round(avg, 4), "launches": cnt, "alg_bytes": byt,
                             "GBps": round(byt / (avg * 1e-3) / 1e9, 1) if byt else None}
-    dom = max(("scan_reduce", "scan_apply", "gather"), key=lambda k: phases[k]["avg_ms"])
+    dom = max((k for k in phases if phases[k]["alg_bytes"]), key=lambda k: phases[k]["avg_ms"])
     ach = phases[dom]["GBps"]
     tr = traffic_for(dom)
     # whole-step algorithmic bytes: read f, write P, read P, read niv, write g
@@ -183,6 +194,7 @@ def main():
         "phases": phases,
         "preprocess_s": {"total": round(t_prep, 3), **{k: round(v, 3) for k, v in P.info.items()
                                                       if k.startswith("t_")}},
+        "walk": {k: P.info[k] for k in ("walk_runs", "walk_events", "walk_snapshots")},
         "generate_s": round(t_gen, 3),
         "kernel_hash": kernel_hash(),
     }

@@ -82,6 +82,9 @@ typedef struct {
   int64_t mirsky_levels;  /* length of the longest chain of the poset (Mirsky, §4)      */
   int64_t udep_levels;    /* levels of the U-solve dependency DAG                       */
   int64_t device_bytes;   /* device memory held by the handle, workspace excluded       */
+  int64_t walk_runs;      /* runs of the walking gather over the niv map (0: not used)  */
+  int64_t walk_events;    /* niv change events inside those runs                        */
+  int64_t walk_snapshots; /* running-sum snapshots those runs store                     */
   int32_t chains_planted; /* 1 if the caller supplied the chains                        */
   int32_t device;
   double t_validate, t_chains, t_niv, t_levels, t_upload;  /* preprocessing seconds      */
@@ -192,7 +195,7 @@ px_status px_zeta_adjoint_batched(px_batch* b, int dtype, const void* w, int64_t
  * px_profile(0) stops.  px_profile_read synchronises on the recorded events and returns,
  * for each of the first nphases phases, the summed milliseconds and the launch count.
  * Phase names: px_profile_phase_name(i) (scan_reduce, scan_carry, scan_apply, gather,
- * usolve_level, chain_diff, absmax).  Not for use under HIP graph capture. */
+ * usolve_level, chain_diff, absmax, walk_events, walk_combine).  Not for use under HIP graph capture. */
 px_status px_profile(int on);
 px_status px_profile_read(double* ms, int64_t* count, int nphases);
 const char* px_profile_phase_name(int i);

@@ -99,37 +99,93 @@ void seg_tables(const std::vector<int32_t>& chain_off, std::vector<int32_t>& seg
   }
 }
 
-// Runs of `T` rows along every chain for the walking gather, ordered by the
-// relative height of the run inside its chain (ties by chain), so that the
-// waves resident together cover one height band of every chain.
+// Runs of the walking gather for one niv map (see px::WalkTables).  Every chain
+// is cut into runs of at most kWalkT rows and at most kWalkEvents change
+// events, so that no wavefront's serial event work is much longer than the
+// average; the runs are then ordered by the relative height of their middle
+// inside their chain (ties by chain), so that the waves resident together
+// gather from one height band of every chain.
 constexpr int kWalkT = 128;
-std::vector<int32_t> walk_table(const std::vector<int32_t>& chain_off, int T) {
+constexpr int kWalkEvents = 96;
+
+struct HostWalk {
+  std::vector<int32_t> runs;  // pairs (r0, r1)
+  std::vector<int32_t> ev;    // pairs (new row or -1, (u << 8) | chain)
+  std::vector<int32_t> ev_off, snap_off, snap_of_row;
+  int32_t nsnap = 0;
+};
+
+void build_walk(const px::Prep& P, const std::vector<int32_t>& nv, HostWalk& W) {
+  const int64_t k = P.k, n = P.n;
+  auto nchanges = [&](int32_t r) {  // other-chain entries of row r that differ from row r-1
+    const int32_t c = P.chain_of_row[r];
+    const int32_t* a = &nv[(size_t)r * k];
+    const int32_t* b = &nv[(size_t)(r - 1) * k];
+    int cnt = 0;
+    for (int64_t j = 0; j < k; ++j) cnt += (j != c && a[j] != b[j]);
+    return cnt;
+  };
   struct Run {
     double h;
-    int32_t c, r0;
+    int32_t c, r0, r1;
   };
   std::vector<Run> runs;
-  const int64_t nc = (int64_t)chain_off.size() - 1;
-  for (int64_t c = 0; c < nc; ++c) {
-    const int64_t len = chain_off[c + 1] - chain_off[c];
-    const int64_t nq = (len + T - 1) / T;
-    for (int64_t q = 0; q < nq; ++q)
-      runs.push_back({(q + 0.5) / (double)nq, (int32_t)c, (int32_t)(chain_off[c] + q * T)});
+  for (int64_t c = 0; c < k; ++c) {
+    const int32_t lo = P.chain_off[c], hi = P.chain_off[c + 1];
+    int32_t r = lo;
+    while (r < hi) {
+      const int32_t r0 = r++;
+      int ev = 0;
+      while (r < hi && r - r0 < kWalkT) {
+        const int e = nchanges(r);
+        if (ev + e > kWalkEvents && r > r0 + 1) break;
+        ev += e;
+        ++r;
+      }
+      runs.push_back({(0.5 * (r0 + r) - lo) / (double)(hi - lo), (int32_t)c, r0, r});
+    }
   }
-  std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) { return a.h < b.h; });
-  std::vector<int32_t> out(runs.size());
-  for (size_t i = 0; i < runs.size(); ++i) out[i] = runs[i].r0;
-  return out;
+  std::stable_sort(runs.begin(), runs.end(), [](const Run& x, const Run& y) { return x.h < y.h; });
+  W.runs.resize(2 * runs.size());
+  W.ev.clear();
+  W.ev_off.assign(runs.size() + 1, 0);
+  W.snap_off.assign(runs.size() + 1, 0);
+  W.snap_of_row.assign(n, 0);
+  int32_t m = 0;
+  for (size_t s = 0; s < runs.size(); ++s) {
+    const Run& R = runs[s];
+    W.runs[2 * s] = R.r0;
+    W.runs[2 * s + 1] = R.r1;
+    W.snap_off[s] = m;
+    int32_t cur = m++;
+    W.snap_of_row[R.r0] = cur;
+    for (int32_t r = R.r0 + 1; r < R.r1; ++r) {
+      const int32_t* a = &nv[(size_t)r * k];
+      const int32_t* b = &nv[(size_t)(r - 1) * k];
+      bool any = false;
+      for (int64_t j = 0; j < k; ++j)
+        if (j != R.c && a[j] != b[j]) {
+          W.ev.push_back(a[j]);
+          W.ev.push_back(((r - R.r0) << 8) | (int32_t)j);
+          any = true;
+        }
+      if (any) cur = m++;
+      W.snap_of_row[r] = cur;
+    }
+    W.ev_off[s + 1] = (int32_t)(W.ev.size() / 2);
+  }
+  W.snap_off[runs.size()] = m;
+  W.nsnap = m;
 }
 
 struct Layout {
-  size_t y = 0, p64 = 0, r64 = 0, aux = 0, stats = 0, total = 0;
+  size_t y = 0, p64 = 0, r64 = 0, aux = 0, stats = 0, snaps = 0, total = 0;
 };
 
 // Workspace layout of one call: a [n, B] matrix of the working type (P or Y),
 // for float32 refinement two float64 [n, B] matrices (P64 and the residual),
 // the scan's tile states and the refinement statistics.
-Layout layout(int64_t n, int64_t B, int dtype, bool refine, int64_t ntiles) {
+Layout layout(int64_t n, int64_t B, int dtype, bool refine, int64_t ntiles, int64_t nsnap = 0) {
   Layout L;
   size_t o = 0;
   L.y = o;
@@ -144,6 +200,8 @@ Layout layout(int64_t n, int64_t B, int dtype, bool refine, int64_t ntiles) {
   o = align256(o + (size_t)ntiles * B * 16 * 2);
   L.stats = o;
   o = align256(o + (size_t)(2 * B + 1) * 8);
+  L.snaps = o;
+  o = align256(o + (size_t)nsnap * B * elem_size(dtype));
   L.total = o;
   return L;
 }
@@ -156,9 +214,10 @@ px_status hip_status(hipError_t e, const char* what) {
 // Opt-in per-kernel timing with HIP events recorded on the launch stream
 // (px_profile / px_profile_read).  Off by default: then it costs one branch.
 namespace prof {
-enum Phase { SCAN_REDUCE = 0, SCAN_CARRY, SCAN_APPLY, GATHER, USOLVE, CHAIN_DIFF, ABSMAX, NPH };
-const char* const kNames[NPH] = {"scan_reduce", "scan_carry", "scan_apply", "gather",
-                                 "usolve_level", "chain_diff", "absmax"};
+enum Phase { SCAN_REDUCE = 0, SCAN_CARRY, SCAN_APPLY, GATHER, USOLVE, CHAIN_DIFF, ABSMAX, WALK_EVENTS, WALK_COMBINE,
+             NPH };
+const char* const kNames[NPH] = {"scan_reduce", "scan_carry", "scan_apply", "gather", "usolve_level",
+                                 "chain_diff",  "absmax",     "walk_events", "walk_combine"};
 std::mutex mu;
 std::atomic<bool> on{false};
 struct Rec {
@@ -198,6 +257,15 @@ struct Scope {
     pending.push_back({ph, a, b});
   }
 };
+// Times the two kernels of the walking gather separately.
+struct WalkHook : px::LaunchHook {
+  Scope* sc[2] = {nullptr, nullptr};
+  void before(int k, hipStream_t s) override { sc[k] = new Scope(k ? WALK_COMBINE : WALK_EVENTS, s); }
+  void after(int k, hipStream_t) override {
+    delete sc[k];
+    sc[k] = nullptr;
+  }
+};
 }  // namespace prof
 
 hipError_t run_scan(const px::DevPoset& d, int dir, px::ElemType tin, const void* x, int64_t ldx, px::ElemType tout,
@@ -218,9 +286,15 @@ hipError_t run_scan(const px::DevPoset& d, int dir, px::ElemType tin, const void
 }
 
 hipError_t run_gather(const px::DevPoset& d, bool up, px::ElemType tp, const void* P, int64_t B, px::ElemType tout,
-                      void* out, int64_t ldo, px::ElemType tres, const void* resid, int64_t ldr, hipStream_t s) {
-  prof::Scope sc(prof::GATHER, s);
-  return px::launch_gather(d, up, tp, P, B, tout, out, ldo, tres, resid, ldr, s);
+                      void* out, int64_t ldo, px::ElemType tres, const void* resid, int64_t ldr, void* snaps,
+                      hipStream_t s) {
+  if (prof::on) {
+    prof::WalkHook hook;
+    if (snaps) return px::launch_gather(d, up, tp, P, B, tout, out, ldo, tres, resid, ldr, snaps, &hook, s);
+    prof::Scope sc(prof::GATHER, s);
+    return px::launch_gather(d, up, tp, P, B, tout, out, ldo, tres, resid, ldr, nullptr, nullptr, s);
+  }
+  return px::launch_gather(d, up, tp, P, B, tout, out, ldo, tres, resid, ldr, snaps, nullptr, s);
 }
 
 hipError_t run_chain_diff(const px::DevPoset& d, int dir, px::ElemType ty, const void* Y, int64_t B,
@@ -237,9 +311,10 @@ struct px_poset {
   bool host_only = false, has_up = false, mirsky = false;
   int32_t *d_node_of_row = nullptr, *d_chain_of_row = nullptr, *d_chain_off = nullptr, *d_niv = nullptr,
           *d_niv_up = nullptr, *d_lev_down = nullptr, *d_lev_up = nullptr, *d_segoff = nullptr,
-          *d_walk = nullptr;
+          *d_walk[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
   int64_t ntiles[7] = {0, 0, 0, 0, 0, 0, 0};
-  int32_t nwalk = 0;
+  int64_t nevents[2] = {0, 0};
+  int32_t nsnap[2] = {0, 0};
   px::DevPoset dp;
   Workspace ws;
   int64_t device_bytes = 0;
@@ -262,10 +337,16 @@ struct px_batch {
 namespace {
 
 void free_poset_device(px_poset* p) {
-  int32_t* bufs[] = {p->d_node_of_row, p->d_chain_of_row, p->d_chain_off, p->d_niv, p->d_niv_up,
-                     p->d_lev_down,     p->d_lev_up,       p->d_segoff,    p->d_walk};
+  int32_t* bufs[] = {p->d_node_of_row, p->d_chain_of_row, p->d_chain_off, p->d_niv,
+                     p->d_niv_up,      p->d_lev_down,     p->d_lev_up,    p->d_segoff};
   for (int32_t* b : bufs)
     if (b) (void)hipFree(b);
+  for (auto& dir : p->d_walk)
+    for (int32_t*& b : dir)
+      if (b) {
+        (void)hipFree(b);
+        b = nullptr;
+      }
   p->ws.release();
 }
 
@@ -305,13 +386,13 @@ px_status zeta_impl(px_poset* p, bool up, int dtype, const void* f, int64_t ldf,
   if (!dg.ok) return fail(PX_EHIP, "hipSetDevice failed");
   const int cw = px::col_width(B);
   const int64_t nt = p->ntiles[px::seg_index(cw)];
-  Layout L = layout(p->prep.n, B, dtype, false, nt);
+  Layout L = layout(p->prep.n, B, dtype, false, nt, std::max(p->nsnap[0], p->nsnap[1]));
   if ((st = p->ws.ensure(L.total)) != PX_OK) return st;
   char* w = (char*)p->ws.p;
   hipStream_t s = (hipStream_t)stream;
   const px::ElemType T = etype(dtype);
   hipError_t e = run_scan(p->dp, up ? -1 : 1, T, f, ldf, T, w + L.y, B, w + L.aux, nt, s);
-  if (e == hipSuccess) e = run_gather(p->dp, up, T, w + L.y, B, T, g, ldg, T, nullptr, 0, s);
+  if (e == hipSuccess) e = run_gather(p->dp, up, T, w + L.y, B, T, g, ldg, T, nullptr, 0, w + L.snaps, s);
   return hip_status(e, "zeta launch");
 }
 
@@ -373,7 +454,7 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   auto residual = [&]() -> hipError_t {
     hipError_t e2 = run_scan(p->dp, dir, px::E_F32, f, ldf, px::E_F64, w + L.p64, B, w + L.aux, nt, s);
     if (e2 == hipSuccess)
-      e2 = run_gather(p->dp, up, px::E_F64, w + L.p64, B, px::E_F64, r64, B, px::E_F32, g, ldg, s);
+      e2 = run_gather(p->dp, up, px::E_F64, w + L.p64, B, px::E_F64, r64, B, px::E_F32, g, ldg, nullptr, s);
     return e2;
   };
   int it = 0;
@@ -488,10 +569,26 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
     if (e == hipSuccess) e = upload(&p->d_lev_down, P.lev_down_rows.data(), P.lev_down_rows.size(), b);
     if (e == hipSuccess && p->has_up) e = upload(&p->d_lev_up, P.lev_up_rows.data(), P.lev_up_rows.size(), b);
     if (e == hipSuccess) e = upload(&p->d_segoff, segoff.data(), segoff.size(), b);
-    if (e == hipSuccess) {
-      std::vector<int32_t> wt = walk_table(P.chain_off, kWalkT);
-      p->nwalk = (int32_t)wt.size();
-      e = upload(&p->d_walk, wt.data(), wt.size(), b);
+    for (int dir = 0; dir < 2 && e == hipSuccess && P.k <= 64; ++dir) {
+      if (dir == 1 && !p->has_up) break;
+      HostWalk W;
+      build_walk(P, dir ? P.niv_up : P.niv, W);
+      p->nevents[dir] = (int64_t)W.ev.size() / 2;
+      p->nsnap[dir] = W.nsnap;
+      px::WalkTables& t = p->dp.walk[dir];
+      t.nruns = (int32_t)(W.runs.size() / 2);
+      t.nsnap = W.nsnap;
+      int32_t** db = p->d_walk[dir];
+      e = upload(&db[0], W.runs.data(), W.runs.size(), b);
+      if (e == hipSuccess) e = upload(&db[1], W.ev.data(), W.ev.size(), b);
+      if (e == hipSuccess) e = upload(&db[2], W.ev_off.data(), W.ev_off.size(), b);
+      if (e == hipSuccess) e = upload(&db[3], W.snap_off.data(), W.snap_off.size(), b);
+      if (e == hipSuccess) e = upload(&db[4], W.snap_of_row.data(), W.snap_of_row.size(), b);
+      t.runs = (const int2*)db[0];
+      t.ev = (const int2*)db[1];
+      t.ev_off = db[2];
+      t.snap_off = db[3];
+      t.snap_of_row = db[4];
     }
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -512,9 +609,6 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
   d.niv = p->d_niv;
   d.niv_up = p->d_niv_up;
   d.segoff = p->d_segoff;
-  d.walk = p->d_walk;
-  d.nwalk = p->nwalk;
-  d.walk_T = kWalkT;
   *out = p;
   return PX_OK;
 }
@@ -543,6 +637,9 @@ px_status px_poset_info(const px_poset* p, px_info* o) {
   o->mirsky_levels = P.mirsky;
   o->udep_levels = P.udep;
   o->device_bytes = p->device_bytes;
+  o->walk_runs = p->dp.walk[0].nruns;
+  o->walk_events = p->nevents[0];
+  o->walk_snapshots = p->nsnap[0];
   o->chains_planted = P.planted ? 1 : 0;
   o->device = p->device;
   o->t_validate = P.t_validate;
@@ -588,7 +685,7 @@ px_status px_reserve(px_poset* p, int dtype, int64_t B) {
   if (B < 1) return fail(PX_EINVAL, "B must be >= 1");
   DeviceGuard dg(p->device);
   const int64_t nt = p->ntiles[px::seg_index(px::col_width(B))];
-  return p->ws.ensure(layout(p->prep.n, B, dtype, dtype == PX_F32, nt).total);
+  return p->ws.ensure(layout(p->prep.n, B, dtype, dtype == PX_F32, nt, std::max(p->nsnap[0], p->nsnap[1])).total);
 }
 
 px_status px_zeta(px_poset* p, int dtype, const void* f, int64_t ldf, void* g, int64_t ldg, int64_t B, void* stream) {
@@ -744,7 +841,7 @@ static px_status batch_zeta(px_batch* b, bool up, int dtype, const void* f, int6
   hipStream_t s = (hipStream_t)stream;
   const px::ElemType T = etype(dtype);
   hipError_t e = run_scan(b->dp, up ? -1 : 1, T, f, ldf, T, w + L.y, B, w + L.aux, nt, s);
-  if (e == hipSuccess) e = run_gather(b->dp, up, T, w + L.y, B, T, g, ldg, T, nullptr, 0, s);
+  if (e == hipSuccess) e = run_gather(b->dp, up, T, w + L.y, B, T, g, ldg, T, nullptr, 0, nullptr, s);
   return hip_status(e, "batched zeta launch");
 }
 

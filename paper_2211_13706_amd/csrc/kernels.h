@@ -14,6 +14,21 @@ namespace px {
 
 enum ElemType { E_I64 = 0, E_F32 = 1, E_F64 = 2 };
 
+// Runs of the walking gather (see k_walk_events): run s covers rows
+// [runs[s].x, runs[s].y) of one chain; its niv change events are
+// ev[ev_off[s] .. ev_off[s+1]), each {new row or -1, (row offset << 8) | chain},
+// sorted by row offset, own chain excluded; it owns snapshots
+// [snap_off[s], snap_off[s+1]) (first row, then every row with events), and
+// snap_of_row[r] is the snapshot that row r adds to its own P[r].
+struct WalkTables {
+  const int2* runs = nullptr;
+  const int2* ev = nullptr;
+  const int32_t* ev_off = nullptr;
+  const int32_t* snap_off = nullptr;
+  const int32_t* snap_of_row = nullptr;
+  int32_t nruns = 0, nsnap = 0;
+};
+
 // Static description of one poset (or a batch of posets) on the device.
 struct DevPoset {
   int32_t n = 0, k = 0;           // for a batch: total rows; k = 0 (per-poset k)
@@ -24,10 +39,8 @@ struct DevPoset {
   const int32_t* niv = nullptr;         // [n*k] or, for a batch, at niv_off[poset]
   const int32_t* niv_up = nullptr;
   const int32_t* segoff = nullptr;      // [7][nchains+1] tile offsets per tile height
-  // walk segments of the gather: first row of each run of walk_T rows of one
-  // chain, ordered by relative height (single posets only)
-  const int32_t* walk = nullptr;
-  int32_t nwalk = 0, walk_T = 0;
+  // tables of the walking gather, [0] for niv (zeta), [1] for the up-niv map
+  WalkTables walk[2];
   // batch only
   const int64_t* niv_off = nullptr;     // element offset of each poset's niv block
   const int32_t* poset_of_row = nullptr;
@@ -55,9 +68,18 @@ hipError_t launch_chain_scan_phase(int phase, const DevPoset& d, int dir, ElemTy
 // Gather-reduce U c: out[node(r)] = Σ_j P[nv[r][j]] over finite entries.  With
 // resid != nullptr (float64 P only): out = resid[node] - Σ (residual of a
 // refinement step; resid has element type tres, leading dim ldr).
+// Called around the two kernels of the walking gather (0 = events, 1 = combine),
+// e.g. to record timing events on the launch stream.
+struct LaunchHook {
+  virtual void before(int kernel, hipStream_t s) = 0;
+  virtual void after(int kernel, hipStream_t s) = 0;
+  virtual ~LaunchHook() = default;
+};
+
+// snaps: scratch for walk[up].nsnap * B values of type tp (nullable: one-thread-per-row gather).
 hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P, int64_t B,
                          ElemType tout, void* out, int64_t ldo, ElemType tres, const void* resid,
-                         int64_t ldr, hipStream_t s);
+                         int64_t ldr, void* snaps, LaunchHook* hook, hipStream_t s);
 
 // One level of the solve U y' = g: for the rows lev_rows[0..cnt),
 // Y[r] = g[node(r)] - Σ_{j: nv[r][j] != r} Y[nv[r][j]].

@@ -20,7 +20,8 @@
 namespace px {
 
 constexpr int WG = 256;
-constexpr int RPT = 16;  // rows per thread in a scan tile
+constexpr int RPT = 16;          // rows per thread in a scan tile
+constexpr int COMBINE_ROWS = 8;  // rows per thread in the walk's combine pass
 
 int col_width(int64_t B) {
   int cw = 1;
@@ -143,35 +144,50 @@ __global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw
 }
 
 // Phase 2: exclusive scan of the tile totals along every chain, per column.
+// One workgroup per (chain, 16 columns): windows of 128 tile totals are staged
+// in LDS, each of 16 thread groups combines 8 of them, the group totals are
+// combined in order, and the carries are written; a running carry links the
+// windows.  The combination order is fixed, so results are reproducible.
 template <typename St>
 __global__ __launch_bounds__(WG) void k_scan_carry(DevPoset d, int segi, int dir, int64_t B,
                                                    const St* __restrict__ A, St* __restrict__ C) {
-  const int64_t idx = (int64_t)blockIdx.x * WG + threadIdx.x;
-  if (idx >= (int64_t)d.nchains * B) return;
-  const int c = (int)(idx / B);
-  const int64_t col = idx % B;
+  constexpr int CB = 16, NS = WG / CB, TPS = 8, WIN = NS * TPS;
+  __shared__ St sh[WIN * CB];
+  __shared__ St tot[NS * CB];
+  const int c = blockIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.y * CB;
+  const int lc = threadIdx.x % CB, sg = threadIdx.x / CB;
+  const int64_t col = c0 + lc;
   const int32_t* so = d.segoff + (int64_t)segi * (d.nchains + 1);
+  const int t0 = so[c], t1 = so[c + 1], nt = t1 - t0;
   St carry;
   carry.zero();
-  const int t0 = so[c], t1 = so[c + 1];
-  constexpr int CH = 16;  // tile totals loaded per round trip
-  for (int base = 0; base < t1 - t0; base += CH) {
-    St a[CH];
-#pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int i = min(base + u, t1 - t0 - 1);
-      const int t = dir > 0 ? t0 + i : t1 - 1 - i;
-      a[u] = A[(int64_t)t * B + col];
+  for (int w0 = 0; w0 < nt; w0 += WIN) {
+    for (int x = threadIdx.x; x < WIN * CB; x += WG) {
+      const int i = w0 + x / CB;
+      const int64_t cc = c0 + x % CB;
+      St v;
+      v.zero();
+      if (i < nt && cc < B) v = A[(int64_t)(dir > 0 ? t0 + i : t1 - 1 - i) * B + cc];
+      sh[x] = v;
     }
+    __syncthreads();
+    St part;
+    part.zero();
 #pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int i = base + u;
-      if (i < t1 - t0) {
-        const int t = dir > 0 ? t0 + i : t1 - 1 - i;
-        C[(int64_t)t * B + col] = carry;
-        carry.combine(a[u]);
-      }
+    for (int u = 0; u < TPS; ++u) part.combine(sh[(sg * TPS + u) * CB + lc]);
+    tot[sg * CB + lc] = part;
+    __syncthreads();
+    St pre = carry;
+    for (int g = 0; g < sg; ++g) pre.combine(tot[g * CB + lc]);
+#pragma unroll
+    for (int u = 0; u < TPS; ++u) {
+      const int i = w0 + sg * TPS + u;
+      if (i < nt && col < B) C[(int64_t)(dir > 0 ? t0 + i : t1 - 1 - i) * B + col] = pre;
+      pre.combine(sh[(sg * TPS + u) * CB + lc]);
     }
+    for (int g = 0; g < NS; ++g) carry.combine(tot[g * CB + lc]);
+    __syncthreads();
   }
 }
 
@@ -269,94 +285,135 @@ __global__ __launch_bounds__(WG) void k_gather(DevPoset d, const int32_t* __rest
   }
 }
 
-// Gather-reduce by walking chains.  Along a chain the niv rows change little
-// from one element to the next (x below y implies out(x) ⊆ out(y), Theorem 4),
-// so a wavefront walks `walk_T` consecutive rows of one chain with its 64
-// lanes on 64 right-hand-side columns and keeps the running sum
-//   acc(r) = Σ_{j != own chain} P[nv[r][j]]
-// in float64 (exact int64 wrap for integers): a full gather for the first row,
-// then for each later row only the entries j whose niv changed contribute
-// P[new] - P[old].  The own chain's entry is the row itself, so
-// out(r) = acc(r) + P[r].  The changed entries are found with one ballot over
-// the niv row held one entry per lane (k <= 64); up to 4 changes are gathered
-// in parallel.  Segments are ordered by relative height so that concurrently
-// resident waves gather from nearby P rows.
+// Gather-reduce by walking chains (two kernels).  Along a chain the niv rows
+// change little from one element to the next (x below y implies
+// out(x) ⊆ out(y), Theorem 4): at n = 2^20, k = 64 a row differs from the one
+// below in about one other-chain entry.  Preprocessing cuts every chain into
+// runs of at most 128 rows and a bounded number of change events and encodes
+// each run as the niv row of its first element plus the events
+// (row offset u, chain j, new row) of its later rows, own chain excluded.
+//
+// G1 (k_walk_events): one wavefront per run, lanes = 64 right-hand-side
+// columns, niv held one entry per lane.  It gathers the first row in full and
+// keeps acc = Σ_{j != own} P[cur_j] in float64 (exact int64 wrap), applies the
+// events 16 at a time with their gathers in flight (P[new] - P[old]), and
+// stores acc as a snapshot after the first row and after every row with
+// events: S[snap_off[s] + m].
+// G2 (k_walk_combine): a streaming pass, out[node(r)] = P[r] + S[snap_of_row[r]]
+// (the own chain contributes the row itself), 16 rows of a thread in flight.
+// Snapshots are stored in the P type; for float32 this adds one rounding of
+// |acc| <= (Z|f|)(x).
 template <typename TP>
-__global__ __launch_bounds__(WG) void k_gather_walk(DevPoset d, const int32_t* __restrict__ nv,
-                                                    const TP* __restrict__ P, int64_t B, TP* __restrict__ out,
-                                                    int64_t ldo) {
+__global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* __restrict__ nv, WalkTables w,
+                                                    const TP* __restrict__ P, int64_t B, TP* __restrict__ S) {
   using W = typename Wide<TP>::W;
   const int lane = threadIdx.x & 63;
   const int64_t ncb = (B + 63) >> 6;
   const int64_t gw = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
-  if (gw >= (int64_t)d.nwalk * ncb) return;
+  if (gw >= (int64_t)w.nruns * ncb) return;
   const int64_t seg = gw / ncb;
   const int64_t col = (gw % ncb) * 64 + lane;
   const bool colok = col < B;
   const int64_t colc = colok ? col : 0;
-  const int r0 = d.walk[seg];
+  const int r0 = w.runs[seg].x;
   const int c = d.chain_of_row[r0];
-  const int r1 = min(r0 + d.walk_T, d.chain_off[c + 1]);
   const int k = d.k;
-  const uint64_t notown = ~(1ull << c);
+  const int2* __restrict__ ev = w.ev;
+  const int32_t* __restrict__ ev_off = w.ev_off;
+  const int32_t* __restrict__ snap_off = w.snap_off;
 
-  // first row: the full gather, 16 loads in flight
   int cur = lane < k ? nv[(int64_t)r0 * k + lane] : -1;
   W acc = W(0);
-  for (int j0 = 0; j0 < k; j0 += 16) {
-    TP v[16];
-    bool ok[16];
+  for (int j0 = 0; j0 < k; j0 += 32) {
+    TP v[32];
+    bool ok[32];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < 32; ++u) {
       const int j = j0 + u;
       const int t = __builtin_amdgcn_readlane(cur, j & 63);
       ok[u] = j < k && j != c && t >= 0;
       v[u] = P[(int64_t)(ok[u] ? t : r0) * B + colc];
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
+    for (int u = 0; u < 32; ++u)
       if (ok[u]) acc += (W)v[u];
   }
+  int64_t m = snap_off[seg];
+  const int64_t mlast = snap_off[seg + 1] - 1;  // never write past the run's own snapshots
+  if (colok) S[m * B + col] = (TP)acc;
 
-  int prev = cur;
-  for (int r = r0; r < r1; r += 8) {
-    int nvc[8];
-    TP po[8];
+  const int e0 = ev_off[seg], e1 = ev_off[seg + 1];
+  for (int eb = e0; eb < e1; eb += 64) {
+    const int ne = min(64, e1 - eb);
+    const int2 evl = lane < ne ? ev[eb + lane] : make_int2(-1, 0);
+    for (int g0 = 0; g0 < ne; g0 += 16) {
+      TP vn[16], vo[16];
+      bool okn[16], oko[16];
+      int ue[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int rr = min(r + u, r1 - 1);
-      nvc[u] = lane < k ? nv[(int64_t)rr * k + lane] : -1;
-      po[u] = P[(int64_t)rr * B + colc];
-    }
+      for (int q = 0; q < 16; ++q) {
+        const bool has = g0 + q < ne;
+        const int i = has ? g0 + q : 0;
+        const int key = __builtin_amdgcn_readlane(evl.y, i);
+        const int nw = __builtin_amdgcn_readlane(evl.x, i);
+        const int j = key & 255;
+        const int old = __builtin_amdgcn_readlane(cur, j & 63);
+        if (has) cur = lane == j ? nw : cur;
+        okn[q] = has && nw >= 0;
+        oko[q] = has && old >= 0;
+        ue[q] = has ? (key >> 8) : -1;
+        vn[q] = P[(int64_t)(okn[q] ? nw : r0) * B + colc];
+        vo[q] = P[(int64_t)(oko[q] ? old : r0) * B + colc];
+      }
+      // the row offset of the event after this group (or -1 at the end of the run)
+      const int inext = g0 + 16;
+      const int unext = inext < ne ? (__builtin_amdgcn_readlane(evl.y, inext) >> 8)
+                                   : (eb + 64 < e1 ? (ev[eb + 64].y >> 8) : -1);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (r + u >= r1) break;
-      uint64_t m = __ballot(nvc[u] != prev) & notown;
-      while (m) {
-        TP vn[4], vo[4];
-        bool okn[4], oko[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const bool has = m != 0;
-          const int j = has ? (int)__builtin_ctzll(m) : 0;
-          m &= m - 1;
-          const int tn = __builtin_amdgcn_readlane(nvc[u], j);
-          const int to = __builtin_amdgcn_readlane(prev, j);
-          okn[q] = has && tn >= 0;
-          oko[q] = has && to >= 0;
-          vn[q] = P[(int64_t)(okn[q] ? tn : r0) * B + colc];
-          vo[q] = P[(int64_t)(oko[q] ? to : r0) * B + colc];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 16; ++q) {
+        if (ue[q] >= 0) {
           if (okn[q]) acc += (W)vn[q];
           if (oko[q]) acc -= (W)vo[q];
+          const int un = q + 1 < 16 ? ue[q + 1] : unext;
+          if (un != ue[q]) {  // last event of its row: snapshot
+            m = min(m + 1, mlast);
+            if (colok) S[m * B + col] = (TP)acc;
+          }
         }
       }
-      prev = nvc[u];
-      if (colok) out[(int64_t)d.node_of_row[r + u] * ldo + col] = (TP)(acc + (W)po[u]);
     }
   }
+}
+
+template <typename TP>
+__global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* __restrict__ snap_of_row,
+                                                     const TP* __restrict__ P, const TP* __restrict__ S, int64_t B,
+                                                     TP* __restrict__ out, int64_t ldo) {
+  using W = typename Wide<TP>::W;
+  constexpr int cw = 64, RPC = COMBINE_ROWS;
+  const int RG = WG / cw;
+  const int64_t rbase = ((int64_t)blockIdx.x * RG + threadIdx.x / cw) * RPC;
+  const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
+  if (rbase >= d.n) return;
+  const int64_t colc = col < B ? col : 0;
+  int32_t nd[RPC], sm[RPC];
+#pragma unroll
+  for (int i = 0; i < RPC; ++i) {
+    const int64_t r = min(rbase + i, (int64_t)d.n - 1);
+    nd[i] = d.node_of_row[r];
+    sm[i] = snap_of_row[r];
+  }
+  TP pv[RPC], sv[RPC];
+#pragma unroll
+  for (int i = 0; i < RPC; ++i) {
+    const int64_t r = min(rbase + i, (int64_t)d.n - 1);
+    pv[i] = P[r * B + colc];
+    sv[i] = S[(int64_t)sm[i] * B + colc];
+  }
+  if (col >= B) return;
+#pragma unroll
+  for (int i = 0; i < RPC; ++i)
+    if (rbase + i < d.n) out[(int64_t)nd[i] * ldo + col] = (TP)((W)pv[i] + (W)sv[i]);
 }
 
 // Batched gather over many posets of different width: row r belongs to
@@ -500,9 +557,8 @@ hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int6
   if (phase == 0) {
     hipLaunchKernelGGL((k_scan_reduce<Tin, Tout>), g, dim3(WG), 0, s, d, segi, cw, (const Tin*)x, ldx, B, A);
   } else if (phase == 1) {
-    const int64_t nc = (int64_t)d.nchains * B;
-    hipLaunchKernelGGL((k_scan_carry<St>), dim3((unsigned)((nc + WG - 1) / WG)), dim3(WG), 0, s, d, segi, dir, B,
-                       (const St*)A, C);
+    hipLaunchKernelGGL((k_scan_carry<St>), dim3((unsigned)d.nchains, (unsigned)((B + 15) / 16)), dim3(WG), 0, s, d,
+                       segi, dir, B, (const St*)A, C);
   } else {
     hipLaunchKernelGGL((k_scan_apply<Tin, Tout>), g, dim3(WG), 0, s, d, segi, cw, dir, (const Tin*)x, ldx, B,
                        (const St*)C, (Tout*)P);
@@ -523,7 +579,8 @@ hipError_t launch_chain_scan_phase(int phase, const DevPoset& d, int dir, ElemTy
 }
 
 hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P, int64_t B, ElemType tout,
-                         void* out, int64_t ldo, ElemType tres, const void* resid, int64_t ldr, hipStream_t s) {
+                         void* out, int64_t ldo, ElemType tres, const void* resid, int64_t ldr, void* snaps,
+                         LaunchHook* hook, hipStream_t s) {
   if (d.n == 0) return hipSuccess;
   const int cw = col_width(B);
   const dim3 g = grid2(d.n, cw, B);
@@ -554,16 +611,33 @@ hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P,
       return hipErrorInvalidValue;
     return hipGetLastError();
   }
-  if (d.walk && d.k <= 64 && B >= 32 && tp == tout) {
-    const int64_t waves = (int64_t)d.nwalk * ((B + 63) / 64);
+  const WalkTables& w = d.walk[up ? 1 : 0];
+  if (w.runs && snaps && d.k <= 64 && B >= 32 && tp == tout) {
+    const int64_t waves = (int64_t)w.nruns * ((B + 63) / 64);
     const dim3 gw((unsigned)((waves + (WG / 64) - 1) / (WG / 64)));
+    const dim3 gc((unsigned)((d.n + (WG / 64) * COMBINE_ROWS - 1) / ((WG / 64) * COMBINE_ROWS)),
+                  (unsigned)((B + 63) / 64));
+    if (hook) hook->before(0, s);
     if (tp == E_F32)
-      hipLaunchKernelGGL((k_gather_walk<float>), gw, dim3(WG), 0, s, d, nv, (const float*)P, B, (float*)out, ldo);
+      hipLaunchKernelGGL((k_walk_events<float>), gw, dim3(WG), 0, s, d, nv, w, (const float*)P, B, (float*)snaps);
     else if (tp == E_F64)
-      hipLaunchKernelGGL((k_gather_walk<double>), gw, dim3(WG), 0, s, d, nv, (const double*)P, B, (double*)out, ldo);
+      hipLaunchKernelGGL((k_walk_events<double>), gw, dim3(WG), 0, s, d, nv, w, (const double*)P, B,
+                         (double*)snaps);
     else
-      hipLaunchKernelGGL((k_gather_walk<int64_t>), gw, dim3(WG), 0, s, d, nv, (const int64_t*)P, B, (int64_t*)out,
-                         ldo);
+      hipLaunchKernelGGL((k_walk_events<int64_t>), gw, dim3(WG), 0, s, d, nv, w, (const int64_t*)P, B,
+                         (int64_t*)snaps);
+    if (hook) hook->after(0, s);
+    if (hook) hook->before(1, s);
+    if (tp == E_F32)
+      hipLaunchKernelGGL((k_walk_combine<float>), gc, dim3(WG), 0, s, d, w.snap_of_row, (const float*)P,
+                         (const float*)snaps, B, (float*)out, ldo);
+    else if (tp == E_F64)
+      hipLaunchKernelGGL((k_walk_combine<double>), gc, dim3(WG), 0, s, d, w.snap_of_row, (const double*)P,
+                         (const double*)snaps, B, (double*)out, ldo);
+    else
+      hipLaunchKernelGGL((k_walk_combine<int64_t>), gc, dim3(WG), 0, s, d, w.snap_of_row, (const int64_t*)P,
+                         (const int64_t*)snaps, B, (int64_t*)out, ldo);
+    if (hook) hook->after(1, s);
     return hipGetLastError();
   }
   if (tp == E_I64 && tout == E_I64)
