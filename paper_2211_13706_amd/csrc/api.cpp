@@ -110,7 +110,7 @@ constexpr int kWalkEvents = 96;
 
 struct HostWalk {
   std::vector<int32_t> runs;  // pairs (r0, r1)
-  std::vector<int32_t> ev;    // pairs (new row or -1, (u << 8) | chain)
+  std::vector<int32_t> ev;    // quadruples (new row, old row, (u << 8) | chain, 0), -1 = none
   std::vector<int32_t> ev_off, snap_off, snap_of_row;
   int32_t nsnap = 0;
 };
@@ -166,13 +166,15 @@ void build_walk(const px::Prep& P, const std::vector<int32_t>& nv, HostWalk& W) 
       for (int64_t j = 0; j < k; ++j)
         if (j != R.c && a[j] != b[j]) {
           W.ev.push_back(a[j]);
-          W.ev.push_back(((r - R.r0) << 8) | (int32_t)j);
+          W.ev.push_back(b[j]);
+          W.ev.push_back(((r - R.r0) << 8) | (int32_t)std::min<int64_t>(j, 255));
+          W.ev.push_back(0);
           any = true;
         }
       if (any) cur = m++;
       W.snap_of_row[r] = cur;
     }
-    W.ev_off[s + 1] = (int32_t)(W.ev.size() / 2);
+    W.ev_off[s + 1] = (int32_t)(W.ev.size() / 4);
   }
   W.snap_off[runs.size()] = m;
   W.nsnap = m;
@@ -201,7 +203,7 @@ Layout layout(int64_t n, int64_t B, int dtype, bool refine, int64_t ntiles, int6
   L.stats = o;
   o = align256(o + (size_t)(2 * B + 1) * 8);
   L.snaps = o;
-  o = align256(o + (size_t)nsnap * B * elem_size(dtype));
+  o = align256(o + (size_t)nsnap * B * (refine ? 8 : elem_size(dtype)));
   L.total = o;
   return L;
 }
@@ -315,6 +317,7 @@ struct px_poset {
   int64_t ntiles[7] = {0, 0, 0, 0, 0, 0, 0};
   int64_t nevents[2] = {0, 0};
   int32_t nsnap[2] = {0, 0};
+  std::vector<int32_t> hw_runs[2], hw_ev[2], hw_ev_off[2], hw_snap_off[2], hw_snap_of_row[2];
   px::DevPoset dp;
   Workspace ws;
   int64_t device_bytes = 0;
@@ -329,6 +332,8 @@ struct px_batch {
   int32_t *d_node_of_row = nullptr, *d_chain_of_row = nullptr, *d_chain_off = nullptr, *d_niv = nullptr,
           *d_niv_up = nullptr, *d_segoff = nullptr, *d_poset_of_row = nullptr, *d_k = nullptr, *d_row_off = nullptr;
   int64_t* d_niv_off = nullptr;
+  int32_t* d_walk[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
+  int32_t nsnap[2] = {0, 0};
   int64_t ntiles[7] = {0, 0, 0, 0, 0, 0, 0};
   px::DevPoset dp;
   Workspace ws;
@@ -420,7 +425,7 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   const bool refine = dtype == PX_F32;
   const int cw = px::col_width(B);
   const int64_t nt = p->ntiles[px::seg_index(cw)];
-  Layout L = layout(n, B, dtype, refine, nt);
+  Layout L = layout(n, B, dtype, refine, nt, std::max(p->nsnap[0], p->nsnap[1]));
   if ((st = p->ws.ensure(L.total)) != PX_OK) return st;
   char* w = (char*)p->ws.p;
   hipStream_t s = (hipStream_t)stream;
@@ -454,7 +459,7 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   auto residual = [&]() -> hipError_t {
     hipError_t e2 = run_scan(p->dp, dir, px::E_F32, f, ldf, px::E_F64, w + L.p64, B, w + L.aux, nt, s);
     if (e2 == hipSuccess)
-      e2 = run_gather(p->dp, up, px::E_F64, w + L.p64, B, px::E_F64, r64, B, px::E_F32, g, ldg, nullptr, s);
+      e2 = run_gather(p->dp, up, px::E_F64, w + L.p64, B, px::E_F64, r64, B, px::E_F32, g, ldg, w + L.snaps, s);
     return e2;
   };
   int it = 0;
@@ -569,11 +574,11 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
     if (e == hipSuccess) e = upload(&p->d_lev_down, P.lev_down_rows.data(), P.lev_down_rows.size(), b);
     if (e == hipSuccess && p->has_up) e = upload(&p->d_lev_up, P.lev_up_rows.data(), P.lev_up_rows.size(), b);
     if (e == hipSuccess) e = upload(&p->d_segoff, segoff.data(), segoff.size(), b);
-    for (int dir = 0; dir < 2 && e == hipSuccess && P.k <= 64; ++dir) {
+    for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
       if (dir == 1 && !p->has_up) break;
       HostWalk W;
       build_walk(P, dir ? P.niv_up : P.niv, W);
-      p->nevents[dir] = (int64_t)W.ev.size() / 2;
+      p->nevents[dir] = (int64_t)W.ev.size() / 4;
       p->nsnap[dir] = W.nsnap;
       px::WalkTables& t = p->dp.walk[dir];
       t.nruns = (int32_t)(W.runs.size() / 2);
@@ -584,8 +589,13 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
       if (e == hipSuccess) e = upload(&db[2], W.ev_off.data(), W.ev_off.size(), b);
       if (e == hipSuccess) e = upload(&db[3], W.snap_off.data(), W.snap_off.size(), b);
       if (e == hipSuccess) e = upload(&db[4], W.snap_of_row.data(), W.snap_of_row.size(), b);
+      p->hw_runs[dir] = W.runs;
+      p->hw_ev[dir] = W.ev;
+      p->hw_ev_off[dir] = W.ev_off;
+      p->hw_snap_off[dir] = W.snap_off;
+      p->hw_snap_of_row[dir] = W.snap_of_row;
       t.runs = (const int2*)db[0];
-      t.ev = (const int2*)db[1];
+      t.ev = (const int4*)db[1];
       t.ev_off = db[2];
       t.snap_off = db[3];
       t.snap_of_row = db[4];
@@ -775,6 +785,44 @@ px_status px_batch_build(int count, px_poset* const* posets, px_batch** out) {
   if (e == hipSuccess) e = upload(&b->d_k, kk.data(), kk.size(), bytes);
   if (e == hipSuccess) e = upload(&b->d_row_off, row_off.data(), row_off.size(), bytes);
   if (e == hipSuccess) e = upload(&b->d_niv_off, niv_off.data(), niv_off.size(), bytes);
+  // walk tables of every poset, rows, events and snapshots shifted into the batch
+  for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
+    if (dir == 1 && !has_up) break;
+    std::vector<int32_t> runs, ev, ev_off(1, 0), snap_off(1, 0), snap_of_row(rows);
+    int32_t eo = 0, so = 0;
+    for (int i = 0; i < count; ++i) {
+      const px_poset* q = posets[i];
+      const int32_t o = row_off[i];
+      for (int32_t r : q->hw_runs[dir]) runs.push_back(r + o);
+      const std::vector<int32_t>& qe = q->hw_ev[dir];
+      for (size_t x = 0; x < qe.size(); x += 4) {
+        ev.push_back(qe[x] >= 0 ? qe[x] + o : -1);
+        ev.push_back(qe[x + 1] >= 0 ? qe[x + 1] + o : -1);
+        ev.push_back(qe[x + 2]);
+        ev.push_back(0);
+      }
+      for (size_t x = 1; x < q->hw_ev_off[dir].size(); ++x) ev_off.push_back(q->hw_ev_off[dir][x] + eo);
+      for (size_t x = 1; x < q->hw_snap_off[dir].size(); ++x) snap_off.push_back(q->hw_snap_off[dir][x] + so);
+      for (int64_t r = 0; r < q->prep.n; ++r) snap_of_row[o + r] = q->hw_snap_of_row[dir][r] + so;
+      eo += (int32_t)(qe.size() / 4);
+      so += q->nsnap[dir];
+    }
+    b->nsnap[dir] = so;
+    px::WalkTables& t = b->dp.walk[dir];
+    t.nruns = (int32_t)(runs.size() / 2);
+    t.nsnap = so;
+    int32_t** db = b->d_walk[dir];
+    e = upload(&db[0], runs.data(), runs.size(), bytes);
+    if (e == hipSuccess) e = upload(&db[1], ev.data(), ev.size(), bytes);
+    if (e == hipSuccess) e = upload(&db[2], ev_off.data(), ev_off.size(), bytes);
+    if (e == hipSuccess) e = upload(&db[3], snap_off.data(), snap_off.size(), bytes);
+    if (e == hipSuccess) e = upload(&db[4], snap_of_row.data(), snap_of_row.size(), bytes);
+    t.runs = (const int2*)db[0];
+    t.ev = (const int4*)db[1];
+    t.ev_off = db[2];
+    t.snap_off = db[3];
+    t.snap_of_row = db[4];
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     px_batch_free(b);
@@ -806,6 +854,9 @@ px_status px_batch_free(px_batch* b) {
   for (int32_t* q : bufs)
     if (q) (void)hipFree(q);
   if (b->d_niv_off) (void)hipFree(b->d_niv_off);
+  for (auto& dir : b->d_walk)
+    for (int32_t* q : dir)
+      if (q) (void)hipFree(q);
   b->ws.release();
   delete b;
   return PX_OK;
@@ -823,7 +874,7 @@ px_status px_batch_reserve(px_batch* b, int dtype, int64_t B) {
   if (B < 1) return fail(PX_EINVAL, "B must be >= 1");
   DeviceGuard dg(b->device);
   const int64_t nt = b->ntiles[px::seg_index(px::col_width(B))];
-  return b->ws.ensure(layout(b->rows, B, dtype, false, nt).total);
+  return b->ws.ensure(layout(b->rows, B, dtype, false, nt, std::max(b->nsnap[0], b->nsnap[1])).total);
 }
 
 static px_status batch_zeta(px_batch* b, bool up, int dtype, const void* f, int64_t ldf, void* g, int64_t ldg,
@@ -835,13 +886,13 @@ static px_status batch_zeta(px_batch* b, bool up, int dtype, const void* f, int6
   DeviceGuard dg(b->device);
   if (!dg.ok) return fail(PX_EHIP, "hipSetDevice failed");
   const int64_t nt = b->ntiles[px::seg_index(px::col_width(B))];
-  Layout L = layout(b->rows, B, dtype, false, nt);
+  Layout L = layout(b->rows, B, dtype, false, nt, std::max(b->nsnap[0], b->nsnap[1]));
   if ((st = b->ws.ensure(L.total)) != PX_OK) return st;
   char* w = (char*)b->ws.p;
   hipStream_t s = (hipStream_t)stream;
   const px::ElemType T = etype(dtype);
   hipError_t e = run_scan(b->dp, up ? -1 : 1, T, f, ldf, T, w + L.y, B, w + L.aux, nt, s);
-  if (e == hipSuccess) e = run_gather(b->dp, up, T, w + L.y, B, T, g, ldg, T, nullptr, 0, nullptr, s);
+  if (e == hipSuccess) e = run_gather(b->dp, up, T, w + L.y, B, T, g, ldg, T, nullptr, 0, w + L.snaps, s);
   return hip_status(e, "batched zeta launch");
 }
 

@@ -16,13 +16,13 @@ enum ElemType { E_I64 = 0, E_F32 = 1, E_F64 = 2 };
 
 // Runs of the walking gather (see k_walk_events): run s covers rows
 // [runs[s].x, runs[s].y) of one chain; its niv change events are
-// ev[ev_off[s] .. ev_off[s+1]), each {new row or -1, (row offset << 8) | chain},
-// sorted by row offset, own chain excluded; it owns snapshots
+// ev[ev_off[s] .. ev_off[s+1]), each {new row, old row, (row offset << 8) | chain, 0}
+// (-1 = none), sorted by row offset, own chain excluded; it owns snapshots
 // [snap_off[s], snap_off[s+1]) (first row, then every row with events), and
 // snap_of_row[r] is the snapshot that row r adds to its own P[r].
 struct WalkTables {
   const int2* runs = nullptr;
-  const int2* ev = nullptr;
+  const int4* ev = nullptr;
   const int32_t* ev_off = nullptr;
   const int32_t* snap_off = nullptr;
   const int32_t* snap_of_row = nullptr;

@@ -103,43 +103,67 @@ __device__ inline int find_chain(const int32_t* so, int nchains, int t) {
   return lo;
 }
 
-// Phase 1: per tile and column, the compensated total of the tile's rows.
-template <typename Tin, typename Tout>
-__global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw, const Tin* __restrict__ x,
-                                                    int64_t ldx, int64_t B,
+// Phase 1: per tile and column, the compensated total of the tile's rows.  A
+// workgroup reduces two tiles, so that each thread has 2*RPT loads in flight.
+// With CWT = 64 a row group is one wavefront, so its row (and node) indices
+// are wave-uniform and live in scalar registers.
+template <typename Tin, typename Tout, int CWT>
+__global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw_rt, const Tin* __restrict__ x,
+                                                    int64_t ldx, int64_t B, int64_t ntiles,
                                                     typename ScanTraits<Tin, Tout>::St* __restrict__ A) {
   using Tr = ScanTraits<Tin, Tout>;
   using St = typename Tr::St;
-  __shared__ St sm[WG];
-  const int t = blockIdx.x;
+  constexpr int NT = 2;
+  const int cw = CWT ? CWT : cw_rt;
+  __shared__ St sm[NT][WG];
   const int32_t* so = d.segoff + (int64_t)segi * (d.nchains + 1);
-  const int c = find_chain(so, d.nchains, t);
   const int seg = (WG / cw) * RPT;
-  const int64_t base = d.chain_off[c] + (int64_t)(t - so[c]) * seg;
-  const int64_t end = d.chain_off[c + 1];
   const int lane = threadIdx.x % cw, rg = threadIdx.x / cw;
   const int64_t col = (int64_t)blockIdx.y * cw + lane;
   const int64_t colc = col < B ? col : 0;
-  const int64_t r0 = base + (int64_t)rg * RPT;
+  int64_t r0[NT], end[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const int t = min((int64_t)blockIdx.x * NT + q, ntiles - 1);
+    const int c = find_chain(so, d.nchains, t);
+    r0[q] = d.chain_off[c] + (int64_t)(t - so[c]) * seg + (int64_t)rg * RPT;
+    end[q] = d.chain_off[c + 1];
+  }
   // row indices first, then every load unconditionally (rows clamped into the
-  // chain, columns into the matrix), so that all RPT loads are in flight together
-  int32_t nodes[RPT];
+  // chain, columns into the matrix), so that all loads are in flight together
+  int32_t nodes[NT][RPT];
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) nodes[i] = d.node_of_row[min(r0 + i, end - 1)];
-  Tin v[RPT];
+  for (int q = 0; q < NT; ++q)
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) v[i] = x[(int64_t)nodes[i] * ldx + colc];
-  St st;
-  st.zero();
+    for (int i = 0; i < RPT; ++i) {
+      nodes[q][i] = d.node_of_row[min(r0[q] + i, end[q] - 1)];
+      if (CWT == 64) nodes[q][i] = __builtin_amdgcn_readfirstlane(nodes[q][i]);
+    }
+  Tin v[NT][RPT];
 #pragma unroll
-  for (int i = 0; i < RPT; ++i)
-    if (r0 + i < end) st.add(Tr::in(v[i]));
-  sm[threadIdx.x] = st;
+  for (int q = 0; q < NT; ++q)
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) v[q][i] = x[(int64_t)nodes[q][i] * ldx + colc];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    St st;
+    st.zero();
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+      if (r0[q] + i < end[q]) st.add(Tr::in(v[q][i]));
+    sm[q][threadIdx.x] = st;
+  }
   __syncthreads();
   if (rg == 0 && col < B) {
-    St tot = sm[lane];
-    for (int g = 1; g < WG / cw; ++g) tot.combine(sm[g * cw + lane]);
-    A[(int64_t)t * B + col] = tot;
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int64_t t = (int64_t)blockIdx.x * NT + q;
+      if (t < ntiles) {
+        St tot = sm[q][lane];
+        for (int g = 1; g < WG / cw; ++g) tot.combine(sm[q][g * cw + lane]);
+        A[t * B + col] = tot;
+      }
+    }
   }
 }
 
@@ -192,13 +216,14 @@ __global__ __launch_bounds__(WG) void k_scan_carry(DevPoset d, int segi, int dir
 }
 
 // Phase 3: scan inside the tile from its carry; write P chain-major.
-template <typename Tin, typename Tout>
-__global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw, int dir, const Tin* __restrict__ x,
-                                                   int64_t ldx, int64_t B,
+template <typename Tin, typename Tout, int CWT>
+__global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_rt, int dir,
+                                                   const Tin* __restrict__ x, int64_t ldx, int64_t B,
                                                    const typename ScanTraits<Tin, Tout>::St* __restrict__ C,
                                                    Tout* __restrict__ P) {
   using Tr = ScanTraits<Tin, Tout>;
   using St = typename Tr::St;
+  const int cw = CWT ? CWT : cw_rt;
   using Tv = decltype(Tr::in(Tin()));
   __shared__ St sm[WG];
   const int t = blockIdx.x;
@@ -214,7 +239,10 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw,
   const int64_t colc = col < B ? col : 0;
   int32_t nodes[RPT];
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) nodes[i] = d.node_of_row[min(r0 + i, end - 1)];
+  for (int i = 0; i < RPT; ++i) {
+    nodes[i] = d.node_of_row[min(r0 + i, end - 1)];
+    if (CWT == 64) nodes[i] = __builtin_amdgcn_readfirstlane(nodes[i]);
+  }
   Tin raw[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) raw[i] = x[(int64_t)nodes[i] * ldx + colc];
@@ -290,19 +318,23 @@ __global__ __launch_bounds__(WG) void k_gather(DevPoset d, const int32_t* __rest
 // out(x) ⊆ out(y), Theorem 4): at n = 2^20, k = 64 a row differs from the one
 // below in about one other-chain entry.  Preprocessing cuts every chain into
 // runs of at most 128 rows and a bounded number of change events and encodes
-// each run as the niv row of its first element plus the events
-// (row offset u, chain j, new row) of its later rows, own chain excluded.
+// each run as the niv row of its first element plus the events of its later
+// rows, {new row, old row, (row offset << 8) | chain}, own chain excluded
+// (-1 = none).
 //
-// G1 (k_walk_events): one wavefront per run, lanes = 64 right-hand-side
-// columns, niv held one entry per lane.  It gathers the first row in full and
-// keeps acc = Σ_{j != own} P[cur_j] in float64 (exact int64 wrap), applies the
-// events 16 at a time with their gathers in flight (P[new] - P[old]), and
-// stores acc as a snapshot after the first row and after every row with
-// events: S[snap_off[s] + m].
-// G2 (k_walk_combine): a streaming pass, out[node(r)] = P[r] + S[snap_of_row[r]]
-// (the own chain contributes the row itself), 16 rows of a thread in flight.
-// Snapshots are stored in the P type; for float32 this adds one rounding of
-// |acc| <= (Z|f|)(x).
+// G1 keeps, for each run and right-hand side, acc = Σ_{j != own} P[niv_j(r)]
+// in float64 (exact int64 wrap): a full gather for the first row, then
+// acc += P[new] - P[old] per event, 16 (uniform form) or 8 (lane-split form)
+// events with their gathers in flight together.  It stores acc as a snapshot
+// after the first row and after every row with events: S[snap_off[s] + m].
+// G2 is a streaming pass: out[node(r)] = P[r] + S[snap_of_row[r]] (the own
+// chain contributes the row itself), or resid[node(r)] minus that for a
+// refinement residual.  Snapshots are stored in the P type; for float32 this
+// adds one rounding of |acc| <= (Z|f|)(x).
+//
+// Uniform form (k_walk_events, single poset, B >= 32, k <= 64): one wavefront
+// per run, lanes = 64 columns; event fields are read with readlane, so all
+// control flow is scalar.
 template <typename TP>
 __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* __restrict__ nv, WalkTables w,
                                                     const TP* __restrict__ P, int64_t B, TP* __restrict__ S) {
@@ -311,18 +343,14 @@ __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* _
   const int64_t ncb = (B + 63) >> 6;
   const int64_t gw = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
   if (gw >= (int64_t)w.nruns * ncb) return;
-  const int64_t seg = gw / ncb;
+  const int64_t run = gw / ncb;
   const int64_t col = (gw % ncb) * 64 + lane;
   const bool colok = col < B;
   const int64_t colc = colok ? col : 0;
-  const int r0 = w.runs[seg].x;
-  const int c = d.chain_of_row[r0];
+  const int r0 = w.runs[run].x;
   const int k = d.k;
-  const int2* __restrict__ ev = w.ev;
-  const int32_t* __restrict__ ev_off = w.ev_off;
-  const int32_t* __restrict__ snap_off = w.snap_off;
 
-  int cur = lane < k ? nv[(int64_t)r0 * k + lane] : -1;
+  const int cur = lane < k ? nv[(int64_t)r0 * k + lane] : -1;
   W acc = W(0);
   for (int j0 = 0; j0 < k; j0 += 32) {
     TP v[32];
@@ -331,21 +359,21 @@ __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* _
     for (int u = 0; u < 32; ++u) {
       const int j = j0 + u;
       const int t = __builtin_amdgcn_readlane(cur, j & 63);
-      ok[u] = j < k && j != c && t >= 0;
+      ok[u] = j < k && t >= 0 && t != r0;
       v[u] = P[(int64_t)(ok[u] ? t : r0) * B + colc];
     }
 #pragma unroll
     for (int u = 0; u < 32; ++u)
       if (ok[u]) acc += (W)v[u];
   }
-  int64_t m = snap_off[seg];
-  const int64_t mlast = snap_off[seg + 1] - 1;  // never write past the run's own snapshots
+  int64_t m = w.snap_off[run];
+  const int64_t mlast = w.snap_off[run + 1] - 1;  // never write past the run's own snapshots
   if (colok) S[m * B + col] = (TP)acc;
 
-  const int e0 = ev_off[seg], e1 = ev_off[seg + 1];
+  const int e0 = w.ev_off[run], e1 = w.ev_off[run + 1];
   for (int eb = e0; eb < e1; eb += 64) {
     const int ne = min(64, e1 - eb);
-    const int2 evl = lane < ne ? ev[eb + lane] : make_int2(-1, 0);
+    const int4 evl = lane < ne ? w.ev[eb + lane] : make_int4(-1, -1, 0, 0);
     for (int g0 = 0; g0 < ne; g0 += 16) {
       TP vn[16], vo[16];
       bool okn[16], oko[16];
@@ -354,21 +382,19 @@ __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* _
       for (int q = 0; q < 16; ++q) {
         const bool has = g0 + q < ne;
         const int i = has ? g0 + q : 0;
-        const int key = __builtin_amdgcn_readlane(evl.y, i);
         const int nw = __builtin_amdgcn_readlane(evl.x, i);
-        const int j = key & 255;
-        const int old = __builtin_amdgcn_readlane(cur, j & 63);
-        if (has) cur = lane == j ? nw : cur;
+        const int old = __builtin_amdgcn_readlane(evl.y, i);
+        const int key = __builtin_amdgcn_readlane(evl.z, i);
         okn[q] = has && nw >= 0;
         oko[q] = has && old >= 0;
         ue[q] = has ? (key >> 8) : -1;
         vn[q] = P[(int64_t)(okn[q] ? nw : r0) * B + colc];
         vo[q] = P[(int64_t)(oko[q] ? old : r0) * B + colc];
       }
-      // the row offset of the event after this group (or -1 at the end of the run)
+      // row offset of the event after this group (-1 at the end of the run)
       const int inext = g0 + 16;
-      const int unext = inext < ne ? (__builtin_amdgcn_readlane(evl.y, inext) >> 8)
-                                   : (eb + 64 < e1 ? (ev[eb + 64].y >> 8) : -1);
+      const int unext = inext < ne ? (__builtin_amdgcn_readlane(evl.z, inext) >> 8)
+                                   : (eb + 64 < e1 ? (w.ev[eb + 64].z >> 8) : -1);
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         if (ue[q] >= 0) {
@@ -385,12 +411,103 @@ __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* _
   }
 }
 
+// Lane-split form (any B <= 64, batches of posets, any k): a wavefront runs
+// 64/cw runs side by side, cw lanes (columns) each; every lane follows its own
+// run's events with per-lane predication.  The own-chain entry of the first
+// row is the row itself, which identifies it without chain numbers.
 template <typename TP>
-__global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* __restrict__ snap_of_row,
-                                                     const TP* __restrict__ P, const TP* __restrict__ S, int64_t B,
-                                                     TP* __restrict__ out, int64_t ldo) {
+__global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int32_t* __restrict__ nv, WalkTables w,
+                                                          int cw, const TP* __restrict__ P, int64_t B,
+                                                          TP* __restrict__ S) {
   using W = typename Wide<TP>::W;
-  constexpr int cw = 64, RPC = COMBINE_ROWS;
+  const int lane = threadIdx.x & 63;
+  const int nsub = 64 / cw;
+  const int64_t run = ((int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6)) * nsub + lane / cw;
+  const int col = lane % cw;
+  const bool active = run < w.nruns;
+  const bool colok = active && col < B;
+  const int64_t colc = col < B ? col : 0;
+  const int64_t runc = active ? run : 0;
+  const int r0 = w.runs[runc].x;
+  int k;
+  const int32_t* nr;
+  if (d.poset_of_row) {
+    const int p = d.poset_of_row[r0];
+    k = d.k_of_poset[p];
+    nr = nv + d.niv_off[p] + (int64_t)(r0 - d.row_off[p]) * k;
+  } else {
+    k = d.k;
+    nr = nv + (int64_t)r0 * k;
+  }
+  if (!active) k = 0;
+  int kmax = k;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) kmax = max(kmax, __shfl_xor(kmax, off));
+
+  W acc = W(0);
+  for (int j0 = 0; j0 < kmax; j0 += 16) {
+    TP v[16];
+    bool ok[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int j = j0 + u;
+      const int t = j < k ? nr[j] : -1;
+      ok[u] = t >= 0 && t != r0;
+      v[u] = P[(int64_t)(ok[u] ? t : r0) * B + colc];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (ok[u]) acc += (W)v[u];
+  }
+  int64_t m = w.snap_off[runc];
+  const int64_t mlast = w.snap_off[runc + 1] - 1;
+  if (colok) S[m * B + col] = (TP)acc;
+
+  const int e0 = w.ev_off[runc];
+  const int ne = active ? w.ev_off[runc + 1] - e0 : 0;
+  int nemax = ne;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) nemax = max(nemax, __shfl_xor(nemax, off));
+  for (int g0 = 0; g0 < nemax; g0 += 8) {
+    TP vn[8], vo[8];
+    bool okn[8], oko[8];
+    int ue[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const int i = g0 + q;
+      ue[q] = i < ne ? (w.ev[e0 + i].z >> 8) : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = g0 + q;
+      const bool has = i < ne;
+      const int4 e = has ? w.ev[e0 + i] : make_int4(-1, -1, 0, 0);
+      okn[q] = e.x >= 0;
+      oko[q] = e.y >= 0;
+      vn[q] = P[(int64_t)(okn[q] ? e.x : r0) * B + colc];
+      vo[q] = P[(int64_t)(oko[q] ? e.y : r0) * B + colc];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (ue[q] >= 0) {
+        if (okn[q]) acc += (W)vn[q];
+        if (oko[q]) acc -= (W)vo[q];
+        if (ue[q + 1] != ue[q]) {
+          m = min(m + 1, mlast);
+          if (colok) S[m * B + col] = (TP)acc;
+        }
+      }
+    }
+  }
+}
+
+template <typename TP, typename Tres, bool RESID>
+__global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* __restrict__ snap_of_row, int cw,
+                                                     const TP* __restrict__ P, const TP* __restrict__ S, int64_t B,
+                                                     TP* __restrict__ out, int64_t ldo, const Tres* __restrict__ res,
+                                                     int64_t ldr) {
+  using W = typename Wide<TP>::W;
+  constexpr int RPC = COMBINE_ROWS;
   const int RG = WG / cw;
   const int64_t rbase = ((int64_t)blockIdx.x * RG + threadIdx.x / cw) * RPC;
   const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
@@ -412,8 +529,48 @@ __global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* 
   }
   if (col >= B) return;
 #pragma unroll
-  for (int i = 0; i < RPC; ++i)
-    if (rbase + i < d.n) out[(int64_t)nd[i] * ldo + col] = (TP)((W)pv[i] + (W)sv[i]);
+  for (int i = 0; i < RPC; ++i) {
+    if (rbase + i < d.n) {
+      if constexpr (RESID)
+        out[(int64_t)nd[i] * ldo + col] = (TP)((double)res[(int64_t)nd[i] * ldr + col] - ((W)pv[i] + (W)sv[i]));
+      else
+        out[(int64_t)nd[i] * ldo + col] = (TP)((W)pv[i] + (W)sv[i]);
+    }
+  }
+}
+
+template <typename TP>
+hipError_t walk_typed(const DevPoset& d, const int32_t* nv, const WalkTables& w, const void* P, int64_t B, void* out,
+                      int64_t ldo, ElemType tres, const void* resid, int64_t ldr, void* snaps, LaunchHook* hook,
+                      hipStream_t s) {
+  const bool uniform = !d.poset_of_row && d.k <= 64 && B >= 32;
+  const int cw = col_width(B);
+  if (hook) hook->before(0, s);
+  if (uniform) {
+    const int64_t waves = (int64_t)w.nruns * ((B + 63) / 64);
+    hipLaunchKernelGGL((k_walk_events<TP>), dim3((unsigned)((waves + (WG / 64) - 1) / (WG / 64))), dim3(WG), 0, s,
+                       d, nv, w, (const TP*)P, B, (TP*)snaps);
+  } else {
+    const int64_t waves = (w.nruns + (64 / cw) - 1) / (64 / cw);
+    hipLaunchKernelGGL((k_walk_events_split<TP>), dim3((unsigned)((waves + (WG / 64) - 1) / (WG / 64))), dim3(WG),
+                       0, s, d, nv, w, cw, (const TP*)P, B, (TP*)snaps);
+  }
+  if (hook) hook->after(0, s);
+  if (hook) hook->before(1, s);
+  const int ccw = uniform ? 64 : cw;
+  const int64_t rows_per_block = (WG / ccw) * COMBINE_ROWS;
+  const dim3 gc((unsigned)((d.n + rows_per_block - 1) / rows_per_block), (unsigned)((B + ccw - 1) / ccw));
+  if (resid && tres == E_F32)
+    hipLaunchKernelGGL((k_walk_combine<TP, float, true>), gc, dim3(WG), 0, s, d, w.snap_of_row, ccw, (const TP*)P,
+                       (const TP*)snaps, B, (TP*)out, ldo, (const float*)resid, ldr);
+  else if (resid)
+    hipLaunchKernelGGL((k_walk_combine<TP, double, true>), gc, dim3(WG), 0, s, d, w.snap_of_row, ccw, (const TP*)P,
+                       (const TP*)snaps, B, (TP*)out, ldo, (const double*)resid, ldr);
+  else
+    hipLaunchKernelGGL((k_walk_combine<TP, TP, false>), gc, dim3(WG), 0, s, d, w.snap_of_row, ccw, (const TP*)P,
+                       (const TP*)snaps, B, (TP*)out, ldo, (const TP*)nullptr, 0);
+  if (hook) hook->after(1, s);
+  return hipGetLastError();
 }
 
 // Batched gather over many posets of different width: row r belongs to
@@ -555,12 +712,21 @@ hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int6
   St* C = A + ntiles * B;
   dim3 g((unsigned)ntiles, (unsigned)((B + cw - 1) / cw));
   if (phase == 0) {
-    hipLaunchKernelGGL((k_scan_reduce<Tin, Tout>), g, dim3(WG), 0, s, d, segi, cw, (const Tin*)x, ldx, B, A);
+    const dim3 g2((unsigned)((ntiles + 1) / 2), (unsigned)((B + cw - 1) / cw));
+    if (cw == 64)
+      hipLaunchKernelGGL((k_scan_reduce<Tin, Tout, 64>), g2, dim3(WG), 0, s, d, segi, cw, (const Tin*)x, ldx, B,
+                         ntiles, A);
+    else
+      hipLaunchKernelGGL((k_scan_reduce<Tin, Tout, 0>), g2, dim3(WG), 0, s, d, segi, cw, (const Tin*)x, ldx, B,
+                         ntiles, A);
   } else if (phase == 1) {
     hipLaunchKernelGGL((k_scan_carry<St>), dim3((unsigned)d.nchains, (unsigned)((B + 15) / 16)), dim3(WG), 0, s, d,
                        segi, dir, B, (const St*)A, C);
+  } else if (cw == 64) {
+    hipLaunchKernelGGL((k_scan_apply<Tin, Tout, 64>), g, dim3(WG), 0, s, d, segi, cw, dir, (const Tin*)x, ldx, B,
+                       (const St*)C, (Tout*)P);
   } else {
-    hipLaunchKernelGGL((k_scan_apply<Tin, Tout>), g, dim3(WG), 0, s, d, segi, cw, dir, (const Tin*)x, ldx, B,
+    hipLaunchKernelGGL((k_scan_apply<Tin, Tout, 0>), g, dim3(WG), 0, s, d, segi, cw, dir, (const Tin*)x, ldx, B,
                        (const St*)C, (Tout*)P);
   }
   return hipGetLastError();
@@ -585,8 +751,17 @@ hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P,
   const int cw = col_width(B);
   const dim3 g = grid2(d.n, cw, B);
   const int32_t* nv = up ? d.niv_up : d.niv;
+  if (resid && (tp != E_F64 || tout != E_F64)) return hipErrorInvalidValue;
+  // the walking gather when its tables and snapshot scratch are there
+  const WalkTables& w = d.walk[up ? 1 : 0];
+  if (w.runs && snaps && tp == tout && (B <= 64 || (!d.poset_of_row && d.k <= 64))) {
+    if (tp == E_F32) return walk_typed<float>(d, nv, w, P, B, out, ldo, tres, resid, ldr, snaps, hook, s);
+    if (tp == E_F64) return walk_typed<double>(d, nv, w, P, B, out, ldo, tres, resid, ldr, snaps, hook, s);
+    if (tp == E_I64) return walk_typed<int64_t>(d, nv, w, P, B, out, ldo, tres, resid, ldr, snaps, hook, s);
+    return hipErrorInvalidValue;
+  }
+  // otherwise one thread per (row, column) over all k niv entries
   if (resid) {
-    if (tp != E_F64 || tout != E_F64) return hipErrorInvalidValue;
     if (tres == E_F32)
       hipLaunchKernelGGL((k_gather<double, double, float, true>), g, dim3(WG), 0, s, d, nv, cw, (const double*)P, B,
                          (double*)out, ldo, (const float*)resid, ldr);
@@ -609,35 +784,6 @@ hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P,
                          B, (int64_t*)out, ldo);
     else
       return hipErrorInvalidValue;
-    return hipGetLastError();
-  }
-  const WalkTables& w = d.walk[up ? 1 : 0];
-  if (w.runs && snaps && d.k <= 64 && B >= 32 && tp == tout) {
-    const int64_t waves = (int64_t)w.nruns * ((B + 63) / 64);
-    const dim3 gw((unsigned)((waves + (WG / 64) - 1) / (WG / 64)));
-    const dim3 gc((unsigned)((d.n + (WG / 64) * COMBINE_ROWS - 1) / ((WG / 64) * COMBINE_ROWS)),
-                  (unsigned)((B + 63) / 64));
-    if (hook) hook->before(0, s);
-    if (tp == E_F32)
-      hipLaunchKernelGGL((k_walk_events<float>), gw, dim3(WG), 0, s, d, nv, w, (const float*)P, B, (float*)snaps);
-    else if (tp == E_F64)
-      hipLaunchKernelGGL((k_walk_events<double>), gw, dim3(WG), 0, s, d, nv, w, (const double*)P, B,
-                         (double*)snaps);
-    else
-      hipLaunchKernelGGL((k_walk_events<int64_t>), gw, dim3(WG), 0, s, d, nv, w, (const int64_t*)P, B,
-                         (int64_t*)snaps);
-    if (hook) hook->after(0, s);
-    if (hook) hook->before(1, s);
-    if (tp == E_F32)
-      hipLaunchKernelGGL((k_walk_combine<float>), gc, dim3(WG), 0, s, d, w.snap_of_row, (const float*)P,
-                         (const float*)snaps, B, (float*)out, ldo);
-    else if (tp == E_F64)
-      hipLaunchKernelGGL((k_walk_combine<double>), gc, dim3(WG), 0, s, d, w.snap_of_row, (const double*)P,
-                         (const double*)snaps, B, (double*)out, ldo);
-    else
-      hipLaunchKernelGGL((k_walk_combine<int64_t>), gc, dim3(WG), 0, s, d, w.snap_of_row, (const int64_t*)P,
-                         (const int64_t*)snaps, B, (int64_t*)out, ldo);
-    if (hook) hook->after(1, s);
     return hipGetLastError();
   }
   if (tp == E_I64 && tout == E_I64)

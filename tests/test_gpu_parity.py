@@ -135,7 +135,7 @@ def test_results_independent_of_decomposition_and_schedule(px, cfg0):
 
 
 # ------------------------------------------------------------ float accuracy
-@pytest.mark.parametrize("B", [1, 5, 16, 64])
+@pytest.mark.parametrize("B", [1, 5, 16, 33, 64, 100])
 def test_f32_zeta_tolerance(px, cfg0, B):
     p, R = cfg0
     P = build(px, p)
