@@ -102,6 +102,140 @@ def cpu_baseline(p, f, budget_s: float):
                       f"(down-set by BFS, float64 pairwise sums), {dt:.1f} s single-threaded"}
 
 
+def _time(fn, steps, sync):
+    for _ in range(2):
+        fn()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return (time.perf_counter() - t0) / steps
+
+
+def legs_config1(px, P, p, dev, steps):
+    """int64 zeta and the exact Möbius round trip, and the float32 adjoint, on the headline poset."""
+    import torch
+    import workloads as W
+    sync = torch.cuda.synchronize
+    out = {}
+    fi = torch.from_numpy(W.functions(p.n, B, "int", seed=3, lo=-1000, hi=1000)).to(dev)
+    gi = torch.empty_like(fi)
+    fb = torch.empty_like(fi)
+    P.reserve(torch.int64, B)
+    t = _time(lambda: px.zeta(P, fi, out=gi), steps, sync)
+    out["zeta_int64"] = {"ms": round(t * 1e3, 4), "node_rhs_per_s": p.n * B / t}
+    t = _time(lambda: px.mobius(P, gi, out=fb), max(2, steps // 4), sync)
+    out["mobius_int64"] = {"ms": round(t * 1e3, 4), "node_rhs_per_s": p.n * B / t,
+                           "levels": P.info["levels_down"], "roundtrip_exact": bool(torch.equal(fb, fi))}
+    del fi, gi, fb
+    ff = torch.from_numpy(W.functions(p.n, B, "normal", seed=4)).to(dev)
+    ga = torch.empty_like(ff)
+    t = _time(lambda: px.zeta_adjoint(P, ff, out=ga), steps, sync)
+    out["zeta_adjoint_f32"] = {"ms": round(t * 1e3, 4), "node_rhs_per_s": p.n * B / t}
+    return out
+
+
+def leg_grid(px, dev, steps, refine=3):
+    """Config 2: the 4096 x 64 grid, B = 16 float32 g ~ U(-1, 1).  Batched float32 Möbius with
+    float64-residual refinement against B single-RHS float64 Möbius calls."""
+    import torch
+    import workloads as W
+    sync = torch.cuda.synchronize
+    q = W.grid_poset(4096, 64)
+    G = px.poset_build(q.n, q.indptr, q.indices, q.chain_of, q.chain_pos, device=0)
+    Bg = 16
+    g = torch.from_numpy(W.functions(q.n, Bg, "uniform", seed=10, lo=-1.0, hi=1.0)).to(dev)
+    f = torch.empty_like(g)
+    G.reserve(torch.float32, Bg)
+    t32 = _time(lambda: px.mobius(G, g, out=f, max_refine=refine), steps, sync)
+    _, rep = px.mobius(G, g, out=f, max_refine=refine, report=True)
+    g64 = g.double()
+    cols = [g64[:, b:b + 1].contiguous() for b in range(Bg)]
+    f64 = [torch.empty_like(c) for c in cols]
+    G.reserve(torch.float64, 1)
+    t64 = _time(lambda: [px.mobius(G, c, out=o) for c, o in zip(cols, f64)], max(2, steps // 4), sync)
+    # agreement of the refined float32 result with the float64 solve, normwise per column
+    f64m = torch.cat(f64, dim=1)
+    err = ((f.double() - f64m).abs().amax(0) / f64m.abs().amax(0)).max().item()
+    return {"workload": "grid 4096x64 (n=262144, k=64), B=16 float32 U(-1,1)",
+            "levels": G.info["levels_down"], "mirsky_levels": G.info["mirsky_levels"],
+            "f32_refined_ms": round(t32 * 1e3, 4), "refine_steps": refine,
+            "f64_single_rhs_x16_ms": round(t64 * 1e3, 4), "speedup": round(t64 / t32, 2),
+            "rel_err_vs_f64": err, "report": rep}
+
+
+def leg_batched(px, dev, steps, count=512):
+    """Config 3: uneven posets, forward zeta + adjoint per step, replayed from a HIP graph."""
+    import torch
+    import workloads as W
+    from paper_2211_13706_amd.autograd import batch_zeta_fn
+    sync = torch.cuda.synchronize
+    t0 = time.perf_counter()
+    posets = W.batched_posets(count, seed=40)
+    Ps = [px.poset_build(q.n, q.indptr, q.indices, q.chain_of, q.chain_pos, device=0) for q in posets]
+    bt = px.batch_build(Ps)
+    t_prep = time.perf_counter() - t0
+    Bb = 8
+    f = torch.randn(bt.rows, Bb, device=dev, requires_grad=True)
+    w = torch.randn(bt.rows, Bb, device=dev)
+    bt.reserve(torch.float32, Bb)
+
+    def step():
+        f.grad = None
+        (batch_zeta_fn(bt, f) * w).sum().backward()
+    t_eager = _time(step, steps, sync)
+    g = torch.empty(bt.rows, Bb, device=dev)
+    gw = torch.empty(bt.rows, Bb, device=dev)
+    fd = f.detach()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        px.zeta_batched(bt, fd, out=g)
+        px.zeta_adjoint_batched(bt, w, out=gw)
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        px.zeta_batched(bt, fd, out=g)
+        px.zeta_adjoint_batched(bt, w, out=gw)
+    t_graph = _time(graph.replay, steps, sync)
+    ok = bool(torch.allclose(gw, f.grad, rtol=0, atol=0))
+    return {"workload": f"{count} posets, n log-uniform in [1000, 65536], k in 4..128, B=8 float32",
+            "rows": int(bt.rows), "preprocess_s": round(t_prep, 2),
+            "autograd_fwd_bwd_ms": round(t_eager * 1e3, 4), "graph_fwd_adj_ms": round(t_graph * 1e3, 4),
+            "node_rhs_per_s_graph": 2 * bt.rows * Bb / t_graph, "graph_grad_equal_eager": ok}
+
+
+def leg_large(px, dev, steps):
+    """Config 4: n = 2^23, k = 32, B = 16 float32: zeta, float32 Möbius(zeta(f)) with refinement,
+    and the exact int64 round trip."""
+    import torch
+    import workloads as W
+    sync = torch.cuda.synchronize
+    t0 = time.perf_counter()
+    q = W.chain_poset(1 << 23, 32, 3, seed=4)
+    L = px.poset_build(q.n, q.indptr, q.indices, q.chain_of, q.chain_pos, device=0)
+    t_prep = time.perf_counter() - t0
+    Bl = 16
+    f = torch.from_numpy(W.functions(q.n, Bl, "normal", seed=5)).to(dev)
+    g = torch.empty_like(f)
+    L.reserve(torch.float32, Bl)
+    tz = _time(lambda: px.zeta(L, f, out=g), steps, sync)
+    try:
+        f2, rep = px.mobius(L, g, max_refine=2, report=True)
+        err = ((f2 - f).abs().amax(0) / f.abs().amax(0)).max().item()
+    except px.PosetxError as e:  # the float Möbius of this poset is ill-conditioned
+        rep, err = {"status": e.name}, None
+    fi = torch.from_numpy(W.functions(q.n, Bl, "int", seed=6, lo=-1000, hi=1000)).to(dev)
+    gi = px.zeta(L, fi)
+    tm = _time(lambda: px.mobius(L, gi), 2, sync)
+    exact = bool(torch.equal(px.mobius(L, gi), fi))
+    return {"workload": "n=8388608, k=32, 3 cross edges, B=16", "preprocess_s": round(t_prep, 2),
+            "levels": L.info["levels_down"], "zeta_f32_ms": round(tz * 1e3, 4),
+            "zeta_node_rhs_per_s": q.n * Bl / tz, "mobius_int64_ms": round(tm * 1e3, 4),
+            "int64_roundtrip_exact": exact, "f32_roundtrip_rel_err": err, "f32_refine_report": rep}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +243,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--legs", default="default", choices=["none", "default", "all"],
+                    help="extra measurements of the other hot-path rows (all: also the batched and n=2^23 configs)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for counter scaling)")
     args = ap.parse_args()
@@ -198,6 +334,20 @@ def main():
         "generate_s": round(t_gen, 3),
         "kernel_hash": kernel_hash(),
     }
+    if args.legs != "none":
+        def note(msg):
+            print(f"[bench] {msg}", file=sys.stderr, flush=True)
+        note("legs: config 1 int64 and adjoint")
+        legs = legs_config1(px, P, p, dev, args.steps)
+        note("legs: grid Möbius")
+        legs["grid_mobius"] = leg_grid(px, dev, args.steps)
+        if args.legs == "all":
+            del P
+            note("legs: batched posets")
+            legs["batched"] = leg_batched(px, dev, args.steps)
+            note("legs: n = 2^23")
+            legs["large"] = leg_large(px, dev, max(2, args.steps // 4))
+        out["legs"] = legs
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, f_host, args.cpu_budget)
     print(json.dumps(out), flush=True)
