@@ -271,6 +271,9 @@ def main():
     f_host = W.functions(p.n, B, "normal", seed=2)
     f = torch.from_numpy(f_host).to(dev)
     g = torch.empty_like(f)
+    t0 = time.perf_counter()
+    tune = P.autotune(torch.float32, B)
+    t_tune = time.perf_counter() - t0
     P.reserve(torch.float32, B)
     if args.copy_ref:
         a = torch.empty(64 << 20, dtype=torch.float32, device=dev).normal_()
@@ -330,7 +333,8 @@ def main():
         "phases": phases,
         "preprocess_s": {"total": round(t_prep, 3), **{k: round(v, 3) for k, v in P.info.items()
                                                       if k.startswith("t_")}},
-        "walk": {k: P.info[k] for k in ("walk_runs", "walk_events", "walk_snapshots")},
+        "walk": {k: P.info[k] for k in ("walk_runs", "walk_events", "walk_snapshots", "walk_T", "walk_emax")},
+        "autotune": {**tune, "seconds": round(t_tune, 2)},
         "generate_s": round(t_gen, 3),
         "kernel_hash": kernel_hash(),
     }

@@ -85,6 +85,8 @@ typedef struct {
   int64_t walk_runs;      /* runs of the walking gather over the niv map (0: not used)  */
   int64_t walk_events;    /* niv change events inside those runs                        */
   int64_t walk_snapshots; /* running-sum snapshots those runs store                     */
+  int64_t walk_T;         /* their run length and event cap (see px_autotune)            */
+  int64_t walk_emax;
   int32_t chains_planted; /* 1 if the caller supplied the chains                        */
   int32_t device;
   double t_validate, t_chains, t_niv, t_levels, t_upload;  /* preprocessing seconds      */
@@ -189,6 +191,29 @@ px_status px_zeta_batched(px_batch* b, int dtype, const void* f, int64_t ldf, vo
                           int64_t ldg, int64_t B, void* stream);
 px_status px_zeta_adjoint_batched(px_batch* b, int dtype, const void* w, int64_t ldw, void* out,
                                   int64_t ldo, int64_t B, void* stream);
+
+/* Report of an autotuning call. */
+typedef struct {
+  int32_t walk_T;         /* run length of the walking gather (rows)                     */
+  int32_t walk_emax;      /* change events per run at most                               */
+  int32_t rhs_tile;       /* column tile of the lane-split gather (0 = smallest >= B)   */
+  double ms_best;         /* one zeta call with the chosen shape, milliseconds           */
+  double ms_default;      /* the same with the default shape (-1 if not timed)           */
+  int32_t from_cache;     /* 1 if the shape came from the cache without timing           */
+} px_tune_report;
+
+/*
+ * Autotuner of the gather tile shapes: for a poset, the chain tile (walk run
+ * length 64/128/256 rows x event cap 48/96/192) and, for B < 32, the RHS tile
+ * (columns per lane group); for a batch, the RHS tile.  Every candidate is
+ * timed on the device with HIP events (median of 5 zeta calls on the null
+ * stream) and the fastest is kept in the handle.  Results are cached per
+ * shape for the process and, when the environment variable POSETX_TUNE_CACHE
+ * names a file, appended there and reused by later processes.  Synchronous;
+ * allocates two [n, B] scratch matrices while it runs.  rep may be NULL.
+ */
+px_status px_autotune(px_poset* p, int dtype, int64_t B, px_tune_report* rep);
+px_status px_batch_autotune(px_batch* b, int dtype, int64_t B, px_tune_report* rep);
 
 /* Optional per-kernel timing.  px_profile(1) resets the totals and starts recording a
  * pair of HIP events on the launch stream around every kernel launch of every handle;

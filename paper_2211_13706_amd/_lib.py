@@ -25,7 +25,7 @@ EXPORTS = [
     "px_poset_levels", "px_reserve", "px_zeta", "px_zeta_adjoint", "px_mobius", "px_mobius_adjoint",
     "px_batch_build", "px_batch_free", "px_batch_reserve", "px_batch_rows", "px_zeta_batched",
     "px_zeta_adjoint_batched", "px_last_error", "px_version", "px_profile", "px_profile_read",
-    "px_profile_phase_name",
+    "px_profile_phase_name", "px_autotune", "px_batch_autotune",
 ]
 
 
@@ -39,9 +39,18 @@ class PosetxError(RuntimeError):
 class Info(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n", "k", "edges", "nnz_niv", "nnz_niv_up", "max_chain", "levels_down", "levels_up",
-        "mirsky_levels", "udep_levels", "device_bytes", "walk_runs", "walk_events", "walk_snapshots")] + [
+        "mirsky_levels", "udep_levels", "device_bytes", "walk_runs", "walk_events", "walk_snapshots", "walk_T",
+        "walk_emax")] + [
         ("chains_planted", ctypes.c_int32), ("device", ctypes.c_int32)] + [
         (name, ctypes.c_double) for name in ("t_validate", "t_chains", "t_niv", "t_levels", "t_upload")]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("walk_T", ctypes.c_int32), ("walk_emax", ctypes.c_int32), ("rhs_tile", ctypes.c_int32),
+                ("ms_best", ctypes.c_double), ("ms_default", ctypes.c_double), ("from_cache", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -78,6 +87,8 @@ def _declare(lib):
         "px_zeta_batched": [P, i32, P, i64, P, i64, i64, P],
         "px_zeta_adjoint_batched": [P, i32, P, i64, P, i64, i64, P],
         "px_profile": [i32],
+        "px_autotune": [P, i32, i64, ctypes.POINTER(TuneReport)],
+        "px_batch_autotune": [P, i32, i64, ctypes.POINTER(TuneReport)],
         "px_profile_read": [P, P, i32],
     }
     for name, args in sig.items():

@@ -7,7 +7,10 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -100,11 +103,12 @@ void seg_tables(const std::vector<int32_t>& chain_off, std::vector<int32_t>& seg
 }
 
 // Runs of the walking gather for one niv map (see px::WalkTables).  Every chain
-// is cut into runs of at most kWalkT rows and at most kWalkEvents change
+// is cut into runs of at most T rows (T <= 255) and at most `emax` change
 // events, so that no wavefront's serial event work is much longer than the
 // average; the runs are then ordered by the relative height of their middle
 // inside their chain (ties by chain), so that the waves resident together
-// gather from one height band of every chain.
+// gather from one height band of every chain.  Defaults; px_autotune picks
+// per poset and B.
 constexpr int kWalkT = 128;
 constexpr int kWalkEvents = 96;
 
@@ -115,7 +119,7 @@ struct HostWalk {
   int32_t nsnap = 0;
 };
 
-void build_walk(const px::Prep& P, const std::vector<int32_t>& nv, HostWalk& W) {
+void build_walk(const px::Prep& P, const std::vector<int32_t>& nv, HostWalk& W, int T, int emax) {
   const int64_t k = P.k, n = P.n;
   auto nchanges = [&](int32_t r) {  // other-chain entries of row r that differ from row r-1
     const int32_t c = P.chain_of_row[r];
@@ -136,9 +140,9 @@ void build_walk(const px::Prep& P, const std::vector<int32_t>& nv, HostWalk& W) 
     while (r < hi) {
       const int32_t r0 = r++;
       int ev = 0;
-      while (r < hi && r - r0 < kWalkT) {
+      while (r < hi && r - r0 < T) {
         const int e = nchanges(r);
-        if (ev + e > kWalkEvents && r > r0 + 1) break;
+        if (ev + e > emax && r > r0 + 1) break;
         ev += e;
         ++r;
       }
@@ -318,6 +322,7 @@ struct px_poset {
   int64_t nevents[2] = {0, 0};
   int32_t nsnap[2] = {0, 0};
   std::vector<int32_t> hw_runs[2], hw_ev[2], hw_ev_off[2], hw_snap_off[2], hw_snap_of_row[2];
+  int32_t walk_T = 0, walk_emax = 0;
   px::DevPoset dp;
   Workspace ws;
   int64_t device_bytes = 0;
@@ -502,6 +507,113 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   return PX_OK;
 }
 
+// (Re)build and upload the walk tables of both niv maps with run length T and
+// event cap emax.
+hipError_t set_walk(px_poset* p, int T, int emax) {
+  const px::Prep& P = p->prep;
+  hipError_t e = hipSuccess;
+  for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
+    if (dir == 1 && !p->has_up) break;
+    HostWalk W;
+    build_walk(P, dir ? P.niv_up : P.niv, W, T, emax);
+    int32_t** db = p->d_walk[dir];
+    for (int i = 0; i < 5; ++i)
+      if (db[i]) {
+        (void)hipFree(db[i]);
+        db[i] = nullptr;
+      }
+    px::WalkTables& t = p->dp.walk[dir];
+    const int32_t keep_cw = t.cw;
+    t = px::WalkTables();
+    t.cw = keep_cw;
+    int64_t b = 0;
+    e = upload(&db[0], W.runs.data(), W.runs.size(), b);
+    if (e == hipSuccess) e = upload(&db[1], W.ev.data(), W.ev.size(), b);
+    if (e == hipSuccess) e = upload(&db[2], W.ev_off.data(), W.ev_off.size(), b);
+    if (e == hipSuccess) e = upload(&db[3], W.snap_off.data(), W.snap_off.size(), b);
+    if (e == hipSuccess) e = upload(&db[4], W.snap_of_row.data(), W.snap_of_row.size(), b);
+    if (e != hipSuccess) break;
+    p->nevents[dir] = (int64_t)W.ev.size() / 4;
+    p->nsnap[dir] = W.nsnap;
+    t.nruns = (int32_t)(W.runs.size() / 2);
+    t.nsnap = W.nsnap;
+    t.runs = (const int2*)db[0];
+    t.ev = (const int4*)db[1];
+    t.ev_off = db[2];
+    t.snap_off = db[3];
+    t.snap_of_row = db[4];
+    p->hw_runs[dir] = std::move(W.runs);
+    p->hw_ev[dir] = std::move(W.ev);
+    p->hw_ev_off[dir] = std::move(W.ev_off);
+    p->hw_snap_off[dir] = std::move(W.snap_off);
+    p->hw_snap_of_row[dir] = std::move(W.snap_of_row);
+  }
+  p->walk_T = T;
+  p->walk_emax = emax;
+  return e;
+}
+
+// Autotuning: time candidate tile shapes of the walking gather on the device
+// and keep the fastest.  Results are cached per shape (n, k, niv size, B,
+// dtype) in the process and, if POSETX_TUNE_CACHE names a file, across
+// processes (one "key T emax cw ms" line per tuned shape).
+struct TuneResult {
+  int T = kWalkT, emax = kWalkEvents, cw = 0;
+  double ms = 0;
+};
+std::mutex tune_mu;
+std::map<std::string, TuneResult> tune_cache;
+bool tune_loaded = false;
+
+void tune_load() {
+  if (tune_loaded) return;
+  tune_loaded = true;
+  const char* path = std::getenv("POSETX_TUNE_CACHE");
+  if (!path) return;
+  FILE* fh = std::fopen(path, "r");
+  if (!fh) return;
+  char key[256];
+  TuneResult r;
+  while (std::fscanf(fh, "%255s %d %d %d %lf", key, &r.T, &r.emax, &r.cw, &r.ms) == 5) tune_cache[key] = r;
+  std::fclose(fh);
+}
+
+void tune_store(const std::string& key, const TuneResult& r) {
+  tune_cache[key] = r;
+  const char* path = std::getenv("POSETX_TUNE_CACHE");
+  if (!path) return;
+  FILE* fh = std::fopen(path, "a");
+  if (!fh) return;
+  std::fprintf(fh, "%s %d %d %d %.6f\n", key.c_str(), r.T, r.emax, r.cw, r.ms);
+  std::fclose(fh);
+}
+
+// Milliseconds of one zeta call (median of reps), on the null stream.
+template <typename Run>
+double time_ms(Run run, int reps) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return -1;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return -1;
+  }
+  std::vector<float> t;
+  if (!run()) return -1;  // warm-up
+  for (int i = 0; i < reps; ++i) {
+    (void)hipEventRecord(a, nullptr);
+    if (!run()) return -1;
+    (void)hipEventRecord(b, nullptr);
+    (void)hipEventSynchronize(b);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, a, b);
+    t.push_back(ms);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  std::sort(t.begin(), t.end());
+  return t[t.size() / 2];
+}
+
 }  // namespace
 
 extern "C" {
@@ -574,32 +686,7 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
     if (e == hipSuccess) e = upload(&p->d_lev_down, P.lev_down_rows.data(), P.lev_down_rows.size(), b);
     if (e == hipSuccess && p->has_up) e = upload(&p->d_lev_up, P.lev_up_rows.data(), P.lev_up_rows.size(), b);
     if (e == hipSuccess) e = upload(&p->d_segoff, segoff.data(), segoff.size(), b);
-    for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
-      if (dir == 1 && !p->has_up) break;
-      HostWalk W;
-      build_walk(P, dir ? P.niv_up : P.niv, W);
-      p->nevents[dir] = (int64_t)W.ev.size() / 4;
-      p->nsnap[dir] = W.nsnap;
-      px::WalkTables& t = p->dp.walk[dir];
-      t.nruns = (int32_t)(W.runs.size() / 2);
-      t.nsnap = W.nsnap;
-      int32_t** db = p->d_walk[dir];
-      e = upload(&db[0], W.runs.data(), W.runs.size(), b);
-      if (e == hipSuccess) e = upload(&db[1], W.ev.data(), W.ev.size(), b);
-      if (e == hipSuccess) e = upload(&db[2], W.ev_off.data(), W.ev_off.size(), b);
-      if (e == hipSuccess) e = upload(&db[3], W.snap_off.data(), W.snap_off.size(), b);
-      if (e == hipSuccess) e = upload(&db[4], W.snap_of_row.data(), W.snap_of_row.size(), b);
-      p->hw_runs[dir] = W.runs;
-      p->hw_ev[dir] = W.ev;
-      p->hw_ev_off[dir] = W.ev_off;
-      p->hw_snap_off[dir] = W.snap_off;
-      p->hw_snap_of_row[dir] = W.snap_of_row;
-      t.runs = (const int2*)db[0];
-      t.ev = (const int4*)db[1];
-      t.ev_off = db[2];
-      t.snap_off = db[3];
-      t.snap_of_row = db[4];
-    }
+    if (e == hipSuccess) e = set_walk(p, kWalkT, kWalkEvents);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       free_poset_device(p);
@@ -650,6 +737,8 @@ px_status px_poset_info(const px_poset* p, px_info* o) {
   o->walk_runs = p->dp.walk[0].nruns;
   o->walk_events = p->nevents[0];
   o->walk_snapshots = p->nsnap[0];
+  o->walk_T = p->walk_T;
+  o->walk_emax = p->walk_emax;
   o->chains_planted = P.planted ? 1 : 0;
   o->device = p->device;
   o->t_validate = P.t_validate;
@@ -715,6 +804,82 @@ px_status px_mobius(px_poset* p, int dtype, const void* g, int64_t ldg, void* f,
 px_status px_mobius_adjoint(px_poset* p, int dtype, const void* v, int64_t ldv, void* out, int64_t ldo, int64_t B,
                             int max_refine, double tol, void* stream, px_refine_report* rep) {
   return mobius_impl(p, true, dtype, v, ldv, out, ldo, B, max_refine, tol, stream, rep);
+}
+
+px_status px_autotune(px_poset* p, int dtype, int64_t B, px_tune_report* rep) {
+  if (!p) return fail(PX_EINVAL, "null poset");
+  if (p->host_only) return fail(PX_EUNSUPPORTED, "poset was built with PX_BUILD_HOST_ONLY");
+  if (dtype != PX_I64 && dtype != PX_F32 && dtype != PX_F64) return fail(PX_EINVAL, "unknown dtype");
+  if (B < 1) return fail(PX_EINVAL, "B must be >= 1");
+  const int64_t n = p->prep.n;
+  if (rep) *rep = px_tune_report{p->walk_T, p->walk_emax, p->dp.walk[0].cw, 0.0, 0.0, 0};
+  if (n == 0) return PX_OK;
+  DeviceGuard dg(p->device);
+  if (!dg.ok) return fail(PX_EHIP, "hipSetDevice failed");
+  std::lock_guard<std::mutex> lk(tune_mu);
+  tune_load();
+  const std::string key = "poset:" + std::to_string(n) + ":" + std::to_string(p->prep.k) + ":" +
+                          std::to_string(p->prep.nnz_niv) + ":" + std::to_string(B) + ":" + std::to_string(dtype);
+  auto apply = [&](const TuneResult& r) -> px_status {
+    if (r.T != p->walk_T || r.emax != p->walk_emax) {
+      hipError_t e = set_walk(p, r.T, r.emax);
+      if (e != hipSuccess) return hip_status(e, "walk table upload");
+    }
+    p->dp.walk[0].cw = p->dp.walk[1].cw = r.cw;
+    return PX_OK;
+  };
+  auto it = tune_cache.find(key);
+  if (it != tune_cache.end()) {
+    px_status st = apply(it->second);
+    if (rep) *rep = px_tune_report{it->second.T, it->second.emax, it->second.cw, it->second.ms, 0.0, 1};
+    return st;
+  }
+  const size_t bytes = (size_t)n * B * elem_size(dtype);
+  void *f = nullptr, *g = nullptr;
+  if (hipMalloc(&f, bytes) != hipSuccess || hipMalloc(&g, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    if (f) (void)hipFree(f);
+    return fail(PX_ENOMEM, "autotune buffers");
+  }
+  (void)hipMemset(f, 0, bytes);
+  auto run = [&]() { return zeta_impl(p, false, dtype, f, B, g, B, B, nullptr) == PX_OK; };
+  const int T0 = p->walk_T, E0 = p->walk_emax;
+  TuneResult best;
+  best.ms = 1e30;
+  double ms_default = -1;
+  const int dcw = px::col_width(B);
+  std::vector<int> cws{0};
+  if (B < 32)
+    for (int c = 2 * dcw; c <= 64 && c <= 4 * dcw; c *= 2) cws.push_back(c);
+  px_status st = PX_OK;
+  for (int T : {64, 128, 256}) {
+    for (int E : {48, 96, 192}) {
+      hipError_t e = set_walk(p, T, E);
+      if (e != hipSuccess) {
+        st = hip_status(e, "walk table upload");
+        break;
+      }
+      for (int c : cws) {
+        p->dp.walk[0].cw = p->dp.walk[1].cw = c;
+        const double ms = time_ms(run, 5);
+        if (ms < 0) {
+          st = fail(PX_EHIP, "autotune run failed");
+          break;
+        }
+        if (T == T0 && E == E0 && c == 0) ms_default = ms;
+        if (ms < best.ms) best = TuneResult{T, E, c, ms};
+      }
+      if (st != PX_OK) break;
+    }
+    if (st != PX_OK) break;
+  }
+  (void)hipFree(f);
+  (void)hipFree(g);
+  if (st != PX_OK) return st;
+  if ((st = apply(best)) != PX_OK) return st;
+  tune_store(key, best);
+  if (rep) *rep = px_tune_report{best.T, best.emax, best.cw, best.ms, ms_default, 0};
+  return PX_OK;
 }
 
 // ------------------------------------------------------------------- batches
@@ -894,6 +1059,55 @@ static px_status batch_zeta(px_batch* b, bool up, int dtype, const void* f, int6
   hipError_t e = run_scan(b->dp, up ? -1 : 1, T, f, ldf, T, w + L.y, B, w + L.aux, nt, s);
   if (e == hipSuccess) e = run_gather(b->dp, up, T, w + L.y, B, T, g, ldg, T, nullptr, 0, w + L.snaps, s);
   return hip_status(e, "batched zeta launch");
+}
+
+px_status px_batch_autotune(px_batch* b, int dtype, int64_t B, px_tune_report* rep) {
+  if (!b) return fail(PX_EINVAL, "null batch");
+  if (dtype != PX_I64 && dtype != PX_F32 && dtype != PX_F64) return fail(PX_EINVAL, "unknown dtype");
+  if (B < 1) return fail(PX_EINVAL, "B must be >= 1");
+  if (rep) *rep = px_tune_report{0, 0, b->dp.walk[0].cw, 0.0, 0.0, 0};
+  DeviceGuard dg(b->device);
+  if (!dg.ok) return fail(PX_EHIP, "hipSetDevice failed");
+  std::lock_guard<std::mutex> lk(tune_mu);
+  tune_load();
+  const std::string key = "batch:" + std::to_string(b->count) + ":" + std::to_string(b->rows) + ":" +
+                          std::to_string(b->nsnap[0]) + ":" + std::to_string(B) + ":" + std::to_string(dtype);
+  auto it = tune_cache.find(key);
+  if (it != tune_cache.end()) {
+    b->dp.walk[0].cw = b->dp.walk[1].cw = it->second.cw;
+    if (rep) *rep = px_tune_report{0, 0, it->second.cw, it->second.ms, 0.0, 1};
+    return PX_OK;
+  }
+  const size_t bytes = (size_t)b->rows * B * elem_size(dtype);
+  void *f = nullptr, *g = nullptr;
+  if (hipMalloc(&f, bytes) != hipSuccess || hipMalloc(&g, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    if (f) (void)hipFree(f);
+    return fail(PX_ENOMEM, "autotune buffers");
+  }
+  (void)hipMemset(f, 0, bytes);
+  auto run = [&]() { return batch_zeta(b, false, dtype, f, B, g, B, B, nullptr) == PX_OK; };
+  TuneResult best;
+  best.ms = 1e30;
+  double ms_default = -1;
+  const int dcw = px::col_width(B);
+  for (int c = dcw; c <= 64; c *= 2) {
+    b->dp.walk[0].cw = b->dp.walk[1].cw = (c == dcw ? 0 : c);
+    const double ms = time_ms(run, 5);
+    if (ms < 0) {
+      (void)hipFree(f);
+      (void)hipFree(g);
+      return fail(PX_EHIP, "autotune run failed");
+    }
+    if (c == dcw) ms_default = ms;
+    if (ms < best.ms) best = TuneResult{0, 0, c == dcw ? 0 : c, ms};
+  }
+  (void)hipFree(f);
+  (void)hipFree(g);
+  b->dp.walk[0].cw = b->dp.walk[1].cw = best.cw;
+  tune_store(key, best);
+  if (rep) *rep = px_tune_report{0, 0, best.cw, best.ms, ms_default, 0};
+  return PX_OK;
 }
 
 px_status px_zeta_batched(px_batch* b, int dtype, const void* f, int64_t ldf, void* g, int64_t ldg, int64_t B,

@@ -27,6 +27,7 @@ struct WalkTables {
   const int32_t* snap_off = nullptr;
   const int32_t* snap_of_row = nullptr;
   int32_t nruns = 0, nsnap = 0;
+  int32_t cw = 0;  // column tile of the lane-split form (0: the smallest power of two >= B)
 };
 
 // Static description of one poset (or a batch of posets) on the device.

@@ -544,7 +544,8 @@ hipError_t walk_typed(const DevPoset& d, const int32_t* nv, const WalkTables& w,
                       int64_t ldo, ElemType tres, const void* resid, int64_t ldr, void* snaps, LaunchHook* hook,
                       hipStream_t s) {
   const bool uniform = !d.poset_of_row && d.k <= 64 && B >= 32;
-  const int cw = col_width(B);
+  int cw = col_width(B);
+  if (w.cw > cw && w.cw <= 64 && (w.cw & (w.cw - 1)) == 0) cw = w.cw;
   if (hook) hook->before(0, s);
   if (uniform) {
     const int64_t waves = (int64_t)w.nruns * ((B + 63) / 64);

@@ -103,6 +103,15 @@ class Poset:
         code = {torch.int64: 0, torch.float32: 1, torch.float64: 2}[dtype]
         _lib.check(_lib.lib().px_reserve(self.handle, code, int(B)), "px_reserve")
 
+    def autotune(self, dtype, B: int) -> dict:
+        """Pick the gather tile shapes for this poset and B by timing them (px_autotune)."""
+        import torch
+        code = {torch.int64: 0, torch.float32: 1, torch.float64: 2}[dtype]
+        rep = _lib.TuneReport()
+        _lib.check(_lib.lib().px_autotune(self.handle, code, int(B), ctypes.byref(rep)), "px_autotune")
+        self.info = self.info_dict()
+        return rep.as_dict()
+
 
 def poset_build(n, indptr, indices, chain_of=None, chain_pos=None, flags: int = 0, device: int = 0) -> Poset:
     """Preprocess a DAG given as CSR child lists (px_poset_build)."""
@@ -211,6 +220,15 @@ class Batch:
         import torch
         code = {torch.int64: 0, torch.float32: 1, torch.float64: 2}[dtype]
         _lib.check(_lib.lib().px_batch_reserve(self.handle, code, int(B)), "px_batch_reserve")
+
+    def autotune(self, dtype, B: int) -> dict:
+        """Pick the RHS tile of the batched gather by timing the candidates (px_batch_autotune)."""
+        import torch
+        code = {torch.int64: 0, torch.float32: 1, torch.float64: 2}[dtype]
+        rep = _lib.TuneReport()
+        _lib.check(_lib.lib().px_batch_autotune(self.handle, code, int(B), ctypes.byref(rep)),
+                   "px_batch_autotune")
+        return rep.as_dict()
 
 
 def batch_build(posets) -> Batch:

@@ -355,3 +355,32 @@ def test_argument_errors_and_nonfinite(px, cfg0):
         px.mobius(Pc, g, max_refine=2, tol=1e-6)
     assert e.value.name == "PX_ENONFINITE"
     torch.cuda.synchronize()
+
+
+# --------------------------------------------------------------- autotuner
+def test_autotune_keeps_results_exact(px, cfg0):
+    p, R = cfg0
+    f = W.functions(p.n, 64, "int", seed=50, lo=-100, hi=100)
+    want = O.zeta(R, f)
+    for B in (64, 16):
+        P = build(px, p)
+        rep = P.autotune(__import__("torch").int64, B)
+        assert rep["walk_T"] in (64, 128, 256) and rep["walk_emax"] in (48, 96, 192)
+        assert rep["ms_best"] > 0
+        assert P.info["walk_T"] == rep["walk_T"]
+        fb = f[:, :B]
+        assert np.array_equal(H(px.zeta(P, T(fb))), want[:, :B])
+        assert np.array_equal(H(px.mobius(P, px.zeta(P, T(fb)))), fb)
+        assert np.array_equal(H(px.zeta_adjoint(P, T(fb))), O.zeta_adjoint(R, fb))
+        again = build(px, p).autotune(__import__("torch").int64, B)
+        assert again["from_cache"] == 1 and again["walk_T"] == rep["walk_T"]
+    posets = W.batched_posets(6, seed=51, nmin=100, nmax=800)
+    b = px.batch_build([build(px, q) for q in posets])
+    rb = b.autotune(__import__("torch").int64, 8)
+    assert rb["rhs_tile"] in (0, 16, 32, 64)
+    fx = W.functions(b.rows, 8, "int", seed=52, lo=-100, hi=100)
+    g = H(px.zeta_batched(b, T(fx)))
+    for i, q in enumerate(posets):
+        s, e = b.offsets[i], b.offsets[i + 1]
+        Rq = O.reachability(q.n, q.indptr, q.indices)
+        assert np.array_equal(g[s:e], O.zeta(Rq, fx[s:e]))
