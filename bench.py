@@ -61,10 +61,12 @@ def algorithmic_bytes(phase: str, n: int, k: int, B: int, s: int, info: dict) ->
         return n * B * s + n * 4 + n * B * s
     if phase == "scan_reduce":   # read f, read node_of_row
         return n * B * s + n * 4
+    if phase == "scan_onepass":  # read f, read node_of_row, write P
+        return n * B * s + n * 4 + n * B * s
     return 0
 
 
-def profile_read(lib, nph=9):
+def profile_read(lib, nph=10):
     import ctypes
     ms = (ctypes.c_double * nph)()
     cnt = (ctypes.c_int64 * nph)()
@@ -297,7 +299,8 @@ def main():
     ms_step = dt * 1e3 / args.steps
     value = p.n * B / (dt / args.steps)
     phases = {}
-    for name in ("scan_reduce", "scan_carry", "scan_apply", "gather", "walk_events", "walk_combine"):
+    for name in ("scan_reduce", "scan_carry", "scan_apply", "scan_onepass", "gather", "walk_events",
+                 "walk_combine"):
         ms, cnt = prof[name]
         if cnt:
             avg = ms / cnt

@@ -184,8 +184,29 @@ void build_walk(const px::Prep& P, const std::vector<int32_t>& nv, HostWalk& W, 
   W.nsnap = m;
 }
 
+// Tile orders of the single-pass scan: for each tile height and direction, the
+// tiles sorted by their position in the scan (from the bottom for prefix scans,
+// from the top for suffix scans), then by chain.
+std::vector<int32_t> scan_orders(const std::vector<int32_t>& segoff, int64_t nchains, const int64_t ntiles[7]) {
+  std::vector<int32_t> out;
+  for (int dir = 0; dir < 2; ++dir)
+    for (int i = 0; i < 7; ++i) {
+      const int32_t* so = &segoff[i * (nchains + 1)];
+      std::vector<std::pair<int64_t, int32_t>> key;
+      key.reserve(ntiles[i]);
+      for (int64_t c = 0; c < nchains; ++c)
+        for (int32_t t = so[c]; t < so[c + 1]; ++t) {
+          const int32_t q = t - so[c], nq = so[c + 1] - so[c];
+          key.push_back({(int64_t)(dir == 0 ? q : nq - 1 - q) * nchains + c, t});
+        }
+      std::sort(key.begin(), key.end());
+      for (auto& kv : key) out.push_back(kv.second);
+    }
+  return out;
+}
+
 struct Layout {
-  size_t y = 0, p64 = 0, r64 = 0, aux = 0, stats = 0, snaps = 0, total = 0;
+  size_t y = 0, p64 = 0, r64 = 0, aux = 0, stats = 0, snaps = 0, sync = 0, total = 0;
 };
 
 // Workspace layout of one call: a [n, B] matrix of the working type (P or Y),
@@ -208,6 +229,8 @@ Layout layout(int64_t n, int64_t B, int dtype, bool refine, int64_t ntiles, int6
   o = align256(o + (size_t)(2 * B + 1) * 8);
   L.snaps = o;
   o = align256(o + (size_t)nsnap * B * (refine ? 8 : elem_size(dtype)));
+  L.sync = o;
+  o = align256(o + (size_t)(2 + ntiles * ((B + px::col_width(B) - 1) / px::col_width(B))) * 4);
   L.total = o;
   return L;
 }
@@ -221,9 +244,10 @@ px_status hip_status(hipError_t e, const char* what) {
 // (px_profile / px_profile_read).  Off by default: then it costs one branch.
 namespace prof {
 enum Phase { SCAN_REDUCE = 0, SCAN_CARRY, SCAN_APPLY, GATHER, USOLVE, CHAIN_DIFF, ABSMAX, WALK_EVENTS, WALK_COMBINE,
-             NPH };
-const char* const kNames[NPH] = {"scan_reduce", "scan_carry", "scan_apply", "gather", "usolve_level",
-                                 "chain_diff",  "absmax",     "walk_events", "walk_combine"};
+             SCAN_ONEPASS, NPH };
+const char* const kNames[NPH] = {"scan_reduce", "scan_carry",   "scan_apply",  "gather",
+                                 "usolve_level", "chain_diff",  "absmax",      "walk_events",
+                                 "walk_combine", "scan_onepass"};
 std::mutex mu;
 std::atomic<bool> on{false};
 struct Rec {
@@ -274,8 +298,29 @@ struct WalkHook : px::LaunchHook {
 };
 }  // namespace prof
 
+// Polls per look-back wait of the single-pass scan (about 30 ms by default;
+// POSETX_LB_SPIN overrides it, e.g. 0 to exercise the direct-sum fallback).
+int lb_spin_limit() {
+  const char* v = std::getenv("POSETX_LB_SPIN");
+  if (v && *v) return (int)std::min<long>(std::max<long>(std::strtol(v, nullptr, 10), 0), 1 << 30);
+  return 1 << 16;
+}
+
+// The reduce / carry / apply scan is the default: at n = 2^20, k = 64, B = 64
+// it takes 0.18 ms against 0.27 ms for the single-pass scan, whose tiles wait
+// on their predecessors' flags.  POSETX_SCAN=onepass selects the single-pass
+// scan (read on every call).
+bool use_onepass() {
+  const char* v = std::getenv("POSETX_SCAN");
+  return v && std::strcmp(v, "onepass") == 0;
+}
+
 hipError_t run_scan(const px::DevPoset& d, int dir, px::ElemType tin, const void* x, int64_t ldx, px::ElemType tout,
-                    void* P, int64_t B, void* aux, int64_t nt, hipStream_t s) {
+                    void* P, int64_t B, void* aux, int64_t nt, int* sync, hipStream_t s) {
+  if (sync && use_onepass() && d.scan_order[dir > 0 ? 0 : 1][px::seg_index(px::col_width(B))]) {
+    prof::Scope sc(prof::SCAN_ONEPASS, s);
+    return px::launch_chain_scan_onepass(d, dir, tin, x, ldx, tout, P, B, aux, nt, sync, lb_spin_limit(), s);
+  }
   hipError_t e;
   {
     prof::Scope sc(prof::SCAN_REDUCE, s);
@@ -316,7 +361,7 @@ struct px_poset {
   int device = 0;
   bool host_only = false, has_up = false, mirsky = false;
   int32_t *d_node_of_row = nullptr, *d_chain_of_row = nullptr, *d_chain_off = nullptr, *d_niv = nullptr,
-          *d_niv_up = nullptr, *d_lev_down = nullptr, *d_lev_up = nullptr, *d_segoff = nullptr,
+          *d_niv_up = nullptr, *d_lev_down = nullptr, *d_lev_up = nullptr, *d_segoff = nullptr, *d_order = nullptr,
           *d_walk[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
   int64_t ntiles[7] = {0, 0, 0, 0, 0, 0, 0};
   int64_t nevents[2] = {0, 0};
@@ -335,7 +380,8 @@ struct px_batch {
   int64_t rows = 0;
   bool has_up = false;
   int32_t *d_node_of_row = nullptr, *d_chain_of_row = nullptr, *d_chain_off = nullptr, *d_niv = nullptr,
-          *d_niv_up = nullptr, *d_segoff = nullptr, *d_poset_of_row = nullptr, *d_k = nullptr, *d_row_off = nullptr;
+          *d_niv_up = nullptr, *d_segoff = nullptr, *d_poset_of_row = nullptr, *d_k = nullptr, *d_row_off = nullptr,
+          *d_order = nullptr;
   int64_t* d_niv_off = nullptr;
   int32_t* d_walk[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
   int32_t nsnap[2] = {0, 0};
@@ -347,8 +393,8 @@ struct px_batch {
 namespace {
 
 void free_poset_device(px_poset* p) {
-  int32_t* bufs[] = {p->d_node_of_row, p->d_chain_of_row, p->d_chain_off, p->d_niv,
-                     p->d_niv_up,      p->d_lev_down,     p->d_lev_up,    p->d_segoff};
+  int32_t* bufs[] = {p->d_node_of_row, p->d_chain_of_row, p->d_chain_off, p->d_niv, p->d_niv_up,
+                     p->d_lev_down,     p->d_lev_up,       p->d_segoff,    p->d_order};
   for (int32_t* b : bufs)
     if (b) (void)hipFree(b);
   for (auto& dir : p->d_walk)
@@ -401,7 +447,7 @@ px_status zeta_impl(px_poset* p, bool up, int dtype, const void* f, int64_t ldf,
   char* w = (char*)p->ws.p;
   hipStream_t s = (hipStream_t)stream;
   const px::ElemType T = etype(dtype);
-  hipError_t e = run_scan(p->dp, up ? -1 : 1, T, f, ldf, T, w + L.y, B, w + L.aux, nt, s);
+  hipError_t e = run_scan(p->dp, up ? -1 : 1, T, f, ldf, T, w + L.y, B, w + L.aux, nt, (int*)(w + L.sync), s);
   if (e == hipSuccess) e = run_gather(p->dp, up, T, w + L.y, B, T, g, ldg, T, nullptr, 0, w + L.snaps, s);
   return hip_status(e, "zeta launch");
 }
@@ -462,7 +508,7 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   };
   // r = g - zeta(f), zeta applied in float64 to the float32 iterate.
   auto residual = [&]() -> hipError_t {
-    hipError_t e2 = run_scan(p->dp, dir, px::E_F32, f, ldf, px::E_F64, w + L.p64, B, w + L.aux, nt, s);
+    hipError_t e2 = run_scan(p->dp, dir, px::E_F32, f, ldf, px::E_F64, w + L.p64, B, w + L.aux, nt, (int*)(w + L.sync), s);
     if (e2 == hipSuccess)
       e2 = run_gather(p->dp, up, px::E_F64, w + L.p64, B, px::E_F64, r64, B, px::E_F32, g, ldg, w + L.snaps, s);
     return e2;
@@ -686,6 +732,16 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
     if (e == hipSuccess) e = upload(&p->d_lev_down, P.lev_down_rows.data(), P.lev_down_rows.size(), b);
     if (e == hipSuccess && p->has_up) e = upload(&p->d_lev_up, P.lev_up_rows.data(), P.lev_up_rows.size(), b);
     if (e == hipSuccess) e = upload(&p->d_segoff, segoff.data(), segoff.size(), b);
+    if (e == hipSuccess) {
+      std::vector<int32_t> ord = scan_orders(segoff, P.k, p->ntiles);
+      e = upload(&p->d_order, ord.data(), ord.size(), b);
+      int64_t o = 0;
+      for (int dir = 0; dir < 2; ++dir)
+        for (int i = 0; i < 7; ++i) {
+          p->dp.scan_order[dir][i] = p->d_order ? p->d_order + o : nullptr;
+          o += p->ntiles[i];
+        }
+    }
     if (e == hipSuccess) e = set_walk(p, kWalkT, kWalkEvents);
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -946,6 +1002,16 @@ px_status px_batch_build(int count, px_poset* const* posets, px_batch** out) {
   if (e == hipSuccess) e = upload(&b->d_niv, niv.data(), niv.size(), bytes);
   if (e == hipSuccess && has_up) e = upload(&b->d_niv_up, niv_up.data(), niv_up.size(), bytes);
   if (e == hipSuccess) e = upload(&b->d_segoff, segoff.data(), segoff.size(), bytes);
+  if (e == hipSuccess) {
+    std::vector<int32_t> ord = scan_orders(segoff, chains, b->ntiles);
+    e = upload(&b->d_order, ord.data(), ord.size(), bytes);
+    int64_t o = 0;
+    for (int dir = 0; dir < 2; ++dir)
+      for (int i = 0; i < 7; ++i) {
+        b->dp.scan_order[dir][i] = b->d_order ? b->d_order + o : nullptr;
+        o += b->ntiles[i];
+      }
+  }
   if (e == hipSuccess) e = upload(&b->d_poset_of_row, poset_of_row.data(), poset_of_row.size(), bytes);
   if (e == hipSuccess) e = upload(&b->d_k, kk.data(), kk.size(), bytes);
   if (e == hipSuccess) e = upload(&b->d_row_off, row_off.data(), row_off.size(), bytes);
@@ -1014,8 +1080,8 @@ px_status px_batch_build(int count, px_poset* const* posets, px_batch** out) {
 px_status px_batch_free(px_batch* b) {
   if (!b) return PX_OK;
   DeviceGuard dg(b->device);
-  int32_t* bufs[] = {b->d_node_of_row, b->d_chain_of_row, b->d_chain_off, b->d_niv,  b->d_niv_up,
-                     b->d_segoff,      b->d_poset_of_row,  b->d_k,         b->d_row_off};
+  int32_t* bufs[] = {b->d_node_of_row, b->d_chain_of_row, b->d_chain_off, b->d_niv,     b->d_niv_up,
+                     b->d_segoff,      b->d_poset_of_row,  b->d_k,         b->d_row_off, b->d_order};
   for (int32_t* q : bufs)
     if (q) (void)hipFree(q);
   if (b->d_niv_off) (void)hipFree(b->d_niv_off);
@@ -1056,7 +1122,7 @@ static px_status batch_zeta(px_batch* b, bool up, int dtype, const void* f, int6
   char* w = (char*)b->ws.p;
   hipStream_t s = (hipStream_t)stream;
   const px::ElemType T = etype(dtype);
-  hipError_t e = run_scan(b->dp, up ? -1 : 1, T, f, ldf, T, w + L.y, B, w + L.aux, nt, s);
+  hipError_t e = run_scan(b->dp, up ? -1 : 1, T, f, ldf, T, w + L.y, B, w + L.aux, nt, (int*)(w + L.sync), s);
   if (e == hipSuccess) e = run_gather(b->dp, up, T, w + L.y, B, T, g, ldg, T, nullptr, 0, w + L.snaps, s);
   return hip_status(e, "batched zeta launch");
 }

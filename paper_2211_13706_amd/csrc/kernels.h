@@ -42,6 +42,9 @@ struct DevPoset {
   const int32_t* segoff = nullptr;      // [7][nchains+1] tile offsets per tile height
   // tables of the walking gather, [0] for niv (zeta), [1] for the up-niv map
   WalkTables walk[2];
+  // single-pass scan: tiles in scan-position-major order, [0] prefix / [1] suffix,
+  // one table per tile height (as segoff)
+  const int32_t* scan_order[2][7] = {{nullptr}};
   // batch only
   const int64_t* niv_off = nullptr;     // element offset of each poset's niv block
   const int32_t* poset_of_row = nullptr;
@@ -65,6 +68,14 @@ int seg_rows(int cw);      // rows of one scan tile
 hipError_t launch_chain_scan_phase(int phase, const DevPoset& d, int dir, ElemType tin, const void* x,
                                    int64_t ldx, ElemType tout, void* P, int64_t B, void* aux,
                                    int64_t ntiles, hipStream_t s);
+
+// The same scan in one pass with a deterministic look-back between tiles.
+// sync: 2 + ntiles * ceil(B / cw) int words of scratch (cleared by the launch).
+// spin_limit bounds each wait for an earlier tile (polls); a tile that gives up
+// sums the missing tiles from the input instead.
+hipError_t launch_chain_scan_onepass(const DevPoset& d, int dir, ElemType tin, const void* x, int64_t ldx,
+                                     ElemType tout, void* P, int64_t B, void* aux, int64_t ntiles, int* sync,
+                                     int spin_limit, hipStream_t s);
 
 // Gather-reduce U c: out[node(r)] = Σ_j P[nv[r][j]] over finite entries.  With
 // resid != nullptr (float64 P only): out = resid[node] - Σ (residual of a

@@ -281,6 +281,286 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
   }
 }
 
+// Single-pass chain scan with a deterministic multi-level look-back.
+//
+// Workgroups take tiles (and column blocks) in scan-position-major order of
+// their index, so a tile only waits for tiles of its chain held by workgroups
+// of lower index.  Workgroups are dispatched in index order on each XCD, so
+// the lowest unfinished workgroup is always resident and never waits for a
+// later one: every wait ends.  (A single claim counter would serialise all
+// workgroups on one device-scope atomic, about 20 ns each.)  Positions
+// along a chain are read as base-16 numbers; the level-m group of a position is
+// the run of 16^m positions sharing its digits above m.  Each tile publishes
+// exactly one state: the total of the largest group it closes (its own total
+// when its lowest digit is below 15; the total of its 16-tile group when it is
+// the group's last tile, and so on up).  The carry of the tile at position p is
+// the fold, in a fixed order, of the totals of the complete groups before it:
+// at every level m, the d_m(p) earlier sibling groups (d_m = digit m of p).
+// All waits of a tile are issued together, one lane per awaited flag, and the
+// dependency depth is the number of levels, so no serial chain of waits runs
+// along the scan.  The fold order depends on p alone, so results are
+// bit-reproducible from run to run.
+//
+// Publication: states are stored with relaxed device-scope atomics, which are
+// coherent across the per-XCD L2s without cache maintenance, and the publishing
+// wave waits until those stores have completed (vmcnt 0) before it stores the
+// flag.  A release fence would write back the whole L2, holding the tile
+// outputs, once per tile; with no wait at all the flag may overtake the last
+// quarter-wave line of the state.  Readers load states with relaxed
+// device-scope atomics after their flag loads have returned.
+//
+// Waits are bounded (spin_limit polls).  A tile that gives up sums the missing
+// groups straight from the input rows instead (slower, still correct, no longer
+// bit-reproducible) and sets the error word so that other waits give up early.
+constexpr int LB_LG = 4;
+constexpr int LB_G = 1 << LB_LG;
+constexpr int LB_LEVELS = 8;  // chain positions < 2^31
+
+// Tile states travel as relaxed device-scope atomics, which are coherent
+// across the per-XCD L2s without a cache write-back or invalidate.  A release
+// fence would write back the whole L2 (the tile outputs are in it) once per
+// tile; instead the publishing wave waits until its own state stores have
+// completed (vmcnt reaches zero) before it stores the flag.  Without that wait
+// the flag store may overtake the last quarter-wave line of the state.  The
+// reader's loads are issued after its flag load has returned the flag.
+template <typename St>
+__device__ inline void st_put(St* p, const St& v) {
+  static_assert(sizeof(St) % 8 == 0, "tile state is whole 64-bit words");
+  uint64_t w[sizeof(St) / 8];
+  __builtin_memcpy(w, &v, sizeof(St));
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(St) / 8); ++i)
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p) + i, w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename St>
+__device__ inline St st_get(const St* p) {
+  uint64_t w[sizeof(St) / 8];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(St) / 8); ++i)
+    w[i] = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p) + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  St v;
+  __builtin_memcpy(&v, w, sizeof(St));
+  return v;
+}
+
+// This wave's earlier vector-memory operations have completed; also a compiler
+// barrier, so no memory access moves across it.
+__device__ inline void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+template <typename Tin, typename Tout, int CWT>
+__global__ __launch_bounds__(WG) void k_scan_onepass(DevPoset d, int segi, int cw_rt, int dir,
+                                                     const Tin* __restrict__ x, int64_t ldx, int64_t B,
+                                                     int64_t ntiles, const int32_t* __restrict__ order,
+                                                     typename ScanTraits<Tin, Tout>::St* __restrict__ Val,
+                                                     int* __restrict__ flags, int* __restrict__ err,
+                                                     int spin_limit, Tout* __restrict__ P) {
+  using Tr = ScanTraits<Tin, Tout>;
+  using St = typename Tr::St;
+  using Tv = decltype(Tr::in(Tin()));
+  const int cw = CWT ? CWT : cw_rt;
+  __shared__ St sm[WG];
+  __shared__ St carry_sh[64];
+  const int64_t ncb = (B + cw - 1) / cw;
+  const int64_t item = blockIdx.x;
+  if (item >= ntiles * ncb) return;
+  const int64_t cb = item % ncb;
+  const int t = order[item / ncb];
+  const int32_t* so = d.segoff + (int64_t)segi * (d.nchains + 1);
+  const int c = find_chain(so, d.nchains, t);
+  const int RG = WG / cw;
+  const int seg = RG * RPT;
+  const int q = t - so[c];
+  const int nq = so[c + 1] - so[c];
+  const int pos = dir > 0 ? q : nq - 1 - q;
+  const int64_t base = d.chain_off[c] + (int64_t)q * seg;
+  const int64_t end = d.chain_off[c + 1];
+  const int lane = threadIdx.x % cw, rg = threadIdx.x / cw;
+  const int64_t col = cb * cw + lane;
+  const int64_t colc = col < B ? col : 0;
+  const int64_t r0 = base + (int64_t)rg * RPT;
+
+  // load the tile and scan each thread's rows
+  int32_t nodes[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    nodes[i] = d.node_of_row[min(r0 + i, end - 1)];
+    if (CWT == 64) nodes[i] = __builtin_amdgcn_readfirstlane(nodes[i]);
+  }
+  Tin raw[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) raw[i] = x[(int64_t)nodes[i] * ldx + colc];
+  Tv v[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) v[i] = (r0 + i < end) ? Tr::in(raw[i]) : Tv(0);
+  St loc;
+  loc.zero();
+  if (dir > 0) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) loc.add(v[i]);
+  } else {
+#pragma unroll
+    for (int i = RPT - 1; i >= 0; --i) loc.add(v[i]);
+  }
+  sm[threadIdx.x] = loc;
+  __syncthreads();
+
+  // wave 0 handles the look-back; its lanes with rg == 0 hold one column each
+  if (threadIdx.x < 64) {
+    const int wl = threadIdx.x;
+    const bool own = rg == 0 && col < B;
+    St tot;
+    tot.zero();
+    if (rg == 0) {
+      if (dir > 0)
+        for (int g = 0; g < RG; ++g) tot.combine(sm[g * cw + lane]);
+      else
+        for (int g = RG - 1; g >= 0; --g) tot.combine(sm[g * cw + lane]);
+    }
+    auto tile_at = [&](int64_t pp) { return dir > 0 ? so[c] + (int)pp : so[c + 1] - 1 - (int)pp; };
+    auto digit = [&](int m) { return (int)(((int64_t)pos >> (LB_LG * m)) & (LB_G - 1)); };
+    // sum of the tiles at positions [p0, p1), read from the input (fallback)
+    auto direct = [&](int64_t p0, int64_t p1) {
+      St acc;
+      acc.zero();
+      for (int64_t pp = p0; pp < p1; ++pp) {
+        const int64_t rb = d.chain_off[c] + (int64_t)(tile_at(pp) - so[c]) * seg;
+        const int64_t re = min(rb + seg, end);
+        if (dir > 0)
+          for (int64_t r = rb; r < re; ++r) acc.add(Tr::in(x[(int64_t)d.node_of_row[r] * ldx + colc]));
+        else
+          for (int64_t r = re - 1; r >= rb; --r) acc.add(Tr::in(x[(int64_t)d.node_of_row[r] * ldx + colc]));
+      }
+      return acc;
+    };
+    int lam = 0;  // number of trailing 15 digits: this tile closes its level-lam group
+    while (lam < LB_LEVELS && digit(lam) == LB_G - 1) ++lam;
+    const bool publish = pos != nq - 1;  // nobody reads the last tile of a chain
+    const int64_t me = (int64_t)t * ncb + cb;
+    auto put = [&](const St& v) {
+      if (own) st_put(&Val[(int64_t)t * B + col], v);
+      wait_vmem();
+      if (wl == 0) __hip_atomic_store(&flags[me], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    if (lam == 0 && publish) put(tot);
+    // Awaited groups, in fold order: the tail (levels lam-1 .. 0, 15 siblings
+    // each) and then the head (levels LB_LEVELS-1 .. lam, digit(m) each).
+    const int ntail = (LB_G - 1) * lam;
+    int nhead = 0;
+    for (int m = lam; m < LB_LEVELS; ++m) nhead += digit(m);
+    // item j -> position of the last tile of that group, and its level m
+    auto item = [&](int j, int& m) -> int64_t {
+      int i;
+      if (j < ntail) {
+        m = lam - 1 - j / (LB_G - 1);
+        i = j % (LB_G - 1);
+      } else {
+        j -= ntail;
+        for (m = LB_LEVELS - 1; m > lam && j >= digit(m); --m) j -= digit(m);
+        i = j;
+      }
+      const int64_t base = ((int64_t)pos >> (LB_LG * (m + 1))) << (LB_LG * (m + 1));
+      return base + ((int64_t)(i + 1) << (LB_LG * m)) - 1;
+    };
+    // wait for items [j0, j1) (at most 64); returns the mask of items given up on
+    auto await_items = [&](int j0, int j1) -> uint64_t {
+      const int j = j0 + wl;
+      bool ok = j >= j1;
+      const int* fl = flags;
+      if (!ok) {
+        int m;
+        fl = &flags[(int64_t)tile_at(item(j, m)) * ncb + cb];
+      }
+      for (int spin = 0;; ++spin) {
+        if (!ok) ok = __hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= 1;
+        if (__all(ok)) break;
+        bool give_up = spin >= spin_limit;
+        if ((spin & 255) == 255 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) give_up = true;
+        if (__any(give_up)) {
+          if (wl == 0 && spin >= spin_limit) atomicOr(err, 1);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      return __ballot(!ok);
+    };
+    // fold of items [j0, j1) in order; loads go out eight at a time
+    auto fold = [&](int j0, int j1, uint64_t miss) {
+      St acc;
+      acc.zero();
+      for (int j = j0; j < j1; j += 8) {
+        St v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          v[u].zero();
+          const int jj = j + u;
+          if (jj < j1 && !((miss >> (jj - j0)) & 1) && own) {
+            int m;
+            v[u] = st_get(&Val[(int64_t)tile_at(item(jj, m)) * B + col]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int jj = j + u;
+          if (jj >= j1) break;
+          if ((miss >> (jj - j0)) & 1) {
+            int m;
+            const int64_t q = item(jj, m);
+            acc.combine(direct(q + 1 - ((int64_t)1 << (LB_LG * m)), q + 1));
+          } else {
+            acc.combine(v[u]);
+          }
+        }
+      }
+      return acc;
+    };
+    St tail;
+    tail.zero();
+    for (int j0 = 0; j0 < ntail; j0 += 64) {
+      const int j1 = min(ntail, j0 + 64);
+      tail.combine(fold(j0, j1, await_items(j0, j1)));
+    }
+    if (lam > 0 && publish) {
+      St closed = tail;
+      closed.combine(tot);
+      put(closed);
+    }
+    St carry;
+    carry.zero();
+    for (int j0 = ntail; j0 < ntail + nhead; j0 += 64) {
+      const int j1 = min(ntail + nhead, j0 + 64);
+      carry.combine(fold(j0, j1, await_items(j0, j1)));
+    }
+    carry.combine(tail);
+    if (rg == 0) carry_sh[lane] = carry;
+  }
+  __syncthreads();
+  if (col >= B) return;
+  St st = carry_sh[lane];
+  if (dir > 0) {
+    for (int g = 0; g < rg; ++g) st.combine(sm[g * cw + lane]);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      st.add(v[i]);
+      const int64_t r = r0 + i;
+      if (r < end) P[r * B + col] = Tr::out(st.value());
+    }
+  } else {
+    for (int g = RG - 1; g > rg; --g) st.combine(sm[g * cw + lane]);
+#pragma unroll
+    for (int i = RPT - 1; i >= 0; --i) {
+      st.add(v[i]);
+      const int64_t r = r0 + i;
+      if (r < end) P[r * B + col] = Tr::out(st.value());
+    }
+  }
+}
+
+__global__ void k_fill_i32(int* p, int64_t cnt, int v) {
+  const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i < cnt) p[i] = v;
+}
+
 // ------------------------------------------------------------ gather-reduce
 template <typename T> struct Wide;
 template <> struct Wide<int64_t> { using W = uint64_t; };
@@ -734,6 +1014,42 @@ hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int6
 }
 
 }  // namespace
+
+namespace {
+template <typename Tin, typename Tout>
+hipError_t onepass_typed(const DevPoset& d, int dir, const void* x, int64_t ldx, void* P, int64_t B, void* aux,
+                         int64_t ntiles, int* sync, int spin_limit, hipStream_t s) {
+  using St = typename ScanTraits<Tin, Tout>::St;
+  const int cw = col_width(B);
+  const int segi = seg_index(cw);
+  const int64_t ncb = (B + cw - 1) / cw;
+  const int32_t* order = d.scan_order[dir > 0 ? 0 : 1][segi];
+  if (!order) return hipErrorInvalidValue;
+  St* Val = (St*)aux;
+  // sync words: [0] unused, [1] error, [2..] one flag per (tile, column block)
+  const int64_t nsync = 2 + ntiles * ncb;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nsync + WG - 1) / WG)), dim3(WG), 0, s, sync, nsync, 0);
+  const dim3 g((unsigned)(ntiles * ncb));
+  if (cw == 64)
+    hipLaunchKernelGGL((k_scan_onepass<Tin, Tout, 64>), g, dim3(WG), 0, s, d, segi, cw, dir, (const Tin*)x, ldx, B,
+                       ntiles, order, Val, sync + 2, sync + 1, spin_limit, (Tout*)P);
+  else
+    hipLaunchKernelGGL((k_scan_onepass<Tin, Tout, 0>), g, dim3(WG), 0, s, d, segi, cw, dir, (const Tin*)x, ldx, B,
+                       ntiles, order, Val, sync + 2, sync + 1, spin_limit, (Tout*)P);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_chain_scan_onepass(const DevPoset& d, int dir, ElemType tin, const void* x, int64_t ldx,
+                                     ElemType tout, void* P, int64_t B, void* aux, int64_t ntiles, int* sync,
+                                     int spin_limit, hipStream_t s) {
+  if (d.n == 0 || ntiles == 0) return hipSuccess;
+  if (tin == E_I64 && tout == E_I64) return onepass_typed<int64_t, int64_t>(d, dir, x, ldx, P, B, aux, ntiles, sync, spin_limit, s);
+  if (tin == E_F32 && tout == E_F32) return onepass_typed<float, float>(d, dir, x, ldx, P, B, aux, ntiles, sync, spin_limit, s);
+  if (tin == E_F64 && tout == E_F64) return onepass_typed<double, double>(d, dir, x, ldx, P, B, aux, ntiles, sync, spin_limit, s);
+  if (tin == E_F32 && tout == E_F64) return onepass_typed<float, double>(d, dir, x, ldx, P, B, aux, ntiles, sync, spin_limit, s);
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_chain_scan_phase(int phase, const DevPoset& d, int dir, ElemType tin, const void* x, int64_t ldx,
                                    ElemType tout, void* P, int64_t B, void* aux, int64_t ntiles, hipStream_t s) {

@@ -43,6 +43,11 @@ def T(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev())
 
 
+def px_int64():
+    import torch
+    return torch.int64
+
+
 def H(t):
     import torch
     torch.cuda.synchronize()
@@ -259,6 +264,39 @@ def test_grid_config2_f32_refined(px):
     print(f"grid f32 Möbius: plain err {rel(plain, want):.2e}, refined {rel(H(got), want):.2e}, {rep}")
 
 
+# ------------------------------------------------------------ scan schedules
+SCAN_MODES = {"3phase": {}, "onepass": {"POSETX_SCAN": "onepass"},
+              "fallback": {"POSETX_SCAN": "onepass", "POSETX_LB_SPIN": "0"}}
+
+
+@pytest.mark.parametrize("mode", list(SCAN_MODES))
+def test_scan_schedules_grid_exact(px, mode, monkeypatch):
+    """Every chain-scan schedule gives the exact 2-D prefix sums at full size.
+
+    Grid 4096 x 64 with B = 64: one 64-wide column block and chains of 64 tiles,
+    so the single-pass look-back crosses several super-tiles.  "fallback" makes
+    every look-back wait give up at once, so tiles sum their predecessors from
+    the input.  int64 is compared with the closed form; float32 runs on integer
+    data whose chain prefixes stay below 2**24 and whose k-term sums are exact in
+    float64, so it must equal the closed form rounded once to float32.  The
+    adjoint (suffix scan) is the reversed 2-D prefix sum.
+    """
+    for k, v in SCAN_MODES[mode].items():
+        monkeypatch.setenv(k, v)
+    h, w, B = 4096, 64, 64
+    p = W.grid_poset(h, w)
+    P = build(px, p)
+    f = W.functions(p.n, B, "int", seed=40, lo=-1000, hi=1000)
+    f3 = f.reshape(h, w, B)
+    want = f3.cumsum(0).cumsum(1).reshape(p.n, B)
+    want_adj = f3[::-1, ::-1].cumsum(0).cumsum(1)[::-1, ::-1].reshape(p.n, B)
+    assert np.array_equal(H(px.zeta(P, T(f))), want)
+    assert np.array_equal(H(px.zeta_adjoint(P, T(f))), want_adj)
+    f32 = T(f.astype(np.float32))
+    assert np.array_equal(H(px.zeta(P, f32)), want.astype(np.float32))
+    assert np.array_equal(H(px.zeta_adjoint(P, f32)), want_adj.astype(np.float32))
+
+
 # ------------------------------------------------------- full-size, sampled
 @pytest.fixture(scope="module")
 def cfg1():
@@ -276,6 +314,24 @@ def test_config1_f32_zeta_sampled(px, cfg1):
     want = O.zeta_at(p.n, p.indptr, p.indices, f, nodes)
     zabs = O.zeta_at(p.n, p.indptr, p.indices, np.abs(f), nodes)
     check_f32_zeta(g, want, zabs)
+
+
+@pytest.mark.parametrize("mode", list(SCAN_MODES))
+def test_config1_f32_integer_data_exact_roundtrip(px, cfg1, mode, monkeypatch):
+    """float32 zeta at n = 2**20, B = 64 checked at every element.
+
+    Integer data in [-1000, 1000]: each chain prefix is below 16384 * 1000 < 2**24
+    and the k-term sums are exact in float64, so every float32 output is the
+    exact integer result, which the exact int64 Möbius must map back to f.
+    """
+    for k, v in SCAN_MODES[mode].items():
+        monkeypatch.setenv(k, v)
+    p, nodes = cfg1
+    P = build(px, p)
+    f = W.functions(p.n, 64, "int", seed=41, lo=-1000, hi=1000)
+    g32 = px.zeta(P, T(f.astype(np.float32)))
+    assert np.array_equal(H(g32)[nodes], O.zeta_at(p.n, p.indptr, p.indices, f, nodes).astype(np.float32))
+    assert np.array_equal(H(px.mobius(P, g32.to(dtype=px_int64()))), f)
 
 
 def test_config1_int64_zeta_sampled_and_roundtrip(px, cfg1):
