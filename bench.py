@@ -43,16 +43,16 @@ def kernel_hash() -> str:
 
 
 def algorithmic_bytes(phase: str, n: int, k: int, B: int, s: int, info: dict) -> int:
-    """Compulsory bytes of one launch of each kernel (every array touched once).
+    """Compulsory bytes of one launch of each kernel: every array it touches, once.
 
-    walk_events: the change events (8 B), the first niv row of every run (4k B),
-    the P rows the method must gather (one per event and k-1 per run start) and
-    the snapshots it stores; re-reads of a chain's previous P row are not counted.
+    walk_events: the change events (16 B each) and the run table (16 B per run),
+    the niv row of every run's first element (4k B), every P row it reads counted
+    once (walk_rows_distinct) and the snapshots it stores.
     walk_combine: P, the snapshots, node_of_row and snap_of_row, and g.
     """
     runs, ev, snaps = info.get("walk_runs", 0), info.get("walk_events", 0), info.get("walk_snapshots", 0)
     if phase == "walk_events":
-        return ev * 8 + runs * (k * 4 + 16) + (ev + runs * (k - 1)) * B * s + snaps * B * s
+        return ev * 16 + runs * (k * 4 + 16) + info.get("walk_rows_distinct", 0) * B * s + snaps * B * s
     if phase == "walk_combine":
         return n * B * s + snaps * B * s + 8 * n + n * B * s
     if phase == "gather":        # one thread per row: read P, niv, node_of_row, write g
@@ -64,6 +64,15 @@ def algorithmic_bytes(phase: str, n: int, k: int, B: int, s: int, info: dict) ->
     if phase == "scan_onepass":  # read f, read node_of_row, write P
         return n * B * s + n * 4 + n * B * s
     return 0
+
+
+def gathered_bytes(phase: str, k: int, B: int, s: int, info: dict) -> int:
+    """Bytes a kernel moves through the memory hierarchy, re-reads included: for
+    walk_events every P-row load (first rows' gathers, both rows of each event)."""
+    if phase != "walk_events":
+        return 0
+    runs, ev, snaps = info.get("walk_runs", 0), info.get("walk_events", 0), info.get("walk_snapshots", 0)
+    return ev * 16 + runs * (k * 4 + 16) + info.get("walk_row_loads", 0) * B * s + snaps * B * s
 
 
 def profile_read(lib, nph=10):
@@ -307,6 +316,10 @@ def main():
             byt = algorithmic_bytes(name, p.n, P.k, B, 4, P.info)
             phases[name] = {"avg_ms": round(avg, 4), "launches": cnt, "alg_bytes": byt,
                             "GBps": round(byt / (avg * 1e-3) / 1e9, 1) if byt else None}
+            gb = gathered_bytes(name, P.k, B, 4, P.info)
+            if gb:
+                phases[name]["gathered_bytes"] = gb
+                phases[name]["gathered_GBps"] = round(gb / (avg * 1e-3) / 1e9, 1)
     dom = max((k for k in phases if phases[k]["alg_bytes"]), key=lambda k: phases[k]["avg_ms"])
     ach = phases[dom]["GBps"]
     tr = traffic_for(dom)
@@ -330,13 +343,16 @@ def main():
                    "n": p.n, "k": P.k, "B": B, "edges": p.nedges},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr,
-                     "alg_bytes_per_launch": phases[dom]["alg_bytes"]},
+                     "alg_bytes_per_launch": phases[dom]["alg_bytes"],
+                     "gathered_GBps": phases[dom].get("gathered_GBps"),
+                     "traffic_GBps": round(tr / (phases[dom]["avg_ms"] * 1e-3) / 1e9, 1) if tr else None},
         "step_roofline": {"alg_bytes": step_bytes, "GBps": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
                           "frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "phases": phases,
         "preprocess_s": {"total": round(t_prep, 3), **{k: round(v, 3) for k, v in P.info.items()
                                                       if k.startswith("t_")}},
-        "walk": {k: P.info[k] for k in ("walk_runs", "walk_events", "walk_snapshots", "walk_T", "walk_emax")},
+        "walk": {k: P.info[k] for k in ("walk_runs", "walk_events", "walk_snapshots", "walk_T", "walk_emax",
+                                        "walk_rows_distinct", "walk_row_loads")},
         "autotune": {**tune, "seconds": round(t_tune, 2)},
         "generate_s": round(t_gen, 3),
         "kernel_hash": kernel_hash(),

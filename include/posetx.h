@@ -87,6 +87,9 @@ typedef struct {
   int64_t walk_snapshots; /* running-sum snapshots those runs store                     */
   int64_t walk_T;         /* their run length and event cap (see px_autotune)            */
   int64_t walk_emax;
+  int64_t walk_rows_distinct; /* distinct P rows those runs read (each counted once)     */
+  int64_t walk_row_loads;     /* P-row loads they issue (first rows' gathers, both rows
+                                 of every event)                                        */
   int32_t chains_planted; /* 1 if the caller supplied the chains                        */
   int32_t device;
   double t_validate, t_chains, t_niv, t_levels, t_upload;  /* preprocessing seconds      */

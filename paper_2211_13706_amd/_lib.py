@@ -40,7 +40,7 @@ class Info(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n", "k", "edges", "nnz_niv", "nnz_niv_up", "max_chain", "levels_down", "levels_up",
         "mirsky_levels", "udep_levels", "device_bytes", "walk_runs", "walk_events", "walk_snapshots", "walk_T",
-        "walk_emax")] + [
+        "walk_emax", "walk_rows_distinct", "walk_row_loads")] + [
         ("chains_planted", ctypes.c_int32), ("device", ctypes.c_int32)] + [
         (name, ctypes.c_double) for name in ("t_validate", "t_chains", "t_niv", "t_levels", "t_upload")]
 

@@ -117,6 +117,7 @@ struct HostWalk {
   std::vector<int32_t> ev;    // quadruples (new row, old row, (u << 8) | chain, 0), -1 = none
   std::vector<int32_t> ev_off, snap_off, snap_of_row;
   int32_t nsnap = 0;
+  int64_t rows_distinct = 0, row_loads = 0;  // P rows the event kernel reads: distinct, and loads
 };
 
 void build_walk(const px::Prep& P, const std::vector<int32_t>& nv, HostWalk& W, int T, int emax) {
@@ -182,6 +183,26 @@ void build_walk(const px::Prep& P, const std::vector<int32_t>& nv, HostWalk& W, 
   }
   W.snap_off[runs.size()] = m;
   W.nsnap = m;
+  // P rows read by the event kernel: the other-chain entries of every run's
+  // first row, and the new and old rows of every event
+  std::vector<char> seen(n, 0);
+  W.row_loads = 0;
+  auto touch = [&](int32_t t) {
+    if (t < 0) return;
+    ++W.row_loads;
+    seen[t] = 1;
+  };
+  for (size_t s = 0; s < runs.size(); ++s) {
+    const int32_t r0 = runs[s].r0;
+    for (int64_t j = 0; j < k; ++j)
+      if (j != runs[s].c) touch(nv[(size_t)r0 * k + j]);
+  }
+  for (size_t e = 0; e < W.ev.size(); e += 4) {
+    touch(W.ev[e]);
+    touch(W.ev[e + 1]);
+  }
+  W.rows_distinct = 0;
+  for (char c : seen) W.rows_distinct += c;
 }
 
 // Tile orders of the single-pass scan: for each tile height and direction, the
@@ -368,6 +389,7 @@ struct px_poset {
   int32_t nsnap[2] = {0, 0};
   std::vector<int32_t> hw_runs[2], hw_ev[2], hw_ev_off[2], hw_snap_off[2], hw_snap_of_row[2];
   int32_t walk_T = 0, walk_emax = 0;
+  int64_t walk_rows[2][2] = {{0, 0}, {0, 0}};  // per map: distinct P rows read, P-row loads
   px::DevPoset dp;
   Workspace ws;
   int64_t device_bytes = 0;
@@ -580,6 +602,8 @@ hipError_t set_walk(px_poset* p, int T, int emax) {
     if (e == hipSuccess) e = upload(&db[4], W.snap_of_row.data(), W.snap_of_row.size(), b);
     if (e != hipSuccess) break;
     p->nevents[dir] = (int64_t)W.ev.size() / 4;
+    p->walk_rows[dir][0] = W.rows_distinct;
+    p->walk_rows[dir][1] = W.row_loads;
     p->nsnap[dir] = W.nsnap;
     t.nruns = (int32_t)(W.runs.size() / 2);
     t.nsnap = W.nsnap;
@@ -795,6 +819,8 @@ px_status px_poset_info(const px_poset* p, px_info* o) {
   o->walk_snapshots = p->nsnap[0];
   o->walk_T = p->walk_T;
   o->walk_emax = p->walk_emax;
+  o->walk_rows_distinct = p->walk_rows[0][0];
+  o->walk_row_loads = p->walk_rows[0][1];
   o->chains_planted = P.planted ? 1 : 0;
   o->device = p->device;
   o->t_validate = P.t_validate;

@@ -118,7 +118,9 @@ __global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw
   __shared__ St sm[NT][WG];
   const int32_t* so = d.segoff + (int64_t)segi * (d.nchains + 1);
   const int seg = (WG / cw) * RPT;
-  const int lane = threadIdx.x % cw, rg = threadIdx.x / cw;
+  // with 64-wide column blocks the row group is the wavefront index: uniform
+  const int lane = threadIdx.x % cw;
+  const int rg = CWT == 64 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64)) : (int)(threadIdx.x / cw);
   const int64_t col = (int64_t)blockIdx.y * cw + lane;
   const int64_t colc = col < B ? col : 0;
   int64_t r0[NT], end[NT];
@@ -233,7 +235,9 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
   const int seg = RG * RPT;
   const int64_t base = d.chain_off[c] + (int64_t)(t - so[c]) * seg;
   const int64_t end = d.chain_off[c + 1];
-  const int lane = threadIdx.x % cw, rg = threadIdx.x / cw;
+  // with 64-wide column blocks the row group is the wavefront index: uniform
+  const int lane = threadIdx.x % cw;
+  const int rg = CWT == 64 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64)) : (int)(threadIdx.x / cw);
   const int64_t col = (int64_t)blockIdx.y * cw + lane;
   const int64_t r0 = base + (int64_t)rg * RPT;
   const int64_t colc = col < B ? col : 0;
@@ -374,7 +378,9 @@ __global__ __launch_bounds__(WG) void k_scan_onepass(DevPoset d, int segi, int c
   const int pos = dir > 0 ? q : nq - 1 - q;
   const int64_t base = d.chain_off[c] + (int64_t)q * seg;
   const int64_t end = d.chain_off[c + 1];
-  const int lane = threadIdx.x % cw, rg = threadIdx.x / cw;
+  // with 64-wide column blocks the row group is the wavefront index: uniform
+  const int lane = threadIdx.x % cw;
+  const int rg = CWT == 64 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64)) : (int)(threadIdx.x / cw);
   const int64_t col = cb * cw + lane;
   const int64_t colc = col < B ? col : 0;
   const int64_t r0 = base + (int64_t)rg * RPT;
@@ -620,40 +626,50 @@ __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* _
                                                     const TP* __restrict__ P, int64_t B, TP* __restrict__ S) {
   using W = typename Wide<TP>::W;
   const int lane = threadIdx.x & 63;
-  const int64_t ncb = (B + 63) >> 6;
-  const int64_t gw = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
-  if (gw >= (int64_t)w.nruns * ncb) return;
-  const int64_t run = gw / ncb;
-  const int64_t col = (gw % ncb) * 64 + lane;
+  const int ncb = (int)((B + 63) >> 6);
+  // Wave-uniform values go through readfirstlane so that they live in scalar
+  // registers: every gather is then one load from a scalar row base at a fixed
+  // per-lane offset, with no per-lane address arithmetic.
+  const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (WG / 64) + (threadIdx.x >> 6)));
+  if ((int64_t)gw >= (int64_t)w.nruns * ncb) return;
+  const int run = gw / ncb;
+  const int col = (gw % ncb) * 64 + lane;
   const bool colok = col < B;
-  const int64_t colc = colok ? col : 0;
-  const int r0 = w.runs[run].x;
+  const int colc = colok ? col : 0;
+  const int r0 = __builtin_amdgcn_readfirstlane(w.runs[run].x);
   const int k = d.k;
+  const int e0 = __builtin_amdgcn_readfirstlane(w.ev_off[run]);
+  const int e1 = __builtin_amdgcn_readfirstlane(w.ev_off[run + 1]);
+  auto prow = [&](int t) { return P + (int64_t)t * B; };
 
+  // the first row's niv entries and the first batch of events load together
   const int cur = lane < k ? nv[(int64_t)r0 * k + lane] : -1;
+  const int4 ev_first = lane < e1 - e0 ? w.ev[e0 + lane] : make_int4(-1, -1, 0, 0);
+  // full gather of the first row, 32 loads in flight (64 cost more in occupancy
+  // than they save)
+  constexpr int PG = 32;
   W acc = W(0);
-  for (int j0 = 0; j0 < k; j0 += 32) {
-    TP v[32];
-    bool ok[32];
+  for (int j0 = 0; j0 < k; j0 += PG) {
+    TP v[PG];
+    bool ok[PG];
 #pragma unroll
-    for (int u = 0; u < 32; ++u) {
+    for (int u = 0; u < PG; ++u) {
       const int j = j0 + u;
       const int t = __builtin_amdgcn_readlane(cur, j & 63);
       ok[u] = j < k && t >= 0 && t != r0;
-      v[u] = P[(int64_t)(ok[u] ? t : r0) * B + colc];
+      v[u] = prow(ok[u] ? t : r0)[colc];
     }
 #pragma unroll
-    for (int u = 0; u < 32; ++u)
+    for (int u = 0; u < PG; ++u)
       if (ok[u]) acc += (W)v[u];
   }
-  int64_t m = w.snap_off[run];
-  const int64_t mlast = w.snap_off[run + 1] - 1;  // never write past the run's own snapshots
-  if (colok) S[m * B + col] = (TP)acc;
+  int m = __builtin_amdgcn_readfirstlane(w.snap_off[run]);
+  const int mlast = __builtin_amdgcn_readfirstlane(w.snap_off[run + 1]) - 1;  // the run's own snapshots only
+  if (colok) (S + (int64_t)m * B)[col] = (TP)acc;
 
-  const int e0 = w.ev_off[run], e1 = w.ev_off[run + 1];
   for (int eb = e0; eb < e1; eb += 64) {
     const int ne = min(64, e1 - eb);
-    const int4 evl = lane < ne ? w.ev[eb + lane] : make_int4(-1, -1, 0, 0);
+    const int4 evl = eb == e0 ? ev_first : (lane < ne ? w.ev[eb + lane] : make_int4(-1, -1, 0, 0));
     for (int g0 = 0; g0 < ne; g0 += 16) {
       TP vn[16], vo[16];
       bool okn[16], oko[16];
@@ -668,13 +684,13 @@ __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* _
         okn[q] = has && nw >= 0;
         oko[q] = has && old >= 0;
         ue[q] = has ? (key >> 8) : -1;
-        vn[q] = P[(int64_t)(okn[q] ? nw : r0) * B + colc];
-        vo[q] = P[(int64_t)(oko[q] ? old : r0) * B + colc];
+        vn[q] = prow(okn[q] ? nw : r0)[colc];
+        vo[q] = prow(oko[q] ? old : r0)[colc];
       }
       // row offset of the event after this group (-1 at the end of the run)
       const int inext = g0 + 16;
       const int unext = inext < ne ? (__builtin_amdgcn_readlane(evl.z, inext) >> 8)
-                                   : (eb + 64 < e1 ? (w.ev[eb + 64].z >> 8) : -1);
+                                   : (eb + 64 < e1 ? (__builtin_amdgcn_readfirstlane(w.ev[eb + 64].z) >> 8) : -1);
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         if (ue[q] >= 0) {
@@ -683,7 +699,7 @@ __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* _
           const int un = q + 1 < 16 ? ue[q + 1] : unext;
           if (un != ue[q]) {  // last event of its row: snapshot
             m = min(m + 1, mlast);
-            if (colok) S[m * B + col] = (TP)acc;
+            if (colok) (S + (int64_t)m * B)[col] = (TP)acc;
           }
         }
       }
@@ -781,40 +797,45 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
   }
 }
 
-template <typename TP, typename Tres, bool RESID>
-__global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* __restrict__ snap_of_row, int cw,
+// UNI: cw == 64, so each wavefront owns whole rows and row quantities are
+// wave-uniform (kept in scalar registers, loads from scalar row bases).
+template <typename TP, typename Tres, bool RESID, bool UNI>
+__global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* __restrict__ snap_of_row, int cw_rt,
                                                      const TP* __restrict__ P, const TP* __restrict__ S, int64_t B,
                                                      TP* __restrict__ out, int64_t ldo, const Tres* __restrict__ res,
                                                      int64_t ldr) {
   using W = typename Wide<TP>::W;
   constexpr int RPC = COMBINE_ROWS;
+  const int cw = UNI ? 64 : cw_rt;
+  auto uni = [](int v) { return UNI ? __builtin_amdgcn_readfirstlane(v) : v; };
   const int RG = WG / cw;
-  const int64_t rbase = ((int64_t)blockIdx.x * RG + threadIdx.x / cw) * RPC;
-  const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
+  const int rbase = uni((int)((blockIdx.x * RG + threadIdx.x / cw) * RPC));
+  const int col = (int)blockIdx.y * cw + (int)(threadIdx.x % cw);
   if (rbase >= d.n) return;
-  const int64_t colc = col < B ? col : 0;
+  const int colc = col < B ? col : 0;
   int32_t nd[RPC], sm[RPC];
 #pragma unroll
   for (int i = 0; i < RPC; ++i) {
-    const int64_t r = min(rbase + i, (int64_t)d.n - 1);
-    nd[i] = d.node_of_row[r];
-    sm[i] = snap_of_row[r];
+    const int r = min(rbase + i, d.n - 1);
+    nd[i] = uni(d.node_of_row[r]);
+    sm[i] = uni(snap_of_row[r]);
   }
   TP pv[RPC], sv[RPC];
 #pragma unroll
   for (int i = 0; i < RPC; ++i) {
-    const int64_t r = min(rbase + i, (int64_t)d.n - 1);
-    pv[i] = P[r * B + colc];
-    sv[i] = S[(int64_t)sm[i] * B + colc];
+    const int r = min(rbase + i, d.n - 1);
+    pv[i] = (P + (int64_t)r * B)[colc];
+    sv[i] = (S + (int64_t)sm[i] * B)[colc];
   }
   if (col >= B) return;
 #pragma unroll
   for (int i = 0; i < RPC; ++i) {
     if (rbase + i < d.n) {
       if constexpr (RESID)
-        out[(int64_t)nd[i] * ldo + col] = (TP)((double)res[(int64_t)nd[i] * ldr + col] - ((W)pv[i] + (W)sv[i]));
+        (out + (int64_t)nd[i] * ldo)[col] =
+            (TP)((double)(res + (int64_t)nd[i] * ldr)[col] - ((W)pv[i] + (W)sv[i]));
       else
-        out[(int64_t)nd[i] * ldo + col] = (TP)((W)pv[i] + (W)sv[i]);
+        (out + (int64_t)nd[i] * ldo)[col] = (TP)((W)pv[i] + (W)sv[i]);
     }
   }
 }
@@ -841,15 +862,27 @@ hipError_t walk_typed(const DevPoset& d, const int32_t* nv, const WalkTables& w,
   const int ccw = uniform ? 64 : cw;
   const int64_t rows_per_block = (WG / ccw) * COMBINE_ROWS;
   const dim3 gc((unsigned)((d.n + rows_per_block - 1) / rows_per_block), (unsigned)((B + ccw - 1) / ccw));
-  if (resid && tres == E_F32)
-    hipLaunchKernelGGL((k_walk_combine<TP, float, true>), gc, dim3(WG), 0, s, d, w.snap_of_row, ccw, (const TP*)P,
-                       (const TP*)snaps, B, (TP*)out, ldo, (const float*)resid, ldr);
-  else if (resid)
-    hipLaunchKernelGGL((k_walk_combine<TP, double, true>), gc, dim3(WG), 0, s, d, w.snap_of_row, ccw, (const TP*)P,
-                       (const TP*)snaps, B, (TP*)out, ldo, (const double*)resid, ldr);
-  else
-    hipLaunchKernelGGL((k_walk_combine<TP, TP, false>), gc, dim3(WG), 0, s, d, w.snap_of_row, ccw, (const TP*)P,
-                       (const TP*)snaps, B, (TP*)out, ldo, (const TP*)nullptr, 0);
+  if (ccw == 64) {
+    if (resid && tres == E_F32)
+      hipLaunchKernelGGL((k_walk_combine<TP, float, true, true>), gc, dim3(WG), 0, s, d, w.snap_of_row, ccw,
+                         (const TP*)P, (const TP*)snaps, B, (TP*)out, ldo, (const float*)resid, ldr);
+    else if (resid)
+      hipLaunchKernelGGL((k_walk_combine<TP, double, true, true>), gc, dim3(WG), 0, s, d, w.snap_of_row, ccw,
+                         (const TP*)P, (const TP*)snaps, B, (TP*)out, ldo, (const double*)resid, ldr);
+    else
+      hipLaunchKernelGGL((k_walk_combine<TP, TP, false, true>), gc, dim3(WG), 0, s, d, w.snap_of_row, ccw,
+                         (const TP*)P, (const TP*)snaps, B, (TP*)out, ldo, (const TP*)nullptr, 0);
+  } else {
+    if (resid && tres == E_F32)
+      hipLaunchKernelGGL((k_walk_combine<TP, float, true, false>), gc, dim3(WG), 0, s, d, w.snap_of_row, ccw,
+                         (const TP*)P, (const TP*)snaps, B, (TP*)out, ldo, (const float*)resid, ldr);
+    else if (resid)
+      hipLaunchKernelGGL((k_walk_combine<TP, double, true, false>), gc, dim3(WG), 0, s, d, w.snap_of_row, ccw,
+                         (const TP*)P, (const TP*)snaps, B, (TP*)out, ldo, (const double*)resid, ldr);
+    else
+      hipLaunchKernelGGL((k_walk_combine<TP, TP, false, false>), gc, dim3(WG), 0, s, d, w.snap_of_row, ccw,
+                         (const TP*)P, (const TP*)snaps, B, (TP*)out, ldo, (const TP*)nullptr, 0);
+  }
   if (hook) hook->after(1, s);
   return hipGetLastError();
 }
