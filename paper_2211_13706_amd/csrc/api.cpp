@@ -236,11 +236,11 @@ struct Layout {
 Layout layout(int64_t n, int64_t B, int dtype, bool refine, int64_t ntiles, int64_t nsnap = 0) {
   Layout L;
   size_t o = 0;
-  L.y = o;
-  o = align256(o + (size_t)n * B * elem_size(dtype));
+  L.y = o;  // one row more: the scan's zero row
+  o = align256(o + (size_t)(n + 1) * B * elem_size(dtype));
   if (refine) {
     L.p64 = o;
-    o = align256(o + (size_t)n * B * 8);
+    o = align256(o + (size_t)(n + 1) * B * 8);
     L.r64 = o;
     o = align256(o + (size_t)n * B * 8);
   }
@@ -596,7 +596,14 @@ hipError_t set_walk(px_poset* p, int T, int emax) {
     t.cw = keep_cw;
     int64_t b = 0;
     e = upload(&db[0], W.runs.data(), W.runs.size(), b);
-    if (e == hipSuccess) e = upload(&db[1], W.ev.data(), W.ev.size(), b);
+    if (e == hipSuccess) {  // "no element" names the zero row n of P on the device
+      std::vector<int32_t> evd(W.ev);
+      for (size_t x = 0; x < evd.size(); x += 4) {
+        if (evd[x] < 0) evd[x] = (int32_t)P.n;
+        if (evd[x + 1] < 0) evd[x + 1] = (int32_t)P.n;
+      }
+      e = upload(&db[1], evd.data(), evd.size(), b);
+    }
     if (e == hipSuccess) e = upload(&db[2], W.ev_off.data(), W.ev_off.size(), b);
     if (e == hipSuccess) e = upload(&db[3], W.snap_off.data(), W.snap_off.size(), b);
     if (e == hipSuccess) e = upload(&db[4], W.snap_of_row.data(), W.snap_of_row.size(), b);
@@ -1052,9 +1059,9 @@ px_status px_batch_build(int count, px_poset* const* posets, px_batch** out) {
       const int32_t o = row_off[i];
       for (int32_t r : q->hw_runs[dir]) runs.push_back(r + o);
       const std::vector<int32_t>& qe = q->hw_ev[dir];
-      for (size_t x = 0; x < qe.size(); x += 4) {
-        ev.push_back(qe[x] >= 0 ? qe[x] + o : -1);
-        ev.push_back(qe[x + 1] >= 0 ? qe[x + 1] + o : -1);
+      for (size_t x = 0; x < qe.size(); x += 4) {  // "no element": the batch's zero row
+        ev.push_back(qe[x] >= 0 ? qe[x] + o : (int32_t)rows);
+        ev.push_back(qe[x + 1] >= 0 ? qe[x + 1] + o : (int32_t)rows);
         ev.push_back(qe[x + 2]);
         ev.push_back(0);
       }

@@ -20,6 +20,8 @@ enum ElemType { E_I64 = 0, E_F32 = 1, E_F64 = 2 };
 // (-1 = none), sorted by row offset, own chain excluded; it owns snapshots
 // [snap_off[s], snap_off[s+1]) (first row, then every row with events), and
 // snap_of_row[r] is the snapshot that row r adds to its own P[r].
+// Event rows name row n (a zero row of P that the scan keeps zero) for "no
+// element"; P therefore has n + 1 rows.
 struct WalkTables {
   const int2* runs = nullptr;
   const int4* ev = nullptr;
@@ -60,7 +62,8 @@ int seg_rows(int cw);      // rows of one scan tile
 
 // Chain scan V x (forward, dir=+1, prefix from the bottom) or V^T x (dir=-1,
 // suffix from the top), three deterministic phases.  x is node order
-// (ld ldx, element type tin); P is chain-major dense [n, B] of type tout.
+// (ld ldx, element type tin); P is chain-major dense [n + 1, B] of type tout,
+// row n set to zero.
 // Scan state: compensated float for E_F32 -> E_F32, compensated double when
 // tout is E_F64, wrapping uint64 for E_I64.  aux must hold 2 * ntiles * B *
 // 16 bytes.

@@ -174,9 +174,10 @@ __global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw
 // in LDS, each of 16 thread groups combines 8 of them, the group totals are
 // combined in order, and the carries are written; a running carry links the
 // windows.  The combination order is fixed, so results are reproducible.
-template <typename St>
+template <typename St, typename Tout>
 __global__ __launch_bounds__(WG) void k_scan_carry(DevPoset d, int segi, int dir, int64_t B,
-                                                   const St* __restrict__ A, St* __restrict__ C) {
+                                                   const St* __restrict__ A, St* __restrict__ C,
+                                                   Tout* __restrict__ P) {
   constexpr int CB = 16, NS = WG / CB, TPS = 8, WIN = NS * TPS;
   __shared__ St sh[WIN * CB];
   __shared__ St tot[NS * CB];
@@ -184,6 +185,8 @@ __global__ __launch_bounds__(WG) void k_scan_carry(DevPoset d, int segi, int dir
   const int64_t c0 = (int64_t)blockIdx.y * CB;
   const int lc = threadIdx.x % CB, sg = threadIdx.x / CB;
   const int64_t col = c0 + lc;
+  // row n of P stays zero: the walk reads it for "no element"
+  if (c == 0 && sg == 0 && col < B) P[(int64_t)d.n * B + col] = Tout(0);
   const int32_t* so = d.segoff + (int64_t)segi * (d.nchains + 1);
   const int t0 = so[c], t1 = so[c + 1], nt = t1 - t0;
   St carry;
@@ -367,6 +370,9 @@ __global__ __launch_bounds__(WG) void k_scan_onepass(DevPoset d, int segi, int c
   const int64_t ncb = (B + cw - 1) / cw;
   const int64_t item = blockIdx.x;
   if (item >= ntiles * ncb) return;
+  // row n of P stays zero: the walk reads it for "no element"
+  if (item < ncb && threadIdx.x < cw && item * cw + threadIdx.x < B)
+    P[(int64_t)d.n * B + item * cw + threadIdx.x] = Tout(0);
   const int64_t cb = item % ncb;
   const int t = order[item / ncb];
   const int32_t* so = d.segoff + (int64_t)segi * (d.nchains + 1);
@@ -621,15 +627,16 @@ __global__ __launch_bounds__(WG) void k_gather(DevPoset d, const int32_t* __rest
 // Uniform form (k_walk_events, single poset, B >= 32, k <= 64): one wavefront
 // per run, lanes = 64 columns; event fields are read with readlane, so all
 // control flow is scalar.
-template <typename TP>
+template <typename TP, bool OFF32>
 __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* __restrict__ nv, WalkTables w,
                                                     const TP* __restrict__ P, int64_t B, TP* __restrict__ S) {
   using W = typename Wide<TP>::W;
   const int lane = threadIdx.x & 63;
   const int ncb = (int)((B + 63) >> 6);
   // Wave-uniform values go through readfirstlane so that they live in scalar
-  // registers: every gather is then one load from a scalar row base at a fixed
-  // per-lane offset, with no per-lane address arithmetic.
+  // registers: every gather is then one load from a scalar base at a per-lane
+  // offset.  Row n of P is a zero row: the tables name it for "no element",
+  // so that every event adds P[new] - P[old] without a predicate.
   const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (WG / 64) + (threadIdx.x >> 6)));
   if ((int64_t)gw >= (int64_t)w.nruns * ncb) return;
   const int run = gw / ncb;
@@ -638,69 +645,64 @@ __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* _
   const int colc = colok ? col : 0;
   const int r0 = __builtin_amdgcn_readfirstlane(w.runs[run].x);
   const int k = d.k;
+  const int zr = d.n;
   const int e0 = __builtin_amdgcn_readfirstlane(w.ev_off[run]);
   const int e1 = __builtin_amdgcn_readfirstlane(w.ev_off[run + 1]);
-  auto prow = [&](int t) { return P + (int64_t)t * B; };
+  // P[t][col]: with OFF32 (all of P within 2^31 bytes) one scalar 32-bit
+  // multiply per row and a 32-bit lane offset from P's base
+  const uint32_t rowb = (uint32_t)(B * sizeof(TP));
+  const uint32_t lofs = (uint32_t)colc * (uint32_t)sizeof(TP);
+  auto ld = [&](int t) -> TP {
+    if (OFF32) return *(const TP*)((const char*)P + ((uint32_t)t * rowb + lofs));
+    return (P + (int64_t)t * B)[colc];
+  };
 
   // the first row's niv entries and the first batch of events load together
   const int cur = lane < k ? nv[(int64_t)r0 * k + lane] : -1;
-  const int4 ev_first = lane < e1 - e0 ? w.ev[e0 + lane] : make_int4(-1, -1, 0, 0);
+  const int4 ev_first = lane < e1 - e0 ? w.ev[e0 + lane] : make_int4(zr, zr, -1, 0);
   // full gather of the first row, 32 loads in flight (64 cost more in occupancy
-  // than they save)
+  // than they save); missing entries and the own chain read the zero row
   constexpr int PG = 32;
   W acc = W(0);
   for (int j0 = 0; j0 < k; j0 += PG) {
     TP v[PG];
-    bool ok[PG];
 #pragma unroll
     for (int u = 0; u < PG; ++u) {
       const int j = j0 + u;
       const int t = __builtin_amdgcn_readlane(cur, j & 63);
-      ok[u] = j < k && t >= 0 && t != r0;
-      v[u] = prow(ok[u] ? t : r0)[colc];
+      v[u] = ld(j < k && t >= 0 && t != r0 ? t : zr);
     }
 #pragma unroll
-    for (int u = 0; u < PG; ++u)
-      if (ok[u]) acc += (W)v[u];
+    for (int u = 0; u < PG; ++u) acc += (W)v[u];
   }
   int m = __builtin_amdgcn_readfirstlane(w.snap_off[run]);
   const int mlast = __builtin_amdgcn_readfirstlane(w.snap_off[run + 1]) - 1;  // the run's own snapshots only
   if (colok) (S + (int64_t)m * B)[col] = (TP)acc;
 
+  constexpr int EG = 16;  // events per group, both gathers of each in flight
   for (int eb = e0; eb < e1; eb += 64) {
     const int ne = min(64, e1 - eb);
-    const int4 evl = eb == e0 ? ev_first : (lane < ne ? w.ev[eb + lane] : make_int4(-1, -1, 0, 0));
-    for (int g0 = 0; g0 < ne; g0 += 16) {
-      TP vn[16], vo[16];
-      bool okn[16], oko[16];
-      int ue[16];
+    const int4 evl = eb == e0 ? ev_first : (lane < ne ? w.ev[eb + lane] : make_int4(zr, zr, -1, 0));
+    for (int g0 = 0; g0 < ne; g0 += EG) {
+      TP vn[EG], vo[EG];
+      int ue[EG + 1];  // row offset of each event (-1: none); the last entry looks one event ahead
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const bool has = g0 + q < ne;
-        const int i = has ? g0 + q : 0;
-        const int nw = __builtin_amdgcn_readlane(evl.x, i);
-        const int old = __builtin_amdgcn_readlane(evl.y, i);
-        const int key = __builtin_amdgcn_readlane(evl.z, i);
-        okn[q] = has && nw >= 0;
-        oko[q] = has && old >= 0;
-        ue[q] = has ? (key >> 8) : -1;
-        vn[q] = prow(okn[q] ? nw : r0)[colc];
-        vo[q] = prow(oko[q] ? old : r0)[colc];
+      for (int q = 0; q < EG; ++q) {
+        const int i = g0 + q;  // lanes >= ne hold the zero row and offset -1
+        vn[q] = ld(__builtin_amdgcn_readlane(evl.x, i));
+        vo[q] = ld(__builtin_amdgcn_readlane(evl.y, i));
+        ue[q] = __builtin_amdgcn_readlane(evl.z, i) >> 8;
       }
-      // row offset of the event after this group (-1 at the end of the run)
-      const int inext = g0 + 16;
-      const int unext = inext < ne ? (__builtin_amdgcn_readlane(evl.z, inext) >> 8)
-                                   : (eb + 64 < e1 ? (__builtin_amdgcn_readfirstlane(w.ev[eb + 64].z) >> 8) : -1);
+      // the row offset of the event after this group (-1 at the end of the run)
+      const int inext = g0 + EG;
+      ue[EG] = inext < ne ? (__builtin_amdgcn_readlane(evl.z, inext) >> 8)
+                          : (eb + 64 < e1 ? (__builtin_amdgcn_readfirstlane(w.ev[eb + 64].z) >> 8) : -1);
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        if (ue[q] >= 0) {
-          if (okn[q]) acc += (W)vn[q];
-          if (oko[q]) acc -= (W)vo[q];
-          const int un = q + 1 < 16 ? ue[q + 1] : unext;
-          if (un != ue[q]) {  // last event of its row: snapshot
-            m = min(m + 1, mlast);
-            if (colok) (S + (int64_t)m * B)[col] = (TP)acc;
-          }
+      for (int q = 0; q < EG; ++q) {
+        acc += (W)vn[q] - (W)vo[q];
+        if (ue[q] >= 0 && ue[q + 1] != ue[q]) {  // last event of its row: snapshot
+          m = min(m + 1, mlast);
+          if (colok) (S + (int64_t)m * B)[col] = (TP)acc;
         }
       }
     }
@@ -850,8 +852,11 @@ hipError_t walk_typed(const DevPoset& d, const int32_t* nv, const WalkTables& w,
   if (hook) hook->before(0, s);
   if (uniform) {
     const int64_t waves = (int64_t)w.nruns * ((B + 63) / 64);
-    hipLaunchKernelGGL((k_walk_events<TP>), dim3((unsigned)((waves + (WG / 64) - 1) / (WG / 64))), dim3(WG), 0, s,
-                       d, nv, w, (const TP*)P, B, (TP*)snaps);
+    const dim3 g((unsigned)((waves + (WG / 64) - 1) / (WG / 64)));
+    if (((int64_t)d.n + 1) * B * (int64_t)sizeof(TP) < ((int64_t)1 << 31))
+      hipLaunchKernelGGL((k_walk_events<TP, true>), g, dim3(WG), 0, s, d, nv, w, (const TP*)P, B, (TP*)snaps);
+    else
+      hipLaunchKernelGGL((k_walk_events<TP, false>), g, dim3(WG), 0, s, d, nv, w, (const TP*)P, B, (TP*)snaps);
   } else {
     const int64_t waves = (w.nruns + (64 / cw) - 1) / (64 / cw);
     hipLaunchKernelGGL((k_walk_events_split<TP>), dim3((unsigned)((waves + (WG / 64) - 1) / (WG / 64))), dim3(WG),
@@ -1034,8 +1039,8 @@ hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int6
       hipLaunchKernelGGL((k_scan_reduce<Tin, Tout, 0>), g2, dim3(WG), 0, s, d, segi, cw, (const Tin*)x, ldx, B,
                          ntiles, A);
   } else if (phase == 1) {
-    hipLaunchKernelGGL((k_scan_carry<St>), dim3((unsigned)d.nchains, (unsigned)((B + 15) / 16)), dim3(WG), 0, s, d,
-                       segi, dir, B, (const St*)A, C);
+    hipLaunchKernelGGL((k_scan_carry<St, Tout>), dim3((unsigned)d.nchains, (unsigned)((B + 15) / 16)), dim3(WG), 0,
+                       s, d, segi, dir, B, (const St*)A, C, (Tout*)P);
   } else if (cw == 64) {
     hipLaunchKernelGGL((k_scan_apply<Tin, Tout, 64>), g, dim3(WG), 0, s, d, segi, cw, dir, (const Tin*)x, ldx, B,
                        (const St*)C, (Tout*)P);
