@@ -637,7 +637,14 @@ __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* _
   // registers: every gather is then one load from a scalar base at a per-lane
   // offset.  Row n of P is a zero row: the tables name it for "no element",
   // so that every event adds P[new] - P[old] without a predicate.
-  const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (WG / 64) + (threadIdx.x >> 6)));
+  // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+  // L2: XCD x takes a contiguous slice of the height-ordered runs, so that its
+  // L2 holds one height band instead of every band at once (a bijection of
+  // the block indices).
+  const int nblk = (int)gridDim.x, q8 = nblk >> 3, r8 = nblk & 7;
+  const int xcd = (int)(blockIdx.x & 7), slot = (int)(blockIdx.x >> 3);
+  const int blk = xcd * q8 + min(xcd, r8) + slot;
+  const int gw = __builtin_amdgcn_readfirstlane(blk * (WG / 64) + (int)(threadIdx.x >> 6));
   if ((int64_t)gw >= (int64_t)w.nruns * ncb) return;
   const int run = gw / ncb;
   const int col = (gw % ncb) * 64 + lane;
