@@ -444,6 +444,10 @@ hipError_t solve_levels(const px_poset* p, bool up, px::ElemType tin, const void
                         void* Y, int64_t B, hipStream_t s) {
   const std::vector<int32_t>& ptr = up ? p->prep.lev_up_ptr : p->prep.lev_down_ptr;
   const int32_t* rows = up ? p->d_lev_up : p->d_lev_down;
+  if (p->prep.n > 0) {
+    hipError_t e = px::launch_usolve_begin(p->dp, ty, Y, B, s);
+    if (e != hipSuccess) return e;
+  }
   for (size_t l = 0; l + 1 < ptr.size(); ++l) {
     prof::Scope sc(prof::USOLVE, s);
     hipError_t e = px::launch_usolve_level(p->dp, up, rows + ptr[l], ptr[l + 1] - ptr[l], tin, g, ldg, ty, Y, B, s);

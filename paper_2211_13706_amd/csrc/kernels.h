@@ -98,6 +98,10 @@ hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P,
 
 // One level of the solve U y' = g: for the rows lev_rows[0..cnt),
 // Y[r] = g[node(r)] - Σ_{j: nv[r][j] != r} Y[nv[r][j]].
+// Before the levels of a solve into Y ([n + 1, B] of type ty): row n of Y set
+// to zero (the uniform solve reads it for the own and missing niv entries).
+hipError_t launch_usolve_begin(const DevPoset& d, ElemType ty, void* Y, int64_t B, hipStream_t s);
+
 hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_rows, int64_t cnt,
                                ElemType tin, const void* g, int64_t ldg, ElemType ty, void* Y,
                                int64_t B, hipStream_t s);

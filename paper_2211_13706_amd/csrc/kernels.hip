@@ -944,6 +944,47 @@ __global__ __launch_bounds__(WG) void k_usolve(DevPoset d, const int32_t* __rest
   Y[r * B + col] = (TY)acc;
 }
 
+// With 64-wide column blocks each wavefront solves one row: the row and its
+// niv entries are wave-uniform (scalar registers), its k - 1 dependencies go
+// out 32 at a time from scalar row bases, and the own and missing entries read
+// row n of Y, which launch_usolve_begin sets to zero.  Same subtraction order
+// as k_usolve (a zero row subtracts nothing), so results are identical.
+template <typename Tin, typename TY>
+__global__ __launch_bounds__(WG) void k_usolve_uni(DevPoset d, const int32_t* __restrict__ nv,
+                                                   const int32_t* __restrict__ rows, int cnt,
+                                                   const Tin* __restrict__ g, int64_t ldg, TY* __restrict__ Y,
+                                                   int64_t B) {
+  using W = typename Wide<TY>::W;
+  const int lane = threadIdx.x & 63;
+  const int i = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (WG / 64) + (threadIdx.x >> 6)));
+  if (i >= cnt) return;
+  const int col = (int)blockIdx.y * 64 + lane;
+  const bool colok = col < B;
+  const int colc = colok ? col : 0;
+  const int r = __builtin_amdgcn_readfirstlane(rows[i]);
+  const int node = __builtin_amdgcn_readfirstlane(d.node_of_row[r]);
+  const int k = d.k, zr = d.n;
+  const int cur = lane < k ? nv[(int64_t)r * k + lane] : -1;
+  W acc = (W)(g + (int64_t)node * ldg)[colc];
+  for (int j0 = 0; j0 < k; j0 += 32) {
+    TY v[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int j = j0 + u;
+      const int t = __builtin_amdgcn_readlane(cur, j & 63);
+      v[u] = (Y + (int64_t)(j < k && t >= 0 && t != r ? t : zr) * B)[colc];
+    }
+#pragma unroll
+    for (int u = 0; u < 32; ++u) acc -= (W)v[u];
+  }
+  if (colok) (Y + (int64_t)r * B)[col] = (TY)acc;
+}
+
+__global__ void k_zero_bytes(uint32_t* p, int64_t words) {
+  const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i < words) p[i] = 0u;
+}
+
 // ------------------------------------------------------------ chain difference
 // With stats != nullptr (refinement, accumulate mode): per column the largest
 // |correction| into stats[col], the largest |updated value| into stats[B+col]
@@ -1162,12 +1203,38 @@ hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P,
   return hipGetLastError();
 }
 
+hipError_t launch_usolve_begin(const DevPoset& d, ElemType ty, void* Y, int64_t B, hipStream_t s) {
+  const int64_t words = B * (ty == E_F32 ? 1 : 2);
+  hipLaunchKernelGGL(k_zero_bytes, dim3((unsigned)((words + WG - 1) / WG)), dim3(WG), 0, s,
+                     (uint32_t*)((char*)Y + (int64_t)d.n * B * (ty == E_F32 ? 4 : 8)), words);
+  return hipGetLastError();
+}
+
 hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_rows, int64_t cnt, ElemType tin,
                                const void* g, int64_t ldg, ElemType ty, void* Y, int64_t B, hipStream_t s) {
   if (cnt == 0) return hipSuccess;
   const int cw = col_width(B);
   const dim3 gr = grid2(cnt, cw, B);
   const int32_t* nv = up ? d.niv_up : d.niv;
+  if (cw == 64 && d.k <= 64 && !d.poset_of_row && cnt < INT32_MAX) {
+    const dim3 gu((unsigned)((cnt + (WG / 64) - 1) / (WG / 64)), (unsigned)((B + 63) / 64));
+    const int c = (int)cnt;
+    if (tin == E_I64 && ty == E_I64)
+      hipLaunchKernelGGL((k_usolve_uni<int64_t, int64_t>), gu, dim3(WG), 0, s, d, nv, lev_rows, c, (const int64_t*)g,
+                         ldg, (int64_t*)Y, B);
+    else if (tin == E_F32 && ty == E_F32)
+      hipLaunchKernelGGL((k_usolve_uni<float, float>), gu, dim3(WG), 0, s, d, nv, lev_rows, c, (const float*)g, ldg,
+                         (float*)Y, B);
+    else if (tin == E_F64 && ty == E_F32)
+      hipLaunchKernelGGL((k_usolve_uni<double, float>), gu, dim3(WG), 0, s, d, nv, lev_rows, c, (const double*)g, ldg,
+                         (float*)Y, B);
+    else if (tin == E_F64 && ty == E_F64)
+      hipLaunchKernelGGL((k_usolve_uni<double, double>), gu, dim3(WG), 0, s, d, nv, lev_rows, c, (const double*)g,
+                         ldg, (double*)Y, B);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   if (tin == E_I64 && ty == E_I64)
     hipLaunchKernelGGL((k_usolve<int64_t, int64_t>), gr, dim3(WG), 0, s, d, nv, lev_rows, cnt, cw,
                        (const int64_t*)g, ldg, (int64_t*)Y, B);
