@@ -946,7 +946,7 @@ __global__ __launch_bounds__(WG) void k_usolve(DevPoset d, const int32_t* __rest
 
 // With 64-wide column blocks each wavefront solves one row: the row and its
 // niv entries are wave-uniform (scalar registers), its k - 1 dependencies go
-// out 32 at a time from scalar row bases, and the own and missing entries read
+// out all at once from scalar row bases, and the own and missing entries read
 // row n of Y, which launch_usolve_begin sets to zero.  Same subtraction order
 // as k_usolve (a zero row subtracts nothing), so results are identical.
 template <typename Tin, typename TY>
@@ -966,17 +966,15 @@ __global__ __launch_bounds__(WG) void k_usolve_uni(DevPoset d, const int32_t* __
   const int k = d.k, zr = d.n;
   const int cur = lane < k ? nv[(int64_t)r * k + lane] : -1;
   W acc = (W)(g + (int64_t)node * ldg)[colc];
-  for (int j0 = 0; j0 < k; j0 += 32) {
-    TY v[32];
+  // levels hold few rows, so occupancy matters little: all k loads in flight
+  TY v[64];
 #pragma unroll
-    for (int u = 0; u < 32; ++u) {
-      const int j = j0 + u;
-      const int t = __builtin_amdgcn_readlane(cur, j & 63);
-      v[u] = (Y + (int64_t)(j < k && t >= 0 && t != r ? t : zr) * B)[colc];
-    }
-#pragma unroll
-    for (int u = 0; u < 32; ++u) acc -= (W)v[u];
+  for (int j = 0; j < 64; ++j) {
+    const int t = __builtin_amdgcn_readlane(cur, j);
+    v[j] = (Y + (int64_t)(j < k && t >= 0 && t != r ? t : zr) * B)[colc];
   }
+#pragma unroll
+  for (int j = 0; j < 64; ++j) acc -= (W)v[j];
   if (colok) (Y + (int64_t)r * B)[col] = (TY)acc;
 }
 
@@ -991,33 +989,51 @@ __global__ void k_zero_bytes(uint32_t* p, int64_t words) {
 // (float64 bit patterns, non-negative so integer max orders them), and a
 // non-finite flag into stats[2B]; reduced over the workgroup's rows in LDS
 // first, one atomic per column per workgroup.
-template <typename TY, typename Tout>
-__global__ __launch_bounds__(WG) void k_chain_diff(DevPoset d, int dir, int cw, const TY* __restrict__ Y, int64_t B,
+template <typename TY, typename Tout, int CWT>
+__global__ __launch_bounds__(WG) void k_chain_diff(DevPoset d, int dir, int cw_rt, const TY* __restrict__ Y, int64_t B,
                                                    Tout* __restrict__ out, int64_t ldo, int accumulate,
                                                    uint64_t* __restrict__ stats) {
   using W = typename Wide<TY>::W;
+  constexpr int RPC = 8;  // rows per thread, loads in flight together
+  const int cw = CWT ? CWT : cw_rt;
   const int RG = WG / cw;
-  const int64_t r = (int64_t)blockIdx.x * RG + threadIdx.x / cw;
+  // with 64-wide column blocks a row group is one wavefront: rows are uniform
+  auto uni = [](int v) { return CWT == 64 ? __builtin_amdgcn_readfirstlane(v) : v; };
+  const int rbase = uni((int)((blockIdx.x * RG + threadIdx.x / cw) * RPC));
   const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
-  const bool active = r < d.n && col < B;
+  const int64_t colc = col < B ? col : 0;
+  const int n = d.n;
+  int nd[RPC], nb[RPC];
+  TY y[RPC], yb[RPC];
+#pragma unroll
+  for (int i = 0; i < RPC; ++i) {
+    const int r = min(rbase + i, n - 1);
+    const int c = uni(d.chain_of_row[r]);
+    // the neighbour in the chain (below for dir > 0, above otherwise); the
+    // chain's end rows take the row itself and subtract nothing
+    const int rb = dir > 0 ? (r > d.chain_off[c] ? r - 1 : -1) : (r + 1 < d.chain_off[c + 1] ? r + 1 : -1);
+    nb[i] = uni(rb);
+    nd[i] = uni(d.node_of_row[r]);
+    y[i] = Y[(int64_t)r * B + colc];
+    yb[i] = Y[(int64_t)(rb >= 0 ? rb : r) * B + colc];
+  }
   double dmax = 0, fmax = 0;
   bool bad = false;
-  if (active) {
-    const int c = d.chain_of_row[r];
-    W v = (W)Y[r * B + col];
-    if (dir > 0) {
-      if (r > d.chain_off[c]) v -= (W)Y[(r - 1) * B + col];
-    } else {
-      if (r + 1 < d.chain_off[c + 1]) v -= (W)Y[(r + 1) * B + col];
-    }
-    const int64_t node = d.node_of_row[r];
-    Tout* o = out + node * ldo + col;
-    Tout nv = accumulate ? (Tout)((W)*o + v) : (Tout)v;
-    *o = nv;
-    if constexpr (std::is_floating_point<W>::value) {
-      dmax = fabs((double)v);
-      fmax = fabs((double)nv);
-      bad = !isfinite(dmax) || !isfinite(fmax);
+  if (col < B) {
+#pragma unroll
+    for (int i = 0; i < RPC; ++i) {
+      if (rbase + i >= n) break;
+      W v = (W)y[i];
+      if (nb[i] >= 0) v -= (W)yb[i];
+      Tout* o = out + (int64_t)nd[i] * ldo + col;
+      const Tout nvv = accumulate ? (Tout)((W)*o + v) : (Tout)v;
+      *o = nvv;
+      if constexpr (std::is_floating_point<W>::value) {
+        const double a1 = fabs((double)v), a2 = fabs((double)nvv);
+        bad = bad || !isfinite(a1) || !isfinite(a2);
+        dmax = fmax_(dmax, a1);
+        fmax = fmax_(fmax, a2);
+      }
     }
   }
   if (!stats) return;
@@ -1029,14 +1045,14 @@ __global__ __launch_bounds__(WG) void k_chain_diff(DevPoset d, int dir, int cw, 
   sf[threadIdx.x] = bad ? 0.0 : fmax;
   if (bad) sb = 1;
   __syncthreads();
-  if (threadIdx.x < cw && col < B) {
-    double a = 0, b = 0;
+  if ((int)threadIdx.x < cw && col < B) {
+    double a = 0, bb = 0;
     for (int g = 0; g < RG; ++g) {
       a = fmax_(a, sd[g * cw + threadIdx.x]);
-      b = fmax_(b, sf[g * cw + threadIdx.x]);
+      bb = fmax_(bb, sf[g * cw + threadIdx.x]);
     }
     atomicMax((unsigned long long*)&stats[col], (unsigned long long)__double_as_longlong(a));
-    atomicMax((unsigned long long*)&stats[B + col], (unsigned long long)__double_as_longlong(b));
+    atomicMax((unsigned long long*)&stats[B + col], (unsigned long long)__double_as_longlong(bb));
   }
   if (threadIdx.x == 0 && sb) atomicMax((unsigned long long*)&stats[2 * B], 1ull);
 }
@@ -1252,24 +1268,35 @@ hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_ro
   return hipGetLastError();
 }
 
+namespace {
+template <typename TY, typename Tout>
+void chain_diff_typed(const DevPoset& d, int dir, int cw, const void* Y, int64_t B, void* out, int64_t ldo,
+                      bool accumulate, uint64_t* stats, hipStream_t s) {
+  const int64_t rows_per_block = (WG / cw) * 8;
+  const dim3 g((unsigned)((d.n + rows_per_block - 1) / rows_per_block), (unsigned)((B + cw - 1) / cw));
+  if (cw == 64)
+    hipLaunchKernelGGL((k_chain_diff<TY, Tout, 64>), g, dim3(WG), 0, s, d, dir, cw, (const TY*)Y, B, (Tout*)out, ldo,
+                       (int)accumulate, stats);
+  else
+    hipLaunchKernelGGL((k_chain_diff<TY, Tout, 0>), g, dim3(WG), 0, s, d, dir, cw, (const TY*)Y, B, (Tout*)out, ldo,
+                       (int)accumulate, stats);
+}
+}  // namespace
+
 hipError_t launch_chain_diff(const DevPoset& d, int dir, ElemType ty, const void* Y, int64_t B, ElemType tout,
                              void* out, int64_t ldo, bool accumulate, uint64_t* stats, hipStream_t s) {
   if (d.n == 0) return hipSuccess;
   const int cw = col_width(B);
-  const dim3 g = grid2(d.n, cw, B);
   if (stats) {
     const int64_t cnt = 2 * B + 1;
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((cnt + WG - 1) / WG)), dim3(WG), 0, s, stats, cnt, (uint64_t)0);
   }
   if (ty == E_I64 && tout == E_I64)
-    hipLaunchKernelGGL((k_chain_diff<int64_t, int64_t>), g, dim3(WG), 0, s, d, dir, cw, (const int64_t*)Y, B,
-                       (int64_t*)out, ldo, (int)accumulate, stats);
+    chain_diff_typed<int64_t, int64_t>(d, dir, cw, Y, B, out, ldo, accumulate, stats, s);
   else if (ty == E_F32 && tout == E_F32)
-    hipLaunchKernelGGL((k_chain_diff<float, float>), g, dim3(WG), 0, s, d, dir, cw, (const float*)Y, B,
-                       (float*)out, ldo, (int)accumulate, stats);
+    chain_diff_typed<float, float>(d, dir, cw, Y, B, out, ldo, accumulate, stats, s);
   else if (ty == E_F64 && tout == E_F64)
-    hipLaunchKernelGGL((k_chain_diff<double, double>), g, dim3(WG), 0, s, d, dir, cw, (const double*)Y, B,
-                       (double*)out, ldo, (int)accumulate, stats);
+    chain_diff_typed<double, double>(d, dir, cw, Y, B, out, ldo, accumulate, stats, s);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -96,7 +96,7 @@ def cfg0():
     return p, R
 
 
-@pytest.mark.parametrize("B,ld", [(1, 1), (3, 5), (64, 64)])
+@pytest.mark.parametrize("B,ld", [(1, 1), (3, 5), (64, 64), (100, 104)])
 def test_cfg0_int64_bit_exact(px, cfg0, B, ld):
     p, R = cfg0
     P = build(px, p)
@@ -153,10 +153,12 @@ def test_f32_zeta_tolerance(px, cfg0, B):
     check_f32_zeta(H(px.zeta_adjoint(P, T(f))), wantT, zabsT)
 
 
-def test_f64_zeta_and_mobius(px, cfg0):
+@pytest.mark.parametrize("B", [8, 40])
+def test_f64_zeta_and_mobius(px, cfg0, B):
+    """B = 40: one 64-wide column block, 24 lanes idle (uniform-row kernels)."""
     p, R = cfg0
     P = build(px, p)
-    f = W.functions(p.n, 8, "normal64", seed=12)
+    f = W.functions(p.n, B, "normal64", seed=12)
     g = H(px.zeta(P, T(f)))
     assert rel(g, O.zeta(R, f, exact=False)) <= 1e-12
     assert rel(H(px.zeta_adjoint(P, T(f))), O.zeta_adjoint(R, f, exact=False)) <= 1e-12
@@ -164,12 +166,14 @@ def test_f64_zeta_and_mobius(px, cfg0):
     assert rel(H(px.mobius(P, T(g))), f) <= 1e-9
 
 
-def test_f32_mobius_refined_small_poset(px):
-    """g = Z f with integer f is exact in float32, so M g = f exactly is the target."""
+@pytest.mark.parametrize("B", [8, 48])
+def test_f32_mobius_refined_small_poset(px, B):
+    """g = Z f with integer f is exact in float32, so M g = f exactly is the target.
+    B = 48 takes the uniform-row solve and walk (float32 solve, float64 residual)."""
     p = W.chain_poset(1500, 12, 3, seed=21)
     R = O.reachability(p.n, p.indptr, p.indices)
     P = build(px, p)
-    f = W.functions(p.n, 8, "int", seed=22, lo=-100, hi=100)
+    f = W.functions(p.n, B, "int", seed=22, lo=-100, hi=100)
     g32 = O.zeta(R, f).astype(np.float32)
     got, rep = px.mobius(P, T(g32), max_refine=8, tol=1e-8, report=True)
     assert rel(H(got), f) <= 1e-5, rep
