@@ -220,7 +220,10 @@ __global__ __launch_bounds__(WG) void k_scan_carry(DevPoset d, int segi, int dir
   }
 }
 
-// Phase 3: scan inside the tile from its carry; write P chain-major.
+// Phase 3: scan inside the tile from its carry; write P chain-major.  This is
+// the last read of f and P is not read back soon: both streams are
+// non-temporal, so that f read by phase 1 stays in the MALL for this read and
+// the next call's phase 1.
 template <typename Tin, typename Tout, int CWT>
 __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_rt, int dir,
                                                    const Tin* __restrict__ x, int64_t ldx, int64_t B,
@@ -252,7 +255,7 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
   }
   Tin raw[RPT];
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) raw[i] = x[(int64_t)nodes[i] * ldx + colc];
+  for (int i = 0; i < RPT; ++i) raw[i] = __builtin_nontemporal_load(&x[(int64_t)nodes[i] * ldx + colc]);
   Tv v[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) v[i] = (r0 + i < end) ? Tr::in(raw[i]) : Tv(0);
@@ -275,7 +278,7 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
     for (int i = 0; i < RPT; ++i) {
       st.add(v[i]);
       int64_t r = r0 + i;
-      if (r < end) P[r * B + col] = Tr::out(st.value());
+      if (r < end) __builtin_nontemporal_store(Tr::out(st.value()), &P[r * B + col]);
     }
   } else {
     for (int g = RG - 1; g > rg; --g) st.combine(sm[g * cw + lane]);
@@ -283,7 +286,7 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
     for (int i = RPT - 1; i >= 0; --i) {
       st.add(v[i]);
       int64_t r = r0 + i;
-      if (r < end) P[r * B + col] = Tr::out(st.value());
+      if (r < end) __builtin_nontemporal_store(Tr::out(st.value()), &P[r * B + col]);
     }
   }
 }
@@ -808,6 +811,9 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
 
 // UNI: cw == 64, so each wavefront owns whole rows and row quantities are
 // wave-uniform (kept in scalar registers, loads from scalar row bases).
+// P is read here for the last time and g is written once: both streams are
+// non-temporal, so that they do not evict f and P's gathered rows from the
+// caches (f stays in the 256 MB MALL between its two reads by the scan).
 template <typename TP, typename Tres, bool RESID, bool UNI>
 __global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* __restrict__ snap_of_row, int cw_rt,
                                                      const TP* __restrict__ P, const TP* __restrict__ S, int64_t B,
@@ -833,7 +839,7 @@ __global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* 
 #pragma unroll
   for (int i = 0; i < RPC; ++i) {
     const int r = min(rbase + i, d.n - 1);
-    pv[i] = (P + (int64_t)r * B)[colc];
+    pv[i] = __builtin_nontemporal_load(&(P + (int64_t)r * B)[colc]);
     sv[i] = (S + (int64_t)sm[i] * B)[colc];
   }
   if (col >= B) return;
@@ -844,7 +850,7 @@ __global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* 
         (out + (int64_t)nd[i] * ldo)[col] =
             (TP)((double)(res + (int64_t)nd[i] * ldr)[col] - ((W)pv[i] + (W)sv[i]));
       else
-        (out + (int64_t)nd[i] * ldo)[col] = (TP)((W)pv[i] + (W)sv[i]);
+        __builtin_nontemporal_store((TP)((W)pv[i] + (W)sv[i]), &(out + (int64_t)nd[i] * ldo)[col]);
     }
   }
 }
