@@ -42,25 +42,37 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(phase: str, n: int, k: int, B: int, s: int, info: dict) -> int:
+def algorithmic_bytes(phase: str, n: int, k: int, B: int, s: int, info: dict, compact: bool = False) -> int:
     """Compulsory bytes of one launch of each kernel: every array it touches, once.
 
+    Tile states (the scan's per-tile totals and carries, n/64 tiles of 64 rows
+    for 64-column blocks, 2s bytes per column) count where they are read or
+    written.  The compact walk (the default at B = 64) records P only at the
+    walk's gathered rows (walk_rows_distinct slots): the reduce also writes their
+    tile-local prefixes L, the carry reads L and writes Q, the walk reads Q
+    instead of P, and apply_combine writes g = P + snapshot without writing P.
     walk_events: the change events (16 B each) and the run table (16 B per run),
-    the niv row of every run's first element (4k B), every P row it reads counted
-    once (walk_rows_distinct) and the snapshots it stores.
+    the first-row entries of every run (4k B), every gathered row counted once
+    and the snapshots it stores.
     walk_combine: P, the snapshots, node_of_row and snap_of_row, and g.
     """
     runs, ev, snaps = info.get("walk_runs", 0), info.get("walk_events", 0), info.get("walk_snapshots", 0)
+    slots = info.get("walk_rows_distinct", 0)
+    states = -(-n // 64) * B * 2 * s
     if phase == "walk_events":
-        return ev * 16 + runs * (k * 4 + 16) + info.get("walk_rows_distinct", 0) * B * s + snaps * B * s
+        return ev * 16 + runs * (k * 4 + 16) + slots * B * s + snaps * B * s
     if phase == "walk_combine":
         return n * B * s + snaps * B * s + 8 * n + n * B * s
+    if phase == "apply_combine":  # read f, C, snapshots, node_of_row, snap_of_row; write g
+        return n * B * s + states + snaps * B * s + 8 * n + n * B * s
     if phase == "gather":        # one thread per row: read P, niv, node_of_row, write g
         return n * B * s + n * k * 4 + n * 4 + n * B * s
-    if phase == "scan_apply":    # read f, read node_of_row, write P
-        return n * B * s + n * 4 + n * B * s
-    if phase == "scan_reduce":   # read f, read node_of_row
-        return n * B * s + n * 4
+    if phase == "scan_apply":    # read f, C, node_of_row, write P
+        return n * B * s + states + n * 4 + n * B * s
+    if phase == "scan_reduce":   # read f, node_of_row, write tile totals (and L)
+        return n * B * s + n * 4 + states + (slots * B * s if compact else 0)
+    if phase == "scan_carry":    # read tile totals, write carries (and read L, write Q)
+        return 2 * states + (2 * slots * B * s if compact else 0)
     if phase == "scan_onepass":  # read f, read node_of_row, write P
         return n * B * s + n * 4 + n * B * s
     return 0
@@ -75,7 +87,7 @@ def gathered_bytes(phase: str, k: int, B: int, s: int, info: dict) -> int:
     return ev * 16 + runs * (k * 4 + 16) + info.get("walk_row_loads", 0) * B * s + snaps * B * s
 
 
-def profile_read(lib, nph=10):
+def profile_read(lib, nph=11):
     import ctypes
     ms = (ctypes.c_double * nph)()
     cnt = (ctypes.c_int64 * nph)()
@@ -317,12 +329,13 @@ def main():
     ms_step = dt * 1e3 / args.steps
     value = p.n * B / (dt / args.steps)
     phases = {}
+    compact = prof["apply_combine"][1] > 0
     for name in ("scan_reduce", "scan_carry", "scan_apply", "scan_onepass", "gather", "walk_events",
-                 "walk_combine"):
+                 "walk_combine", "apply_combine"):
         ms, cnt = prof[name]
         if cnt:
             avg = ms / cnt
-            byt = algorithmic_bytes(name, p.n, P.k, B, 4, P.info)
+            byt = algorithmic_bytes(name, p.n, P.k, B, 4, P.info, compact)
             phases[name] = {"avg_ms": round(avg, 4), "launches": cnt, "alg_bytes": byt,
                             "GBps": round(byt / (avg * 1e-3) / 1e9, 1) if byt else None}
             gb = gathered_bytes(name, P.k, B, 4, P.info)
@@ -332,8 +345,11 @@ def main():
     dom = max((k for k in phases if phases[k]["alg_bytes"]), key=lambda k: phases[k]["avg_ms"])
     ach = phases[dom]["GBps"]
     tr = traffic_for(dom)
-    # whole-step algorithmic bytes: read f, write P, read P, read niv, write g
+    # whole-step bytes of the factored method Z = U V as stated: read f, write P,
+    # read P, read niv, write g (20 B per node and right-hand side at k = B);
+    # the compact walk moves fewer (the sum of the phases' bytes)
     step_bytes = 4 * p.n * B * 4 + p.n * P.k * 4
+    moved = sum(ph["alg_bytes"] for ph in phases.values())
     out = {
         "metric": METRIC,
         "value": value,
@@ -357,7 +373,10 @@ def main():
                      "gathered_GBps": phases[dom].get("gathered_GBps"),
                      "traffic_GBps": round(tr / (phases[dom]["avg_ms"] * 1e-3) / 1e9, 1) if tr else None},
         "step_roofline": {"alg_bytes": step_bytes, "GBps": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
-                          "frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                          "frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "path": "compact walk" if compact else "scan + walk over P",
+                          "phase_bytes": moved,
+                          "phase_GBps": round(moved / (ms_step * 1e-3) / 1e9, 1)},
         "phases": phases,
         "preprocess_s": {"total": round(t_prep, 3), **{k: round(v, 3) for k, v in P.info.items()
                                                       if k.startswith("t_")}},

@@ -223,7 +223,8 @@ px_status px_batch_autotune(px_batch* b, int dtype, int64_t B, px_tune_report* r
  * px_profile(0) stops.  px_profile_read synchronises on the recorded events and returns,
  * for each of the first nphases phases, the summed milliseconds and the launch count.
  * Phase names: px_profile_phase_name(i) (scan_reduce, scan_carry, scan_apply, gather,
- * usolve_level, chain_diff, absmax, walk_events, walk_combine, scan_onepass).  Not for use under HIP graph capture. */
+ * usolve_level, chain_diff, absmax, walk_events, walk_combine, scan_onepass, apply_combine).
+ * Not for use under HIP graph capture. */
 px_status px_profile(int on);
 px_status px_profile_read(double* ms, int64_t* count, int nphases);
 const char* px_profile_phase_name(int i);

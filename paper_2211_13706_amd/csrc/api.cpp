@@ -205,6 +205,90 @@ void build_walk(const px::Prep& P, const std::vector<int32_t>& nv, HostWalk& W, 
   for (char c : seen) W.rows_distinct += c;
 }
 
+// Compact form of a walk (see px::WalkTables): the gathered rows numbered in
+// row order inside the 64-row tiles of the 64-column scan, and the walk's
+// first-row entries and events with slots instead of rows.
+struct HostCompact {
+  std::vector<uint64_t> tmask;
+  std::vector<int32_t> qoff, tile_of_slot, init, evq;
+  int32_t nslots = 0;
+};
+
+void build_compact(const px::Prep& P, const std::vector<int32_t>& nv, const HostWalk& W, HostCompact& H) {
+  const int64_t k = P.k, seg = px::seg_rows(64);
+  std::vector<int64_t> so(k + 1, 0);  // first tile of each chain
+  for (int64_t c = 0; c < k; ++c) so[c + 1] = so[c] + (P.chain_off[c + 1] - P.chain_off[c] + seg - 1) / seg;
+  const int64_t nt = so[k];
+  auto tile_bit = [&](int32_t r, int64_t& t, int& b) {
+    const int32_t c = P.chain_of_row[r];
+    const int64_t pos = r - P.chain_off[c];
+    t = so[c] + pos / seg;
+    b = (int)(pos % seg);
+  };
+  const size_t nruns = W.runs.size() / 2;
+  H.tmask.assign(nt, 0);
+  auto mark = [&](int32_t r) {
+    if (r < 0) return;
+    int64_t t;
+    int b;
+    tile_bit(r, t, b);
+    H.tmask[t] |= uint64_t(1) << b;
+  };
+  for (size_t s = 0; s < nruns; ++s) {
+    const int32_t r0 = W.runs[2 * s], c = P.chain_of_row[r0];
+    for (int64_t j = 0; j < k; ++j)
+      if (j != c) mark(nv[(size_t)r0 * k + j]);
+  }
+  for (size_t e = 0; e < W.ev.size(); e += 4) {
+    mark(W.ev[e]);
+    mark(W.ev[e + 1]);
+  }
+  H.qoff.assign(nt + 1, 0);
+  for (int64_t t = 0; t < nt; ++t) H.qoff[t + 1] = H.qoff[t] + __builtin_popcountll(H.tmask[t]);
+  H.nslots = H.qoff[nt];
+  H.tile_of_slot.resize(H.nslots);
+  for (int64_t t = 0; t < nt; ++t)
+    for (int32_t q = H.qoff[t]; q < H.qoff[t + 1]; ++q) H.tile_of_slot[q] = (int32_t)t;
+  auto slot = [&](int32_t r) -> int32_t {
+    if (r < 0) return H.nslots;
+    int64_t t;
+    int b;
+    tile_bit(r, t, b);
+    return H.qoff[t] + __builtin_popcountll(H.tmask[t] & ((uint64_t(1) << b) - 1));
+  };
+  H.init.assign(nruns * k, H.nslots);
+  for (size_t s = 0; s < nruns; ++s) {
+    const int32_t r0 = W.runs[2 * s], c = P.chain_of_row[r0];
+    for (int64_t j = 0; j < k; ++j)
+      if (j != c) H.init[s * k + j] = slot(nv[(size_t)r0 * k + j]);
+  }
+  H.evq = W.ev;
+  for (size_t e = 0; e < H.evq.size(); e += 4) {
+    H.evq[e] = slot(W.ev[e]);
+    H.evq[e + 1] = slot(W.ev[e + 1]);
+  }
+}
+
+// Every index the compact kernels derive from the tables stays inside Q, L
+// and the tile arrays: slots counted per tile agree with the masks, every
+// slot's tile holds it, and the walk names slots 0..nslots only.
+bool compact_consistent(const HostCompact& H, int64_t ntiles) {
+  const int64_t nt = (int64_t)H.tmask.size();
+  if (nt != ntiles || (int64_t)H.qoff.size() != nt + 1 || H.qoff[0] != 0 || H.qoff[nt] != H.nslots) return false;
+  for (int64_t t = 0; t < nt; ++t)
+    if (H.qoff[t + 1] - H.qoff[t] != __builtin_popcountll(H.tmask[t])) return false;
+  if ((int64_t)H.tile_of_slot.size() != H.nslots) return false;
+  for (int32_t q = 0; q < H.nslots; ++q) {
+    const int32_t t = H.tile_of_slot[q];
+    if (t < 0 || t >= nt || q < H.qoff[t] || q >= H.qoff[t + 1]) return false;
+  }
+  for (int32_t v : H.init)
+    if (v < 0 || v > H.nslots) return false;
+  for (size_t e = 0; e < H.evq.size(); e += 4)
+    if (H.evq[e] < 0 || H.evq[e] > H.nslots || H.evq[e + 1] < 0 || H.evq[e + 1] > H.nslots) return false;
+  return true;
+}
+
 // Tile orders of the single-pass scan: for each tile height and direction, the
 // tiles sorted by their position in the scan (from the bottom for prefix scans,
 // from the top for suffix scans), then by chain.
@@ -227,13 +311,16 @@ std::vector<int32_t> scan_orders(const std::vector<int32_t>& segoff, int64_t nch
 }
 
 struct Layout {
-  size_t y = 0, p64 = 0, r64 = 0, aux = 0, stats = 0, snaps = 0, sync = 0, total = 0;
+  size_t y = 0, p64 = 0, r64 = 0, aux = 0, stats = 0, snaps = 0, sync = 0, lq = 0, total = 0;
 };
 
 // Workspace layout of one call: a [n, B] matrix of the working type (P or Y),
 // for float32 refinement two float64 [n, B] matrices (P64 and the residual),
 // the scan's tile states and the refinement statistics.
-Layout layout(int64_t n, int64_t B, int dtype, bool refine, int64_t ntiles, int64_t nsnap = 0) {
+// With nslots >= 0 also the compact walk's L and Q ((2 * nslots + 1) rows of
+// the working type: float64 for the residual of a refinement).
+Layout layout(int64_t n, int64_t B, int dtype, bool refine, int64_t ntiles, int64_t nsnap = 0,
+              int64_t nslots = -1) {
   Layout L;
   size_t o = 0;
   L.y = o;  // one row more: the scan's zero row
@@ -252,6 +339,8 @@ Layout layout(int64_t n, int64_t B, int dtype, bool refine, int64_t ntiles, int6
   o = align256(o + (size_t)nsnap * B * (refine ? 8 : elem_size(dtype)));
   L.sync = o;
   o = align256(o + (size_t)(2 + ntiles * ((B + px::col_width(B) - 1) / px::col_width(B))) * 4);
+  L.lq = o;
+  if (nslots >= 0) o = align256(o + (size_t)(2 * nslots + 1) * B * (refine ? 8 : elem_size(dtype)));
   L.total = o;
   return L;
 }
@@ -265,10 +354,10 @@ px_status hip_status(hipError_t e, const char* what) {
 // (px_profile / px_profile_read).  Off by default: then it costs one branch.
 namespace prof {
 enum Phase { SCAN_REDUCE = 0, SCAN_CARRY, SCAN_APPLY, GATHER, USOLVE, CHAIN_DIFF, ABSMAX, WALK_EVENTS, WALK_COMBINE,
-             SCAN_ONEPASS, NPH };
+             SCAN_ONEPASS, APPLY_COMBINE, NPH };
 const char* const kNames[NPH] = {"scan_reduce", "scan_carry",   "scan_apply",  "gather",
                                  "usolve_level", "chain_diff",  "absmax",      "walk_events",
-                                 "walk_combine", "scan_onepass"};
+                                 "walk_combine", "scan_onepass", "apply_combine"};
 std::mutex mu;
 std::atomic<bool> on{false};
 struct Rec {
@@ -312,6 +401,18 @@ struct Scope {
 struct WalkHook : px::LaunchHook {
   Scope* sc[2] = {nullptr, nullptr};
   void before(int k, hipStream_t s) override { sc[k] = new Scope(k ? WALK_COMBINE : WALK_EVENTS, s); }
+  void after(int k, hipStream_t) override {
+    delete sc[k];
+    sc[k] = nullptr;
+  }
+};
+// Times the four kernels of the compact walk.
+struct CompactHook : px::LaunchHook {
+  Scope* sc[4] = {nullptr, nullptr, nullptr, nullptr};
+  void before(int k, hipStream_t s) override {
+    static const int ph[4] = {SCAN_REDUCE, SCAN_CARRY, WALK_EVENTS, APPLY_COMBINE};
+    sc[k] = new Scope(ph[k], s);
+  }
   void after(int k, hipStream_t) override {
     delete sc[k];
     sc[k] = nullptr;
@@ -369,6 +470,26 @@ hipError_t run_gather(const px::DevPoset& d, bool up, px::ElemType tp, const voi
   return px::launch_gather(d, up, tp, P, B, tout, out, ldo, tres, resid, ldr, snaps, nullptr, s);
 }
 
+// The compact walk is the default wherever it applies (single poset, k <= 64,
+// 64-column blocks); POSETX_WALK=rows (read on every call) selects the
+// scan that writes P and the walk over P instead.
+bool compact_enabled() {
+  const char* v = std::getenv("POSETX_WALK");
+  return !(v && std::strcmp(v, "rows") == 0);
+}
+
+hipError_t run_compact(const px::DevPoset& d, int dir, px::ElemType tin, const void* x, int64_t ldx,
+                       px::ElemType tout, void* out, int64_t ldo, px::ElemType tres, const void* resid, int64_t ldr,
+                       int64_t B, void* aux, int64_t nt, void* lq, void* snaps, hipStream_t s) {
+  if (prof::on) {
+    prof::CompactHook hook;
+    return px::launch_zeta_compact(d, dir, tin, x, ldx, tout, out, ldo, tres, resid, ldr, B, aux, nt, lq, snaps,
+                                   &hook, s);
+  }
+  return px::launch_zeta_compact(d, dir, tin, x, ldx, tout, out, ldo, tres, resid, ldr, B, aux, nt, lq, snaps,
+                                 nullptr, s);
+}
+
 hipError_t run_chain_diff(const px::DevPoset& d, int dir, px::ElemType ty, const void* Y, int64_t B,
                           px::ElemType tout, void* out, int64_t ldo, bool acc, uint64_t* stats, hipStream_t s) {
   prof::Scope sc(prof::CHAIN_DIFF, s);
@@ -390,6 +511,10 @@ struct px_poset {
   std::vector<int32_t> hw_runs[2], hw_ev[2], hw_ev_off[2], hw_snap_off[2], hw_snap_of_row[2];
   int32_t walk_T = 0, walk_emax = 0;
   int64_t walk_rows[2][2] = {{0, 0}, {0, 0}};  // per map: distinct P rows read, P-row loads
+  // compact walk tables per map (tmask, qoff, tile_of_slot, init, evq); nslots
+  // is -1 where the map has none
+  void* d_compact[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
+  int32_t nslots[2] = {-1, -1};
   px::DevPoset dp;
   Workspace ws;
   int64_t device_bytes = 0;
@@ -425,6 +550,12 @@ void free_poset_device(px_poset* p) {
         (void)hipFree(b);
         b = nullptr;
       }
+  for (auto& dir : p->d_compact)
+    for (void*& b : dir)
+      if (b) {
+        (void)hipFree(b);
+        b = nullptr;
+      }
   p->ws.release();
 }
 
@@ -436,6 +567,12 @@ px_status check_matrix_args(int64_t n, int dtype, const void* a, int64_t lda, co
   if (lda < B || ldb < B) return fail(PX_EINVAL, "leading dimension smaller than B");
   if (n > 0 && (!a || !b)) return fail(PX_EINVAL, "null function matrix");
   return PX_OK;
+}
+
+int64_t max_slots(const px_poset* p) { return std::max(p->nslots[0], p->nslots[1]); }
+
+bool use_compact(const px_poset* p, bool up, int64_t B) {
+  return p->nslots[up ? 1 : 0] >= 0 && compact_enabled() && px::compact_ok(p->dp, up, B);
 }
 
 // Level-scheduled solve U y' = g (Alg. 4, first loop; Alg. 5 schedule), one
@@ -468,11 +605,15 @@ px_status zeta_impl(px_poset* p, bool up, int dtype, const void* f, int64_t ldf,
   if (!dg.ok) return fail(PX_EHIP, "hipSetDevice failed");
   const int cw = px::col_width(B);
   const int64_t nt = p->ntiles[px::seg_index(cw)];
-  Layout L = layout(p->prep.n, B, dtype, false, nt, std::max(p->nsnap[0], p->nsnap[1]));
+  Layout L = layout(p->prep.n, B, dtype, false, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p));
   if ((st = p->ws.ensure(L.total)) != PX_OK) return st;
   char* w = (char*)p->ws.p;
   hipStream_t s = (hipStream_t)stream;
   const px::ElemType T = etype(dtype);
+  if (use_compact(p, up, B))
+    return hip_status(run_compact(p->dp, up ? -1 : 1, T, f, ldf, T, g, ldg, T, nullptr, 0, B, w + L.aux, nt,
+                                  w + L.lq, w + L.snaps, s),
+                      "zeta launch");
   hipError_t e = run_scan(p->dp, up ? -1 : 1, T, f, ldf, T, w + L.y, B, w + L.aux, nt, (int*)(w + L.sync), s);
   if (e == hipSuccess) e = run_gather(p->dp, up, T, w + L.y, B, T, g, ldg, T, nullptr, 0, w + L.snaps, s);
   return hip_status(e, "zeta launch");
@@ -502,7 +643,7 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   const bool refine = dtype == PX_F32;
   const int cw = px::col_width(B);
   const int64_t nt = p->ntiles[px::seg_index(cw)];
-  Layout L = layout(n, B, dtype, refine, nt, std::max(p->nsnap[0], p->nsnap[1]));
+  Layout L = layout(n, B, dtype, refine, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p));
   if ((st = p->ws.ensure(L.total)) != PX_OK) return st;
   char* w = (char*)p->ws.p;
   hipStream_t s = (hipStream_t)stream;
@@ -534,6 +675,9 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   };
   // r = g - zeta(f), zeta applied in float64 to the float32 iterate.
   auto residual = [&]() -> hipError_t {
+    if (use_compact(p, up, B))
+      return run_compact(p->dp, dir, px::E_F32, f, ldf, px::E_F64, r64, B, px::E_F32, g, ldg, B, w + L.aux, nt,
+                         w + L.lq, w + L.snaps, s);
     hipError_t e2 = run_scan(p->dp, dir, px::E_F32, f, ldf, px::E_F64, w + L.p64, B, w + L.aux, nt, (int*)(w + L.sync), s);
     if (e2 == hipSuccess)
       e2 = run_gather(p->dp, up, px::E_F64, w + L.p64, B, px::E_F64, r64, B, px::E_F32, g, ldg, w + L.snaps, s);
@@ -623,6 +767,43 @@ hipError_t set_walk(px_poset* p, int T, int emax) {
     t.ev_off = db[2];
     t.snap_off = db[3];
     t.snap_of_row = db[4];
+    // compact form (single poset, k <= 64)
+    void** dc = p->d_compact[dir];
+    for (int i = 0; i < 5; ++i)
+      if (dc[i]) {
+        (void)hipFree(dc[i]);
+        dc[i] = nullptr;
+      }
+    p->nslots[dir] = -1;
+    if (P.k <= 64) {
+      HostCompact H;
+      build_compact(P, dir ? P.niv_up : P.niv, W, H);
+      if (!compact_consistent(H, p->ntiles[px::seg_index(64)])) {
+        e = hipErrorInvalidValue;
+        break;
+      }
+      uint64_t* tm = nullptr;
+      int32_t *qo = nullptr, *ts = nullptr, *in = nullptr, *eq = nullptr;
+      e = upload(&tm, H.tmask.data(), H.tmask.size(), b);
+      dc[0] = tm;
+      if (e == hipSuccess) e = upload(&qo, H.qoff.data(), H.qoff.size(), b);
+      dc[1] = qo;
+      if (e == hipSuccess) e = upload(&ts, H.tile_of_slot.data(), H.tile_of_slot.size(), b);
+      dc[2] = ts;
+      if (e == hipSuccess) e = upload(&in, H.init.data(), H.init.size(), b);
+      dc[3] = in;
+      if (e == hipSuccess) e = upload(&eq, H.evq.data(), H.evq.size(), b);
+      dc[4] = eq;
+      if (e != hipSuccess) break;
+      t.tmask = tm;
+      t.qoff = qo;
+      t.tile_of_slot = ts;
+      t.init = in;
+      t.evq = (const int4*)eq;
+      t.nslots = H.nslots;
+      t.qoff_tiles = (int64_t)H.tmask.size();
+      p->nslots[dir] = H.nslots;
+    }
     p->hw_runs[dir] = std::move(W.runs);
     p->hw_ev[dir] = std::move(W.ev);
     p->hw_ev_off[dir] = std::move(W.ev_off);
@@ -877,7 +1058,8 @@ px_status px_reserve(px_poset* p, int dtype, int64_t B) {
   if (B < 1) return fail(PX_EINVAL, "B must be >= 1");
   DeviceGuard dg(p->device);
   const int64_t nt = p->ntiles[px::seg_index(px::col_width(B))];
-  return p->ws.ensure(layout(p->prep.n, B, dtype, dtype == PX_F32, nt, std::max(p->nsnap[0], p->nsnap[1])).total);
+  return p->ws.ensure(
+      layout(p->prep.n, B, dtype, dtype == PX_F32, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p)).total);
 }
 
 px_status px_zeta(px_poset* p, int dtype, const void* f, int64_t ldf, void* g, int64_t ldg, int64_t B, void* stream) {

@@ -22,6 +22,16 @@ enum ElemType { E_I64 = 0, E_F32 = 1, E_F64 = 2 };
 // snap_of_row[r] is the snapshot that row r adds to its own P[r].
 // Event rows name row n (a zero row of P that the scan keeps zero) for "no
 // element"; P therefore has n + 1 rows.
+//
+// Compact form (single poset, k <= 64): the event kernel reads P only at the
+// rows it gathers (the other-chain niv entries of each run's first row and
+// the rows of the events), so the scan can record P at those rows alone, in
+// Q, and never write P.  The gathered rows are numbered ("slots") in row
+// order within the 64-row scan tiles of 64-column blocks:
+// slot(r) = qoff[t] + popcount(tmask[t] & ((1 << b) - 1)) for row r at bit b of
+// tile t.  init[s * k + j] is the slot of niv_j(first row of run s) and evq
+// are the events with slots; both name slot nslots (a zero row of Q) for the
+// own chain and "no element".
 struct WalkTables {
   const int2* runs = nullptr;
   const int4* ev = nullptr;
@@ -30,6 +40,14 @@ struct WalkTables {
   const int32_t* snap_of_row = nullptr;
   int32_t nruns = 0, nsnap = 0;
   int32_t cw = 0;  // column tile of the lane-split form (0: the smallest power of two >= B)
+  // compact form (absent: tmask == nullptr)
+  const uint64_t* tmask = nullptr;       // [tiles of height 64]
+  const int32_t* qoff = nullptr;         // [tiles of height 64 + 1]
+  const int32_t* tile_of_slot = nullptr; // [nslots]
+  const int32_t* init = nullptr;         // [nruns * k]
+  const int4* evq = nullptr;             // as ev, rows replaced by slots
+  int32_t nslots = 0;
+  int64_t qoff_tiles = 0;                // tiles of height 64 that tmask / qoff cover
 };
 
 // Static description of one poset (or a batch of posets) on the device.
@@ -95,6 +113,24 @@ struct LaunchHook {
 hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P, int64_t B,
                          ElemType tout, void* out, int64_t ldo, ElemType tres, const void* resid,
                          int64_t ldr, void* snaps, LaunchHook* hook, hipStream_t s);
+
+// Zeta (dir=+1, niv map) or its adjoint (dir=-1, up map) through the
+// compact walk, for a single poset with k <= 64 and col_width(B) == 64 whose
+// walk tables have the compact form:
+//   0. tile totals, and the tile-local prefixes at the gathered rows (L);
+//   1. tile carries, and Q = carry + L at the gathered rows, Q[nslots] = 0;
+//   2. walk events on Q into snapshots;
+//   3. the scan inside each tile fused with the combine:
+//      out[node(r)] = P[r] + S[snap_of_row[r]]
+//      (or resid[node(r)] minus that, for a refinement residual).
+// P never exists.  tin -> tout as for the scan (E_F32 -> E_F64 only with resid).
+// aux: 2 * ntiles * B * 16 bytes (tile states); lq: (2 * nslots + 1) * B
+// elements of tout; snaps: nsnap * B elements of tout.
+// hook (nullable) is called around the four kernels (0..3).
+bool compact_ok(const DevPoset& d, bool up, int64_t B);
+hipError_t launch_zeta_compact(const DevPoset& d, int dir, ElemType tin, const void* x, int64_t ldx, ElemType tout,
+                               void* out, int64_t ldo, ElemType tres, const void* resid, int64_t ldr, int64_t B,
+                               void* aux, int64_t ntiles, void* lq, void* snaps, LaunchHook* hook, hipStream_t s);
 
 // One level of the solve U y' = g: for the rows lev_rows[0..cnt),
 // Y[r] = g[node(r)] - Σ_{j: nv[r][j] != r} Y[nv[r][j]].

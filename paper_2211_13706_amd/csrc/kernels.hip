@@ -94,6 +94,12 @@ template <> struct ScanTraits<float, double> {
   __device__ static double out(double v) { return v; }
 };
 
+// accumulation type of sums of TP values (exact wrap for int64)
+template <typename T> struct Wide;
+template <> struct Wide<int64_t> { using W = uint64_t; };
+template <> struct Wide<float> { using W = double; };
+template <> struct Wide<double> { using W = double; };
+
 __device__ inline int find_chain(const int32_t* so, int nchains, int t) {
   int lo = 0, hi = nchains;  // so[lo] <= t < so[hi]
   while (hi - lo > 1) {
@@ -107,12 +113,19 @@ __device__ inline int find_chain(const int32_t* so, int nchains, int t) {
 // workgroup reduces two tiles, so that each thread has 2*RPT loads in flight.
 // With CWT = 64 a row group is one wavefront, so its row (and node) indices
 // are wave-uniform and live in scalar registers.
-template <typename Tin, typename Tout, int CWT>
+//
+// MARK (compact walk, 64-column blocks): also the tile-local prefix (from the
+// tile's first row in scan order) at every gathered row, into L[slot].  Rows
+// of a tile are marked in tmask[t]; their slots are consecutive from qoff[t].
+template <typename Tin, typename Tout, int CWT, bool MARK>
 __global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw_rt, const Tin* __restrict__ x,
                                                     int64_t ldx, int64_t B, int64_t ntiles,
-                                                    typename ScanTraits<Tin, Tout>::St* __restrict__ A) {
+                                                    typename ScanTraits<Tin, Tout>::St* __restrict__ A, int dir,
+                                                    const uint64_t* __restrict__ tmask,
+                                                    const int32_t* __restrict__ qoff, Tout* __restrict__ L) {
   using Tr = ScanTraits<Tin, Tout>;
   using St = typename Tr::St;
+  static_assert(!MARK || CWT == 64, "marked rows need wave-uniform row groups");
   constexpr int NT = 2;
   const int cw = CWT ? CWT : cw_rt;
   __shared__ St sm[NT][WG];
@@ -156,6 +169,44 @@ __global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw
     sm[q][threadIdx.x] = st;
   }
   __syncthreads();
+  if constexpr (MARK) {
+    constexpr int RG = WG / 64;
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int64_t t = (int64_t)blockIdx.x * NT + q;
+      if (t >= ntiles) continue;
+      // the tile's marks: scalar; this wavefront's rows are bits [rg*RPT, rg*RPT + RPT)
+      const uint64_t mask = tmask[t];
+      const uint32_t wm = (uint32_t)(mask >> (rg * RPT)) & ((1u << RPT) - 1);
+      if (wm == 0) continue;
+      const int below = __popcll(mask & ((uint64_t(1) << (rg * RPT)) - 1));
+      St pre;
+      pre.zero();
+      if (dir > 0) {
+        int sl = qoff[t] + below;
+        for (int g = 0; g < rg; ++g) pre.combine(sm[q][g * 64 + lane]);
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          if (r0[q] + i < end[q]) pre.add(Tr::in(v[q][i]));
+          if ((wm >> i) & 1) {
+            if (col < B) L[(int64_t)sl * B + col] = Tr::out(pre.value());
+            ++sl;
+          }
+        }
+      } else {
+        int sl = qoff[t] + below + __popc(wm) - 1;
+        for (int g = RG - 1; g > rg; --g) pre.combine(sm[q][g * 64 + lane]);
+#pragma unroll
+        for (int i = RPT - 1; i >= 0; --i) {
+          if (r0[q] + i < end[q]) pre.add(Tr::in(v[q][i]));
+          if ((wm >> i) & 1) {
+            if (col < B) L[(int64_t)sl * B + col] = Tr::out(pre.value());
+            --sl;
+          }
+        }
+      }
+    }
+  }
   if (rg == 0 && col < B) {
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
@@ -174,19 +225,29 @@ __global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw
 // in LDS, each of 16 thread groups combines 8 of them, the group totals are
 // combined in order, and the carries are written; a running carry links the
 // windows.  The combination order is fixed, so results are reproducible.
-template <typename St, typename Tout>
+//
+// MARK (compact walk): the carries of a window stay in LDS and the gathered
+// rows of its tiles are completed, Q[slot] = carry(tile) + L[slot].  The
+// gridDim.z workgroups of one (chain, column block) each scan the chain's
+// tile totals (LDS work) and complete their share of the slots; the first of
+// them writes the carries.
+template <typename St, typename Tout, bool MARK>
 __global__ __launch_bounds__(WG) void k_scan_carry(DevPoset d, int segi, int dir, int64_t B,
                                                    const St* __restrict__ A, St* __restrict__ C,
-                                                   Tout* __restrict__ P) {
-  constexpr int CB = 16, NS = WG / CB, TPS = 8, WIN = NS * TPS;
+                                                   Tout* __restrict__ P, const int32_t* __restrict__ qoff,
+                                                   const int32_t* __restrict__ tile_of_slot,
+                                                   const Tout* __restrict__ L, int32_t nslots) {
+  constexpr int CB = 16, NS = WG / CB, TPS = 16, WIN = NS * TPS;
   __shared__ St sh[WIN * CB];
   __shared__ St tot[NS * CB];
   const int c = blockIdx.x;
   const int64_t c0 = (int64_t)blockIdx.y * CB;
   const int lc = threadIdx.x % CB, sg = threadIdx.x / CB;
   const int64_t col = c0 + lc;
-  // row n of P stays zero: the walk reads it for "no element"
-  if (c == 0 && sg == 0 && col < B) P[(int64_t)d.n * B + col] = Tout(0);
+  const bool lead = blockIdx.z == 0;
+  // the zero row (row n of P, or slot nslots of Q) stays zero: the walk reads
+  // it for "no element"
+  if (c == 0 && lead && sg == 0 && col < B) P[(int64_t)(MARK ? nslots : d.n) * B + col] = Tout(0);
   const int32_t* so = d.segoff + (int64_t)segi * (d.nchains + 1);
   const int t0 = so[c], t1 = so[c + 1], nt = t1 - t0;
   St carry;
@@ -212,10 +273,44 @@ __global__ __launch_bounds__(WG) void k_scan_carry(DevPoset d, int segi, int dir
 #pragma unroll
     for (int u = 0; u < TPS; ++u) {
       const int i = w0 + sg * TPS + u;
-      if (i < nt && col < B) C[(int64_t)(dir > 0 ? t0 + i : t1 - 1 - i) * B + col] = pre;
-      pre.combine(sh[(sg * TPS + u) * CB + lc]);
+      if (lead && i < nt && col < B) C[(int64_t)(dir > 0 ? t0 + i : t1 - 1 - i) * B + col] = pre;
+      const St a = sh[(sg * TPS + u) * CB + lc];
+      if (MARK) sh[(sg * TPS + u) * CB + lc] = pre;  // this thread's own entry: read just before
+      pre.combine(a);
     }
     for (int g = 0; g < NS; ++g) carry.combine(tot[g * CB + lc]);
+    if constexpr (MARK) {
+      __syncthreads();
+      // tiles of the window (tile index order) and their slots
+      const int wn = min(WIN, nt - w0);
+      const int tlo = dir > 0 ? t0 + w0 : t1 - w0 - wn;
+      const int s0 = qoff[tlo], s1 = qoff[tlo + wn];
+      const int per = (s1 - s0 + (int)gridDim.z - 1) / (int)gridDim.z;
+      const int a0 = s0 + (int)blockIdx.z * per, a1 = min(s1, a0 + per);
+      const int cnt = max(a1 - a0, 0) * CB;
+      constexpr int U = 4;
+      for (int x0 = threadIdx.x; x0 < cnt; x0 += WG * U) {
+        int sl[U], ti[U];
+        Tout lv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int x = min(x0 + u * WG, cnt - 1);
+          sl[u] = a0 + x / CB;
+          ti[u] = tile_of_slot[sl[u]];
+          lv[u] = L[(int64_t)sl[u] * B + (col < B ? col : 0)];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int x = x0 + u * WG;
+          if (x < cnt && col < B) {
+            const int i = (dir > 0 ? ti[u] - t0 : t1 - 1 - ti[u]) - w0;  // position in the window
+            St q = sh[i * CB + lc];
+            q.add((decltype(q.value()))lv[u]);
+            P[(int64_t)sl[u] * B + col] = (Tout)q.value();
+          }
+        }
+      }
+    }
     __syncthreads();
   }
 }
@@ -224,13 +319,22 @@ __global__ __launch_bounds__(WG) void k_scan_carry(DevPoset d, int segi, int dir
 // the last read of f and P is not read back soon: both streams are
 // non-temporal, so that f read by phase 1 stays in the MALL for this read and
 // the next call's phase 1.
-template <typename Tin, typename Tout, int CWT>
+//
+// MODE 1 / 2 (compact walk, 64-column blocks): instead of writing P[r], add
+// the other chains' sum S[snap_of_row[r]] (from the walk) and write the zeta
+// value out[node(r)] = P[r] + S (MODE 1), or the refinement residual
+// out[node(r)] = res[node(r)] - (P[r] + S) (MODE 2).
+template <typename Tin, typename Tout, int CWT, int MODE, typename Tres>
 __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_rt, int dir,
                                                    const Tin* __restrict__ x, int64_t ldx, int64_t B,
                                                    const typename ScanTraits<Tin, Tout>::St* __restrict__ C,
-                                                   Tout* __restrict__ P) {
+                                                   Tout* __restrict__ P, const int32_t* __restrict__ snap_of_row,
+                                                   const Tout* __restrict__ S, int64_t ldo,
+                                                   const Tres* __restrict__ res, int64_t ldr) {
   using Tr = ScanTraits<Tin, Tout>;
   using St = typename Tr::St;
+  using W = typename Wide<Tout>::W;
+  static_assert(MODE == 0 || CWT == 64, "the fused combine needs wave-uniform rows");
   const int cw = CWT ? CWT : cw_rt;
   using Tv = decltype(Tr::in(Tin()));
   __shared__ St sm[WG];
@@ -256,6 +360,28 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
   Tin raw[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) raw[i] = __builtin_nontemporal_load(&x[(int64_t)nodes[i] * ldx + colc]);
+  Tout sv[MODE ? RPT : 1];
+  if constexpr (MODE != 0) {
+    int32_t sn[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) sn[i] = __builtin_amdgcn_readfirstlane(snap_of_row[min(r0 + i, end - 1)]);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) sv[i] = (S + (int64_t)sn[i] * B)[colc];
+  }
+  // row i's result: P[r] itself, or the combined zeta value / residual
+  auto put = [&](int i, const St& st) {
+    const int64_t r = r0 + i;
+    if (r >= end) return;
+    if constexpr (MODE == 0) {
+      __builtin_nontemporal_store(Tr::out(st.value()), &P[r * B + col]);
+    } else if constexpr (MODE == 1) {
+      __builtin_nontemporal_store((Tout)((W)Tr::out(st.value()) + (W)sv[i]), &P[(int64_t)nodes[i] * ldo + col]);
+    } else {
+      __builtin_nontemporal_store(
+          (Tout)((double)res[(int64_t)nodes[i] * ldr + col] - ((W)Tr::out(st.value()) + (W)sv[i])),
+          &P[(int64_t)nodes[i] * ldo + col]);
+    }
+  };
   Tv v[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) v[i] = (r0 + i < end) ? Tr::in(raw[i]) : Tv(0);
@@ -277,16 +403,14 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       st.add(v[i]);
-      int64_t r = r0 + i;
-      if (r < end) __builtin_nontemporal_store(Tr::out(st.value()), &P[r * B + col]);
+      put(i, st);
     }
   } else {
     for (int g = RG - 1; g > rg; --g) st.combine(sm[g * cw + lane]);
 #pragma unroll
     for (int i = RPT - 1; i >= 0; --i) {
       st.add(v[i]);
-      int64_t r = r0 + i;
-      if (r < end) __builtin_nontemporal_store(Tr::out(st.value()), &P[r * B + col]);
+      put(i, st);
     }
   }
 }
@@ -577,10 +701,6 @@ __global__ void k_fill_i32(int* p, int64_t cnt, int v) {
 }
 
 // ------------------------------------------------------------ gather-reduce
-template <typename T> struct Wide;
-template <> struct Wide<int64_t> { using W = uint64_t; };
-template <> struct Wide<float> { using W = double; };
-template <> struct Wide<double> { using W = double; };
 
 __device__ inline double fmax_(double a, double b) { return a > b ? a : b; }
 
@@ -630,7 +750,11 @@ __global__ __launch_bounds__(WG) void k_gather(DevPoset d, const int32_t* __rest
 // Uniform form (k_walk_events, single poset, B >= 32, k <= 64): one wavefront
 // per run, lanes = 64 columns; event fields are read with readlane, so all
 // control flow is scalar.
-template <typename TP, bool OFF32>
+//
+// COMPACT: P is the compact Q of the gathered rows (slots), the first row's
+// entries come from w.init and the events from w.evq; slot nslots is the zero
+// row.
+template <typename TP, bool OFF32, bool COMPACT>
 __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* __restrict__ nv, WalkTables w,
                                                     const TP* __restrict__ P, int64_t B, TP* __restrict__ S) {
   using W = typename Wide<TP>::W;
@@ -655,7 +779,8 @@ __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* _
   const int colc = colok ? col : 0;
   const int r0 = __builtin_amdgcn_readfirstlane(w.runs[run].x);
   const int k = d.k;
-  const int zr = d.n;
+  const int zr = COMPACT ? w.nslots : d.n;
+  const int4* __restrict__ evs = COMPACT ? w.evq : w.ev;
   const int e0 = __builtin_amdgcn_readfirstlane(w.ev_off[run]);
   const int e1 = __builtin_amdgcn_readfirstlane(w.ev_off[run + 1]);
   // P[t][col]: with OFF32 (all of P within 2^31 bytes) one scalar 32-bit
@@ -668,8 +793,9 @@ __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* _
   };
 
   // the first row's niv entries and the first batch of events load together
-  const int cur = lane < k ? nv[(int64_t)r0 * k + lane] : -1;
-  const int4 ev_first = lane < e1 - e0 ? w.ev[e0 + lane] : make_int4(zr, zr, -1, 0);
+  const int cur = COMPACT ? (lane < k ? w.init[(int64_t)run * k + lane] : zr)
+                          : (lane < k ? nv[(int64_t)r0 * k + lane] : -1);
+  const int4 ev_first = lane < e1 - e0 ? evs[e0 + lane] : make_int4(zr, zr, -1, 0);
   // full gather of the first row, 32 loads in flight (64 cost more in occupancy
   // than they save); missing entries and the own chain read the zero row
   constexpr int PG = 32;
@@ -680,7 +806,7 @@ __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* _
     for (int u = 0; u < PG; ++u) {
       const int j = j0 + u;
       const int t = __builtin_amdgcn_readlane(cur, j & 63);
-      v[u] = ld(j < k && t >= 0 && t != r0 ? t : zr);
+      v[u] = ld(COMPACT ? t : (j < k && t >= 0 && t != r0 ? t : zr));
     }
 #pragma unroll
     for (int u = 0; u < PG; ++u) acc += (W)v[u];
@@ -692,7 +818,7 @@ __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* _
   constexpr int EG = 16;  // events per group, both gathers of each in flight
   for (int eb = e0; eb < e1; eb += 64) {
     const int ne = min(64, e1 - eb);
-    const int4 evl = eb == e0 ? ev_first : (lane < ne ? w.ev[eb + lane] : make_int4(zr, zr, -1, 0));
+    const int4 evl = eb == e0 ? ev_first : (lane < ne ? evs[eb + lane] : make_int4(zr, zr, -1, 0));
     for (int g0 = 0; g0 < ne; g0 += EG) {
       TP vn[EG], vo[EG];
       int ue[EG + 1];  // row offset of each event (-1: none); the last entry looks one event ahead
@@ -706,7 +832,7 @@ __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* _
       // the row offset of the event after this group (-1 at the end of the run)
       const int inext = g0 + EG;
       ue[EG] = inext < ne ? (__builtin_amdgcn_readlane(evl.z, inext) >> 8)
-                          : (eb + 64 < e1 ? (__builtin_amdgcn_readfirstlane(w.ev[eb + 64].z) >> 8) : -1);
+                          : (eb + 64 < e1 ? (__builtin_amdgcn_readfirstlane(evs[eb + 64].z) >> 8) : -1);
 #pragma unroll
       for (int q = 0; q < EG; ++q) {
         acc += (W)vn[q] - (W)vo[q];
@@ -867,9 +993,11 @@ hipError_t walk_typed(const DevPoset& d, const int32_t* nv, const WalkTables& w,
     const int64_t waves = (int64_t)w.nruns * ((B + 63) / 64);
     const dim3 g((unsigned)((waves + (WG / 64) - 1) / (WG / 64)));
     if (((int64_t)d.n + 1) * B * (int64_t)sizeof(TP) < ((int64_t)1 << 31))
-      hipLaunchKernelGGL((k_walk_events<TP, true>), g, dim3(WG), 0, s, d, nv, w, (const TP*)P, B, (TP*)snaps);
+      hipLaunchKernelGGL((k_walk_events<TP, true, false>), g, dim3(WG), 0, s, d, nv, w, (const TP*)P, B,
+                         (TP*)snaps);
     else
-      hipLaunchKernelGGL((k_walk_events<TP, false>), g, dim3(WG), 0, s, d, nv, w, (const TP*)P, B, (TP*)snaps);
+      hipLaunchKernelGGL((k_walk_events<TP, false, false>), g, dim3(WG), 0, s, d, nv, w, (const TP*)P, B,
+                         (TP*)snaps);
   } else {
     const int64_t waves = (w.nruns + (64 / cw) - 1) / (64 / cw);
     hipLaunchKernelGGL((k_walk_events_split<TP>), dim3((unsigned)((waves + (WG / 64) - 1) / (WG / 64))), dim3(WG),
@@ -1103,21 +1231,69 @@ hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int6
   if (phase == 0) {
     const dim3 g2((unsigned)((ntiles + 1) / 2), (unsigned)((B + cw - 1) / cw));
     if (cw == 64)
-      hipLaunchKernelGGL((k_scan_reduce<Tin, Tout, 64>), g2, dim3(WG), 0, s, d, segi, cw, (const Tin*)x, ldx, B,
-                         ntiles, A);
+      hipLaunchKernelGGL((k_scan_reduce<Tin, Tout, 64, false>), g2, dim3(WG), 0, s, d, segi, cw, (const Tin*)x,
+                         ldx, B, ntiles, A, dir, (const uint64_t*)nullptr, (const int32_t*)nullptr, (Tout*)nullptr);
     else
-      hipLaunchKernelGGL((k_scan_reduce<Tin, Tout, 0>), g2, dim3(WG), 0, s, d, segi, cw, (const Tin*)x, ldx, B,
-                         ntiles, A);
+      hipLaunchKernelGGL((k_scan_reduce<Tin, Tout, 0, false>), g2, dim3(WG), 0, s, d, segi, cw, (const Tin*)x,
+                         ldx, B, ntiles, A, dir, (const uint64_t*)nullptr, (const int32_t*)nullptr, (Tout*)nullptr);
   } else if (phase == 1) {
-    hipLaunchKernelGGL((k_scan_carry<St, Tout>), dim3((unsigned)d.nchains, (unsigned)((B + 15) / 16)), dim3(WG), 0,
-                       s, d, segi, dir, B, (const St*)A, C, (Tout*)P);
+    hipLaunchKernelGGL((k_scan_carry<St, Tout, false>), dim3((unsigned)d.nchains, (unsigned)((B + 15) / 16)),
+                       dim3(WG), 0, s, d, segi, dir, B, (const St*)A, C, (Tout*)P, (const int32_t*)nullptr,
+                       (const int32_t*)nullptr, (const Tout*)nullptr, 0);
   } else if (cw == 64) {
-    hipLaunchKernelGGL((k_scan_apply<Tin, Tout, 64>), g, dim3(WG), 0, s, d, segi, cw, dir, (const Tin*)x, ldx, B,
-                       (const St*)C, (Tout*)P);
+    hipLaunchKernelGGL((k_scan_apply<Tin, Tout, 64, 0, Tout>), g, dim3(WG), 0, s, d, segi, cw, dir, (const Tin*)x,
+                       ldx, B, (const St*)C, (Tout*)P, (const int32_t*)nullptr, (const Tout*)nullptr, 0,
+                       (const Tout*)nullptr, 0);
   } else {
-    hipLaunchKernelGGL((k_scan_apply<Tin, Tout, 0>), g, dim3(WG), 0, s, d, segi, cw, dir, (const Tin*)x, ldx, B,
-                       (const St*)C, (Tout*)P);
+    hipLaunchKernelGGL((k_scan_apply<Tin, Tout, 0, 0, Tout>), g, dim3(WG), 0, s, d, segi, cw, dir, (const Tin*)x,
+                       ldx, B, (const St*)C, (Tout*)P, (const int32_t*)nullptr, (const Tout*)nullptr, 0,
+                       (const Tout*)nullptr, 0);
   }
+  return hipGetLastError();
+}
+
+// Workgroups per (chain, 16 columns) of the compact carry: each completes a
+// quarter of the chain's gathered rows.
+constexpr int kCarrySplit = 4;
+
+template <typename Tin, typename Tout, int MODE, typename Tres>
+hipError_t compact_typed(const DevPoset& d, int dir, const void* x, int64_t ldx, void* out, int64_t ldo,
+                         const void* resid, int64_t ldr, int64_t B, void* aux, int64_t ntiles, void* lq,
+                         void* snaps, LaunchHook* hook, hipStream_t s) {
+  using St = typename ScanTraits<Tin, Tout>::St;
+  const WalkTables& w = d.walk[dir > 0 ? 0 : 1];
+  const int segi = seg_index(64);
+  St* A = (St*)aux;
+  St* C = A + ntiles * B;
+  Tout* L = (Tout*)lq;
+  Tout* Q = L + (int64_t)w.nslots * B;
+  const unsigned ncb = (unsigned)((B + 63) / 64);
+  if (hook) hook->before(0, s);
+  hipLaunchKernelGGL((k_scan_reduce<Tin, Tout, 64, true>), dim3((unsigned)((ntiles + 1) / 2), ncb), dim3(WG), 0, s,
+                     d, segi, 64, (const Tin*)x, ldx, B, ntiles, A, dir, w.tmask, w.qoff, L);
+  if (hook) hook->after(0, s);
+  if (hook) hook->before(1, s);
+  hipLaunchKernelGGL((k_scan_carry<St, Tout, true>),
+                     dim3((unsigned)d.nchains, (unsigned)((B + 15) / 16), (unsigned)kCarrySplit), dim3(WG), 0, s, d,
+                     segi, dir, B, (const St*)A, C, Q, w.qoff, w.tile_of_slot, (const Tout*)L, w.nslots);
+  if (hook) hook->after(1, s);
+  if (hook) hook->before(2, s);
+  {
+    const int64_t waves = (int64_t)w.nruns * ncb;
+    const dim3 g((unsigned)((waves + (WG / 64) - 1) / (WG / 64)));
+    if (((int64_t)w.nslots + 1) * B * (int64_t)sizeof(Tout) < ((int64_t)1 << 31))
+      hipLaunchKernelGGL((k_walk_events<Tout, true, true>), g, dim3(WG), 0, s, d, (const int32_t*)nullptr, w,
+                         (const Tout*)Q, B, (Tout*)snaps);
+    else
+      hipLaunchKernelGGL((k_walk_events<Tout, false, true>), g, dim3(WG), 0, s, d, (const int32_t*)nullptr, w,
+                         (const Tout*)Q, B, (Tout*)snaps);
+  }
+  if (hook) hook->after(2, s);
+  if (hook) hook->before(3, s);
+  hipLaunchKernelGGL((k_scan_apply<Tin, Tout, 64, MODE, Tres>), dim3((unsigned)ntiles, ncb), dim3(WG), 0, s, d, segi,
+                     64, dir, (const Tin*)x, ldx, B, (const St*)C, (Tout*)out, w.snap_of_row, (const Tout*)snaps,
+                     ldo, (const Tres*)resid, ldr);
+  if (hook) hook->after(3, s);
   return hipGetLastError();
 }
 
@@ -1166,6 +1342,39 @@ hipError_t launch_chain_scan_phase(int phase, const DevPoset& d, int dir, ElemTy
   if (tin == E_F32 && tout == E_F32) return scan_typed<float, float>(phase, d, dir, x, ldx, P, B, aux, ntiles, s);
   if (tin == E_F64 && tout == E_F64) return scan_typed<double, double>(phase, d, dir, x, ldx, P, B, aux, ntiles, s);
   if (tin == E_F32 && tout == E_F64) return scan_typed<float, double>(phase, d, dir, x, ldx, P, B, aux, ntiles, s);
+  return hipErrorInvalidValue;
+}
+
+bool compact_ok(const DevPoset& d, bool up, int64_t B) {
+  const WalkTables& w = d.walk[up ? 1 : 0];
+  return d.n > 0 && !d.poset_of_row && d.k <= 64 && col_width(B) == 64 && w.runs && w.tmask && w.qoff &&
+         w.init && w.snap_of_row;
+}
+
+hipError_t launch_zeta_compact(const DevPoset& d, int dir, ElemType tin, const void* x, int64_t ldx, ElemType tout,
+                               void* out, int64_t ldo, ElemType tres, const void* resid, int64_t ldr, int64_t B,
+                               void* aux, int64_t ntiles, void* lq, void* snaps, LaunchHook* hook, hipStream_t s) {
+  if (!compact_ok(d, dir < 0, B) || ntiles != d.walk[dir > 0 ? 0 : 1].qoff_tiles) return hipErrorInvalidValue;
+  if (!resid) {
+    if (tin != tout) return hipErrorInvalidValue;
+    if (tin == E_I64)
+      return compact_typed<int64_t, int64_t, 1, int64_t>(d, dir, x, ldx, out, ldo, nullptr, 0, B, aux, ntiles, lq,
+                                                         snaps, hook, s);
+    if (tin == E_F32)
+      return compact_typed<float, float, 1, float>(d, dir, x, ldx, out, ldo, nullptr, 0, B, aux, ntiles, lq, snaps,
+                                                   hook, s);
+    if (tin == E_F64)
+      return compact_typed<double, double, 1, double>(d, dir, x, ldx, out, ldo, nullptr, 0, B, aux, ntiles, lq,
+                                                      snaps, hook, s);
+    return hipErrorInvalidValue;
+  }
+  if (tin != E_F32 || tout != E_F64) return hipErrorInvalidValue;
+  if (tres == E_F32)
+    return compact_typed<float, double, 2, float>(d, dir, x, ldx, out, ldo, resid, ldr, B, aux, ntiles, lq, snaps,
+                                                  hook, s);
+  if (tres == E_F64)
+    return compact_typed<float, double, 2, double>(d, dir, x, ldx, out, ldo, resid, ldr, B, aux, ntiles, lq, snaps,
+                                                   hook, s);
   return hipErrorInvalidValue;
 }
 

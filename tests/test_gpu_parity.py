@@ -269,8 +269,12 @@ def test_grid_config2_f32_refined(px):
 
 
 # ------------------------------------------------------------ scan schedules
-SCAN_MODES = {"3phase": {}, "onepass": {"POSETX_SCAN": "onepass"},
-              "fallback": {"POSETX_SCAN": "onepass", "POSETX_LB_SPIN": "0"}}
+# "compact": the default at 64-column blocks (the scan records P only at the
+# walk's gathered rows and the combine is fused into it); the others write P
+# with the named scan and walk over it.
+SCAN_MODES = {"compact": {}, "3phase": {"POSETX_WALK": "rows"},
+              "onepass": {"POSETX_WALK": "rows", "POSETX_SCAN": "onepass"},
+              "fallback": {"POSETX_WALK": "rows", "POSETX_SCAN": "onepass", "POSETX_LB_SPIN": "0"}}
 
 
 @pytest.mark.parametrize("mode", list(SCAN_MODES))
@@ -299,6 +303,59 @@ def test_scan_schedules_grid_exact(px, mode, monkeypatch):
     f32 = T(f.astype(np.float32))
     assert np.array_equal(H(px.zeta(P, f32)), want.astype(np.float32))
     assert np.array_equal(H(px.zeta_adjoint(P, f32)), want_adj.astype(np.float32))
+
+
+# ---------------------------------------------------------- compact walk
+@pytest.mark.parametrize("shape", ["cfg0", "short_chains", "one_chain", "k64"])
+@pytest.mark.parametrize("B", [33, 64, 100])
+def test_compact_walk_matches_oracle_and_rows_walk(px, shape, B, monkeypatch):
+    """The compact walk (no P matrix) against the oracle and the walk over P.
+
+    Shapes: chains of 125 rows (two 64-row tiles, the second ragged); chains of
+    about 8 rows (every tile ragged, many slots per tile); one chain (no other
+    chain, so no gathered rows at all); 64 chains (the widest compact form).
+    B = 33 and 100 leave lanes of the last 64-column block idle.  int64 is
+    bit-exact both ways; float64 agrees to rounding.
+    """
+    p = {"cfg0": lambda: W.chain_poset(2000, 16, 4, seed=0),
+         "short_chains": lambda: W.chain_poset(400, 50, 3, seed=60),
+         "one_chain": lambda: W.chain_only(300, seed=61),
+         "k64": lambda: W.chain_poset(3000, 64, 3, seed=62)}[shape]()
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = build(px, p)
+    f = W.functions(p.n, B, "int", seed=63, lo=-10**6, hi=10**6)
+    ff = W.functions(p.n, B, "normal64", seed=64)
+    got = {}
+    for mode in ("compact", "rows"):
+        if mode == "rows":
+            monkeypatch.setenv("POSETX_WALK", "rows")
+        got[mode] = (H(px.zeta(P, T(f))), H(px.zeta_adjoint(P, T(f))),
+                     H(px.zeta(P, T(ff))), H(px.zeta_adjoint(P, T(ff))))
+    for mode, (g, a, gf, af) in got.items():
+        assert np.array_equal(g, O.zeta(R, f)), mode
+        assert np.array_equal(a, O.zeta_adjoint(R, f)), mode
+        assert rel(gf, O.zeta(R, ff, exact=False)) <= 1e-12, mode
+        assert rel(af, O.zeta_adjoint(R, ff, exact=False)) <= 1e-12, mode
+    assert P.info["walk_rows_distinct"] == 0 if shape == "one_chain" else P.info["walk_rows_distinct"] > 0
+
+
+def test_compact_walk_refinement_residual(px, monkeypatch):
+    """float32 Möbius with float64 residuals: the compact residual (fused
+    res - (P + S)) and the residual over P reach the same accuracy."""
+    p = W.chain_poset(2500, 20, 3, seed=65)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = build(px, p)
+    f = W.functions(p.n, 64, "int", seed=66, lo=-100, hi=100)
+    g32 = O.zeta(R, f).astype(np.float32)
+    v32 = O.zeta_adjoint(R, f).astype(np.float32)
+    for mode in ("compact", "rows"):
+        if mode == "rows":
+            monkeypatch.setenv("POSETX_WALK", "rows")
+        got, rep = px.mobius(P, T(g32), max_refine=8, tol=1e-8, report=True)
+        assert rel(H(got), f) <= 1e-5, (mode, rep)
+        assert rep["residual"] <= 1e-6 and not rep["nonfinite"], (mode, rep)
+        gotT, repT = px.mobius_adjoint(P, T(v32), max_refine=8, tol=1e-8, report=True)
+        assert rel(H(gotT), f) <= 1e-5, (mode, repT)
 
 
 # ------------------------------------------------------- full-size, sampled
