@@ -102,6 +102,18 @@ void seg_tables(const std::vector<int32_t>& chain_off, std::vector<int32_t>& seg
   }
 }
 
+// {first row, end row of its chain} of every 64-row tile (64-column blocks).
+std::vector<int32_t> tile64_table(const std::vector<int32_t>& chain_off) {
+  const int64_t nc = (int64_t)chain_off.size() - 1, seg = px::seg_rows(64);
+  std::vector<int32_t> t;
+  for (int64_t c = 0; c < nc; ++c)
+    for (int64_t r = chain_off[c]; r < chain_off[c + 1]; r += seg) {
+      t.push_back((int32_t)r);
+      t.push_back(chain_off[c + 1]);
+    }
+  return t;
+}
+
 // Runs of the walking gather for one niv map (see px::WalkTables).  Every chain
 // is cut into runs of at most T rows (T <= 255) and at most `emax` change
 // events, so that no wavefront's serial event work is much longer than the
@@ -504,7 +516,7 @@ struct px_poset {
   bool host_only = false, has_up = false, mirsky = false;
   int32_t *d_node_of_row = nullptr, *d_chain_of_row = nullptr, *d_chain_off = nullptr, *d_niv = nullptr,
           *d_niv_up = nullptr, *d_lev_down = nullptr, *d_lev_up = nullptr, *d_segoff = nullptr, *d_order = nullptr,
-          *d_walk[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
+          *d_tile64 = nullptr, *d_walk[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
   int64_t ntiles[7] = {0, 0, 0, 0, 0, 0, 0};
   int64_t nevents[2] = {0, 0};
   int32_t nsnap[2] = {0, 0};
@@ -527,7 +539,7 @@ struct px_batch {
   int64_t rows = 0;
   bool has_up = false;
   int32_t *d_node_of_row = nullptr, *d_chain_of_row = nullptr, *d_chain_off = nullptr, *d_niv = nullptr,
-          *d_niv_up = nullptr, *d_segoff = nullptr, *d_poset_of_row = nullptr, *d_k = nullptr, *d_row_off = nullptr,
+          *d_niv_up = nullptr, *d_segoff = nullptr, *d_tile64 = nullptr, *d_poset_of_row = nullptr, *d_k = nullptr, *d_row_off = nullptr,
           *d_order = nullptr;
   int64_t* d_niv_off = nullptr;
   int32_t* d_walk[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
@@ -541,7 +553,7 @@ namespace {
 
 void free_poset_device(px_poset* p) {
   int32_t* bufs[] = {p->d_node_of_row, p->d_chain_of_row, p->d_chain_off, p->d_niv, p->d_niv_up,
-                     p->d_lev_down,     p->d_lev_up,       p->d_segoff,    p->d_order};
+                     p->d_lev_down,     p->d_lev_up,       p->d_segoff,    p->d_order, p->d_tile64};
   for (int32_t* b : bufs)
     if (b) (void)hipFree(b);
   for (auto& dir : p->d_walk)
@@ -949,6 +961,12 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
     if (e == hipSuccess && p->has_up) e = upload(&p->d_lev_up, P.lev_up_rows.data(), P.lev_up_rows.size(), b);
     if (e == hipSuccess) e = upload(&p->d_segoff, segoff.data(), segoff.size(), b);
     if (e == hipSuccess) {
+      std::vector<int32_t> t64 = tile64_table(P.chain_off);
+      e = (int64_t)t64.size() == 2 * p->ntiles[px::seg_index(64)]
+              ? upload(&p->d_tile64, t64.data(), t64.size(), b)
+              : hipErrorInvalidValue;
+    }
+    if (e == hipSuccess) {
       std::vector<int32_t> ord = scan_orders(segoff, P.k, p->ntiles);
       e = upload(&p->d_order, ord.data(), ord.size(), b);
       int64_t o = 0;
@@ -978,6 +996,7 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
   d.niv = p->d_niv;
   d.niv_up = p->d_niv_up;
   d.segoff = p->d_segoff;
+  d.tile64 = (const int2*)p->d_tile64;
   *out = p;
   return PX_OK;
 }
@@ -1222,6 +1241,12 @@ px_status px_batch_build(int count, px_poset* const* posets, px_batch** out) {
   if (e == hipSuccess && has_up) e = upload(&b->d_niv_up, niv_up.data(), niv_up.size(), bytes);
   if (e == hipSuccess) e = upload(&b->d_segoff, segoff.data(), segoff.size(), bytes);
   if (e == hipSuccess) {
+    std::vector<int32_t> t64 = tile64_table(chain_off);
+    e = (int64_t)t64.size() == 2 * b->ntiles[px::seg_index(64)]
+            ? upload(&b->d_tile64, t64.data(), t64.size(), bytes)
+            : hipErrorInvalidValue;
+  }
+  if (e == hipSuccess) {
     std::vector<int32_t> ord = scan_orders(segoff, chains, b->ntiles);
     e = upload(&b->d_order, ord.data(), ord.size(), bytes);
     int64_t o = 0;
@@ -1288,6 +1313,7 @@ px_status px_batch_build(int count, px_poset* const* posets, px_batch** out) {
   d.niv = b->d_niv;
   d.niv_up = b->d_niv_up;
   d.segoff = b->d_segoff;
+  d.tile64 = (const int2*)b->d_tile64;
   d.niv_off = b->d_niv_off;
   d.poset_of_row = b->d_poset_of_row;
   d.k_of_poset = b->d_k;
@@ -1300,7 +1326,8 @@ px_status px_batch_free(px_batch* b) {
   if (!b) return PX_OK;
   DeviceGuard dg(b->device);
   int32_t* bufs[] = {b->d_node_of_row, b->d_chain_of_row, b->d_chain_off, b->d_niv,     b->d_niv_up,
-                     b->d_segoff,      b->d_poset_of_row,  b->d_k,         b->d_row_off, b->d_order};
+                     b->d_segoff,      b->d_poset_of_row,  b->d_k,         b->d_row_off, b->d_order,
+                     b->d_tile64};
   for (int32_t* q : bufs)
     if (q) (void)hipFree(q);
   if (b->d_niv_off) (void)hipFree(b->d_niv_off);

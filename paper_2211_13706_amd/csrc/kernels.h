@@ -60,6 +60,7 @@ struct DevPoset {
   const int32_t* niv = nullptr;         // [n*k] or, for a batch, at niv_off[poset]
   const int32_t* niv_up = nullptr;
   const int32_t* segoff = nullptr;      // [7][nchains+1] tile offsets per tile height
+  const int2* tile64 = nullptr;         // 64-row tiles: {first row, end row of its chain} (nullable)
   // tables of the walking gather, [0] for niv (zeta), [1] for the up-niv map
   WalkTables walk[2];
   // single-pass scan: tiles in scan-position-major order, [0] prefix / [1] suffix,

@@ -37,6 +37,8 @@ int seg_rows(int cw) { return (WG / cw) * RPT; }
 
 namespace {
 
+constexpr int reduce_tiles(int cwt) { return cwt == 64 ? 1 : 2; }
+
 // ------------------------------------------------------------------ scan state
 // Wrapping 64-bit integer sum (two's complement modulo 2^64).
 struct StateI {
@@ -110,13 +112,19 @@ __device__ inline int find_chain(const int32_t* so, int nchains, int t) {
 }
 
 // Phase 1: per tile and column, the compensated total of the tile's rows.  A
-// workgroup reduces two tiles, so that each thread has 2*RPT loads in flight.
+// workgroup reduces reduce_tiles(CWT) tiles: two for narrow column blocks, so
+// that each thread has 2*RPT loads in flight; one for 64-column blocks, whose
+// tile rows come from one scalar table load (measured faster at n = 2^20).
 // With CWT = 64 a row group is one wavefront, so its row (and node) indices
 // are wave-uniform and live in scalar registers.
 //
 // MARK (compact walk, 64-column blocks): also the tile-local prefix (from the
 // tile's first row in scan order) at every gathered row, into L[slot].  Rows
 // of a tile are marked in tmask[t]; their slots are consecutive from qoff[t].
+// Each wavefront sums its rows in scan order and keeps its running sum at its
+// first MK marked rows in LDS; after the barrier each of them is combined with
+// the sum of the row groups before it.  A wavefront with more marks (rare)
+// sums its rows again for the rest.
 template <typename Tin, typename Tout, int CWT, bool MARK>
 __global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw_rt, const Tin* __restrict__ x,
                                                     int64_t ldx, int64_t B, int64_t ntiles,
@@ -126,7 +134,7 @@ __global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw
   using Tr = ScanTraits<Tin, Tout>;
   using St = typename Tr::St;
   static_assert(!MARK || CWT == 64, "marked rows need wave-uniform row groups");
-  constexpr int NT = 2;
+  constexpr int NT = reduce_tiles(CWT);
   const int cw = CWT ? CWT : cw_rt;
   __shared__ St sm[NT][WG];
   const int32_t* so = d.segoff + (int64_t)segi * (d.nchains + 1);
@@ -137,12 +145,24 @@ __global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw
   const int64_t col = (int64_t)blockIdx.y * cw + lane;
   const int64_t colc = col < B ? col : 0;
   int64_t r0[NT], end[NT];
+  uint64_t tm[NT];  // MARK: the tiles' marks and first slots, loaded with the rows
+  int qo[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
     const int t = min((int64_t)blockIdx.x * NT + q, ntiles - 1);
-    const int c = find_chain(so, d.nchains, t);
-    r0[q] = d.chain_off[c] + (int64_t)(t - so[c]) * seg + (int64_t)rg * RPT;
-    end[q] = d.chain_off[c + 1];
+    if (MARK) {
+      tm[q] = tmask[t];
+      qo[q] = qoff[t];
+    }
+    if (CWT == 64 && d.tile64) {  // one scalar load instead of a search over the chains
+      const int2 tr = d.tile64[t];
+      r0[q] = tr.x + (int64_t)rg * RPT;
+      end[q] = tr.y;
+    } else {
+      const int c = find_chain(so, d.nchains, t);
+      r0[q] = d.chain_off[c] + (int64_t)(t - so[c]) * seg + (int64_t)rg * RPT;
+      end[q] = d.chain_off[c + 1];
+    }
   }
   // row indices first, then every load unconditionally (rows clamped into the
   // chain, columns into the matrix), so that all loads are in flight together
@@ -159,13 +179,34 @@ __global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw
   for (int q = 0; q < NT; ++q)
 #pragma unroll
     for (int i = 0; i < RPT; ++i) v[q][i] = x[(int64_t)nodes[q][i] * ldx + colc];
+  // MARK: this wavefront's marked rows (bits of its RPT rows, scalar)
+  constexpr int MK = 4;
+  __shared__ St lm[MARK ? NT * MK : 1][WG];
+  uint32_t wm[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q)
+    wm[q] = (MARK && (int64_t)blockIdx.x * NT + q < ntiles) ? (uint32_t)(tm[q] >> (rg * RPT)) & ((1u << RPT) - 1)
+                                                          : 0u;
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
     St st;
     st.zero();
-#pragma unroll
-    for (int i = 0; i < RPT; ++i)
+    int m = 0;
+    // MARK sums in scan order (dir < 0: from the top) and keeps the running sum at marks
+    auto step = [&](int i) {
       if (r0[q] + i < end[q]) st.add(Tr::in(v[q][i]));
+      if (MARK && ((wm[q] >> i) & 1)) {
+        if (m < MK) lm[q * MK + m][threadIdx.x] = st;
+        ++m;
+      }
+    };
+    if (MARK && dir < 0) {
+#pragma unroll
+      for (int i = RPT - 1; i >= 0; --i) step(i);
+    } else {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) step(i);
+    }
     sm[q][threadIdx.x] = st;
   }
   __syncthreads();
@@ -173,36 +214,41 @@ __global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw
     constexpr int RG = WG / 64;
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
-      const int64_t t = (int64_t)blockIdx.x * NT + q;
-      if (t >= ntiles) continue;
-      // the tile's marks: scalar; this wavefront's rows are bits [rg*RPT, rg*RPT + RPT)
-      const uint64_t mask = tmask[t];
-      const uint32_t wm = (uint32_t)(mask >> (rg * RPT)) & ((1u << RPT) - 1);
-      if (wm == 0) continue;
-      const int below = __popcll(mask & ((uint64_t(1) << (rg * RPT)) - 1));
-      St pre;
-      pre.zero();
+      if (wm[q] == 0) continue;
+      const int nm = __popc(wm[q]);
+      // slots of this wavefront's marks, in scan order: from first, by sgn
+      const int below = __popcll(tm[q] & ((uint64_t(1) << (rg * RPT)) - 1));
+      const int first = dir > 0 ? qo[q] + below : qo[q] + below + nm - 1;
+      const int sgn = dir > 0 ? 1 : -1;
+      St base;  // the row groups before this one in scan order
+      base.zero();
       if (dir > 0) {
-        int sl = qoff[t] + below;
-        for (int g = 0; g < rg; ++g) pre.combine(sm[q][g * 64 + lane]);
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-          if (r0[q] + i < end[q]) pre.add(Tr::in(v[q][i]));
-          if ((wm >> i) & 1) {
-            if (col < B) L[(int64_t)sl * B + col] = Tr::out(pre.value());
-            ++sl;
-          }
-        }
+        for (int g = 0; g < rg; ++g) base.combine(sm[q][g * 64 + lane]);
       } else {
-        int sl = qoff[t] + below + __popc(wm) - 1;
-        for (int g = RG - 1; g > rg; --g) pre.combine(sm[q][g * 64 + lane]);
-#pragma unroll
-        for (int i = RPT - 1; i >= 0; --i) {
+        for (int g = RG - 1; g > rg; --g) base.combine(sm[q][g * 64 + lane]);
+      }
+      for (int m = 0; m < min(nm, MK); ++m) {
+        St pre = base;
+        pre.combine(lm[q * MK + m][threadIdx.x]);
+        if (col < B) __builtin_nontemporal_store(Tr::out(pre.value()), &L[(int64_t)(first + sgn * m) * B + col]);
+      }
+      if (nm > MK) {
+        St pre = base;
+        int m = 0;
+        auto step = [&](int i) {
           if (r0[q] + i < end[q]) pre.add(Tr::in(v[q][i]));
-          if ((wm >> i) & 1) {
-            if (col < B) L[(int64_t)sl * B + col] = Tr::out(pre.value());
-            --sl;
+          if ((wm[q] >> i) & 1) {
+            if (m >= MK && col < B)
+              __builtin_nontemporal_store(Tr::out(pre.value()), &L[(int64_t)(first + sgn * m) * B + col]);
+            ++m;
           }
+        };
+        if (dir < 0) {
+#pragma unroll
+          for (int i = RPT - 1; i >= 0; --i) step(i);
+        } else {
+#pragma unroll
+          for (int i = 0; i < RPT; ++i) step(i);
         }
       }
     }
@@ -252,7 +298,30 @@ __global__ __launch_bounds__(WG) void k_scan_carry(DevPoset d, int segi, int dir
   const int t0 = so[c], t1 = so[c + 1], nt = t1 - t0;
   St carry;
   carry.zero();
+  constexpr int U = 8;  // MARK: slots completed per thread and batch, loads in flight together
   for (int w0 = 0; w0 < nt; w0 += WIN) {
+    // MARK: this workgroup's share [a0, a0 + cnt / CB) of the window's slots; the
+    // first batch of their tiles and L values loads together with the window
+    int a0 = 0, cnt = 0;
+    int ti[U];
+    Tout lv[U];
+    auto load_batch = [&](int x0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int x = min(x0 + u * WG, cnt - 1);
+        ti[u] = tile_of_slot[a0 + x / CB];
+        lv[u] = L[(int64_t)(a0 + x / CB) * B + (col < B ? col : 0)];
+      }
+    };
+    if constexpr (MARK) {
+      const int wn = min(WIN, nt - w0);
+      const int tlo = dir > 0 ? t0 + w0 : t1 - w0 - wn;  // the window's tiles in index order
+      const int s0 = qoff[tlo], s1 = qoff[tlo + wn];
+      const int per = (s1 - s0 + (int)gridDim.z - 1) / (int)gridDim.z;
+      a0 = s0 + (int)blockIdx.z * per;
+      cnt = max(min(s1, a0 + per) - a0, 0) * CB;
+      if ((int)threadIdx.x < cnt) load_batch(threadIdx.x);
+    }
     for (int x = threadIdx.x; x < WIN * CB; x += WG) {
       const int i = w0 + x / CB;
       const int64_t cc = c0 + x % CB;
@@ -281,24 +350,9 @@ __global__ __launch_bounds__(WG) void k_scan_carry(DevPoset d, int segi, int dir
     for (int g = 0; g < NS; ++g) carry.combine(tot[g * CB + lc]);
     if constexpr (MARK) {
       __syncthreads();
-      // tiles of the window (tile index order) and their slots
-      const int wn = min(WIN, nt - w0);
-      const int tlo = dir > 0 ? t0 + w0 : t1 - w0 - wn;
-      const int s0 = qoff[tlo], s1 = qoff[tlo + wn];
-      const int per = (s1 - s0 + (int)gridDim.z - 1) / (int)gridDim.z;
-      const int a0 = s0 + (int)blockIdx.z * per, a1 = min(s1, a0 + per);
-      const int cnt = max(a1 - a0, 0) * CB;
-      constexpr int U = 4;
+      // Q[slot] = carry of the slot's tile (in sh) + L[slot]
       for (int x0 = threadIdx.x; x0 < cnt; x0 += WG * U) {
-        int sl[U], ti[U];
-        Tout lv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int x = min(x0 + u * WG, cnt - 1);
-          sl[u] = a0 + x / CB;
-          ti[u] = tile_of_slot[sl[u]];
-          lv[u] = L[(int64_t)sl[u] * B + (col < B ? col : 0)];
-        }
+        if (x0 != (int)threadIdx.x) load_batch(x0);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int x = x0 + u * WG;
@@ -306,7 +360,7 @@ __global__ __launch_bounds__(WG) void k_scan_carry(DevPoset d, int segi, int dir
             const int i = (dir > 0 ? ti[u] - t0 : t1 - 1 - ti[u]) - w0;  // position in the window
             St q = sh[i * CB + lc];
             q.add((decltype(q.value()))lv[u]);
-            P[(int64_t)sl[u] * B + col] = (Tout)q.value();
+            P[(int64_t)(a0 + x / CB) * B + col] = (Tout)q.value();
           }
         }
       }
@@ -339,12 +393,18 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
   using Tv = decltype(Tr::in(Tin()));
   __shared__ St sm[WG];
   const int t = blockIdx.x;
-  const int32_t* so = d.segoff + (int64_t)segi * (d.nchains + 1);
-  const int c = find_chain(so, d.nchains, t);
   const int RG = WG / cw;
-  const int seg = RG * RPT;
-  const int64_t base = d.chain_off[c] + (int64_t)(t - so[c]) * seg;
-  const int64_t end = d.chain_off[c + 1];
+  int64_t base, end;
+  if (CWT == 64 && d.tile64) {  // one scalar load instead of a search over the chains
+    const int2 tr = d.tile64[t];
+    base = tr.x;
+    end = tr.y;
+  } else {
+    const int32_t* so = d.segoff + (int64_t)segi * (d.nchains + 1);
+    const int c = find_chain(so, d.nchains, t);
+    base = d.chain_off[c] + (int64_t)(t - so[c]) * (RG * RPT);
+    end = d.chain_off[c + 1];
+  }
   // with 64-wide column blocks the row group is the wavefront index: uniform
   const int lane = threadIdx.x % cw;
   const int rg = CWT == 64 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64)) : (int)(threadIdx.x / cw);
@@ -360,13 +420,16 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
   Tin raw[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) raw[i] = __builtin_nontemporal_load(&x[(int64_t)nodes[i] * ldx + colc]);
+  // MODE != 0: the rows' snapshots; consecutive rows mostly share one, which
+  // is loaded once (scalar tests) and copied once the loads have returned
   Tout sv[MODE ? RPT : 1];
+  int32_t sn[MODE ? RPT : 1];
   if constexpr (MODE != 0) {
-    int32_t sn[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) sn[i] = __builtin_amdgcn_readfirstlane(snap_of_row[min(r0 + i, end - 1)]);
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) sv[i] = (S + (int64_t)sn[i] * B)[colc];
+    for (int i = 0; i < RPT; ++i)
+      if (i == 0 || sn[i] != sn[i - 1]) sv[i] = (S + (int64_t)sn[i] * B)[colc];
   }
   // row i's result: P[r] itself, or the combined zeta value / residual
   auto put = [&](int i, const St& st) {
@@ -397,6 +460,11 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
   sm[threadIdx.x] = loc;
   __syncthreads();
   if (col >= B) return;
+  if constexpr (MODE != 0) {
+#pragma unroll
+    for (int i = 1; i < RPT; ++i)
+      if (sn[i] == sn[i - 1]) sv[i] = sv[i - 1];
+  }
   St st = C[(int64_t)t * B + col];
   if (dir > 0) {
     for (int g = 0; g < rg; ++g) st.combine(sm[g * cw + lane]);
@@ -1229,7 +1297,8 @@ hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int6
   St* C = A + ntiles * B;
   dim3 g((unsigned)ntiles, (unsigned)((B + cw - 1) / cw));
   if (phase == 0) {
-    const dim3 g2((unsigned)((ntiles + 1) / 2), (unsigned)((B + cw - 1) / cw));
+    const int nt = reduce_tiles(cw == 64 ? 64 : 0);
+    const dim3 g2((unsigned)((ntiles + nt - 1) / nt), (unsigned)((B + cw - 1) / cw));
     if (cw == 64)
       hipLaunchKernelGGL((k_scan_reduce<Tin, Tout, 64, false>), g2, dim3(WG), 0, s, d, segi, cw, (const Tin*)x,
                          ldx, B, ntiles, A, dir, (const uint64_t*)nullptr, (const int32_t*)nullptr, (Tout*)nullptr);
@@ -1269,7 +1338,7 @@ hipError_t compact_typed(const DevPoset& d, int dir, const void* x, int64_t ldx,
   Tout* Q = L + (int64_t)w.nslots * B;
   const unsigned ncb = (unsigned)((B + 63) / 64);
   if (hook) hook->before(0, s);
-  hipLaunchKernelGGL((k_scan_reduce<Tin, Tout, 64, true>), dim3((unsigned)((ntiles + 1) / 2), ncb), dim3(WG), 0, s,
+  hipLaunchKernelGGL((k_scan_reduce<Tin, Tout, 64, true>), dim3((unsigned)((ntiles + reduce_tiles(64) - 1) / reduce_tiles(64)), ncb), dim3(WG), 0, s,
                      d, segi, 64, (const Tin*)x, ldx, B, ntiles, A, dir, w.tmask, w.qoff, L);
   if (hook) hook->after(0, s);
   if (hook) hook->before(1, s);
