@@ -358,6 +358,36 @@ def test_compact_walk_refinement_residual(px, monkeypatch):
         assert rel(H(gotT), f) <= 1e-5, (mode, repT)
 
 
+# ------------------------------------------------------------ Möbius shapes
+@pytest.mark.parametrize("shape", ["cfg0", "mirsky", "long_chains", "grid"])
+@pytest.mark.parametrize("B", [1, 40, 64])
+def test_mobius_shapes_exact_and_backward_stable(px, shape, B):
+    """Möbius and its adjoint against the substitution oracle on level
+    schedules of different shapes: cfg0; the Mirsky schedule (one row per chain
+    and level); 4 long chains with few cross edges; a 96 x 16 grid (whole chains
+    per level).  int64 is exact.  float64 on zeta images: the solve is backward
+    stable (residual at rounding level); the forward error carries the inputs'
+    own float64 rounding amplified by the Möbius transform (about 1e-9 here).
+    """
+    p = {"cfg0": lambda: W.chain_poset(2000, 16, 4, seed=0),
+         "mirsky": lambda: W.chain_poset(600, 8, 3, seed=70),
+         "long_chains": lambda: W.chain_poset(1200, 4, 1, seed=71),
+         "grid": lambda: W.grid_poset(96, 16)}[shape]()
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = build(px, p, flags=px.PX_BUILD_LEVELS_MIRSKY if shape == "mirsky" else 0)
+    g = W.functions(p.n, B, "int", seed=72, lo=-1000, hi=1000)
+    assert np.array_equal(H(px.mobius(P, T(g))), O.mobius_by_substitution(R, g))
+    assert np.array_equal(H(px.mobius_adjoint(P, T(g))), O.mobius_adjoint_by_substitution(R, g))
+    f64 = W.functions(p.n, B, "normal64", seed=73)
+    z64, zt64 = O.zeta(R, f64, exact=False), O.zeta_adjoint(R, f64, exact=False)
+    mf, maf = H(px.mobius(P, T(z64))), H(px.mobius_adjoint(P, T(zt64)))
+    assert rel(O.zeta(R, mf, exact=False), z64) <= 1e-12
+    assert rel(O.zeta_adjoint(R, maf, exact=False), zt64) <= 1e-12
+    assert rel(mf, f64) <= 1e-8 and rel(maf, f64) <= 1e-8
+    f = W.functions(p.n, B, "int", seed=74, lo=-100, hi=100)
+    assert np.array_equal(H(px.mobius(P, px.zeta(P, T(f)))), f)
+
+
 # ------------------------------------------------------- full-size, sampled
 @pytest.fixture(scope="module")
 def cfg1():
