@@ -108,6 +108,25 @@ def traffic_for(phase: str):
     return t.get("per_launch_bytes", {}).get(phase)
 
 
+def measured_copy_gbps(dev, mib: int = 256, reps: int = 10) -> float:
+    """Read + write bandwidth of a plain device-to-device copy of `mib` MiB (torch), timed with
+    HIP events: the practical streaming rate that the roofline is also compared against."""
+    import torch
+    a = torch.empty(mib << 18, dtype=torch.float32, device=dev).normal_()
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return round(2 * (mib << 20) / t / 1e9, 1)
+
+
 def cpu_baseline(p, f, budget_s: float):
     """The oracle as it stands (BFS over each sampled element's down-set, float64 sums),
     on a bounded sample of elements of the same workload."""
@@ -150,7 +169,9 @@ def legs_config1(px, P, p, dev, steps):
     out["zeta_int64"] = {"ms": round(t * 1e3, 4), "node_rhs_per_s": p.n * B / t}
     t = _time(lambda: px.mobius(P, gi, out=fb), max(2, steps // 4), sync)
     out["mobius_int64"] = {"ms": round(t * 1e3, 4), "node_rhs_per_s": p.n * B / t,
-                           "levels": P.info["levels_down"], "roundtrip_exact": bool(torch.equal(fb, fi))}
+                           "levels": P.info["levels_down"],
+                           "us_per_level": round(t * 1e6 / max(1, P.info["levels_down"]), 2),
+                           "roundtrip_exact": bool(torch.equal(fb, fi))}
     del fi, gi, fb
     ff = torch.from_numpy(W.functions(p.n, B, "normal", seed=4)).to(dev)
     ga = torch.empty_like(ff)
@@ -181,8 +202,15 @@ def leg_grid(px, dev, steps, refine=3):
     # agreement of the refined float32 result with the float64 solve, normwise per column
     f64m = torch.cat(f64, dim=1)
     err = ((f.double() - f64m).abs().amax(0) / f64m.abs().amax(0)).max().item()
+    # one exact int64 solve: the time per level of the schedule
+    gi = torch.from_numpy(W.functions(q.n, Bg, "int", seed=11, lo=-1000, hi=1000)).to(dev)
+    fi = torch.empty_like(gi)
+    G.reserve(torch.int64, Bg)
+    ti = _time(lambda: px.mobius(G, gi, out=fi), steps, sync)
     return {"workload": "grid 4096x64 (n=262144, k=64), B=16 float32 U(-1,1)",
             "levels": G.info["levels_down"], "mirsky_levels": G.info["mirsky_levels"],
+            "int64_mobius_ms": round(ti * 1e3, 4),
+            "us_per_level": round(ti * 1e6 / max(1, G.info["levels_down"]), 2),
             "f32_refined_ms": round(t32 * 1e3, 4), "refine_steps": refine,
             "f64_single_rhs_x16_ms": round(t64 * 1e3, 4), "speedup": round(t64 / t32, 2),
             "rel_err_vs_f64": err, "report": rep}
@@ -223,10 +251,17 @@ def leg_batched(px, dev, steps, count=512):
         px.zeta_adjoint_batched(bt, w, out=gw)
     t_graph = _time(graph.replay, steps, sync)
     ok = bool(torch.allclose(gw, f.grad, rtol=0, atol=0))
+    # compulsory bytes of forward + adjoint: per direction the niv map (4k B per row)
+    # and f, P written, P read and g (4 B per row and RHS each)
+    nk = sum(int(P.n) * int(P.k) for P in Ps)
+    alg = 2 * (4 * nk + 4 * 4 * int(bt.rows) * Bb)
+    floor_ms = alg / (HBM_PEAK_GBS * 1e9) * 1e3
     return {"workload": f"{count} posets, n log-uniform in [1000, 65536], k in 4..128, B=8 float32",
             "rows": int(bt.rows), "preprocess_s": round(t_prep, 2),
             "autograd_fwd_bwd_ms": round(t_eager * 1e3, 4), "graph_fwd_adj_ms": round(t_graph * 1e3, 4),
-            "node_rhs_per_s_graph": 2 * bt.rows * Bb / t_graph, "graph_grad_equal_eager": ok}
+            "node_rhs_per_s_graph": 2 * bt.rows * Bb / t_graph, "graph_grad_equal_eager": ok,
+            "alg_bytes": alg, "hbm_floor_ms": round(floor_ms, 4),
+            "frac_of_floor": round(floor_ms / (t_graph * 1e3), 4)}
 
 
 def leg_large(px, dev, steps):
@@ -253,10 +288,13 @@ def leg_large(px, dev, steps):
     gi = px.zeta(L, fi)
     tm = _time(lambda: px.mobius(L, gi), 2, sync)
     exact = bool(torch.equal(px.mobius(L, gi), fi))
+    exact_adj = bool(torch.equal(px.mobius_adjoint(L, px.zeta_adjoint(L, fi)), fi))
     return {"workload": "n=8388608, k=32, 3 cross edges, B=16", "preprocess_s": round(t_prep, 2),
             "levels": L.info["levels_down"], "zeta_f32_ms": round(tz * 1e3, 4),
             "zeta_node_rhs_per_s": q.n * Bl / tz, "mobius_int64_ms": round(tm * 1e3, 4),
-            "int64_roundtrip_exact": exact, "f32_roundtrip_rel_err": err, "f32_refine_report": rep}
+            "us_per_level": round(tm * 1e6 / max(1, L.info["levels_down"]), 2),
+            "int64_roundtrip_exact": exact, "int64_adjoint_roundtrip_exact": exact_adj,
+            "f32_roundtrip_rel_err": err, "f32_refine_report": rep}
 
 
 def main():
@@ -325,6 +363,7 @@ def main():
     dt_prof = time.perf_counter() - t1
     prof = profile_read(lib)
     lib.px_profile(0)
+    copy_gbps = measured_copy_gbps(dev)
 
     ms_step = dt * 1e3 / args.steps
     value = p.n * B / (dt / args.steps)
@@ -371,6 +410,7 @@ def main():
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr,
                      "alg_bytes_per_launch": phases[dom]["alg_bytes"],
                      "gathered_GBps": phases[dom].get("gathered_GBps"),
+                     "copy_GBps": copy_gbps, "frac_of_copy": round(ach / copy_gbps, 4),
                      "traffic_GBps": round(tr / (phases[dom]["avg_ms"] * 1e-3) / 1e9, 1) if tr else None},
         "step_roofline": {"alg_bytes": step_bytes, "GBps": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
                           "frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

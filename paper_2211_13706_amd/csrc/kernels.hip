@@ -916,7 +916,10 @@ __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* _
 // Lane-split form (any B <= 64, batches of posets, any k): a wavefront runs
 // 64/cw runs side by side, cw lanes (columns) each; every lane follows its own
 // run's events with per-lane predication.  The own-chain entry of the first
-// row is the row itself, which identifies it without chain numbers.
+// row is the row itself, which identifies it without chain numbers.  As in the
+// uniform form, XCD x takes a contiguous slice of the runs: for a batch, whose
+// runs are poset after poset, each XCD's L2 then holds the P rows of the few
+// posets it is working on instead of all of them.
 template <typename TP>
 __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int32_t* __restrict__ nv, WalkTables w,
                                                           int cw, const TP* __restrict__ P, int64_t B,
@@ -924,7 +927,10 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
   using W = typename Wide<TP>::W;
   const int lane = threadIdx.x & 63;
   const int nsub = 64 / cw;
-  const int64_t run = ((int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6)) * nsub + lane / cw;
+  const int nblk = (int)gridDim.x, q8 = nblk >> 3, r8 = nblk & 7;
+  const int xcd = (int)(blockIdx.x & 7), slot = (int)(blockIdx.x >> 3);
+  const int blk = xcd * q8 + min(xcd, r8) + slot;
+  const int64_t run = ((int64_t)blk * (WG / 64) + (threadIdx.x >> 6)) * nsub + lane / cw;
   const int col = lane % cw;
   const bool active = run < w.nruns;
   const bool colok = active && col < B;
@@ -947,19 +953,43 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
   for (int off = 32; off >= 1; off >>= 1) kmax = max(kmax, __shfl_xor(kmax, off));
 
   W acc = W(0);
-  for (int j0 = 0; j0 < kmax; j0 += 16) {
-    TP v[16];
-    bool ok[16];
+  if (cw >= 8) {
+    // the first row's entries 16 at a time, two per lane of the run's group,
+    // shared by lane shuffles; the next 16 load with this group's gathers
+    const int sub = lane % cw, base = lane - sub, s8 = sub & 7;
+    auto ent = [&](int j) { return j < k ? nr[j] : -1; };
+    int ta = ent(s8), tb = ent(8 + s8);
+    for (int j0 = 0; j0 < kmax; j0 += 16) {
+      const int na = ent(j0 + 16 + s8), nb = ent(j0 + 24 + s8);
+      TP v[16];
+      bool ok[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int j = j0 + u;
-      const int t = j < k ? nr[j] : -1;
-      ok[u] = t >= 0 && t != r0;
-      v[u] = P[(int64_t)(ok[u] ? t : r0) * B + colc];
+      for (int u = 0; u < 16; ++u) {
+        const int t = __shfl(u < 8 ? ta : tb, base + (u & 7));
+        ok[u] = t >= 0 && t != r0;
+        v[u] = P[(int64_t)(ok[u] ? t : r0) * B + colc];
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (ok[u]) acc += (W)v[u];
+      ta = na;
+      tb = nb;
     }
+  } else {
+    for (int j0 = 0; j0 < kmax; j0 += 16) {
+      TP v[16];
+      bool ok[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
-      if (ok[u]) acc += (W)v[u];
+      for (int u = 0; u < 16; ++u) {
+        const int j = j0 + u;
+        const int t = j < k ? nr[j] : -1;
+        ok[u] = t >= 0 && t != r0;
+        v[u] = P[(int64_t)(ok[u] ? t : r0) * B + colc];
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (ok[u]) acc += (W)v[u];
+    }
   }
   int64_t m = w.snap_off[runc];
   const int64_t mlast = w.snap_off[runc + 1] - 1;
@@ -970,6 +1000,47 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
   int nemax = ne;
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) nemax = max(nemax, __shfl_xor(nemax, off));
+  if (cw >= 8) {
+    // Groups of 16 events: lane j of the run's cw lanes loads records j & 7 and
+    // 8 + (j & 7) (two loads for the group), the fields go round the group by
+    // lane shuffles, and the next group's records load while this group's 32
+    // gathers are in flight.
+    const int sub = lane % cw, base = lane - sub, s8 = sub & 7;
+    const int4 none = make_int4(-1, -1, -1, 0);
+    auto rec = [&](int i) { return i < ne ? w.ev[e0 + i] : none; };
+    int4 ra = rec(s8), rb = rec(8 + s8);
+    for (int g0 = 0; g0 < nemax; g0 += 16) {
+      const int4 na = rec(g0 + 16 + s8), nb = rec(g0 + 24 + s8);
+      TP vn[16], vo[16];
+      bool okn[16], oko[16];
+      int ue[17];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int4& r = q < 8 ? ra : rb;
+        const int ex = __shfl(r.x, base + (q & 7)), ey = __shfl(r.y, base + (q & 7));
+        ue[q] = __shfl(r.z, base + (q & 7)) >> 8;  // -1: no event
+        okn[q] = ex >= 0;
+        oko[q] = ey >= 0;
+        vn[q] = P[(int64_t)(okn[q] ? ex : r0) * B + colc];
+        vo[q] = P[(int64_t)(oko[q] ? ey : r0) * B + colc];
+      }
+      ue[16] = __shfl(na.z, base) >> 8;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        if (ue[q] >= 0) {
+          if (okn[q]) acc += (W)vn[q];
+          if (oko[q]) acc -= (W)vo[q];
+          if (ue[q + 1] != ue[q]) {
+            m = min(m + 1, mlast);
+            if (colok) S[m * B + col] = (TP)acc;
+          }
+        }
+      }
+      ra = na;
+      rb = nb;
+    }
+    return;
+  }
   for (int g0 = 0; g0 < nemax; g0 += 8) {
     TP vn[8], vo[8];
     bool okn[8], oko[8];
