@@ -102,15 +102,25 @@ void seg_tables(const std::vector<int32_t>& chain_off, std::vector<int32_t>& seg
   }
 }
 
-// {first row, end row of its chain} of every 64-row tile (64-column blocks).
-std::vector<int32_t> tile64_table(const std::vector<int32_t>& chain_off) {
-  const int64_t nc = (int64_t)chain_off.size() - 1, seg = px::seg_rows(64);
+// For each tile height (as seg_tables): {first row, end row of its chain} of
+// every tile, concatenated over the heights, and the most tiles of any chain.
+std::vector<int32_t> tile_tables(const std::vector<int32_t>& chain_off, int64_t off[8], int32_t maxt[7]) {
+  const int64_t nc = (int64_t)chain_off.size() - 1;
   std::vector<int32_t> t;
-  for (int64_t c = 0; c < nc; ++c)
-    for (int64_t r = chain_off[c]; r < chain_off[c + 1]; r += seg) {
-      t.push_back((int32_t)r);
-      t.push_back(chain_off[c + 1]);
+  for (int i = 0; i < 7; ++i) {
+    const int64_t seg = px::seg_rows(1 << i);
+    off[i] = (int64_t)t.size() / 2;
+    maxt[i] = 0;
+    for (int64_t c = 0; c < nc; ++c) {
+      const int64_t nt = (chain_off[c + 1] - chain_off[c] + seg - 1) / seg;
+      maxt[i] = std::max<int32_t>(maxt[i], (int32_t)nt);
+      for (int64_t r = chain_off[c]; r < chain_off[c + 1]; r += seg) {
+        t.push_back((int32_t)r);
+        t.push_back(chain_off[c + 1]);
+      }
     }
+  }
+  off[7] = (int64_t)t.size() / 2;
   return t;
 }
 
@@ -516,7 +526,7 @@ struct px_poset {
   bool host_only = false, has_up = false, mirsky = false;
   int32_t *d_node_of_row = nullptr, *d_chain_of_row = nullptr, *d_chain_off = nullptr, *d_niv = nullptr,
           *d_niv_up = nullptr, *d_lev_down = nullptr, *d_lev_up = nullptr, *d_segoff = nullptr, *d_order = nullptr,
-          *d_tile64 = nullptr, *d_walk[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
+          *d_tiles = nullptr, *d_walk[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
   int64_t ntiles[7] = {0, 0, 0, 0, 0, 0, 0};
   int64_t nevents[2] = {0, 0};
   int32_t nsnap[2] = {0, 0};
@@ -539,7 +549,7 @@ struct px_batch {
   int64_t rows = 0;
   bool has_up = false;
   int32_t *d_node_of_row = nullptr, *d_chain_of_row = nullptr, *d_chain_off = nullptr, *d_niv = nullptr,
-          *d_niv_up = nullptr, *d_segoff = nullptr, *d_tile64 = nullptr, *d_poset_of_row = nullptr, *d_k = nullptr, *d_row_off = nullptr,
+          *d_niv_up = nullptr, *d_segoff = nullptr, *d_tiles = nullptr, *d_poset_of_row = nullptr, *d_k = nullptr, *d_row_off = nullptr,
           *d_order = nullptr;
   int64_t* d_niv_off = nullptr;
   int32_t* d_walk[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
@@ -553,7 +563,7 @@ namespace {
 
 void free_poset_device(px_poset* p) {
   int32_t* bufs[] = {p->d_node_of_row, p->d_chain_of_row, p->d_chain_off, p->d_niv, p->d_niv_up,
-                     p->d_lev_down,     p->d_lev_up,       p->d_segoff,    p->d_order, p->d_tile64};
+                     p->d_lev_down,     p->d_lev_up,       p->d_segoff,    p->d_order, p->d_tiles};
   for (int32_t* b : bufs)
     if (b) (void)hipFree(b);
   for (auto& dir : p->d_walk)
@@ -961,10 +971,13 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
     if (e == hipSuccess && p->has_up) e = upload(&p->d_lev_up, P.lev_up_rows.data(), P.lev_up_rows.size(), b);
     if (e == hipSuccess) e = upload(&p->d_segoff, segoff.data(), segoff.size(), b);
     if (e == hipSuccess) {
-      std::vector<int32_t> t64 = tile64_table(P.chain_off);
-      e = (int64_t)t64.size() == 2 * p->ntiles[px::seg_index(64)]
-              ? upload(&p->d_tile64, t64.data(), t64.size(), b)
-              : hipErrorInvalidValue;
+      int64_t off[8];
+      std::vector<int32_t> tt = tile_tables(P.chain_off, off, p->dp.max_chain_tiles);
+      for (int i = 0; i < 7; ++i)
+        if (off[i + 1] - off[i] != p->ntiles[i]) e = hipErrorInvalidValue;
+      if (e == hipSuccess) e = upload(&p->d_tiles, tt.data(), tt.size(), b);
+      for (int i = 0; i < 7 && e == hipSuccess; ++i)
+        p->dp.tiles[i] = p->d_tiles ? (const int2*)p->d_tiles + off[i] : nullptr;
     }
     if (e == hipSuccess) {
       std::vector<int32_t> ord = scan_orders(segoff, P.k, p->ntiles);
@@ -996,7 +1009,6 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
   d.niv = p->d_niv;
   d.niv_up = p->d_niv_up;
   d.segoff = p->d_segoff;
-  d.tile64 = (const int2*)p->d_tile64;
   *out = p;
   return PX_OK;
 }
@@ -1241,10 +1253,13 @@ px_status px_batch_build(int count, px_poset* const* posets, px_batch** out) {
   if (e == hipSuccess && has_up) e = upload(&b->d_niv_up, niv_up.data(), niv_up.size(), bytes);
   if (e == hipSuccess) e = upload(&b->d_segoff, segoff.data(), segoff.size(), bytes);
   if (e == hipSuccess) {
-    std::vector<int32_t> t64 = tile64_table(chain_off);
-    e = (int64_t)t64.size() == 2 * b->ntiles[px::seg_index(64)]
-            ? upload(&b->d_tile64, t64.data(), t64.size(), bytes)
-            : hipErrorInvalidValue;
+    int64_t off[8];
+    std::vector<int32_t> tt = tile_tables(chain_off, off, b->dp.max_chain_tiles);
+    for (int i = 0; i < 7; ++i)
+      if (off[i + 1] - off[i] != b->ntiles[i]) e = hipErrorInvalidValue;
+    if (e == hipSuccess) e = upload(&b->d_tiles, tt.data(), tt.size(), bytes);
+    for (int i = 0; i < 7 && e == hipSuccess; ++i)
+      b->dp.tiles[i] = b->d_tiles ? (const int2*)b->d_tiles + off[i] : nullptr;
   }
   if (e == hipSuccess) {
     std::vector<int32_t> ord = scan_orders(segoff, chains, b->ntiles);
@@ -1313,7 +1328,6 @@ px_status px_batch_build(int count, px_poset* const* posets, px_batch** out) {
   d.niv = b->d_niv;
   d.niv_up = b->d_niv_up;
   d.segoff = b->d_segoff;
-  d.tile64 = (const int2*)b->d_tile64;
   d.niv_off = b->d_niv_off;
   d.poset_of_row = b->d_poset_of_row;
   d.k_of_poset = b->d_k;
@@ -1327,7 +1341,7 @@ px_status px_batch_free(px_batch* b) {
   DeviceGuard dg(b->device);
   int32_t* bufs[] = {b->d_node_of_row, b->d_chain_of_row, b->d_chain_off, b->d_niv,     b->d_niv_up,
                      b->d_segoff,      b->d_poset_of_row,  b->d_k,         b->d_row_off, b->d_order,
-                     b->d_tile64};
+                     b->d_tiles};
   for (int32_t* q : bufs)
     if (q) (void)hipFree(q);
   if (b->d_niv_off) (void)hipFree(b->d_niv_off);

@@ -60,7 +60,10 @@ struct DevPoset {
   const int32_t* niv = nullptr;         // [n*k] or, for a batch, at niv_off[poset]
   const int32_t* niv_up = nullptr;
   const int32_t* segoff = nullptr;      // [7][nchains+1] tile offsets per tile height
-  const int2* tile64 = nullptr;         // 64-row tiles: {first row, end row of its chain} (nullable)
+  // per tile height (as segoff): every tile's {first row, end row of its chain}
+  // (nullable), and the most tiles any chain has
+  const int2* tiles[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int32_t max_chain_tiles[7] = {0, 0, 0, 0, 0, 0, 0};
   // tables of the walking gather, [0] for niv (zeta), [1] for the up-niv map
   WalkTables walk[2];
   // single-pass scan: tiles in scan-position-major order, [0] prefix / [1] suffix,

@@ -154,8 +154,8 @@ __global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw
       tm[q] = tmask[t];
       qo[q] = qoff[t];
     }
-    if (CWT == 64 && d.tile64) {  // one scalar load instead of a search over the chains
-      const int2 tr = d.tile64[t];
+    if (d.tiles[segi]) {  // one (scalar) load instead of a search over the chains
+      const int2 tr = d.tiles[segi][t];
       r0[q] = tr.x + (int64_t)rg * RPT;
       end[q] = tr.y;
     } else {
@@ -369,6 +369,42 @@ __global__ __launch_bounds__(WG) void k_scan_carry(DevPoset d, int segi, int dir
   }
 }
 
+// Phase 2 for posets whose chains have few tiles (at most kShortCarry): one
+// thread per (chain, column) folds the chain's tile totals in scan order,
+// eight loads in flight, instead of a workgroup staging windows in LDS.  The
+// combination order is that of the windowed kernel's prefix, so both are
+// reproducible (they may differ from each other in the last bits).
+constexpr int kShortCarry = 64;
+template <typename St, typename Tout>
+__global__ __launch_bounds__(WG) void k_scan_carry_short(DevPoset d, int segi, int dir, int64_t B,
+                                                         const St* __restrict__ A, St* __restrict__ C,
+                                                         Tout* __restrict__ P) {
+  const int64_t idx = (int64_t)blockIdx.x * WG + threadIdx.x;
+  const int64_t c = idx / B, col = idx % B;
+  if (c >= d.nchains) return;
+  if (c == 0) P[(int64_t)d.n * B + col] = Tout(0);  // the walk's zero row
+  const int32_t* so = d.segoff + (int64_t)segi * (d.nchains + 1);
+  const int t0 = so[c], t1 = so[c + 1], nt = t1 - t0;
+  St carry;
+  carry.zero();
+  for (int i0 = 0; i0 < nt; i0 += 8) {
+    St a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = min(i0 + u, nt - 1);
+      a[u] = A[(int64_t)(dir > 0 ? t0 + i : t1 - 1 - i) * B + col];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u;
+      if (i < nt) {
+        C[(int64_t)(dir > 0 ? t0 + i : t1 - 1 - i) * B + col] = carry;
+        carry.combine(a[u]);
+      }
+    }
+  }
+}
+
 // Phase 3: scan inside the tile from its carry; write P chain-major.  This is
 // the last read of f and P is not read back soon: both streams are
 // non-temporal, so that f read by phase 1 stays in the MALL for this read and
@@ -395,8 +431,8 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
   const int t = blockIdx.x;
   const int RG = WG / cw;
   int64_t base, end;
-  if (CWT == 64 && d.tile64) {  // one scalar load instead of a search over the chains
-    const int2 tr = d.tile64[t];
+  if (d.tiles[segi]) {  // one (scalar) load instead of a search over the chains
+    const int2 tr = d.tiles[segi][t];
     base = tr.x;
     end = tr.y;
   } else {
@@ -1377,9 +1413,15 @@ hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int6
       hipLaunchKernelGGL((k_scan_reduce<Tin, Tout, 0, false>), g2, dim3(WG), 0, s, d, segi, cw, (const Tin*)x,
                          ldx, B, ntiles, A, dir, (const uint64_t*)nullptr, (const int32_t*)nullptr, (Tout*)nullptr);
   } else if (phase == 1) {
-    hipLaunchKernelGGL((k_scan_carry<St, Tout, false>), dim3((unsigned)d.nchains, (unsigned)((B + 15) / 16)),
-                       dim3(WG), 0, s, d, segi, dir, B, (const St*)A, C, (Tout*)P, (const int32_t*)nullptr,
-                       (const int32_t*)nullptr, (const Tout*)nullptr, 0);
+    if (d.max_chain_tiles[segi] <= kShortCarry) {
+      const int64_t threads = (int64_t)d.nchains * B;
+      hipLaunchKernelGGL((k_scan_carry_short<St, Tout>), dim3((unsigned)((threads + WG - 1) / WG)), dim3(WG), 0, s,
+                         d, segi, dir, B, (const St*)A, C, (Tout*)P);
+    } else {
+      hipLaunchKernelGGL((k_scan_carry<St, Tout, false>), dim3((unsigned)d.nchains, (unsigned)((B + 15) / 16)),
+                         dim3(WG), 0, s, d, segi, dir, B, (const St*)A, C, (Tout*)P, (const int32_t*)nullptr,
+                         (const int32_t*)nullptr, (const Tout*)nullptr, 0);
+    }
   } else if (cw == 64) {
     hipLaunchKernelGGL((k_scan_apply<Tin, Tout, 64, 0, Tout>), g, dim3(WG), 0, s, d, segi, cw, dir, (const Tin*)x,
                        ldx, B, (const St*)C, (Tout*)P, (const int32_t*)nullptr, (const Tout*)nullptr, 0,
