@@ -472,7 +472,11 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
     const int64_t r = r0 + i;
     if (r >= end) return;
     if constexpr (MODE == 0) {
-      __builtin_nontemporal_store(Tr::out(st.value()), &P[r * B + col]);
+      // a narrow tile's store covers pieces of several lines: leave it to L2 to merge them
+      if (CWT == 64)
+        __builtin_nontemporal_store(Tr::out(st.value()), &P[r * B + col]);
+      else
+        P[r * B + col] = Tr::out(st.value());
     } else if constexpr (MODE == 1) {
       __builtin_nontemporal_store((Tout)((W)Tr::out(st.value()) + (W)sv[i]), &P[(int64_t)nodes[i] * ldo + col]);
     } else {
@@ -495,6 +499,33 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
   }
   sm[threadIdx.x] = loc;
   __syncthreads();
+  // the row groups before this one in scan order: folded one by one for a few
+  // groups; for narrow column tiles (up to 32 groups) an inclusive scan over the
+  // groups in LDS, log2(RG) steps in a fixed order
+  St pre;
+  pre.zero();
+  if (RG <= 4) {
+    if (dir > 0) {
+      for (int g = 0; g < rg; ++g) pre.combine(sm[g * cw + lane]);
+    } else {
+      for (int g = RG - 1; g > rg; --g) pre.combine(sm[g * cw + lane]);
+    }
+  } else {
+    for (int off = 1; off < RG; off <<= 1) {
+      const int src = dir > 0 ? rg - off : rg + off;
+      const bool has = src >= 0 && src < RG;
+      St a;
+      if (has) a = sm[src * cw + lane];
+      __syncthreads();
+      if (has) {
+        a.combine(sm[threadIdx.x]);
+        sm[threadIdx.x] = a;
+      }
+      __syncthreads();
+    }
+    const int src = dir > 0 ? rg - 1 : rg + 1;
+    if (src >= 0 && src < RG) pre = sm[src * cw + lane];
+  }
   if (col >= B) return;
   if constexpr (MODE != 0) {
 #pragma unroll
@@ -502,15 +533,14 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
       if (sn[i] == sn[i - 1]) sv[i] = sv[i - 1];
   }
   St st = C[(int64_t)t * B + col];
+  st.combine(pre);
   if (dir > 0) {
-    for (int g = 0; g < rg; ++g) st.combine(sm[g * cw + lane]);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       st.add(v[i]);
       put(i, st);
     }
   } else {
-    for (int g = RG - 1; g > rg; --g) st.combine(sm[g * cw + lane]);
 #pragma unroll
     for (int i = RPT - 1; i >= 0; --i) {
       st.add(v[i]);
@@ -1125,33 +1155,40 @@ __global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* 
   const int cw = UNI ? 64 : cw_rt;
   auto uni = [](int v) { return UNI ? __builtin_amdgcn_readfirstlane(v) : v; };
   const int RG = WG / cw;
-  const int rbase = uni((int)((blockIdx.x * RG + threadIdx.x / cw) * RPC));
+  // row of step i: UNI, a wavefront's RPC consecutive rows; narrow tiles, the
+  // block's row groups side by side at every step (RG consecutive rows), so
+  // that each load of P covers whole lines
+  const int g = (int)(threadIdx.x / cw);
+  const int rb = UNI ? uni((int)((blockIdx.x * RG + g) * RPC)) : (int)(blockIdx.x * RG * RPC) + g;
+  const int rs = UNI ? 1 : RG;
   const int col = (int)blockIdx.y * cw + (int)(threadIdx.x % cw);
-  if (rbase >= d.n) return;
+  if (rb >= d.n) return;
   const int colc = col < B ? col : 0;
   int32_t nd[RPC], sm[RPC];
 #pragma unroll
   for (int i = 0; i < RPC; ++i) {
-    const int r = min(rbase + i, d.n - 1);
+    const int r = min(rb + i * rs, d.n - 1);
     nd[i] = uni(d.node_of_row[r]);
     sm[i] = uni(snap_of_row[r]);
   }
   TP pv[RPC], sv[RPC];
 #pragma unroll
   for (int i = 0; i < RPC; ++i) {
-    const int r = min(rbase + i, d.n - 1);
+    const int r = min(rb + i * rs, d.n - 1);
     pv[i] = __builtin_nontemporal_load(&(P + (int64_t)r * B)[colc]);
     sv[i] = (S + (int64_t)sm[i] * B)[colc];
   }
   if (col >= B) return;
 #pragma unroll
   for (int i = 0; i < RPC; ++i) {
-    if (rbase + i < d.n) {
+    if (rb + i * rs < d.n) {
       if constexpr (RESID)
         (out + (int64_t)nd[i] * ldo)[col] =
             (TP)((double)(res + (int64_t)nd[i] * ldr)[col] - ((W)pv[i] + (W)sv[i]));
-      else
+      else if (UNI)
         __builtin_nontemporal_store((TP)((W)pv[i] + (W)sv[i]), &(out + (int64_t)nd[i] * ldo)[col]);
+      else
+        (out + (int64_t)nd[i] * ldo)[col] = (TP)((W)pv[i] + (W)sv[i]);
     }
   }
 }
