@@ -526,7 +526,8 @@ struct px_poset {
   bool host_only = false, has_up = false, mirsky = false;
   int32_t *d_node_of_row = nullptr, *d_chain_of_row = nullptr, *d_chain_off = nullptr, *d_niv = nullptr,
           *d_niv_up = nullptr, *d_lev_down = nullptr, *d_lev_up = nullptr, *d_segoff = nullptr, *d_order = nullptr,
-          *d_tiles = nullptr, *d_walk[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
+          *d_tiles = nullptr, *d_lev_niv[2] = {nullptr, nullptr}, *d_lev_node[2] = {nullptr, nullptr},
+          *d_walk[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
   int64_t ntiles[7] = {0, 0, 0, 0, 0, 0, 0};
   int64_t nevents[2] = {0, 0};
   int32_t nsnap[2] = {0, 0};
@@ -563,7 +564,8 @@ namespace {
 
 void free_poset_device(px_poset* p) {
   int32_t* bufs[] = {p->d_node_of_row, p->d_chain_of_row, p->d_chain_off, p->d_niv, p->d_niv_up,
-                     p->d_lev_down,     p->d_lev_up,       p->d_segoff,    p->d_order, p->d_tiles};
+                     p->d_lev_down,     p->d_lev_up,       p->d_segoff,    p->d_order, p->d_tiles,
+                     p->d_lev_niv[0],   p->d_lev_niv[1],   p->d_lev_node[0], p->d_lev_node[1]};
   for (int32_t* b : bufs)
     if (b) (void)hipFree(b);
   for (auto& dir : p->d_walk)
@@ -609,7 +611,8 @@ hipError_t solve_levels(const px_poset* p, bool up, px::ElemType tin, const void
   }
   for (size_t l = 0; l + 1 < ptr.size(); ++l) {
     prof::Scope sc(prof::USOLVE, s);
-    hipError_t e = px::launch_usolve_level(p->dp, up, rows + ptr[l], ptr[l + 1] - ptr[l], tin, g, ldg, ty, Y, B, s);
+    hipError_t e =
+        px::launch_usolve_level(p->dp, up, rows + ptr[l], ptr[l], ptr[l + 1] - ptr[l], tin, g, ldg, ty, Y, B, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -969,6 +972,21 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
     if (e == hipSuccess && p->has_up) e = upload(&p->d_niv_up, P.niv_up.data(), P.niv_up.size(), b);
     if (e == hipSuccess) e = upload(&p->d_lev_down, P.lev_down_rows.data(), P.lev_down_rows.size(), b);
     if (e == hipSuccess && p->has_up) e = upload(&p->d_lev_up, P.lev_up_rows.data(), P.lev_up_rows.size(), b);
+    // level-ordered niv rows and node ids for the uniform level solve
+    for (int dir = 0; dir < 2 && e == hipSuccess && P.k <= 64; ++dir) {
+      if (dir == 1 && !p->has_up) break;
+      const std::vector<int32_t>& lr = dir ? P.lev_up_rows : P.lev_down_rows;
+      const std::vector<int32_t>& nv = dir ? P.niv_up : P.niv;
+      std::vector<int32_t> lnv(lr.size() * P.k), lnode(lr.size());
+      for (size_t i = 0; i < lr.size(); ++i) {
+        std::copy_n(&nv[(size_t)lr[i] * P.k], P.k, &lnv[i * P.k]);
+        lnode[i] = P.node_of_row[lr[i]];
+      }
+      e = upload(&p->d_lev_niv[dir], lnv.data(), lnv.size(), b);
+      if (e == hipSuccess) e = upload(&p->d_lev_node[dir], lnode.data(), lnode.size(), b);
+      p->dp.lev_niv[dir] = p->d_lev_niv[dir];
+      p->dp.lev_node[dir] = p->d_lev_node[dir];
+    }
     if (e == hipSuccess) e = upload(&p->d_segoff, segoff.data(), segoff.size(), b);
     if (e == hipSuccess) {
       int64_t off[8];

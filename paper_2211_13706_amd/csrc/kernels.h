@@ -66,6 +66,10 @@ struct DevPoset {
   int32_t max_chain_tiles[7] = {0, 0, 0, 0, 0, 0, 0};
   // tables of the walking gather, [0] for niv (zeta), [1] for the up-niv map
   WalkTables walk[2];
+  // level solves, [0] down / [1] up: the niv rows (k entries each) and node ids
+  // of the rows in level order (nullable; single posets with k <= 64)
+  const int32_t* lev_niv[2] = {nullptr, nullptr};
+  const int32_t* lev_node[2] = {nullptr, nullptr};
   // single-pass scan: tiles in scan-position-major order, [0] prefix / [1] suffix,
   // one table per tile height (as segoff)
   const int32_t* scan_order[2][7] = {{nullptr}};
@@ -142,7 +146,8 @@ hipError_t launch_zeta_compact(const DevPoset& d, int dir, ElemType tin, const v
 // to zero (the uniform solve reads it for the own and missing niv entries).
 hipError_t launch_usolve_begin(const DevPoset& d, ElemType ty, void* Y, int64_t B, hipStream_t s);
 
-hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_rows, int64_t cnt,
+// i0: the level's first position in the level order (lev_rows = rows + i0).
+hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_rows, int64_t i0, int64_t cnt,
                                ElemType tin, const void* g, int64_t ldg, ElemType ty, void* Y,
                                int64_t B, hipStream_t s);
 

@@ -1295,11 +1295,17 @@ __global__ __launch_bounds__(WG) void k_usolve(DevPoset d, const int32_t* __rest
 // out all at once from scalar row bases, and the own and missing entries read
 // row n of Y, which launch_usolve_begin sets to zero.  Same subtraction order
 // as k_usolve (a zero row subtracts nothing), so results are identical.
+//
+// With level-ordered copies of the niv rows and node ids (lnv, lnode; the
+// level starts at position i0), a row's entries, node and index load together
+// instead of after the row index: one dependent memory round trip less per
+// level.
 template <typename Tin, typename TY>
 __global__ __launch_bounds__(WG) void k_usolve_uni(DevPoset d, const int32_t* __restrict__ nv,
                                                    const int32_t* __restrict__ rows, int cnt,
                                                    const Tin* __restrict__ g, int64_t ldg, TY* __restrict__ Y,
-                                                   int64_t B) {
+                                                   int64_t B, const int32_t* __restrict__ lnv,
+                                                   const int32_t* __restrict__ lnode, int64_t i0) {
   using W = typename Wide<TY>::W;
   const int lane = threadIdx.x & 63;
   const int i = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (WG / 64) + (threadIdx.x >> 6)));
@@ -1307,10 +1313,16 @@ __global__ __launch_bounds__(WG) void k_usolve_uni(DevPoset d, const int32_t* __
   const int col = (int)blockIdx.y * 64 + lane;
   const bool colok = col < B;
   const int colc = colok ? col : 0;
-  const int r = __builtin_amdgcn_readfirstlane(rows[i]);
-  const int node = __builtin_amdgcn_readfirstlane(d.node_of_row[r]);
   const int k = d.k, zr = d.n;
-  const int cur = lane < k ? nv[(int64_t)r * k + lane] : -1;
+  const int r = __builtin_amdgcn_readfirstlane(rows[i]);
+  int node, cur;
+  if (lnv) {
+    node = __builtin_amdgcn_readfirstlane(lnode[i0 + i]);
+    cur = lane < k ? lnv[(i0 + i) * k + lane] : -1;
+  } else {
+    node = __builtin_amdgcn_readfirstlane(d.node_of_row[r]);
+    cur = lane < k ? nv[(int64_t)r * k + lane] : -1;
+  }
   W acc = (W)(g + (int64_t)node * ldg)[colc];
   // levels hold few rows, so occupancy matters little: all k loads in flight
   TY v[64];
@@ -1660,8 +1672,9 @@ hipError_t launch_usolve_begin(const DevPoset& d, ElemType ty, void* Y, int64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_rows, int64_t cnt, ElemType tin,
-                               const void* g, int64_t ldg, ElemType ty, void* Y, int64_t B, hipStream_t s) {
+hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_rows, int64_t i0, int64_t cnt,
+                               ElemType tin, const void* g, int64_t ldg, ElemType ty, void* Y, int64_t B,
+                               hipStream_t s) {
   if (cnt == 0) return hipSuccess;
   const int cw = col_width(B);
   const dim3 gr = grid2(cnt, cw, B);
@@ -1669,18 +1682,20 @@ hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_ro
   if (cw == 64 && d.k <= 64 && !d.poset_of_row && cnt < INT32_MAX) {
     const dim3 gu((unsigned)((cnt + (WG / 64) - 1) / (WG / 64)), (unsigned)((B + 63) / 64));
     const int c = (int)cnt;
+    const int32_t* lnv = d.lev_niv[up ? 1 : 0];
+    const int32_t* lnode = d.lev_node[up ? 1 : 0];
     if (tin == E_I64 && ty == E_I64)
       hipLaunchKernelGGL((k_usolve_uni<int64_t, int64_t>), gu, dim3(WG), 0, s, d, nv, lev_rows, c, (const int64_t*)g,
-                         ldg, (int64_t*)Y, B);
+                         ldg, (int64_t*)Y, B, lnv, lnode, i0);
     else if (tin == E_F32 && ty == E_F32)
       hipLaunchKernelGGL((k_usolve_uni<float, float>), gu, dim3(WG), 0, s, d, nv, lev_rows, c, (const float*)g, ldg,
-                         (float*)Y, B);
+                         (float*)Y, B, lnv, lnode, i0);
     else if (tin == E_F64 && ty == E_F32)
       hipLaunchKernelGGL((k_usolve_uni<double, float>), gu, dim3(WG), 0, s, d, nv, lev_rows, c, (const double*)g, ldg,
-                         (float*)Y, B);
+                         (float*)Y, B, lnv, lnode, i0);
     else if (tin == E_F64 && ty == E_F64)
       hipLaunchKernelGGL((k_usolve_uni<double, double>), gu, dim3(WG), 0, s, d, nv, lev_rows, c, (const double*)g,
-                         ldg, (double*)Y, B);
+                         ldg, (double*)Y, B, lnv, lnode, i0);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();
