@@ -322,13 +322,23 @@ __global__ __launch_bounds__(WG) void k_scan_carry(DevPoset d, int segi, int dir
       cnt = max(min(s1, a0 + per) - a0, 0) * CB;
       if ((int)threadIdx.x < cnt) load_batch(threadIdx.x);
     }
-    for (int x = threadIdx.x; x < WIN * CB; x += WG) {
-      const int i = w0 + x / CB;
-      const int64_t cc = c0 + x % CB;
-      St v;
-      v.zero();
-      if (i < nt && cc < B) v = A[(int64_t)(dir > 0 ? t0 + i : t1 - 1 - i) * B + cc];
-      sh[x] = v;
+    {
+      // the window's WIN * CB totals, WIN * CB / WG per thread, all loads in
+      // flight before the LDS stores (addresses clamped, outside values zero)
+      constexpr int PER = WIN * CB / WG;
+      St v[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int x = (int)threadIdx.x + u * WG;
+        const int i = w0 + x / CB;
+        const int64_t cc = c0 + x % CB;
+        const int ic = min(i, nt - 1);
+        const int64_t ccc = cc < B ? cc : B - 1;
+        v[u] = A[(int64_t)(dir > 0 ? t0 + ic : t1 - 1 - ic) * B + ccc];
+        if (i >= nt || cc >= B) v[u].zero();
+      }
+#pragma unroll
+      for (int u = 0; u < PER; ++u) sh[threadIdx.x + u * WG] = v[u];
     }
     __syncthreads();
     St part;
