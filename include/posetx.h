@@ -38,6 +38,14 @@
  *  - Every call returns a px_status; px_last_error() gives a thread-local
  *    message for the last failure on the calling thread.  No C++ exception
  *    crosses this interface.
+ *  - Execution paths (results agree to rounding; int64 bit for bit), read from
+ *    the environment on every call: for a single poset with at most 64 chains
+ *    and B > 32, zeta and its adjoint complete the chain prefixes only at the
+ *    rows the gather reads and never form the full prefix matrix;
+ *    POSETX_WALK=rows forms it instead.  POSETX_SCAN=onepass selects the
+ *    single-pass chain scan for the paths that form it, with POSETX_LB_SPIN
+ *    bounding its waits (polls; 0 makes every wait give up and sum its
+ *    predecessors from the input).  POSETX_TUNE_CACHE: see px_autotune.
  */
 #ifndef POSETX_H
 #define POSETX_H

@@ -339,6 +339,22 @@ def test_compact_walk_matches_oracle_and_rows_walk(px, shape, B, monkeypatch):
     assert P.info["walk_rows_distinct"] == 0 if shape == "one_chain" else P.info["walk_rows_distinct"] > 0
 
 
+@pytest.mark.parametrize("B", [8, 64])
+def test_zeta_in_place(px, cfg0, B):
+    """f == g (same pointer and leading dimension) is allowed for zeta and its
+    adjoint: the compact walk (B = 64) writes an element only after the same
+    thread has read it; the walk over P (B = 8) reads f only in the scan."""
+    p, R = cfg0
+    P = build(px, p)
+    f = W.functions(p.n, B, "int", seed=67, lo=-100, hi=100)
+    x = T(f)
+    assert px.zeta(P, x, out=x) is x
+    assert np.array_equal(H(x), O.zeta(R, f))
+    y = T(f)
+    px.zeta_adjoint(P, y, out=y)
+    assert np.array_equal(H(y), O.zeta_adjoint(R, f))
+
+
 def test_compact_walk_refinement_residual(px, monkeypatch):
     """float32 Möbius with float64 residuals: the compact residual (fused
     res - (P + S)) and the residual over P reach the same accuracy."""
