@@ -155,6 +155,17 @@ def _time(fn, steps, sync):
     return (time.perf_counter() - t0) / steps
 
 
+def f64_growth(px, P, n, dev, B_: int = 4):
+    """max|M r| / max|r| for r ~ U(-1, 1) in float64: how far the Möbius transform of this poset
+    amplifies data (an infinite or NaN result means float64 overflows)."""
+    import torch
+    import workloads as W
+    r = torch.from_numpy(W.functions(n, B_, "uniform", seed=12, lo=-1.0, hi=1.0).astype("float64")).to(dev)
+    m = px.mobius(P, r)
+    g = (m.abs().amax() / r.abs().amax()).item()
+    return g if g == g and g != float("inf") else str(g)
+
+
 def legs_config1(px, P, p, dev, steps):
     """int64 zeta and the exact Möbius round trip, and the float32 adjoint, on the headline poset."""
     import torch
@@ -173,6 +184,7 @@ def legs_config1(px, P, p, dev, steps):
                            "us_per_level": round(t * 1e6 / max(1, P.info["levels_down"]), 2),
                            "roundtrip_exact": bool(torch.equal(fb, fi))}
     del fi, gi, fb
+    out["mobius_f64_growth"] = f64_growth(px, P, p.n, dev)
     ff = torch.from_numpy(W.functions(p.n, B, "normal", seed=4)).to(dev)
     ga = torch.empty_like(ff)
     t = _time(lambda: px.zeta_adjoint(P, ff, out=ga), steps, sync)
@@ -289,11 +301,13 @@ def leg_large(px, dev, steps):
     tm = _time(lambda: px.mobius(L, gi), 2, sync)
     exact = bool(torch.equal(px.mobius(L, gi), fi))
     exact_adj = bool(torch.equal(px.mobius_adjoint(L, px.zeta_adjoint(L, fi)), fi))
+    growth = f64_growth(px, L, q.n, dev)
     return {"workload": "n=8388608, k=32, 3 cross edges, B=16", "preprocess_s": round(t_prep, 2),
             "levels": L.info["levels_down"], "zeta_f32_ms": round(tz * 1e3, 4),
             "zeta_node_rhs_per_s": q.n * Bl / tz, "mobius_int64_ms": round(tm * 1e3, 4),
             "us_per_level": round(tm * 1e6 / max(1, L.info["levels_down"]), 2),
             "int64_roundtrip_exact": exact, "int64_adjoint_roundtrip_exact": exact_adj,
+            "mobius_f64_growth": growth,
             "f32_roundtrip_rel_err": err, "f32_refine_report": rep}
 
 
