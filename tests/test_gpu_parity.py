@@ -306,21 +306,25 @@ def test_scan_schedules_grid_exact(px, mode, monkeypatch):
 
 
 # ---------------------------------------------------------- compact walk
-@pytest.mark.parametrize("shape", ["cfg0", "short_chains", "one_chain", "k64"])
-@pytest.mark.parametrize("B", [33, 64, 100])
+@pytest.mark.parametrize("shape", ["cfg0", "short_chains", "one_chain", "k64", "tile64", "tile65"])
+@pytest.mark.parametrize("B", [33, 64, 65, 100, 128])
 def test_compact_walk_matches_oracle_and_rows_walk(px, shape, B, monkeypatch):
     """The compact walk (no P matrix) against the oracle and the walk over P.
 
     Shapes: chains of 125 rows (two 64-row tiles, the second ragged); chains of
     about 8 rows (every tile ragged, many slots per tile); one chain (no other
-    chain, so no gathered rows at all); 64 chains (the widest compact form).
-    B = 33 and 100 leave lanes of the last 64-column block idle.  int64 is
-    bit-exact both ways; float64 agrees to rounding.
+    chain, so no gathered rows at all); 64 chains (the widest compact form);
+    chains of exactly 64 rows (one full tile each, bit 63 of the tile masks) and
+    of 65 rows (a one-row tail tile).  B = 33, 65 and 100 leave lanes of the
+    last 64-column block idle; B = 128 is two full blocks.  int64 is bit-exact
+    both ways; float64 agrees to rounding.
     """
     p = {"cfg0": lambda: W.chain_poset(2000, 16, 4, seed=0),
          "short_chains": lambda: W.chain_poset(400, 50, 3, seed=60),
          "one_chain": lambda: W.chain_only(300, seed=61),
-         "k64": lambda: W.chain_poset(3000, 64, 3, seed=62)}[shape]()
+         "k64": lambda: W.chain_poset(3000, 64, 3, seed=62),
+         "tile64": lambda: W.chain_poset(64 * 16, 16, 3, seed=75),
+         "tile65": lambda: W.chain_poset(65 * 16, 16, 3, seed=76)}[shape]()
     R = O.reachability(p.n, p.indptr, p.indices)
     P = build(px, p)
     f = W.functions(p.n, B, "int", seed=63, lo=-10**6, hi=10**6)
@@ -439,6 +443,32 @@ def test_config1_f32_integer_data_exact_roundtrip(px, cfg1, mode, monkeypatch):
     g32 = px.zeta(P, T(f.astype(np.float32)))
     assert np.array_equal(H(g32)[nodes], O.zeta_at(p.n, p.indptr, p.indices, f, nodes).astype(np.float32))
     assert np.array_equal(H(px.mobius(P, g32.to(dtype=px_int64()))), f)
+
+
+@pytest.fixture(scope="module")
+def cfg1_b512(cfg1):
+    p, nodes = cfg1
+    rng = np.random.default_rng(77)
+    f16 = rng.integers(-1000, 1001, size=(p.n, 512), dtype=np.int16)
+    sel = nodes[-2:]  # the top of a chain and node 0
+    return f16, sel, O.zeta_at(p.n, p.indptr, p.indices, f16, sel)
+
+
+@pytest.mark.parametrize("walk", ["compact", "rows"])
+def test_config1_f32_B512_sampled_exact(px, cfg1, cfg1_b512, walk, monkeypatch):
+    """B = 512 at n = 2**20: eight 64-column blocks, and for the walk over P a P
+    matrix of (n + 1) * 512 * 4 bytes > 2**31, so the walk's gathers take
+    64-bit row offsets.  Integer data in [-1000, 1000] (chain prefixes below
+    2**24, k-term sums exact in float64): every output is the exact integer
+    rounded once to float32."""
+    import torch
+    if walk == "rows":
+        monkeypatch.setenv("POSETX_WALK", "rows")
+    p, _ = cfg1
+    f16, sel, want = cfg1_b512
+    P = build(px, p)
+    g = px.zeta(P, torch.from_numpy(f16).to(dev()).float())
+    assert np.array_equal(H(g)[sel], want.astype(np.float32))
 
 
 def test_config1_int64_zeta_sampled_and_roundtrip(px, cfg1):
