@@ -6,6 +6,12 @@
 // zeta-fast).  The Möbius transform solves U y' = g by substitution,
 // level by level, then applies V^{-1}, one subtraction per element (§3, Alg. 4).
 //
+// For a single poset with at most 64 chains and 64-column blocks the zeta
+// transform never forms V f: the scan completes the prefixes only at the rows
+// U reads, and U's own-chain term is added inside the scan's last pass (the
+// compact walk: k_scan_reduce / k_scan_carry with MARK, k_walk_events with
+// COMPACT, k_scan_apply modes 1 and 2).
+//
 // Thread layout shared by all kernels: a 256-thread workgroup covers `cw`
 // consecutive right-hand-side columns (lanes) times 256/cw rows, so that the
 // lanes of a wavefront read contiguous bytes of a row; B is padded to cw.
