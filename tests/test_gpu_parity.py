@@ -530,6 +530,27 @@ def test_batched_zeta_and_adjoint(px):
         assert (np.abs(grad[s:e] - want) <= 3 * U32 * zabs + 1e-30).all()
 
 
+@pytest.mark.parametrize("B", [1, 33, 100])
+def test_batched_widths_and_dtypes(px, B):
+    """Batches at other widths: B = 1 (one lane per run), 33 (64-column lane
+    groups in the split walk) and 100 (more than 64 columns: one thread per row
+    and column over every niv entry).  int64 exact, float64 to rounding."""
+    posets = W.batched_posets(10, seed=80, nmin=50, nmax=700)
+    Ps = [build(px, q) for q in posets]
+    b = px.batch_build(Ps)
+    f = W.functions(b.rows, B, "int", seed=81, lo=-1000, hi=1000)
+    f64 = W.functions(b.rows, B, "normal64", seed=82)
+    g, a = H(px.zeta_batched(b, T(f))), H(px.zeta_adjoint_batched(b, T(f)))
+    g64, a64 = H(px.zeta_batched(b, T(f64))), H(px.zeta_adjoint_batched(b, T(f64)))
+    for i, q in enumerate(posets):
+        s0, e0 = b.offsets[i], b.offsets[i + 1]
+        R = O.reachability(q.n, q.indptr, q.indices)
+        assert np.array_equal(g[s0:e0], O.zeta(R, f[s0:e0]))
+        assert np.array_equal(a[s0:e0], O.zeta_adjoint(R, f[s0:e0]))
+        assert rel(g64[s0:e0], O.zeta(R, f64[s0:e0], exact=False)) <= 1e-12
+        assert rel(a64[s0:e0], O.zeta_adjoint(R, f64[s0:e0], exact=False)) <= 1e-12
+
+
 # ------------------------------------------------------------ error handling
 def test_argument_errors_and_nonfinite(px, cfg0):
     import torch
