@@ -854,6 +854,27 @@ __global__ void k_fill_i32(int* p, int64_t cnt, int v) {
 
 __device__ inline double fmax_(double a, double b) { return a > b ? a : b; }
 
+// Σ over a row's k niv entries of M[entry][col], skipping -1 and `skip`:
+// 32 entries load together, then their 32 rows together, instead of one entry
+// and one dependent row at a time.  Skipped entries read row zr of M, which
+// every producer of M keeps zero, so that no load is behind a branch.
+template <typename TM, typename W>
+__device__ inline W niv_sum(const int32_t* __restrict__ nr, int k, int64_t skip, int64_t zr,
+                            const TM* __restrict__ M, int64_t B, int64_t col) {
+  W acc = W(0);
+  for (int j0 = 0; j0 < k; j0 += 32) {
+    int32_t t[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) t[u] = j0 + u < k ? nr[j0 + u] : -1;
+    TM v[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) v[u] = M[(t[u] >= 0 && t[u] != skip ? (int64_t)t[u] : zr) * B + col];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) acc += (W)v[u];
+  }
+  return acc;
+}
+
 template <typename TP, typename Tout, typename Tres, bool RESID>
 __global__ __launch_bounds__(WG) void k_gather(DevPoset d, const int32_t* __restrict__ nv, int cw,
                                                const TP* __restrict__ P, int64_t B, Tout* __restrict__ out,
@@ -864,12 +885,7 @@ __global__ __launch_bounds__(WG) void k_gather(DevPoset d, const int32_t* __rest
   const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
   if (r >= d.n || col >= B) return;
   const int k = d.k;
-  const int32_t* nr = nv + r * k;
-  W acc = W(0);
-  for (int j = 0; j < k; ++j) {
-    const int32_t t = nr[j];
-    if (t >= 0) acc += (W)P[(int64_t)t * B + col];
-  }
+  const W acc = niv_sum<TP, W>(nv + r * k, k, -1, d.n, P, B, col);  // row n of P is zero
   const int64_t node = d.node_of_row[r];
   if constexpr (RESID) {
     out[node * ldo + col] = (Tout)((double)res[node * ldr + col] - (double)acc);
@@ -1275,12 +1291,7 @@ __global__ __launch_bounds__(WG) void k_gather_batched(DevPoset d, const int32_t
   if (r >= d.n || col >= B) return;
   const int p = d.poset_of_row[r];
   const int k = d.k_of_poset[p];
-  const int32_t* nr = nv + d.niv_off[p] + (r - d.row_off[p]) * k;
-  W acc = W(0);
-  for (int j = 0; j < k; ++j) {
-    const int32_t t = nr[j];
-    if (t >= 0) acc += (W)P[(int64_t)t * B + col];
-  }
+  const W acc = niv_sum<TP, W>(nv + d.niv_off[p] + (r - d.row_off[p]) * k, k, -1, d.n, P, B, col);
   out[(int64_t)d.node_of_row[r] * ldo + col] = (Tout)acc;
 }
 
@@ -1297,12 +1308,7 @@ __global__ __launch_bounds__(WG) void k_usolve(DevPoset d, const int32_t* __rest
   if (i >= cnt || col >= B) return;
   const int64_t r = rows[i];
   const int64_t node = d.node_of_row[r];
-  W acc = (W)g[node * ldg + col];
-  const int32_t* nr = nv + r * d.k;
-  for (int j = 0; j < d.k; ++j) {
-    const int32_t t = nr[j];
-    if (t >= 0 && t != r) acc -= (W)Y[(int64_t)t * B + col];
-  }
+  const W acc = (W)g[node * ldg + col] - niv_sum<TY, W>(nv + r * d.k, d.k, r, d.n, Y, B, col);
   Y[r * B + col] = (TY)acc;
 }
 
