@@ -476,12 +476,17 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
   // is loaded once (scalar tests) and copied once the loads have returned
   Tout sv[MODE ? RPT : 1];
   int32_t sn[MODE ? RPT : 1];
+  Tres rv[MODE == 2 ? RPT : 1];  // MODE 2: the residual's right-hand side, loaded with f
   if constexpr (MODE != 0) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) sn[i] = __builtin_amdgcn_readfirstlane(snap_of_row[min(r0 + i, end - 1)]);
 #pragma unroll
     for (int i = 0; i < RPT; ++i)
       if (i == 0 || sn[i] != sn[i - 1]) sv[i] = (S + (int64_t)sn[i] * B)[colc];
+  }
+  if constexpr (MODE == 2) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) rv[i] = res[(int64_t)nodes[i] * ldr + colc];
   }
   // row i's result: P[r] itself, or the combined zeta value / residual
   auto put = [&](int i, const St& st) {
@@ -496,9 +501,8 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
     } else if constexpr (MODE == 1) {
       __builtin_nontemporal_store((Tout)((W)Tr::out(st.value()) + (W)sv[i]), &P[(int64_t)nodes[i] * ldo + col]);
     } else {
-      __builtin_nontemporal_store(
-          (Tout)((double)res[(int64_t)nodes[i] * ldr + col] - ((W)Tr::out(st.value()) + (W)sv[i])),
-          &P[(int64_t)nodes[i] * ldo + col]);
+      __builtin_nontemporal_store((Tout)((double)rv[i] - ((W)Tr::out(st.value()) + (W)sv[i])),
+                                  &P[(int64_t)nodes[i] * ldo + col]);
     }
   };
   Tv v[RPT];
@@ -1204,19 +1208,20 @@ __global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* 
     sm[i] = uni(snap_of_row[r]);
   }
   TP pv[RPC], sv[RPC];
+  Tres rv[RESID ? RPC : 1];
 #pragma unroll
   for (int i = 0; i < RPC; ++i) {
     const int r = min(rb + i * rs, d.n - 1);
     pv[i] = __builtin_nontemporal_load(&(P + (int64_t)r * B)[colc]);
     sv[i] = (S + (int64_t)sm[i] * B)[colc];
+    if constexpr (RESID) rv[i] = (res + (int64_t)nd[i] * ldr)[colc];
   }
   if (col >= B) return;
 #pragma unroll
   for (int i = 0; i < RPC; ++i) {
     if (rb + i * rs < d.n) {
       if constexpr (RESID)
-        (out + (int64_t)nd[i] * ldo)[col] =
-            (TP)((double)(res + (int64_t)nd[i] * ldr)[col] - ((W)pv[i] + (W)sv[i]));
+        (out + (int64_t)nd[i] * ldo)[col] = (TP)((double)rv[i] - ((W)pv[i] + (W)sv[i]));
       else if (UNI)
         __builtin_nontemporal_store((TP)((W)pv[i] + (W)sv[i]), &(out + (int64_t)nd[i] * ldo)[col]);
       else
@@ -1383,19 +1388,33 @@ __global__ __launch_bounds__(WG) void k_chain_diff(DevPoset d, int dir, int cw_r
   const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
   const int64_t colc = col < B ? col : 0;
   const int n = d.n;
-  int nd[RPC], nb[RPC];
+  int nd[RPC], nb[RPC], bound[RPC];
   TY y[RPC], yb[RPC];
+  // in phases, so that each phase's loads are in flight together: the rows'
+  // chains and nodes, the chains' end rows, then the rows of Y
 #pragma unroll
   for (int i = 0; i < RPC; ++i) {
     const int r = min(rbase + i, n - 1);
-    const int c = uni(d.chain_of_row[r]);
+    bound[i] = uni(d.chain_of_row[r]) + (dir > 0 ? 0 : 1);
+    nd[i] = uni(d.node_of_row[r]);
+  }
+#pragma unroll
+  for (int i = 0; i < RPC; ++i) bound[i] = uni(d.chain_off[bound[i]]);
+#pragma unroll
+  for (int i = 0; i < RPC; ++i) {
+    const int r = min(rbase + i, n - 1);
     // the neighbour in the chain (below for dir > 0, above otherwise); the
     // chain's end rows take the row itself and subtract nothing
-    const int rb = dir > 0 ? (r > d.chain_off[c] ? r - 1 : -1) : (r + 1 < d.chain_off[c + 1] ? r + 1 : -1);
+    const int rb = dir > 0 ? (r > bound[i] ? r - 1 : -1) : (r + 1 < bound[i] ? r + 1 : -1);
     nb[i] = uni(rb);
-    nd[i] = uni(d.node_of_row[r]);
     y[i] = Y[(int64_t)r * B + colc];
     yb[i] = Y[(int64_t)(rb >= 0 ? rb : r) * B + colc];
+  }
+  // the iterate, when accumulating a correction, loads with the rows above
+  Tout ov[RPC];
+  if (accumulate) {
+#pragma unroll
+    for (int i = 0; i < RPC; ++i) ov[i] = out[(int64_t)nd[i] * ldo + colc];
   }
   double dmax = 0, fmax = 0;
   bool bad = false;
@@ -1406,7 +1425,7 @@ __global__ __launch_bounds__(WG) void k_chain_diff(DevPoset d, int dir, int cw_r
       W v = (W)y[i];
       if (nb[i] >= 0) v -= (W)yb[i];
       Tout* o = out + (int64_t)nd[i] * ldo + col;
-      const Tout nvv = accumulate ? (Tout)((W)*o + v) : (Tout)v;
+      const Tout nvv = accumulate ? (Tout)((W)ov[i] + v) : (Tout)v;
       *o = nvv;
       if constexpr (std::is_floating_point<W>::value) {
         const double a1 = fabs((double)v), a2 = fabs((double)nvv);
