@@ -1065,11 +1065,14 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
       const int na = ent(j0 + 16 + s8), nb = ent(j0 + 24 + s8);
       TP v[16];
       bool ok[16];
+      int t[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) t[u] = __shfl(u < 8 ? ta : tb, base + (u & 7));
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
-        const int t = __shfl(u < 8 ? ta : tb, base + (u & 7));
-        ok[u] = t >= 0 && t != r0;
-        v[u] = P[(int64_t)(ok[u] ? t : r0) * B + colc];
+        ok[u] = t[u] >= 0 && t[u] != r0;
+        v[u] = P[(int64_t)(ok[u] ? t[u] : r0) * B + colc];
       }
 #pragma unroll
       for (int u = 0; u < 16; ++u)
@@ -1115,16 +1118,22 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
       const int4 na = rec(g0 + 16 + s8), nb = rec(g0 + 24 + s8);
       TP vn[16], vo[16];
       bool okn[16], oko[16];
-      int ue[17];
+      int ue[17], ex[16], ey[16];
+      // all shuffles first (one wait for the lot), then all gathers
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int4& r = q < 8 ? ra : rb;
-        const int ex = __shfl(r.x, base + (q & 7)), ey = __shfl(r.y, base + (q & 7));
+        ex[q] = __shfl(r.x, base + (q & 7));
+        ey[q] = __shfl(r.y, base + (q & 7));
         ue[q] = __shfl(r.z, base + (q & 7)) >> 8;  // -1: no event
-        okn[q] = ex >= 0;
-        oko[q] = ey >= 0;
-        vn[q] = P[(int64_t)(okn[q] ? ex : r0) * B + colc];
-        vo[q] = P[(int64_t)(oko[q] ? ey : r0) * B + colc];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        okn[q] = ex[q] >= 0;
+        oko[q] = ey[q] >= 0;
+        vn[q] = P[(int64_t)(okn[q] ? ex[q] : r0) * B + colc];
+        vo[q] = P[(int64_t)(oko[q] ? ey[q] : r0) * B + colc];
       }
       ue[16] = __shfl(na.z, base) >> 8;
 #pragma unroll
