@@ -302,12 +302,29 @@ def leg_large(px, dev, steps):
     exact = bool(torch.equal(px.mobius(L, gi), fi))
     exact_adj = bool(torch.equal(px.mobius_adjoint(L, px.zeta_adjoint(L, fi)), fi))
     growth = f64_growth(px, L, q.n, dev)
+    # autograd through both transforms, loss = Σ w·T(x): zeta's backward is the adjoint walk;
+    # Möbius's backward is M^T w, which overflows float32 here like M itself
+    from paper_2211_13706_amd.autograd import mobius_fn, zeta_fn
+    fa = f.clone().requires_grad_(True)
+    wz = torch.randn_like(f)
+
+    def zstep():
+        fa.grad = None
+        (zeta_fn(L, fa) * wz).sum().backward()
+    t_ag = _time(zstep, steps, sync)
+    ga = g.clone().requires_grad_(True)
+    try:
+        (mobius_fn(L, ga) * wz).sum().backward()
+        mob_bwd = "finite" if bool(torch.isfinite(ga.grad).all()) else "nonfinite"
+    except px.PosetxError as e:
+        mob_bwd = e.name
     return {"workload": "n=8388608, k=32, 3 cross edges, B=16", "preprocess_s": round(t_prep, 2),
             "levels": L.info["levels_down"], "zeta_f32_ms": round(tz * 1e3, 4),
             "zeta_node_rhs_per_s": q.n * Bl / tz, "mobius_int64_ms": round(tm * 1e3, 4),
             "us_per_level": round(tm * 1e6 / max(1, L.info["levels_down"]), 2),
             "int64_roundtrip_exact": exact, "int64_adjoint_roundtrip_exact": exact_adj,
             "mobius_f64_growth": growth,
+            "autograd_zeta_fwd_bwd_ms": round(t_ag * 1e3, 4), "autograd_mobius_bwd": mob_bwd,
             "f32_roundtrip_rel_err": err, "f32_refine_report": rep}
 
 
