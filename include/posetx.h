@@ -77,6 +77,10 @@ typedef enum {
 #define PX_BUILD_HOST_ONLY 0x1u      /* preprocess on the host only: no device buffers, no compute  */
 #define PX_BUILD_NO_ADJOINT 0x2u     /* skip the up-niv map and its levels (adjoints unavailable)   */
 #define PX_BUILD_LEVELS_MIRSKY 0x4u  /* schedule Möbius over Mirsky antichains (§4, Alg. 5/6)       */
+#define PX_BUILD_SPARSE_NIV 0x8u     /* keep the niv maps as rows of their finite entries (nnz(N)
+                                        storage, §2.4) instead of dense [n, k] rows; automatic for
+                                        more than 256 chains.  Such posets take the one-thread-per-
+                                        row gathers and level solves and cannot join a batch     */
 
 typedef struct {
   int64_t n;              /* elements                                                   */
@@ -101,6 +105,8 @@ typedef struct {
   int32_t chains_planted; /* 1 if the caller supplied the chains                        */
   int32_t device;
   double t_validate, t_chains, t_niv, t_levels, t_upload;  /* preprocessing seconds      */
+  int32_t niv_sparse;     /* 1 if the niv maps are kept sparse (PX_BUILD_SPARSE_NIV)    */
+  int32_t reserved;
 } px_info;
 
 typedef struct {
@@ -141,6 +147,11 @@ px_status px_poset_info(const px_poset* p, px_info* out);
  *   levels: level[n] of every node in the Möbius schedule (up != 0: adjoint schedule). */
 px_status px_poset_chains(const px_poset* p, int32_t* chain_of, int32_t* chain_pos);
 px_status px_poset_niv(const px_poset* p, int up, int32_t* out);
+/* The same map by rows of its finite entries (N of §2.4 in CSR form, node order):
+ * the entries of node x are nodes[ptr[x] .. ptr[x+1]), the node ids niv_j(x) in
+ * ascending chain j.  ptr: n+1 entries; nodes: px_info.nnz_niv (up: nnz_niv_up)
+ * entries.  Available for dense and sparse handles. */
+px_status px_poset_niv_csr(const px_poset* p, int up, int64_t* ptr, int32_t* nodes);
 px_status px_poset_levels(const px_poset* p, int up, int32_t* level);
 
 /* Grow the workspace for dtype and B right-hand sides now, so that later calls with

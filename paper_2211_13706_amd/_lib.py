@@ -16,6 +16,7 @@ PX_I64, PX_F32, PX_F64 = 0, 1, 2
 PX_BUILD_HOST_ONLY = 0x1
 PX_BUILD_NO_ADJOINT = 0x2
 PX_BUILD_LEVELS_MIRSKY = 0x4
+PX_BUILD_SPARSE_NIV = 0x8
 
 STATUS = {0: "PX_OK", 1: "PX_EINVAL", 2: "PX_ECYCLE", 3: "PX_ECHAIN", 4: "PX_ENOMEM", 5: "PX_EHIP",
           6: "PX_EUNSUPPORTED", 7: "PX_ENONFINITE", 8: "PX_ENOTCONV"}
@@ -25,7 +26,7 @@ EXPORTS = [
     "px_poset_levels", "px_reserve", "px_zeta", "px_zeta_adjoint", "px_mobius", "px_mobius_adjoint",
     "px_batch_build", "px_batch_free", "px_batch_reserve", "px_batch_rows", "px_zeta_batched",
     "px_zeta_adjoint_batched", "px_last_error", "px_version", "px_profile", "px_profile_read",
-    "px_profile_phase_name", "px_autotune", "px_batch_autotune",
+    "px_profile_phase_name", "px_autotune", "px_batch_autotune", "px_poset_niv_csr",
 ]
 
 
@@ -42,7 +43,8 @@ class Info(ctypes.Structure):
         "mirsky_levels", "udep_levels", "device_bytes", "walk_runs", "walk_events", "walk_snapshots", "walk_T",
         "walk_emax", "walk_rows_distinct", "walk_row_loads")] + [
         ("chains_planted", ctypes.c_int32), ("device", ctypes.c_int32)] + [
-        (name, ctypes.c_double) for name in ("t_validate", "t_chains", "t_niv", "t_levels", "t_upload")]
+        (name, ctypes.c_double) for name in ("t_validate", "t_chains", "t_niv", "t_levels", "t_upload")] + [
+        ("niv_sparse", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -74,6 +76,7 @@ def _declare(lib):
         "px_poset_info": [P, ctypes.POINTER(Info)],
         "px_poset_chains": [P, P, P],
         "px_poset_niv": [P, i32, P],
+        "px_poset_niv_csr": [P, i32, P, P],
         "px_poset_levels": [P, i32, P],
         "px_reserve": [P, i32, i64],
         "px_zeta": [P, i32, P, i64, P, i64, i64, P],

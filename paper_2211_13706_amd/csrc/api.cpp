@@ -485,7 +485,8 @@ hipError_t run_gather(const px::DevPoset& d, bool up, px::ElemType tp, const voi
                       hipStream_t s) {
   if (prof::on) {
     prof::WalkHook hook;
-    if (snaps) return px::launch_gather(d, up, tp, P, B, tout, out, ldo, tres, resid, ldr, snaps, &hook, s);
+    if (snaps && !d.nivp[up ? 1 : 0])
+      return px::launch_gather(d, up, tp, P, B, tout, out, ldo, tres, resid, ldr, snaps, &hook, s);
     prof::Scope sc(prof::GATHER, s);
     return px::launch_gather(d, up, tp, P, B, tout, out, ldo, tres, resid, ldr, nullptr, nullptr, s);
   }
@@ -528,6 +529,8 @@ struct px_poset {
           *d_niv_up = nullptr, *d_lev_down = nullptr, *d_lev_up = nullptr, *d_segoff = nullptr, *d_order = nullptr,
           *d_tiles = nullptr, *d_lev_niv[2] = {nullptr, nullptr}, *d_lev_node[2] = {nullptr, nullptr},
           *d_walk[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
+  int32_t* d_nivr[2] = {nullptr, nullptr};  // sparse niv rows: entries and row offsets
+  int64_t* d_nivp[2] = {nullptr, nullptr};
   int64_t ntiles[7] = {0, 0, 0, 0, 0, 0, 0};
   int64_t nevents[2] = {0, 0};
   int32_t nsnap[2] = {0, 0};
@@ -565,8 +568,11 @@ namespace {
 void free_poset_device(px_poset* p) {
   int32_t* bufs[] = {p->d_node_of_row, p->d_chain_of_row, p->d_chain_off, p->d_niv, p->d_niv_up,
                      p->d_lev_down,     p->d_lev_up,       p->d_segoff,    p->d_order, p->d_tiles,
-                     p->d_lev_niv[0],   p->d_lev_niv[1],   p->d_lev_node[0], p->d_lev_node[1]};
+                     p->d_lev_niv[0],   p->d_lev_niv[1],   p->d_lev_node[0], p->d_lev_node[1],
+                     p->d_nivr[0],      p->d_nivr[1]};
   for (int32_t* b : bufs)
+    if (b) (void)hipFree(b);
+  for (int64_t* b : p->d_nivp)
     if (b) (void)hipFree(b);
   for (auto& dir : p->d_walk)
     for (int32_t*& b : dir)
@@ -945,7 +951,8 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
   std::string msg;
   int rc;
   try {
-    rc = px::preprocess(n, indptr, indices, chain_of, chain_pos, p->has_up, p->mirsky, p->prep, msg);
+    rc = px::preprocess(n, indptr, indices, chain_of, chain_pos, p->has_up, p->mirsky,
+                        (flags & PX_BUILD_SPARSE_NIV) != 0, p->prep, msg);
   } catch (const std::bad_alloc&) {
     rc = PX_ENOMEM;
     msg = "host allocation failed during preprocessing";
@@ -968,12 +975,21 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
     hipError_t e = upload(&p->d_node_of_row, P.node_of_row.data(), P.node_of_row.size(), b);
     if (e == hipSuccess) e = upload(&p->d_chain_of_row, P.chain_of_row.data(), P.chain_of_row.size(), b);
     if (e == hipSuccess) e = upload(&p->d_chain_off, P.chain_off.data(), P.chain_off.size(), b);
-    if (e == hipSuccess) e = upload(&p->d_niv, P.niv.data(), P.niv.size(), b);
-    if (e == hipSuccess && p->has_up) e = upload(&p->d_niv_up, P.niv_up.data(), P.niv_up.size(), b);
+    if (!P.sparse) {
+      if (e == hipSuccess) e = upload(&p->d_niv, P.niv.data(), P.niv.size(), b);
+      if (e == hipSuccess && p->has_up) e = upload(&p->d_niv_up, P.niv_up.data(), P.niv_up.size(), b);
+    } else {
+      for (int m = 0; m < (p->has_up ? 2 : 1) && e == hipSuccess; ++m) {
+        e = upload(&p->d_nivp[m], P.nivp[m].data(), P.nivp[m].size(), b);
+        if (e == hipSuccess) e = upload(&p->d_nivr[m], P.nivr[m].data(), P.nivr[m].size(), b);
+        p->dp.nivp[m] = p->d_nivp[m];
+        p->dp.nivr[m] = p->d_nivr[m];
+      }
+    }
     if (e == hipSuccess) e = upload(&p->d_lev_down, P.lev_down_rows.data(), P.lev_down_rows.size(), b);
     if (e == hipSuccess && p->has_up) e = upload(&p->d_lev_up, P.lev_up_rows.data(), P.lev_up_rows.size(), b);
     // level-ordered niv rows and node ids for the uniform level solve
-    for (int dir = 0; dir < 2 && e == hipSuccess && P.k <= 64; ++dir) {
+    for (int dir = 0; dir < 2 && e == hipSuccess && P.k <= 64 && !P.sparse; ++dir) {
       if (dir == 1 && !p->has_up) break;
       const std::vector<int32_t>& lr = dir ? P.lev_up_rows : P.lev_down_rows;
       const std::vector<int32_t>& nv = dir ? P.niv_up : P.niv;
@@ -1007,7 +1023,8 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
           o += p->ntiles[i];
         }
     }
-    if (e == hipSuccess) e = set_walk(p, kWalkT, kWalkEvents);
+    // the walking gathers read dense niv rows; sparse rows take the plain gather
+    if (e == hipSuccess && !P.sparse) e = set_walk(p, kWalkT, kWalkEvents);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       free_poset_device(p);
@@ -1069,6 +1086,8 @@ px_status px_poset_info(const px_poset* p, px_info* o) {
   o->t_niv = P.t_niv;
   o->t_levels = P.t_levels;
   o->t_upload = p->t_upload;
+  o->niv_sparse = P.sparse ? 1 : 0;
+  o->reserved = 0;
   return PX_OK;
 }
 
@@ -1083,10 +1102,42 @@ px_status px_poset_niv(const px_poset* p, int up, int32_t* out) {
   if (!p || (p->prep.n > 0 && !out)) return fail(PX_EINVAL, "null argument");
   if (up && !p->has_up) return fail(PX_EUNSUPPORTED, "poset was built with PX_BUILD_NO_ADJOINT");
   const px::Prep& P = p->prep;
+  if (P.sparse) {
+    std::fill(out, out + P.n * P.k, -1);
+    const std::vector<int64_t>& ep = P.nivp[up ? 1 : 0];
+    const std::vector<int32_t>& er = P.nivr[up ? 1 : 0];
+    for (int64_t x = 0; x < P.n; ++x) {
+      const int32_t r = P.row_of_node[x];
+      for (int64_t e = ep[r]; e < ep[r + 1]; ++e) out[x * P.k + P.chain_of_row[er[e]]] = P.node_of_row[er[e]];
+    }
+    return PX_OK;
+  }
   const std::vector<int32_t>& nv = up ? P.niv_up : P.niv;
   for (int64_t x = 0; x < P.n; ++x) {
     const int32_t* R = &nv[(size_t)P.row_of_node[x] * P.k];
     for (int64_t j = 0; j < P.k; ++j) out[x * P.k + j] = R[j] >= 0 ? P.node_of_row[R[j]] : -1;
+  }
+  return PX_OK;
+}
+
+px_status px_poset_niv_csr(const px_poset* p, int up, int64_t* ptr, int32_t* nodes) {
+  if (!p || !ptr || (p->prep.n > 0 && !nodes && (up ? p->prep.nnz_niv_up : p->prep.nnz_niv) > 0))
+    return fail(PX_EINVAL, "null argument");
+  if (up && !p->has_up) return fail(PX_EUNSUPPORTED, "poset was built with PX_BUILD_NO_ADJOINT");
+  const px::Prep& P = p->prep;
+  const int m = up ? 1 : 0;
+  int64_t o = 0;
+  ptr[0] = 0;
+  for (int64_t x = 0; x < P.n; ++x) {
+    const int32_t r = P.row_of_node[x];
+    if (P.sparse) {
+      for (int64_t e = P.nivp[m][r]; e < P.nivp[m][r + 1]; ++e) nodes[o++] = P.node_of_row[P.nivr[m][e]];
+    } else {
+      const int32_t* R = &(up ? P.niv_up : P.niv)[(size_t)r * P.k];
+      for (int64_t j = 0; j < P.k; ++j)
+        if (R[j] >= 0) nodes[o++] = P.node_of_row[R[j]];
+    }
+    ptr[x + 1] = o;
   }
   return PX_OK;
 }
@@ -1137,7 +1188,7 @@ px_status px_autotune(px_poset* p, int dtype, int64_t B, px_tune_report* rep) {
   if (B < 1) return fail(PX_EINVAL, "B must be >= 1");
   const int64_t n = p->prep.n;
   if (rep) *rep = px_tune_report{p->walk_T, p->walk_emax, p->dp.walk[0].cw, 0.0, 0.0, 0};
-  if (n == 0) return PX_OK;
+  if (n == 0 || p->prep.sparse) return PX_OK;  // sparse rows: nothing to tune
   DeviceGuard dg(p->device);
   if (!dg.ok) return fail(PX_EHIP, "hipSetDevice failed");
   std::lock_guard<std::mutex> lk(tune_mu);
@@ -1215,6 +1266,7 @@ px_status px_batch_build(int count, px_poset* const* posets, px_batch** out) {
   for (int i = 0; i < count; ++i) {
     if (!posets[i]) return fail(PX_EINVAL, "null poset in batch");
     if (posets[i]->host_only) return fail(PX_EUNSUPPORTED, "host-only poset in batch");
+    if (posets[i]->prep.sparse) return fail(PX_EUNSUPPORTED, "batches take posets with dense niv rows");
     if (posets[i]->device != dev) return fail(PX_EINVAL, "posets of a batch must share a device");
     has_up = has_up && posets[i]->has_up;
   }

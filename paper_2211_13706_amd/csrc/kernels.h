@@ -59,6 +59,10 @@ struct DevPoset {
   int32_t nchains = 0;
   const int32_t* niv = nullptr;         // [n*k] or, for a batch, at niv_off[poset]
   const int32_t* niv_up = nullptr;
+  // sparse niv rows, [0] niv / [1] up-niv (single posets; nullptr: dense):
+  // row r's finite entries are nivr[m][nivp[m][r] .. nivp[m][r + 1]), ascending
+  const int64_t* nivp[2] = {nullptr, nullptr};
+  const int32_t* nivr[2] = {nullptr, nullptr};
   const int32_t* segoff = nullptr;      // [7][nchains+1] tile offsets per tile height
   // per tile height (as segoff): every tile's {first row, end row of its chain}
   // (nullable), and the most tiles any chain has
@@ -106,7 +110,8 @@ hipError_t launch_chain_scan_onepass(const DevPoset& d, int dir, ElemType tin, c
                                      ElemType tout, void* P, int64_t B, void* aux, int64_t ntiles, int* sync,
                                      int spin_limit, hipStream_t s);
 
-// Gather-reduce U c: out[node(r)] = Σ_j P[nv[r][j]] over finite entries.  With
+// Gather-reduce U c: out[node(r)] = Σ_j P[nv[r][j]] over finite entries, in
+// chain order (dense rows, or the sparse rows nivp / nivr when present).  With
 // resid != nullptr (float64 P only): out = resid[node] - Σ (residual of a
 // refinement step; resid has element type tres, leading dim ldr).
 // Called around the two kernels of the walking gather (0 = events, 1 = combine),

@@ -858,14 +858,15 @@ __global__ void k_fill_i32(int* p, int64_t cnt, int v) {
 
 __device__ inline double fmax_(double a, double b) { return a > b ? a : b; }
 
-// Σ over a row's k niv entries of M[entry][col], skipping -1 and `skip`:
-// 32 entries load together, then their 32 rows together, instead of one entry
-// and one dependent row at a time.  Skipped entries read row zr of M, which
-// every producer of M keeps zero, so that no load is behind a branch.
-template <typename TM, typename W>
+// acc plus (SUB: minus) M[entry][col] for a row's k niv entries in chain
+// order, one at a time, skipping -1 and `skip`: 32 entries load together,
+// then their 32 rows together, instead of one entry and one dependent row at a
+// time.  Skipped entries read row zr of M, which every producer of M keeps
+// zero, so that no load is behind a branch (adding or subtracting that zero
+// leaves acc unchanged).
+template <typename TM, typename W, bool SUB = false>
 __device__ inline W niv_sum(const int32_t* __restrict__ nr, int k, int64_t skip, int64_t zr,
-                            const TM* __restrict__ M, int64_t B, int64_t col) {
-  W acc = W(0);
+                            const TM* __restrict__ M, int64_t B, int64_t col, W acc = W(0)) {
   for (int j0 = 0; j0 < k; j0 += 32) {
     int32_t t[32];
 #pragma unroll
@@ -874,7 +875,26 @@ __device__ inline W niv_sum(const int32_t* __restrict__ nr, int k, int64_t skip,
 #pragma unroll
     for (int u = 0; u < 32; ++u) v[u] = M[(t[u] >= 0 && t[u] != skip ? (int64_t)t[u] : zr) * B + col];
 #pragma unroll
-    for (int u = 0; u < 32; ++u) acc += (W)v[u];
+    for (int u = 0; u < 32; ++u) acc = SUB ? acc - (W)v[u] : acc + (W)v[u];
+  }
+  return acc;
+}
+
+// The same over a sparse row: its finite entries er[e0 .. e1) (ascending
+// chain order), 16 at a time.  The terms and their order are those of the
+// dense row, so results agree bit for bit with niv_sum.
+template <typename TM, typename W, bool SUB = false>
+__device__ inline W csr_sum(const int32_t* __restrict__ er, int64_t e0, int64_t e1, int64_t skip, int64_t zr,
+                            const TM* __restrict__ M, int64_t B, int64_t col, W acc = W(0)) {
+  for (int64_t e = e0; e < e1; e += 16) {
+    int32_t t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) t[u] = e + u < e1 ? er[e + u] : -1;
+    TM v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = M[(t[u] >= 0 && t[u] != skip ? (int64_t)t[u] : zr) * B + col];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc = SUB ? acc - (W)v[u] : acc + (W)v[u];
   }
   return acc;
 }
@@ -890,6 +910,27 @@ __global__ __launch_bounds__(WG) void k_gather(DevPoset d, const int32_t* __rest
   if (r >= d.n || col >= B) return;
   const int k = d.k;
   const W acc = niv_sum<TP, W>(nv + r * k, k, -1, d.n, P, B, col);  // row n of P is zero
+  const int64_t node = d.node_of_row[r];
+  if constexpr (RESID) {
+    out[node * ldo + col] = (Tout)((double)res[node * ldr + col] - (double)acc);
+  } else {
+    out[node * ldo + col] = (Tout)acc;
+  }
+}
+
+// The gather over sparse niv rows (CSR: ep[r] .. ep[r + 1] index er), one
+// thread per (row, column).
+template <typename TP, typename Tout, typename Tres, bool RESID>
+__global__ __launch_bounds__(WG) void k_gather_csr(DevPoset d, const int64_t* __restrict__ ep,
+                                                   const int32_t* __restrict__ er, int cw, const TP* __restrict__ P,
+                                                   int64_t B, Tout* __restrict__ out, int64_t ldo,
+                                                   const Tres* __restrict__ res, int64_t ldr) {
+  using W = typename Wide<TP>::W;
+  const int RG = WG / cw;
+  const int64_t r = (int64_t)blockIdx.x * RG + threadIdx.x / cw;
+  const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
+  if (r >= d.n || col >= B) return;
+  const W acc = csr_sum<TP, W>(er, ep[r], ep[r + 1], -1, d.n, P, B, col);  // row n of P is zero
   const int64_t node = d.node_of_row[r];
   if constexpr (RESID) {
     out[node * ldo + col] = (Tout)((double)res[node * ldr + col] - (double)acc);
@@ -1322,7 +1363,24 @@ __global__ __launch_bounds__(WG) void k_usolve(DevPoset d, const int32_t* __rest
   if (i >= cnt || col >= B) return;
   const int64_t r = rows[i];
   const int64_t node = d.node_of_row[r];
-  const W acc = (W)g[node * ldg + col] - niv_sum<TY, W>(nv + r * d.k, d.k, r, d.n, Y, B, col);
+  const W acc = niv_sum<TY, W, true>(nv + r * d.k, d.k, r, d.n, Y, B, col, (W)g[node * ldg + col]);
+  Y[r * B + col] = (TY)acc;
+}
+
+// The same over sparse niv rows (CSR ep / er).
+template <typename Tin, typename TY>
+__global__ __launch_bounds__(WG) void k_usolve_csr(DevPoset d, const int64_t* __restrict__ ep,
+                                                   const int32_t* __restrict__ er, const int32_t* __restrict__ rows,
+                                                   int64_t cnt, int cw, const Tin* __restrict__ g, int64_t ldg,
+                                                   TY* __restrict__ Y, int64_t B) {
+  using W = typename Wide<TY>::W;
+  const int RG = WG / cw;
+  const int64_t i = (int64_t)blockIdx.x * RG + threadIdx.x / cw;
+  const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
+  if (i >= cnt || col >= B) return;
+  const int64_t r = rows[i];
+  const int64_t node = d.node_of_row[r];
+  const W acc = csr_sum<TY, W, true>(er, ep[r], ep[r + 1], r, d.n, Y, B, col, (W)g[node * ldg + col]);
   Y[r * B + col] = (TY)acc;
 }
 
@@ -1330,7 +1388,8 @@ __global__ __launch_bounds__(WG) void k_usolve(DevPoset d, const int32_t* __rest
 // niv entries are wave-uniform (scalar registers), its k - 1 dependencies go
 // out all at once from scalar row bases, and the own and missing entries read
 // row n of Y, which launch_usolve_begin sets to zero.  Same subtraction order
-// as k_usolve (a zero row subtracts nothing), so results are identical.
+// as k_usolve (g minus one entry at a time, in chain order; a zero row
+// subtracts nothing), so results are identical.
 //
 // With level-ordered copies of the niv rows and node ids (lnv, lnode; the
 // level starts at position i0), a row's entries, node and index load together
@@ -1667,6 +1726,29 @@ hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P,
   const dim3 g = grid2(d.n, cw, B);
   const int32_t* nv = up ? d.niv_up : d.niv;
   if (resid && (tp != E_F64 || tout != E_F64)) return hipErrorInvalidValue;
+  if (const int64_t* ep = d.nivp[up ? 1 : 0]) {  // sparse niv rows
+    const int32_t* er = d.nivr[up ? 1 : 0];
+    if (resid && tres == E_F32)
+      hipLaunchKernelGGL((k_gather_csr<double, double, float, true>), g, dim3(WG), 0, s, d, ep, er, cw,
+                         (const double*)P, B, (double*)out, ldo, (const float*)resid, ldr);
+    else if (resid && tres == E_F64)
+      hipLaunchKernelGGL((k_gather_csr<double, double, double, true>), g, dim3(WG), 0, s, d, ep, er, cw,
+                         (const double*)P, B, (double*)out, ldo, (const double*)resid, ldr);
+    else if (resid)
+      return hipErrorInvalidValue;
+    else if (tp == E_I64 && tout == E_I64)
+      hipLaunchKernelGGL((k_gather_csr<int64_t, int64_t, int64_t, false>), g, dim3(WG), 0, s, d, ep, er, cw,
+                         (const int64_t*)P, B, (int64_t*)out, ldo, (const int64_t*)nullptr, 0);
+    else if (tp == E_F32 && tout == E_F32)
+      hipLaunchKernelGGL((k_gather_csr<float, float, float, false>), g, dim3(WG), 0, s, d, ep, er, cw,
+                         (const float*)P, B, (float*)out, ldo, (const float*)nullptr, 0);
+    else if (tp == E_F64 && tout == E_F64)
+      hipLaunchKernelGGL((k_gather_csr<double, double, double, false>), g, dim3(WG), 0, s, d, ep, er, cw,
+                         (const double*)P, B, (double*)out, ldo, (const double*)nullptr, 0);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   // the walking gather when its tables and snapshot scratch are there
   const WalkTables& w = d.walk[up ? 1 : 0];
   if (w.runs && snaps && tp == tout && (B <= 64 || (!d.poset_of_row && d.k <= 64))) {
@@ -1729,6 +1811,24 @@ hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_ro
   const int cw = col_width(B);
   const dim3 gr = grid2(cnt, cw, B);
   const int32_t* nv = up ? d.niv_up : d.niv;
+  if (const int64_t* ep = d.nivp[up ? 1 : 0]) {  // sparse niv rows
+    const int32_t* er = d.nivr[up ? 1 : 0];
+    if (tin == E_I64 && ty == E_I64)
+      hipLaunchKernelGGL((k_usolve_csr<int64_t, int64_t>), gr, dim3(WG), 0, s, d, ep, er, lev_rows, cnt, cw,
+                         (const int64_t*)g, ldg, (int64_t*)Y, B);
+    else if (tin == E_F32 && ty == E_F32)
+      hipLaunchKernelGGL((k_usolve_csr<float, float>), gr, dim3(WG), 0, s, d, ep, er, lev_rows, cnt, cw,
+                         (const float*)g, ldg, (float*)Y, B);
+    else if (tin == E_F64 && ty == E_F32)
+      hipLaunchKernelGGL((k_usolve_csr<double, float>), gr, dim3(WG), 0, s, d, ep, er, lev_rows, cnt, cw,
+                         (const double*)g, ldg, (float*)Y, B);
+    else if (tin == E_F64 && ty == E_F64)
+      hipLaunchKernelGGL((k_usolve_csr<double, double>), gr, dim3(WG), 0, s, d, ep, er, lev_rows, cnt, cw,
+                         (const double*)g, ldg, (double*)Y, B);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   if (cw == 64 && d.k <= 64 && !d.poset_of_row && cnt < INT32_MAX) {
     const dim3 gu((unsigned)((cnt + (WG / 64) - 1) / (WG / 64)), (unsigned)((B + 63) / 64));
     const int c = (int)cnt;

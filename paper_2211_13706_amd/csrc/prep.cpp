@@ -103,7 +103,8 @@ void hopcroft_karp(int64_t n, const int64_t* indptr, const int32_t* indices, std
 }  // namespace
 
 int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const int32_t* chain_of,
-               const int32_t* chain_pos, bool want_up, bool mirsky_schedule, Prep& P, std::string& msg) {
+               const int32_t* chain_pos, bool want_up, bool mirsky_schedule, bool want_sparse, Prep& P,
+               std::string& msg) {
   double t0 = now_s();
   if (n < 0 || n >= INT32_MAX) {
     msg = "n out of range";
@@ -244,42 +245,100 @@ int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const i
   // is the largest row of chain j reachable from x: a row-wise max over the
   // children, and x itself on its own chain.  The own-chain entry before x is
   // inserted must be the row just below x: this checks planted chains.
-  P.niv.assign((size_t)n * k, -1);
-  for (int64_t h = 0; h < n; ++h) {
-    int32_t x = order[h];
-    int32_t r = P.row_of_node[x];
-    int32_t* R = &P.niv[(size_t)r * k];
-    for (int64_t e = indptr[x]; e < indptr[x + 1]; ++e) {
-      const int32_t* Rz = &P.niv[(size_t)P.row_of_node[indices[e]] * k];
-      for (int64_t j = 0; j < k; ++j) R[j] = std::max(R[j], Rz[j]);
-    }
-    int32_t c = P.chain_of[x];
-    int32_t expect = P.chain_pos[x] > 0 ? r - 1 : -1;
-    if (R[c] != expect) {
-      msg = "chain " + std::to_string(c) + " is not totally ordered at position " +
-            std::to_string(P.chain_pos[x]) + " (node " + std::to_string(x) + ")";
-      return PX_ECHAIN;
-    }
-    R[c] = r;
-  }
-  for (size_t i = 0; i < P.niv.size(); ++i) P.nnz_niv += P.niv[i] >= 0;
-  if (want_up) {
-    // Dual order: the lowest element of chain j above x is a row-wise min over parents.
-    P.niv_up.assign((size_t)n * k, INT32_MAX);
-    for (int64_t h = n; h-- > 0;) {
+  auto chain_error = [&](int64_t x) {
+    msg = "chain " + std::to_string(P.chain_of[x]) + " is not totally ordered at position " +
+          std::to_string(P.chain_pos[x]) + " (node " + std::to_string(x) + ")";
+    return PX_ECHAIN;
+  };
+  P.sparse = want_sparse || k > kSparseNivChains;
+  if (!P.sparse) {
+    P.niv.assign((size_t)n * k, -1);
+    for (int64_t h = 0; h < n; ++h) {
       int32_t x = order[h];
       int32_t r = P.row_of_node[x];
-      int32_t* R = &P.niv_up[(size_t)r * k];
-      for (int64_t e = rptr[x]; e < rptr[x + 1]; ++e) {
-        const int32_t* Rp = &P.niv_up[(size_t)P.row_of_node[ridx[e]] * k];
-        for (int64_t j = 0; j < k; ++j) R[j] = std::min(R[j], Rp[j]);
+      int32_t* R = &P.niv[(size_t)r * k];
+      for (int64_t e = indptr[x]; e < indptr[x + 1]; ++e) {
+        const int32_t* Rz = &P.niv[(size_t)P.row_of_node[indices[e]] * k];
+        for (int64_t j = 0; j < k; ++j) R[j] = std::max(R[j], Rz[j]);
       }
-      R[P.chain_of[x]] = r;
+      int32_t c = P.chain_of[x];
+      int32_t expect = P.chain_pos[x] > 0 ? r - 1 : -1;
+      if (R[c] != expect) return chain_error(x);
+      R[c] = r;
     }
-    for (size_t i = 0; i < P.niv_up.size(); ++i) {
-      if (P.niv_up[i] == INT32_MAX) P.niv_up[i] = -1;
-      P.nnz_niv_up += P.niv_up[i] >= 0;
+    for (size_t i = 0; i < P.niv.size(); ++i) P.nnz_niv += P.niv[i] >= 0;
+    if (want_up) {
+      // Dual order: the lowest element of chain j above x is a row-wise min over parents.
+      P.niv_up.assign((size_t)n * k, INT32_MAX);
+      for (int64_t h = n; h-- > 0;) {
+        int32_t x = order[h];
+        int32_t r = P.row_of_node[x];
+        int32_t* R = &P.niv_up[(size_t)r * k];
+        for (int64_t e = rptr[x]; e < rptr[x + 1]; ++e) {
+          const int32_t* Rp = &P.niv_up[(size_t)P.row_of_node[ridx[e]] * k];
+          for (int64_t j = 0; j < k; ++j) R[j] = std::min(R[j], Rp[j]);
+        }
+        R[P.chain_of[x]] = r;
+      }
+      for (size_t i = 0; i < P.niv_up.size(); ++i) {
+        if (P.niv_up[i] == INT32_MAX) P.niv_up[i] = -1;
+        P.nnz_niv_up += P.niv_up[i] >= 0;
+      }
     }
+  } else {
+    // The same recursion on rows that list only their finite entries (nnz(N)
+    // instead of n * k storage): a row is the per-chain max (min for the dual
+    // map) over its children's (parents') rows, merged through a k-wide
+    // scratch row, plus its own entry.  Rows are built in topological order
+    // into a pool and then laid out by row.
+    std::vector<int32_t> acc(k, -1), touched;
+    touched.reserve(k);
+    auto build = [&](bool up) -> int {
+      std::vector<int64_t> st(n), ln(n);
+      std::vector<int32_t> pool;
+      pool.reserve((size_t)n * 4);
+      for (int64_t h = 0; h < n; ++h) {
+        const int32_t x = order[up ? n - 1 - h : h];
+        const int32_t r = P.row_of_node[x];
+        touched.clear();
+        const int64_t e0 = up ? rptr[x] : indptr[x], e1 = up ? rptr[x + 1] : indptr[x + 1];
+        for (int64_t e = e0; e < e1; ++e) {
+          const int32_t rz = P.row_of_node[up ? ridx[e] : indices[e]];
+          for (int64_t i = st[rz], ie = st[rz] + ln[rz]; i < ie; ++i) {
+            const int32_t v = pool[i];
+            int32_t& a = acc[P.chain_of_row[v]];
+            if (a < 0) {
+              touched.push_back(P.chain_of_row[v]);
+              a = v;
+            } else {
+              a = up ? std::min(a, v) : std::max(a, v);
+            }
+          }
+        }
+        const int32_t c = P.chain_of[x];
+        if (!up && acc[c] != (P.chain_pos[x] > 0 ? r - 1 : -1)) return chain_error(x);
+        if (acc[c] < 0) touched.push_back(c);
+        acc[c] = r;
+        std::sort(touched.begin(), touched.end());
+        st[r] = (int64_t)pool.size();
+        ln[r] = (int64_t)touched.size();
+        for (int32_t j : touched) {
+          pool.push_back(acc[j]);
+          acc[j] = -1;
+        }
+      }
+      std::vector<int64_t>& ptr = P.nivp[up ? 1 : 0];
+      std::vector<int32_t>& ent = P.nivr[up ? 1 : 0];
+      ptr.assign(n + 1, 0);
+      for (int64_t r = 0; r < n; ++r) ptr[r + 1] = ptr[r] + ln[r];
+      ent.resize(pool.size());
+      for (int64_t r = 0; r < n; ++r) std::copy_n(pool.begin() + st[r], ln[r], ent.begin() + ptr[r]);
+      (up ? P.nnz_niv_up : P.nnz_niv) = (int64_t)ent.size();
+      return PX_OK;
+    };
+    int rc = build(false);
+    if (rc == PX_OK && want_up) rc = build(true);
+    if (rc != PX_OK) return rc;
   }
   double t3 = now_s();
   P.t_niv = t3 - t2;
@@ -297,20 +356,22 @@ int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const i
     std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
     for (int64_t r = 0; r < n; ++r) rows[fill[lev[r]]++] = (int32_t)r;
   };
-  auto udep_levels = [&](const std::vector<int32_t>& nv, bool up, std::vector<int32_t>& lev) {
+  auto udep_levels = [&](bool up, std::vector<int32_t>& lev) {
     lev.assign(n, 0);
+    const std::vector<int32_t>& nv = up ? P.niv_up : P.niv;
     for (int64_t h = 0; h < n; ++h) {
       int32_t x = order[up ? n - 1 - h : h];
       int32_t r = P.row_of_node[x];
-      const int32_t* R = &nv[(size_t)r * k];
+      const int32_t* R = P.sparse ? P.nivr[up ? 1 : 0].data() + P.nivp[up ? 1 : 0][r] : &nv[(size_t)r * k];
+      const int64_t len = P.sparse ? P.nivp[up ? 1 : 0][r + 1] - P.nivp[up ? 1 : 0][r] : k;
       int32_t l = 0;
-      for (int64_t j = 0; j < k; ++j)
+      for (int64_t j = 0; j < len; ++j)
         if (R[j] >= 0 && R[j] != r) l = std::max(l, lev[R[j]] + 1);
       lev[r] = l;
     }
   };
   std::vector<int32_t> ud;
-  udep_levels(P.niv, false, ud);
+  udep_levels(false, ud);
   for (int64_t r = 0; r < n; ++r) P.udep = std::max<int64_t>(P.udep, ud[r] + 1);
   if (mirsky_schedule) {
     P.lev_down.resize(n);
@@ -330,7 +391,7 @@ int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const i
       P.lev_up.resize(n);
       for (int64_t x = 0; x < n; ++x) P.lev_up[P.row_of_node[x]] = comir[x];
     } else {
-      udep_levels(P.niv_up, true, P.lev_up);
+      udep_levels(true, P.lev_up);
     }
     bucket(P.lev_up, P.lev_up_ptr, P.lev_up_rows);
   } else {

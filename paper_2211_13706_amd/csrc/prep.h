@@ -20,6 +20,13 @@ struct Prep {
   std::vector<int32_t> niv;
   // niv_up[r*k + j]: row of the lowest element of chain j above row r, or -1.
   std::vector<int32_t> niv_up;
+  // Sparse form (sparse == true; niv and niv_up then stay empty): the finite
+  // entries of row r of map m (0 = niv, 1 = niv_up) are
+  // nivr[m][nivp[m][r] .. nivp[m][r+1]), in ascending chain order, which in the
+  // chain-major numbering is ascending row order.
+  bool sparse = false;
+  std::vector<int64_t> nivp[2];
+  std::vector<int32_t> nivr[2];
   // level schedules: rows of level l are lev_rows[lev_ptr[l] .. lev_ptr[l+1])
   std::vector<int32_t> lev_down, lev_up;          // level per row
   std::vector<int32_t> lev_down_ptr, lev_down_rows, lev_up_ptr, lev_up_rows;
@@ -27,9 +34,13 @@ struct Prep {
   double t_validate = 0, t_chains = 0, t_niv = 0, t_levels = 0;
 };
 
-// Returns a px_status value; on failure `msg` says why.
+// Decompositions with more chains than this keep the niv maps sparse.
+constexpr int64_t kSparseNivChains = 256;
+
+// Returns a px_status value; on failure `msg` says why.  want_sparse forces
+// the sparse form of the niv maps.
 int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const int32_t* chain_of,
-               const int32_t* chain_pos, bool want_up, bool mirsky_schedule, Prep& out,
+               const int32_t* chain_pos, bool want_up, bool mirsky_schedule, bool want_sparse, Prep& out,
                std::string& msg);
 
 }  // namespace px

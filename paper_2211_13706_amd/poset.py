@@ -93,6 +93,15 @@ class Poset:
         _lib.check(_lib.lib().px_poset_niv(self.handle, int(up), out.ctypes.data), "px_poset_niv")
         return out
 
+    def niv_csr(self, up: bool = False):
+        """The niv map by rows of its finite entries (px_poset_niv_csr): (ptr, node ids)."""
+        info = self.info_dict()
+        ptr = np.empty(self.n + 1, np.int64)
+        nodes = np.empty(max(1, info["nnz_niv_up" if up else "nnz_niv"]), np.int32)
+        _lib.check(_lib.lib().px_poset_niv_csr(self.handle, int(up), ptr.ctypes.data, nodes.ctypes.data),
+                   "px_poset_niv_csr")
+        return ptr, nodes[: ptr[-1]]
+
     def levels(self, up: bool = False) -> np.ndarray:
         out = np.empty(self.n, np.int32)
         _lib.check(_lib.lib().px_poset_levels(self.handle, int(up), out.ctypes.data), "px_poset_levels")

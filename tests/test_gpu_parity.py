@@ -609,3 +609,105 @@ def test_autotune_keeps_results_exact(px, cfg0):
         s, e = b.offsets[i], b.offsets[i + 1]
         Rq = O.reachability(q.n, q.indptr, q.indices)
         assert np.array_equal(g[s:e], O.zeta(Rq, fx[s:e]))
+
+
+# ------------------------------------------------------ sparse niv rows (CSR)
+@pytest.fixture(scope="module")
+def er2k():
+    """Erdős–Rényi DAGs of average degree 4 and 6 (the workload of §5), n = 2000:
+    widths 300-400, so the niv maps are kept as rows of their finite entries."""
+    out = {}
+    for deg in (4, 6):
+        p = W.er_dag(2000, deg, seed=5)
+        out[deg] = (p, O.reachability(p.n, p.indptr, p.indices))
+    return out
+
+
+@pytest.mark.parametrize("deg", [4, 6])
+@pytest.mark.parametrize("B", [1, 8, 64, 100])
+def test_er_dag_sparse_niv_int64_exact(px, er2k, deg, B):
+    p, R = er2k[deg]
+    P = build(px, p, planted=False)
+    assert P.info_dict()["niv_sparse"] == 1 and P.k > 256
+    f = W.functions(p.n, B, "int", seed=20 + B, lo=-100, hi=100)
+    ft = T(f)
+    g = H(px.zeta(P, ft))
+    assert np.array_equal(g, O.zeta(R, f))
+    assert np.array_equal(H(px.zeta_adjoint(P, ft)), O.zeta_adjoint(R, f))
+    assert np.array_equal(H(px.mobius(P, T(g))), f)
+    gr = W.functions(p.n, B, "int", seed=40 + B, lo=-1000, hi=1000)
+    assert np.array_equal(H(px.mobius(P, T(gr))), O.mobius_by_substitution(R, gr))
+    assert np.array_equal(H(px.mobius_adjoint(P, T(gr))), O.mobius_adjoint_by_substitution(R, gr))
+
+
+@pytest.mark.parametrize("deg", [4, 6])
+@pytest.mark.parametrize("B", [1, 33, 64])
+def test_er_dag_sparse_niv_float(px, er2k, deg, B):
+    """float32 zeta within the compensated-scan bound, float64 to 1e-12, and the refined
+    float32 Möbius to 1e-5 (max|M r|/max|r| is 41 and 196 on these DAGs: well-posed)."""
+    p, R = er2k[deg]
+    P = build(px, p, planted=False)
+    f = W.functions(p.n, B, "normal", seed=60 + B)
+    fa = np.abs(f).astype(np.float64)
+    check_f32_zeta(H(px.zeta(P, T(f))), O.zeta(R, f, exact=False), O.zeta(R, fa, exact=False))
+    check_f32_zeta(H(px.zeta_adjoint(P, T(f))), O.zeta_adjoint(R, f, exact=False),
+                   O.zeta_adjoint(R, fa, exact=False))
+    f64 = f.astype(np.float64)
+    assert rel(H(px.zeta(P, T(f64))), O.zeta(R, f64, exact=False)) <= 1e-12
+    g64 = O.zeta(R, f64, exact=False)
+    assert rel(H(px.mobius(P, T(g64))), f64) <= 1e-12
+    g = W.functions(p.n, B, "uniform", seed=80 + B, lo=-1, hi=1)
+    want = O.mobius(R, g.astype(np.float64), exact=False)
+    got = H(px.mobius(P, T(g), max_refine=3))
+    assert rel(got, want) <= 1e-5
+    wantT = O.mobius_adjoint(R, g.astype(np.float64), exact=False)
+    assert rel(H(px.mobius_adjoint(P, T(g), max_refine=3)), wantT) <= 1e-5
+
+
+@pytest.mark.parametrize("case", ["cfg0", "lattice"])
+@pytest.mark.parametrize("B", [5, 64])
+def test_forced_sparse_niv_matches_dense(px, cfg0, case, B):
+    """PX_BUILD_SPARSE_NIV on posets that default to dense rows: the same int64 results,
+    and the same float64 Möbius bit for bit (both solves subtract the same terms in
+    chain order, one at a time)."""
+    p = cfg0[0] if case == "cfg0" else W.boolean_lattice(8)
+    planted = case == "cfg0"
+    A = build(px, p, planted=planted)
+    S = build(px, p, planted=planted, flags=px.PX_BUILD_SPARSE_NIV)
+    assert A.info_dict()["niv_sparse"] == 0 and S.info_dict()["niv_sparse"] == 1
+    f = W.functions(p.n, B, "int", seed=90 + B, lo=-1000, hi=1000)
+    ft = T(f)
+    for fn in (px.zeta, px.zeta_adjoint, px.mobius, px.mobius_adjoint):
+        assert np.array_equal(H(fn(A, ft)), H(fn(S, ft)))
+    g = T(W.functions(p.n, B, "normal", seed=95 + B).astype(np.float64))
+    assert np.array_equal(H(px.mobius(A, g)), H(px.mobius(S, g)))
+    assert np.array_equal(H(px.mobius_adjoint(A, g)), H(px.mobius_adjoint(S, g)))
+
+
+def test_sparse_niv_poset_not_batchable(px, er2k):
+    p, _ = er2k[4]
+    P = build(px, p, planted=False)
+    with pytest.raises(px.PosetxError) as ei:
+        px.batch_build([P])
+    assert ei.value.name == "PX_EUNSUPPORTED"
+
+
+def test_er_dag_sparse_niv_n65536_sampled(px):
+    """n = 2^16, average degree 4 (k ~ 13,000, 14M niv entries; dense rows would take
+    3.5 GB): float32 zeta at sampled nodes against down-set sums, int64 round trip exact."""
+    p = W.er_dag(1 << 16, 4, seed=1)
+    P = build(px, p, planted=False)
+    assert P.info_dict()["niv_sparse"] == 1
+    rng = np.random.default_rng(3)
+    nodes = rng.choice(p.n, 8, replace=False)
+    f = W.functions(p.n, 64, "normal", seed=5)
+    g = H(px.zeta(P, T(f)))[nodes]
+    check_f32_zeta(g, O.zeta_at(p.n, p.indptr, p.indices, f, nodes),
+                   O.zeta_at(p.n, p.indptr, p.indices, np.abs(f), nodes))
+    wT = H(px.zeta_adjoint(P, T(f)))[nodes]
+    check_f32_zeta(wT, O.zeta_adjoint_at(p.n, p.indptr, p.indices, f, nodes),
+                   O.zeta_adjoint_at(p.n, p.indptr, p.indices, np.abs(f), nodes))
+    fi = W.functions(p.n, 16, "int", seed=6, lo=-(2**40), hi=2**40)
+    gi = px.zeta(P, T(fi))
+    assert np.array_equal(H(px.mobius(P, gi)), fi)
+    assert np.array_equal(H(px.mobius_adjoint(P, px.zeta_adjoint(P, T(fi)))), fi)

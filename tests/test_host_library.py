@@ -83,17 +83,45 @@ def _check_against_closure(px, P, p, R):
 
 @pytest.mark.parametrize("case", ["example", "cfg0", "lattice6", "grid", "random"])
 @pytest.mark.parametrize("planted", [True, False])
-def test_preprocessing_matches_closure(px, case, planted):
+@pytest.mark.parametrize("sparse", [False, True])
+def test_preprocessing_matches_closure(px, case, planted, sparse):
     p = {"example": W.worked_example, "cfg0": lambda: W.chain_poset(600, 16, 4, seed=0),
          "lattice6": lambda: W.boolean_lattice(6), "grid": lambda: W.grid_poset(20, 7),
          "random": lambda: W.random_small_dag(90, 0.08, 3)}[case]()
     if planted and p.chain_of is None:
         pytest.skip("no planted chains for this poset")
     R = O.reachability(p.n, p.indptr, p.indices)
-    P = _host(px, p, planted=planted)
+    P = _host(px, p, planted=planted, flags=px.PX_BUILD_SPARSE_NIV if sparse else 0)
+    assert P.info["niv_sparse"] == int(sparse)
     if planted:
         assert P.k == p.k_planted
     _check_against_closure(px, P, p, R)
+    _check_csr(P)
+
+
+def _check_csr(P):
+    """px_poset_niv_csr lists exactly the finite entries of px_poset_niv, in chain order."""
+    co, _ = P.chains()
+    for up in (False, True):
+        niv = P.niv(up)
+        ptr, nodes = P.niv_csr(up)
+        assert ptr[0] == 0 and ptr[-1] == int((niv >= 0).sum())
+        for x in range(P.n):
+            row = niv[x][niv[x] >= 0]
+            assert np.array_equal(nodes[ptr[x]:ptr[x + 1]], row)
+            assert (np.diff(co[row]) > 0).all()
+
+
+@pytest.mark.parametrize("n,deg", [(1500, 4), (2000, 6)])
+def test_er_dag_sparse_niv_matches_closure(px, n, deg):
+    """Erdős–Rényi DAGs of average degree 4 and 6 (§5) are wide (k > 256 here): the
+    niv maps are kept sparse automatically and agree with the closure."""
+    p = W.er_dag(n, deg, seed=2)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = _host(px, p, planted=False)
+    assert P.k > 256 and P.info["niv_sparse"] == 1
+    _check_against_closure(px, P, p, R)
+    _check_csr(P)
 
 
 def test_matching_chains_reach_width(px):
@@ -142,6 +170,10 @@ def test_rejects_bad_input(px):
     c0 = np.nonzero(p.chain_of == 0)[0]; cp2[c0] = cp2[c0].max() - cp2[c0]
     assert _err(px, lambda: px.poset_build(12, p.indptr, p.indices, p.chain_of, cp2,
                                            flags=px.PX_BUILD_HOST_ONLY)) == "PX_ECHAIN"
+    # the sparse recursion checks the chains the same way
+    for cpos, cof in ((cp, co), (cp2, p.chain_of)):
+        assert _err(px, lambda: px.poset_build(12, p.indptr, p.indices, cof, cpos,
+                                               flags=px.PX_BUILD_HOST_ONLY | px.PX_BUILD_SPARSE_NIV)) == "PX_ECHAIN"
     # duplicate chain position
     cp3 = p.chain_pos.copy(); cp3[c0[0]] = cp3[c0[1]]
     assert _err(px, lambda: px.poset_build(12, p.indptr, p.indices, p.chain_of, cp3,
