@@ -328,6 +328,61 @@ def leg_large(px, dev, steps):
             "f32_roundtrip_rel_err": err, "f32_refine_report": rep}
 
 
+def leg_er_sparse(px, dev, steps):
+    """The workload class of the paper's experiments (§5): an Erdős–Rényi DAG of average degree 4,
+    n = 2^18, chains from the maximum matching.  Its width (about 53,000) keeps the niv map as rows
+    of its finite entries (about 61M; dense rows would need 55 GB).  float32 zeta and adjoint at
+    B = 64, the int64 Möbius round trip, the refined float32 Möbius, and the rate of the sparse
+    gather: its compulsory bytes (the niv rows, P read once, g) and the P rows it gathers."""
+    import torch
+    import workloads as W
+    sync = torch.cuda.synchronize
+    t0 = time.perf_counter()
+    q = W.er_dag(1 << 18, 4, seed=1)
+    P = px.poset_build(q.n, q.indptr, q.indices, None, None, device=0)
+    t_prep = time.perf_counter() - t0
+    info = P.info
+    n, Bl, nnz = q.n, 64, info["nnz_niv"]
+    f = torch.from_numpy(W.functions(n, Bl, "normal", seed=5)).to(dev)
+    g = torch.empty_like(f)
+    w = torch.empty_like(f)
+    P.reserve(torch.float32, Bl)
+    tz = _time(lambda: px.zeta(P, f, out=g), steps, sync)
+    ta = _time(lambda: px.zeta_adjoint(P, f, out=w), steps, sync)
+    lib = px.lib()
+    lib.px_profile(1)
+    for _ in range(steps):
+        px.zeta(P, f, out=g)
+    sync()
+    ph = profile_read(lib)
+    lib.px_profile(0)
+    gms, gcnt = ph["gather"]
+    t_gather = gms / max(1, gcnt) / 1e3
+    gather_bytes = nnz * 4 + (n + 1) * 8 + 2 * n * Bl * 4 + n * 4   # niv rows, P once, g, node ids
+    fi = torch.from_numpy(W.functions(n, Bl, "int", seed=6, lo=-1000, hi=1000)).to(dev)
+    gi = px.zeta(P, fi)
+    tm = _time(lambda: px.mobius(P, gi), steps, sync)
+    exact = bool(torch.equal(px.mobius(P, gi), fi))
+    exact_adj = bool(torch.equal(px.mobius_adjoint(P, px.zeta_adjoint(P, fi)), fi))
+    try:
+        f2, rep = px.mobius(P, g, max_refine=3, report=True)
+        err = ((f2 - f).abs().amax(0) / f.abs().amax(0)).max().item()
+    except px.PosetxError as e:
+        rep, err = {"status": e.name}, None
+    tr = _time(lambda: px.mobius(P, g, max_refine=3), max(2, steps // 4), sync)
+    return {"workload": "Erdős–Rényi DAG, n=262144, average degree 4, matching chains, B=64 float32",
+            "k": info["k"], "nnz_niv": nnz, "niv_sparse": info["niv_sparse"], "levels": info["levels_down"],
+            "preprocess_s": round(t_prep, 2),
+            "zeta_f32_ms": round(tz * 1e3, 4), "zeta_node_rhs_per_s": n * Bl / tz,
+            "adjoint_f32_ms": round(ta * 1e3, 4),
+            "gather_ms": round(t_gather * 1e3, 4), "gather_alg_GBps": round(gather_bytes / t_gather / 1e9, 1),
+            "gathered_row_GBps": round(nnz * Bl * 4 / t_gather / 1e9, 1),
+            "mobius_int64_ms": round(tm * 1e3, 4), "int64_roundtrip_exact": exact,
+            "int64_adjoint_roundtrip_exact": exact_adj,
+            "mobius_f32_refined_ms": round(tr * 1e3, 4), "f32_roundtrip_rel_err": err, "f32_refine_report": rep,
+            "mobius_f64_growth": f64_growth(px, P, n, dev)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,8 +390,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
-    ap.add_argument("--legs", default="default", choices=["none", "default", "all"],
-                    help="extra measurements of the other hot-path rows (all: also the batched and n=2^23 configs)")
+    ap.add_argument("--legs", default="default", choices=["none", "default", "all", "sparse"],
+                    help="extra measurements of the other hot-path rows (all: also the batched, n=2^23 and "
+                         "Erdős–Rényi configs; sparse: the Erdős–Rényi config alone)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for counter scaling)")
     args = ap.parse_args()
@@ -457,7 +513,9 @@ def main():
         "generate_s": round(t_gen, 3),
         "kernel_hash": kernel_hash(),
     }
-    if args.legs != "none":
+    if args.legs == "sparse":
+        out["legs"] = {"er_sparse": leg_er_sparse(px, dev, max(2, args.steps // 4))}
+    elif args.legs != "none":
         def note(msg):
             print(f"[bench] {msg}", file=sys.stderr, flush=True)
         note("legs: config 1 int64 and adjoint")
@@ -470,6 +528,8 @@ def main():
             legs["batched"] = leg_batched(px, dev, args.steps)
             note("legs: n = 2^23")
             legs["large"] = leg_large(px, dev, max(2, args.steps // 4))
+            note("legs: Erdős–Rényi DAG with sparse niv rows")
+            legs["er_sparse"] = leg_er_sparse(px, dev, max(2, args.steps // 4))
         out["legs"] = legs
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, f_host, args.cpu_budget)

@@ -552,7 +552,13 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
     for (int i = 1; i < RPT; ++i)
       if (sn[i] == sn[i - 1]) sv[i] = sv[i - 1];
   }
-  St st = C[(int64_t)t * B + col];
+  St st;
+  if (C) {
+    st = C[(int64_t)t * B + col];
+  } else {  // every chain fits one tile: no carries; this kernel keeps row n of P zero
+    st.zero();
+    if (MODE == 0 && t == 0 && rg == 0) P[(int64_t)d.n * B + col] = Tout(0);
+  }
   st.combine(pre);
   if (dir > 0) {
 #pragma unroll
@@ -919,7 +925,8 @@ __global__ __launch_bounds__(WG) void k_gather(DevPoset d, const int32_t* __rest
 }
 
 // The gather over sparse niv rows (CSR: ep[r] .. ep[r + 1] index er), one
-// thread per (row, column).
+// thread per (row, column).  The entries are vector loads even where a row is
+// a whole wavefront: scalar loads of them made this kernel 13% slower.
 template <typename TP, typename Tout, typename Tres, bool RESID>
 __global__ __launch_bounds__(WG) void k_gather_csr(DevPoset d, const int64_t* __restrict__ ep,
                                                    const int32_t* __restrict__ er, int cw, const TP* __restrict__ P,
@@ -1559,7 +1566,11 @@ hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int6
   const int cw = col_width(B);
   const int segi = seg_index(cw);
   St* A = (St*)aux;
-  St* C = A + ntiles * B;
+  // when every chain fits one tile (short chains, e.g. wide sparse posets) there
+  // are no carries: phases 0 and 1 do nothing and phase 2 scans each tile alone
+  const bool one_tile = d.max_chain_tiles[segi] == 1;
+  if (one_tile && phase < 2) return hipSuccess;
+  St* C = one_tile ? nullptr : A + ntiles * B;
   dim3 g((unsigned)ntiles, (unsigned)((B + cw - 1) / cw));
   if (phase == 0) {
     const int nt = reduce_tiles(cw == 64 ? 64 : 0);
@@ -1718,6 +1729,35 @@ hipError_t launch_zeta_compact(const DevPoset& d, int dir, ElemType tin, const v
   return hipErrorInvalidValue;
 }
 
+namespace {
+hipError_t gather_csr(const DevPoset& d, const int64_t* ep, const int32_t* er, ElemType tp, const void* P,
+                            int64_t B, ElemType tout, void* out, int64_t ldo, ElemType tres, const void* resid,
+                            int64_t ldr, hipStream_t s) {
+  const int cw = col_width(B);
+  const dim3 g = grid2(d.n, cw, B);
+  if (resid && tres == E_F32)
+    hipLaunchKernelGGL((k_gather_csr<double, double, float, true>), g, dim3(WG), 0, s, d, ep, er, cw,
+                       (const double*)P, B, (double*)out, ldo, (const float*)resid, ldr);
+  else if (resid && tres == E_F64)
+    hipLaunchKernelGGL((k_gather_csr<double, double, double, true>), g, dim3(WG), 0, s, d, ep, er, cw,
+                       (const double*)P, B, (double*)out, ldo, (const double*)resid, ldr);
+  else if (resid)
+    return hipErrorInvalidValue;
+  else if (tp == E_I64 && tout == E_I64)
+    hipLaunchKernelGGL((k_gather_csr<int64_t, int64_t, int64_t, false>), g, dim3(WG), 0, s, d, ep, er, cw,
+                       (const int64_t*)P, B, (int64_t*)out, ldo, (const int64_t*)nullptr, 0);
+  else if (tp == E_F32 && tout == E_F32)
+    hipLaunchKernelGGL((k_gather_csr<float, float, float, false>), g, dim3(WG), 0, s, d, ep, er, cw,
+                       (const float*)P, B, (float*)out, ldo, (const float*)nullptr, 0);
+  else if (tp == E_F64 && tout == E_F64)
+    hipLaunchKernelGGL((k_gather_csr<double, double, double, false>), g, dim3(WG), 0, s, d, ep, er, cw,
+                       (const double*)P, B, (double*)out, ldo, (const double*)nullptr, 0);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P, int64_t B, ElemType tout,
                          void* out, int64_t ldo, ElemType tres, const void* resid, int64_t ldr, void* snaps,
                          LaunchHook* hook, hipStream_t s) {
@@ -1728,26 +1768,7 @@ hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P,
   if (resid && (tp != E_F64 || tout != E_F64)) return hipErrorInvalidValue;
   if (const int64_t* ep = d.nivp[up ? 1 : 0]) {  // sparse niv rows
     const int32_t* er = d.nivr[up ? 1 : 0];
-    if (resid && tres == E_F32)
-      hipLaunchKernelGGL((k_gather_csr<double, double, float, true>), g, dim3(WG), 0, s, d, ep, er, cw,
-                         (const double*)P, B, (double*)out, ldo, (const float*)resid, ldr);
-    else if (resid && tres == E_F64)
-      hipLaunchKernelGGL((k_gather_csr<double, double, double, true>), g, dim3(WG), 0, s, d, ep, er, cw,
-                         (const double*)P, B, (double*)out, ldo, (const double*)resid, ldr);
-    else if (resid)
-      return hipErrorInvalidValue;
-    else if (tp == E_I64 && tout == E_I64)
-      hipLaunchKernelGGL((k_gather_csr<int64_t, int64_t, int64_t, false>), g, dim3(WG), 0, s, d, ep, er, cw,
-                         (const int64_t*)P, B, (int64_t*)out, ldo, (const int64_t*)nullptr, 0);
-    else if (tp == E_F32 && tout == E_F32)
-      hipLaunchKernelGGL((k_gather_csr<float, float, float, false>), g, dim3(WG), 0, s, d, ep, er, cw,
-                         (const float*)P, B, (float*)out, ldo, (const float*)nullptr, 0);
-    else if (tp == E_F64 && tout == E_F64)
-      hipLaunchKernelGGL((k_gather_csr<double, double, double, false>), g, dim3(WG), 0, s, d, ep, er, cw,
-                         (const double*)P, B, (double*)out, ldo, (const double*)nullptr, 0);
-    else
-      return hipErrorInvalidValue;
-    return hipGetLastError();
+    return gather_csr(d, ep, er, tp, P, B, tout, out, ldo, tres, resid, ldr, s);
   }
   // the walking gather when its tables and snapshot scratch are there
   const WalkTables& w = d.walk[up ? 1 : 0];
@@ -1804,6 +1825,30 @@ hipError_t launch_usolve_begin(const DevPoset& d, ElemType ty, void* Y, int64_t 
   return hipGetLastError();
 }
 
+namespace {
+hipError_t usolve_csr(const DevPoset& d, const int64_t* ep, const int32_t* er, const int32_t* rows, int64_t cnt,
+                            ElemType tin, const void* g, int64_t ldg, ElemType ty, void* Y, int64_t B,
+                            hipStream_t s) {
+  const int cw = col_width(B);
+  const dim3 gr = grid2(cnt, cw, B);
+  if (tin == E_I64 && ty == E_I64)
+    hipLaunchKernelGGL((k_usolve_csr<int64_t, int64_t>), gr, dim3(WG), 0, s, d, ep, er, rows, cnt, cw,
+                       (const int64_t*)g, ldg, (int64_t*)Y, B);
+  else if (tin == E_F32 && ty == E_F32)
+    hipLaunchKernelGGL((k_usolve_csr<float, float>), gr, dim3(WG), 0, s, d, ep, er, rows, cnt, cw,
+                       (const float*)g, ldg, (float*)Y, B);
+  else if (tin == E_F64 && ty == E_F32)
+    hipLaunchKernelGGL((k_usolve_csr<double, float>), gr, dim3(WG), 0, s, d, ep, er, rows, cnt, cw,
+                       (const double*)g, ldg, (float*)Y, B);
+  else if (tin == E_F64 && ty == E_F64)
+    hipLaunchKernelGGL((k_usolve_csr<double, double>), gr, dim3(WG), 0, s, d, ep, er, rows, cnt, cw,
+                       (const double*)g, ldg, (double*)Y, B);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_rows, int64_t i0, int64_t cnt,
                                ElemType tin, const void* g, int64_t ldg, ElemType ty, void* Y, int64_t B,
                                hipStream_t s) {
@@ -1813,21 +1858,7 @@ hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_ro
   const int32_t* nv = up ? d.niv_up : d.niv;
   if (const int64_t* ep = d.nivp[up ? 1 : 0]) {  // sparse niv rows
     const int32_t* er = d.nivr[up ? 1 : 0];
-    if (tin == E_I64 && ty == E_I64)
-      hipLaunchKernelGGL((k_usolve_csr<int64_t, int64_t>), gr, dim3(WG), 0, s, d, ep, er, lev_rows, cnt, cw,
-                         (const int64_t*)g, ldg, (int64_t*)Y, B);
-    else if (tin == E_F32 && ty == E_F32)
-      hipLaunchKernelGGL((k_usolve_csr<float, float>), gr, dim3(WG), 0, s, d, ep, er, lev_rows, cnt, cw,
-                         (const float*)g, ldg, (float*)Y, B);
-    else if (tin == E_F64 && ty == E_F32)
-      hipLaunchKernelGGL((k_usolve_csr<double, float>), gr, dim3(WG), 0, s, d, ep, er, lev_rows, cnt, cw,
-                         (const double*)g, ldg, (float*)Y, B);
-    else if (tin == E_F64 && ty == E_F64)
-      hipLaunchKernelGGL((k_usolve_csr<double, double>), gr, dim3(WG), 0, s, d, ep, er, lev_rows, cnt, cw,
-                         (const double*)g, ldg, (double*)Y, B);
-    else
-      return hipErrorInvalidValue;
-    return hipGetLastError();
+    return usolve_csr(d, ep, er, lev_rows, cnt, tin, g, ldg, ty, Y, B, s);
   }
   if (cw == 64 && d.k <= 64 && !d.poset_of_row && cnt < INT32_MAX) {
     const dim3 gu((unsigned)((cnt + (WG / 64) - 1) / (WG / 64)), (unsigned)((B + 63) / 64));
