@@ -506,7 +506,8 @@ def main():
                           "phase_GBps": round(moved / (ms_step * 1e-3) / 1e9, 1)},
         "phases": phases,
         "preprocess_s": {"total": round(t_prep, 3), **{k: round(v, 3) for k, v in P.info.items()
-                                                      if k.startswith("t_")}},
+                                                      if k.startswith("t_")},
+                         "niv_device_rounds": P.info["niv_device_rounds"]},
         "walk": {k: P.info[k] for k in ("walk_runs", "walk_events", "walk_snapshots", "walk_T", "walk_emax",
                                         "walk_rows_distinct", "walk_row_loads")},
         "autotune": {**tune, "seconds": round(t_tune, 2)},

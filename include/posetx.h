@@ -106,7 +106,8 @@ typedef struct {
   int32_t device;
   double t_validate, t_chains, t_niv, t_levels, t_upload;  /* preprocessing seconds      */
   int32_t niv_sparse;     /* 1 if the niv maps are kept sparse (PX_BUILD_SPARSE_NIV)    */
-  int32_t reserved;
+  int32_t niv_device_rounds; /* rounds of the device computation of the dense niv maps
+                                (0: the host recursion computed them)                    */
 } px_info;
 
 typedef struct {
@@ -119,7 +120,10 @@ typedef struct {
 
 /*
  * Build a poset handle (one-time preprocessing, §4: chain decomposition,
- * niv map by the recursion of Theorem 5, levels; then upload).
+ * niv map by the recursion of Theorem 5, levels; then upload).  For a device
+ * handle with dense niv rows the two niv maps are computed on the device as the
+ * fixed point of that recursion (the same maps; POSETX_PREP=host keeps them on
+ * the host); the rest of the preprocessing runs on the host.
  *   n          elements, 0 <= n < 2^31
  *   indptr     host, n+1 entries, indptr[0] = 0, non-decreasing
  *   indices    host, indptr[n] entries in [0, n)

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "niv_device.h"
 #include "posetx.h"
 #include "prep.h"
 
@@ -950,14 +951,28 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
   p->device = device;
   std::string msg;
   int rc;
+  // dense niv maps are computed on the device unless the handle is host-only
+  // or POSETX_PREP=host asks for the host recursion
+  const char* prep_env = std::getenv("POSETX_PREP");
+  const bool dev_niv = !p->host_only && n > 0 && !(prep_env && std::strcmp(prep_env, "host") == 0);
+  px::NivHook hook = [&](px::Prep& P, const std::vector<int64_t>& rptr, const std::vector<int32_t>& ridx,
+                         std::string& m) -> int {
+    DeviceGuard dg(device);
+    if (!dg.ok) return -1;
+    int rounds = 0;
+    const int r = px::device_niv(P, indptr, indices, rptr, ridx, p->has_up, &p->d_niv, &p->d_niv_up, &rounds, m);
+    if (r == PX_OK) P.niv_rounds = rounds;
+    return r;
+  };
   try {
     rc = px::preprocess(n, indptr, indices, chain_of, chain_pos, p->has_up, p->mirsky,
-                        (flags & PX_BUILD_SPARSE_NIV) != 0, p->prep, msg);
+                        (flags & PX_BUILD_SPARSE_NIV) != 0, p->prep, msg, dev_niv ? &hook : nullptr);
   } catch (const std::bad_alloc&) {
     rc = PX_ENOMEM;
     msg = "host allocation failed during preprocessing";
   }
   if (rc != PX_OK) {
+    if (!p->host_only) free_poset_device(p);
     delete p;
     return fail((px_status)rc, msg);
   }
@@ -975,7 +990,9 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
     hipError_t e = upload(&p->d_node_of_row, P.node_of_row.data(), P.node_of_row.size(), b);
     if (e == hipSuccess) e = upload(&p->d_chain_of_row, P.chain_of_row.data(), P.chain_of_row.size(), b);
     if (e == hipSuccess) e = upload(&p->d_chain_off, P.chain_off.data(), P.chain_off.size(), b);
-    if (!P.sparse) {
+    if (!P.sparse && p->d_niv) {  // computed on the device
+      b += (int64_t)(P.niv.size() + P.niv_up.size()) * 4;
+    } else if (!P.sparse) {
       if (e == hipSuccess) e = upload(&p->d_niv, P.niv.data(), P.niv.size(), b);
       if (e == hipSuccess && p->has_up) e = upload(&p->d_niv_up, P.niv_up.data(), P.niv_up.size(), b);
     } else {
@@ -1087,7 +1104,7 @@ px_status px_poset_info(const px_poset* p, px_info* o) {
   o->t_levels = P.t_levels;
   o->t_upload = p->t_upload;
   o->niv_sparse = P.sparse ? 1 : 0;
-  o->reserved = 0;
+  o->niv_device_rounds = P.niv_rounds;
   return PX_OK;
 }
 

@@ -1,0 +1,25 @@
+// The niv maps computed on the device (dense rows); see niv_device.hip.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "prep.h"
+
+namespace px {
+
+// Computes P.niv (and P.niv_up if want_up) for the chains already in P, on
+// the current device, as the fixed point of the chain recursion, and checks
+// planted chains.  rptr / ridx: the parent lists (reversed CSR).  On success
+// returns PX_OK, leaves the device copies in *out_niv / *out_up (hipMalloc'd,
+// owned by the caller; rows as in P, -1 = none), fills P.niv / P.niv_up on the
+// host and the number of rounds taken.  Returns -1 (nothing allocated, nothing
+// changed) where the rounds do not settle within their cap, so that the caller
+// runs the host recursion instead; PX_ECHAIN for a chain that is not totally
+// ordered; PX_ENOMEM / PX_EHIP with msg set.
+int device_niv(Prep& P, const int64_t* indptr, const int32_t* indices, const std::vector<int64_t>& rptr,
+               const std::vector<int32_t>& ridx, bool want_up, int32_t** out_niv, int32_t** out_up, int* rounds,
+               std::string& msg);
+
+}  // namespace px

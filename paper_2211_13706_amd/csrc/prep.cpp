@@ -104,7 +104,7 @@ void hopcroft_karp(int64_t n, const int64_t* indptr, const int32_t* indices, std
 
 int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const int32_t* chain_of,
                const int32_t* chain_pos, bool want_up, bool mirsky_schedule, bool want_sparse, Prep& P,
-               std::string& msg) {
+               std::string& msg, const NivHook* niv_hook) {
   double t0 = now_s();
   if (n < 0 || n >= INT32_MAX) {
     msg = "n out of range";
@@ -251,7 +251,14 @@ int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const i
     return PX_ECHAIN;
   };
   P.sparse = want_sparse || k > kSparseNivChains;
-  if (!P.sparse) {
+  int hook_rc = -1;
+  if (!P.sparse && niv_hook && *niv_hook) hook_rc = (*niv_hook)(P, rptr, ridx, msg);
+  if (hook_rc > 0) return hook_rc;
+  if (!P.sparse && hook_rc == PX_OK) {
+    for (size_t i = 0; i < P.niv.size(); ++i) P.nnz_niv += P.niv[i] >= 0;
+    for (size_t i = 0; i < P.niv_up.size(); ++i) P.nnz_niv_up += P.niv_up[i] >= 0;
+  } else if (!P.sparse) {
+    P.niv_rounds = 0;
     P.niv.assign((size_t)n * k, -1);
     for (int64_t h = 0; h < n; ++h) {
       int32_t x = order[h];

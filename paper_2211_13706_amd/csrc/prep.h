@@ -4,6 +4,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -31,16 +32,24 @@ struct Prep {
   std::vector<int32_t> lev_down, lev_up;          // level per row
   std::vector<int32_t> lev_down_ptr, lev_down_rows, lev_up_ptr, lev_up_rows;
   int64_t nnz_niv = 0, nnz_niv_up = 0, max_chain = 0, mirsky = 0, udep = 0;
+  int32_t niv_rounds = 0;  // rounds of a device computation of niv (0: the host recursion)
   double t_validate = 0, t_chains = 0, t_niv = 0, t_levels = 0;
 };
 
 // Decompositions with more chains than this keep the niv maps sparse.
 constexpr int64_t kSparseNivChains = 256;
 
+// Computes the dense niv maps elsewhere (on a device) once the chains are
+// known, given the parent lists: returns PX_OK with P.niv (and P.niv_up)
+// filled, -1 to let the host recursion run instead, or an error status with
+// msg set.
+using NivHook = std::function<int(Prep& P, const std::vector<int64_t>& rptr, const std::vector<int32_t>& ridx,
+                                  std::string& msg)>;
+
 // Returns a px_status value; on failure `msg` says why.  want_sparse forces
-// the sparse form of the niv maps.
+// the sparse form of the niv maps; niv_hook (nullable) is tried for dense ones.
 int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const int32_t* chain_of,
                const int32_t* chain_pos, bool want_up, bool mirsky_schedule, bool want_sparse, Prep& out,
-               std::string& msg);
+               std::string& msg, const NivHook* niv_hook = nullptr);
 
 }  // namespace px

@@ -711,3 +711,64 @@ def test_er_dag_sparse_niv_n65536_sampled(px):
     gi = px.zeta(P, T(fi))
     assert np.array_equal(H(px.mobius(P, gi)), fi)
     assert np.array_equal(H(px.mobius_adjoint(P, px.zeta_adjoint(P, T(fi)))), fi)
+
+
+# ------------------------------------------- niv maps computed on the device
+def _host_only(px, p, planted):
+    return px.poset_build(p.n, p.indptr, p.indices, p.chain_of if planted else None,
+                          p.chain_pos if planted else None, flags=px.PX_BUILD_HOST_ONLY)
+
+
+@pytest.mark.parametrize("case", ["example", "cfg0", "cfg0_matching", "grid", "lattice", "random", "antichain",
+                                  "chain", "batched_small"])
+def test_device_niv_equals_host_recursion(px, case):
+    """The device fixed point of the chain recursion gives the host recursion's maps
+    (Theorem 5), for both directions, and the same level schedules."""
+    p, planted = {
+        "example": (W.worked_example(), True), "cfg0": (W.chain_poset(2000, 16, 4, seed=0), True),
+        "cfg0_matching": (W.chain_poset(2000, 16, 4, seed=0), False), "grid": (W.grid_poset(300, 20), True),
+        "lattice": (W.boolean_lattice(8), False), "random": (W.random_small_dag(400, 0.02, 5), False),
+        "antichain": (W.antichain(100), False), "chain": (W.chain_only(500, seed=2), True),
+        "batched_small": (W.batched_posets(1, seed=4, nmin=3000, nmax=3000)[0], True)}[case]
+    if planted and p.chain_of is None:
+        planted = False
+    Hh = _host_only(px, p, planted)
+    D = build(px, p, planted=planted)
+    info = D.info_dict()
+    assert info["niv_sparse"] == 0 and info["niv_device_rounds"] >= 1
+    for up in (False, True):
+        assert np.array_equal(D.niv(up), Hh.niv(up))
+        assert np.array_equal(D.levels(up), Hh.levels(up))
+    assert info["nnz_niv"] == Hh.info_dict()["nnz_niv"] and info["nnz_niv_up"] == Hh.info_dict()["nnz_niv_up"]
+
+
+def test_device_niv_config1_and_host_switch(px, cfg1, monkeypatch):
+    """n = 2^20, k = 64: the device maps equal the host's; POSETX_PREP=host selects the host recursion."""
+    p, _ = cfg1
+    D = build(px, p)
+    rounds = D.info_dict()["niv_device_rounds"]
+    assert 2 <= rounds <= 64
+    Hh = _host_only(px, p, True)
+    assert np.array_equal(D.niv(), Hh.niv())
+    assert np.array_equal(D.niv(True), Hh.niv(True))
+    monkeypatch.setenv("POSETX_PREP", "host")
+    assert build(px, W.chain_poset(2000, 16, 4, seed=0)).info_dict()["niv_device_rounds"] == 0
+
+
+def test_device_niv_rejects_unordered_chains(px):
+    """Planted chains that the DAG does not order are rejected by the device check too."""
+    p = W.worked_example()
+    co, cp = p.chain_of.copy(), p.chain_pos.copy()
+    co[[4, 5]] = co[[5, 4]]; cp[[4, 5]] = cp[[5, 4]]     # x5 and x6 are incomparable
+    cp2 = p.chain_pos.copy()
+    c0 = np.nonzero(p.chain_of == 0)[0]; cp2[c0] = cp2[c0].max() - cp2[c0]
+    q = W.chain_poset(2000, 16, 4, seed=0)
+    cq = q.chain_pos.copy()
+    c3 = np.nonzero(q.chain_of == 3)[0]
+    i, j = c3[np.argsort(cq[c3])][[500 // 16, 500 // 16 + 7]]
+    cq[[i, j]] = cq[[j, i]]                               # two elements of one chain swapped
+    for (n, indptr, indices, cof, cpos) in ((12, p.indptr, p.indices, co, cp), (12, p.indptr, p.indices, p.chain_of, cp2),
+                                            (q.n, q.indptr, q.indices, q.chain_of, cq)):
+        with pytest.raises(px.PosetxError) as ei:
+            px.poset_build(n, indptr, indices, cof, cpos, device=0)
+        assert ei.value.name == "PX_ECHAIN"
