@@ -189,7 +189,25 @@ def legs_config1(px, P, p, dev, steps):
     ga = torch.empty_like(ff)
     t = _time(lambda: px.zeta_adjoint(P, ff, out=ga), steps, sync)
     out["zeta_adjoint_f32"] = {"ms": round(t * 1e3, 4), "node_rhs_per_s": p.n * B / t}
+    del ff, ga
+    out["preprocess"] = leg_preprocess(px, P, p)
     return out
+
+
+def leg_preprocess(px, P, p):
+    """The niv maps of the headline poset: device fixed point (as built) against the host
+    recursion (POSETX_PREP=host), seconds of each and whether the maps agree."""
+    os.environ["POSETX_PREP"] = "host"
+    try:
+        t0 = time.perf_counter()
+        Q = px.poset_build(p.n, p.indptr, p.indices, p.chain_of, p.chain_pos, device=0)
+        t_host = time.perf_counter() - t0
+    finally:
+        del os.environ["POSETX_PREP"]
+    same = bool(np.array_equal(P.niv(), Q.niv()) and np.array_equal(P.niv(True), Q.niv(True)))
+    return {"niv_device_s": round(P.info["t_niv"], 3), "niv_device_rounds": P.info["niv_device_rounds"],
+            "niv_host_s": round(Q.info["t_niv"], 3), "build_host_niv_s": round(t_host, 3),
+            "maps_equal": same}
 
 
 def leg_grid(px, dev, steps, refine=3):
