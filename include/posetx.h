@@ -121,9 +121,10 @@ typedef struct {
 /*
  * Build a poset handle (one-time preprocessing, §4: chain decomposition,
  * niv map by the recursion of Theorem 5, levels; then upload).  For a device
- * handle with dense niv rows the two niv maps are computed on the device as the
- * fixed point of that recursion (the same maps; POSETX_PREP=host keeps them on
- * the host); the rest of the preprocessing runs on the host.
+ * handle with dense niv rows of at least 2^24 entries (n * k) the two niv maps
+ * are computed on the device as the fixed point of that recursion (the same
+ * maps; POSETX_PREP=host or =device forces the host recursion or the device
+ * for any size); the rest of the preprocessing runs on the host.
  *   n          elements, 0 <= n < 2^31
  *   indptr     host, n+1 entries, indptr[0] = 0, non-decreasing
  *   indices    host, indptr[n] entries in [0, n)

@@ -951,12 +951,16 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
   p->device = device;
   std::string msg;
   int rc;
-  // dense niv maps are computed on the device unless the handle is host-only
-  // or POSETX_PREP=host asks for the host recursion
+  // dense niv maps of at least 2^24 entries are computed on the device (smaller
+  // ones are quicker on the host); POSETX_PREP=host / device forces either side
   const char* prep_env = std::getenv("POSETX_PREP");
-  const bool dev_niv = !p->host_only && n > 0 && !(prep_env && std::strcmp(prep_env, "host") == 0);
+  const bool force_host = prep_env && std::strcmp(prep_env, "host") == 0;
+  const bool force_dev = prep_env && std::strcmp(prep_env, "device") == 0;
+  const bool dev_niv = !p->host_only && n > 0 && !force_host;
+  const int64_t min_dev_entries = force_dev ? 0 : (int64_t)1 << 24;
   px::NivHook hook = [&](px::Prep& P, const std::vector<int64_t>& rptr, const std::vector<int32_t>& ridx,
                          std::string& m) -> int {
+    if (P.n * P.k < min_dev_entries) return -1;
     DeviceGuard dg(device);
     if (!dg.ok) return -1;
     int rounds = 0;

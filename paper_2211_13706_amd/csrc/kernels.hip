@@ -1533,19 +1533,40 @@ __global__ __launch_bounds__(WG) void k_chain_diff(DevPoset d, int dir, int cw_r
 
 // --------------------------------------------------------------- statistics
 template <typename TG>
-__global__ __launch_bounds__(WG) void k_absmax(int64_t n, int64_t B, const double* __restrict__ r,
+__global__ __launch_bounds__(WG) void k_absmax(int64_t n, int64_t B, int cw, const double* __restrict__ r,
                                                const TG* __restrict__ g, int64_t ldg, uint64_t* stats) {
-  const int64_t total = n * B;
-  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < total; i += (int64_t)gridDim.x * WG) {
-    const int64_t x = i / B, col = i % B;
-    double a = fabs(r[i]);
-    double b = fabs((double)g[x * ldg + col]);
-    if (!isfinite(a) || !isfinite(b)) {
-      atomicMax((unsigned long long*)&stats[2 * B], 1ull);
-      continue;
+  // each thread keeps the maxima of its rows of one column; the row groups of a
+  // workgroup are folded in LDS and one lane per column updates the totals
+  // (bit patterns of non-negative doubles order as unsigned integers)
+  __shared__ double sa[WG], sb[WG];
+  const int RG = WG / cw;
+  const int rg = threadIdx.x / cw;
+  const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
+  double ma = 0, mb = 0;
+  bool bad = false;
+  if (col < B) {
+    for (int64_t x = (int64_t)blockIdx.x * RG + rg; x < n; x += (int64_t)gridDim.x * RG) {
+      const double a = fabs(r[x * B + col]);
+      const double b = fabs((double)g[x * ldg + col]);
+      if (!isfinite(a) || !isfinite(b)) {
+        bad = true;
+        continue;
+      }
+      ma = fmax_(ma, a);
+      mb = fmax_(mb, b);
     }
-    atomicMax((unsigned long long*)&stats[col], (unsigned long long)__double_as_longlong(a));
-    atomicMax((unsigned long long*)&stats[B + col], (unsigned long long)__double_as_longlong(b));
+  }
+  sa[threadIdx.x] = ma;
+  sb[threadIdx.x] = mb;
+  if (bad) atomicMax((unsigned long long*)&stats[2 * B], 1ull);
+  __syncthreads();
+  if (rg == 0 && col < B) {
+    for (int q = 1; q < RG; ++q) {
+      ma = fmax_(ma, sa[q * cw + threadIdx.x]);
+      mb = fmax_(mb, sb[q * cw + threadIdx.x]);
+    }
+    atomicMax((unsigned long long*)&stats[col], (unsigned long long)__double_as_longlong(ma));
+    atomicMax((unsigned long long*)&stats[B + col], (unsigned long long)__double_as_longlong(mb));
   }
 }
 
@@ -1937,14 +1958,15 @@ hipError_t launch_absmax(int64_t n, int64_t B, const double* r, ElemType tg, con
   const int64_t cnt = 2 * B + 1;
   hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((cnt + WG - 1) / WG)), dim3(WG), 0, s, stats, cnt, (uint64_t)0);
   if (n == 0) return hipGetLastError();
-  int64_t blocks = (n * B + WG - 1) / WG;
-  if (blocks > 4096) blocks = 4096;
+  const int cw = col_width(B);
+  const int64_t rows_per_block = WG / cw;
+  int64_t blocks = (n + rows_per_block - 1) / rows_per_block;
+  if (blocks > 2048) blocks = 2048;
+  const dim3 grid((unsigned)blocks, (unsigned)((B + cw - 1) / cw));
   if (tg == E_F32)
-    hipLaunchKernelGGL((k_absmax<float>), dim3((unsigned)blocks), dim3(WG), 0, s, n, B, r, (const float*)g, ldg,
-                       stats);
+    hipLaunchKernelGGL((k_absmax<float>), grid, dim3(WG), 0, s, n, B, cw, r, (const float*)g, ldg, stats);
   else if (tg == E_F64)
-    hipLaunchKernelGGL((k_absmax<double>), dim3((unsigned)blocks), dim3(WG), 0, s, n, B, r, (const double*)g, ldg,
-                       stats);
+    hipLaunchKernelGGL((k_absmax<double>), grid, dim3(WG), 0, s, n, B, cw, r, (const double*)g, ldg, stats);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -194,6 +194,7 @@ void row_csr(const Prep& P, const int64_t* ptr, const int32_t* idx, bool cross_o
   const int64_t n = P.n;
   rp.assign(n + 1, 0);
   rr.clear();
+  rr.reserve((size_t)ptr[n]);
   for (int64_t r = 0; r < n; ++r) {
     const int32_t x = P.node_of_row[r];
     for (int64_t e = ptr[x]; e < ptr[x + 1]; ++e) {

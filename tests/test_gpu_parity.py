@@ -721,9 +721,10 @@ def _host_only(px, p, planted):
 
 @pytest.mark.parametrize("case", ["example", "cfg0", "cfg0_matching", "grid", "lattice", "random", "antichain",
                                   "chain", "batched_small"])
-def test_device_niv_equals_host_recursion(px, case):
+def test_device_niv_equals_host_recursion(px, case, monkeypatch):
     """The device fixed point of the chain recursion gives the host recursion's maps
     (Theorem 5), for both directions, and the same level schedules."""
+    monkeypatch.setenv("POSETX_PREP", "device")
     p, planted = {
         "example": (W.worked_example(), True), "cfg0": (W.chain_poset(2000, 16, 4, seed=0), True),
         "cfg0_matching": (W.chain_poset(2000, 16, 4, seed=0), False), "grid": (W.grid_poset(300, 20), True),
@@ -753,10 +754,14 @@ def test_device_niv_config1_and_host_switch(px, cfg1, monkeypatch):
     assert np.array_equal(D.niv(True), Hh.niv(True))
     monkeypatch.setenv("POSETX_PREP", "host")
     assert build(px, W.chain_poset(2000, 16, 4, seed=0)).info_dict()["niv_device_rounds"] == 0
+    monkeypatch.delenv("POSETX_PREP")
+    # below 2^24 entries the host recursion is the default
+    assert build(px, W.chain_poset(2000, 16, 4, seed=0)).info_dict()["niv_device_rounds"] == 0
 
 
-def test_device_niv_rejects_unordered_chains(px):
+def test_device_niv_rejects_unordered_chains(px, monkeypatch):
     """Planted chains that the DAG does not order are rejected by the device check too."""
+    monkeypatch.setenv("POSETX_PREP", "device")
     p = W.worked_example()
     co, cp = p.chain_of.copy(), p.chain_pos.copy()
     co[[4, 5]] = co[[5, 4]]; cp[[4, 5]] = cp[[5, 4]]     # x5 and x6 are incomparable
@@ -772,3 +777,20 @@ def test_device_niv_rejects_unordered_chains(px):
         with pytest.raises(px.PosetxError) as ei:
             px.poset_build(n, indptr, indices, cof, cpos, device=0)
         assert ei.value.name == "PX_ECHAIN"
+
+
+@pytest.mark.parametrize("B", [1, 5, 64, 100])
+def test_refine_report_residual_matches_host(px, B):
+    """The report's backward error max_col ||g - zeta(f)||_inf / ||g||_inf (zeta in float64 of
+    the returned float32 f) equals the same quantity from the oracle's exact zeta.  An unrefined
+    solve on a 64 x 16 grid keeps the residual (~1e-7) far above float64 rounding (~1e-14)."""
+    p = W.grid_poset(64, 16)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = build(px, p)
+    g = W.functions(p.n, B, "uniform", seed=120 + B, lo=-1, hi=1)
+    got, rep = px.mobius(P, T(g), max_refine=0, report=True)
+    fh = H(got).astype(np.float64)
+    r = g.astype(np.float64) - O.zeta(R, fh)
+    want = float((np.abs(r).max(axis=0) / np.abs(g).astype(np.float64).max(axis=0)).max())
+    assert want > 0 and abs(rep["residual"] - want) <= 1e-4 * want, (rep, want)
+    assert not rep["nonfinite"] and rep["iterations"] == 0
