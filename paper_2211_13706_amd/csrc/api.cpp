@@ -334,16 +334,17 @@ std::vector<int32_t> scan_orders(const std::vector<int32_t>& segoff, int64_t nch
 }
 
 struct Layout {
-  size_t y = 0, p64 = 0, r64 = 0, aux = 0, stats = 0, snaps = 0, sync = 0, lq = 0, total = 0;
+  size_t y = 0, p64 = 0, r64 = 0, aux = 0, stats = 0, snaps = 0, sync = 0, lq = 0, part = 0, total = 0;
 };
 
 // Workspace layout of one call: a [n, B] matrix of the working type (P or Y),
 // for float32 refinement two float64 [n, B] matrices (P64 and the residual),
-// the scan's tile states and the refinement statistics.
+// the scan's tile states and the refinement statistics.  nparts: chunk sums
+// of the split long rows of a sparse level solve (8 bytes per column).
 // With nslots >= 0 also the compact walk's L and Q ((2 * nslots + 1) rows of
 // the working type: float64 for the residual of a refinement).
 Layout layout(int64_t n, int64_t B, int dtype, bool refine, int64_t ntiles, int64_t nsnap = 0,
-              int64_t nslots = -1) {
+              int64_t nslots = -1, int64_t nparts = 0) {
   Layout L;
   size_t o = 0;
   L.y = o;  // one row more: the scan's zero row
@@ -364,6 +365,8 @@ Layout layout(int64_t n, int64_t B, int dtype, bool refine, int64_t ntiles, int6
   o = align256(o + (size_t)(2 + ntiles * ((B + px::col_width(B) - 1) / px::col_width(B))) * 4);
   L.lq = o;
   if (nslots >= 0) o = align256(o + (size_t)(2 * nslots + 1) * B * (refine ? 8 : elem_size(dtype)));
+  L.part = o;
+  o = align256(o + (size_t)nparts * B * 8);
   L.total = o;
   return L;
 }
@@ -542,6 +545,16 @@ struct px_poset {
   // is -1 where the map has none
   void* d_compact[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
   int32_t nslots[2] = {-1, -1};
+  // sparse level solves: per level, the short rows, and the long rows split
+  // into chunks of consecutive entries (kSplitChunk), per map
+  struct Split {
+    bool on = false;
+    std::vector<int32_t> sptr, lptr, cptr;  // per level: offsets into d_short, d_long, d_items
+    int32_t* d_short = nullptr;
+    int4* d_long = nullptr;
+    int4* d_items = nullptr;
+    int64_t max_items = 0;
+  } split[2];
   px::DevPoset dp;
   Workspace ws;
   int64_t device_bytes = 0;
@@ -575,6 +588,12 @@ void free_poset_device(px_poset* p) {
     if (b) (void)hipFree(b);
   for (int64_t* b : p->d_nivp)
     if (b) (void)hipFree(b);
+  for (auto& sp : p->split) {
+    if (sp.d_short) (void)hipFree(sp.d_short);
+    if (sp.d_long) (void)hipFree(sp.d_long);
+    if (sp.d_items) (void)hipFree(sp.d_items);
+    sp = px_poset::Split();
+  }
   for (auto& dir : p->d_walk)
     for (int32_t*& b : dir)
       if (b) {
@@ -601,6 +620,50 @@ px_status check_matrix_args(int64_t n, int dtype, const void* a, int64_t lda, co
 }
 
 int64_t max_slots(const px_poset* p) { return std::max(p->nslots[0], p->nslots[1]); }
+int64_t max_parts(const px_poset* p) { return std::max(p->split[0].max_items, p->split[1].max_items); }
+
+// Entries per chunk of a split long row in a sparse level solve: a level waits
+// for its longest row, and the rows of the last levels of a wide poset are
+// long (thousands of entries in a handful of rows).
+constexpr int64_t kSplitChunk = 256;
+
+// The split schedule of map m of a sparse poset (host side).
+void build_split(const px::Prep& P, int m, px_poset::Split& sp) {
+  const std::vector<int32_t>& lptr = m ? P.lev_up_ptr : P.lev_down_ptr;
+  const std::vector<int32_t>& rows = m ? P.lev_up_rows : P.lev_down_rows;
+  const std::vector<int64_t>& ep = P.nivp[m];
+  std::vector<int32_t> shorts;
+  std::vector<int4> longs, items;
+  sp.sptr.assign(1, 0);
+  sp.lptr.assign(1, 0);
+  sp.cptr.assign(1, 0);
+  sp.max_items = 0;
+  for (size_t l = 0; l + 1 < lptr.size(); ++l) {
+    const size_t c0 = items.size();
+    for (int32_t i = lptr[l]; i < lptr[l + 1]; ++i) {
+      const int32_t r = rows[i];
+      const int64_t e0 = ep[r], e1 = ep[r + 1];
+      if (e1 - e0 <= kSplitChunk) {
+        shorts.push_back(r);
+        continue;
+      }
+      const int32_t first = (int32_t)(items.size() - c0);
+      for (int64_t e = e0; e < e1; e += kSplitChunk)
+        items.push_back(make_int4(r, (int32_t)e, (int32_t)std::min(e + kSplitChunk, e1), 0));
+      longs.push_back(make_int4(r, first, (int32_t)(items.size() - c0) - first, 0));
+    }
+    sp.sptr.push_back((int32_t)shorts.size());
+    sp.lptr.push_back((int32_t)longs.size());
+    sp.cptr.push_back((int32_t)items.size());
+    sp.max_items = std::max<int64_t>(sp.max_items, (int64_t)(items.size() - c0));
+  }
+  sp.on = true;
+  int64_t b = 0;
+  hipError_t e = upload(&sp.d_short, shorts.data(), shorts.size(), b);
+  if (e == hipSuccess) e = upload(&sp.d_long, longs.data(), longs.size(), b);
+  if (e == hipSuccess) e = upload(&sp.d_items, items.data(), items.size(), b);
+  if (e != hipSuccess) sp.on = false;
+}
 
 bool use_compact(const px_poset* p, bool up, int64_t B) {
   return p->nslots[up ? 1 : 0] >= 0 && compact_enabled() && px::compact_ok(p->dp, up, B);
@@ -609,12 +672,28 @@ bool use_compact(const px_poset* p, bool up, int64_t B) {
 // Level-scheduled solve U y' = g (Alg. 4, first loop; Alg. 5 schedule), one
 // launch per level so that every level sees the previous one complete.
 hipError_t solve_levels(const px_poset* p, bool up, px::ElemType tin, const void* g, int64_t ldg, px::ElemType ty,
-                        void* Y, int64_t B, hipStream_t s) {
+                        void* Y, int64_t B, void* part, hipStream_t s) {
   const std::vector<int32_t>& ptr = up ? p->prep.lev_up_ptr : p->prep.lev_down_ptr;
   const int32_t* rows = up ? p->d_lev_up : p->d_lev_down;
   if (p->prep.n > 0) {
     hipError_t e = px::launch_usolve_begin(p->dp, ty, Y, B, s);
     if (e != hipSuccess) return e;
+  }
+  const px_poset::Split& sp = p->split[up ? 1 : 0];
+  if (sp.on) {  // sparse rows: short rows whole, long rows in chunks
+    for (size_t l = 0; l + 1 < ptr.size(); ++l) {
+      prof::Scope sc(prof::USOLVE, s);
+      hipError_t e = hipSuccess;
+      const int64_t ns = sp.sptr[l + 1] - sp.sptr[l];
+      if (ns)
+        e = px::launch_usolve_level(p->dp, up, sp.d_short + sp.sptr[l], sp.sptr[l], ns, tin, g, ldg, ty, Y, B, s);
+      const int64_t nl = sp.lptr[l + 1] - sp.lptr[l];
+      if (e == hipSuccess && nl)
+        e = px::launch_usolve_split(p->dp, up, sp.d_items + sp.cptr[l], sp.cptr[l + 1] - sp.cptr[l],
+                                    sp.d_long + sp.lptr[l], nl, tin, g, ldg, ty, Y, B, part, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
   for (size_t l = 0; l + 1 < ptr.size(); ++l) {
     prof::Scope sc(prof::USOLVE, s);
@@ -675,13 +754,13 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   const bool refine = dtype == PX_F32;
   const int cw = px::col_width(B);
   const int64_t nt = p->ntiles[px::seg_index(cw)];
-  Layout L = layout(n, B, dtype, refine, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p));
+  Layout L = layout(n, B, dtype, refine, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p), max_parts(p));
   if ((st = p->ws.ensure(L.total)) != PX_OK) return st;
   char* w = (char*)p->ws.p;
   hipStream_t s = (hipStream_t)stream;
   const px::ElemType T = etype(dtype);
   const int dir = up ? -1 : 1;
-  hipError_t e = solve_levels(p, up, T, g, ldg, T, w + L.y, B, s);
+  hipError_t e = solve_levels(p, up, T, g, ldg, T, w + L.y, B, w + L.part, s);
   if (e == hipSuccess) e = run_chain_diff(p->dp, dir, T, w + L.y, B, T, f, ldf, false, nullptr, s);
   if (e != hipSuccess) return hip_status(e, "mobius launch");
   if (!refine) return PX_OK;
@@ -720,7 +799,7 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   bool nonfinite = false, converged = false;
   while (it < max_refine) {
     e = residual();
-    if (e == hipSuccess) e = solve_levels(p, up, px::E_F64, r64, B, px::E_F32, w + L.y, B, s);
+    if (e == hipSuccess) e = solve_levels(p, up, px::E_F64, r64, B, px::E_F32, w + L.y, B, w + L.part, s);
     if (e == hipSuccess)
       e = run_chain_diff(p->dp, dir, px::E_F32, w + L.y, B, px::E_F32, f, ldf, true, check ? dstats : nullptr, s);
     if (e != hipSuccess) return hip_status(e, "refinement launch");
@@ -1044,8 +1123,11 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
           o += p->ntiles[i];
         }
     }
-    // the walking gathers read dense niv rows; sparse rows take the plain gather
+    // the walking gathers read dense niv rows; sparse rows take the plain gather,
+    // and their level solves split long rows (entry offsets held in 32 bits)
     if (e == hipSuccess && !P.sparse) e = set_walk(p, kWalkT, kWalkEvents);
+    if (e == hipSuccess && P.sparse && P.nnz_niv < INT32_MAX && P.nnz_niv_up < INT32_MAX)
+      for (int m = 0; m < (p->has_up ? 2 : 1); ++m) build_split(P, m, p->split[m]);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       free_poset_device(p);
@@ -1180,7 +1262,8 @@ px_status px_reserve(px_poset* p, int dtype, int64_t B) {
   DeviceGuard dg(p->device);
   const int64_t nt = p->ntiles[px::seg_index(px::col_width(B))];
   return p->ws.ensure(
-      layout(p->prep.n, B, dtype, dtype == PX_F32, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p)).total);
+      layout(p->prep.n, B, dtype, dtype == PX_F32, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p),
+             max_parts(p)).total);
 }
 
 px_status px_zeta(px_poset* p, int dtype, const void* f, int64_t ldf, void* g, int64_t ldg, int64_t B, void* stream) {

@@ -156,6 +156,15 @@ hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_ro
                                ElemType tin, const void* g, int64_t ldg, ElemType ty, void* Y,
                                int64_t B, hipStream_t s);
 
+// The long rows of a level of a sparse solve, split into chunks: items[i] =
+// {row, first entry, end entry, 0} (nitems), longs[j] = {row, first item,
+// items, 0} (nlongs, the items of a row consecutive and in entry order).
+// Y[row] = g[node(row)] minus the chunk sums in order.  part: nitems * B
+// 8-byte words of scratch.
+hipError_t launch_usolve_split(const DevPoset& d, bool up, const int4* items, int64_t nitems, const int4* longs,
+                               int64_t nlongs, ElemType tin, const void* g, int64_t ldg, ElemType ty, void* Y,
+                               int64_t B, void* part, hipStream_t s);
+
 // y = V^{-1} y' (dir=+1: minus the element below in the chain; dir=-1: minus the
 // element above).  accumulate: out += result instead of out = result.
 // stats (nullable, float32/float64 only): 2B+1 uint64 words that receive the

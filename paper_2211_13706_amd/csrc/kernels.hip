@@ -1374,6 +1374,41 @@ __global__ __launch_bounds__(WG) void k_usolve(DevPoset d, const int32_t* __rest
   Y[r * B + col] = (TY)acc;
 }
 
+// Long sparse rows of a level are split into chunks of consecutive entries:
+// item i = {row, first entry, end entry, 0} gets part[i] = Σ Y[entry] over
+// its chunk (own row skipped), one item per row group; then each long row
+// {row, first item, items, 0} takes g minus its chunks' sums in chunk order.
+// A row's result depends only on its chunking, which the host fixes.
+template <typename TY>
+__global__ __launch_bounds__(WG) void k_usolve_csr_part(DevPoset d, const int4* __restrict__ items, int64_t cnt,
+                                                        int cw, const int32_t* __restrict__ er,
+                                                        const TY* __restrict__ Y, int64_t B,
+                                                        typename Wide<TY>::W* __restrict__ part) {
+  using W = typename Wide<TY>::W;
+  const int RG = WG / cw;
+  const int64_t i = (int64_t)blockIdx.x * RG + threadIdx.x / cw;
+  const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
+  if (i >= cnt || col >= B) return;
+  const int4 it = items[i];
+  part[i * B + col] = csr_sum<TY, W>(er, it.y, it.z, it.x, d.n, Y, B, col);
+}
+
+template <typename Tin, typename TY>
+__global__ __launch_bounds__(WG) void k_usolve_csr_fin(DevPoset d, const int4* __restrict__ longs, int64_t cnt,
+                                                       int cw, const Tin* __restrict__ g, int64_t ldg,
+                                                       const typename Wide<TY>::W* __restrict__ part,
+                                                       TY* __restrict__ Y, int64_t B) {
+  using W = typename Wide<TY>::W;
+  const int RG = WG / cw;
+  const int64_t i = (int64_t)blockIdx.x * RG + threadIdx.x / cw;
+  const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
+  if (i >= cnt || col >= B) return;
+  const int4 lr = longs[i];
+  W acc = (W)g[(int64_t)d.node_of_row[lr.x] * ldg + col];
+  for (int c = 0; c < lr.z; ++c) acc -= part[(int64_t)(lr.y + c) * B + col];
+  Y[(int64_t)lr.x * B + col] = (TY)acc;
+}
+
 // The same over sparse niv rows (CSR ep / er).
 template <typename Tin, typename TY>
 __global__ __launch_bounds__(WG) void k_usolve_csr(DevPoset d, const int64_t* __restrict__ ep,
@@ -1869,6 +1904,38 @@ hipError_t usolve_csr(const DevPoset& d, const int64_t* ep, const int32_t* er, c
   return hipGetLastError();
 }
 }  // namespace
+
+namespace {
+template <typename Tin, typename TY>
+hipError_t usolve_split_typed(const DevPoset& d, const int32_t* er, const int4* items, int64_t nitems,
+                              const int4* longs, int64_t nlongs, const void* g, int64_t ldg, void* Y, int64_t B,
+                              void* part, hipStream_t s) {
+  using W = typename Wide<TY>::W;
+  const int cw = col_width(B);
+  hipLaunchKernelGGL((k_usolve_csr_part<TY>), grid2(nitems, cw, B), dim3(WG), 0, s, d, items, nitems, cw, er,
+                     (const TY*)Y, B, (W*)part);
+  hipLaunchKernelGGL((k_usolve_csr_fin<Tin, TY>), grid2(nlongs, cw, B), dim3(WG), 0, s, d, longs, nlongs, cw,
+                     (const Tin*)g, ldg, (const W*)part, (TY*)Y, B);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_usolve_split(const DevPoset& d, bool up, const int4* items, int64_t nitems, const int4* longs,
+                               int64_t nlongs, ElemType tin, const void* g, int64_t ldg, ElemType ty, void* Y,
+                               int64_t B, void* part, hipStream_t s) {
+  if (nlongs == 0) return hipSuccess;
+  const int32_t* er = d.nivr[up ? 1 : 0];
+  if (!er) return hipErrorInvalidValue;
+  if (tin == E_I64 && ty == E_I64)
+    return usolve_split_typed<int64_t, int64_t>(d, er, items, nitems, longs, nlongs, g, ldg, Y, B, part, s);
+  if (tin == E_F32 && ty == E_F32)
+    return usolve_split_typed<float, float>(d, er, items, nitems, longs, nlongs, g, ldg, Y, B, part, s);
+  if (tin == E_F64 && ty == E_F32)
+    return usolve_split_typed<double, float>(d, er, items, nitems, longs, nlongs, g, ldg, Y, B, part, s);
+  if (tin == E_F64 && ty == E_F64)
+    return usolve_split_typed<double, double>(d, er, items, nitems, longs, nlongs, g, ldg, Y, B, part, s);
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_rows, int64_t i0, int64_t cnt,
                                ElemType tin, const void* g, int64_t ldg, ElemType ty, void* Y, int64_t B,
