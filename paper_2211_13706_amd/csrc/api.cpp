@@ -491,8 +491,8 @@ hipError_t run_gather(const px::DevPoset& d, bool up, px::ElemType tp, const voi
     prof::WalkHook hook;
     if (snaps && !d.nivp[up ? 1 : 0])
       return px::launch_gather(d, up, tp, P, B, tout, out, ldo, tres, resid, ldr, snaps, &hook, s);
-    prof::Scope sc(prof::GATHER, s);
-    return px::launch_gather(d, up, tp, P, B, tout, out, ldo, tres, resid, ldr, nullptr, nullptr, s);
+    prof::Scope sc(prof::GATHER, s);  // (sparse rows: snaps holds the split gather's chunk sums)
+    return px::launch_gather(d, up, tp, P, B, tout, out, ldo, tres, resid, ldr, snaps, nullptr, s);
   }
   return px::launch_gather(d, up, tp, P, B, tout, out, ldo, tres, resid, ldr, snaps, nullptr, s);
 }
@@ -554,6 +554,11 @@ struct px_poset {
     int4* d_long = nullptr;
     int4* d_items = nullptr;
     int64_t max_items = 0;
+    // the zeta gather's split (all rows at once)
+    int32_t* d_gshort = nullptr;
+    int4* d_glong = nullptr;
+    int4* d_gitems = nullptr;
+    int64_t gitems = 0;
   } split[2];
   px::DevPoset dp;
   Workspace ws;
@@ -592,6 +597,9 @@ void free_poset_device(px_poset* p) {
     if (sp.d_short) (void)hipFree(sp.d_short);
     if (sp.d_long) (void)hipFree(sp.d_long);
     if (sp.d_items) (void)hipFree(sp.d_items);
+    if (sp.d_gshort) (void)hipFree(sp.d_gshort);
+    if (sp.d_glong) (void)hipFree(sp.d_glong);
+    if (sp.d_gitems) (void)hipFree(sp.d_gitems);
     sp = px_poset::Split();
   }
   for (auto& dir : p->d_walk)
@@ -620,15 +628,37 @@ px_status check_matrix_args(int64_t n, int dtype, const void* a, int64_t lda, co
 }
 
 int64_t max_slots(const px_poset* p) { return std::max(p->nslots[0], p->nslots[1]); }
-int64_t max_parts(const px_poset* p) { return std::max(p->split[0].max_items, p->split[1].max_items); }
+int64_t max_parts(const px_poset* p) {
+  return std::max({p->split[0].max_items, p->split[1].max_items, p->split[0].gitems, p->split[1].gitems});
+}
 
 // Entries per chunk of a split long row in a sparse level solve: a level waits
 // for its longest row, and the rows of the last levels of a wide poset are
 // long (thousands of entries in a handful of rows).
 constexpr int64_t kSplitChunk = 256;
 
-// The split schedule of map m of a sparse poset (host side).
-void build_split(const px::Prep& P, int m, px_poset::Split& sp) {
+// Short rows and chunks of the long ones among rows[0 .. cnt) (host side);
+// longs[j].y is relative to the first item added here.
+void split_rows(const std::vector<int64_t>& ep, const int32_t* rows, int64_t cnt, std::vector<int32_t>& shorts,
+                std::vector<int4>& longs, std::vector<int4>& items) {
+  const size_t c0 = items.size();
+  for (int64_t i = 0; i < cnt; ++i) {
+    const int32_t r = rows ? rows[i] : (int32_t)i;
+    const int64_t e0 = ep[r], e1 = ep[r + 1];
+    if (e1 - e0 <= kSplitChunk) {
+      shorts.push_back(r);
+      continue;
+    }
+    const int32_t first = (int32_t)(items.size() - c0);
+    for (int64_t e = e0; e < e1; e += kSplitChunk)
+      items.push_back(make_int4(r, (int32_t)e, (int32_t)std::min(e + kSplitChunk, e1), 0));
+    longs.push_back(make_int4(r, first, (int32_t)(items.size() - c0) - first, 0));
+  }
+}
+
+// The split schedules of map m of a sparse poset: per level for the solve,
+// and over all rows for the zeta gather.
+void build_split(const px::Prep& P, int m, px_poset::Split& sp, px::GatherSplit& gs) {
   const std::vector<int32_t>& lptr = m ? P.lev_up_ptr : P.lev_down_ptr;
   const std::vector<int32_t>& rows = m ? P.lev_up_rows : P.lev_down_rows;
   const std::vector<int64_t>& ep = P.nivp[m];
@@ -640,18 +670,7 @@ void build_split(const px::Prep& P, int m, px_poset::Split& sp) {
   sp.max_items = 0;
   for (size_t l = 0; l + 1 < lptr.size(); ++l) {
     const size_t c0 = items.size();
-    for (int32_t i = lptr[l]; i < lptr[l + 1]; ++i) {
-      const int32_t r = rows[i];
-      const int64_t e0 = ep[r], e1 = ep[r + 1];
-      if (e1 - e0 <= kSplitChunk) {
-        shorts.push_back(r);
-        continue;
-      }
-      const int32_t first = (int32_t)(items.size() - c0);
-      for (int64_t e = e0; e < e1; e += kSplitChunk)
-        items.push_back(make_int4(r, (int32_t)e, (int32_t)std::min(e + kSplitChunk, e1), 0));
-      longs.push_back(make_int4(r, first, (int32_t)(items.size() - c0) - first, 0));
-    }
+    split_rows(ep, rows.data() + lptr[l], lptr[l + 1] - lptr[l], shorts, longs, items);
     sp.sptr.push_back((int32_t)shorts.size());
     sp.lptr.push_back((int32_t)longs.size());
     sp.cptr.push_back((int32_t)items.size());
@@ -662,7 +681,25 @@ void build_split(const px::Prep& P, int m, px_poset::Split& sp) {
   hipError_t e = upload(&sp.d_short, shorts.data(), shorts.size(), b);
   if (e == hipSuccess) e = upload(&sp.d_long, longs.data(), longs.size(), b);
   if (e == hipSuccess) e = upload(&sp.d_items, items.data(), items.size(), b);
-  if (e != hipSuccess) sp.on = false;
+  if (e != hipSuccess) {
+    sp.on = false;
+    return;
+  }
+  shorts.clear();
+  longs.clear();
+  items.clear();
+  split_rows(ep, nullptr, P.n, shorts, longs, items);
+  e = upload(&sp.d_gshort, shorts.data(), shorts.size(), b);
+  if (e == hipSuccess) e = upload(&sp.d_glong, longs.data(), longs.size(), b);
+  if (e == hipSuccess) e = upload(&sp.d_gitems, items.data(), items.size(), b);
+  if (e != hipSuccess) return;
+  sp.gitems = (int64_t)items.size();
+  gs.shorts = sp.d_gshort;
+  gs.nshorts = (int64_t)shorts.size();
+  gs.items = sp.d_gitems;
+  gs.nitems = (int64_t)items.size();
+  gs.longs = sp.d_glong;
+  gs.nlongs = (int64_t)longs.size();
 }
 
 bool use_compact(const px_poset* p, bool up, int64_t B) {
@@ -716,7 +753,7 @@ px_status zeta_impl(px_poset* p, bool up, int dtype, const void* f, int64_t ldf,
   if (!dg.ok) return fail(PX_EHIP, "hipSetDevice failed");
   const int cw = px::col_width(B);
   const int64_t nt = p->ntiles[px::seg_index(cw)];
-  Layout L = layout(p->prep.n, B, dtype, false, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p));
+  Layout L = layout(p->prep.n, B, dtype, false, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p), max_parts(p));
   if ((st = p->ws.ensure(L.total)) != PX_OK) return st;
   char* w = (char*)p->ws.p;
   hipStream_t s = (hipStream_t)stream;
@@ -726,7 +763,9 @@ px_status zeta_impl(px_poset* p, bool up, int dtype, const void* f, int64_t ldf,
                                   w + L.lq, w + L.snaps, s),
                       "zeta launch");
   hipError_t e = run_scan(p->dp, up ? -1 : 1, T, f, ldf, T, w + L.y, B, w + L.aux, nt, (int*)(w + L.sync), s);
-  if (e == hipSuccess) e = run_gather(p->dp, up, T, w + L.y, B, T, g, ldg, T, nullptr, 0, w + L.snaps, s);
+  // sparse rows: the chunk sums of the split gather take the snapshots' place
+  if (e == hipSuccess)
+    e = run_gather(p->dp, up, T, w + L.y, B, T, g, ldg, T, nullptr, 0, p->prep.sparse ? w + L.part : w + L.snaps, s);
   return hip_status(e, "zeta launch");
 }
 
@@ -791,7 +830,8 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
                          w + L.lq, w + L.snaps, s);
     hipError_t e2 = run_scan(p->dp, dir, px::E_F32, f, ldf, px::E_F64, w + L.p64, B, w + L.aux, nt, (int*)(w + L.sync), s);
     if (e2 == hipSuccess)
-      e2 = run_gather(p->dp, up, px::E_F64, w + L.p64, B, px::E_F64, r64, B, px::E_F32, g, ldg, w + L.snaps, s);
+      e2 = run_gather(p->dp, up, px::E_F64, w + L.p64, B, px::E_F64, r64, B, px::E_F32, g, ldg,
+                      p->prep.sparse ? w + L.part : w + L.snaps, s);
     return e2;
   };
   int it = 0;
@@ -1127,7 +1167,7 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
     // and their level solves split long rows (entry offsets held in 32 bits)
     if (e == hipSuccess && !P.sparse) e = set_walk(p, kWalkT, kWalkEvents);
     if (e == hipSuccess && P.sparse && P.nnz_niv < INT32_MAX && P.nnz_niv_up < INT32_MAX)
-      for (int m = 0; m < (p->has_up ? 2 : 1); ++m) build_split(P, m, p->split[m]);
+      for (int m = 0; m < (p->has_up ? 2 : 1); ++m) build_split(P, m, p->split[m], p->dp.gsplit[m]);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       free_poset_device(p);

@@ -50,6 +50,17 @@ struct WalkTables {
   int64_t qoff_tiles = 0;                // tiles of height 64 that tmask / qoff cover
 };
 
+// The sparse gather's rows split by length: the short rows (taken whole) and
+// the long ones in chunks, as for the level solve (see launch_usolve_split).
+struct GatherSplit {
+  const int32_t* shorts = nullptr;  // nullptr: no split, every row whole
+  int64_t nshorts = 0;
+  const int4* items = nullptr;
+  int64_t nitems = 0;
+  const int4* longs = nullptr;
+  int64_t nlongs = 0;
+};
+
 // Static description of one poset (or a batch of posets) on the device.
 struct DevPoset {
   int32_t n = 0, k = 0;           // for a batch: total rows; k = 0 (per-poset k)
@@ -63,6 +74,7 @@ struct DevPoset {
   // row r's finite entries are nivr[m][nivp[m][r] .. nivp[m][r + 1]), ascending
   const int64_t* nivp[2] = {nullptr, nullptr};
   const int32_t* nivr[2] = {nullptr, nullptr};
+  GatherSplit gsplit[2];
   const int32_t* segoff = nullptr;      // [7][nchains+1] tile offsets per tile height
   // per tile height (as segoff): every tile's {first row, end row of its chain}
   // (nullable), and the most tiles any chain has
@@ -122,7 +134,8 @@ struct LaunchHook {
   virtual ~LaunchHook() = default;
 };
 
-// snaps: scratch for walk[up].nsnap * B values of type tp (nullable: one-thread-per-row gather).
+// snaps: scratch for walk[up].nsnap * B values of type tp (nullable: one-thread-per-row gather);
+// for sparse rows with a split (gsplit), gsplit.nitems * B 8-byte chunk sums.
 hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P, int64_t B,
                          ElemType tout, void* out, int64_t ldo, ElemType tres, const void* resid,
                          int64_t ldr, void* snaps, LaunchHook* hook, hipStream_t s);

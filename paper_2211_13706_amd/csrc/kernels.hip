@@ -925,18 +925,21 @@ __global__ __launch_bounds__(WG) void k_gather(DevPoset d, const int32_t* __rest
 }
 
 // The gather over sparse niv rows (CSR: ep[r] .. ep[r + 1] index er), one
-// thread per (row, column).  The entries are vector loads even where a row is
-// a whole wavefront: scalar loads of them made this kernel 13% slower.
+// thread per (row, column), over all rows or the listed ones (rows != nullptr).
+// The entries are vector loads even where a row is a whole wavefront: scalar
+// loads of them made this kernel 13% slower.
 template <typename TP, typename Tout, typename Tres, bool RESID>
 __global__ __launch_bounds__(WG) void k_gather_csr(DevPoset d, const int64_t* __restrict__ ep,
-                                                   const int32_t* __restrict__ er, int cw, const TP* __restrict__ P,
-                                                   int64_t B, Tout* __restrict__ out, int64_t ldo,
-                                                   const Tres* __restrict__ res, int64_t ldr) {
+                                                   const int32_t* __restrict__ er, const int32_t* __restrict__ rows,
+                                                   int64_t nrows, int cw, const TP* __restrict__ P, int64_t B,
+                                                   Tout* __restrict__ out, int64_t ldo, const Tres* __restrict__ res,
+                                                   int64_t ldr) {
   using W = typename Wide<TP>::W;
   const int RG = WG / cw;
-  const int64_t r = (int64_t)blockIdx.x * RG + threadIdx.x / cw;
+  const int64_t i = (int64_t)blockIdx.x * RG + threadIdx.x / cw;
   const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
-  if (r >= d.n || col >= B) return;
+  if (i >= nrows || col >= B) return;
+  const int64_t r = rows ? rows[i] : i;
   const W acc = csr_sum<TP, W>(er, ep[r], ep[r + 1], -1, d.n, P, B, col);  // row n of P is zero
   const int64_t node = d.node_of_row[r];
   if constexpr (RESID) {
@@ -1379,18 +1382,42 @@ __global__ __launch_bounds__(WG) void k_usolve(DevPoset d, const int32_t* __rest
 // its chunk (own row skipped), one item per row group; then each long row
 // {row, first item, items, 0} takes g minus its chunks' sums in chunk order.
 // A row's result depends only on its chunking, which the host fixes.
-template <typename TY>
-__global__ __launch_bounds__(WG) void k_usolve_csr_part(DevPoset d, const int4* __restrict__ items, int64_t cnt,
-                                                        int cw, const int32_t* __restrict__ er,
-                                                        const TY* __restrict__ Y, int64_t B,
-                                                        typename Wide<TY>::W* __restrict__ part) {
+// (SKIP_OWN: the solve, which leaves the row's own entry out; the zeta gather
+// keeps it.)
+template <typename TY, bool SKIP_OWN>
+__global__ __launch_bounds__(WG) void k_csr_part(DevPoset d, const int4* __restrict__ items, int64_t cnt, int cw,
+                                                 const int32_t* __restrict__ er, const TY* __restrict__ Y, int64_t B,
+                                                 typename Wide<TY>::W* __restrict__ part) {
   using W = typename Wide<TY>::W;
   const int RG = WG / cw;
   const int64_t i = (int64_t)blockIdx.x * RG + threadIdx.x / cw;
   const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
   if (i >= cnt || col >= B) return;
   const int4 it = items[i];
-  part[i * B + col] = csr_sum<TY, W>(er, it.y, it.z, it.x, d.n, Y, B, col);
+  part[i * B + col] = csr_sum<TY, W>(er, it.y, it.z, SKIP_OWN ? it.x : -1, d.n, Y, B, col);
+}
+
+// The zeta gather's long rows: out[node(row)] = Σ of the chunk sums in order
+// (or resid minus that for a refinement residual).
+template <typename TP, typename Tout, typename Tres, bool RESID>
+__global__ __launch_bounds__(WG) void k_gather_csr_fin(DevPoset d, const int4* __restrict__ longs, int64_t cnt,
+                                                       int cw, const typename Wide<TP>::W* __restrict__ part,
+                                                       int64_t B, Tout* __restrict__ out, int64_t ldo,
+                                                       const Tres* __restrict__ res, int64_t ldr) {
+  using W = typename Wide<TP>::W;
+  const int RG = WG / cw;
+  const int64_t i = (int64_t)blockIdx.x * RG + threadIdx.x / cw;
+  const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
+  if (i >= cnt || col >= B) return;
+  const int4 lr = longs[i];
+  W acc = W(0);
+  for (int c = 0; c < lr.z; ++c) acc += part[(int64_t)(lr.y + c) * B + col];
+  const int64_t node = d.node_of_row[lr.x];
+  if constexpr (RESID) {
+    out[node * ldo + col] = (Tout)((double)res[node * ldr + col] - (double)acc);
+  } else {
+    out[node * ldo + col] = (Tout)acc;
+  }
 }
 
 template <typename Tin, typename TY>
@@ -1786,31 +1813,63 @@ hipError_t launch_zeta_compact(const DevPoset& d, int dir, ElemType tin, const v
 }
 
 namespace {
-hipError_t gather_csr(const DevPoset& d, const int64_t* ep, const int32_t* er, ElemType tp, const void* P,
-                            int64_t B, ElemType tout, void* out, int64_t ldo, ElemType tres, const void* resid,
-                            int64_t ldr, hipStream_t s) {
+hipError_t gather_csr(const DevPoset& d, const int64_t* ep, const int32_t* er, const int32_t* rows, int64_t nrows,
+                      ElemType tp, const void* P, int64_t B, ElemType tout, void* out, int64_t ldo, ElemType tres,
+                      const void* resid, int64_t ldr, hipStream_t s) {
+  if (nrows == 0) return hipSuccess;
   const int cw = col_width(B);
-  const dim3 g = grid2(d.n, cw, B);
+  const dim3 g = grid2(nrows, cw, B);
   if (resid && tres == E_F32)
-    hipLaunchKernelGGL((k_gather_csr<double, double, float, true>), g, dim3(WG), 0, s, d, ep, er, cw,
+    hipLaunchKernelGGL((k_gather_csr<double, double, float, true>), g, dim3(WG), 0, s, d, ep, er, rows, nrows, cw,
                        (const double*)P, B, (double*)out, ldo, (const float*)resid, ldr);
   else if (resid && tres == E_F64)
-    hipLaunchKernelGGL((k_gather_csr<double, double, double, true>), g, dim3(WG), 0, s, d, ep, er, cw,
+    hipLaunchKernelGGL((k_gather_csr<double, double, double, true>), g, dim3(WG), 0, s, d, ep, er, rows, nrows, cw,
                        (const double*)P, B, (double*)out, ldo, (const double*)resid, ldr);
   else if (resid)
     return hipErrorInvalidValue;
   else if (tp == E_I64 && tout == E_I64)
-    hipLaunchKernelGGL((k_gather_csr<int64_t, int64_t, int64_t, false>), g, dim3(WG), 0, s, d, ep, er, cw,
-                       (const int64_t*)P, B, (int64_t*)out, ldo, (const int64_t*)nullptr, 0);
+    hipLaunchKernelGGL((k_gather_csr<int64_t, int64_t, int64_t, false>), g, dim3(WG), 0, s, d, ep, er, rows, nrows,
+                       cw, (const int64_t*)P, B, (int64_t*)out, ldo, (const int64_t*)nullptr, 0);
   else if (tp == E_F32 && tout == E_F32)
-    hipLaunchKernelGGL((k_gather_csr<float, float, float, false>), g, dim3(WG), 0, s, d, ep, er, cw,
+    hipLaunchKernelGGL((k_gather_csr<float, float, float, false>), g, dim3(WG), 0, s, d, ep, er, rows, nrows, cw,
                        (const float*)P, B, (float*)out, ldo, (const float*)nullptr, 0);
   else if (tp == E_F64 && tout == E_F64)
-    hipLaunchKernelGGL((k_gather_csr<double, double, double, false>), g, dim3(WG), 0, s, d, ep, er, cw,
+    hipLaunchKernelGGL((k_gather_csr<double, double, double, false>), g, dim3(WG), 0, s, d, ep, er, rows, nrows, cw,
                        (const double*)P, B, (double*)out, ldo, (const double*)nullptr, 0);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+// The long rows of the sparse gather: chunk sums, then each row's total.
+template <typename TP, typename Tout, typename Tres, bool RESID>
+hipError_t gather_split_typed(const DevPoset& d, int m, const void* P, int64_t B, void* out, int64_t ldo,
+                              const void* resid, int64_t ldr, void* part, hipStream_t s) {
+  using W = typename Wide<TP>::W;
+  const int cw = col_width(B);
+  const GatherSplit& gs = d.gsplit[m];
+  hipLaunchKernelGGL((k_csr_part<TP, false>), grid2(gs.nitems, cw, B), dim3(WG), 0, s, d, gs.items, gs.nitems, cw,
+                     d.nivr[m], (const TP*)P, B, (W*)part);
+  hipLaunchKernelGGL((k_gather_csr_fin<TP, Tout, Tres, RESID>), grid2(gs.nlongs, cw, B), dim3(WG), 0, s, d,
+                     gs.longs, gs.nlongs, cw, (const W*)part, B, (Tout*)out, ldo, (const Tres*)resid, ldr);
+  return hipGetLastError();
+}
+
+hipError_t gather_split(const DevPoset& d, int m, ElemType tp, const void* P, int64_t B, ElemType tout, void* out,
+                        int64_t ldo, ElemType tres, const void* resid, int64_t ldr, void* part, hipStream_t s) {
+  if (d.gsplit[m].nlongs == 0) return hipSuccess;
+  if (resid && tres == E_F32)
+    return gather_split_typed<double, double, float, true>(d, m, P, B, out, ldo, resid, ldr, part, s);
+  if (resid && tres == E_F64)
+    return gather_split_typed<double, double, double, true>(d, m, P, B, out, ldo, resid, ldr, part, s);
+  if (resid) return hipErrorInvalidValue;
+  if (tp == E_I64 && tout == E_I64)
+    return gather_split_typed<int64_t, int64_t, int64_t, false>(d, m, P, B, out, ldo, nullptr, 0, part, s);
+  if (tp == E_F32 && tout == E_F32)
+    return gather_split_typed<float, float, float, false>(d, m, P, B, out, ldo, nullptr, 0, part, s);
+  if (tp == E_F64 && tout == E_F64)
+    return gather_split_typed<double, double, double, false>(d, m, P, B, out, ldo, nullptr, 0, part, s);
+  return hipErrorInvalidValue;
 }
 }  // namespace
 
@@ -1823,8 +1882,14 @@ hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P,
   const int32_t* nv = up ? d.niv_up : d.niv;
   if (resid && (tp != E_F64 || tout != E_F64)) return hipErrorInvalidValue;
   if (const int64_t* ep = d.nivp[up ? 1 : 0]) {  // sparse niv rows
-    const int32_t* er = d.nivr[up ? 1 : 0];
-    return gather_csr(d, ep, er, tp, P, B, tout, out, ldo, tres, resid, ldr, s);
+    const int m = up ? 1 : 0;
+    const int32_t* er = d.nivr[m];
+    const GatherSplit& gs = d.gsplit[m];
+    if (!gs.shorts || !snaps) return gather_csr(d, ep, er, nullptr, d.n, tp, P, B, tout, out, ldo, tres, resid, ldr, s);
+    // short rows whole, long rows in chunks (snaps: the chunk sums)
+    hipError_t e = gather_csr(d, ep, er, gs.shorts, gs.nshorts, tp, P, B, tout, out, ldo, tres, resid, ldr, s);
+    if (e == hipSuccess) e = gather_split(d, m, tp, P, B, tout, out, ldo, tres, resid, ldr, snaps, s);
+    return e;
   }
   // the walking gather when its tables and snapshot scratch are there
   const WalkTables& w = d.walk[up ? 1 : 0];
@@ -1912,7 +1977,7 @@ hipError_t usolve_split_typed(const DevPoset& d, const int32_t* er, const int4* 
                               void* part, hipStream_t s) {
   using W = typename Wide<TY>::W;
   const int cw = col_width(B);
-  hipLaunchKernelGGL((k_usolve_csr_part<TY>), grid2(nitems, cw, B), dim3(WG), 0, s, d, items, nitems, cw, er,
+  hipLaunchKernelGGL((k_csr_part<TY, true>), grid2(nitems, cw, B), dim3(WG), 0, s, d, items, nitems, cw, er,
                      (const TY*)Y, B, (W*)part);
   hipLaunchKernelGGL((k_usolve_csr_fin<Tin, TY>), grid2(nlongs, cw, B), dim3(WG), 0, s, d, longs, nlongs, cw,
                      (const Tin*)g, ldg, (const W*)part, (TY*)Y, B);
