@@ -151,6 +151,11 @@ px_status px_poset_info(const px_poset* p, px_info* out);
  *           up != 0 gives the dual map: the lowest element of chain j above x.
  *   levels: level[n] of every node in the Möbius schedule (up != 0: adjoint schedule). */
 px_status px_poset_chains(const px_poset* p, int32_t* chain_of, int32_t* chain_pos);
+/* The chain-major numbering the kernels work in: row_of_node[x] = first row of
+ * x's chain + its position (chains in order, bottom first), n entries.  Function
+ * matrices stay in node order at this interface; the numbering lets a caller
+ * relate them to the chain-major prefix matrix V f (§3). */
+px_status px_poset_rows(const px_poset* p, int64_t* row_of_node);
 px_status px_poset_niv(const px_poset* p, int up, int32_t* out);
 /* The same map by rows of its finite entries (N of §2.4 in CSR form, node order):
  * the entries of node x are nodes[ptr[x] .. ptr[x+1]), the node ids niv_j(x) in

@@ -1241,6 +1241,12 @@ px_status px_poset_chains(const px_poset* p, int32_t* chain_of, int32_t* chain_p
   return PX_OK;
 }
 
+px_status px_poset_rows(const px_poset* p, int64_t* row_of_node) {
+  if (!p || (p->prep.n > 0 && !row_of_node)) return fail(PX_EINVAL, "null argument");
+  std::copy(p->prep.row_of_node.begin(), p->prep.row_of_node.end(), row_of_node);
+  return PX_OK;
+}
+
 px_status px_poset_niv(const px_poset* p, int up, int32_t* out) {
   if (!p || (p->prep.n > 0 && !out)) return fail(PX_EINVAL, "null argument");
   if (up && !p->has_up) return fail(PX_EUNSUPPORTED, "poset was built with PX_BUILD_NO_ADJOINT");

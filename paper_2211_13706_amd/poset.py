@@ -88,6 +88,12 @@ class Poset:
         _lib.check(_lib.lib().px_poset_chains(self.handle, co.ctypes.data, cp.ctypes.data), "px_poset_chains")
         return co, cp
 
+    def rows(self) -> np.ndarray:
+        """Chain-major row of every node (px_poset_rows)."""
+        out = np.empty(self.n, np.int64)
+        _lib.check(_lib.lib().px_poset_rows(self.handle, out.ctypes.data), "px_poset_rows")
+        return out
+
     def niv(self, up: bool = False) -> np.ndarray:
         out = np.empty((self.n, self.k), np.int32)
         _lib.check(_lib.lib().px_poset_niv(self.handle, int(up), out.ctypes.data), "px_poset_niv")

@@ -794,3 +794,21 @@ def test_refine_report_residual_matches_host(px, B):
     want = float((np.abs(r).max(axis=0) / np.abs(g).astype(np.float64).max(axis=0)).max())
     assert want > 0 and abs(rep["residual"] - want) <= 1e-4 * want, (rep, want)
     assert not rep["nonfinite"] and rep["iterations"] == 0
+
+
+@pytest.mark.parametrize("case", ["example", "chain", "antichain", "grid"])
+def test_forced_sparse_niv_small_posets_exact(px, case):
+    """Sparse rows on degenerate shapes (one chain, no relations, the worked example, a grid):
+    int64 zeta, Möbius and both adjoints bit-exact against the closure."""
+    p, planted = {"example": (W.worked_example(), True), "chain": (W.chain_only(300, seed=1), True),
+                  "antichain": (W.antichain(77), False), "grid": (W.grid_poset(40, 9), True)}[case]
+    R = O.reachability(p.n, p.indptr, p.indices)
+    S = build(px, p, planted=planted, flags=px.PX_BUILD_SPARSE_NIV)
+    assert S.info_dict()["niv_sparse"] == 1
+    for B in (1, 64):
+        f = W.functions(p.n, B, "int", seed=7 + B, lo=-(2**40), hi=2**40)
+        ft = T(f)
+        assert np.array_equal(H(px.zeta(S, ft)), O.zeta(R, f))
+        assert np.array_equal(H(px.zeta_adjoint(S, ft)), O.zeta_adjoint(R, f))
+        assert np.array_equal(H(px.mobius(S, ft)), O.mobius_by_substitution(R, f))
+        assert np.array_equal(H(px.mobius_adjoint(S, ft)), O.mobius_adjoint_by_substitution(R, f))

@@ -51,6 +51,10 @@ def _host(px, p, **kw):
 def _check_against_closure(px, P, p, R):
     co, cp = P.chains()
     k = P.k
+    # chain-major numbering: chains in order, bottom first
+    rows = P.rows()
+    off = np.concatenate([[0], np.cumsum(np.bincount(co, minlength=k))])
+    assert np.array_equal(rows, off[co] + cp) and np.array_equal(np.sort(rows), np.arange(p.n))
     # chains are totally ordered, positions 0..len-1
     for c in range(k):
         nodes = np.nonzero(co == c)[0]
