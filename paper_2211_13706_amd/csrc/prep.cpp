@@ -2,9 +2,15 @@
 #include "prep.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <climits>
+#include <condition_variable>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <mutex>
+#include <thread>
 
 #include "posetx.h"
 
@@ -13,6 +19,90 @@ namespace {
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// A fixed team of threads (the caller's included) that runs fn(thread, lo, hi)
+// over chunks of [0, count) per call of run(); workers persist across calls.
+class Workers {
+ public:
+  explicit Workers(int nt) : nt_(std::max(1, nt)) {
+    for (int t = 1; t < nt_; ++t) th_.emplace_back([this, t] { loop(t); });
+  }
+  ~Workers() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+      ++gen_;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+  int size() const { return nt_; }
+  using Fn = std::function<void(int, int64_t, int64_t)>;
+  void run(int64_t count, int64_t chunk, const Fn& fn) {
+    if (nt_ == 1 || count <= chunk) {
+      if (count > 0) fn(0, 0, count);
+      return;
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      fn_ = &fn;
+      count_ = count;
+      chunk_ = chunk;
+      next_.store(0);
+      busy_ = nt_ - 1;
+      ++gen_;
+    }
+    cv_.notify_all();
+    work(0);
+    std::unique_lock<std::mutex> lk(mu_);
+    done_.wait(lk, [this] { return busy_ == 0; });
+    fn_ = nullptr;
+  }
+
+ private:
+  void work(int t) {
+    for (;;) {
+      const int64_t lo = next_.fetch_add(chunk_);
+      if (lo >= count_) return;
+      (*fn_)(t, lo, std::min(lo + chunk_, count_));
+    }
+  }
+  void loop(int t) {
+    uint64_t seen = 0;
+    for (;;) {
+      std::unique_lock<std::mutex> lk(mu_);
+      cv_.wait(lk, [&] { return gen_ != seen; });
+      seen = gen_;
+      if (stop_) return;
+      lk.unlock();
+      work(t);
+      lk.lock();
+      if (--busy_ == 0) done_.notify_one();
+    }
+  }
+  int nt_;
+  std::vector<std::thread> th_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+  int busy_ = 0;
+  const Fn* fn_ = nullptr;
+  int64_t count_ = 0, chunk_ = 1;
+  std::atomic<int64_t> next_{0};
+};
+
+// Threads for the host recursion over sparse rows: up to 16, one for small
+// posets; POSETX_PREP_THREADS overrides (1..64).
+int prep_threads(int64_t n) {
+  if (const char* v = std::getenv("POSETX_PREP_THREADS")) {
+    const int t = std::atoi(v);
+    if (t >= 1) return std::min(t, 64);
+  }
+  if (n < (1 << 15)) return 1;
+  const unsigned hc = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(16u, hc ? hc : 1u));
 }
 
 // Parent lists (reversed CSR) of the child lists.
@@ -258,34 +348,75 @@ int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const i
     for (size_t i = 0; i < P.niv.size(); ++i) P.nnz_niv += P.niv[i] >= 0;
     for (size_t i = 0; i < P.niv_up.size(); ++i) P.nnz_niv_up += P.niv_up[i] >= 0;
   } else if (!P.sparse) {
+    // Rows of one height (the longest path down to a leaf; up to a root for
+    // the dual map) depend only on lower ones, so a team of threads takes the
+    // rows of a height together; the maps do not depend on the thread count.
     P.niv_rounds = 0;
-    P.niv.assign((size_t)n * k, -1);
-    for (int64_t h = 0; h < n; ++h) {
-      int32_t x = order[h];
-      int32_t r = P.row_of_node[x];
-      int32_t* R = &P.niv[(size_t)r * k];
-      for (int64_t e = indptr[x]; e < indptr[x + 1]; ++e) {
-        const int32_t* Rz = &P.niv[(size_t)P.row_of_node[indices[e]] * k];
-        for (int64_t j = 0; j < k; ++j) R[j] = std::max(R[j], Rz[j]);
+    Workers team(prep_threads(n));
+    auto heights = [&](bool up, std::vector<int64_t>& hptr, std::vector<int32_t>& hnodes) {
+      std::vector<int32_t> height(n, 0);
+      if (!up) {
+        height = mir;
+      } else {
+        for (int64_t h = n; h-- > 0;) {
+          const int32_t x = order[h];
+          for (int64_t e = indptr[x]; e < indptr[x + 1]; ++e)
+            height[indices[e]] = std::max(height[indices[e]], height[x] + 1);
+        }
       }
-      int32_t c = P.chain_of[x];
-      int32_t expect = P.chain_pos[x] > 0 ? r - 1 : -1;
-      if (R[c] != expect) return chain_error(x);
-      R[c] = r;
+      int32_t H = 0;
+      for (int64_t x = 0; x < n; ++x) H = std::max(H, height[x] + 1);
+      hptr.assign(H + 1, 0);
+      for (int64_t x = 0; x < n; ++x) hptr[height[x] + 1]++;
+      for (int32_t h = 0; h < H; ++h) hptr[h + 1] += hptr[h];
+      hnodes.resize(n);
+      std::vector<int64_t> fill(hptr.begin(), hptr.end() - 1);
+      for (int64_t x = 0; x < n; ++x) hnodes[fill[height[x]]++] = (int32_t)x;
+    };
+    std::vector<int64_t> hptr;
+    std::vector<int32_t> hnodes;
+    P.niv.assign((size_t)n * k, -1);
+    heights(false, hptr, hnodes);
+    std::atomic<int64_t> bad{INT64_MAX};  // smallest node whose chain check fails
+    for (size_t h = 0; h + 1 < hptr.size(); ++h) {
+      team.run(hptr[h + 1] - hptr[h], 64, [&](int, int64_t lo, int64_t hi) {
+        for (int64_t i = hptr[h] + lo; i < hptr[h] + hi; ++i) {
+          const int32_t x = hnodes[i];
+          const int32_t r = P.row_of_node[x];
+          int32_t* R = &P.niv[(size_t)r * k];
+          for (int64_t e = indptr[x]; e < indptr[x + 1]; ++e) {
+            const int32_t* Rz = &P.niv[(size_t)P.row_of_node[indices[e]] * k];
+            for (int64_t j = 0; j < k; ++j) R[j] = std::max(R[j], Rz[j]);
+          }
+          const int32_t c = P.chain_of[x];
+          if (R[c] != (P.chain_pos[x] > 0 ? r - 1 : -1)) {
+            int64_t cur = bad.load();
+            while (x < cur && !bad.compare_exchange_weak(cur, x)) {
+            }
+          }
+          R[c] = r;
+        }
+      });
+      if (bad.load() != INT64_MAX) return chain_error(bad.load());
     }
     for (size_t i = 0; i < P.niv.size(); ++i) P.nnz_niv += P.niv[i] >= 0;
     if (want_up) {
       // Dual order: the lowest element of chain j above x is a row-wise min over parents.
       P.niv_up.assign((size_t)n * k, INT32_MAX);
-      for (int64_t h = n; h-- > 0;) {
-        int32_t x = order[h];
-        int32_t r = P.row_of_node[x];
-        int32_t* R = &P.niv_up[(size_t)r * k];
-        for (int64_t e = rptr[x]; e < rptr[x + 1]; ++e) {
-          const int32_t* Rp = &P.niv_up[(size_t)P.row_of_node[ridx[e]] * k];
-          for (int64_t j = 0; j < k; ++j) R[j] = std::min(R[j], Rp[j]);
-        }
-        R[P.chain_of[x]] = r;
+      heights(true, hptr, hnodes);
+      for (size_t h = 0; h + 1 < hptr.size(); ++h) {
+        team.run(hptr[h + 1] - hptr[h], 64, [&](int, int64_t lo, int64_t hi) {
+          for (int64_t i = hptr[h] + lo; i < hptr[h] + hi; ++i) {
+            const int32_t x = hnodes[i];
+            const int32_t r = P.row_of_node[x];
+            int32_t* R = &P.niv_up[(size_t)r * k];
+            for (int64_t e = rptr[x]; e < rptr[x + 1]; ++e) {
+              const int32_t* Rp = &P.niv_up[(size_t)P.row_of_node[ridx[e]] * k];
+              for (int64_t j = 0; j < k; ++j) R[j] = std::min(R[j], Rp[j]);
+            }
+            R[P.chain_of[x]] = r;
+          }
+        });
       }
       for (size_t i = 0; i < P.niv_up.size(); ++i) {
         if (P.niv_up[i] == INT32_MAX) P.niv_up[i] = -1;
@@ -296,42 +427,101 @@ int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const i
     // The same recursion on rows that list only their finite entries (nnz(N)
     // instead of n * k storage): a row is the per-chain max (min for the dual
     // map) over its children's (parents') rows, merged through a k-wide
-    // scratch row, plus its own entry.  Rows are built in topological order
-    // into a pool and then laid out by row.
-    std::vector<int32_t> acc(k, -1), touched;
-    touched.reserve(k);
+    // scratch row, plus its own entry.  Rows depend only on rows of lower
+    // height (the longest path down to a leaf, or up to a root for the dual
+    // map), so the rows of one height are merged by a team of threads into
+    // per-thread buffers and then appended to a pool; at the end the rows are
+    // laid out by row.  The maps do not depend on the number of threads.
+    Workers team(prep_threads(n));
+    const int nt = team.size();
+    struct Local {
+      std::vector<int32_t> acc, touched, buf;
+      std::vector<int64_t> rec;  // (row, offset in buf, length) triples
+    };
+    std::vector<Local> loc(nt);
+    for (Local& L : loc) L.acc.assign(k, -1);
     auto build = [&](bool up) -> int {
+      // heights and the nodes of each height, ascending node id
+      std::vector<int32_t> height(n, 0);
+      if (!up) {
+        height = mir;
+      } else {
+        for (int64_t h = n; h-- > 0;) {
+          const int32_t x = order[h];
+          for (int64_t e = indptr[x]; e < indptr[x + 1]; ++e)
+            height[indices[e]] = std::max(height[indices[e]], height[x] + 1);
+        }
+      }
+      int32_t H = 0;
+      for (int64_t x = 0; x < n; ++x) H = std::max(H, height[x] + 1);
+      std::vector<int64_t> hptr(H + 1, 0);
+      for (int64_t x = 0; x < n; ++x) hptr[height[x] + 1]++;
+      for (int32_t h = 0; h < H; ++h) hptr[h + 1] += hptr[h];
+      std::vector<int32_t> hnodes(n);
+      {
+        std::vector<int64_t> fill(hptr.begin(), hptr.end() - 1);
+        for (int64_t x = 0; x < n; ++x) hnodes[fill[height[x]]++] = (int32_t)x;
+      }
       std::vector<int64_t> st(n), ln(n);
       std::vector<int32_t> pool;
       pool.reserve((size_t)n * 4);
-      for (int64_t h = 0; h < n; ++h) {
-        const int32_t x = order[up ? n - 1 - h : h];
-        const int32_t r = P.row_of_node[x];
-        touched.clear();
-        const int64_t e0 = up ? rptr[x] : indptr[x], e1 = up ? rptr[x + 1] : indptr[x + 1];
-        for (int64_t e = e0; e < e1; ++e) {
-          const int32_t rz = P.row_of_node[up ? ridx[e] : indices[e]];
-          for (int64_t i = st[rz], ie = st[rz] + ln[rz]; i < ie; ++i) {
-            const int32_t v = pool[i];
-            int32_t& a = acc[P.chain_of_row[v]];
-            if (a < 0) {
-              touched.push_back(P.chain_of_row[v]);
-              a = v;
-            } else {
-              a = up ? std::min(a, v) : std::max(a, v);
+      std::atomic<int64_t> bad{INT64_MAX};  // smallest node whose chain check fails
+      std::atomic<bool> oom{false};
+      const Workers::Fn merge = [&](int t, int64_t lo, int64_t hi) {
+        Local& L = loc[t];
+        try {
+          for (int64_t i = lo; i < hi; ++i) {
+            const int32_t x = hnodes[i];
+            const int32_t r = P.row_of_node[x];
+            L.touched.clear();
+            const int64_t e0 = up ? rptr[x] : indptr[x], e1 = up ? rptr[x + 1] : indptr[x + 1];
+            for (int64_t e = e0; e < e1; ++e) {
+              const int32_t rz = P.row_of_node[up ? ridx[e] : indices[e]];
+              for (int64_t j = st[rz], je = st[rz] + ln[rz]; j < je; ++j) {
+                const int32_t v = pool[j];
+                int32_t& a = L.acc[P.chain_of_row[v]];
+                if (a < 0) {
+                  L.touched.push_back(P.chain_of_row[v]);
+                  a = v;
+                } else {
+                  a = up ? std::min(a, v) : std::max(a, v);
+                }
+              }
+            }
+            const int32_t c = P.chain_of[x];
+            if (!up && L.acc[c] != (P.chain_pos[x] > 0 ? r - 1 : -1)) {
+              int64_t cur = bad.load();
+              while (x < cur && !bad.compare_exchange_weak(cur, x)) {
+              }
+            }
+            if (L.acc[c] < 0) L.touched.push_back(c);
+            L.acc[c] = r;
+            std::sort(L.touched.begin(), L.touched.end());
+            L.rec.push_back(r);
+            L.rec.push_back((int64_t)L.buf.size());
+            L.rec.push_back((int64_t)L.touched.size());
+            for (int32_t j : L.touched) {
+              L.buf.push_back(L.acc[j]);
+              L.acc[j] = -1;
             }
           }
+        } catch (const std::bad_alloc&) {
+          oom = true;
         }
-        const int32_t c = P.chain_of[x];
-        if (!up && acc[c] != (P.chain_pos[x] > 0 ? r - 1 : -1)) return chain_error(x);
-        if (acc[c] < 0) touched.push_back(c);
-        acc[c] = r;
-        std::sort(touched.begin(), touched.end());
-        st[r] = (int64_t)pool.size();
-        ln[r] = (int64_t)touched.size();
-        for (int32_t j : touched) {
-          pool.push_back(acc[j]);
-          acc[j] = -1;
+      };
+      for (int32_t h = 0; h < H; ++h) {
+        team.run(hptr[h + 1] - hptr[h], 64, [&](int t, int64_t lo, int64_t hi) { merge(t, hptr[h] + lo, hptr[h] + hi); });
+        if (oom) throw std::bad_alloc();
+        if (bad.load() != INT64_MAX) return chain_error(bad.load());
+        for (Local& L : loc) {  // append this height's rows to the pool
+          const int64_t base = (int64_t)pool.size();
+          pool.insert(pool.end(), L.buf.begin(), L.buf.end());
+          for (size_t q = 0; q < L.rec.size(); q += 3) {
+            st[L.rec[q]] = base + L.rec[q + 1];
+            ln[L.rec[q]] = L.rec[q + 2];
+          }
+          L.buf.clear();
+          L.rec.clear();
         }
       }
       std::vector<int64_t>& ptr = P.nivp[up ? 1 : 0];

@@ -221,3 +221,19 @@ def test_config1_preprocessing_scale(px):
         pos = np.where(niv[nodes] >= 0, cp[np.maximum(niv[nodes], 0)], -1)
         assert (np.diff(pos, axis=0) >= 0).all()
     assert info["udep_levels"] < info["mirsky_levels"]
+
+
+def test_threaded_recursion_matches_serial(px, monkeypatch):
+    """The host recursion merges the rows of one height on several threads; the maps and
+    level schedules do not depend on the thread count (sparse rows of a wide ER DAG, and
+    dense rows with the chain check)."""
+    for p, planted in ((W.er_dag(1 << 15, 4, seed=9), False), (W.chain_poset(1 << 15, 16, 3, seed=9), True)):
+        got = []
+        for t in ("1", "6"):
+            monkeypatch.setenv("POSETX_PREP_THREADS", t)
+            P = _host(px, p, planted=planted)
+            got.append((P.niv_csr(), P.niv_csr(True), P.levels(), P.levels(True)))
+        (a, b) = got
+        for x, y in zip(a[:2], b[:2]):
+            assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
+        assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
