@@ -1147,6 +1147,7 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
     if (e == hipSuccess) {
       int64_t off[8];
       std::vector<int32_t> tt = tile_tables(P.chain_off, off, p->dp.max_chain_tiles);
+      p->dp.max_chain = (int32_t)P.max_chain;
       for (int i = 0; i < 7; ++i)
         if (off[i + 1] - off[i] != p->ntiles[i]) e = hipErrorInvalidValue;
       if (e == hipSuccess) e = upload(&p->d_tiles, tt.data(), tt.size(), b);
@@ -1475,6 +1476,8 @@ px_status px_batch_build(int count, px_poset* const* posets, px_batch** out) {
   if (e == hipSuccess) {
     int64_t off[8];
     std::vector<int32_t> tt = tile_tables(chain_off, off, b->dp.max_chain_tiles);
+    for (size_t c = 0; c + 1 < chain_off.size(); ++c)
+      b->dp.max_chain = std::max(b->dp.max_chain, chain_off[c + 1] - chain_off[c]);
     for (int i = 0; i < 7; ++i)
       if (off[i + 1] - off[i] != b->ntiles[i]) e = hipErrorInvalidValue;
     if (e == hipSuccess) e = upload(&b->d_tiles, tt.data(), tt.size(), bytes);

@@ -80,6 +80,7 @@ struct DevPoset {
   // (nullable), and the most tiles any chain has
   const int2* tiles[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int32_t max_chain_tiles[7] = {0, 0, 0, 0, 0, 0, 0};
+  int32_t max_chain = 0;                // rows of the longest chain
   // tables of the walking gather, [0] for niv (zeta), [1] for the up-niv map
   WalkTables walk[2];
   // level solves, [0] down / [1] up: the niv rows (k entries each) and node ids

@@ -1642,6 +1642,45 @@ inline dim3 grid2(int64_t rows, int cw, int64_t B) {
   return dim3((unsigned)((rows + RG - 1) / RG), (unsigned)((B + cw - 1) / cw));
 }
 
+// Short chains (every chain within one scan tile and at most kShortChain
+// rows): one thread per (chain, column) scans its chain's rows in order, 16
+// loads in flight, instead of a 64-row tile per chain of which wide sparse
+// posets (chains of ~5 rows) fill a twelfth.  Row n of P is set to zero here.
+constexpr int kShortChain = 256;
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(WG) void k_scan_chains(DevPoset d, int dir, int cw, const Tin* __restrict__ x,
+                                                    int64_t ldx, int64_t B, Tout* __restrict__ P) {
+  using Tr = ScanTraits<Tin, Tout>;
+  using St = typename Tr::St;
+  const int RG = WG / cw;
+  const int64_t c = (int64_t)blockIdx.x * RG + threadIdx.x / cw;
+  const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
+  if (col >= B) return;
+  if (c == 0) P[(int64_t)d.n * B + col] = Tout(0);
+  if (c >= d.nchains) return;
+  const int64_t r0 = d.chain_off[c], r1 = d.chain_off[c + 1], len = r1 - r0;
+  St st;
+  st.zero();
+  for (int64_t i0 = 0; i0 < len; i0 += 16) {
+    int32_t nodes[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int64_t i = min(i0 + u, len - 1);
+      nodes[u] = d.node_of_row[dir > 0 ? r0 + i : r1 - 1 - i];
+    }
+    Tin raw[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) raw[u] = x[(int64_t)nodes[u] * ldx + col];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      if (i0 + u >= len) break;
+      st.add(Tr::in(raw[u]));
+      const int64_t r = dir > 0 ? r0 + i0 + u : r1 - 1 - i0 - u;
+      P[r * B + col] = Tr::out(st.value());
+    }
+  }
+}
+
 template <typename Tin, typename Tout>
 hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int64_t ldx, void* P, int64_t B,
                       void* aux, int64_t ntiles, hipStream_t s) {
@@ -1654,6 +1693,11 @@ hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int6
   const bool one_tile = d.max_chain_tiles[segi] == 1;
   if (one_tile && phase < 2) return hipSuccess;
   St* C = one_tile ? nullptr : A + ntiles * B;
+  if (one_tile && d.max_chain <= kShortChain) {
+    const dim3 gc((unsigned)((d.nchains + WG / cw - 1) / (WG / cw)), (unsigned)((B + cw - 1) / cw));
+    hipLaunchKernelGGL((k_scan_chains<Tin, Tout>), gc, dim3(WG), 0, s, d, dir, cw, (const Tin*)x, ldx, B, (Tout*)P);
+    return hipGetLastError();
+  }
   dim3 g((unsigned)ntiles, (unsigned)((B + cw - 1) / cw));
   if (phase == 0) {
     const int nt = reduce_tiles(cw == 64 ? 64 : 0);
