@@ -93,14 +93,16 @@ class Workers {
   std::atomic<int64_t> next_{0};
 };
 
-// Threads for the host recursion over sparse rows: up to 16, one for small
-// posets; POSETX_PREP_THREADS overrides (1..64).
-int prep_threads(int64_t n) {
+// Threads for the host recursion by heights: up to 16; one for small posets
+// and for posets whose heights hold fewer than 256 rows on average (the rows
+// of a narrow height run on the calling thread anyway).  POSETX_PREP_THREADS
+// overrides (1..64).
+int prep_threads(int64_t n, int64_t heights) {
   if (const char* v = std::getenv("POSETX_PREP_THREADS")) {
     const int t = std::atoi(v);
     if (t >= 1) return std::min(t, 64);
   }
-  if (n < (1 << 15)) return 1;
+  if (n < (1 << 15) || n < 256 * heights) return 1;
   const unsigned hc = std::thread::hardware_concurrency();
   return (int)std::max(1u, std::min(16u, hc ? hc : 1u));
 }
@@ -352,7 +354,7 @@ int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const i
     // the dual map) depend only on lower ones, so a team of threads takes the
     // rows of a height together; the maps do not depend on the thread count.
     P.niv_rounds = 0;
-    Workers team(prep_threads(n));
+    Workers team(prep_threads(n, P.mirsky));
     auto heights = [&](bool up, std::vector<int64_t>& hptr, std::vector<int32_t>& hnodes) {
       std::vector<int32_t> height(n, 0);
       if (!up) {
@@ -432,7 +434,7 @@ int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const i
     // map), so the rows of one height are merged by a team of threads into
     // per-thread buffers and then appended to a pool; at the end the rows are
     // laid out by row.  The maps do not depend on the number of threads.
-    Workers team(prep_threads(n));
+    Workers team(prep_threads(n, P.mirsky));
     const int nt = team.size();
     struct Local {
       std::vector<int32_t> acc, touched, buf;
