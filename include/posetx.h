@@ -148,7 +148,9 @@ px_status px_poset_info(const px_poset* p, px_info* out);
 /* Host copies of the preprocessing products, in NODE order (for inspection and tests).
  *   chains: chain_of[n], chain_pos[n]
  *   niv:    out[n * k]; out[x*k + j] = node id of niv_j(x), or -1 (the paper's ∞);
- *           up != 0 gives the dual map: the lowest element of chain j above x.
+ *           up != 0 gives the dual map: the lowest element of chain j above x.  For a
+ *           handle with sparse rows this expands them to n * k entries (see
+ *           px_poset_niv_csr for the compact form).
  *   levels: level[n] of every node in the Möbius schedule (up != 0: adjoint schedule). */
 px_status px_poset_chains(const px_poset* p, int32_t* chain_of, int32_t* chain_pos);
 /* The chain-major numbering the kernels work in: row_of_node[x] = first row of
