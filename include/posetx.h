@@ -143,6 +143,16 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
                          const int32_t* chain_of, const int32_t* chain_pos, uint32_t flags,
                          int device, px_poset** out);
 px_status px_poset_free(px_poset* p);
+
+/* Save the preprocessing of a handle (chains, niv maps, level schedules) to a
+ * file, and build a handle from such a file without preprocessing again (the
+ * preprocessing is the one-time cost that the transforms amortise, §5).  The
+ * file is raw arrays in this machine's byte order.  px_poset_load checks every
+ * array against n and k (PX_EINVAL for a file that is not a saved poset or is
+ * inconsistent); flags: PX_BUILD_HOST_ONLY or 0 (the other build choices come
+ * from the file); device as for px_poset_build.  Synchronous. */
+px_status px_poset_save(const px_poset* p, const char* path);
+px_status px_poset_load(const char* path, uint32_t flags, int device, px_poset** out);
 px_status px_poset_info(const px_poset* p, px_info* out);
 
 /* Host copies of the preprocessing products, in NODE order (for inspection and tests).

@@ -27,6 +27,7 @@ EXPORTS = [
     "px_batch_build", "px_batch_free", "px_batch_reserve", "px_batch_rows", "px_zeta_batched",
     "px_zeta_adjoint_batched", "px_last_error", "px_version", "px_profile", "px_profile_read",
     "px_profile_phase_name", "px_autotune", "px_batch_autotune", "px_poset_niv_csr", "px_poset_rows",
+    "px_poset_save", "px_poset_load",
 ]
 
 
@@ -78,6 +79,8 @@ def _declare(lib):
         "px_poset_niv": [P, i32, P],
         "px_poset_niv_csr": [P, i32, P, P],
         "px_poset_rows": [P, P],
+        "px_poset_save": [P, ctypes.c_char_p],
+        "px_poset_load": [ctypes.c_char_p, u32, i32, ctypes.POINTER(P)],
         "px_poset_levels": [P, i32, P],
         "px_reserve": [P, i32, i64],
         "px_zeta": [P, i32, P, i64, P, i64, i64, P],

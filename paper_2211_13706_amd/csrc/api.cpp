@@ -1058,53 +1058,17 @@ px_status px_profile_read(double* ms, int64_t* count, int nphases) {
 const char* px_profile_phase_name(int i) { return (i >= 0 && i < prof::NPH) ? prof::kNames[i] : ""; }
 const char* px_version(void) { return "posetx 0.1 (gfx950)"; }
 
-px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indices, const int32_t* chain_of,
-                         const int32_t* chain_pos, uint32_t flags, int device, px_poset** out) {
-  if (!out) return fail(PX_EINVAL, "null output handle");
-  *out = nullptr;
-  px_poset* p = new (std::nothrow) px_poset();
-  if (!p) return fail(PX_ENOMEM, "host allocation failed");
-  p->host_only = flags & PX_BUILD_HOST_ONLY;
-  p->has_up = !(flags & PX_BUILD_NO_ADJOINT);
-  p->mirsky = flags & PX_BUILD_LEVELS_MIRSKY;
-  p->device = device;
-  std::string msg;
-  int rc;
-  // dense niv maps of at least 2^24 entries are computed on the device (smaller
-  // ones are quicker on the host); POSETX_PREP=host / device forces either side
-  const char* prep_env = std::getenv("POSETX_PREP");
-  const bool force_host = prep_env && std::strcmp(prep_env, "host") == 0;
-  const bool force_dev = prep_env && std::strcmp(prep_env, "device") == 0;
-  const bool dev_niv = !p->host_only && n > 0 && !force_host;
-  const int64_t min_dev_entries = force_dev ? 0 : (int64_t)1 << 24;
-  px::NivHook hook = [&](px::Prep& P, const std::vector<int64_t>& rptr, const std::vector<int32_t>& ridx,
-                         std::string& m) -> int {
-    if (P.n * P.k < min_dev_entries) return -1;
-    DeviceGuard dg(device);
-    if (!dg.ok) return -1;
-    int rounds = 0;
-    const int r = px::device_niv(P, indptr, indices, rptr, ridx, p->has_up, &p->d_niv, &p->d_niv_up, &rounds, m);
-    if (r == PX_OK) P.niv_rounds = rounds;
-    return r;
-  };
-  try {
-    rc = px::preprocess(n, indptr, indices, chain_of, chain_pos, p->has_up, p->mirsky,
-                        (flags & PX_BUILD_SPARSE_NIV) != 0, p->prep, msg, dev_niv ? &hook : nullptr);
-  } catch (const std::bad_alloc&) {
-    rc = PX_ENOMEM;
-    msg = "host allocation failed during preprocessing";
-  }
-  if (rc != PX_OK) {
-    if (!p->host_only) free_poset_device(p);
-    delete p;
-    return fail((px_status)rc, msg);
-  }
+// Device side of a preprocessed handle (tables, uploads, walks); on failure
+// the handle is freed.
+static px_status finish_poset(px_poset* p, int device, px_poset** out) {
+  const int64_t n = p->prep.n;
   std::vector<int32_t> segoff;
   seg_tables(p->prep.chain_off, segoff, p->ntiles);
   if (!p->host_only && n > 0) {
     double t0 = now_s();
     DeviceGuard dg(device);
     if (!dg.ok) {
+      free_poset_device(p);
       delete p;
       return fail(PX_EHIP, "hipSetDevice(" + std::to_string(device) + ") failed");
     }
@@ -1190,6 +1154,227 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
   d.segoff = p->d_segoff;
   *out = p;
   return PX_OK;
+}
+
+px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indices, const int32_t* chain_of,
+                         const int32_t* chain_pos, uint32_t flags, int device, px_poset** out) {
+  if (!out) return fail(PX_EINVAL, "null output handle");
+  *out = nullptr;
+  px_poset* p = new (std::nothrow) px_poset();
+  if (!p) return fail(PX_ENOMEM, "host allocation failed");
+  p->host_only = flags & PX_BUILD_HOST_ONLY;
+  p->has_up = !(flags & PX_BUILD_NO_ADJOINT);
+  p->mirsky = flags & PX_BUILD_LEVELS_MIRSKY;
+  p->device = device;
+  std::string msg;
+  int rc;
+  // dense niv maps of at least 2^24 entries are computed on the device (smaller
+  // ones are quicker on the host); POSETX_PREP=host / device forces either side
+  const char* prep_env = std::getenv("POSETX_PREP");
+  const bool force_host = prep_env && std::strcmp(prep_env, "host") == 0;
+  const bool force_dev = prep_env && std::strcmp(prep_env, "device") == 0;
+  const bool dev_niv = !p->host_only && n > 0 && !force_host;
+  const int64_t min_dev_entries = force_dev ? 0 : (int64_t)1 << 24;
+  px::NivHook hook = [&](px::Prep& P, const std::vector<int64_t>& rptr, const std::vector<int32_t>& ridx,
+                         std::string& m) -> int {
+    if (P.n * P.k < min_dev_entries) return -1;
+    DeviceGuard dg(device);
+    if (!dg.ok) return -1;
+    int rounds = 0;
+    const int r = px::device_niv(P, indptr, indices, rptr, ridx, p->has_up, &p->d_niv, &p->d_niv_up, &rounds, m);
+    if (r == PX_OK) P.niv_rounds = rounds;
+    return r;
+  };
+  try {
+    rc = px::preprocess(n, indptr, indices, chain_of, chain_pos, p->has_up, p->mirsky,
+                        (flags & PX_BUILD_SPARSE_NIV) != 0, p->prep, msg, dev_niv ? &hook : nullptr);
+  } catch (const std::bad_alloc&) {
+    rc = PX_ENOMEM;
+    msg = "host allocation failed during preprocessing";
+  }
+  if (rc != PX_OK) {
+    if (!p->host_only) free_poset_device(p);
+    delete p;
+    return fail((px_status)rc, msg);
+  }
+  return finish_poset(p, device, out);
+}
+
+// ------------------------------------------------ saved preprocessing
+// File: "PXPOSET1", a byte-order word, flag bits, the scalars, then every
+// array as (count, raw little-endian elements), then "PXEND\0\0\0".  Loading
+// checks every index array against n and k before anything reaches a kernel.
+extern "C++" {
+namespace {
+constexpr char kMagic[8] = {'P', 'X', 'P', 'O', 'S', 'E', 'T', '1'};
+constexpr char kEnd[8] = {'P', 'X', 'E', 'N', 'D', 0, 0, 0};
+
+struct Writer {
+  FILE* f;
+  bool ok = true;
+  void raw(const void* p, size_t n) { ok = ok && (n == 0 || fwrite(p, 1, n, f) == n); }
+  template <typename T> void val(T v) { raw(&v, sizeof(T)); }
+  template <typename T> void vec(const std::vector<T>& v) {
+    val<uint64_t>(v.size());
+    raw(v.data(), v.size() * sizeof(T));
+  }
+};
+struct Reader {
+  FILE* f;
+  bool ok = true;
+  void raw(void* p, size_t n) { ok = ok && (n == 0 || fread(p, 1, n, f) == n); }
+  template <typename T> T val() {
+    T v{};
+    raw(&v, sizeof(T));
+    return v;
+  }
+  template <typename T> void vec(std::vector<T>& v, uint64_t max_count) {
+    const uint64_t c = val<uint64_t>();
+    if (!ok || c > max_count) {
+      ok = false;
+      return;
+    }
+    v.resize(c);
+    raw(v.data(), c * sizeof(T));
+  }
+};
+
+bool in_range(const std::vector<int32_t>& v, int64_t lo, int64_t hi) {
+  for (int32_t x : v)
+    if (x < lo || x >= hi) return false;
+  return true;
+}
+bool offsets_ok(const std::vector<int32_t>& ptr, int64_t total) {
+  if (ptr.empty() || ptr[0] != 0 || ptr.back() != total) return false;
+  for (size_t i = 1; i < ptr.size(); ++i)
+    if (ptr[i] < ptr[i - 1]) return false;
+  return true;
+}
+
+// Every index the kernels derive from the preprocessing stays inside its array.
+bool prep_consistent(const px::Prep& P, bool has_up, std::string& why) {
+  const int64_t n = P.n, k = P.k;
+  auto bad = [&](const char* w) {
+    why = w;
+    return false;
+  };
+  if (n < 0 || n >= INT32_MAX || k < 0 || k > n || (n > 0 && k == 0)) return bad("n or k out of range");
+  if ((int64_t)P.chain_off.size() != k + 1 || !offsets_ok(P.chain_off, n)) return bad("chain offsets");
+  if ((int64_t)P.chain_of.size() != n || (int64_t)P.chain_pos.size() != n || (int64_t)P.row_of_node.size() != n ||
+      (int64_t)P.node_of_row.size() != n || (int64_t)P.chain_of_row.size() != n)
+    return bad("per-node array sizes");
+  for (int64_t x = 0; x < n; ++x) {
+    const int32_t c = P.chain_of[x], r = P.row_of_node[x];
+    if (c < 0 || c >= k || r < 0 || r >= n || P.node_of_row[r] != x || P.chain_of_row[r] != c ||
+        r != P.chain_off[c] + P.chain_pos[x])
+      return bad("chain numbering");
+  }
+  const int nm = has_up ? 2 : 1;
+  if (!P.sparse) {
+    if ((int64_t)P.niv.size() != n * k || (int64_t)P.niv_up.size() != (has_up ? n * k : 0)) return bad("niv sizes");
+    if (!in_range(P.niv, -1, n) || !in_range(P.niv_up, -1, n)) return bad("niv entries");
+  } else {
+    if (!P.niv.empty() || !P.niv_up.empty()) return bad("niv sizes");
+    for (int m = 0; m < nm; ++m) {
+      const std::vector<int64_t>& ep = P.nivp[m];
+      if ((int64_t)ep.size() != n + 1 || ep[0] != 0 || ep[n] != (int64_t)P.nivr[m].size()) return bad("sparse niv offsets");
+      for (int64_t r = 0; r < n; ++r)
+        if (ep[r + 1] < ep[r]) return bad("sparse niv offsets");
+      if (!in_range(P.nivr[m], 0, n)) return bad("sparse niv entries");
+    }
+  }
+  if ((int64_t)P.lev_down.size() != n || (int64_t)P.lev_down_rows.size() != n ||
+      !offsets_ok(P.lev_down_ptr, n) || !in_range(P.lev_down_rows, 0, n))
+    return bad("level schedule");
+  if (has_up && ((int64_t)P.lev_up.size() != n || (int64_t)P.lev_up_rows.size() != n ||
+                 !offsets_ok(P.lev_up_ptr, n) || !in_range(P.lev_up_rows, 0, n)))
+    return bad("adjoint level schedule");
+  return true;
+}
+}  // namespace
+}  // extern "C++"
+
+px_status px_poset_save(const px_poset* p, const char* path) {
+  if (!p || !path) return fail(PX_EINVAL, "null argument");
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(PX_EINVAL, std::string("cannot open ") + path + " for writing");
+  const px::Prep& P = p->prep;
+  Writer w{f};
+  w.raw(kMagic, 8);
+  w.val<uint32_t>(0x01020304u);
+  w.val<uint32_t>((p->has_up ? 1u : 0u) | (p->mirsky ? 2u : 0u) | (P.planted ? 4u : 0u) | (P.sparse ? 8u : 0u));
+  for (int64_t v : {P.n, P.k, P.edges, P.nnz_niv, P.nnz_niv_up, P.max_chain, P.mirsky, P.udep}) w.val<int64_t>(v);
+  w.val<int32_t>(P.niv_rounds);
+  for (double v : {P.t_validate, P.t_chains, P.t_niv, P.t_levels}) w.val<double>(v);
+  for (const std::vector<int32_t>* v : {&P.chain_of, &P.chain_pos, &P.chain_off, &P.row_of_node, &P.node_of_row,
+                                        &P.chain_of_row, &P.niv, &P.niv_up, &P.nivr[0], &P.nivr[1], &P.lev_down,
+                                        &P.lev_up, &P.lev_down_ptr, &P.lev_down_rows, &P.lev_up_ptr, &P.lev_up_rows})
+    w.vec(*v);
+  w.vec(P.nivp[0]);
+  w.vec(P.nivp[1]);
+  w.raw(kEnd, 8);
+  const bool ok = w.ok && std::fclose(f) == 0;
+  if (!ok) return fail(PX_EINVAL, std::string("writing ") + path + " failed");
+  return PX_OK;
+}
+
+px_status px_poset_load(const char* path, uint32_t flags, int device, px_poset** out) {
+  if (!path || !out) return fail(PX_EINVAL, "null argument");
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(PX_EINVAL, std::string("cannot open ") + path);
+  px_poset* p = new (std::nothrow) px_poset();
+  if (!p) {
+    std::fclose(f);
+    return fail(PX_ENOMEM, "host allocation failed");
+  }
+  px::Prep& P = p->prep;
+  Reader rd{f};
+  char magic[8], end[8];
+  std::string why = "truncated or malformed file";
+  try {
+    rd.raw(magic, 8);
+    const uint32_t order = rd.val<uint32_t>();
+    const uint32_t bits = rd.val<uint32_t>();
+    if (!rd.ok || std::memcmp(magic, kMagic, 8) != 0 || order != 0x01020304u) {
+      rd.ok = false;
+      why = "not a saved poset of this library and byte order";
+    }
+    p->has_up = bits & 1u;
+    p->mirsky = bits & 2u;
+    P.planted = bits & 4u;
+    P.sparse = bits & 8u;
+    int64_t* sc[] = {&P.n, &P.k, &P.edges, &P.nnz_niv, &P.nnz_niv_up, &P.max_chain, &P.mirsky, &P.udep};
+    for (int64_t* v : sc) *v = rd.val<int64_t>();
+    P.niv_rounds = rd.val<int32_t>();
+    for (double* v : {&P.t_validate, &P.t_chains, &P.t_niv, &P.t_levels}) *v = rd.val<double>();
+    const bool dims = rd.ok && P.n >= 0 && P.n < INT32_MAX && P.k >= 0 && P.k <= P.n;
+    const uint64_t nk = dims ? (uint64_t)P.n * (uint64_t)P.k : 0, n1 = dims ? (uint64_t)P.n + 1 : 0;
+    const uint64_t big = dims ? std::max<uint64_t>({nk, n1, (uint64_t)std::max<int64_t>(0, P.nnz_niv),
+                                                   (uint64_t)std::max<int64_t>(0, P.nnz_niv_up)}) : 0;
+    if (!dims) rd.ok = false;
+    for (std::vector<int32_t>* v : {&P.chain_of, &P.chain_pos, &P.chain_off, &P.row_of_node, &P.node_of_row,
+                                    &P.chain_of_row, &P.niv, &P.niv_up, &P.nivr[0], &P.nivr[1], &P.lev_down,
+                                    &P.lev_up, &P.lev_down_ptr, &P.lev_down_rows, &P.lev_up_ptr, &P.lev_up_rows})
+      rd.vec(*v, big);
+    rd.vec(P.nivp[0], n1);
+    rd.vec(P.nivp[1], n1);
+    rd.raw(end, 8);
+    if (rd.ok && std::memcmp(end, kEnd, 8) != 0) rd.ok = false;
+  } catch (const std::bad_alloc&) {
+    std::fclose(f);
+    delete p;
+    return fail(PX_ENOMEM, "host allocation failed while loading");
+  }
+  std::fclose(f);
+  if (!rd.ok || !prep_consistent(P, p->has_up, why)) {
+    delete p;
+    return fail(PX_EINVAL, std::string(path) + ": " + why);
+  }
+  if (!p->has_up) P.lev_up_ptr.assign(1, 0);
+  p->host_only = flags & PX_BUILD_HOST_ONLY;
+  p->device = device;
+  return finish_poset(p, device, out);
 }
 
 px_status px_poset_free(px_poset* p) {

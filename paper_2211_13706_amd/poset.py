@@ -9,6 +9,7 @@ stream; all computation runs in libposetx.
 from __future__ import annotations
 
 import ctypes
+import os
 
 import numpy as np
 
@@ -88,6 +89,10 @@ class Poset:
         _lib.check(_lib.lib().px_poset_chains(self.handle, co.ctypes.data, cp.ctypes.data), "px_poset_chains")
         return co, cp
 
+    def save(self, path) -> None:
+        """Write the preprocessing to a file (px_poset_save)."""
+        _lib.check(_lib.lib().px_poset_save(self.handle, os.fsencode(path)), "px_poset_save")
+
     def rows(self) -> np.ndarray:
         """Chain-major row of every node (px_poset_rows)."""
         out = np.empty(self.n, np.int64)
@@ -146,6 +151,16 @@ def poset_build(n, indptr, indices, chain_of=None, chain_pos=None, flags: int = 
         None if co is None else co.ctypes.data, None if cp is None else cp.ctypes.data,
         int(flags), int(device), ctypes.byref(h)), "px_poset_build")
     return Poset(h, n, device)
+
+
+def poset_load(path, flags: int = 0, device: int = 0) -> Poset:
+    """A handle from a file written by Poset.save, without preprocessing again (px_poset_load)."""
+    h = ctypes.c_void_p()
+    _lib.check(_lib.lib().px_poset_load(os.fsencode(path), int(flags), int(device), ctypes.byref(h)),
+               "px_poset_load")
+    info = _lib.Info()
+    _lib.check(_lib.lib().px_poset_info(h, ctypes.byref(info)), "px_poset_info")
+    return Poset(h, info.n, device)
 
 
 def _transform(fn_name, P, x, out):

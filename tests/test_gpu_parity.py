@@ -812,3 +812,18 @@ def test_forced_sparse_niv_small_posets_exact(px, case):
         assert np.array_equal(H(px.zeta_adjoint(S, ft)), O.zeta_adjoint(R, f))
         assert np.array_equal(H(px.mobius(S, ft)), O.mobius_by_substitution(R, f))
         assert np.array_equal(H(px.mobius_adjoint(S, ft)), O.mobius_adjoint_by_substitution(R, f))
+
+
+@pytest.mark.parametrize("case", ["cfg0", "er"])
+def test_saved_poset_loads_on_device(px, case, tmp_path):
+    """A handle loaded from a saved file (no preprocessing) computes what the built one does."""
+    p, planted = {"cfg0": (W.chain_poset(2000, 16, 4, seed=0), True), "er": (W.er_dag(2000, 4, seed=5), False)}[case]
+    A = build(px, p, planted=planted)
+    path = tmp_path / "p.pxposet"
+    A.save(path)
+    L = px.poset_load(path, device=0)
+    assert L.info_dict()["niv_sparse"] == A.info_dict()["niv_sparse"]
+    for B in (1, 64):
+        f = T(W.functions(p.n, B, "int", seed=3 + B, lo=-1000, hi=1000))
+        for fn in (px.zeta, px.zeta_adjoint, px.mobius, px.mobius_adjoint):
+            assert np.array_equal(H(fn(A, f)), H(fn(L, f)))

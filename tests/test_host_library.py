@@ -237,3 +237,54 @@ def test_threaded_recursion_matches_serial(px, monkeypatch):
         for x, y in zip(a[:2], b[:2]):
             assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
         assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+
+
+@pytest.mark.parametrize("case", ["cfg0", "er", "lattice", "antichain"])
+def test_save_load_roundtrip(px, case, tmp_path):
+    """A saved handle loads back with the same chains, maps, schedules and counts."""
+    p, planted = {"cfg0": (W.chain_poset(2000, 16, 4, seed=0), True), "er": (W.er_dag(1500, 4, seed=2), False),
+                  "lattice": (W.boolean_lattice(6), False), "antichain": (W.antichain(9), False)}[case]
+    A = _host(px, p, planted=planted)
+    path = tmp_path / "p.pxposet"
+    A.save(path)
+    Bq = px.poset_load(path, flags=px.PX_BUILD_HOST_ONLY)
+    for a, b in zip(A.chains(), Bq.chains()):
+        assert np.array_equal(a, b)
+    assert np.array_equal(A.rows(), Bq.rows())
+    for up in (False, True):
+        for a, b in zip(A.niv_csr(up), Bq.niv_csr(up)):
+            assert np.array_equal(a, b)
+        assert np.array_equal(A.levels(up), Bq.levels(up))
+    ia, ib = A.info_dict(), Bq.info_dict()
+    for key in ("n", "k", "edges", "nnz_niv", "nnz_niv_up", "max_chain", "levels_down", "levels_up",
+                "mirsky_levels", "udep_levels", "niv_sparse", "chains_planted"):
+        assert ia[key] == ib[key], key
+
+
+def test_load_rejects_bad_files(px, tmp_path):
+    """Truncated, foreign and index-corrupted files are refused with PX_EINVAL."""
+    p = W.chain_poset(300, 8, 3, seed=1)
+    A = _host(px, p)
+    good = tmp_path / "good.pxposet"
+    A.save(good)
+    data = bytearray(good.read_bytes())
+    cases = {"truncated": data[: len(data) // 2], "foreign": b"not a poset file at all" + bytes(64),
+             "empty": b""}
+    # corrupt one node_of_row entry: the arrays follow the header (8 magic + 4 + 4 + 8 * 8 + 4 + 4 * 8);
+    # chain_of, chain_pos, chain_off, row_of_node, then node_of_row
+    hdr = 8 + 4 + 4 + 64 + 4 + 32
+    n, k = p.n, 8
+    off = hdr
+    for cnt in (n, n, k + 1, n):
+        off += 8 + 4 * cnt
+    bad = bytearray(data)
+    bad[off + 8: off + 12] = (10 ** 6).to_bytes(4, "little")
+    cases["index"] = bad
+    for name, blob in cases.items():
+        f = tmp_path / f"{name}.pxposet"
+        f.write_bytes(bytes(blob))
+        with pytest.raises(px.PosetxError) as ei:
+            px.poset_load(f, flags=px.PX_BUILD_HOST_ONLY)
+        assert ei.value.name == "PX_EINVAL", name
+    with pytest.raises(px.PosetxError):
+        px.poset_load(tmp_path / "missing.pxposet", flags=px.PX_BUILD_HOST_ONLY)
