@@ -118,6 +118,23 @@ class Poset:
         _lib.check(_lib.lib().px_poset_levels(self.handle, int(up), out.ctypes.data), "px_poset_levels")
         return out
 
+    # transforms as methods (the module functions with the same names)
+    def zeta(self, f, out=None):
+        """g = Z f."""
+        return zeta(self, f, out)
+
+    def zeta_T(self, w, out=None):
+        """Z^T w."""
+        return zeta_adjoint(self, w, out)
+
+    def mobius(self, g, out=None, max_refine: int = 3, tol: float = 0.0, report: bool = False):
+        """f = M g (float32: float64-residual refinement)."""
+        return mobius(self, g, out, max_refine, tol, report)
+
+    def mobius_T(self, v, out=None, max_refine: int = 3, tol: float = 0.0, report: bool = False):
+        """M^T v."""
+        return mobius_adjoint(self, v, out, max_refine, tol, report)
+
     def reserve(self, dtype, B: int):
         import torch
         code = {torch.int64: 0, torch.float32: 1, torch.float64: 2}[dtype]

@@ -827,3 +827,15 @@ def test_saved_poset_loads_on_device(px, case, tmp_path):
         f = T(W.functions(p.n, B, "int", seed=3 + B, lo=-1000, hi=1000))
         for fn in (px.zeta, px.zeta_adjoint, px.mobius, px.mobius_adjoint):
             assert np.array_equal(H(fn(A, f)), H(fn(L, f)))
+
+
+def test_poset_methods_match_functions(px, cfg0):
+    """Poset.zeta / zeta_T / mobius / mobius_T are the module functions."""
+    p, R = cfg0
+    P = build(px, p)
+    f = W.functions(p.n, 3, "int", seed=200, lo=-100, hi=100)
+    ft = T(f)
+    assert np.array_equal(H(P.zeta(ft)), O.zeta(R, f))
+    assert np.array_equal(H(P.zeta_T(ft)), O.zeta_adjoint(R, f))
+    assert np.array_equal(H(P.mobius(ft)), O.mobius_by_substitution(R, f))
+    assert np.array_equal(H(P.mobius_T(ft)), O.mobius_adjoint_by_substitution(R, f))
