@@ -839,3 +839,21 @@ def test_poset_methods_match_functions(px, cfg0):
     assert np.array_equal(H(P.zeta_T(ft)), O.zeta_adjoint(R, f))
     assert np.array_equal(H(P.mobius(ft)), O.mobius_by_substitution(R, f))
     assert np.array_equal(H(P.mobius_T(ft)), O.mobius_adjoint_by_substitution(R, f))
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("sparse", [False, True])
+def test_random_dags_int64_exact(px, seed, sparse):
+    """Random DAGs of varied size and density (chains from the matching), dense and sparse
+    rows, narrow and wide RHS: every transform bit-exact against the closure."""
+    n, prob = [(60, 0.2), (200, 0.05), (333, 0.02), (128, 0.5), (500, 0.01), (257, 0.08)][seed]
+    p = W.random_small_dag(n, prob, 100 + seed)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = build(px, p, planted=False, flags=px.PX_BUILD_SPARSE_NIV if sparse else 0)
+    for B in (1, 65):
+        f = W.functions(p.n, B, "int", seed=300 + seed, lo=-(2**50), hi=2**50)
+        ft = T(f)
+        assert np.array_equal(H(px.zeta(P, ft)), O.zeta(R, f))
+        assert np.array_equal(H(px.zeta_adjoint(P, ft)), O.zeta_adjoint(R, f))
+        assert np.array_equal(H(px.mobius(P, ft)), O.mobius_by_substitution(R, f))
+        assert np.array_equal(H(px.mobius_adjoint(P, ft)), O.mobius_adjoint_by_substitution(R, f))
