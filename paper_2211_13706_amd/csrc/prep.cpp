@@ -107,6 +107,33 @@ int prep_threads(int64_t n, int64_t heights) {
   return (int)std::max(1u, std::min(16u, hc ? hc : 1u));
 }
 
+// Nodes grouped by height, ascending node id within a height: for the down
+// map the longest path down to a leaf (mir), for the dual map the longest path
+// up to a root.  Rows of one height depend only on rows of lower heights in
+// the recursion of Theorem 5 and in the U-dependency levels.
+void by_height(int64_t n, const int64_t* indptr, const int32_t* indices, const std::vector<int32_t>& order,
+               const std::vector<int32_t>& mir, bool up, std::vector<int64_t>& hptr, std::vector<int32_t>& hnodes) {
+  std::vector<int32_t> height;
+  if (!up) {
+    height = mir;
+  } else {
+    height.assign(n, 0);
+    for (int64_t h = n; h-- > 0;) {
+      const int32_t x = order[h];
+      for (int64_t e = indptr[x]; e < indptr[x + 1]; ++e)
+        height[indices[e]] = std::max(height[indices[e]], height[x] + 1);
+    }
+  }
+  int32_t H = 0;
+  for (int64_t x = 0; x < n; ++x) H = std::max(H, height[x] + 1);
+  hptr.assign(H + 1, 0);
+  for (int64_t x = 0; x < n; ++x) hptr[height[x] + 1]++;
+  for (int32_t h = 0; h < H; ++h) hptr[h + 1] += hptr[h];
+  hnodes.resize(n);
+  std::vector<int64_t> fill(hptr.begin(), hptr.end() - 1);
+  for (int64_t x = 0; x < n; ++x) hnodes[fill[height[x]]++] = (int32_t)x;
+}
+
 // Parent lists (reversed CSR) of the child lists.
 void reverse_csr(int64_t n, const int64_t* indptr, const int32_t* indices, std::vector<int64_t>& rptr,
                  std::vector<int32_t>& ridx) {
@@ -355,25 +382,8 @@ int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const i
     // rows of a height together; the maps do not depend on the thread count.
     P.niv_rounds = 0;
     Workers team(prep_threads(n, P.mirsky));
-    auto heights = [&](bool up, std::vector<int64_t>& hptr, std::vector<int32_t>& hnodes) {
-      std::vector<int32_t> height(n, 0);
-      if (!up) {
-        height = mir;
-      } else {
-        for (int64_t h = n; h-- > 0;) {
-          const int32_t x = order[h];
-          for (int64_t e = indptr[x]; e < indptr[x + 1]; ++e)
-            height[indices[e]] = std::max(height[indices[e]], height[x] + 1);
-        }
-      }
-      int32_t H = 0;
-      for (int64_t x = 0; x < n; ++x) H = std::max(H, height[x] + 1);
-      hptr.assign(H + 1, 0);
-      for (int64_t x = 0; x < n; ++x) hptr[height[x] + 1]++;
-      for (int32_t h = 0; h < H; ++h) hptr[h + 1] += hptr[h];
-      hnodes.resize(n);
-      std::vector<int64_t> fill(hptr.begin(), hptr.end() - 1);
-      for (int64_t x = 0; x < n; ++x) hnodes[fill[height[x]]++] = (int32_t)x;
+    auto heights = [&](bool up, std::vector<int64_t>& hp, std::vector<int32_t>& hn) {
+      by_height(n, indptr, indices, order, mir, up, hp, hn);
     };
     std::vector<int64_t> hptr;
     std::vector<int32_t> hnodes;
@@ -443,27 +453,11 @@ int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const i
     std::vector<Local> loc(nt);
     for (Local& L : loc) L.acc.assign(k, -1);
     auto build = [&](bool up) -> int {
-      // heights and the nodes of each height, ascending node id
-      std::vector<int32_t> height(n, 0);
-      if (!up) {
-        height = mir;
-      } else {
-        for (int64_t h = n; h-- > 0;) {
-          const int32_t x = order[h];
-          for (int64_t e = indptr[x]; e < indptr[x + 1]; ++e)
-            height[indices[e]] = std::max(height[indices[e]], height[x] + 1);
-        }
-      }
-      int32_t H = 0;
-      for (int64_t x = 0; x < n; ++x) H = std::max(H, height[x] + 1);
-      std::vector<int64_t> hptr(H + 1, 0);
-      for (int64_t x = 0; x < n; ++x) hptr[height[x] + 1]++;
-      for (int32_t h = 0; h < H; ++h) hptr[h + 1] += hptr[h];
-      std::vector<int32_t> hnodes(n);
-      {
-        std::vector<int64_t> fill(hptr.begin(), hptr.end() - 1);
-        for (int64_t x = 0; x < n; ++x) hnodes[fill[height[x]]++] = (int32_t)x;
-      }
+      // the nodes of each height, ascending node id
+      std::vector<int64_t> hptr;
+      std::vector<int32_t> hnodes;
+      by_height(n, indptr, indices, order, mir, up, hptr, hnodes);
+      const int32_t H = (int32_t)hptr.size() - 1;
       std::vector<int64_t> st(n), ln(n);
       std::vector<int32_t> pool;
       pool.reserve((size_t)n * 4);
@@ -555,18 +549,27 @@ int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const i
     std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
     for (int64_t r = 0; r < n; ++r) rows[fill[lev[r]]++] = (int32_t)r;
   };
+  // (the entries of a row lie at lower heights, so a height's rows are taken
+  // together by a thread team, as in the recursion)
+  Workers lteam(prep_threads(n, P.mirsky));
   auto udep_levels = [&](bool up, std::vector<int32_t>& lev) {
     lev.assign(n, 0);
     const std::vector<int32_t>& nv = up ? P.niv_up : P.niv;
-    for (int64_t h = 0; h < n; ++h) {
-      int32_t x = order[up ? n - 1 - h : h];
-      int32_t r = P.row_of_node[x];
-      const int32_t* R = P.sparse ? P.nivr[up ? 1 : 0].data() + P.nivp[up ? 1 : 0][r] : &nv[(size_t)r * k];
-      const int64_t len = P.sparse ? P.nivp[up ? 1 : 0][r + 1] - P.nivp[up ? 1 : 0][r] : k;
-      int32_t l = 0;
-      for (int64_t j = 0; j < len; ++j)
-        if (R[j] >= 0 && R[j] != r) l = std::max(l, lev[R[j]] + 1);
-      lev[r] = l;
+    std::vector<int64_t> hptr;
+    std::vector<int32_t> hnodes;
+    by_height(n, indptr, indices, order, mir, up, hptr, hnodes);
+    for (size_t h = 0; h + 1 < hptr.size(); ++h) {
+      lteam.run(hptr[h + 1] - hptr[h], 256, [&](int, int64_t lo, int64_t hi) {
+        for (int64_t i = hptr[h] + lo; i < hptr[h] + hi; ++i) {
+          const int32_t r = P.row_of_node[hnodes[i]];
+          const int32_t* R = P.sparse ? P.nivr[up ? 1 : 0].data() + P.nivp[up ? 1 : 0][r] : &nv[(size_t)r * k];
+          const int64_t len = P.sparse ? P.nivp[up ? 1 : 0][r + 1] - P.nivp[up ? 1 : 0][r] : k;
+          int32_t l = 0;
+          for (int64_t j = 0; j < len; ++j)
+            if (R[j] >= 0 && R[j] != r) l = std::max(l, lev[R[j]] + 1);
+          lev[r] = l;
+        }
+      });
     }
   };
   std::vector<int32_t> ud;
