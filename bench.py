@@ -346,17 +346,18 @@ def leg_large(px, dev, steps):
             "f32_roundtrip_rel_err": err, "f32_refine_report": rep}
 
 
-def leg_er_sparse(px, dev, steps):
-    """The workload class of the paper's experiments (§5): an Erdős–Rényi DAG of average degree 4,
-    n = 2^18, chains from the maximum matching.  Its width (about 53,000) keeps the niv map as rows
-    of its finite entries (about 61M; dense rows would need 55 GB).  float32 zeta and adjoint at
-    B = 64, the int64 Möbius round trip, the refined float32 Möbius, and the rate of the sparse
-    gather: its compulsory bytes (the niv rows, P read once, g) and the P rows it gathers."""
+def leg_er_sparse(px, dev, steps, n_log2=18, deg=4, refine=True):
+    """The workload class of the paper's experiments (§5): an Erdős–Rényi DAG of average degree
+    `deg`, n = 2^n_log2, chains from the maximum matching.  At n = 2^18, degree 4 its width (about
+    53,000) keeps the niv map as rows of its finite entries (about 61M; dense rows would need
+    55 GB).  float32 zeta and adjoint at B = 64, the int64 Möbius round trip, the refined float32
+    Möbius, and the rate of the sparse gather: its compulsory bytes (the niv rows, P read once, g)
+    and the P rows it gathers."""
     import torch
     import workloads as W
     sync = torch.cuda.synchronize
     t0 = time.perf_counter()
-    q = W.er_dag(1 << 18, 4, seed=1)
+    q = W.er_dag(1 << n_log2, deg, seed=1)
     P = px.poset_build(q.n, q.indptr, q.indices, None, None, device=0)
     t_prep = time.perf_counter() - t0
     info = P.info
@@ -382,13 +383,15 @@ def leg_er_sparse(px, dev, steps):
     tm = _time(lambda: px.mobius(P, gi), steps, sync)
     exact = bool(torch.equal(px.mobius(P, gi), fi))
     exact_adj = bool(torch.equal(px.mobius_adjoint(P, px.zeta_adjoint(P, fi)), fi))
-    try:
-        f2, rep = px.mobius(P, g, max_refine=3, report=True)
-        err = ((f2 - f).abs().amax(0) / f.abs().amax(0)).max().item()
-    except px.PosetxError as e:
-        rep, err = {"status": e.name}, None
-    tr = _time(lambda: px.mobius(P, g, max_refine=3), max(2, steps // 4), sync)
-    return {"workload": "Erdős–Rényi DAG, n=262144, average degree 4, matching chains, B=64 float32",
+    rep, err, tr = None, None, float("nan")
+    if refine:
+        try:
+            f2, rep = px.mobius(P, g, max_refine=3, report=True)
+            err = ((f2 - f).abs().amax(0) / f.abs().amax(0)).max().item()
+        except px.PosetxError as e:
+            rep, err = {"status": e.name}, None
+        tr = _time(lambda: px.mobius(P, g, max_refine=3), max(2, steps // 4), sync)
+    return {"workload": f"Erdős–Rényi DAG, n={n}, average degree {deg}, matching chains, B=64 float32",
             "k": info["k"], "nnz_niv": nnz, "niv_sparse": info["niv_sparse"], "levels": info["levels_down"],
             "preprocess_s": round(t_prep, 2),
             "zeta_f32_ms": round(tz * 1e3, 4), "zeta_node_rhs_per_s": n * Bl / tz,
@@ -397,7 +400,8 @@ def leg_er_sparse(px, dev, steps):
             "gathered_row_GBps": round(nnz * Bl * 4 / t_gather / 1e9, 1),
             "mobius_int64_ms": round(tm * 1e3, 4), "int64_roundtrip_exact": exact,
             "int64_adjoint_roundtrip_exact": exact_adj,
-            "mobius_f32_refined_ms": round(tr * 1e3, 4), "f32_roundtrip_rel_err": err, "f32_refine_report": rep,
+            "mobius_f32_refined_ms": round(tr * 1e3, 4) if refine else None, "f32_roundtrip_rel_err": err,
+            "f32_refine_report": rep,
             "mobius_f64_growth": f64_growth(px, P, n, dev)}
 
 
@@ -549,6 +553,9 @@ def main():
             legs["large"] = leg_large(px, dev, max(2, args.steps // 4))
             note("legs: Erdős–Rényi DAG with sparse niv rows")
             legs["er_sparse"] = leg_er_sparse(px, dev, max(2, args.steps // 4))
+            note("legs: Erdős–Rényi DAGs, degree 6 and n = 2^20")
+            legs["er_sparse_deg6"] = leg_er_sparse(px, dev, max(2, args.steps // 4), n_log2=16, deg=6)
+            legs["er_sparse_n1M"] = leg_er_sparse(px, dev, 3, n_log2=20, deg=4, refine=False)
         out["legs"] = legs
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, f_host, args.cpu_budget)
