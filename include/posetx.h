@@ -46,6 +46,11 @@
  *    single-pass chain scan for the paths that form it, with POSETX_LB_SPIN
  *    bounding its waits (polls; 0 makes every wait give up and sum its
  *    predecessors from the input).  POSETX_TUNE_CACHE: see px_autotune.
+ *    Posets with sparse niv rows (PX_BUILD_SPARSE_NIV, or more than 256
+ *    chains) take the chain scan, a gather over their rows and a level solve,
+ *    rows of more than 256 entries summed in fixed chunks.  Preprocessing:
+ *    POSETX_PREP (see px_poset_build) and POSETX_PREP_THREADS (host threads of
+ *    the recursion, default up to 16 for posets with wide levels).
  */
 #ifndef POSETX_H
 #define POSETX_H
