@@ -15,9 +15,12 @@
 // is one gather over the other-chain children and one prefix max along every
 // chain (a three-pass tile scan), until a round changes nothing.  Every X_t
 // lies below the unique fixed point and the rounds increase, so the result is
-// exactly the recursion's.  Random-height posets converge in about ten rounds
-// (a round is needed per chain change along the paths that realise niv);
-// a poset that needs more than kMaxRounds falls back to the host recursion.
+// exactly the recursion's.  A round is needed per chain change along the
+// paths that realise niv, and such a path never needs to come back to a chain
+// (from its first element on a chain it can go down that chain instead), so
+// k + 1 rounds always suffice: ten per map on random-height posets with 64
+// chains, 64 on a 64-column grid.  The cap kMaxRounds (above the 256 chains of
+// dense rows) sends a poset back to the host recursion should it be reached.
 // The dual map is the same with min, parents and suffixes.
 //
 // Planted chains are checked afterwards, as the host recursion checks them:
