@@ -558,6 +558,7 @@ struct px_poset {
     int32_t* d_gshort = nullptr;
     int4* d_glong = nullptr;
     int4* d_gitems = nullptr;
+    int4* d_gitems8 = nullptr;
     int64_t gitems = 0;
   } split[2];
   px::DevPoset dp;
@@ -600,6 +601,7 @@ void free_poset_device(px_poset* p) {
     if (sp.d_gshort) (void)hipFree(sp.d_gshort);
     if (sp.d_glong) (void)hipFree(sp.d_glong);
     if (sp.d_gitems) (void)hipFree(sp.d_gitems);
+    if (sp.d_gitems8) (void)hipFree(sp.d_gitems8);
     sp = px_poset::Split();
   }
   for (auto& dir : p->d_walk)
@@ -637,10 +639,16 @@ int64_t max_parts(const px_poset* p) {
 // long (thousands of entries in a handful of rows).
 constexpr int64_t kSplitChunk = 256;
 
-// Short rows and chunks of the long ones among rows[0 .. cnt) (host side);
-// longs[j].y is relative to the first item added here.
-void split_rows(const std::vector<int64_t>& ep, const int32_t* rows, int64_t cnt, std::vector<int32_t>& shorts,
-                std::vector<int4>& longs, std::vector<int4>& items) {
+// Short rows and chunks of the long ones among rows[0 .. cnt) (host side).
+// A row's chunks take consecutive slots (item.w, relative to the first item
+// added here; longs[j].y is its first slot).  With by_entry the items are
+// then ordered by the row of their first entry, so that chunks gathered
+// together read nearby rows.  On the n = 2^18 ER DAG at B = 64 this made the
+// int64 level solve 12% and the float64 residual gather about 10% faster but
+// the float32 zeta gather 1.5% slower, so the gather keeps both orders and
+// takes the ordered one for 8-byte elements.
+void split_rows(const std::vector<int64_t>& ep, const std::vector<int32_t>& er, const int32_t* rows, int64_t cnt,
+                bool by_entry, std::vector<int32_t>& shorts, std::vector<int4>& longs, std::vector<int4>& items) {
   const size_t c0 = items.size();
   for (int64_t i = 0; i < cnt; ++i) {
     const int32_t r = rows ? rows[i] : (int32_t)i;
@@ -650,10 +658,14 @@ void split_rows(const std::vector<int64_t>& ep, const int32_t* rows, int64_t cnt
       continue;
     }
     const int32_t first = (int32_t)(items.size() - c0);
-    for (int64_t e = e0; e < e1; e += kSplitChunk)
-      items.push_back(make_int4(r, (int32_t)e, (int32_t)std::min(e + kSplitChunk, e1), 0));
+    for (int64_t e = e0; e < e1; e += kSplitChunk) {
+      const int32_t w = (int32_t)(items.size() - c0);
+      items.push_back(make_int4(r, (int32_t)e, (int32_t)std::min(e + kSplitChunk, e1), w));
+    }
     longs.push_back(make_int4(r, first, (int32_t)(items.size() - c0) - first, 0));
   }
+  if (by_entry)
+    std::stable_sort(items.begin() + c0, items.end(), [&](const int4& a, const int4& b) { return er[a.y] < er[b.y]; });
 }
 
 // The split schedules of map m of a sparse poset: per level for the solve,
@@ -670,7 +682,7 @@ void build_split(const px::Prep& P, int m, px_poset::Split& sp, px::GatherSplit&
   sp.max_items = 0;
   for (size_t l = 0; l + 1 < lptr.size(); ++l) {
     const size_t c0 = items.size();
-    split_rows(ep, rows.data() + lptr[l], lptr[l + 1] - lptr[l], shorts, longs, items);
+    split_rows(ep, P.nivr[m], rows.data() + lptr[l], lptr[l + 1] - lptr[l], true, shorts, longs, items);
     sp.sptr.push_back((int32_t)shorts.size());
     sp.lptr.push_back((int32_t)longs.size());
     sp.cptr.push_back((int32_t)items.size());
@@ -688,15 +700,21 @@ void build_split(const px::Prep& P, int m, px_poset::Split& sp, px::GatherSplit&
   shorts.clear();
   longs.clear();
   items.clear();
-  split_rows(ep, nullptr, P.n, shorts, longs, items);
+  split_rows(ep, P.nivr[m], nullptr, P.n, false, shorts, longs, items);
   e = upload(&sp.d_gshort, shorts.data(), shorts.size(), b);
   if (e == hipSuccess) e = upload(&sp.d_glong, longs.data(), longs.size(), b);
   if (e == hipSuccess) e = upload(&sp.d_gitems, items.data(), items.size(), b);
+  if (e == hipSuccess) {
+    std::stable_sort(items.begin(), items.end(),
+                     [&](const int4& a, const int4& c) { return P.nivr[m][a.y] < P.nivr[m][c.y]; });
+    e = upload(&sp.d_gitems8, items.data(), items.size(), b);
+  }
   if (e != hipSuccess) return;
   sp.gitems = (int64_t)items.size();
   gs.shorts = sp.d_gshort;
   gs.nshorts = (int64_t)shorts.size();
   gs.items = sp.d_gitems;
+  gs.items8 = sp.d_gitems8;
   gs.nitems = (int64_t)items.size();
   gs.longs = sp.d_glong;
   gs.nlongs = (int64_t)longs.size();

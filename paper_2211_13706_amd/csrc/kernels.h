@@ -55,7 +55,8 @@ struct WalkTables {
 struct GatherSplit {
   const int32_t* shorts = nullptr;  // nullptr: no split, every row whole
   int64_t nshorts = 0;
-  const int4* items = nullptr;
+  const int4* items = nullptr;    // chunk items in row order (4-byte elements)
+  const int4* items8 = nullptr;   // the same ordered by first entry (8-byte elements)
   int64_t nitems = 0;
   const int4* longs = nullptr;
   int64_t nlongs = 0;
@@ -170,11 +171,11 @@ hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_ro
                                ElemType tin, const void* g, int64_t ldg, ElemType ty, void* Y,
                                int64_t B, hipStream_t s);
 
-// The long rows of a level of a sparse solve, split into chunks: items[i] =
-// {row, first entry, end entry, 0} (nitems), longs[j] = {row, first item,
-// items, 0} (nlongs, the items of a row consecutive and in entry order).
-// Y[row] = g[node(row)] minus the chunk sums in order.  part: nitems * B
-// 8-byte words of scratch.
+// The long rows of a level of a sparse solve, split into chunks: items =
+// {row, first entry, end entry, w} (nitems, in any order; w: the chunk's slot
+// in part), longs[j] = {row, first slot, chunks, 0} (nlongs; a row's chunks
+// take consecutive slots in entry order).  Y[row] = g[node(row)] minus the
+// chunk sums in order.  part: nitems * B 8-byte words of scratch.
 hipError_t launch_usolve_split(const DevPoset& d, bool up, const int4* items, int64_t nitems, const int4* longs,
                                int64_t nlongs, ElemType tin, const void* g, int64_t ldg, ElemType ty, void* Y,
                                int64_t B, void* part, hipStream_t s);

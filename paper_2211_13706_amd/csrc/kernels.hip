@@ -1378,23 +1378,33 @@ __global__ __launch_bounds__(WG) void k_usolve(DevPoset d, const int32_t* __rest
 }
 
 // Long sparse rows of a level are split into chunks of consecutive entries:
-// item i = {row, first entry, end entry, 0} gets part[i] = Σ Y[entry] over
+// item {row, first entry, end entry, w} gets part[w] = Σ Y[entry] over
 // its chunk (own row skipped), one item per row group; then each long row
 // {row, first item, items, 0} takes g minus its chunks' sums in chunk order.
 // A row's result depends only on its chunking, which the host fixes.
 // (SKIP_OWN: the solve, which leaves the row's own entry out; the zeta gather
 // keeps it.)
+//
+// The host may order the items by the row of their first entry, so that
+// chunks taken together gather from the same chains near the same heights;
+// item.w is the chunk's place in its row's run of chunk sums.  Workgroups are
+// dispatched round-robin over the 8 XCDs; a bijection of the block indices
+// gives each XCD a contiguous slice of the ordered items, so that its L2 sees
+// one band of P.
 template <typename TY, bool SKIP_OWN>
 __global__ __launch_bounds__(WG) void k_csr_part(DevPoset d, const int4* __restrict__ items, int64_t cnt, int cw,
                                                  const int32_t* __restrict__ er, const TY* __restrict__ Y, int64_t B,
                                                  typename Wide<TY>::W* __restrict__ part) {
   using W = typename Wide<TY>::W;
   const int RG = WG / cw;
-  const int64_t i = (int64_t)blockIdx.x * RG + threadIdx.x / cw;
+  const int64_t nblk = gridDim.x, q8 = nblk >> 3, r8 = nblk & 7;
+  const int64_t xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int64_t blk = xcd * q8 + min(xcd, r8) + slot;
+  const int64_t i = blk * RG + threadIdx.x / cw;
   const int64_t col = (int64_t)blockIdx.y * cw + threadIdx.x % cw;
   if (i >= cnt || col >= B) return;
   const int4 it = items[i];
-  part[i * B + col] = csr_sum<TY, W>(er, it.y, it.z, SKIP_OWN ? it.x : -1, d.n, Y, B, col);
+  part[(int64_t)it.w * B + col] = csr_sum<TY, W>(er, it.y, it.z, SKIP_OWN ? it.x : -1, d.n, Y, B, col);
 }
 
 // The zeta gather's long rows: out[node(row)] = Σ of the chunk sums in order
@@ -1892,7 +1902,8 @@ hipError_t gather_split_typed(const DevPoset& d, int m, const void* P, int64_t B
   using W = typename Wide<TP>::W;
   const int cw = col_width(B);
   const GatherSplit& gs = d.gsplit[m];
-  hipLaunchKernelGGL((k_csr_part<TP, false>), grid2(gs.nitems, cw, B), dim3(WG), 0, s, d, gs.items, gs.nitems, cw,
+  const int4* items = sizeof(TP) == 8 && gs.items8 ? gs.items8 : gs.items;
+  hipLaunchKernelGGL((k_csr_part<TP, false>), grid2(gs.nitems, cw, B), dim3(WG), 0, s, d, items, gs.nitems, cw,
                      d.nivr[m], (const TP*)P, B, (W*)part);
   hipLaunchKernelGGL((k_gather_csr_fin<TP, Tout, Tres, RESID>), grid2(gs.nlongs, cw, B), dim3(WG), 0, s, d,
                      gs.longs, gs.nlongs, cw, (const W*)part, B, (Tout*)out, ldo, (const Tres*)resid, ldr);
