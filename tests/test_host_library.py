@@ -288,3 +288,23 @@ def test_load_rejects_bad_files(px, tmp_path):
         assert ei.value.name == "PX_EINVAL", name
     with pytest.raises(px.PosetxError):
         px.poset_load(tmp_path / "missing.pxposet", flags=px.PX_BUILD_HOST_ONLY)
+
+
+def test_save_load_keeps_build_choices(px, tmp_path):
+    """No-adjoint and Mirsky-schedule handles keep those choices through a file."""
+    p = W.chain_poset(500, 8, 3, seed=3)
+    for flags in (px.PX_BUILD_NO_ADJOINT, px.PX_BUILD_LEVELS_MIRSKY, px.PX_BUILD_SPARSE_NIV):
+        A = _host(px, p, flags=flags)
+        path = tmp_path / f"p{flags}.pxposet"
+        A.save(path)
+        Bq = px.poset_load(path, flags=px.PX_BUILD_HOST_ONLY)
+        assert np.array_equal(A.levels(), Bq.levels())
+        assert A.info_dict()["levels_down"] == Bq.info_dict()["levels_down"]
+        assert A.info_dict()["niv_sparse"] == Bq.info_dict()["niv_sparse"]
+        if flags == px.PX_BUILD_NO_ADJOINT:
+            with pytest.raises(px.PosetxError) as ei:
+                Bq.niv(up=True)
+            assert ei.value.name == "PX_EUNSUPPORTED"
+        else:
+            for a, b in zip(A.niv_csr(True), Bq.niv_csr(True)):
+                assert np.array_equal(a, b)
