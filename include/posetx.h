@@ -84,8 +84,9 @@ typedef enum {
 #define PX_BUILD_LEVELS_MIRSKY 0x4u  /* schedule Möbius over Mirsky antichains (§4, Alg. 5/6)       */
 #define PX_BUILD_SPARSE_NIV 0x8u     /* keep the niv maps as rows of their finite entries (nnz(N)
                                         storage, §2.4) instead of dense [n, k] rows; automatic for
-                                        more than 256 chains.  Such posets take the one-thread-per-
-                                        row gathers and level solves and cannot join a batch     */
+                                        more than 256 chains.  Such posets take gathers and level
+                                        solves over their rows (long rows in fixed chunks) and
+                                        cannot join a batch                                      */
 
 typedef struct {
   int64_t n;              /* elements                                                   */
