@@ -412,9 +412,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
-    ap.add_argument("--legs", default="default", choices=["none", "default", "all", "sparse"],
+    ap.add_argument("--legs", default="default", choices=["none", "default", "all", "sparse", "batched"],
                     help="extra measurements of the other hot-path rows (all: also the batched, n=2^23 and "
-                         "Erdős–Rényi configs; sparse: the Erdős–Rényi config alone)")
+                         "Erdős–Rényi configs; sparse / batched: that config alone)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for counter scaling)")
     args = ap.parse_args()
@@ -538,6 +538,9 @@ def main():
     }
     if args.legs == "sparse":
         out["legs"] = {"er_sparse": leg_er_sparse(px, dev, max(2, args.steps // 4))}
+    elif args.legs == "batched":
+        del P
+        out["legs"] = {"batched": leg_batched(px, dev, args.steps)}
     elif args.legs != "none":
         def note(msg):
             print(f"[bench] {msg}", file=sys.stderr, flush=True)
