@@ -190,6 +190,14 @@ def legs_config1(px, P, p, dev, steps):
     t = _time(lambda: px.zeta_adjoint(P, ff, out=ga), steps, sync)
     out["zeta_adjoint_f32"] = {"ms": round(t * 1e3, 4), "node_rhs_per_s": p.n * B / t}
     del ff, ga
+    # one GPU's share of an 8-way split of the right-hand sides (the sharding that needs no
+    # exchange): the same poset at B = 8, and its rate against B = 64
+    f8 = torch.from_numpy(W.functions(p.n, 8, "normal", seed=4)).to(dev)
+    g8 = torch.empty_like(f8)
+    P.reserve(torch.float32, 8)
+    t8 = _time(lambda: px.zeta(P, f8, out=g8), steps, sync)
+    out["zeta_f32_B8_share"] = {"ms": round(t8 * 1e3, 4), "node_rhs_per_s": p.n * 8 / t8}
+    del f8, g8
     out["preprocess"] = leg_preprocess(px, P, p)
     return out
 
