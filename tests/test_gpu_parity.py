@@ -857,3 +857,26 @@ def test_random_dags_int64_exact(px, seed, sparse):
         assert np.array_equal(H(px.zeta_adjoint(P, ft)), O.zeta_adjoint(R, f))
         assert np.array_equal(H(px.mobius(P, ft)), O.mobius_by_substitution(R, f))
         assert np.array_equal(H(px.mobius_adjoint(P, ft)), O.mobius_adjoint_by_substitution(R, f))
+
+
+@pytest.mark.parametrize("sparse", [False, True])
+def test_empty_and_single_element_posets(px, sparse):
+    """Degenerate sizes: no elements (every call succeeds and touches nothing), one element
+    (zeta and Möbius are the identity), two comparable elements."""
+    import torch
+    flags = px.PX_BUILD_SPARSE_NIV if sparse else 0
+    E = px.poset_build(0, np.zeros(1, np.int64), np.zeros(0, np.int32), flags=flags, device=0)
+    z = torch.zeros((0, 3), dtype=torch.int64, device=dev())
+    for fn in (px.zeta, px.zeta_adjoint, px.mobius, px.mobius_adjoint):
+        assert fn(E, z).shape == (0, 3)
+    one = W.antichain(1)
+    S = build(px, one, planted=False, flags=flags)
+    f = W.functions(1, 5, "int", seed=1, lo=-9, hi=9)
+    for fn in (px.zeta, px.zeta_adjoint, px.mobius, px.mobius_adjoint):
+        assert np.array_equal(H(fn(S, T(f))), f)
+    two = W.chain_only(2)
+    R = O.reachability(two.n, two.indptr, two.indices)
+    C = build(px, two, flags=flags)
+    f2 = W.functions(2, 70, "int", seed=2, lo=-9, hi=9)
+    assert np.array_equal(H(px.zeta(C, T(f2))), O.zeta(R, f2))
+    assert np.array_equal(H(px.mobius(C, T(f2))), O.mobius_by_substitution(R, f2))
