@@ -1,6 +1,7 @@
 """Benchmark of the fast zeta transform on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--legs]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+                    [--legs none|default|all|sparse|batched]
 
 Workload (the headline configuration): a random-height poset with
 n = 2^20 elements, k = 64 planted chains of 16,384 elements, 3 cross edges
@@ -12,7 +13,10 @@ resident in HBM.  Host preprocessing is timed separately and reported under
 Printed: ONE JSON line with the metric (node·RHS/s), the roofline of the
 dominant kernel (algorithmic bytes per launch / its average HIP-event
 duration on the launch stream), and the CPU oracle timed on a bounded sample
-of the same workload on the host.
+of the same workload on the host.  "legs" adds measurements of the other
+rows: by default the int64 zeta and Möbius, the adjoint, the B = 8 share,
+the preprocessing and the grid Möbius; "all" also the batched posets, the
+n = 2^23 poset and the Erdős–Rényi DAGs with sparse niv rows.
 """
 
 from __future__ import annotations
