@@ -1389,6 +1389,17 @@ px_status px_poset_load(const char* path, uint32_t flags, int device, px_poset**
     delete p;
     return fail(PX_EINVAL, std::string(path) + ": " + why);
   }
+  // the counts that size device work come from the arrays, not from the file's scalars
+  P.max_chain = 0;
+  for (int64_t c = 0; c < P.k; ++c) P.max_chain = std::max<int64_t>(P.max_chain, P.chain_off[c + 1] - P.chain_off[c]);
+  if (P.sparse) {
+    P.nnz_niv = (int64_t)P.nivr[0].size();
+    P.nnz_niv_up = p->has_up ? (int64_t)P.nivr[1].size() : 0;
+  } else {
+    P.nnz_niv = P.nnz_niv_up = 0;
+    for (int32_t v : P.niv) P.nnz_niv += v >= 0;
+    for (int32_t v : P.niv_up) P.nnz_niv_up += v >= 0;
+  }
   if (!p->has_up) P.lev_up_ptr.assign(1, 0);
   p->host_only = flags & PX_BUILD_HOST_ONLY;
   p->device = device;

@@ -308,3 +308,19 @@ def test_save_load_keeps_build_choices(px, tmp_path):
         else:
             for a, b in zip(A.niv_csr(True), Bq.niv_csr(True)):
                 assert np.array_equal(a, b)
+
+
+def test_load_recounts_sizes(px, tmp_path):
+    """The entry counts that size device work are recounted from the arrays on load, not read
+    from the file's header."""
+    p = W.er_dag(600, 4, seed=4)
+    A = _host(px, p, planted=False)
+    path = tmp_path / "p.pxposet"
+    A.save(path)
+    data = bytearray(path.read_bytes())
+    data[40:48] = (3).to_bytes(8, "little", signed=True)      # nnz_niv
+    data[48:56] = (2 ** 40).to_bytes(8, "little", signed=True)  # nnz_niv_up
+    path.write_bytes(bytes(data))
+    Bq = px.poset_load(path, flags=px.PX_BUILD_HOST_ONLY)
+    assert Bq.info_dict()["nnz_niv"] == A.info_dict()["nnz_niv"]
+    assert Bq.info_dict()["nnz_niv_up"] == A.info_dict()["nnz_niv_up"]
