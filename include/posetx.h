@@ -74,7 +74,7 @@ typedef enum {
   PX_ENOMEM = 4,        /* host or device allocation failed                           */
   PX_EHIP = 5,          /* a HIP runtime call or kernel launch failed                 */
   PX_EUNSUPPORTED = 6,  /* operation not available for this handle or dtype           */
-  PX_ENONFINITE = 7,    /* refinement met a NaN or Inf residual                       */
+  PX_ENONFINITE = 7,    /* a floating-point Möbius result or refinement held NaN / Inf */
   PX_ENOTCONV = 8       /* refinement did not reach the tolerance                     */
 } px_status;
 
@@ -202,20 +202,26 @@ px_status px_zeta_adjoint(px_poset* p, int dtype, const void* w, int64_t ldw, vo
 /*
  * f = M g = Z^{-1} g  (fast Möbius transform, §3 and Alg. 4): level-scheduled solve
  * of U y' = g, then f = V^{-1} y' (first difference along every chain).
- *   PX_I64: exact; max_refine and tol are ignored.
+ *   PX_I64: exact; max_refine and tol are ignored; never synchronises.
  *   PX_F64: float64 solve; no refinement.
  *   PX_F32: float32 solve, then up to max_refine steps of iterative refinement:
  *           r = g - zeta(f) with zeta applied in float64, delta = M r (float32
- *           solve), f += delta.  tol > 0 stops early once every column has
- *           ||delta||_inf <= tol * ||f||_inf (a forward-error test: the residual
- *           itself is floored by the float32 rounding of f summed over down-sets);
- *           this check synchronises the stream each step.  tol <= 0 runs exactly
- *           max_refine steps with no host synchronisation.
- *   rep        NULL or receives the refinement report (computes the final residual;
- *              synchronises).
- * g and f must not overlap.  Returns PX_ENONFINITE if a correction or the iterate is
- * not finite, and PX_ENOTCONV if tol > 0 and max_refine > 0 and the correction test
- * was not met within max_refine steps (f is still written).
+ *           solve), f += delta.
+ *   tol (floating-point dtypes):
+ *     > 0   PX_F32 stops early once every column has ||delta||_inf <= tol *
+ *           ||f||_inf (a forward-error test: the residual itself is floored by
+ *           the float32 rounding of f summed over down-sets); this check
+ *           synchronises the stream after each step.
+ *     = 0   runs exactly max_refine steps; then synchronises the stream once and
+ *           checks the result for NaN / Inf.
+ *     < 0   runs exactly max_refine steps asynchronously: no value checks and no
+ *           host synchronisation (the form to record under HIP graph capture).
+ *   rep        NULL or receives the refinement report (PX_F32; computes the final
+ *              residual; synchronises).
+ * g and f must not overlap.  Returns PX_ENONFINITE if tol >= 0 (or rep != NULL) and
+ * the result, a correction or the residual holds a NaN or Inf (f is still written),
+ * and PX_ENOTCONV if tol > 0 and max_refine > 0 and the correction test was not met
+ * within max_refine steps (f is still written).
  */
 px_status px_mobius(px_poset* p, int dtype, const void* g, int64_t ldg, void* f, int64_t ldf,
                     int64_t B, int max_refine, double tol, void* stream, px_refine_report* rep);

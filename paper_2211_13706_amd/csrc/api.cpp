@@ -817,15 +817,35 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   hipStream_t s = (hipStream_t)stream;
   const px::ElemType T = etype(dtype);
   const int dir = up ? -1 : 1;
-  hipError_t e = solve_levels(p, up, T, g, ldg, T, w + L.y, B, w + L.part, s);
-  if (e == hipSuccess) e = run_chain_diff(p->dp, dir, T, w + L.y, B, T, f, ldf, false, nullptr, s);
-  if (e != hipSuccess) return hip_status(e, "mobius launch");
-  if (!refine) return PX_OK;
-
-  const bool check = tol > 0 || rep;
-  double* r64 = (double*)(w + L.r64);
+  // Floating-point results are checked for NaN / Inf unless tol < 0: once, after
+  // the last chain difference, from the statistics it fuses (one synchronisation).
+  const bool fp = dtype != PX_I64;
+  const bool check_end = fp && tol >= 0;
+  const bool check_steps = refine && (tol > 0 || rep);  // statistics read after every step
   uint64_t* dstats = (uint64_t*)(w + L.stats);
   std::vector<uint64_t> hstats(2 * B + 1);
+  const bool stats0 = check_end && (!refine || max_refine == 0);
+  hipError_t e = solve_levels(p, up, T, g, ldg, T, w + L.y, B, w + L.part, s);
+  if (e == hipSuccess) e = run_chain_diff(p->dp, dir, T, w + L.y, B, T, f, ldf, false, stats0 ? dstats : nullptr, s);
+  if (e != hipSuccess) return hip_status(e, "mobius launch");
+  auto read_nonfinite = [&](bool& nonfinite) -> px_status {
+    hipError_t e2 = hipMemcpyAsync(hstats.data() + 2 * B, dstats + 2 * B, 8, hipMemcpyDeviceToHost, s);
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+    if (e2 != hipSuccess) return hip_status(e2, "non-finite check");
+    nonfinite = hstats[2 * B] != 0;
+    return PX_OK;
+  };
+  if (stats0) {
+    bool bad = false;
+    if ((st = read_nonfinite(bad)) != PX_OK) return st;
+    if (bad) {
+      if (rep) rep->nonfinite = 1;
+      return fail(PX_ENONFINITE, "the Möbius transform met a non-finite value");
+    }
+  }
+  if (!refine) return PX_OK;
+
+  double* r64 = (double*)(w + L.r64);
   // Largest over columns of stats[col] / stats[B + col] (float64 bit patterns).
   auto read_ratio = [&](double& ratio, bool& nonfinite) -> px_status {
     hipError_t e2 = hipMemcpyAsync(hstats.data(), dstats, hstats.size() * 8, hipMemcpyDeviceToHost, s);
@@ -856,13 +876,18 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   double corr = 0, resid = 0;
   bool nonfinite = false, converged = false;
   while (it < max_refine) {
+    const bool last_check = check_end && it + 1 == max_refine;
     e = residual();
     if (e == hipSuccess) e = solve_levels(p, up, px::E_F64, r64, B, px::E_F32, w + L.y, B, w + L.part, s);
     if (e == hipSuccess)
-      e = run_chain_diff(p->dp, dir, px::E_F32, w + L.y, B, px::E_F32, f, ldf, true, check ? dstats : nullptr, s);
+      e = run_chain_diff(p->dp, dir, px::E_F32, w + L.y, B, px::E_F32, f, ldf, true,
+                         check_steps || last_check ? dstats : nullptr, s);
     if (e != hipSuccess) return hip_status(e, "refinement launch");
     ++it;
-    if (check) {
+    if (!check_steps && last_check) {
+      if ((st = read_nonfinite(nonfinite)) != PX_OK) return st;
+    }
+    if (check_steps) {
       // stop on the size of the correction relative to the iterate (forward error)
       if ((st = read_ratio(corr, nonfinite)) != PX_OK) return st;
       if (nonfinite) break;

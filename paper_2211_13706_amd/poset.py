@@ -29,16 +29,38 @@ def _dtype_code(t) -> int:
         raise TypeError(f"unsupported dtype {t.dtype}; use int64, float32 or float64") from None
 
 
-def _as_matrix(t, name):
+def _as_matrix(t, name, device=None):
+    """t as a 2-D GPU matrix whose rows the library can address as ptr + row * ld:
+    unit column stride and rows that do not overlap.  Other views (transposes,
+    broadcasts such as expand(n, B) with row stride 0) are copied."""
     if t.dim() == 1:
         t = t.unsqueeze(1)
     if t.dim() != 2:
         raise ValueError(f"{name} must be [n] or [n, B]")
     if not t.is_cuda:
         raise ValueError(f"{name} must be a GPU tensor (the library has no CPU path)")
-    if t.stride(1) != 1 and t.shape[1] > 1:
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name} is on {t.device}, the poset on cuda:{device}")
+    if (t.shape[1] > 1 and t.stride(1) != 1) or (t.shape[0] > 1 and t.stride(0) < t.shape[1]):
         t = t.contiguous()
     return t
+
+
+def _out_matrix(out, x):
+    """The output matrix for input x: a new contiguous one, or the caller's `out`
+    after checking that it has x's shape, dtype and device, unit column stride
+    and non-overlapping rows (the library writes n rows of B elements at ld)."""
+    import torch
+    if out is None:
+        out = torch.empty_like(x, memory_format=torch.contiguous_format)
+        return out, out
+    out2 = out.unsqueeze(1) if out.dim() == 1 else out
+    if (out2.dim() != 2 or tuple(out2.shape) != tuple(x.shape) or out2.dtype != x.dtype
+            or out2.device != x.device):
+        raise ValueError(f"out must be a {tuple(x.shape)} {x.dtype} tensor on {x.device}")
+    if (out2.shape[1] > 1 and out2.stride(1) != 1) or (out2.shape[0] > 1 and out2.stride(0) < out2.shape[1]):
+        raise ValueError("out must have unit column stride and non-overlapping rows")
+    return out, out2
 
 
 def _ld(t):
@@ -181,15 +203,10 @@ def poset_load(path, flags: int = 0, device: int = 0) -> Poset:
 
 
 def _transform(fn_name, P, x, out):
-    import torch
-    x = _as_matrix(x, "input")
+    x = _as_matrix(x, "input", P.device)
     if x.shape[0] != P.n:
         raise ValueError(f"input has {x.shape[0]} rows, poset has {P.n}")
-    if out is None:
-        out = torch.empty_like(x, memory_format=torch.contiguous_format)
-    out2 = out if out.dim() == 2 else out.unsqueeze(1)
-    if out2.shape != x.shape or out2.dtype != x.dtype or out2.stride(1) != 1 and out2.shape[1] > 1:
-        raise ValueError("out must match the input's shape and dtype, with unit column stride")
+    out, out2 = _out_matrix(out, x)
     code = _dtype_code(x)
     fn = getattr(_lib.lib(), fn_name)
     _lib.check(fn(P.handle, code, ctypes.c_void_p(x.data_ptr()), _ld(x), ctypes.c_void_p(out2.data_ptr()),
@@ -208,13 +225,10 @@ def zeta_adjoint(P: Poset, w, out=None):
 
 
 def _mobius(fn_name, P, g, out, max_refine, tol, report):
-    import torch
-    g = _as_matrix(g, "input")
+    g = _as_matrix(g, "input", P.device)
     if g.shape[0] != P.n:
         raise ValueError(f"input has {g.shape[0]} rows, poset has {P.n}")
-    if out is None:
-        out = torch.empty_like(g, memory_format=torch.contiguous_format)
-    out2 = out if out.dim() == 2 else out.unsqueeze(1)
+    out, out2 = _out_matrix(out, g)
     rep = _lib.RefineReport() if report else None
     code = _dtype_code(g)
     fn = getattr(_lib.lib(), fn_name)
@@ -225,7 +239,12 @@ def _mobius(fn_name, P, g, out, max_refine, tol, report):
 
 
 def mobius(P: Poset, g, out=None, max_refine: int = 3, tol: float = 0.0, report: bool = False):
-    """f = M g = Z^{-1} g (px_mobius).  float32 uses float64-residual refinement."""
+    """f = M g = Z^{-1} g (px_mobius).  float32 uses float64-residual refinement.
+
+    tol > 0 stops the refinement early on the correction test; tol = 0 runs
+    max_refine steps and then checks the result for NaN / Inf (PosetxError
+    PX_ENONFINITE; one stream synchronisation); tol < 0 runs asynchronously
+    without value checks (for graph capture).  int64 ignores tol."""
     return _mobius("px_mobius", P, g, out, max_refine, tol, report)
 
 
@@ -247,6 +266,7 @@ class Batch:
         _lib.check(_lib.lib().px_batch_rows(h, ctypes.byref(rows)), "px_batch_rows")
         self.rows = rows.value
         self.offsets = np.concatenate([[0], np.cumsum([p.n for p in self.posets])]).astype(np.int64)
+        self.device = self.posets[0].device if self.posets else 0
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -283,15 +303,13 @@ def batch_build(posets) -> Batch:
 
 
 def _batched(fn_name, b, x, out):
-    import torch
-    x = _as_matrix(x, "input")
+    x = _as_matrix(x, "input", b.device)
     if x.shape[0] != b.rows:
         raise ValueError(f"input has {x.shape[0]} rows, batch has {b.rows}")
-    if out is None:
-        out = torch.empty_like(x, memory_format=torch.contiguous_format)
+    out, out2 = _out_matrix(out, x)
     fn = getattr(_lib.lib(), fn_name)
-    _lib.check(fn(b.handle, _dtype_code(x), ctypes.c_void_p(x.data_ptr()), _ld(x), ctypes.c_void_p(out.data_ptr()),
-                  _ld(out), int(x.shape[1]), _stream(x)), fn_name)
+    _lib.check(fn(b.handle, _dtype_code(x), ctypes.c_void_p(x.data_ptr()), _ld(x), ctypes.c_void_p(out2.data_ptr()),
+                  _ld(out2), int(x.shape[1]), _stream(x)), fn_name)
     return out
 
 
