@@ -297,6 +297,26 @@ def _reverse_csr(p):
     return indptr, src[order].astype(np.int32)
 
 
+@pytest.mark.parametrize("edges", [[(0, 1), (1, 0)], [(0, 1), (1, 2), (2, 0)], [(0, 1), (1, 2), (2, 3), (3, 1), (0, 4)]])
+def test_is_acyclic_rejects_cycles(edges):
+    """A directed cycle makes the reachability relation symmetric on its nodes (x ⪯ y and
+    y ⪯ x with x != y), so it is not a partial order (§2.1); removing one edge of the
+    cycle restores antisymmetry."""
+    n = 1 + max(max(e) for e in edges)
+
+    def csr(es):
+        order = sorted(es)
+        indptr = np.zeros(n + 1, np.int64)
+        for u, _ in order:
+            indptr[u + 1] += 1
+        return np.cumsum(indptr), np.array([v for _, v in order], np.int32)
+
+    R = O.reachability(n, *csr(edges))
+    assert not O.is_acyclic(R)
+    cyc = [e for e in edges if e != (0, 4)]
+    assert O.is_acyclic(O.reachability(n, *csr([e for e in edges if e != cyc[-1]])))
+
+
 def test_int64_wraps_modulo_2_64():
     p = W.chain_only(5)
     R = O.reachability(p.n, p.indptr, p.indices)
