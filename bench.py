@@ -12,8 +12,10 @@ resident in HBM.  Host preprocessing is timed separately and reported under
 
 Printed: ONE JSON line with the metric (node·RHS/s), the roofline of the
 dominant kernel (algorithmic bytes per launch / its average HIP-event
-duration on the launch stream), and the CPU oracle timed on a bounded sample
-of the same workload on the host.  "legs" adds measurements of the other
+duration on the launch stream), the same steps over four rotating input
+buffers (no input left in the cache by the step before), the CPU oracle timed
+on a bounded sample of the same workload on the host, and the straightforward
+O(n·k) C++/OpenMP transforms on all the host cores the process may use.  "legs" adds measurements of the other
 rows: by default the int64 zeta and Möbius, the adjoint, the B = 8 share,
 the preprocessing and the grid Möbius; "all" also the batched posets, the
 n = 2^23 poset and the Erdős–Rényi DAGs with sparse niv rows.
@@ -46,8 +48,27 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(phase: str, n: int, k: int, B: int, s: int, info: dict, compact: bool = False) -> int:
-    """Compulsory bytes of one launch of each kernel: every array it touches, once.
+def algorithmic_bytes(phase: str, n: int, k: int, B: int, s: int, compact: bool = False) -> int:
+    """Compulsory bytes of one launch: the factored method Z = U V reads f, writes the chain
+    prefixes P, reads P once, reads the niv map and writes g, each array once per step
+    (20 B per node·RHS at k = B = 64 in float32).  A kernel is charged the arrays of that
+    list which it reads or writes; tile states, snapshots, index arrays and the compact
+    walk's gathered prefixes are implementation traffic (``moved_bytes``).
+
+    compact walk (P never exists): scan_reduce reads f; apply_combine reads f and writes g.
+    walk over P: scan_apply reads f and writes P; walk_combine reads P and writes g.
+    gather (one thread per row): reads P and niv, writes g."""
+    f = g = p_ = n * B * s
+    niv = n * k * 4
+    return {"scan_reduce": f, "scan_carry": 0, "walk_events": 0,
+            "apply_combine": f + g,
+            "scan_apply": f + p_, "scan_onepass": f + p_,
+            "walk_combine": p_ + g,
+            "gather": p_ + niv + g}.get(phase, 0)
+
+
+def moved_bytes(phase: str, n: int, k: int, B: int, s: int, info: dict, compact: bool = False) -> int:
+    """Bytes a kernel of this implementation moves: every array it touches, once.
 
     Tile states (the scan's per-tile totals and carries, n/64 tiles of 64 rows
     for 64-column blocks, 2s bytes per column) count where they are read or
@@ -148,6 +169,29 @@ def cpu_baseline(p, f, budget_s: float):
                       f"(down-set by BFS, float64 pairwise sums), {dt:.1f} s single-threaded"}
 
 
+def cpu_nk_baseline(P, p, f_host, gpu_rate):
+    """The straightforward O(n·k) CPU transforms (C++17 + OpenMP: Alg. 3 zeta, Alg. 4 Möbius
+    over the level schedule of Alg. 5) on the same dense niv map, on the host's cores: the
+    float32 zeta of the whole workload and the exact int64 Möbius of an int64 copy, each
+    the steady_clock median of 5 calls after one warm-up."""
+    import baseline
+    import workloads as W
+    cpu = baseline.NkCpu(P)
+    tz = cpu.time_zeta(f_host, reps=5)
+    fi = W.functions(p.n, f_host.shape[1], "int", seed=3, lo=-1000, hi=1000)
+    gi = cpu.zeta(fi)
+    tm = cpu.time_mobius(gi, reps=5)
+    exact = bool(np.array_equal(cpu.mobius(gi), fi))
+    nb = p.n * f_host.shape[1]
+    return {"value": nb / tz, "unit": "node·RHS/s", "cores": cpu.threads, "affinity_cpus": cpu.affinity,
+            "cpu_model": baseline.cpu_model(), "build": baseline.lib().variant,
+            "kind": "O(n·k) C++17/OpenMP (Alg. 3 zeta, Alg. 4 + Alg. 5 level-parallel Möbius)",
+            "timing": "std::chrono::steady_clock, median of 5 after 1 warm-up",
+            "zeta_f32_s": tz, "mobius_int64_s": tm, "mobius_int64_node_rhs_per_s": nb / tm,
+            "mobius_roundtrip_exact": exact, "levels": cpu.nlev,
+            "gpu_over_cpu_zeta": round(gpu_rate / (nb / tz), 1)}
+
+
 def _time(fn, steps, sync):
     for _ in range(2):
         fn()
@@ -165,7 +209,7 @@ def f64_growth(px, P, n, dev, B_: int = 4):
     import torch
     import workloads as W
     r = torch.from_numpy(W.functions(n, B_, "uniform", seed=12, lo=-1.0, hi=1.0).astype("float64")).to(dev)
-    m = px.mobius(P, r)
+    m = px.mobius(P, r, tol=-1.0)  # no value check: an overflow is the answer here
     g = (m.abs().amax() / r.abs().amax()).item()
     return g if g == g and g != float("inf") else str(g)
 
@@ -236,13 +280,14 @@ def leg_grid(px, dev, steps, refine=3):
     g = torch.from_numpy(W.functions(q.n, Bg, "uniform", seed=10, lo=-1.0, hi=1.0)).to(dev)
     f = torch.empty_like(g)
     G.reserve(torch.float32, Bg)
-    t32 = _time(lambda: px.mobius(G, g, out=f, max_refine=refine), steps, sync)
+    # asynchronous calls (tol < 0: no value check, no host synchronisation) on both sides
+    t32 = _time(lambda: px.mobius(G, g, out=f, max_refine=refine, tol=-1.0), steps, sync)
     _, rep = px.mobius(G, g, out=f, max_refine=refine, report=True)
     g64 = g.double()
     cols = [g64[:, b:b + 1].contiguous() for b in range(Bg)]
     f64 = [torch.empty_like(c) for c in cols]
     G.reserve(torch.float64, 1)
-    t64 = _time(lambda: [px.mobius(G, c, out=o) for c, o in zip(cols, f64)], max(2, steps // 4), sync)
+    t64 = _time(lambda: [px.mobius(G, c, out=o, tol=-1.0) for c, o in zip(cols, f64)], max(2, steps // 4), sync)
     # agreement of the refined float32 result with the float64 solve, normwise per column
     f64m = torch.cat(f64, dim=1)
     err = ((f.double() - f64m).abs().amax(0) / f64m.abs().amax(0)).max().item()
@@ -404,7 +449,7 @@ def leg_er_sparse(px, dev, steps, n_log2=18, deg=4, refine=True):
             err = ((f2 - f).abs().amax(0) / f.abs().amax(0)).max().item()
         except px.PosetxError as e:
             rep, err = {"status": e.name}, None
-        tr = _time(lambda: px.mobius(P, g, max_refine=3), max(2, steps // 4), sync)
+        tr = _time(lambda: px.mobius(P, g, max_refine=3, tol=-1.0), max(2, steps // 4), sync)
     return {"workload": f"Erdős–Rényi DAG, n={n}, average degree {deg}, matching chains, B=64 float32",
             "k": info["k"], "nnz_niv": nnz, "niv_sparse": info["niv_sparse"], "levels": info["levels_down"],
             "preprocess_s": round(t_prep, 2),
@@ -486,6 +531,21 @@ def main():
     dt_prof = time.perf_counter() - t1
     prof = profile_read(lib)
     lib.px_profile(0)
+    # the same K steps over NROT distinct input and output matrices in turn (1 GiB of
+    # inputs at n = 2^20, B = 64, four times the 256 MB last-level cache), so that no
+    # step finds its input left in the cache by the step before
+    NROT = 4
+    fs = [f] + [torch.from_numpy(W.functions(p.n, B, "normal", seed=200 + i)).to(dev) for i in range(NROT - 1)]
+    gs = [g] + [torch.empty_like(f) for _ in range(NROT - 1)]
+    for i in range(NROT):
+        px.zeta(P, fs[i], out=gs[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(args.steps):
+        px.zeta(P, fs[i % NROT], out=gs[i % NROT])
+    torch.cuda.synchronize()
+    dt_rot = time.perf_counter() - t1
+    del fs, gs
     copy_gbps = measured_copy_gbps(dev)
 
     ms_step = dt * 1e3 / args.steps
@@ -497,9 +557,11 @@ def main():
         ms, cnt = prof[name]
         if cnt:
             avg = ms / cnt
-            byt = algorithmic_bytes(name, p.n, P.k, B, 4, P.info, compact)
+            byt = algorithmic_bytes(name, p.n, P.k, B, 4, compact)
+            mv = moved_bytes(name, p.n, P.k, B, 4, P.info, compact)
             phases[name] = {"avg_ms": round(avg, 4), "launches": cnt, "alg_bytes": byt,
-                            "GBps": round(byt / (avg * 1e-3) / 1e9, 1) if byt else None}
+                            "GBps": round(byt / (avg * 1e-3) / 1e9, 1) if byt else None,
+                            "moved_bytes": mv, "moved_GBps": round(mv / (avg * 1e-3) / 1e9, 1)}
             gb = gathered_bytes(name, P.k, B, 4, P.info)
             if gb:
                 phases[name]["gathered_bytes"] = gb
@@ -509,9 +571,9 @@ def main():
     tr = traffic_for(dom)
     # whole-step bytes of the factored method Z = U V as stated: read f, write P,
     # read P, read niv, write g (20 B per node and right-hand side at k = B);
-    # the compact walk moves fewer (the sum of the phases' bytes)
+    # the compact walk moves fewer (the sum of the phases' moved bytes)
     step_bytes = 4 * p.n * B * 4 + p.n * P.k * 4
-    moved = sum(ph["alg_bytes"] for ph in phases.values())
+    moved = sum(ph["moved_bytes"] for ph in phases.values())
     out = {
         "metric": METRIC,
         "value": value,
@@ -532,14 +594,20 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr,
                      "alg_bytes_per_launch": phases[dom]["alg_bytes"],
+                     "avg_ms": phases[dom]["avg_ms"],
+                     "moved_bytes_per_launch": phases[dom]["moved_bytes"],
+                     "moved_GBps": phases[dom]["moved_GBps"],
                      "gathered_GBps": phases[dom].get("gathered_GBps"),
                      "copy_GBps": copy_gbps, "frac_of_copy": round(ach / copy_gbps, 4),
                      "traffic_GBps": round(tr / (phases[dom]["avg_ms"] * 1e-3) / 1e9, 1) if tr else None},
         "step_roofline": {"alg_bytes": step_bytes, "GBps": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
                           "frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                           "path": "compact walk" if compact else "scan + walk over P",
-                          "phase_bytes": moved,
-                          "phase_GBps": round(moved / (ms_step * 1e-3) / 1e9, 1)},
+                          "phase_moved_bytes": moved,
+                          "phase_moved_GBps": round(moved / (ms_step * 1e-3) / 1e9, 1)},
+        "rotating_inputs": {"buffers": NROT, "ms_per_step": dt_rot * 1e3 / args.steps,
+                            "node_rhs_per_s": p.n * B / (dt_rot / args.steps),
+                            "step_frac": round(step_bytes / (dt_rot / args.steps) / 1e9 / HBM_PEAK_GBS, 4)},
         "phases": phases,
         "preprocess_s": {"total": round(t_prep, 3), **{k: round(v, 3) for k, v in P.info.items()
                                                       if k.startswith("t_")},
@@ -576,6 +644,7 @@ def main():
         out["legs"] = legs
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, f_host, args.cpu_budget)
+        out["cpu_nk_baseline"] = cpu_nk_baseline(P, p, f_host, value)
     print(json.dumps(out), flush=True)
 
 
