@@ -200,6 +200,30 @@ px_status px_zeta_adjoint(px_poset* p, int dtype, const void* w, int64_t ldw, vo
                           int64_t ldo, int64_t B, void* stream);
 
 /*
+ * g = Z f exactly as px_zeta computes it (the same kernels, bit-identical results),
+ * for callers that cannot allocate device memory: code recorded under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  It calls no
+ * hipMalloc, hipFree or other allocating routine.  Its scratch (the prefixes,
+ * tile states and walk snapshots that px_zeta keeps in the handle's workspace)
+ * is a static device array of 64 MiB that every GPU running the library holds
+ * until the process ends; its device address is looked up once per device, on
+ * the first call there.
+ *   Returns PX_EINVAL, before launching anything, when the call needs more than
+ *   64 MiB of scratch (the message says how much).  The scratch of the compact
+ *   walk (one poset, k <= 64, B > 32) is small: at n = 2^20, k = 64, B = 64 float32
+ *   it needs about 97 MiB, so that size is rejected while n = 2^19 fits; the scan
+ *   over P (other shapes) needs (n + 1) * B * elem bytes for P and fits while
+ *   n * B * elem stays below about 60 MiB.
+ *   Every call on one GPU shares that GPU's array and leaves its contents behind;
+ *   nothing in it needs to start at zero (the kernels write every word they read).
+ *   Calls that overlap in time on one GPU (on different streams or from different
+ *   threads) race on it: serialise them.
+ * Other arguments, errors and the asynchronous behaviour are those of px_zeta.
+ */
+px_status px_zeta_noalloc(px_poset* p, int dtype, const void* f, int64_t ldf, void* g,
+                          int64_t ldg, int64_t B, void* stream);
+
+/*
  * f = M g = Z^{-1} g  (fast Möbius transform, §3 and Alg. 4): level-scheduled solve
  * of U y' = g, then f = V^{-1} y' (first difference along every chain).
  *   PX_I64: exact; max_refine and tol are ignored; never synchronises.

@@ -27,7 +27,7 @@ EXPORTS = [
     "px_batch_build", "px_batch_free", "px_batch_reserve", "px_batch_rows", "px_zeta_batched",
     "px_zeta_adjoint_batched", "px_last_error", "px_version", "px_profile", "px_profile_read",
     "px_profile_phase_name", "px_autotune", "px_batch_autotune", "px_poset_niv_csr", "px_poset_rows",
-    "px_poset_save", "px_poset_load",
+    "px_poset_save", "px_poset_load", "px_zeta_noalloc",
 ]
 
 
@@ -85,6 +85,7 @@ def _declare(lib):
         "px_reserve": [P, i32, i64],
         "px_zeta": [P, i32, P, i64, P, i64, i64, P],
         "px_zeta_adjoint": [P, i32, P, i64, P, i64, i64, P],
+        "px_zeta_noalloc": [P, i32, P, i64, P, i64, i64, P],
         "px_mobius": [P, i32, P, i64, P, i64, i64, i32, f64, P, ctypes.POINTER(RefineReport)],
         "px_mobius_adjoint": [P, i32, P, i64, P, i64, i64, i32, f64, P, ctypes.POINTER(RefineReport)],
         "px_batch_build": [i32, P, ctypes.POINTER(P)],

@@ -18,6 +18,7 @@
 
 #include "kernels.h"
 #include "niv_device.h"
+#include "noalloc.h"
 #include "posetx.h"
 #include "prep.h"
 
@@ -759,8 +760,46 @@ hipError_t solve_levels(const px_poset* p, bool up, px::ElemType tin, const void
   return hipSuccess;
 }
 
+// The regions one zeta call uses, and nothing else: the compact walk takes the
+// tile states, the snapshots and L / Q; the scan over P takes P, the tile
+// states, the single-pass flags and the snapshots (sparse rows: the chunk sums).
+Layout zeta_layout(const px_poset* p, bool up, int dtype, int64_t B, bool compact) {
+  const int64_t n = p->prep.n;
+  const size_t es = elem_size(dtype);
+  const int cw = px::col_width(B);
+  const int64_t nt = p->ntiles[px::seg_index(cw)];
+  const int m = up ? 1 : 0;
+  Layout L;
+  size_t o = 0;
+  if (!compact) {
+    L.y = o;
+    o = align256(o + (size_t)(n + 1) * B * es);
+  }
+  L.aux = o;
+  o = align256(o + (size_t)nt * B * 16 * 2);
+  if (!compact) {
+    L.sync = o;
+    o = align256(o + (size_t)(2 + nt * ((B + cw - 1) / cw)) * 4);
+  }
+  L.snaps = o;
+  if (p->prep.sparse) {
+    L.part = o;
+    o = align256(o + (size_t)max_parts(p) * B * 8);
+  } else {
+    o = align256(o + (size_t)p->nsnap[m] * B * es);
+  }
+  if (compact) {
+    L.lq = o;
+    o = align256(o + (size_t)(2 * p->nslots[m] + 1) * B * es);
+  }
+  L.total = o;
+  return L;
+}
+
+// ext (nullable): a caller-provided workspace of ext_bytes bytes, used instead
+// of the handle's grow-only one (then nothing is allocated).
 px_status zeta_impl(px_poset* p, bool up, int dtype, const void* f, int64_t ldf, void* g, int64_t ldg, int64_t B,
-                    void* stream) {
+                    void* stream, void* ext = nullptr, size_t ext_bytes = 0) {
   if (!p) return fail(PX_EINVAL, "null poset");
   if (p->host_only) return fail(PX_EUNSUPPORTED, "poset was built with PX_BUILD_HOST_ONLY");
   if (up && !p->has_up) return fail(PX_EUNSUPPORTED, "poset was built with PX_BUILD_NO_ADJOINT");
@@ -771,12 +810,23 @@ px_status zeta_impl(px_poset* p, bool up, int dtype, const void* f, int64_t ldf,
   if (!dg.ok) return fail(PX_EHIP, "hipSetDevice failed");
   const int cw = px::col_width(B);
   const int64_t nt = p->ntiles[px::seg_index(cw)];
-  Layout L = layout(p->prep.n, B, dtype, false, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p), max_parts(p));
-  if ((st = p->ws.ensure(L.total)) != PX_OK) return st;
-  char* w = (char*)p->ws.p;
+  const bool compact = use_compact(p, up, B);
+  Layout L;
+  char* w;
+  if (ext) {
+    L = zeta_layout(p, up, dtype, B, compact);
+    if (L.total > ext_bytes)
+      return fail(PX_EINVAL, "this call needs " + std::to_string(L.total) + " bytes of scratch; the static scratch holds " +
+                                 std::to_string(ext_bytes));
+    w = (char*)ext;
+  } else {
+    L = layout(p->prep.n, B, dtype, false, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p), max_parts(p));
+    if ((st = p->ws.ensure(L.total)) != PX_OK) return st;
+    w = (char*)p->ws.p;
+  }
   hipStream_t s = (hipStream_t)stream;
   const px::ElemType T = etype(dtype);
-  if (use_compact(p, up, B))
+  if (compact)
     return hip_status(run_compact(p->dp, up ? -1 : 1, T, f, ldf, T, g, ldg, T, nullptr, 0, B, w + L.aux, nt,
                                   w + L.lq, w + L.snaps, s),
                       "zeta launch");
@@ -1559,6 +1609,21 @@ px_status px_zeta(px_poset* p, int dtype, const void* f, int64_t ldf, void* g, i
 px_status px_zeta_adjoint(px_poset* p, int dtype, const void* w, int64_t ldw, void* out, int64_t ldo, int64_t B,
                           void* stream) {
   return zeta_impl(p, true, dtype, w, ldw, out, ldo, B, stream);
+}
+
+px_status px_zeta_noalloc(px_poset* p, int dtype, const void* f, int64_t ldf, void* g, int64_t ldg, int64_t B,
+                          void* stream) {
+  if (!p) return fail(PX_EINVAL, "null poset");
+  if (p->host_only) return fail(PX_EUNSUPPORTED, "poset was built with PX_BUILD_HOST_ONLY");
+  DeviceGuard dg(p->device);
+  if (!dg.ok) return fail(PX_EHIP, "hipSetDevice failed");
+  void* scratch = nullptr;
+  const hipError_t e = px::static_scratch(p->device, &scratch);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(PX_EHIP, std::string("address of the static scratch: ") + hipGetErrorString(e));
+  }
+  return zeta_impl(p, false, dtype, f, ldf, g, ldg, B, stream, scratch, px::kStaticScratchBytes);
 }
 
 px_status px_mobius(px_poset* p, int dtype, const void* g, int64_t ldg, void* f, int64_t ldf, int64_t B,

@@ -224,6 +224,12 @@ def zeta_adjoint(P: Poset, w, out=None):
     return _transform("px_zeta_adjoint", P, w, out)
 
 
+def zeta_noalloc(P: Poset, f, out=None):
+    """g = Z f through px_zeta_noalloc: the library allocates nothing (its scratch is a
+    static 64 MiB device array); pass `out` to keep torch from allocating the result."""
+    return _transform("px_zeta_noalloc", P, f, out)
+
+
 def _mobius(fn_name, P, g, out, max_refine, tol, report):
     g = _as_matrix(g, "input", P.device)
     if g.shape[0] != P.n:
