@@ -114,6 +114,9 @@ typedef struct {
   int32_t niv_sparse;     /* 1 if the niv maps are kept sparse (PX_BUILD_SPARSE_NIV)    */
   int32_t niv_device_rounds; /* rounds of the device computation of the dense niv maps
                                 (0: the host recursion computed them)                    */
+  int64_t run_chunks;     /* chunks of the int64 level solve by runs (niv map; 0: that
+                             solve is not used and int64 solves row by row)              */
+  int64_t run_events;     /* change events those chunks read (niv map)                   */
 } px_info;
 
 typedef struct {

@@ -45,7 +45,8 @@ class Info(ctypes.Structure):
         "walk_emax", "walk_rows_distinct", "walk_row_loads")] + [
         ("chains_planted", ctypes.c_int32), ("device", ctypes.c_int32)] + [
         (name, ctypes.c_double) for name in ("t_validate", "t_chains", "t_niv", "t_levels", "t_upload")] + [
-        ("niv_sparse", ctypes.c_int32), ("niv_device_rounds", ctypes.c_int32)]
+        ("niv_sparse", ctypes.c_int32), ("niv_device_rounds", ctypes.c_int32),
+        ("run_chunks", ctypes.c_int64), ("run_events", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -335,7 +335,7 @@ std::vector<int32_t> scan_orders(const std::vector<int32_t>& segoff, int64_t nch
 }
 
 struct Layout {
-  size_t y = 0, p64 = 0, r64 = 0, aux = 0, stats = 0, snaps = 0, sync = 0, lq = 0, part = 0, total = 0;
+  size_t y = 0, p64 = 0, r64 = 0, aux = 0, stats = 0, snaps = 0, sync = 0, lq = 0, part = 0, flow = 0, total = 0;
 };
 
 // Workspace layout of one call: a [n, B] matrix of the working type (P or Y),
@@ -343,9 +343,10 @@ struct Layout {
 // the scan's tile states and the refinement statistics.  nparts: chunk sums
 // of the split long rows of a sparse level solve (8 bytes per column).
 // With nslots >= 0 also the compact walk's L and Q ((2 * nslots + 1) rows of
-// the working type: float64 for the residual of a refinement).
+// the working type: float64 for the residual of a refinement).  nflow: ints of
+// the persistent int64 solve's error word and ready flags.
 Layout layout(int64_t n, int64_t B, int dtype, bool refine, int64_t ntiles, int64_t nsnap = 0,
-              int64_t nslots = -1, int64_t nparts = 0) {
+              int64_t nslots = -1, int64_t nparts = 0, int64_t nflow = 0) {
   Layout L;
   size_t o = 0;
   L.y = o;  // one row more: the scan's zero row
@@ -368,6 +369,8 @@ Layout layout(int64_t n, int64_t B, int dtype, bool refine, int64_t ntiles, int6
   if (nslots >= 0) o = align256(o + (size_t)(2 * nslots + 1) * B * (refine ? 8 : elem_size(dtype)));
   L.part = o;
   o = align256(o + (size_t)nparts * B * 8);
+  L.flow = o;
+  o = align256(o + (size_t)nflow * 4);
   L.total = o;
   return L;
 }
@@ -535,6 +538,14 @@ struct px_poset {
           *d_tiles = nullptr, *d_lev_niv[2] = {nullptr, nullptr}, *d_lev_node[2] = {nullptr, nullptr},
           *d_walk[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
   int32_t* d_nivr[2] = {nullptr, nullptr};  // sparse niv rows: entries and row offsets
+  // int64 level solve by runs: change events and per-level chunks (px::SegTables)
+  int4* d_run_ev[2] = {nullptr, nullptr};
+  int4* d_run_chunks[2] = {nullptr, nullptr};
+  std::vector<int64_t> run_cptr[2];  // per level: offsets into d_run_chunks
+  int64_t run_events[2] = {0, 0};
+  int32_t* d_run_levn[2] = {nullptr, nullptr};  // per level: its first chunk (levels + 1 entries)
+  int32_t* d_run_dep_ptr[2] = {nullptr, nullptr};  // per chunk: the chunks it reads from
+  int32_t* d_run_deps[2] = {nullptr, nullptr};
   int64_t* d_nivp[2] = {nullptr, nullptr};
   int64_t ntiles[7] = {0, 0, 0, 0, 0, 0, 0};
   int64_t nevents[2] = {0, 0};
@@ -595,6 +606,15 @@ void free_poset_device(px_poset* p) {
     if (b) (void)hipFree(b);
   for (int64_t* b : p->d_nivp)
     if (b) (void)hipFree(b);
+  for (int m = 0; m < 2; ++m) {
+    if (p->d_run_ev[m]) (void)hipFree(p->d_run_ev[m]);
+    if (p->d_run_chunks[m]) (void)hipFree(p->d_run_chunks[m]);
+    if (p->d_run_levn[m]) (void)hipFree(p->d_run_levn[m]);
+    if (p->d_run_dep_ptr[m]) (void)hipFree(p->d_run_dep_ptr[m]);
+    if (p->d_run_deps[m]) (void)hipFree(p->d_run_deps[m]);
+    p->d_run_ev[m] = p->d_run_chunks[m] = nullptr;
+    p->d_run_levn[m] = p->d_run_dep_ptr[m] = p->d_run_deps[m] = nullptr;
+  }
   for (auto& sp : p->split) {
     if (sp.d_short) (void)hipFree(sp.d_short);
     if (sp.d_long) (void)hipFree(sp.d_long);
@@ -721,6 +741,114 @@ void build_split(const px::Prep& P, int m, px_poset::Split& sp, px::GatherSplit&
   gs.nlongs = (int64_t)longs.size();
 }
 
+// Tables of the int64 level solve by runs for one niv map (dense rows, see
+// px::SegTables): the change events of every row against the row below it in
+// its chain, then per level the chunks of at most kSegRows consecutive rows of
+// one chain with at most kSegEvents events in the rows after the first, each
+// {first row, (level << 6) | rows, first event, end event}.
+// Also, per chunk, the chunks it reads from (deps[dep_ptr[c] .. dep_ptr[c + 1])).
+// Returns false (no tables) where the events, chunks or dependencies overflow
+// 32-bit offsets or the levels 25 bits, or where the events would read more than
+// half as many rows as the full sums.
+bool build_runs(const px::Prep& P, bool up, std::vector<int4>& ev, std::vector<int4>& chunks,
+                std::vector<int64_t>& cptr, std::vector<int32_t>& dep_ptr, std::vector<int32_t>& deps) {
+  const int64_t n = P.n, k = P.k;
+  const std::vector<int32_t>& nv = up ? P.niv_up : P.niv;
+  const std::vector<int32_t>& ptr = up ? P.lev_up_ptr : P.lev_down_ptr;
+  const std::vector<int32_t>& rows = up ? P.lev_up_rows : P.lev_down_rows;
+  std::vector<int32_t> ev_ptr(n + 1, 0);
+  ev.clear();
+  for (int64_t r = 0; r < n; ++r) {
+    const int32_t c = P.chain_of_row[r];
+    if (r > P.chain_off[c]) {
+      const int32_t* a = &nv[(size_t)r * k];
+      const int32_t* b = a - k;
+      for (int64_t j = 0; j < k; ++j)
+        if (j != c && a[j] != b[j])
+          ev.push_back(make_int4(a[j] < 0 ? (int)n : a[j], b[j] < 0 ? (int)n : b[j], (int)r, 0));
+    }
+    if (ev.size() >= (size_t)INT32_MAX) return false;
+    ev_ptr[r + 1] = (int32_t)ev.size();
+  }
+  // deltas read two rows per event against k - 1 for a full sum: only worth it
+  // where they read at most half as much (not on a grid, where row i of chain j
+  // changes all j entries below it)
+  if (n > k && 2 * 2 * (int64_t)ev.size() > (k - 1) * (n - k)) return false;
+  chunks.clear();
+  cptr.assign(1, 0);
+  if (ptr.size() > ((size_t)1 << 25)) return false;  // levels packed in 25 bits
+  for (size_t l = 0; l + 1 < ptr.size(); ++l) {
+    for (int64_t i = ptr[l]; i < ptr[l + 1];) {
+      const int32_t r0 = rows[i], c = P.chain_of_row[r0];
+      int64_t j = i + 1;
+      while (j < ptr[l + 1] && j - i < px::kSegRows && rows[j] == rows[j - 1] + 1 && P.chain_of_row[rows[j]] == c &&
+             ev_ptr[rows[j] + 1] - ev_ptr[r0 + 1] <= px::kSegEvents)
+        ++j;
+      const int32_t r1 = rows[j - 1] + 1;
+      chunks.push_back(make_int4(r0, (int)(l << 6) | (r1 - r0), ev_ptr[r0 + 1], ev_ptr[r1]));
+      i = j;
+    }
+    cptr.push_back((int64_t)chunks.size());
+  }
+  if (chunks.size() >= (size_t)INT32_MAX) return false;
+  // the chunks that each chunk reads from: those holding its first row's
+  // other-chain entries and its events' rows (all at lower levels)
+  std::vector<int32_t> chunk_of(n, -1), seen(chunks.size(), -1);
+  for (size_t c = 0; c < chunks.size(); ++c)
+    for (int32_t r = chunks[c].x; r < chunks[c].x + (chunks[c].y & 63); ++r) chunk_of[r] = (int32_t)c;
+  dep_ptr.assign(1, 0);
+  deps.clear();
+  auto add = [&](int32_t row, int32_t c) {
+    if (row < 0 || row >= n) return;
+    const int32_t q = chunk_of[row];
+    if (q >= 0 && q != c && seen[q] != c) {
+      seen[q] = c;
+      deps.push_back(q);
+    }
+  };
+  for (size_t c = 0; c < chunks.size(); ++c) {
+    const int4 ch = chunks[c];
+    const int32_t* a = &nv[(size_t)ch.x * k];
+    for (int64_t j = 0; j < k; ++j)
+      if (a[j] != ch.x) add(a[j], (int32_t)c);
+    for (int32_t e = ch.z; e < ch.w; ++e) {
+      add(ev[e].x, (int32_t)c);
+      add(ev[e].y, (int32_t)c);
+    }
+    if (deps.size() >= (size_t)INT32_MAX) return false;
+    dep_ptr.push_back((int32_t)deps.size());
+  }
+  return true;
+}
+
+// The int64 solve goes by runs wherever its tables exist and B >= 5, in one
+// persistent launch.  POSETX_USOLVE (read on every call): "levels" runs the
+// solve by runs one launch per level, "direct" the row-by-row solve.
+int usolve_mode() {
+  const char* v = std::getenv("POSETX_USOLVE");
+  if (v && std::strcmp(v, "direct") == 0) return 0;
+  if (v && std::strcmp(v, "levels") == 0) return 1;
+  return 2;
+}
+
+// Polls per wait of the persistent solve (about a second); POSETX_FLOW_SPIN
+// overrides it (a tiny value exercises the fallback).
+int flow_spin_limit() {
+  const char* v = std::getenv("POSETX_FLOW_SPIN");
+  return v ? std::max(0, std::atoi(v)) : 1 << 20;
+}
+
+// Ints of the persistent solve's scratch for B columns (0 where it is not used):
+// the error word and a ready flag per row and column block.
+int64_t flow_ints(const px_poset* p, int64_t B) {
+  if (!p->d_run_chunks[0]) return 0;
+  const int cw = px::col_width(B);
+  const int64_t ncb = (B + cw - 1) / cw;
+  const int64_t nch = std::max(p->run_cptr[0].empty() ? 0 : p->run_cptr[0].back(),
+                               p->run_cptr[1].empty() ? 0 : p->run_cptr[1].back());
+  return 1 + ncb * std::max<int64_t>(p->prep.n + 1, nch);
+}
+
 bool use_compact(const px_poset* p, bool up, int64_t B) {
   return p->nslots[up ? 1 : 0] >= 0 && compact_enabled() && px::compact_ok(p->dp, up, B);
 }
@@ -728,7 +856,7 @@ bool use_compact(const px_poset* p, bool up, int64_t B) {
 // Level-scheduled solve U y' = g (Alg. 4, first loop; Alg. 5 schedule), one
 // launch per level so that every level sees the previous one complete.
 hipError_t solve_levels(const px_poset* p, bool up, px::ElemType tin, const void* g, int64_t ldg, px::ElemType ty,
-                        void* Y, int64_t B, void* part, hipStream_t s) {
+                        void* Y, int64_t B, void* part, void* flow, hipStream_t s) {
   const std::vector<int32_t>& ptr = up ? p->prep.lev_up_ptr : p->prep.lev_down_ptr;
   const int32_t* rows = up ? p->d_lev_up : p->d_lev_down;
   if (p->prep.n > 0) {
@@ -747,6 +875,33 @@ hipError_t solve_levels(const px_poset* p, bool up, px::ElemType tin, const void
       if (e == hipSuccess && nl)
         e = px::launch_usolve_split(p->dp, up, sp.d_items + sp.cptr[l], sp.cptr[l + 1] - sp.cptr[l],
                                     sp.d_long + sp.lptr[l], nl, tin, g, ldg, ty, Y, B, part, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  const int m = up ? 1 : 0;
+  const int mode = usolve_mode();
+  if (tin == px::E_I64 && ty == px::E_I64 && p->d_run_chunks[m] && B >= 5 && mode > 0) {
+    const std::vector<int64_t>& cp = p->run_cptr[m];
+    if (mode == 2 && flow) {
+      prof::Scope sc(prof::USOLVE, s);
+      const char* wv = std::getenv("POSETX_FLOW_WAIT");
+      const char* gv = std::getenv("POSETX_FLOW_GRID");
+      // measured: at n = 2^20, k = 64, B = 64 waiting on the chunks read from took 3.3 ms against
+      // 4.4 ms on the rows read; at n = 2^23, k = 32, B = 16 the rows took 9.1 ms against 12.0 ms
+      // (the row groups of a narrow tile proceed as soon as their own rows are ready)
+      int wait = px::col_width(B) == 64 ? px::kWaitDeps : px::kWaitRows;
+      if (wv && std::strcmp(wv, "rows") == 0) wait = px::kWaitRows;
+      if (wv && std::strcmp(wv, "level") == 0) wait = px::kWaitLevel;
+      if (wv && std::strcmp(wv, "deps") == 0) wait = px::kWaitDeps;
+      // 512 workgroups (two per compute unit) poll less than the full resident count: 3.3 against 3.5 ms
+      return px::launch_usolve_flow(p->dp, up, p->d_run_chunks[m], cp.back(), p->d_run_levn[m], p->d_run_dep_ptr[m],
+                                    p->d_run_deps[m], wait, g, ldg, Y, B, (int*)flow, flow_spin_limit(),
+                                    gv ? std::atoi(gv) : 512, s);
+    }
+    for (size_t l = 0; l + 1 < cp.size(); ++l) {
+      prof::Scope sc(prof::USOLVE, s);
+      hipError_t e = px::launch_usolve_runs(p->dp, up, p->d_run_chunks[m] + cp[l], cp[l + 1] - cp[l], g, ldg, Y, B, s);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -861,7 +1016,8 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   const bool refine = dtype == PX_F32;
   const int cw = px::col_width(B);
   const int64_t nt = p->ntiles[px::seg_index(cw)];
-  Layout L = layout(n, B, dtype, refine, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p), max_parts(p));
+  Layout L = layout(n, B, dtype, refine, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p), max_parts(p),
+                    dtype == PX_I64 ? flow_ints(p, B) : 0);
   if ((st = p->ws.ensure(L.total)) != PX_OK) return st;
   char* w = (char*)p->ws.p;
   hipStream_t s = (hipStream_t)stream;
@@ -875,7 +1031,7 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   uint64_t* dstats = (uint64_t*)(w + L.stats);
   std::vector<uint64_t> hstats(2 * B + 1);
   const bool stats0 = check_end && (!refine || max_refine == 0);
-  hipError_t e = solve_levels(p, up, T, g, ldg, T, w + L.y, B, w + L.part, s);
+  hipError_t e = solve_levels(p, up, T, g, ldg, T, w + L.y, B, w + L.part, w + L.flow, s);
   if (e == hipSuccess) e = run_chain_diff(p->dp, dir, T, w + L.y, B, T, f, ldf, false, stats0 ? dstats : nullptr, s);
   if (e != hipSuccess) return hip_status(e, "mobius launch");
   auto read_nonfinite = [&](bool& nonfinite) -> px_status {
@@ -928,7 +1084,7 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   while (it < max_refine) {
     const bool last_check = check_end && it + 1 == max_refine;
     e = residual();
-    if (e == hipSuccess) e = solve_levels(p, up, px::E_F64, r64, B, px::E_F32, w + L.y, B, w + L.part, s);
+    if (e == hipSuccess) e = solve_levels(p, up, px::E_F64, r64, B, px::E_F32, w + L.y, B, w + L.part, nullptr, s);
     if (e == hipSuccess)
       e = run_chain_diff(p->dp, dir, px::E_F32, w + L.y, B, px::E_F32, f, ldf, true,
                          check_steps || last_check ? dstats : nullptr, s);
@@ -1199,6 +1355,25 @@ static px_status finish_poset(px_poset* p, int device, px_poset** out) {
       if (e == hipSuccess) e = upload(&p->d_lev_node[dir], lnode.data(), lnode.size(), b);
       p->dp.lev_niv[dir] = p->d_lev_niv[dir];
       p->dp.lev_node[dir] = p->d_lev_node[dir];
+    }
+    // int64 level solves by runs (dense rows)
+    for (int m = 0; m < (p->has_up ? 2 : 1) && e == hipSuccess && !P.sparse; ++m) {
+      std::vector<int4> ev, chunks;
+      std::vector<int32_t> dep_ptr, deps;
+      if (!build_runs(P, m == 1, ev, chunks, p->run_cptr[m], dep_ptr, deps)) {
+        p->run_cptr[m].clear();
+        continue;
+      }
+      if (deps.empty()) deps.push_back(0);  // a valid pointer for posets without dependencies
+      p->run_events[m] = (int64_t)ev.size();
+      if (ev.empty()) ev.push_back(make_int4((int)n, (int)n, 0, 0));  // a valid pointer for posets without events
+      std::vector<int32_t> levn(p->run_cptr[m].begin(), p->run_cptr[m].end());  // first chunk of every level
+      e = upload(&p->d_run_ev[m], ev.data(), ev.size(), b);
+      if (e == hipSuccess) e = upload(&p->d_run_chunks[m], chunks.data(), chunks.size(), b);
+      if (e == hipSuccess) e = upload(&p->d_run_levn[m], levn.data(), levn.size(), b);
+      if (e == hipSuccess) e = upload(&p->d_run_dep_ptr[m], dep_ptr.data(), dep_ptr.size(), b);
+      if (e == hipSuccess) e = upload(&p->d_run_deps[m], deps.data(), deps.size(), b);
+      p->dp.seg[m].ev = p->d_run_ev[m];
     }
     if (e == hipSuccess) e = upload(&p->d_segoff, segoff.data(), segoff.size(), b);
     if (e == hipSuccess) {
@@ -1521,6 +1696,8 @@ px_status px_poset_info(const px_poset* p, px_info* o) {
   o->t_upload = p->t_upload;
   o->niv_sparse = P.sparse ? 1 : 0;
   o->niv_device_rounds = P.niv_rounds;
+  o->run_chunks = p->run_cptr[0].empty() ? 0 : p->run_cptr[0].back();
+  o->run_events = p->run_events[0];
   return PX_OK;
 }
 
@@ -1599,7 +1776,7 @@ px_status px_reserve(px_poset* p, int dtype, int64_t B) {
   const int64_t nt = p->ntiles[px::seg_index(px::col_width(B))];
   return p->ws.ensure(
       layout(p->prep.n, B, dtype, dtype == PX_F32, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p),
-             max_parts(p)).total);
+             max_parts(p), dtype == PX_I64 ? flow_ints(p, B) : 0).total);
 }
 
 px_status px_zeta(px_poset* p, int dtype, const void* f, int64_t ldf, void* g, int64_t ldg, int64_t B, void* stream) {

@@ -62,6 +62,22 @@ struct GatherSplit {
   int64_t nlongs = 0;
 };
 
+// Tables of the level solve by runs (int64, dense niv rows), per map:
+// ev[e] = {new row, old row, row, 0}: the entries j != own chain in which row
+// `row` differs from the row below it in its chain (row n, a zero row of Y,
+// for "no element"), grouped by row in ascending row order.  A level's chunks
+// are {first row, (level << 6) | rows, first event, end event}: at most
+// kSegRows consecutive rows of one chain, all in that level, and the events of
+// all but the first of them.
+constexpr int kSegRows = 32;
+// Events per chunk (beyond the second row): a chunk's row groups take its
+// events in batches of 16, one batch at a time, so bursts are split over
+// chunks instead.
+constexpr int kSegEvents = 64;
+struct SegTables {
+  const int4* ev = nullptr;
+};
+
 // Static description of one poset (or a batch of posets) on the device.
 struct DevPoset {
   int32_t n = 0, k = 0;           // for a batch: total rows; k = 0 (per-poset k)
@@ -88,6 +104,7 @@ struct DevPoset {
   // of the rows in level order (nullable; single posets with k <= 64)
   const int32_t* lev_niv[2] = {nullptr, nullptr};
   const int32_t* lev_node[2] = {nullptr, nullptr};
+  SegTables seg[2];  // level solve by runs (nullable)
   // single-pass scan: tiles in scan-position-major order, [0] prefix / [1] suffix,
   // one table per tile height (as segoff)
   const int32_t* scan_order[2][7] = {{nullptr}};
@@ -170,6 +187,29 @@ hipError_t launch_usolve_begin(const DevPoset& d, ElemType ty, void* Y, int64_t 
 hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_rows, int64_t i0, int64_t cnt,
                                ElemType tin, const void* g, int64_t ldg, ElemType ty, void* Y,
                                int64_t B, hipStream_t s);
+
+// The whole int64 solve by runs in one persistent launch (plus a clear and a
+// fallback kernel; see k_usolve_flow): the chunks of every level in level
+// order (nchunks), lev_off[l] the first chunk of level l (levels + 1 entries),
+// and the chunks each chunk reads from: deps[dep_ptr[c] .. dep_ptr[c + 1]).
+// wait: what a chunk waits for before it reads Y:
+//   kWaitRows   a ready flag of every row it reads;
+//   kWaitLevel  every chunk of the level below (one done flag per chunk);
+//   kWaitDeps   every chunk it reads from (one done flag per chunk).
+// sync: 1 + ceil(B / col_width(B)) * (n + 1) ints of scratch (chunk flags:
+// nchunks instead of n + 1), cleared by the launch.  spin_limit bounds each
+// wait (polls); a wait that gives up makes the fallback recompute the solve in
+// one workgroup.  max_grid > 0 caps the workgroups.  B >= 5.
+constexpr int kWaitRows = 0, kWaitLevel = 1, kWaitDeps = 2;
+hipError_t launch_usolve_flow(const DevPoset& d, bool up, const int4* chunks, int64_t nchunks, const int32_t* lev_off,
+                              const int32_t* dep_ptr, const int32_t* deps, int wait, const void* g, int64_t ldg, void* Y,
+                              int64_t B, int* sync, int spin_limit, int max_grid, hipStream_t s);
+
+// One level of the int64 solve by runs (dense niv rows, B >= 5): the chunks
+// of that level (see SegTables).
+// g and Y are int64; the result equals launch_usolve_level's bit for bit.
+hipError_t launch_usolve_runs(const DevPoset& d, bool up, const int4* chunks, int64_t nchunks, const void* g,
+                              int64_t ldg, void* Y, int64_t B, hipStream_t s);
 
 // The long rows of a level of a sparse solve, split into chunks: items =
 // {row, first entry, end entry, w} (nitems, in any order; w: the chunk's slot

@@ -19,6 +19,7 @@
 // MFMA.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels.h"
@@ -1510,6 +1511,437 @@ __global__ __launch_bounds__(WG) void k_usolve_uni(DevPoset d, const int32_t* __
   if (colok) (Y + (int64_t)r * B)[col] = (TY)acc;
 }
 
+// Level solve by runs (int64).  The rows of one chain that share a level are
+// consecutive, and along them S(r) = Σ_{j != own} Y[niv_j(r)] changes only at
+// the entries that differ from the row below: S(r) - S(r - 1) = Σ over those
+// entries of Y[new] - Y[old].  Both rows of every such pair are entries of r
+// or of r - 1, so they lie at lower levels and are final.  A workgroup takes a
+// chunk {first row, (level << 6) | rows, first event, end event} of at most
+// kSegRows consecutive rows of one chain in one level (see SegTables):
+//   1. its row groups split the full sum S(first row) (entries rg, rg + RG, ...)
+//      and the chunk's change events, adding each into its row's slot in LDS;
+//   2. an inclusive scan of the slots over the rows gives every S(r), and
+//      Y[r] = g[node(r)] - S(r).
+// Wrapping 64-bit arithmetic is exact in any order, so the result equals the
+// row-by-row solve bit for bit.  Loads of one batch are all in flight together.
+template <typename TY, int CW>
+__global__ __launch_bounds__(WG) void k_usolve_seg(DevPoset d, const int32_t* __restrict__ nv,
+                                                   const int4* __restrict__ chunks, const int4* __restrict__ ev,
+                                                   const TY* __restrict__ g, int64_t ldg, TY* __restrict__ Y,
+                                                   int64_t B) {
+  using W = typename Wide<TY>::W;
+  constexpr int RG = WG / CW;       // row groups (4 .. 32)
+  constexpr int SR = kSegRows / RG; // rows per row group in the scan (8 .. 1)
+  static_assert(SR >= 1 && SR * RG == kSegRows, "kSegRows must be a multiple of the row groups");
+  __shared__ W s_d[kSegRows][CW];
+  __shared__ W s_t[RG][CW];
+  auto uni = [](int v) { return CW == 64 ? __builtin_amdgcn_readfirstlane(v) : v; };
+  const int lane = threadIdx.x % CW;
+  const int rg = uni((int)(threadIdx.x / CW));
+  const int64_t col = (int64_t)blockIdx.y * CW + lane;
+  const bool colok = col < B;
+  const int64_t colc = colok ? col : 0;
+  const int4 c = chunks[blockIdx.x];
+  const int r0 = uni(c.x), nrows = uni(c.y & 63), e0 = uni(c.z), e1 = uni(c.w);
+  const int k = d.k;
+  const int64_t zr = d.n;
+#pragma unroll
+  for (int i = 0; i < SR; ++i) s_d[rg * SR + i][lane] = W(0);
+  __syncthreads();
+  // g of this row group's scan rows
+  W gv[SR];
+#pragma unroll
+  for (int i = 0; i < SR; ++i) {
+    const int ri = rg * SR + i;
+    const int node = uni(d.node_of_row[r0 + (ri < nrows ? ri : 0)]);
+    gv[i] = (W)g[(int64_t)node * ldg + colc];
+  }
+  // the first row's full sum, entries rg, rg + RG, ... (own entry and -1 read the zero row)
+  W part = W(0);
+  const int32_t* __restrict__ nr0 = nv + (int64_t)r0 * k;
+  for (int jb = rg; jb < k; jb += RG * 16) {
+    int32_t t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int j = jb + u * RG;
+      t[u] = j < k ? uni(nr0[j]) : -1;
+    }
+    TY v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = Y[(t[u] >= 0 && t[u] != r0 ? (int64_t)t[u] : zr) * B + colc];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) part += (W)v[u];
+  }
+  // the change events of the later rows, e0 + rg, e0 + rg + RG, ...
+  for (int eb = e0 + rg; eb < e1; eb += RG * 16) {
+    int4 q[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = eb + u * RG;
+      q[u] = e < e1 ? ev[e] : make_int4((int)zr, (int)zr, r0, 0);
+      q[u].x = uni(q[u].x);
+      q[u].y = uni(q[u].y);
+      q[u].z = uni(q[u].z);
+    }
+    TY vn[16], vo[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      vn[u] = Y[(int64_t)q[u].x * B + colc];
+      vo[u] = Y[(int64_t)q[u].y * B + colc];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (eb + u * RG < e1) atomicAdd(&s_d[q[u].z - r0][lane], (W)vn[u] - (W)vo[u]);
+  }
+  atomicAdd(&s_d[0][lane], part);
+  __syncthreads();
+  W sv[SR];
+  W run = W(0);
+#pragma unroll
+  for (int i = 0; i < SR; ++i) {
+    run += s_d[rg * SR + i][lane];
+    sv[i] = run;
+  }
+  s_t[rg][lane] = run;
+  __syncthreads();
+  W base = W(0);
+  for (int q = 0; q < rg; ++q) base += s_t[q][lane];
+#pragma unroll
+  for (int i = 0; i < SR; ++i) {
+    const int ri = rg * SR + i;
+    if (ri < nrows && colok) Y[(int64_t)(r0 + ri) * B + col] = (TY)(gv[i] - (base + sv[i]));
+  }
+}
+
+// Relaxed device-scope loads and stores: coherent across the per-XCD L2s
+// without cache maintenance (as the single-pass scan's tile states).
+template <typename T>
+__device__ inline T ld_dev(const T* p) {
+  static_assert(sizeof(T) == 8, "64-bit elements");
+  const uint64_t w = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  T v;
+  __builtin_memcpy(&v, &w, 8);
+  return v;
+}
+template <typename T>
+__device__ inline void st_dev(T* p, T v) {
+  static_assert(sizeof(T) == 8, "64-bit elements");
+  uint64_t w;
+  __builtin_memcpy(&w, &v, 8);
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Longest wait of the persistent solve, in ticks of the 100 MHz real-time
+// counter (2 s), whatever the polls cost.
+constexpr uint64_t kFlowWaitTicks = 200000000ull;
+
+// Waits until the flags fl[idx] of every index a lane holds (-1 = none) are
+// set, all of them polled together in each round; exits are uniform over the
+// active lanes.  Returns false when it gives up: after spin_limit polls, after
+// kFlowWaitTicks, or when the error word is set.
+template <int M>
+__device__ inline bool await_idx(const int* __restrict__ fl, int (&idx)[M], const int* __restrict__ err,
+                                 int spin_limit) {
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  for (int spin = 0;; ++spin) {
+    int v[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+      v[m] = idx[m] >= 0 ? __hip_atomic_load(fl + idx[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 1;
+    bool pend = false;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      if (v[m] != 0) idx[m] = -1;
+      pend = pend || idx[m] >= 0;
+    }
+    if (!__any(pend)) return true;
+    if (spin >= spin_limit) return false;
+    if ((spin & 15) == 15) {
+      if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0)
+        return false;
+      if (__builtin_amdgcn_s_memrealtime() - t0 > kFlowWaitTicks) return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+// The ready flags of up to N rows (row-group-uniform, -1 = none), lane l of a
+// row group polling rows l, l + CW, ...
+template <int CW, int N>
+__device__ inline bool await_rows(const int* __restrict__ fl, const int32_t (&rows)[N], int lane,
+                                  const int* __restrict__ err, int spin_limit) {
+  constexpr int M = (N + CW - 1) / CW;
+  int mine[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    int r = -1;
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+      if (u == lane + m * CW) r = rows[u];
+    mine[m] = r;
+  }
+  return await_idx<M>(fl, mine, err, spin_limit);
+}
+
+// One wavefront (all lanes active): the flags fl[a .. b), 512 at a time.
+__device__ inline bool await_range(const int* __restrict__ fl, int a, int b, const int* __restrict__ err,
+                                   int spin_limit) {
+  const int lane = (int)(threadIdx.x & 63);
+  for (int w = a; w < b; w += 512) {
+    int idx[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) idx[m] = w + lane + 64 * m < b ? w + lane + 64 * m : -1;
+    if (!await_idx<8>(fl, idx, err, spin_limit)) return false;
+  }
+  return true;
+}
+
+// The int64 solve by runs in one persistent launch: a dataflow over the chunks
+// instead of one launch per level.  Workgroup b takes the (chunk, column
+// block) items b, b + G, b + 2G, ... of the level-ordered list, G workgroups
+// being at most what the device holds resident at once.  Before it reads a row
+// of Y a row group waits for that row's ready flag (one per row and column
+// block), set by the chunk that wrote it (LEVEL: instead one wavefront waits
+// for the done flags of every chunk of the level below, which are contiguous;
+// those chunks waited for their own level below, so all lower levels are then
+// complete).  A chunk reads only rows of lower levels, which come earlier in
+// the list; a workgroup takes its items in order, so the unfinished item of
+// lowest index always has every row it reads finished, and with all
+// workgroups resident every wait ends.  Everything that does not depend on Y
+// (the chunk, g, the first row's entries, the events) is loaded before the
+// waits.
+//
+// Y and the flags travel as relaxed device-scope stores and loads, which are
+// coherent across the per-XCD L2s (as the single-pass scan's tile states); a
+// row group sets its rows' flags after its wave's Y stores have completed
+// (vmcnt 0).  No read-modify-write atomics cross workgroups.
+//
+// Waits are bounded (spin_limit polls, and 2 s of real time).  A workgroup
+// that gives up (also when some workgroups could not be resident) stores the
+// error word and stops, and so does every waiter that sees it; then
+// k_usolve_flow_fix recomputes the whole solve in one workgroup.  flags: ncb * (n + 1) ints and err, cleared
+// before the launch.
+template <typename TY, int CW, int WAIT>
+__global__ __launch_bounds__(WG) void k_usolve_flow(DevPoset d, const int32_t* __restrict__ nv,
+                                                    const int4* __restrict__ chunks, int nchunks,
+                                                    const int32_t* __restrict__ lev_off,
+                                                    const int32_t* __restrict__ dep_ptr,
+                                                    const int32_t* __restrict__ deps,
+                                                    const int4* __restrict__ ev, const TY* __restrict__ g,
+                                                    int64_t ldg, TY* __restrict__ Y, int64_t B,
+                                                    int* __restrict__ flags, int* __restrict__ err, int spin_limit) {
+  using W = typename Wide<TY>::W;
+  constexpr int RG = WG / CW;
+  constexpr int SR = kSegRows / RG;
+  constexpr bool LEVEL = WAIT != kWaitRows;  // chunk done flags (level or dependency waits)
+  static_assert(SR >= 1 && SR * RG == kSegRows, "kSegRows must be a multiple of the row groups");
+  __shared__ W s_d[kSegRows][CW];
+  __shared__ W s_t[RG][CW];
+  __shared__ int s_bad;
+  auto uni = [](int v) { return CW == 64 ? __builtin_amdgcn_readfirstlane(v) : v; };
+  const int lane = threadIdx.x % CW;
+  const int rg = uni((int)(threadIdx.x / CW));
+  const int ncb = (int)((B + CW - 1) / CW);
+  const int total = nchunks * ncb;
+  const int k = d.k;
+  const int zr = d.n;
+  for (int tk = blockIdx.x; tk < total; tk += gridDim.x) {
+    const int ci = tk / ncb, cb = tk - ci * ncb;
+    // LEVEL: one done flag per chunk; otherwise one ready flag per row
+    int* const fl = flags + (int64_t)cb * (LEVEL ? nchunks : zr + 1);
+    const int64_t col = (int64_t)cb * CW + lane;
+    const bool colok = col < B;
+    const int64_t colc = colok ? col : 0;
+    const int4 c = chunks[ci];
+    const int r0 = uni(c.x), nrows = uni(c.y & 63), e0 = uni(c.z), e1 = uni(c.w);
+#pragma unroll
+    for (int i = 0; i < SR; ++i) s_d[rg * SR + i][lane] = W(0);
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    W gv[SR];
+#pragma unroll
+    for (int i = 0; i < SR; ++i) {
+      const int ri = rg * SR + i;
+      const int node = uni(d.node_of_row[r0 + (ri < nrows ? ri : 0)]);
+      gv[i] = (W)g[(int64_t)node * ldg + colc];
+    }
+    // the first batches of the first row's entries (rg, rg + RG, ...; own entry
+    // and -1 skipped) and of the events (e0 + rg, e0 + rg + RG, ...), loaded
+    // before the wait like g
+    const int32_t* __restrict__ nr0 = nv + (int64_t)r0 * k;
+    int32_t t[16], a[16], b[16], rr[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int j = rg + u * RG;
+      const int tt = j < k ? uni(nr0[j]) : -1;
+      t[u] = tt != r0 ? tt : -1;
+    }
+    auto load_events = [&](int eb) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = eb + u * RG;
+        const int4 q = e < e1 ? ev[e] : make_int4(zr, zr, r0, 0);
+        a[u] = uni(q.x) != zr ? uni(q.x) : -1;
+        b[u] = uni(q.y) != zr ? uni(q.y) : -1;
+        rr[u] = uni(q.z);
+      }
+    };
+    load_events(e0 + rg);
+    // WAIT == kWaitDeps: the chunks this one reads from, up to 128 loaded now
+    int dp0 = 0, dp1 = 0, dv[2] = {-1, -1};
+    const int wl = (int)(threadIdx.x & 63);
+    if (WAIT == kWaitDeps && threadIdx.x < 64) {
+      dp0 = __builtin_amdgcn_readfirstlane(dep_ptr[ci]);
+      dp1 = __builtin_amdgcn_readfirstlane(dep_ptr[ci + 1]);
+#pragma unroll
+      for (int m = 0; m < 2; ++m) dv[m] = dp0 + wl + 64 * m < dp1 ? deps[dp0 + wl + 64 * m] : -1;
+    }
+    bool ok = true;
+    if (LEVEL) {
+      if (WAIT == kWaitLevel) {  // every chunk of the level below (and so every lower level) is done
+        const int lev = uni(c.y >> 6);
+        if (lev > 0 && threadIdx.x < 64)
+          if (!await_range(fl, lev_off[lev - 1], lev_off[lev], err, spin_limit)) s_bad = 1;
+      } else if (threadIdx.x < 64) {  // every chunk holding a row this one reads is done
+        bool good = await_idx<2>(fl, dv, err, spin_limit);
+        for (int w = dp0 + 128; w < dp1 && good; w += 128) {
+          int more[2];
+#pragma unroll
+          for (int m = 0; m < 2; ++m) more[m] = w + wl + 64 * m < dp1 ? deps[w + wl + 64 * m] : -1;
+          good = await_idx<2>(fl, more, err, spin_limit);
+        }
+        if (!good) s_bad = 1;
+      }
+      __syncthreads();
+      if (__builtin_amdgcn_readfirstlane(s_bad)) {
+        if (threadIdx.x == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    } else {
+      ok = await_rows<CW, 16>(fl, t, lane, err, spin_limit) && await_rows<CW, 16>(fl, a, lane, err, spin_limit) &&
+           await_rows<CW, 16>(fl, b, lane, err, spin_limit);
+    }
+    W part = W(0);
+    if (ok) {  // the first batches' rows of Y, all in flight together
+      TY v[16], vn[16], vo[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        v[u] = ld_dev(&Y[(int64_t)(t[u] >= 0 ? t[u] : zr) * B + colc]);
+        vn[u] = ld_dev(&Y[(int64_t)(a[u] >= 0 ? a[u] : zr) * B + colc]);
+        vo[u] = ld_dev(&Y[(int64_t)(b[u] >= 0 ? b[u] : zr) * B + colc]);
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) part += (W)v[u];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (e0 + rg + u * RG < e1) atomicAdd(&s_d[rr[u] - r0][lane], (W)vn[u] - (W)vo[u]);
+    }
+    // later batches (k > 16 * RG, or more than 16 events per row group)
+    for (int jb = rg + 16 * RG; jb < k && ok; jb += RG * 16) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int j = jb + u * RG;
+        const int tt = j < k ? uni(nr0[j]) : -1;
+        t[u] = tt != r0 ? tt : -1;
+      }
+      if (!LEVEL) ok = await_rows<CW, 16>(fl, t, lane, err, spin_limit);
+      if (!ok) break;
+      TY v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = ld_dev(&Y[(int64_t)(t[u] >= 0 ? t[u] : zr) * B + colc]);
+#pragma unroll
+      for (int u = 0; u < 16; ++u) part += (W)v[u];
+    }
+    for (int eb = e0 + rg + 16 * RG; eb < e1 && ok; eb += RG * 16) {
+      load_events(eb);
+      if (!LEVEL)
+        ok = await_rows<CW, 16>(fl, a, lane, err, spin_limit) && await_rows<CW, 16>(fl, b, lane, err, spin_limit);
+      if (!ok) break;
+      TY vn[16], vo[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        vn[u] = ld_dev(&Y[(int64_t)(a[u] >= 0 ? a[u] : zr) * B + colc]);
+        vo[u] = ld_dev(&Y[(int64_t)(b[u] >= 0 ? b[u] : zr) * B + colc]);
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (eb + u * RG < e1) atomicAdd(&s_d[rr[u] - r0][lane], (W)vn[u] - (W)vo[u]);
+    }
+    if (ok)
+      atomicAdd(&s_d[0][lane], part);
+    else
+      s_bad = 1;
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_bad)) {
+      if (threadIdx.x == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    W sv[SR];
+    W run = W(0);
+#pragma unroll
+    for (int i = 0; i < SR; ++i) {
+      run += s_d[rg * SR + i][lane];
+      sv[i] = run;
+    }
+    s_t[rg][lane] = run;
+    __syncthreads();
+    W base = W(0);
+    for (int z = 0; z < rg; ++z) base += s_t[z][lane];
+#pragma unroll
+    for (int i = 0; i < SR; ++i) {
+      const int ri = rg * SR + i;
+      if (ri < nrows && colok) st_dev(&Y[(int64_t)(r0 + ri) * B + col], (TY)(gv[i] - (base + sv[i])));
+    }
+    wait_vmem();
+    if (LEVEL) {
+      __syncthreads();  // every wave's Y stores have completed
+      if (threadIdx.x == 0) __hip_atomic_store(&fl[ci], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < SR; ++i) {
+        const int ri = rg * SR + i;
+        if (ri < nrows) __hip_atomic_store(&fl[r0 + ri], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+}
+
+// Fallback of k_usolve_flow: when its error word is set, one workgroup solves
+// again from scratch, chunk after chunk in level order with a barrier between
+// levels, every row by its full sum; otherwise it returns at once.
+template <typename TY>
+__global__ __launch_bounds__(WG) void k_usolve_flow_fix(DevPoset d, const int32_t* __restrict__ nv,
+                                                        const int4* __restrict__ chunks, int nchunks,
+                                                        const TY* __restrict__ g, int64_t ldg, TY* __restrict__ Y,
+                                                        int64_t B, const int* __restrict__ err) {
+  using W = typename Wide<TY>::W;
+  if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0) return;
+  const int k = d.k;
+  const int64_t zr = d.n;
+  const int64_t nel = (int64_t)kSegRows * B;
+  int lev = -1;
+  for (int ci = 0; ci < nchunks; ++ci) {
+    const int4 c = chunks[ci];
+    if ((c.y >> 6) != lev) {
+      __syncthreads();
+      lev = c.y >> 6;
+    }
+    const int nrows = c.y & 63;
+    for (int64_t i = threadIdx.x; i < nel; i += WG) {
+      const int ri = (int)(i / B);
+      const int64_t col = i - (int64_t)ri * B;
+      if (ri >= nrows) continue;
+      const int64_t r = (int64_t)c.x + ri;
+      W acc = (W)g[(int64_t)d.node_of_row[r] * ldg + col];
+      for (int j = 0; j < k; ++j) {
+        const int tt = nv[r * k + j];
+        if (tt >= 0 && tt != r) acc -= (W)ld_dev(&Y[(int64_t)tt * B + col]);
+      }
+      st_dev(&Y[r * B + col], (TY)acc);
+    }
+  }
+}
+
 __global__ void k_zero_bytes(uint32_t* p, int64_t words) {
   const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
   if (i < words) p[i] = 0u;
@@ -2055,6 +2487,109 @@ hipError_t launch_usolve_split(const DevPoset& d, bool up, const int4* items, in
   if (tin == E_F64 && ty == E_F64)
     return usolve_split_typed<double, double>(d, er, items, nitems, longs, nlongs, g, ldg, Y, B, part, s);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_usolve_runs(const DevPoset& d, bool up, const int4* chunks, int64_t nchunks, const void* g,
+                              int64_t ldg, void* Y, int64_t B, hipStream_t s) {
+  if (nchunks == 0) return hipSuccess;
+  const int32_t* nv = up ? d.niv_up : d.niv;
+  const SegTables& t = d.seg[up ? 1 : 0];
+  if (!nv || !t.ev || nchunks > INT32_MAX) return hipErrorInvalidValue;
+  const int cw = col_width(B);
+  const dim3 gr((unsigned)nchunks, (unsigned)((B + cw - 1) / cw));
+  const int64_t* gi = (const int64_t*)g;
+  int64_t* Yi = (int64_t*)Y;
+  switch (cw) {
+    case 64: hipLaunchKernelGGL((k_usolve_seg<int64_t, 64>), gr, dim3(WG), 0, s, d, nv, chunks, t.ev, gi, ldg, Yi, B); break;
+    case 32: hipLaunchKernelGGL((k_usolve_seg<int64_t, 32>), gr, dim3(WG), 0, s, d, nv, chunks, t.ev, gi, ldg, Yi, B); break;
+    case 16: hipLaunchKernelGGL((k_usolve_seg<int64_t, 16>), gr, dim3(WG), 0, s, d, nv, chunks, t.ev, gi, ldg, Yi, B); break;
+    case 8: hipLaunchKernelGGL((k_usolve_seg<int64_t, 8>), gr, dim3(WG), 0, s, d, nv, chunks, t.ev, gi, ldg, Yi, B); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+namespace {
+// Workgroups of k_usolve_flow<TY, CW> the device holds resident at once.
+template <int CW, int WAIT>
+int flow_resident() {
+  static int cached[64] = {0};  // per device
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cached[dev] > 0) return cached[dev];
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_usolve_flow<int64_t, CW, WAIT>, WG, 0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  cached[dev] = std::max(1, per_cu) * std::max(1, cus);
+  return cached[dev];
+}
+
+template <int CW, int WAIT>
+hipError_t flow_typed(const DevPoset& d, const int32_t* nv, const int4* chunks, int nchunks, const int32_t* lev_off,
+                      const int32_t* dep_ptr, const int32_t* deps, const int4* ev, const int64_t* g, int64_t ldg,
+                      int64_t* Y, int64_t B, int* flags, int* err, int spin_limit, int64_t total, int max_grid,
+                      hipStream_t s) {
+  const int res = flow_resident<CW, WAIT>();
+  if (res <= 0) return hipErrorInvalidValue;
+  const unsigned grid = (unsigned)std::min<int64_t>(std::min<int64_t>(total, res), max_grid > 0 ? max_grid : res);
+  hipLaunchKernelGGL((k_usolve_flow<int64_t, CW, WAIT>), dim3(grid), dim3(WG), 0, s, d, nv, chunks, nchunks, lev_off,
+                     dep_ptr, deps, ev, g, ldg, Y, B, flags, err, spin_limit);
+  return hipGetLastError();
+}
+
+template <int CW>
+hipError_t flow_wait(int wait, const DevPoset& d, const int32_t* nv, const int4* chunks, int nchunks,
+                     const int32_t* lev_off, const int32_t* dep_ptr, const int32_t* deps, const int4* ev,
+                     const int64_t* g, int64_t ldg, int64_t* Y, int64_t B, int* flags, int* err, int spin_limit,
+                     int64_t total, int max_grid, hipStream_t s) {
+  switch (wait) {
+    case kWaitRows:
+      return flow_typed<CW, kWaitRows>(d, nv, chunks, nchunks, lev_off, dep_ptr, deps, ev, g, ldg, Y, B, flags, err,
+                                       spin_limit, total, max_grid, s);
+    case kWaitLevel:
+      return flow_typed<CW, kWaitLevel>(d, nv, chunks, nchunks, lev_off, dep_ptr, deps, ev, g, ldg, Y, B, flags, err,
+                                        spin_limit, total, max_grid, s);
+    default:
+      return flow_typed<CW, kWaitDeps>(d, nv, chunks, nchunks, lev_off, dep_ptr, deps, ev, g, ldg, Y, B, flags, err,
+                                       spin_limit, total, max_grid, s);
+  }
+}
+}  // namespace
+
+hipError_t launch_usolve_flow(const DevPoset& d, bool up, const int4* chunks, int64_t nchunks, const int32_t* lev_off,
+                              const int32_t* dep_ptr, const int32_t* deps, int wait, const void* g, int64_t ldg, void* Y,
+                              int64_t B, int* sync, int spin_limit, int max_grid, hipStream_t s) {
+  if (nchunks == 0) return hipSuccess;
+  const int32_t* nv = up ? d.niv_up : d.niv;
+  const SegTables& t = d.seg[up ? 1 : 0];
+  const int cw = col_width(B);
+  const int64_t ncb = (B + cw - 1) / cw;
+  if (!nv || !t.ev || !lev_off || (wait == kWaitDeps && (!dep_ptr || !deps)) || nchunks * ncb >= INT32_MAX ||
+      (int64_t)d.n + 1 >= INT32_MAX || cw < 8 || wait < kWaitRows || wait > kWaitDeps)
+    return hipErrorInvalidValue;
+  int* err = sync;
+  int* flags = sync + 1;
+  const int64_t nsync = 1 + ncb * (wait != kWaitRows ? nchunks : (int64_t)d.n + 1);
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nsync + WG - 1) / WG)), dim3(WG), 0, s, sync, nsync, 0);
+  const int nc = (int)nchunks;
+  const int64_t* gi = (const int64_t*)g;
+  int64_t* Yi = (int64_t*)Y;
+  const int64_t tot = nchunks * ncb;
+  hipError_t e;
+  switch (cw) {
+    case 64: e = flow_wait<64>(wait, d, nv, chunks, nc, lev_off, dep_ptr, deps, t.ev, gi, ldg, Yi, B, flags, err, spin_limit, tot, max_grid, s); break;
+    case 32: e = flow_wait<32>(wait, d, nv, chunks, nc, lev_off, dep_ptr, deps, t.ev, gi, ldg, Yi, B, flags, err, spin_limit, tot, max_grid, s); break;
+    case 16: e = flow_wait<16>(wait, d, nv, chunks, nc, lev_off, dep_ptr, deps, t.ev, gi, ldg, Yi, B, flags, err, spin_limit, tot, max_grid, s); break;
+    case 8: e = flow_wait<8>(wait, d, nv, chunks, nc, lev_off, dep_ptr, deps, t.ev, gi, ldg, Yi, B, flags, err, spin_limit, tot, max_grid, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_usolve_flow_fix<int64_t>), dim3(1), dim3(WG), 0, s, d, nv, chunks, nc, gi, ldg, Yi, B,
+                     (const int*)err);
+  return hipGetLastError();
 }
 
 hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_rows, int64_t i0, int64_t cnt,

@@ -408,6 +408,54 @@ def test_mobius_shapes_exact_and_backward_stable(px, shape, B):
     assert np.array_equal(H(px.mobius(P, px.zeta(P, T(f)))), f)
 
 
+@pytest.mark.parametrize("B", [5, 8, 16, 32, 64, 130])
+@pytest.mark.parametrize("mirsky", [False, True])
+def test_int64_solve_by_runs_matches_oracle_and_direct(px, B, mirsky, monkeypatch):
+    """The int64 level solve by runs (chunks of up to 32 consecutive rows of one
+    chain in one level: a full sum at the chunk's first row, change events after
+    it, a scan in LDS; all levels in one persistent launch whose chunks wait for
+    the chunks they read from) against the substitution oracle and, bit for bit,
+    against the same launch waiting on the rows it reads or on the whole level
+    below (POSETX_FLOW_WAIT=rows / level), the chunks launched level by level
+    and the row-by-row solve (POSETX_USOLVE=levels / direct).  Chains of 250 elements give
+    long runs; the Mirsky schedule gives runs of one row; B covers every column
+    tile width of the kernel and two column blocks."""
+    p = W.chain_poset(2000, 8, 3, seed=90)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = build(px, p, flags=px.PX_BUILD_LEVELS_MIRSKY if mirsky else 0)
+    assert P.info["run_chunks"] > 0
+    g = W.functions(p.n, B, "int", seed=91, lo=-(2 ** 40), hi=2 ** 40)
+    runs = H(px.mobius(P, T(g))), H(px.mobius_adjoint(P, T(g)))
+    assert np.array_equal(runs[0], O.mobius_by_substitution(R, g))
+    assert np.array_equal(runs[1], O.mobius_adjoint_by_substitution(R, g))
+    # waits on the rows read instead of the level below; one launch per level; row by row
+    for var, mode in (("POSETX_FLOW_WAIT", "rows"), ("POSETX_FLOW_WAIT", "level"), ("POSETX_USOLVE", "levels"),
+                      ("POSETX_USOLVE", "direct")):
+        monkeypatch.setenv(var, mode)
+        other = H(px.mobius(P, T(g))), H(px.mobius_adjoint(P, T(g)))
+        assert np.array_equal(runs[0], other[0]) and np.array_equal(runs[1], other[1]), mode
+
+
+@pytest.mark.parametrize("wait", ["deps", "level", "rows"])
+@pytest.mark.parametrize("B", [8, 64])
+def test_int64_persistent_solve_fallback(px, B, wait, monkeypatch):
+    """With a spin limit of 0 polls every wait of the persistent solve gives up at
+    once: the error word is set and the one-workgroup fallback solves again, so
+    the result is still exact (the give-up path forced from the host; every
+    kernel exits normally)."""
+    p = W.chain_poset(1500, 6, 3, seed=92)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = build(px, p)
+    assert P.info["run_chunks"] > 0
+    g = W.functions(p.n, B, "int", seed=93, lo=-(2 ** 40), hi=2 ** 40)
+    monkeypatch.setenv("POSETX_FLOW_SPIN", "0")
+    monkeypatch.setenv("POSETX_FLOW_WAIT", wait)
+    assert np.array_equal(H(px.mobius(P, T(g))), O.mobius_by_substitution(R, g))
+    assert np.array_equal(H(px.mobius_adjoint(P, T(g))), O.mobius_adjoint_by_substitution(R, g))
+    f = W.functions(p.n, B, "int", seed=94, lo=-100, hi=100)
+    assert np.array_equal(H(px.mobius(P, px.zeta(P, T(f)))), f)
+
+
 # ------------------------------------------------------- full-size, sampled
 @pytest.fixture(scope="module")
 def cfg1():
