@@ -1,7 +1,7 @@
 """Benchmark of the fast zeta transform on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--legs none|default|all|sparse|batched]
+                    [--legs none|default|all|sparse|batched|chains]
 
 Workload (the headline configuration): a random-height poset with
 n = 2^20 elements, k = 64 planted chains of 16,384 elements, 3 cross edges
@@ -405,6 +405,35 @@ def leg_large(px, dev, steps):
             "f32_roundtrip_rel_err": err, "f32_refine_report": rep}
 
 
+def leg_min_chains(px, dev, steps, n_log2=18, deg=4):
+    """The same Erdős–Rényi DAG with a minimum chain decomposition (PX_BUILD_MIN_CHAINS, as many
+    chains as the width) against the matching's path cover: k, nnz(N), the decomposition time and
+    the float32 zeta / int64 Möbius times at B = 64."""
+    import torch
+    import workloads as W
+    sync = torch.cuda.synchronize
+    q = W.er_dag(1 << n_log2, deg, seed=1)
+    out = {"workload": f"Erdős–Rényi DAG, n={q.n}, average degree {deg}, B=64"}
+    for name, flags in (("path_cover", 0), ("min_chains", px.PX_BUILD_MIN_CHAINS)):
+        t0 = time.perf_counter()
+        P = px.poset_build(q.n, q.indptr, q.indices, None, None, flags=flags | px.PX_BUILD_NO_ADJOINT, device=0)
+        t_build = time.perf_counter() - t0
+        f = torch.from_numpy(W.functions(q.n, 64, "normal", seed=5)).to(dev)
+        g = torch.empty_like(f)
+        P.reserve(torch.float32, 64)
+        tz = _time(lambda: px.zeta(P, f, out=g), steps, sync)
+        fi = torch.from_numpy(W.functions(q.n, 64, "int", seed=6, lo=-1000, hi=1000)).to(dev)
+        gi = px.zeta(P, fi)
+        tm = _time(lambda: px.mobius(P, gi), max(2, steps // 4), sync)
+        out[name] = {"k": P.info["k"], "nnz_niv": P.info["nnz_niv"], "chains_s": round(P.info["t_chains"], 2),
+                     "build_s": round(t_build, 2), "zeta_f32_ms": round(tz * 1e3, 4),
+                     "mobius_int64_ms": round(tm * 1e3, 4),
+                     "int64_roundtrip_exact": bool(torch.equal(px.mobius(P, gi), fi))}
+        del P, f, g, fi, gi
+        torch.cuda.empty_cache()
+    return out
+
+
 def leg_er_sparse(px, dev, steps, n_log2=18, deg=4, refine=True):
     """The workload class of the paper's experiments (§5): an Erdős–Rényi DAG of average degree
     `deg`, n = 2^n_log2, chains from the maximum matching.  At n = 2^18, degree 4 its width (about
@@ -471,7 +500,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
-    ap.add_argument("--legs", default="default", choices=["none", "default", "all", "sparse", "batched"],
+    ap.add_argument("--legs", default="default", choices=["none", "default", "all", "sparse", "batched", "chains"],
                     help="extra measurements of the other hot-path rows (all: also the batched, n=2^23 and "
                          "Erdős–Rényi configs; sparse / batched: that config alone)")
     ap.add_argument("--copy-ref", action="store_true",
@@ -620,6 +649,9 @@ def main():
     }
     if args.legs == "sparse":
         out["legs"] = {"er_sparse": leg_er_sparse(px, dev, max(2, args.steps // 4))}
+    elif args.legs == "chains":
+        out["legs"] = {"min_chains_n64k": leg_min_chains(px, dev, max(2, args.steps // 4), n_log2=16),
+                       "min_chains_n256k": leg_min_chains(px, dev, max(2, args.steps // 4), n_log2=18)}
     elif args.legs == "batched":
         del P
         out["legs"] = {"batched": leg_batched(px, dev, args.steps)}
@@ -641,6 +673,8 @@ def main():
             note("legs: Erdős–Rényi DAGs, degree 6 and n = 2^20")
             legs["er_sparse_deg6"] = leg_er_sparse(px, dev, max(2, args.steps // 4), n_log2=16, deg=6)
             legs["er_sparse_n1M"] = leg_er_sparse(px, dev, 3, n_log2=20, deg=4, refine=False)
+            note("legs: minimum chain decompositions")
+            legs["min_chains"] = leg_min_chains(px, dev, max(2, args.steps // 4))
         out["legs"] = legs
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, f_host, args.cpu_budget)

@@ -87,6 +87,11 @@ typedef enum {
                                         more than 256 chains.  Such posets take gathers and level
                                         solves over their rows (long rows in fixed chunks) and
                                         cannot join a batch                                      */
+#define PX_BUILD_MIN_CHAINS 0x10u    /* without planted chains: refine the matching's path cover
+                                        (Alg. 1) to a minimum chain decomposition, as many chains
+                                        as the width (Theorem 2), by minimum flow; k and so every
+                                        transform's work can only drop (px_info.path_cover keeps
+                                        the cover's count)                                      */
 
 typedef struct {
   int64_t n;              /* elements                                                   */
@@ -117,6 +122,9 @@ typedef struct {
   int64_t run_chunks;     /* chunks of the int64 level solve by runs (niv map; 0: that
                              solve is not used and int64 solves row by row)              */
   int64_t run_events;     /* change events those chunks read (niv map)                   */
+  int64_t path_cover;     /* chains of the matching's path cover when the library chose
+                             the chains (k is smaller with PX_BUILD_MIN_CHAINS); 0 for
+                             planted or loaded chains                                    */
 } px_info;
 
 typedef struct {

@@ -6,7 +6,8 @@ Püschel, "Fast Möbius and Zeta Transforms"):
 
 * ``closure``   — the reachability relation (transitive closure) of a DAG by
                   brute force, and the chain maps (id, niv) read off it by
-                  their definitions (§2.4).
+                  their definitions (§2.4); the width (Theorem 2) by matching
+                  on the closure.
 * ``transforms``— zeta g = Z f and its adjoint Z^T w (Corollary 1, §2.2),
                   the Möbius function by its recursion (Theorem 1), and the
                   Möbius transform both as f = M g and by substitution on
@@ -30,13 +31,13 @@ against the paper's worked example (§2.2-§3), closed forms (chain, antichain,
 Boolean lattice, grid) and brute-force invariants; see each docstring.
 """
 
-from .closure import reachability, is_acyclic, linear_extension, niv_from_closure, mirsky_levels
+from .closure import reachability, is_acyclic, linear_extension, niv_from_closure, mirsky_levels, width
 from .transforms import (zeta, zeta_adjoint, mobius_function, mobius_matrix, mobius,
                          mobius_adjoint, mobius_by_substitution, mobius_adjoint_by_substitution)
 from .sampled import zeta_at, zeta_adjoint_at
 
 __all__ = [
-    "reachability", "is_acyclic", "linear_extension", "niv_from_closure", "mirsky_levels",
+    "reachability", "is_acyclic", "linear_extension", "niv_from_closure", "mirsky_levels", "width",
     "zeta", "zeta_adjoint", "mobius_function", "mobius_matrix", "mobius", "mobius_adjoint",
     "mobius_by_substitution", "mobius_adjoint_by_substitution", "zeta_at", "zeta_adjoint_at",
 ]

@@ -17,6 +17,7 @@ PX_BUILD_HOST_ONLY = 0x1
 PX_BUILD_NO_ADJOINT = 0x2
 PX_BUILD_LEVELS_MIRSKY = 0x4
 PX_BUILD_SPARSE_NIV = 0x8
+PX_BUILD_MIN_CHAINS = 0x10
 
 STATUS = {0: "PX_OK", 1: "PX_EINVAL", 2: "PX_ECYCLE", 3: "PX_ECHAIN", 4: "PX_ENOMEM", 5: "PX_EHIP",
           6: "PX_EUNSUPPORTED", 7: "PX_ENONFINITE", 8: "PX_ENOTCONV"}
@@ -46,7 +47,7 @@ class Info(ctypes.Structure):
         ("chains_planted", ctypes.c_int32), ("device", ctypes.c_int32)] + [
         (name, ctypes.c_double) for name in ("t_validate", "t_chains", "t_niv", "t_levels", "t_upload")] + [
         ("niv_sparse", ctypes.c_int32), ("niv_device_rounds", ctypes.c_int32),
-        ("run_chunks", ctypes.c_int64), ("run_events", ctypes.c_int64)]
+        ("run_chunks", ctypes.c_int64), ("run_events", ctypes.c_int64), ("path_cover", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -1455,7 +1455,8 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
   };
   try {
     rc = px::preprocess(n, indptr, indices, chain_of, chain_pos, p->has_up, p->mirsky,
-                        (flags & PX_BUILD_SPARSE_NIV) != 0, p->prep, msg, dev_niv ? &hook : nullptr);
+                        (flags & PX_BUILD_SPARSE_NIV) != 0, p->prep, msg, dev_niv ? &hook : nullptr,
+                        (flags & PX_BUILD_MIN_CHAINS) != 0);
   } catch (const std::bad_alloc&) {
     rc = PX_ENOMEM;
     msg = "host allocation failed during preprocessing";
@@ -1698,6 +1699,7 @@ px_status px_poset_info(const px_poset* p, px_info* o) {
   o->niv_device_rounds = P.niv_rounds;
   o->run_chunks = p->run_cptr[0].empty() ? 0 : p->run_cptr[0].back();
   o->run_events = p->run_events[0];
+  o->path_cover = P.path_cover;
   return PX_OK;
 }
 

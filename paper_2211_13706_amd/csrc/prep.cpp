@@ -223,7 +223,7 @@ void hopcroft_karp(int64_t n, const int64_t* indptr, const int32_t* indices, std
 
 int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const int32_t* chain_of,
                const int32_t* chain_pos, bool want_up, bool mirsky_schedule, bool want_sparse, Prep& P,
-               std::string& msg, const NivHook* niv_hook) {
+               std::string& msg, const NivHook* niv_hook, bool min_chains) {
   double t0 = now_s();
   if (n < 0 || n >= INT32_MAX) {
     msg = "n out of range";
@@ -329,6 +329,16 @@ int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const i
       ++k;
     }
     P.k = k;
+    P.path_cover = k;
+    if (min_chains) {  // refine to as many chains as the width
+      std::vector<int32_t> co, cp;
+      const int64_t km = min_chain_decomposition(n, indptr, indices, matchL, co, cp);
+      if (km > 0 && km <= k) {
+        P.chain_of.swap(co);
+        P.chain_pos.swap(cp);
+        P.k = km;
+      }
+    }
   }
   const int64_t k = P.k;
   P.chain_off.assign(k + 1, 0);

@@ -32,6 +32,7 @@ struct Prep {
   std::vector<int32_t> lev_down, lev_up;          // level per row
   std::vector<int32_t> lev_down_ptr, lev_down_rows, lev_up_ptr, lev_up_rows;
   int64_t nnz_niv = 0, nnz_niv_up = 0, max_chain = 0, mirsky = 0, udep = 0;
+  int64_t path_cover = 0;  // chains of the matching's path cover (Alg. 1), before any refinement
   int32_t niv_rounds = 0;  // rounds of a device computation of niv (0: the host recursion)
   double t_validate = 0, t_chains = 0, t_niv = 0, t_levels = 0;
 };
@@ -46,10 +47,21 @@ constexpr int64_t kSparseNivChains = 256;
 using NivHook = std::function<int(Prep& P, const std::vector<int64_t>& rptr, const std::vector<int32_t>& ridx,
                                   std::string& msg)>;
 
+// A minimum chain decomposition (as many chains as the width) starting from
+// the path cover next[v] (the element after v on its path, -1 at a path's
+// end; see chains.cpp).  Returns the number of chains with chain_of /
+// chain_pos filled (position 0 the lowest element), or -1 where the network
+// would not fit 32-bit indices.
+int64_t min_chain_decomposition(int64_t n, const int64_t* indptr, const int32_t* indices,
+                                const std::vector<int32_t>& next, std::vector<int32_t>& chain_of,
+                                std::vector<int32_t>& chain_pos);
+
 // Returns a px_status value; on failure `msg` says why.  want_sparse forces
 // the sparse form of the niv maps; niv_hook (nullable) is tried for dense ones.
+// min_chains: without planted chains, refine the matching's path cover to a
+// minimum chain decomposition.
 int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const int32_t* chain_of,
                const int32_t* chain_pos, bool want_up, bool mirsky_schedule, bool want_sparse, Prep& out,
-               std::string& msg, const NivHook* niv_hook = nullptr);
+               std::string& msg, const NivHook* niv_hook = nullptr, bool min_chains = false);
 
 }  // namespace px

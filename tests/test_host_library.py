@@ -136,6 +136,24 @@ def test_matching_chains_reach_width(px):
     assert P.k == 252            # C(10, 5), Sperner / Dilworth
 
 
+@pytest.mark.parametrize("case", ["er300", "er2000", "er2000d6", "small0", "small1", "lattice", "grid", "example"])
+def test_min_chains_reach_width(px, case):
+    """PX_BUILD_MIN_CHAINS refines the matching's path cover (Alg. 1, edges only)
+    to as many chains as the width (Theorem 2), here the oracle's matching on the
+    closure; the chains partition the elements and are totally ordered, and the
+    niv maps read off the closure for those chains agree."""
+    p = {"er300": lambda: W.er_dag(300, 2, seed=1), "er2000": lambda: W.er_dag(2000, 4, seed=2),
+         "er2000d6": lambda: W.er_dag(2000, 6, seed=3), "small0": lambda: W.random_small_dag(60, 0.08, seed=5),
+         "small1": lambda: W.random_small_dag(120, 0.03, seed=6), "lattice": lambda: W.boolean_lattice(6),
+         "grid": lambda: W.grid_poset(12, 9), "example": W.worked_example}[case]()
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P0 = _host(px, p, planted=False)
+    P = _host(px, p, planted=False, flags=px.PX_BUILD_MIN_CHAINS)
+    assert P.k == O.width(R) <= P0.k
+    assert P.info["path_cover"] == P0.k
+    _check_against_closure(px, P, p, R)
+
+
 def test_mirsky_schedule_flag(px):
     p = W.worked_example()
     P = _host(px, p, flags=px.PX_BUILD_LEVELS_MIRSKY)

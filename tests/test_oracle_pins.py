@@ -372,3 +372,40 @@ def test_sampled_oracle_matches_closure(kind):
         assert np.array_equal(a, b) and np.array_equal(aa, bb)
     else:
         assert np.allclose(a, b, rtol=1e-12, atol=1e-9) and np.allclose(aa, bb, rtol=1e-12, atol=1e-9)
+
+
+# ------------------------------------------------------------------ width
+def _max_antichain_brute(R):
+    """Largest set of pairwise incomparable elements, by trying every subset."""
+    n = R.shape[0]
+    comp = R | R.T
+    best = 0
+    for mask in range(1 << n):
+        idx = [i for i in range(n) if mask >> i & 1]
+        if len(idx) <= best:
+            continue
+        if not comp[np.ix_(idx, idx)][~np.eye(len(idx), dtype=bool)].any():
+            best = len(idx)
+    return best
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_width_is_the_largest_antichain_brute_force(seed):
+    """Theorem 2 / Dilworth: the fewest chains equal the largest antichain, found
+    here by brute force over all subsets of a small random DAG."""
+    p = W.random_small_dag(11, 0.25 + 0.05 * (seed % 3), seed=seed)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    assert O.width(R) == _max_antichain_brute(R)
+
+
+def test_width_closed_forms():
+    """Chain 1, antichain n, a w x h grid min(w, h), the Boolean lattice of
+    subsets of m elements C(m, floor(m/2)) (Sperner), the worked example 4."""
+    def w(p):
+        return O.width(O.reachability(p.n, p.indptr, p.indices))
+    assert w(W.chain_only(40, seed=3)) == 1
+    assert w(W.antichain(13)) == 13
+    assert w(W.grid_poset(7, 5)) == 5 and w(W.grid_poset(3, 9)) == 3
+    for m in (4, 5, 6, 7):
+        assert w(W.boolean_lattice(m)) == math.comb(m, m // 2)
+    assert w(W.worked_example()) == 4
