@@ -25,7 +25,7 @@ ARCH = os.environ.get("POSETX_ARCH", "gfx950")
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-result"]
-SOURCES = ["prep.cpp", "chains.cpp", "api.cpp", "kernels.hip", "niv_device.hip", "noalloc.hip"]
+SOURCES = ["prep.cpp", "chains.cpp", "api.cpp", "kernels.hip", "niv_device.hip", "niv_sparse.hip", "noalloc.hip"]
 
 
 def _hipcc() -> str:

@@ -1333,8 +1333,12 @@ static px_status finish_poset(px_poset* p, int device, px_poset** out) {
       if (e == hipSuccess && p->has_up) e = upload(&p->d_niv_up, P.niv_up.data(), P.niv_up.size(), b);
     } else {
       for (int m = 0; m < (p->has_up ? 2 : 1) && e == hipSuccess; ++m) {
-        e = upload(&p->d_nivp[m], P.nivp[m].data(), P.nivp[m].size(), b);
-        if (e == hipSuccess) e = upload(&p->d_nivr[m], P.nivr[m].data(), P.nivr[m].size(), b);
+        if (p->d_nivp[m] && p->d_nivr[m]) {  // computed on the device
+          b += (int64_t)(P.nivp[m].size() * 8 + P.nivr[m].size() * 4);
+        } else {
+          e = upload(&p->d_nivp[m], P.nivp[m].data(), P.nivp[m].size(), b);
+          if (e == hipSuccess) e = upload(&p->d_nivr[m], P.nivr[m].data(), P.nivr[m].size(), b);
+        }
         p->dp.nivp[m] = p->d_nivp[m];
         p->dp.nivr[m] = p->d_nivr[m];
       }
@@ -1444,7 +1448,13 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
   const bool dev_niv = !p->host_only && n > 0 && !force_host;
   const int64_t min_dev_entries = force_dev ? 0 : (int64_t)1 << 24;
   px::NivHook hook = [&](px::Prep& P, const std::vector<int64_t>& rptr, const std::vector<int32_t>& ridx,
-                         std::string& m) -> int {
+                         const px::Heights* heights, std::string& m) -> int {
+    if (heights) {  // sparse rows: on the device from 2^16 elements (or when forced)
+      if (P.n < (force_dev ? 0 : (int64_t)1 << 16)) return -1;
+      DeviceGuard dg(device);
+      if (!dg.ok) return -1;
+      return px::device_niv_sparse(P, indptr, indices, rptr, ridx, *heights, p->has_up, p->d_nivp, p->d_nivr, m);
+    }
     if (P.n * P.k < min_dev_entries) return -1;
     DeviceGuard dg(device);
     if (!dg.ok) return -1;

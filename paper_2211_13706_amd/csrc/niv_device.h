@@ -22,4 +22,15 @@ int device_niv(Prep& P, const int64_t* indptr, const int32_t* indices, const std
                const std::vector<int32_t>& ridx, bool want_up, int32_t** out_niv, int32_t** out_up, int* rounds,
                std::string& msg);
 
+// The niv maps as rows of their finite entries (P.sparse), on the current
+// device, height after height (see niv_sparse.hip).  On success returns
+// PX_OK, fills P.nivp / P.nivr (and the dual map's if want_up) on the host and
+// leaves device copies in out_ptr[m] / out_rows[m] (hipMalloc'd, owned by the
+// caller).  Returns -1 (nothing kept) for a node with more than 64 neighbours
+// or where device memory runs out, so that the host recursion runs instead;
+// PX_ECHAIN for a chain that is not totally ordered; PX_EHIP with msg set.
+int device_niv_sparse(Prep& P, const int64_t* indptr, const int32_t* indices, const std::vector<int64_t>& rptr,
+                      const std::vector<int32_t>& ridx, const Heights& heights, bool want_up, int64_t* out_ptr[2],
+                      int32_t* out_rows[2], std::string& msg);
+
 }  // namespace px

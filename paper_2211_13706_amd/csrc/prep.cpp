@@ -381,9 +381,16 @@ int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const i
   };
   P.sparse = want_sparse || k > kSparseNivChains;
   int hook_rc = -1;
-  if (!P.sparse && niv_hook && *niv_hook) hook_rc = (*niv_hook)(P, rptr, ridx, msg);
+  if (!P.sparse && niv_hook && *niv_hook) hook_rc = (*niv_hook)(P, rptr, ridx, nullptr, msg);
+  if (P.sparse && niv_hook && *niv_hook) {
+    Heights hs;
+    for (int m = 0; m < (want_up ? 2 : 1); ++m) by_height(n, indptr, indices, order, mir, m == 1, hs.ptr[m], hs.nodes[m]);
+    hook_rc = (*niv_hook)(P, rptr, ridx, &hs, msg);
+  }
   if (hook_rc > 0) return hook_rc;
-  if (!P.sparse && hook_rc == PX_OK) {
+  if (P.sparse && hook_rc == PX_OK) {
+    // rows computed elsewhere
+  } else if (!P.sparse && hook_rc == PX_OK) {
     for (size_t i = 0; i < P.niv.size(); ++i) P.nnz_niv += P.niv[i] >= 0;
     for (size_t i = 0; i < P.niv_up.size(); ++i) P.nnz_niv_up += P.niv_up[i] >= 0;
   } else if (!P.sparse) {

@@ -40,12 +40,19 @@ struct Prep {
 // Decompositions with more chains than this keep the niv maps sparse.
 constexpr int64_t kSparseNivChains = 256;
 
-// Computes the dense niv maps elsewhere (on a device) once the chains are
-// known, given the parent lists: returns PX_OK with P.niv (and P.niv_up)
-// filled, -1 to let the host recursion run instead, or an error status with
-// msg set.
+// The nodes of every height (longest path down to a leaf for map 0, up to a
+// root for map 1), height after height: nodes[m][ptr[m][h] .. ptr[m][h + 1]).
+struct Heights {
+  std::vector<int64_t> ptr[2];
+  std::vector<int32_t> nodes[2];
+};
+
+// Computes the niv maps elsewhere (on a device) once the chains are known,
+// given the parent lists: returns PX_OK with P.niv (and P.niv_up) filled, or
+// for sparse rows (P.sparse; heights non-null) P.nivp / P.nivr, -1 to let the
+// host recursion run instead, or an error status with msg set.
 using NivHook = std::function<int(Prep& P, const std::vector<int64_t>& rptr, const std::vector<int32_t>& ridx,
-                                  std::string& msg)>;
+                                  const Heights* heights, std::string& msg)>;
 
 // A minimum chain decomposition (as many chains as the width) starting from
 // the path cover next[v] (the element after v on its path, -1 at a path's

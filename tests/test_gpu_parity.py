@@ -888,6 +888,73 @@ def test_device_niv_equals_host_recursion(px, case, monkeypatch):
     assert info["nnz_niv"] == int((want[False] >= 0).sum()) and info["nnz_niv_up"] == int((want[True] >= 0).sum())
 
 
+@pytest.mark.parametrize("case", ["er_d4", "er_d6", "example", "lattice", "cfg0", "random", "antichain", "chain"])
+def test_device_sparse_niv_rows_match_oracle(px, case, monkeypatch):
+    """The sparse niv rows merged on the device, height after height (both maps),
+    against the closure oracle's niv (§2.4) and the host recursion's rows; the
+    transforms on those rows are exact (int64, against the oracle)."""
+    monkeypatch.setenv("POSETX_PREP", "device")
+    p, planted = {
+        "er_d4": (W.er_dag(2000, 4, seed=2), False), "er_d6": (W.er_dag(1500, 6, seed=7), False),
+        "example": (W.worked_example(), True), "lattice": (W.boolean_lattice(8), False),
+        "cfg0": (W.chain_poset(2000, 16, 4, seed=0), True), "random": (W.random_small_dag(400, 0.02, 5), False),
+        "antichain": (W.antichain(100), False), "chain": (W.chain_only(500, seed=2), True)}[case]
+    D = build(px, p, planted=planted, flags=px.PX_BUILD_SPARSE_NIV)
+    info = D.info_dict()
+    assert info["niv_sparse"] == 1 and info["niv_device_rounds"] >= 1
+    Hh = px.poset_build(p.n, p.indptr, p.indices, p.chain_of if planted else None, p.chain_pos if planted else None,
+                        flags=px.PX_BUILD_HOST_ONLY | px.PX_BUILD_SPARSE_NIV)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    co, cp = D.chains()
+    lens = np.bincount(co, minlength=D.k)
+    want = {False: O.niv_from_closure(R, co, cp, D.k),
+            True: O.niv_from_closure(np.ascontiguousarray(R.T), co, lens[co] - 1 - cp, D.k)}
+    for up in (False, True):
+        ptr, nodes = D.niv_csr(up)
+        hptr, hnodes = Hh.niv_csr(up)
+        assert np.array_equal(ptr, hptr) and np.array_equal(nodes, hnodes)
+        assert np.array_equal(D.niv(up), want[up])
+        assert np.array_equal(D.levels(up), Hh.levels(up))
+    f = W.functions(p.n, 8, "int", seed=3, lo=-1000, hi=1000)
+    assert np.array_equal(H(px.zeta(D, T(f))), O.zeta(R, f))
+    assert np.array_equal(H(px.zeta_adjoint(D, T(f))), O.zeta_adjoint(R, f))
+    assert np.array_equal(H(px.mobius(D, T(f))), O.mobius_by_substitution(R, f))
+
+
+def test_device_sparse_niv_rejects_unordered_chains(px, monkeypatch):
+    """The device merge checks planted chains as the host recursion does."""
+    monkeypatch.setenv("POSETX_PREP", "device")
+    p = W.worked_example()
+    co, cp = p.chain_of.copy(), p.chain_pos.copy()
+    co[[4, 5]] = co[[5, 4]]; cp[[4, 5]] = cp[[5, 4]]     # x5 and x6 are incomparable
+    with pytest.raises(px.PosetxError) as ei:
+        px.poset_build(p.n, p.indptr, p.indices, co, cp, flags=px.PX_BUILD_SPARSE_NIV, device=0)
+    assert ei.value.name == "PX_ECHAIN"
+    cp2 = p.chain_pos.copy()
+    c0 = np.nonzero(p.chain_of == 0)[0]; cp2[c0] = cp2[c0].max() - cp2[c0]
+    with pytest.raises(px.PosetxError) as ei:
+        px.poset_build(p.n, p.indptr, p.indices, p.chain_of, cp2, flags=px.PX_BUILD_SPARSE_NIV, device=0)
+    assert ei.value.name == "PX_ECHAIN"
+
+
+def test_device_sparse_niv_er_n64k_matches_host(px, monkeypatch):
+    """ER n = 2^16, degree 4 (k = 13,243 chains, 13.8 M entries per map): the default
+    build merges the rows on the device (n >= 2^16); they equal the host recursion's
+    (POSETX_PREP=host), both maps, and the transforms agree bit for bit."""
+    p = W.er_dag(1 << 16, 4, seed=1)
+    D = px.poset_build(p.n, p.indptr, p.indices, device=0)
+    assert D.info["niv_sparse"] == 1 and D.info["niv_device_rounds"] >= 1
+    monkeypatch.setenv("POSETX_PREP", "host")
+    Hh = px.poset_build(p.n, p.indptr, p.indices, device=0)
+    assert Hh.info["niv_device_rounds"] == 0
+    for up in (False, True):
+        a, b = D.niv_csr(up), Hh.niv_csr(up)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    f = T(W.functions(p.n, 16, "int", seed=4, lo=-1000, hi=1000))
+    assert np.array_equal(H(px.zeta(D, f)), H(px.zeta(Hh, f)))
+    assert np.array_equal(H(px.mobius(D, f)), H(px.mobius(Hh, f)))
+
+
 def test_device_niv_config1_and_host_switch(px, cfg1, monkeypatch):
     """n = 2^20, k = 64: the device maps equal the host's; POSETX_PREP=host selects the host recursion."""
     p, _ = cfg1
