@@ -1463,10 +1463,20 @@ px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indice
     if (r == PX_OK) P.niv_rounds = rounds;
     return r;
   };
+  // levels on the device wherever the map already is (device niv rows)
+  px::LevelHook lhook = [&](const px::Prep& P, bool up, const std::vector<int64_t>& hptr,
+                            const std::vector<int32_t>& hnodes, std::vector<int32_t>& lev) -> int {
+    const int m = up ? 1 : 0;
+    const int32_t* nv = P.sparse ? nullptr : (up ? p->d_niv_up : p->d_niv);
+    if (!nv && !(P.sparse && p->d_nivp[m] && p->d_nivr[m])) return -1;
+    DeviceGuard dg(device);
+    if (!dg.ok) return -1;
+    return px::device_udep_levels(P, hptr, hnodes, nv, p->d_nivp[m], p->d_nivr[m], lev);
+  };
   try {
     rc = px::preprocess(n, indptr, indices, chain_of, chain_pos, p->has_up, p->mirsky,
                         (flags & PX_BUILD_SPARSE_NIV) != 0, p->prep, msg, dev_niv ? &hook : nullptr,
-                        (flags & PX_BUILD_MIN_CHAINS) != 0);
+                        (flags & PX_BUILD_MIN_CHAINS) != 0, dev_niv ? &lhook : nullptr);
   } catch (const std::bad_alloc&) {
     rc = PX_ENOMEM;
     msg = "host allocation failed during preprocessing";

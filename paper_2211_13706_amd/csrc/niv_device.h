@@ -33,4 +33,11 @@ int device_niv_sparse(Prep& P, const int64_t* indptr, const int32_t* indices, co
                       const std::vector<int32_t>& ridx, const Heights& heights, bool want_up, int64_t* out_ptr[2],
                       int32_t* out_rows[2], std::string& msg);
 
+// The U-dependency levels of one map on the current device from the map's
+// device rows (dense [n, k] nv, or sparse ep / er), one launch per height
+// (hptr / hnodes), copied into lev.  Returns PX_OK, or -1 on any HIP error
+// (the caller computes them on the host instead).
+int device_udep_levels(const Prep& P, const std::vector<int64_t>& hptr, const std::vector<int32_t>& hnodes,
+                       const int32_t* nv, const int64_t* ep, const int32_t* er, std::vector<int32_t>& lev);
+
 }  // namespace px

@@ -166,6 +166,28 @@ __global__ __launch_bounds__(SWG) void k_sparse_layout(int64_t n, const int64_t*
   for (int64_t j = lane; j < len; j += 64) out[a + j] = pool[s + j];
 }
 
+// One height of the U-dependency levels, a wavefront per row: lev[r] = 1 + the
+// largest level among the row's other-chain entries (dense rows nv [n, k], or
+// the sparse rows ep / er), 0 without any.  Entries lie at lower heights.
+__global__ __launch_bounds__(SWG) void k_udep_level(int64_t cnt, const int32_t* __restrict__ hn,
+                                                    const int32_t* __restrict__ row_of_node, int k,
+                                                    const int32_t* __restrict__ nv, const int64_t* __restrict__ ep,
+                                                    const int32_t* __restrict__ er, int32_t* __restrict__ lev) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t i = (int64_t)blockIdx.x * (SWG / 64) + (threadIdx.x >> 6);
+  if (i >= cnt) return;
+  const int r = __builtin_amdgcn_readfirstlane(row_of_node[hn[i]]);
+  const int32_t* row = nv ? nv + (int64_t)r * k : er + ep[r];
+  const int64_t len = nv ? k : ep[r + 1] - ep[r];
+  int m = 0;
+  for (int64_t j = lane; j < len; j += 64) {
+    const int t = row[j];
+    if (t >= 0 && t != r) m = max(m, lev[t] + 1);
+  }
+  m = wave_max(m);
+  if (lane == 0) lev[r] = m;
+}
+
 unsigned nblocks(int64_t items, int per) { return (unsigned)((items + per - 1) / per); }
 
 struct Held {
@@ -340,6 +362,32 @@ int device_niv_sparse(Prep& P, const int64_t* indptr, const int32_t* indices, co
     out_rows[m] = kept_rows[m];
   }
   P.niv_rounds = (int32_t)(H.ptr[0].size() - 1);
+  return PX_OK;
+}
+
+int device_udep_levels(const Prep& P, const std::vector<int64_t>& hptr, const std::vector<int32_t>& hnodes,
+                       const int32_t* nv, const int64_t* ep, const int32_t* er, std::vector<int32_t>& lev) {
+  const int64_t n = P.n;
+  if (n == 0 || (!nv && (!ep || !er))) return -1;
+  Held hb;
+  const int32_t* d_hn = hb.put(hnodes.data(), hnodes.size());
+  const int32_t* d_ron = hb.put(P.row_of_node.data(), (size_t)n);
+  int32_t* d_lev = hb.get<int32_t>((size_t)n);
+  hipError_t e = hb.err;
+  if (e == hipSuccess) e = hipMemset(d_lev, 0, n * sizeof(int32_t));
+  for (size_t h = 0; h + 1 < hptr.size() && e == hipSuccess; ++h) {
+    const int64_t c = hptr[h + 1] - hptr[h];
+    hipLaunchKernelGGL(k_udep_level, dim3(nblocks(c, SWG / 64)), dim3(SWG), 0, 0, c, d_hn + hptr[h], d_ron,
+                       (int)P.k, nv, ep, er, d_lev);
+    e = hipGetLastError();
+  }
+  lev.resize(n);
+  if (e == hipSuccess) e = hipMemcpy(lev.data(), d_lev, n * sizeof(int32_t), hipMemcpyDeviceToHost);
+  hb.release();
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return -1;
+  }
   return PX_OK;
 }
 

@@ -223,7 +223,7 @@ void hopcroft_karp(int64_t n, const int64_t* indptr, const int32_t* indices, std
 
 int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const int32_t* chain_of,
                const int32_t* chain_pos, bool want_up, bool mirsky_schedule, bool want_sparse, Prep& P,
-               std::string& msg, const NivHook* niv_hook, bool min_chains) {
+               std::string& msg, const NivHook* niv_hook, bool min_chains, const LevelHook* level_hook) {
   double t0 = now_s();
   if (n < 0 || n >= INT32_MAX) {
     msg = "n out of range";
@@ -575,6 +575,7 @@ int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const i
     std::vector<int64_t> hptr;
     std::vector<int32_t> hnodes;
     by_height(n, indptr, indices, order, mir, up, hptr, hnodes);
+    if (level_hook && *level_hook && (*level_hook)(P, up, hptr, hnodes, lev) == PX_OK) return;
     for (size_t h = 0; h + 1 < hptr.size(); ++h) {
       lteam.run(hptr[h + 1] - hptr[h], 256, [&](int, int64_t lo, int64_t hi) {
         for (int64_t i = hptr[h] + lo; i < hptr[h] + hi; ++i) {

@@ -63,12 +63,21 @@ int64_t min_chain_decomposition(int64_t n, const int64_t* indptr, const int32_t*
                                 const std::vector<int32_t>& next, std::vector<int32_t>& chain_of,
                                 std::vector<int32_t>& chain_pos);
 
+// Computes the U-dependency levels of one map elsewhere (on a device, where
+// the map already is): lev[r] = 1 + the largest level among the other-chain
+// entries of row r (0 without any), rows taken height by height (hptr /
+// hnodes as in Heights).  Returns PX_OK with lev filled (n entries) or -1 to
+// let the host compute them.
+using LevelHook = std::function<int(const Prep& P, bool up, const std::vector<int64_t>& hptr,
+                                    const std::vector<int32_t>& hnodes, std::vector<int32_t>& lev)>;
+
 // Returns a px_status value; on failure `msg` says why.  want_sparse forces
 // the sparse form of the niv maps; niv_hook (nullable) is tried for dense ones.
 // min_chains: without planted chains, refine the matching's path cover to a
 // minimum chain decomposition.
 int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const int32_t* chain_of,
                const int32_t* chain_pos, bool want_up, bool mirsky_schedule, bool want_sparse, Prep& out,
-               std::string& msg, const NivHook* niv_hook = nullptr, bool min_chains = false);
+               std::string& msg, const NivHook* niv_hook = nullptr, bool min_chains = false,
+               const LevelHook* level_hook = nullptr);
 
 }  // namespace px
