@@ -245,8 +245,16 @@ def legs_config1(px, P, p, dev, steps):
     P.reserve(torch.float32, 8)
     tune8 = P.autotune(torch.float32, 8)  # the tile shapes for this width (the headline's were for 64)
     t8 = _time(lambda: px.zeta(P, f8, out=g8), steps, sync)
+    P.set_layout("rows")  # the same share with the matrices in chain-major row order
+    f8r = f8[torch.from_numpy(np.argsort(P.rows())).to(dev)].contiguous()
+    g8r = torch.empty_like(f8r)
+    t8r = _time(lambda: px.zeta(P, f8r, out=g8r), steps, sync)
+    eq8 = bool(torch.equal(g8r[torch.from_numpy(P.rows()).to(dev)], g8))
+    P.set_layout("nodes")
     out["zeta_f32_B8_share"] = {"ms": round(t8 * 1e3, 4), "node_rhs_per_s": p.n * 8 / t8,
+                                "rows_layout_ms": round(t8r * 1e3, 4), "rows_layout_equal": eq8,
                                 "autotune": {k: tune8[k] for k in ("walk_T", "walk_emax", "rhs_tile")}}
+    del f8r, g8r
     del f8, g8
     out["preprocess"] = leg_preprocess(px, P, p)
     return out
@@ -368,6 +376,15 @@ def leg_large(px, dev, steps):
     g = torch.empty_like(f)
     L.reserve(torch.float32, Bl)
     tz = _time(lambda: px.zeta(L, f, out=g), steps, sync)
+    # the same transform with the matrices kept in chain-major row order (px_poset_set_layout):
+    # the chain scans and the combine then stream f and g instead of visiting them in node order
+    L.set_layout("rows")
+    fr = f[torch.from_numpy(np.argsort(L.rows())).to(dev)].contiguous()
+    gr = torch.empty_like(fr)
+    tz_rows = _time(lambda: px.zeta(L, fr, out=gr), steps, sync)
+    rows_equal = bool(torch.equal(gr[torch.from_numpy(L.rows()).to(dev)], g))
+    L.set_layout("nodes")
+    del fr, gr
     try:
         f2, rep = px.mobius(L, g, max_refine=2, report=True)
         err = ((f2 - f).abs().amax(0) / f.abs().amax(0)).max().item()
@@ -397,7 +414,9 @@ def leg_large(px, dev, steps):
         mob_bwd = e.name
     return {"workload": "n=8388608, k=32, 3 cross edges, B=16", "preprocess_s": round(t_prep, 2),
             "levels": L.info["levels_down"], "zeta_f32_ms": round(tz * 1e3, 4),
-            "zeta_node_rhs_per_s": q.n * Bl / tz, "mobius_int64_ms": round(tm * 1e3, 4),
+            "zeta_node_rhs_per_s": q.n * Bl / tz,
+            "zeta_f32_rows_layout_ms": round(tz_rows * 1e3, 4), "rows_layout_equal": rows_equal,
+            "mobius_int64_ms": round(tm * 1e3, 4),
             "us_per_level": round(tm * 1e6 / max(1, L.info["levels_down"]), 2),
             "int64_roundtrip_exact": exact, "int64_adjoint_roundtrip_exact": exact_adj,
             "mobius_f64_growth": growth,

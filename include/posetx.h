@@ -125,6 +125,7 @@ typedef struct {
   int64_t path_cover;     /* chains of the matching's path cover when the library chose
                              the chains (k is smaller with PX_BUILD_MIN_CHAINS); 0 for
                              planted or loaded chains                                    */
+  int64_t layout;         /* PX_LAYOUT_NODES or PX_LAYOUT_ROWS (px_poset_set_layout)     */
 } px_info;
 
 typedef struct {
@@ -186,6 +187,20 @@ px_status px_poset_chains(const px_poset* p, int32_t* chain_of, int32_t* chain_p
  * relate them to the chain-major prefix matrix V f (§3). */
 px_status px_poset_rows(const px_poset* p, int64_t* row_of_node);
 px_status px_poset_niv(const px_poset* p, int up, int32_t* out);
+
+/* Function-matrix layout of every later transform on this handle.
+ *   PX_LAYOUT_NODES (default): row x of f, g, w, v, out is node x.
+ *   PX_LAYOUT_ROWS: row r is the element at chain-major row r (px_poset_rows), the
+ *     order in which the chain scans and level solves run, so that every
+ *     kernel streams the matrices instead of visiting them in node order.  A
+ *     caller that keeps its functions permuted this way gets the same values, bit
+ *     for bit, permuted the same way (§3: Z = U V acts on that numbering).
+ * The first switch to rows allocates one int32 table of n entries (not under
+ * graph capture).  Not to be called while a transform on the handle is in
+ * flight.  Batches built from the handle keep node order. */
+#define PX_LAYOUT_NODES 0u
+#define PX_LAYOUT_ROWS 1u
+px_status px_poset_set_layout(px_poset* p, uint32_t layout);
 /* The same map by rows of its finite entries (N of §2.4 in CSR form, node order):
  * the entries of node x are nodes[ptr[x] .. ptr[x+1]), the node ids niv_j(x) in
  * ascending chain j.  ptr: n+1 entries; nodes: px_info.nnz_niv (up: nnz_niv_up)

@@ -18,6 +18,7 @@ PX_BUILD_NO_ADJOINT = 0x2
 PX_BUILD_LEVELS_MIRSKY = 0x4
 PX_BUILD_SPARSE_NIV = 0x8
 PX_BUILD_MIN_CHAINS = 0x10
+PX_LAYOUT_NODES, PX_LAYOUT_ROWS = 0, 1
 
 STATUS = {0: "PX_OK", 1: "PX_EINVAL", 2: "PX_ECYCLE", 3: "PX_ECHAIN", 4: "PX_ENOMEM", 5: "PX_EHIP",
           6: "PX_EUNSUPPORTED", 7: "PX_ENONFINITE", 8: "PX_ENOTCONV"}
@@ -28,7 +29,7 @@ EXPORTS = [
     "px_batch_build", "px_batch_free", "px_batch_reserve", "px_batch_rows", "px_zeta_batched",
     "px_zeta_adjoint_batched", "px_last_error", "px_version", "px_profile", "px_profile_read",
     "px_profile_phase_name", "px_autotune", "px_batch_autotune", "px_poset_niv_csr", "px_poset_rows",
-    "px_poset_save", "px_poset_load", "px_zeta_noalloc",
+    "px_poset_save", "px_poset_load", "px_zeta_noalloc", "px_poset_set_layout",
 ]
 
 
@@ -47,7 +48,8 @@ class Info(ctypes.Structure):
         ("chains_planted", ctypes.c_int32), ("device", ctypes.c_int32)] + [
         (name, ctypes.c_double) for name in ("t_validate", "t_chains", "t_niv", "t_levels", "t_upload")] + [
         ("niv_sparse", ctypes.c_int32), ("niv_device_rounds", ctypes.c_int32),
-        ("run_chunks", ctypes.c_int64), ("run_events", ctypes.c_int64), ("path_cover", ctypes.c_int64)]
+        ("run_chunks", ctypes.c_int64), ("run_events", ctypes.c_int64), ("path_cover", ctypes.c_int64),
+        ("layout", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -81,6 +83,7 @@ def _declare(lib):
         "px_poset_niv": [P, i32, P],
         "px_poset_niv_csr": [P, i32, P, P],
         "px_poset_rows": [P, P],
+        "px_poset_set_layout": [P, u32],
         "px_poset_save": [P, ctypes.c_char_p],
         "px_poset_load": [ctypes.c_char_p, u32, i32, ctypes.POINTER(P)],
         "px_poset_levels": [P, i32, P],

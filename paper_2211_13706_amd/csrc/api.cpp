@@ -538,6 +538,10 @@ struct px_poset {
           *d_tiles = nullptr, *d_lev_niv[2] = {nullptr, nullptr}, *d_lev_node[2] = {nullptr, nullptr},
           *d_walk[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
   int32_t* d_nivr[2] = {nullptr, nullptr};  // sparse niv rows: entries and row offsets
+  // function-matrix layout (px_poset_set_layout); with rows, dp addresses user
+  // matrices through the identity d_iota instead of node_of_row
+  uint32_t layout = PX_LAYOUT_NODES;
+  int32_t* d_iota = nullptr;
   // int64 level solve by runs: change events and per-level chunks (px::SegTables)
   int4* d_run_ev[2] = {nullptr, nullptr};
   int4* d_run_chunks[2] = {nullptr, nullptr};
@@ -600,7 +604,7 @@ namespace {
 void free_poset_device(px_poset* p) {
   int32_t* bufs[] = {p->d_node_of_row, p->d_chain_of_row, p->d_chain_off, p->d_niv, p->d_niv_up,
                      p->d_lev_down,     p->d_lev_up,       p->d_segoff,    p->d_order, p->d_tiles,
-                     p->d_lev_niv[0],   p->d_lev_niv[1],   p->d_lev_node[0], p->d_lev_node[1],
+                     p->d_lev_niv[0],   p->d_lev_niv[1],   p->d_lev_node[0], p->d_lev_node[1], p->d_iota,
                      p->d_nivr[0],      p->d_nivr[1]};
   for (int32_t* b : bufs)
     if (b) (void)hipFree(b);
@@ -849,8 +853,23 @@ int64_t flow_ints(const px_poset* p, int64_t B) {
   return 1 + ncb * std::max<int64_t>(p->prep.n + 1, nch);
 }
 
+// Narrow blocks (B <= 32) take the compact walk in 64-column tiles with the
+// columns beyond B masked, unless POSETX_COMPACT_NARROW=0 (read on every call).
+bool compact_narrow_enabled() {
+  const char* v = std::getenv("POSETX_COMPACT_NARROW");
+  return !(v && std::strcmp(v, "0") == 0);
+}
+
 bool use_compact(const px_poset* p, bool up, int64_t B) {
-  return p->nslots[up ? 1 : 0] >= 0 && compact_enabled() && px::compact_ok(p->dp, up, B);
+  return p->nslots[up ? 1 : 0] >= 0 && compact_enabled() && (px::col_width(B) == 64 || compact_narrow_enabled()) &&
+         px::compact_ok(p->dp, up, B);
+}
+
+// Tiles of the compact walk's scan (64-row tiles whatever B is), and the tile
+// count a workspace for B columns must hold (either scan).
+int64_t compact_tiles(const px_poset* p) { return p->ntiles[px::seg_index(64)]; }
+int64_t ws_tiles(const px_poset* p, int64_t B) {
+  return std::max(p->ntiles[px::seg_index(px::col_width(B))], p->nslots[0] >= 0 ? compact_tiles(p) : (int64_t)0);
 }
 
 // Level-scheduled solve U y' = g (Alg. 4, first loop; Alg. 5 schedule), one
@@ -922,7 +941,7 @@ Layout zeta_layout(const px_poset* p, bool up, int dtype, int64_t B, bool compac
   const int64_t n = p->prep.n;
   const size_t es = elem_size(dtype);
   const int cw = px::col_width(B);
-  const int64_t nt = p->ntiles[px::seg_index(cw)];
+  const int64_t nt = compact ? compact_tiles(p) : p->ntiles[px::seg_index(cw)];
   const int m = up ? 1 : 0;
   Layout L;
   size_t o = 0;
@@ -964,8 +983,8 @@ px_status zeta_impl(px_poset* p, bool up, int dtype, const void* f, int64_t ldf,
   DeviceGuard dg(p->device);
   if (!dg.ok) return fail(PX_EHIP, "hipSetDevice failed");
   const int cw = px::col_width(B);
-  const int64_t nt = p->ntiles[px::seg_index(cw)];
   const bool compact = use_compact(p, up, B);
+  const int64_t nt = compact ? compact_tiles(p) : p->ntiles[px::seg_index(cw)];
   Layout L;
   char* w;
   if (ext) {
@@ -975,7 +994,8 @@ px_status zeta_impl(px_poset* p, bool up, int dtype, const void* f, int64_t ldf,
                                  std::to_string(ext_bytes));
     w = (char*)ext;
   } else {
-    L = layout(p->prep.n, B, dtype, false, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p), max_parts(p));
+    L = layout(p->prep.n, B, dtype, false, ws_tiles(p, B), std::max(p->nsnap[0], p->nsnap[1]), max_slots(p),
+               max_parts(p));
     if ((st = p->ws.ensure(L.total)) != PX_OK) return st;
     w = (char*)p->ws.p;
   }
@@ -1016,8 +1036,8 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   const bool refine = dtype == PX_F32;
   const int cw = px::col_width(B);
   const int64_t nt = p->ntiles[px::seg_index(cw)];
-  Layout L = layout(n, B, dtype, refine, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p), max_parts(p),
-                    dtype == PX_I64 ? flow_ints(p, B) : 0);
+  Layout L = layout(n, B, dtype, refine, ws_tiles(p, B), std::max(p->nsnap[0], p->nsnap[1]), max_slots(p),
+                    max_parts(p), dtype == PX_I64 ? flow_ints(p, B) : 0);
   if ((st = p->ws.ensure(L.total)) != PX_OK) return st;
   char* w = (char*)p->ws.p;
   hipStream_t s = (hipStream_t)stream;
@@ -1070,8 +1090,8 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   // r = g - zeta(f), zeta applied in float64 to the float32 iterate.
   auto residual = [&]() -> hipError_t {
     if (use_compact(p, up, B))
-      return run_compact(p->dp, dir, px::E_F32, f, ldf, px::E_F64, r64, B, px::E_F32, g, ldg, B, w + L.aux, nt,
-                         w + L.lq, w + L.snaps, s);
+      return run_compact(p->dp, dir, px::E_F32, f, ldf, px::E_F64, r64, B, px::E_F32, g, ldg, B, w + L.aux,
+                         compact_tiles(p), w + L.lq, w + L.snaps, s);
     hipError_t e2 = run_scan(p->dp, dir, px::E_F32, f, ldf, px::E_F64, w + L.p64, B, w + L.aux, nt, (int*)(w + L.sync), s);
     if (e2 == hipSuccess)
       e2 = run_gather(p->dp, up, px::E_F64, w + L.p64, B, px::E_F64, r64, B, px::E_F32, g, ldg,
@@ -1720,6 +1740,7 @@ px_status px_poset_info(const px_poset* p, px_info* o) {
   o->run_chunks = p->run_cptr[0].empty() ? 0 : p->run_cptr[0].back();
   o->run_events = p->run_events[0];
   o->path_cover = P.path_cover;
+  o->layout = p->layout;
   return PX_OK;
 }
 
@@ -1727,6 +1748,37 @@ px_status px_poset_chains(const px_poset* p, int32_t* chain_of, int32_t* chain_p
   if (!p || (p->prep.n > 0 && (!chain_of || !chain_pos))) return fail(PX_EINVAL, "null argument");
   std::copy(p->prep.chain_of.begin(), p->prep.chain_of.end(), chain_of);
   std::copy(p->prep.chain_pos.begin(), p->prep.chain_pos.end(), chain_pos);
+  return PX_OK;
+}
+
+px_status px_poset_set_layout(px_poset* p, uint32_t layout) {
+  if (!p) return fail(PX_EINVAL, "null poset");
+  if (layout != PX_LAYOUT_NODES && layout != PX_LAYOUT_ROWS) return fail(PX_EINVAL, "unknown layout");
+  if (p->host_only) return fail(PX_EUNSUPPORTED, "poset was built with PX_BUILD_HOST_ONLY");
+  const int64_t n = p->prep.n;
+  if (layout == PX_LAYOUT_ROWS && n > 0) {
+    if (!p->d_iota) {
+      DeviceGuard dg(p->device);
+      if (!dg.ok) return fail(PX_EHIP, "hipSetDevice failed");
+      std::vector<int32_t> iota(n);
+      for (int64_t r = 0; r < n; ++r) iota[r] = (int32_t)r;
+      const hipError_t e = upload(&p->d_iota, iota.data(), iota.size(), p->device_bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p->d_iota = nullptr;
+        return fail(e == hipErrorOutOfMemory ? PX_ENOMEM : PX_EHIP, "row layout table");
+      }
+    }
+    p->dp.node_of_row = p->d_iota;
+    // the uniform level solve's level-ordered ids: the rows themselves
+    p->dp.lev_node[0] = p->d_lev_node[0] ? p->d_lev_down : nullptr;
+    p->dp.lev_node[1] = p->d_lev_node[1] ? p->d_lev_up : nullptr;
+  } else {
+    p->dp.node_of_row = p->d_node_of_row;
+    p->dp.lev_node[0] = p->d_lev_node[0];
+    p->dp.lev_node[1] = p->d_lev_node[1];
+  }
+  p->layout = layout;
   return PX_OK;
 }
 
@@ -1795,9 +1847,8 @@ px_status px_reserve(px_poset* p, int dtype, int64_t B) {
   if (dtype != PX_I64 && dtype != PX_F32 && dtype != PX_F64) return fail(PX_EINVAL, "unknown dtype");
   if (B < 1) return fail(PX_EINVAL, "B must be >= 1");
   DeviceGuard dg(p->device);
-  const int64_t nt = p->ntiles[px::seg_index(px::col_width(B))];
   return p->ws.ensure(
-      layout(p->prep.n, B, dtype, dtype == PX_F32, nt, std::max(p->nsnap[0], p->nsnap[1]), max_slots(p),
+      layout(p->prep.n, B, dtype, dtype == PX_F32, ws_tiles(p, B), std::max(p->nsnap[0], p->nsnap[1]), max_slots(p),
              max_parts(p), dtype == PX_I64 ? flow_ints(p, B) : 0).total);
 }
 

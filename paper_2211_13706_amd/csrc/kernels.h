@@ -160,8 +160,9 @@ hipError_t launch_gather(const DevPoset& d, bool up, ElemType tp, const void* P,
                          int64_t ldr, void* snaps, LaunchHook* hook, hipStream_t s);
 
 // Zeta (dir=+1, niv map) or its adjoint (dir=-1, up map) through the
-// compact walk, for a single poset with k <= 64 and col_width(B) == 64 whose
-// walk tables have the compact form:
+// compact walk, for a single poset with k <= 64 whose walk tables have the
+// compact form (64-column tiles; with B < 64 the columns beyond B are masked
+// and ntiles is the count of 64-row tiles whatever B is):
 //   0. tile totals, and the tile-local prefixes at the gathered rows (L);
 //   1. tile carries, and Q = carry + L at the gathered rows, Q[nslots] = 0;
 //   2. walk events on Q into snapshots;

@@ -2267,8 +2267,8 @@ hipError_t launch_chain_scan_phase(int phase, const DevPoset& d, int dir, ElemTy
 
 bool compact_ok(const DevPoset& d, bool up, int64_t B) {
   const WalkTables& w = d.walk[up ? 1 : 0];
-  return d.n > 0 && !d.poset_of_row && d.k <= 64 && col_width(B) == 64 && w.runs && w.tmask && w.qoff &&
-         w.init && w.snap_of_row;
+  return d.n > 0 && B >= 1 && !d.poset_of_row && d.k <= 64 && w.runs && w.tmask && w.qoff && w.init &&
+         w.snap_of_row;
 }
 
 hipError_t launch_zeta_compact(const DevPoset& d, int dir, ElemType tin, const void* x, int64_t ldx, ElemType tout,

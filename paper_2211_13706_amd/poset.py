@@ -121,6 +121,13 @@ class Poset:
         _lib.check(_lib.lib().px_poset_rows(self.handle, out.ctypes.data), "px_poset_rows")
         return out
 
+    def set_layout(self, layout: str) -> None:
+        """"nodes" (default): matrix row x is node x; "rows": matrix row r is chain-major row r
+        (self.rows()), the order the kernels run in (px_poset_set_layout)."""
+        code = {"nodes": _lib.PX_LAYOUT_NODES, "rows": _lib.PX_LAYOUT_ROWS}[layout]
+        _lib.check(_lib.lib().px_poset_set_layout(self.handle, code), "px_poset_set_layout")
+        self.info = self.info_dict()
+
     def niv(self, up: bool = False) -> np.ndarray:
         out = np.empty((self.n, self.k), np.int32)
         _lib.check(_lib.lib().px_poset_niv(self.handle, int(up), out.ctypes.data), "px_poset_niv")
