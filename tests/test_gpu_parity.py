@@ -479,6 +479,28 @@ def test_min_chains_transforms_exact(px, n, deg, seed):
     check_f32_zeta(H(px.zeta(P, T(ff))), O.zeta(R, ff, exact=False), O.zeta(R, np.abs(ff).astype(np.float64), exact=False))
 
 
+@pytest.mark.parametrize("B", [1, 8, 16, 32])
+def test_masked_compact_walk_for_narrow_blocks(px, cfg0, B, monkeypatch):
+    """POSETX_COMPACT_NARROW=1: narrow blocks through the compact walk in 64-column
+    tiles (columns beyond B masked) equal the scan over P and the oracle: int64
+    bit-exact, float32 zeta and the refinement residual within the bound."""
+    p, R = cfg0
+    P = build(px, p)
+    fi = W.functions(p.n, B, "int", seed=20 + B, lo=-1000, hi=1000)
+    ff = W.functions(p.n, B, "normal", seed=20 + B)
+    g = O.zeta(R, fi).astype(np.float32)        # exact in float32 (|g| < 2**24)
+    base = [H(px.zeta(P, T(fi))), H(px.zeta_adjoint(P, T(fi))), H(px.zeta(P, T(ff))),
+            H(px.mobius(P, T(g), max_refine=3))]
+    monkeypatch.setenv("POSETX_COMPACT_NARROW", "1")
+    got = [H(px.zeta(P, T(fi))), H(px.zeta_adjoint(P, T(fi))), H(px.zeta(P, T(ff))),
+           H(px.mobius(P, T(g), max_refine=3))]
+    assert np.array_equal(got[0], O.zeta(R, fi)) and np.array_equal(got[1], O.zeta_adjoint(R, fi))
+    assert np.array_equal(got[0], base[0]) and np.array_equal(got[1], base[1])
+    check_f32_zeta(got[2], O.zeta(R, ff, exact=False), O.zeta(R, np.abs(ff).astype(np.float64), exact=False))
+    # the refinement's residual through the masked compact walk converges as through P
+    assert rel(got[3], fi) <= max(2 * rel(base[3], fi), 1e-6)
+
+
 @pytest.mark.parametrize("case", ["cfg0", "er", "grid"])
 def test_row_layout_equals_permuted_node_layout(px, case):
     """PX_LAYOUT_ROWS: matrices indexed by chain-major row give the node-order
