@@ -666,6 +666,10 @@ def main():
         "generate_s": round(t_gen, 3),
         "kernel_hash": kernel_hash(),
     }
+    # the host baselines first: the legs below free the headline poset
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(p, f_host, args.cpu_budget)
+        cpu_nk = cpu_nk_baseline(P, p, f_host, value)
     if args.legs == "sparse":
         out["legs"] = {"er_sparse": leg_er_sparse(px, dev, max(2, args.steps // 4))}
     elif args.legs == "chains":
@@ -696,8 +700,8 @@ def main():
             legs["min_chains"] = leg_min_chains(px, dev, max(2, args.steps // 4))
         out["legs"] = legs
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, f_host, args.cpu_budget)
-        out["cpu_nk_baseline"] = cpu_nk_baseline(P, p, f_host, value)
+        out["cpu_baseline"] = cpu
+        out["cpu_nk_baseline"] = cpu_nk
     print(json.dumps(out), flush=True)
 
 
