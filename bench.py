@@ -348,6 +348,26 @@ def leg_batched(px, dev, steps, count=512):
         px.zeta_adjoint_batched(bt, w, out=gw)
     t_graph = _time(graph.replay, steps, sync)
     ok = bool(torch.allclose(gw, f.grad, rtol=0, atol=0))
+    # the same graph with the matrices in the kernels' row order (px_batch_set_layout)
+    perm = torch.from_numpy(bt.row_order()).to(dev)
+    fr = torch.empty_like(fd)
+    fr[perm] = fd
+    wr = torch.empty_like(w)
+    wr[perm] = w
+    gr = torch.empty_like(g)
+    gwr = torch.empty_like(gw)
+    bt.set_layout("rows")
+    with torch.cuda.stream(s):
+        px.zeta_batched(bt, fr, out=gr)
+        px.zeta_adjoint_batched(bt, wr, out=gwr)
+    torch.cuda.current_stream().wait_stream(s)
+    graph_r = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph_r):
+        px.zeta_batched(bt, fr, out=gr)
+        px.zeta_adjoint_batched(bt, wr, out=gwr)
+    t_graph_r = _time(graph_r.replay, steps, sync)
+    rows_equal = bool(torch.equal(gr[perm], g) and torch.equal(gwr[perm], gw))
+    bt.set_layout("nodes")
     # compulsory bytes of forward + adjoint: per direction the niv map (4k B per row)
     # and f, P written, P read and g (4 B per row and RHS each)
     nk = sum(int(P.n) * int(P.k) for P in Ps)
@@ -358,7 +378,9 @@ def leg_batched(px, dev, steps, count=512):
             "autograd_fwd_bwd_ms": round(t_eager * 1e3, 4), "graph_fwd_adj_ms": round(t_graph * 1e3, 4),
             "node_rhs_per_s_graph": 2 * bt.rows * Bb / t_graph, "graph_grad_equal_eager": ok,
             "alg_bytes": alg, "hbm_floor_ms": round(floor_ms, 4),
-            "frac_of_floor": round(floor_ms / (t_graph * 1e3), 4)}
+            "frac_of_floor": round(floor_ms / (t_graph * 1e3), 4),
+            "graph_fwd_adj_rows_layout_ms": round(t_graph_r * 1e3, 4), "rows_layout_equal": rows_equal,
+            "frac_of_floor_rows_layout": round(floor_ms / (t_graph_r * 1e3), 4)}
 
 
 def leg_large(px, dev, steps):

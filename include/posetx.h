@@ -126,6 +126,10 @@ typedef struct {
                              the chains (k is smaller with PX_BUILD_MIN_CHAINS); 0 for
                              planted or loaded chains                                    */
   int64_t layout;         /* PX_LAYOUT_NODES or PX_LAYOUT_ROWS (px_poset_set_layout)     */
+  int64_t scan_flat;      /* bit i set: the chain scan for blocks of 2^i columns
+                             (i < 6) runs over fixed blocks of rows, a chain start
+                             resetting the sum, instead of tiles cut per chain (chosen
+                             when most chains are short)                               */
 } px_info;
 
 typedef struct {
@@ -297,6 +301,17 @@ px_status px_zeta_batched(px_batch* b, int dtype, const void* f, int64_t ldf, vo
                           int64_t ldg, int64_t B, void* stream);
 px_status px_zeta_adjoint_batched(px_batch* b, int dtype, const void* w, int64_t ldw, void* out,
                                   int64_t ldo, int64_t B, void* stream);
+/* Layout of the batch's function matrices, as px_poset_set_layout for one poset:
+ * PX_LAYOUT_NODES (default) stacks each poset's matrix in node order;
+ * PX_LAYOUT_ROWS stacks each poset's chain-major rows (px_poset_rows), so that
+ * the scans read and the gathers write the matrices in order.  Results are the
+ * same values, bit for bit, permuted the same way.  The first switch to rows
+ * allocates one int32 table of px_batch_rows entries; not to be called while a
+ * transform on the batch is in flight or under graph capture.
+ * px_batch_row_order: row_of_node[x] = batch row of batch node x (o_i + node),
+ * px_batch_rows entries (the permutation a caller applies to switch layouts). */
+px_status px_batch_set_layout(px_batch* b, uint32_t layout);
+px_status px_batch_row_order(const px_batch* b, int64_t* row_of_node);
 
 /* Report of an autotuning call. */
 typedef struct {

@@ -30,6 +30,7 @@ EXPORTS = [
     "px_zeta_adjoint_batched", "px_last_error", "px_version", "px_profile", "px_profile_read",
     "px_profile_phase_name", "px_autotune", "px_batch_autotune", "px_poset_niv_csr", "px_poset_rows",
     "px_poset_save", "px_poset_load", "px_zeta_noalloc", "px_poset_set_layout",
+    "px_batch_set_layout", "px_batch_row_order",
 ]
 
 
@@ -49,7 +50,7 @@ class Info(ctypes.Structure):
         (name, ctypes.c_double) for name in ("t_validate", "t_chains", "t_niv", "t_levels", "t_upload")] + [
         ("niv_sparse", ctypes.c_int32), ("niv_device_rounds", ctypes.c_int32),
         ("run_chunks", ctypes.c_int64), ("run_events", ctypes.c_int64), ("path_cover", ctypes.c_int64),
-        ("layout", ctypes.c_int64)]
+        ("layout", ctypes.c_int64), ("scan_flat", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -84,6 +85,8 @@ def _declare(lib):
         "px_poset_niv_csr": [P, i32, P, P],
         "px_poset_rows": [P, P],
         "px_poset_set_layout": [P, u32],
+        "px_batch_set_layout": [P, u32],
+        "px_batch_row_order": [P, P],
         "px_poset_save": [P, ctypes.c_char_p],
         "px_poset_load": [ctypes.c_char_p, u32, i32, ctypes.POINTER(P)],
         "px_poset_levels": [P, i32, P],

@@ -104,6 +104,20 @@ void seg_tables(const std::vector<int32_t>& chain_off, std::vector<int32_t>& seg
   }
 }
 
+// Tile heights (bit i: seg_rows(1 << i), narrow blocks only) whose scan takes
+// flat tiles (rows in fixed blocks, chain starts resetting the sum): where
+// chain-aligned tiles would be at most 80% full and no chain spans more than
+// 64 flat tiles (the carry of a flat tile folds the earlier tiles of its chain).
+uint32_t flat_mask(int64_t n, int32_t max_chain, const int64_t ntiles[7], const int32_t max_chain_tiles[7]) {
+  uint32_t m = 0;
+  for (int i = 0; i < 6; ++i) {
+    const int64_t H = px::seg_rows(1 << i);
+    const int64_t nft = (n + H - 1) / H;
+    if (max_chain_tiles[i] > 1 && 5 * nft <= 4 * ntiles[i] && max_chain <= 64 * H) m |= 1u << i;
+  }
+  return m;
+}
+
 // For each tile height (as seg_tables): {first row, end row of its chain} of
 // every tile, concatenated over the heights, and the most tiles of any chain.
 std::vector<int32_t> tile_tables(const std::vector<int32_t>& chain_off, int64_t off[8], int32_t maxt[7]) {
@@ -595,6 +609,9 @@ struct px_batch {
   int32_t* d_walk[2][5] = {{nullptr, nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr, nullptr}};
   int32_t nsnap[2] = {0, 0};
   int64_t ntiles[7] = {0, 0, 0, 0, 0, 0, 0};
+  std::vector<int32_t> node_of_row;  // batch node (poset offset + node) of every batch row
+  uint32_t layout = PX_LAYOUT_NODES;  // px_batch_set_layout
+  int32_t* d_iota = nullptr;          // identity row table of the row layout
   px::DevPoset dp;
   Workspace ws;
 };
@@ -1174,6 +1191,8 @@ hipError_t set_walk(px_poset* p, int T, int emax) {
         if (evd[x] < 0) evd[x] = (int32_t)P.n;
         if (evd[x + 1] < 0) evd[x + 1] = (int32_t)P.n;
       }
+      // one padding record (no event), so that record loads may clamp to a run's end
+      evd.insert(evd.end(), {(int32_t)P.n, (int32_t)P.n, -1, 0});
       e = upload(&db[1], evd.data(), evd.size(), b);
     }
     if (e == hipSuccess) e = upload(&db[2], W.ev_off.data(), W.ev_off.size(), b);
@@ -1408,6 +1427,7 @@ static px_status finish_poset(px_poset* p, int device, px_poset** out) {
       int64_t off[8];
       std::vector<int32_t> tt = tile_tables(P.chain_off, off, p->dp.max_chain_tiles);
       p->dp.max_chain = (int32_t)P.max_chain;
+      p->dp.flat_mask = flat_mask(P.n, p->dp.max_chain, p->ntiles, p->dp.max_chain_tiles);
       for (int i = 0; i < 7; ++i)
         if (off[i + 1] - off[i] != p->ntiles[i]) e = hipErrorInvalidValue;
       if (e == hipSuccess) e = upload(&p->d_tiles, tt.data(), tt.size(), b);
@@ -1745,6 +1765,7 @@ px_status px_poset_info(const px_poset* p, px_info* o) {
   o->run_events = p->run_events[0];
   o->path_cover = P.path_cover;
   o->layout = p->layout;
+  o->scan_flat = p->dp.flat_mask;
   return PX_OK;
 }
 
@@ -2036,6 +2057,7 @@ px_status px_batch_build(int count, px_poset* const* posets, px_batch** out) {
     std::vector<int32_t> tt = tile_tables(chain_off, off, b->dp.max_chain_tiles);
     for (size_t c = 0; c + 1 < chain_off.size(); ++c)
       b->dp.max_chain = std::max(b->dp.max_chain, chain_off[c + 1] - chain_off[c]);
+    b->dp.flat_mask = flat_mask(rows, b->dp.max_chain, b->ntiles, b->dp.max_chain_tiles);
     for (int i = 0; i < 7; ++i)
       if (off[i + 1] - off[i] != b->ntiles[i]) e = hipErrorInvalidValue;
     if (e == hipSuccess) e = upload(&b->d_tiles, tt.data(), tt.size(), bytes);
@@ -2078,6 +2100,7 @@ px_status px_batch_build(int count, px_poset* const* posets, px_batch** out) {
       eo += (int32_t)(qe.size() / 4);
       so += q->nsnap[dir];
     }
+    ev.insert(ev.end(), {(int32_t)rows, (int32_t)rows, -1, 0});  // padding record, as for one poset
     b->nsnap[dir] = so;
     px::WalkTables& t = b->dp.walk[dir];
     t.nruns = (int32_t)(runs.size() / 2);
@@ -2113,7 +2136,39 @@ px_status px_batch_build(int count, px_poset* const* posets, px_batch** out) {
   d.poset_of_row = b->d_poset_of_row;
   d.k_of_poset = b->d_k;
   d.row_off = b->d_row_off;
+  b->node_of_row = std::move(node_of_row);
   *out = b;
+  return PX_OK;
+}
+
+px_status px_batch_set_layout(px_batch* b, uint32_t layout) {
+  if (!b) return fail(PX_EINVAL, "null batch");
+  if (layout != PX_LAYOUT_NODES && layout != PX_LAYOUT_ROWS) return fail(PX_EINVAL, "unknown layout");
+  if (layout == PX_LAYOUT_ROWS && b->rows > 0) {
+    if (!b->d_iota) {
+      DeviceGuard dg(b->device);
+      if (!dg.ok) return fail(PX_EHIP, "hipSetDevice failed");
+      std::vector<int32_t> iota(b->rows);
+      for (int64_t r = 0; r < b->rows; ++r) iota[r] = (int32_t)r;
+      int64_t bytes = 0;
+      const hipError_t e = upload(&b->d_iota, iota.data(), iota.size(), bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b->d_iota = nullptr;
+        return fail(e == hipErrorOutOfMemory ? PX_ENOMEM : PX_EHIP, "row layout table");
+      }
+    }
+    b->dp.node_of_row = b->d_iota;
+  } else {
+    b->dp.node_of_row = b->d_node_of_row;
+  }
+  b->layout = layout;
+  return PX_OK;
+}
+
+px_status px_batch_row_order(const px_batch* b, int64_t* row_of_node) {
+  if (!b || (b->rows > 0 && !row_of_node)) return fail(PX_EINVAL, "null argument");
+  for (int64_t r = 0; r < b->rows; ++r) row_of_node[b->node_of_row[r]] = r;
   return PX_OK;
 }
 
@@ -2122,7 +2177,7 @@ px_status px_batch_free(px_batch* b) {
   DeviceGuard dg(b->device);
   int32_t* bufs[] = {b->d_node_of_row, b->d_chain_of_row, b->d_chain_off, b->d_niv,     b->d_niv_up,
                      b->d_segoff,      b->d_poset_of_row,  b->d_k,         b->d_row_off, b->d_order,
-                     b->d_tiles};
+                     b->d_tiles,       b->d_iota};
   for (int32_t* q : bufs)
     if (q) (void)hipFree(q);
   if (b->d_niv_off) (void)hipFree(b->d_niv_off);

@@ -17,7 +17,8 @@ enum ElemType { E_I64 = 0, E_F32 = 1, E_F64 = 2 };
 // Runs of the walking gather (see k_walk_events): run s covers rows
 // [runs[s].x, runs[s].y) of one chain; its niv change events are
 // ev[ev_off[s] .. ev_off[s+1]), each {new row, old row, (row offset << 8) | chain, 0}
-// (-1 = none), sorted by row offset, own chain excluded; it owns snapshots
+// (-1 = none), sorted by row offset, own chain excluded (ev keeps one padding
+// record {n, n, -1, 0} after the last run's); it owns snapshots
 // [snap_off[s], snap_off[s+1]) (first row, then every row with events), and
 // snap_of_row[r] is the snapshot that row r adds to its own P[r].
 // Event rows name row n (a zero row of P that the scan keeps zero) for "no
@@ -98,6 +99,9 @@ struct DevPoset {
   const int2* tiles[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int32_t max_chain_tiles[7] = {0, 0, 0, 0, 0, 0, 0};
   int32_t max_chain = 0;                // rows of the longest chain
+  // tile heights (bit segi) whose narrow-block scan takes flat tiles: rows in
+  // fixed blocks of seg_rows, a chain start resetting the sum (short chains)
+  uint32_t flat_mask = 0;
   // tables of the walking gather, [0] for niv (zeta), [1] for the up-niv map
   WalkTables walk[2];
   // level solves, [0] down / [1] up: the niv rows (k entries each) and node ids

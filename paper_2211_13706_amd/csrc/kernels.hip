@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 #include "kernels.h"
@@ -576,6 +577,187 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
   }
 }
 
+// Flat tiles (narrow column blocks of posets with short chains, such as
+// batches of small posets): tile t holds rows [t * H, min(n, t * H + H)),
+// H = seg_rows(cw), whatever chains they belong to, so every tile but the last
+// is full; chain-aligned tiles of chains much shorter than H are mostly empty.
+// The scan is segmented: a chain's first row in scan order (its bottom row for
+// dir > 0, its top row for dir < 0) starts a new sum.  Phases as for the
+// chain-aligned scan:
+//   0. A[t]: the compensated total of tile t's last segment in scan order;
+//   1. C[t]: the fold, in scan order, of A over the earlier tiles of the chain
+//      open at tile t's first row in scan order (zero when it starts there);
+//   2. the segmented scan inside each tile from C[t], written to P.
+// Row r starts a segment when its neighbour below (dir > 0) or above (dir < 0)
+// belongs to another chain.
+__device__ inline bool flat_seg_start(const int32_t* __restrict__ cor, int64_t n, int64_t r, int dir) {
+  const int64_t q = r - dir;
+  return q < 0 || q >= n || cor[q] != cor[r];
+}
+
+// Segmented fold: (seen, st) after (f, x) is x when f (a start inside x), else st + x.
+template <typename St>
+__device__ inline void seg_fold(St& st, bool f, const St& x) {
+  if (f) st = x;
+  else st.combine(x);
+}
+
+template <typename Tin, typename Tout>
+struct FlatRows {
+  using Tr = ScanTraits<Tin, Tout>;
+  using Tv = decltype(Tr::in(Tin()));
+  Tv v[RPT];
+  bool seg[RPT];
+  // the RPT rows of row group rg of tile t: values (zero beyond n) and segment starts
+  __device__ void load(const DevPoset& d, int64_t t, int H, int rg, int dir, const Tin* __restrict__ x, int64_t ldx,
+                       int64_t colc) {
+    const int64_t n = d.n;
+    const int64_t r0 = t * H + (int64_t)rg * RPT;
+    int32_t nodes[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) nodes[i] = d.node_of_row[min(r0 + i, n - 1)];
+    Tin raw[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) raw[i] = __builtin_nontemporal_load(&x[(int64_t)nodes[i] * ldx + colc]);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) seg[i] = r0 + i < n && flat_seg_start(d.chain_of_row, n, r0 + i, dir);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) v[i] = r0 + i < n ? Tr::in(raw[i]) : Tv(0);
+  }
+  // this row group's own (seen, total of its last segment) in scan order
+  template <typename St>
+  __device__ void local(int dir, bool& seen, St& st) const {
+    seen = false;
+    st.zero();
+    auto step = [&](int i) {
+      if (seg[i]) {
+        st.zero();
+        seen = true;
+      }
+      st.add(v[i]);
+    };
+    if (dir > 0) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) step(i);
+    } else {
+#pragma unroll
+      for (int i = RPT - 1; i >= 0; --i) step(i);
+    }
+  }
+};
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(WG) void k_scan_reduce_flat(DevPoset d, int cw, int dir, const Tin* __restrict__ x,
+                                                         int64_t ldx, int64_t B,
+                                                         typename ScanTraits<Tin, Tout>::St* __restrict__ A) {
+  using St = typename ScanTraits<Tin, Tout>::St;
+  __shared__ St sm[WG];
+  __shared__ int sf[WG];
+  const int RG = WG / cw, H = RG * RPT;
+  const int64_t t = blockIdx.x;
+  const int lane = threadIdx.x % cw, rg = threadIdx.x / cw;
+  const int64_t col = (int64_t)blockIdx.y * cw + lane;
+  FlatRows<Tin, Tout> fr;
+  fr.load(d, t, H, rg, dir, x, ldx, col < B ? col : 0);
+  bool seen;
+  St st;
+  fr.local(dir, seen, st);
+  sm[threadIdx.x] = st;
+  sf[threadIdx.x] = seen;
+  __syncthreads();
+  if (rg == 0 && col < B) {
+    St acc;
+    acc.zero();
+    if (dir > 0) {
+      for (int g = 0; g < RG; ++g) seg_fold(acc, sf[g * cw + lane] != 0, sm[g * cw + lane]);
+    } else {
+      for (int g = RG - 1; g >= 0; --g) seg_fold(acc, sf[g * cw + lane] != 0, sm[g * cw + lane]);
+    }
+    A[t * B + col] = acc;
+  }
+}
+
+// One thread per (tile, column); also clears row n of P (the walk's zero row).
+template <typename St, typename Tout>
+__global__ __launch_bounds__(WG) void k_scan_carry_flat(DevPoset d, int H, int64_t ntiles, int dir, int64_t B,
+                                                        const St* __restrict__ A, St* __restrict__ C,
+                                                        Tout* __restrict__ P) {
+  const int64_t idx = (int64_t)blockIdx.x * WG + threadIdx.x;
+  const int64_t t = idx / B, col = idx % B;
+  if (t >= ntiles) return;
+  const int64_t n = d.n;
+  if (t == 0) P[n * B + col] = Tout(0);
+  const int64_t first = dir > 0 ? t * H : min(n, t * H + H) - 1;  // the tile's first row in scan order
+  const int c = d.chain_of_row[first];
+  const int64_t start = dir > 0 ? d.chain_off[c] : d.chain_off[c + 1] - 1;
+  const int64_t u0 = start / H;
+  St acc;
+  acc.zero();
+  if (u0 != t) {
+    acc = A[u0 * B + col];
+    for (int64_t u = u0 + dir; u != t; u += dir) acc.combine(A[u * B + col]);
+  }
+  C[t * B + col] = acc;
+}
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(WG) void k_scan_apply_flat(DevPoset d, int cw, int dir, const Tin* __restrict__ x,
+                                                        int64_t ldx, int64_t B,
+                                                        const typename ScanTraits<Tin, Tout>::St* __restrict__ C,
+                                                        Tout* __restrict__ P) {
+  using Tr = ScanTraits<Tin, Tout>;
+  using St = typename Tr::St;
+  __shared__ St sm[WG];
+  __shared__ int sf[WG];
+  const int RG = WG / cw, H = RG * RPT;
+  const int64_t t = blockIdx.x;
+  const int lane = threadIdx.x % cw, rg = threadIdx.x / cw;
+  const int64_t col = (int64_t)blockIdx.y * cw + lane;
+  FlatRows<Tin, Tout> fr;
+  fr.load(d, t, H, rg, dir, x, ldx, col < B ? col : 0);
+  bool seen;
+  St loc;
+  fr.local(dir, seen, loc);
+  sm[threadIdx.x] = loc;
+  sf[threadIdx.x] = seen;
+  __syncthreads();
+  // inclusive segmented scan over the row groups in scan order, log2(RG) steps
+  for (int off = 1; off < RG; off <<= 1) {
+    const int src = dir > 0 ? rg - off : rg + off;
+    const bool has = src >= 0 && src < RG;
+    St a;
+    int fa = 0;
+    if (has) {
+      a = sm[src * cw + lane];
+      fa = sf[src * cw + lane];
+    }
+    __syncthreads();
+    if (has) {
+      seg_fold(a, sf[threadIdx.x] != 0, sm[threadIdx.x]);
+      sm[threadIdx.x] = a;
+      sf[threadIdx.x] = fa | sf[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (col >= B) return;
+  St st = C[t * B + col];
+  const int src = dir > 0 ? rg - 1 : rg + 1;
+  if (src >= 0 && src < RG) seg_fold(st, sf[src * cw + lane] != 0, sm[src * cw + lane]);
+  const int64_t r0 = t * H + (int64_t)rg * RPT;
+  auto step = [&](int i) {
+    if (fr.seg[i]) st.zero();
+    st.add(fr.v[i]);
+    if (r0 + i < d.n) P[(r0 + i) * B + col] = Tr::out(st.value());
+  };
+  if (dir > 0) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) step(i);
+  } else {
+#pragma unroll
+    for (int i = RPT - 1; i >= 0; --i) step(i);
+  }
+}
+
 // Single-pass chain scan with a deterministic multi-level look-back.
 //
 // Workgroups take tiles (and column blocks) in scan-position-major order of
@@ -1101,6 +1283,7 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
     k = d.k;
     nr = nv + (int64_t)r0 * k;
   }
+  const int klast = k - 1;  // entries load from nr[min(j, klast)] (k >= 1) and are masked after
   if (!active) k = 0;
   int kmax = k;
 #pragma unroll
@@ -1111,7 +1294,9 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
     // the first row's entries 16 at a time, two per lane of the run's group,
     // shared by lane shuffles; the next 16 load with this group's gathers
     const int sub = lane % cw, base = lane - sub, s8 = sub & 7;
-    auto ent = [&](int j) { return j < k ? nr[j] : -1; };
+    auto ent = [&](int j) {  // OR-ing the mask keeps the load unconditional (no branch)
+      return nr[min(j, klast)] | (j < k ? 0 : -1);
+    };
     int ta = ent(s8), tb = ent(8 + s8);
     for (int j0 = 0; j0 < kmax; j0 += 16) {
       const int na = ent(j0 + 16 + s8), nb = ent(j0 + 24 + s8);
@@ -1158,19 +1343,25 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) nemax = max(nemax, __shfl_xor(nemax, off));
   if (cw >= 8) {
-    // Groups of 16 events: lane j of the run's cw lanes loads records j & 7 and
-    // 8 + (j & 7) (two loads for the group), the fields go round the group by
-    // lane shuffles, and the next group's records load while this group's 32
-    // gathers are in flight.
+    // Groups of 16 events: lane j of the run's cw lanes holds records j & 7 and
+    // 8 + (j & 7), the fields go round the group by lane shuffles, and the next
+    // group's records load behind this group's 32 gathers, so that their wait
+    // overlaps this group's sums.  A row's snapshot is stored when the first
+    // event of a later row comes (or after the last event), which needs nothing
+    // of the next group.  Record indices clamp to the run's end: the tables
+    // keep one padding record after the last run.
     const int sub = lane % cw, base = lane - sub, s8 = sub & 7;
-    const int4 none = make_int4(-1, -1, -1, 0);
-    auto rec = [&](int i) { return i < ne ? w.ev[e0 + i] : none; };
+    auto rec = [&](int i) {  // OR-ing the mask keeps the load unconditional (no branch)
+      const int4 r = w.ev[e0 + min(i, ne)];
+      const int no = i < ne ? 0 : -1;
+      return make_int4(r.x | no, r.y | no, r.z | no, 0);
+    };
     int4 ra = rec(s8), rb = rec(8 + s8);
+    int uprev = -1;  // row offset of the last event applied (-1: none yet)
     for (int g0 = 0; g0 < nemax; g0 += 16) {
-      const int4 na = rec(g0 + 16 + s8), nb = rec(g0 + 24 + s8);
       TP vn[16], vo[16];
       bool okn[16], oko[16];
-      int ue[17], ex[16], ey[16];
+      int ue[16], ex[16], ey[16];
       // all shuffles first (one wait for the lot), then all gathers
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
@@ -1187,20 +1378,25 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
         vn[q] = P[(int64_t)(okn[q] ? ex[q] : r0) * B + colc];
         vo[q] = P[(int64_t)(oko[q] ? ey[q] : r0) * B + colc];
       }
-      ue[16] = __shfl(na.z, base) >> 8;
+      ra = rec(g0 + 16 + s8);
+      rb = rec(g0 + 24 + s8);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         if (ue[q] >= 0) {
-          if (okn[q]) acc += (W)vn[q];
-          if (oko[q]) acc -= (W)vo[q];
-          if (ue[q + 1] != ue[q]) {
+          if (uprev >= 0 && ue[q] != uprev) {  // row uprev is complete
             m = min(m + 1, mlast);
             if (colok) S[m * B + col] = (TP)acc;
           }
+          if (okn[q]) acc += (W)vn[q];
+          if (oko[q]) acc -= (W)vo[q];
+          uprev = ue[q];
         }
       }
-      ra = na;
-      rb = nb;
+    }
+    if (uprev >= 0) {
+      m = min(m + 1, mlast);
+      if (colok) S[m * B + col] = (TP)acc;
     }
     return;
   }
@@ -1234,6 +1430,148 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
         }
       }
     }
+  }
+}
+
+// Vector-lane form of the lane-split walk (B a multiple of V = 16 / sizeof(TP)):
+// a lane carries V consecutive columns, so each gathered row is one 16-byte
+// load and a wavefront gathers 64 / L rows per load instruction, L = cw / V
+// lanes per run (2 <= L <= 16), instead of 64 / cw.  The vector memory unit
+// of a compute unit spends its time per row touched, so narrow blocks gather
+// several times faster this way.  Events and first-row entries are shared by
+// the run's L lanes as in the lane-split form; EG events per group.
+template <typename TP, int L, int EG>
+__global__ __launch_bounds__(WG) void k_walk_events_vec(DevPoset d, const int32_t* __restrict__ nv, WalkTables w,
+                                                        const TP* __restrict__ P, int64_t B, TP* __restrict__ S) {
+  using W = typename Wide<TP>::W;
+  constexpr int V = 16 / sizeof(TP);
+  using VT = TP __attribute__((ext_vector_type(V)));
+  static_assert(L >= 2 && L <= 16 && EG % L == 0 && 16 % L == 0, "lanes per run");
+  constexpr int NSUB = 64 / L;  // runs per wavefront
+  const int lane = threadIdx.x & 63;
+  const int nblk = (int)gridDim.x, q8 = nblk >> 3, r8 = nblk & 7;
+  const int xcd = (int)(blockIdx.x & 7), slot = (int)(blockIdx.x >> 3);
+  const int blk = xcd * q8 + min(xcd, r8) + slot;
+  const int64_t run = ((int64_t)blk * (WG / 64) + (threadIdx.x >> 6)) * NSUB + lane / L;
+  const int sub = lane % L, base = lane - sub;
+  const int64_t col = (int64_t)sub * V;  // B % V == 0: the lane's V columns are all in or all out
+  const bool active = run < w.nruns;
+  const bool colok = active && col < B;
+  const int64_t colc = col < B ? col : 0;
+  const int64_t runc = active ? run : 0;
+  const int r0 = w.runs[runc].x;
+  int k;
+  const int32_t* nr;
+  if (d.poset_of_row) {
+    const int p = d.poset_of_row[r0];
+    k = d.k_of_poset[p];
+    nr = nv + d.niv_off[p] + (int64_t)(r0 - d.row_off[p]) * k;
+  } else {
+    k = d.k;
+    nr = nv + (int64_t)r0 * k;
+  }
+  const int klast = k - 1;
+  if (!active) k = 0;
+  int kmax = k;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) kmax = max(kmax, __shfl_xor(kmax, off));
+  auto row = [&](int t) { return *(const VT*)(P + (int64_t)t * B + colc); };
+
+  W acc[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) acc[v] = W(0);
+  // first row: 16 entries at a time, 16 / L per lane, shared by shuffles (the
+  // mask is OR-ed in so that the loads stay unconditional)
+  for (int j0 = 0; j0 < kmax; j0 += 16) {
+    int e[16 / L];
+#pragma unroll
+    for (int i = 0; i < 16 / L; ++i) {
+      const int j = j0 + sub + L * i;
+      e[i] = nr[min(j, klast)] | (j < k ? 0 : -1);
+    }
+    int t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) t[u] = __shfl(e[u / L], base + u % L);
+    __builtin_amdgcn_sched_barrier(0);
+    VT vv[16];
+    bool ok[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      ok[u] = t[u] >= 0 && t[u] != r0;
+      vv[u] = row(ok[u] ? t[u] : r0);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (ok[u])
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] += (W)vv[u][v];
+  }
+  int64_t m = w.snap_off[runc];
+  const int64_t mlast = w.snap_off[runc + 1] - 1;
+  auto snap = [&]() {
+    VT o;
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[v] = (TP)acc[v];
+    if (colok) *(VT*)(S + m * B + col) = o;
+  };
+  snap();
+
+  const int e0 = w.ev_off[runc];
+  const int ne = active ? w.ev_off[runc + 1] - e0 : 0;
+  int nemax = ne;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) nemax = max(nemax, __shfl_xor(nemax, off));
+  // record i of this run (clamped to the padding record after the last run)
+  auto rec = [&](int i) {
+    const int4 r = w.ev[e0 + min(i, ne)];
+    const int no = i < ne ? 0 : -1;
+    return make_int4(r.x | no, r.y | no, r.z | no, 0);
+  };
+  constexpr int RL = EG / L;  // records per lane and group
+  int4 ra[RL];
+#pragma unroll
+  for (int i = 0; i < RL; ++i) ra[i] = rec(sub + L * i);
+  int uprev = -1;  // row offset of the last event applied (-1: none yet)
+  for (int g0 = 0; g0 < nemax; g0 += EG) {
+    int ex[EG], ey[EG], ue[EG];
+#pragma unroll
+    for (int q = 0; q < EG; ++q) {
+      ex[q] = __shfl(ra[q / L].x, base + q % L);
+      ey[q] = __shfl(ra[q / L].y, base + q % L);
+      ue[q] = __shfl(ra[q / L].z, base + q % L) >> 8;  // -1: no event
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    VT vn[EG], vo[EG];
+    bool okn[EG], oko[EG];
+#pragma unroll
+    for (int q = 0; q < EG; ++q) {
+      okn[q] = ex[q] >= 0;
+      oko[q] = ey[q] >= 0;
+      vn[q] = row(okn[q] ? ex[q] : r0);
+      vo[q] = row(oko[q] ? ey[q] : r0);
+    }
+#pragma unroll
+    for (int i = 0; i < RL; ++i) ra[i] = rec(g0 + EG + sub + L * i);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < EG; ++q) {
+      if (ue[q] >= 0) {
+        if (uprev >= 0 && ue[q] != uprev) {  // row uprev is complete
+          m = min(m + 1, mlast);
+          snap();
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          if (okn[q]) acc[v] += (W)vn[q][v];
+          if (oko[q]) acc[v] -= (W)vo[q][v];
+        }
+        uprev = ue[q];
+      }
+    }
+  }
+  if (uprev >= 0) {
+    m = min(m + 1, mlast);
+    snap();
   }
 }
 
@@ -1291,6 +1629,17 @@ __global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* 
   }
 }
 
+// The vector-lane walk takes B a multiple of 16 / sizeof(TP) with 2 to 16 lanes
+// per run (POSETX_WALK_VEC=0, read on every call, keeps the lane-split form).
+template <typename TP>
+bool walk_vec_ok(int cw, int64_t B) {
+  constexpr int V = 16 / sizeof(TP);
+  const int L = cw / V;
+  if (B % V != 0 || L < 2 || L > 16) return false;
+  const char* e = std::getenv("POSETX_WALK_VEC");
+  return !(e && e[0] == '0');
+}
+
 template <typename TP>
 hipError_t walk_typed(const DevPoset& d, const int32_t* nv, const WalkTables& w, const void* P, int64_t B, void* out,
                       int64_t ldo, ElemType tres, const void* resid, int64_t ldr, void* snaps, LaunchHook* hook,
@@ -1308,6 +1657,17 @@ hipError_t walk_typed(const DevPoset& d, const int32_t* nv, const WalkTables& w,
     else
       hipLaunchKernelGGL((k_walk_events<TP, false, false>), g, dim3(WG), 0, s, d, nv, w, (const TP*)P, B,
                          (TP*)snaps);
+  } else if (walk_vec_ok<TP>(cw, B)) {
+    constexpr int V = 16 / sizeof(TP);
+    const int L = cw / V;
+    const int64_t waves = (w.nruns + (64 / L) - 1) / (64 / L);
+    const dim3 g((unsigned)((waves + (WG / 64) - 1) / (WG / 64)));
+    const TP* p = (const TP*)P;
+    TP* sn = (TP*)snaps;
+    if (L == 2) hipLaunchKernelGGL((k_walk_events_vec<TP, 2, 16>), g, dim3(WG), 0, s, d, nv, w, p, B, sn);
+    else if (L == 4) hipLaunchKernelGGL((k_walk_events_vec<TP, 4, 16>), g, dim3(WG), 0, s, d, nv, w, p, B, sn);
+    else if (L == 8) hipLaunchKernelGGL((k_walk_events_vec<TP, 8, 16>), g, dim3(WG), 0, s, d, nv, w, p, B, sn);
+    else hipLaunchKernelGGL((k_walk_events_vec<TP, 16, 16>), g, dim3(WG), 0, s, d, nv, w, p, B, sn);
   } else {
     const int64_t waves = (w.nruns + (64 / cw) - 1) / (64 / cw);
     hipLaunchKernelGGL((k_walk_events_split<TP>), dim3((unsigned)((waves + (WG / 64) - 1) / (WG / 64))), dim3(WG),
@@ -2123,6 +2483,15 @@ __global__ __launch_bounds__(WG) void k_scan_chains(DevPoset d, int dir, int cw,
   }
 }
 
+// Flat tiles for tile height segi when the host chose them (d.flat_mask);
+// POSETX_SCAN_FLAT=0 / 1 (read on every call) never / always takes them.
+bool flat_scan(const DevPoset& d, int segi) {
+  const char* e = std::getenv("POSETX_SCAN_FLAT");
+  if (e && e[0] == '0') return false;
+  if (e && e[0] == '1') return d.chain_of_row && d.chain_off;
+  return (d.flat_mask >> segi) & 1u;
+}
+
 template <typename Tin, typename Tout>
 hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int64_t ldx, void* P, int64_t B,
                       void* aux, int64_t ntiles, hipStream_t s) {
@@ -2130,6 +2499,24 @@ hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int6
   const int cw = col_width(B);
   const int segi = seg_index(cw);
   St* A = (St*)aux;
+  if (cw < 64 && flat_scan(d, segi)) {  // flat tiles (see k_scan_reduce_flat)
+    const int H = seg_rows(cw);
+    const int64_t nft = ((int64_t)d.n + H - 1) / H;
+    if (nft > ntiles) return hipErrorInvalidValue;  // aux holds ntiles tile states per column
+    St* Cf = A + ntiles * B;
+    const dim3 gf((unsigned)nft, (unsigned)((B + cw - 1) / cw));
+    if (phase == 0) {
+      hipLaunchKernelGGL((k_scan_reduce_flat<Tin, Tout>), gf, dim3(WG), 0, s, d, cw, dir, (const Tin*)x, ldx, B, A);
+    } else if (phase == 1) {
+      const int64_t threads = nft * B;
+      hipLaunchKernelGGL((k_scan_carry_flat<St, Tout>), dim3((unsigned)((threads + WG - 1) / WG)), dim3(WG), 0, s, d,
+                         H, nft, dir, B, (const St*)A, Cf, (Tout*)P);
+    } else {
+      hipLaunchKernelGGL((k_scan_apply_flat<Tin, Tout>), gf, dim3(WG), 0, s, d, cw, dir, (const Tin*)x, ldx, B,
+                         (const St*)Cf, (Tout*)P);
+    }
+    return hipGetLastError();
+  }
   // when every chain fits one tile (short chains, e.g. wide sparse posets) there
   // are no carries: phases 0 and 1 do nothing and phase 2 scans each tile alone
   const bool one_tile = d.max_chain_tiles[segi] == 1;

@@ -301,6 +301,18 @@ class Batch:
         code = {torch.int64: 0, torch.float32: 1, torch.float64: 2}[dtype]
         _lib.check(_lib.lib().px_batch_reserve(self.handle, code, int(B)), "px_batch_reserve")
 
+    def set_layout(self, layout: str) -> None:
+        """"nodes" (default): each poset's rows in node order; "rows": each poset's chain-major
+        rows (self.row_order()), the order the kernels run in (px_batch_set_layout)."""
+        code = {"nodes": _lib.PX_LAYOUT_NODES, "rows": _lib.PX_LAYOUT_ROWS}[layout]
+        _lib.check(_lib.lib().px_batch_set_layout(self.handle, code), "px_batch_set_layout")
+
+    def row_order(self) -> np.ndarray:
+        """Batch row of every batch node (px_batch_row_order)."""
+        out = np.empty(self.rows, np.int64)
+        _lib.check(_lib.lib().px_batch_row_order(self.handle, out.ctypes.data), "px_batch_row_order")
+        return out
+
     def autotune(self, dtype, B: int) -> dict:
         """Pick the RHS tile of the batched gather by timing the candidates (px_batch_autotune)."""
         import torch

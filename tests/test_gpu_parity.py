@@ -685,6 +685,89 @@ def test_batched_widths_and_dtypes(px, B):
         assert rel(a64[s0:e0], O.zeta_adjoint(R, f64[s0:e0], exact=False)) <= 1e-12
 
 
+# ---------------------------------------------------------- flat scan tiles
+@pytest.mark.parametrize("shape", [(3000, 40, 3), (3000, 4, 2), (2500, 150, 4)])
+@pytest.mark.parametrize("B", [1, 3, 8, 16, 32])
+def test_flat_tile_scan_matches_oracle(px, shape, B, monkeypatch):
+    """The chain scan over flat tiles (fixed blocks of rows whatever chains they hold, a
+    chain's first row in scan order resetting the sum), forced on every poset, against the
+    closure oracle: zeta and its adjoint, int64 exact and float64 to rounding, at column
+    blocks of 1 to 32 (tile heights 4096 down to 128 rows).  Four chains of 750 rows span
+    up to six flat tiles, so carries fold several earlier tiles; 40 and 150 chains put
+    many chain starts inside one tile.  The int64 results also equal those of the
+    chain-aligned tiles bit for bit."""
+    n, k, d = shape
+    p = W.chain_poset(n, k, d, seed=n + k + B)
+    P = build(px, p)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    f = W.functions(p.n, B, "int", seed=B, lo=-10**6, hi=10**6)
+    f64 = W.functions(p.n, B, "normal64", seed=B + 1)
+    out = {}
+    for flat in ("1", "0"):
+        monkeypatch.setenv("POSETX_SCAN_FLAT", flat)
+        out[flat] = (H(px.zeta(P, T(f))), H(px.zeta_adjoint(P, T(f))))
+        if flat == "1":
+            assert np.array_equal(out[flat][0], O.zeta(R, f))
+            assert np.array_equal(out[flat][1], O.zeta_adjoint(R, f))
+            assert rel(H(px.zeta(P, T(f64))), O.zeta(R, f64, exact=False)) <= 1e-12
+            assert rel(H(px.zeta_adjoint(P, T(f64))), O.zeta_adjoint(R, f64, exact=False)) <= 1e-12
+    assert np.array_equal(out["1"][0], out["0"][0]) and np.array_equal(out["1"][1], out["0"][1])
+
+
+def test_flat_tiles_chosen_for_short_chains(px):
+    """Chains of 600 rows fill chain-aligned tiles of 512 rows (8 columns) to 59% and take
+    flat tiles there, but not at 32 columns (128-row tiles, 94% full); chains of 16,384
+    rows fill every tile height and keep chain-aligned tiles.  (Chains within one tile
+    keep the single-pass scan of their own tiles.)"""
+    mid = build(px, W.chain_poset(6000, 10, 2, seed=5)).info_dict()["scan_flat"]
+    assert mid & (1 << 3) and not mid & (1 << 5)
+    long_ = build(px, W.chain_poset(1 << 16, 4, 3, seed=6))
+    assert long_.info_dict()["scan_flat"] == 0
+
+
+@pytest.mark.parametrize("B", [8, 16])
+def test_batched_flat_tiles(px, B, monkeypatch):
+    """A batch of uneven posets through flat and chain-aligned scan tiles: int64 zeta and
+    adjoint equal bit for bit and equal the closure oracle per poset."""
+    posets = W.batched_posets(12, seed=90 + B, nmin=100, nmax=2000)
+    b = px.batch_build([build(px, q) for q in posets])
+    f = W.functions(b.rows, B, "int", seed=91, lo=-1000, hi=1000)
+    res = {}
+    for flat in ("1", "0"):
+        monkeypatch.setenv("POSETX_SCAN_FLAT", flat)
+        res[flat] = (H(px.zeta_batched(b, T(f))), H(px.zeta_adjoint_batched(b, T(f))))
+    assert np.array_equal(res["1"][0], res["0"][0]) and np.array_equal(res["1"][1], res["0"][1])
+    g, a = res["1"]
+    for i, q in enumerate(posets):
+        s0, e0 = b.offsets[i], b.offsets[i + 1]
+        R = O.reachability(q.n, q.indptr, q.indices)
+        assert np.array_equal(g[s0:e0], O.zeta(R, f[s0:e0]))
+        assert np.array_equal(a[s0:e0], O.zeta_adjoint(R, f[s0:e0]))
+
+
+@pytest.mark.parametrize("B", [8, 100])
+def test_batched_row_layout(px, B):
+    """A batch with its matrices in the kernels' row order (px_batch_set_layout): zeta and
+    its adjoint equal the node-order results permuted by px_batch_row_order, bit for bit
+    (int64 and float32), at B = 8 (scans and the vector-lane walk) and B = 100 (the
+    one-thread-per-row gather); switching back restores node order."""
+    import torch
+    posets = W.batched_posets(12, seed=95, nmin=100, nmax=2000)
+    b = px.batch_build([build(px, q) for q in posets])
+    perm = torch.from_numpy(b.row_order()).to(dev())
+    assert np.array_equal(np.sort(b.row_order()), np.arange(b.rows))
+    for kind in ("int", "normal"):
+        f = T(W.functions(b.rows, B, kind, seed=96, lo=-1000, hi=1000))
+        g, a = px.zeta_batched(b, f), px.zeta_adjoint_batched(b, f)
+        fr = torch.empty_like(f)
+        fr[perm] = f
+        b.set_layout("rows")
+        gr, ar = px.zeta_batched(b, fr), px.zeta_adjoint_batched(b, fr)
+        b.set_layout("nodes")
+        assert torch.equal(gr[perm], g) and torch.equal(ar[perm], a)
+        assert torch.equal(px.zeta_batched(b, f), g)
+
+
 # ------------------------------------------------------------ error handling
 def test_argument_errors_and_nonfinite(px, cfg0):
     import torch
