@@ -1630,14 +1630,19 @@ __global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* 
 }
 
 // The vector-lane walk takes B a multiple of 16 / sizeof(TP) with 2 to 16 lanes
-// per run (POSETX_WALK_VEC=0, read on every call, keeps the lane-split form).
+// per run, and enough runs for 2048 wavefronts (it holds twice the registers of
+// the lane-split form, so fewer waves are resident; with few runs, as for one
+// poset of 2^20 elements at B = 8, the lane-split form is faster).
+// POSETX_WALK_VEC=0 / 1 (read on every call) never / always takes it.
 template <typename TP>
-bool walk_vec_ok(int cw, int64_t B) {
+bool walk_vec_ok(int cw, int64_t B, int64_t nruns) {
   constexpr int V = 16 / sizeof(TP);
   const int L = cw / V;
   if (B % V != 0 || L < 2 || L > 16) return false;
   const char* e = std::getenv("POSETX_WALK_VEC");
-  return !(e && e[0] == '0');
+  if (e && e[0] == '0') return false;
+  if (e && e[0] == '1') return true;
+  return nruns / (64 / L) >= 2048;
 }
 
 template <typename TP>
@@ -1657,7 +1662,7 @@ hipError_t walk_typed(const DevPoset& d, const int32_t* nv, const WalkTables& w,
     else
       hipLaunchKernelGGL((k_walk_events<TP, false, false>), g, dim3(WG), 0, s, d, nv, w, (const TP*)P, B,
                          (TP*)snaps);
-  } else if (walk_vec_ok<TP>(cw, B)) {
+  } else if (walk_vec_ok<TP>(cw, B, w.nruns)) {
     constexpr int V = 16 / sizeof(TP);
     const int L = cw / V;
     const int64_t waves = (w.nruns + (64 / L) - 1) / (64 / L);

@@ -768,6 +768,40 @@ def test_batched_row_layout(px, B):
         assert torch.equal(px.zeta_batched(b, f), g)
 
 
+@pytest.mark.parametrize("B", [2, 4, 8, 12, 16, 24, 32, 64])
+def test_vector_lane_walk(px, B, monkeypatch):
+    """The vector-lane walk (each lane gathers 16 bytes of a row: 4 float32 or 2 int64 /
+    float64 columns), forced on, against the lane-split walk bit for bit and the closure
+    oracle, for one poset (B < 32; wider blocks take the uniform walk there) and for a
+    batch, int64, float32 and float64.  Widths that are no multiple of the lane's columns,
+    or give fewer than 2 lanes per run, keep the lane-split walk."""
+    import torch
+    cases = []
+    if B < 32:
+        p = W.chain_poset(3000, 24, 3, seed=B)
+        cases.append(([p], build(px, p), False))
+    posets = W.batched_posets(8, seed=97 + B, nmin=100, nmax=1500)
+    cases.append((posets, px.batch_build([build(px, q) for q in posets]), True))
+    for posets_, h, batched in cases:
+        rows = h.rows if batched else h.n
+        offs = h.offsets if batched else np.array([0, rows])
+        zf, af = ((px.zeta_batched, px.zeta_adjoint_batched) if batched else (px.zeta, px.zeta_adjoint))
+        for kind in ("int", "normal", "normal64"):
+            f = T(W.functions(rows, B, kind, seed=B + 7, lo=-1000, hi=1000))
+            res = {}
+            for vec in ("1", "0"):
+                monkeypatch.setenv("POSETX_WALK_VEC", vec)
+                res[vec] = (zf(h, f), af(h, f))
+            assert torch.equal(res["1"][0], res["0"][0]) and torch.equal(res["1"][1], res["0"][1])
+            if kind == "int":
+                g, a = H(res["1"][0]), H(res["1"][1])
+                for i, q in enumerate(posets_):
+                    s0, e0 = offs[i], offs[i + 1]
+                    R = O.reachability(q.n, q.indptr, q.indices)
+                    assert np.array_equal(g[s0:e0], O.zeta(R, H(f)[s0:e0]))
+                    assert np.array_equal(a[s0:e0], O.zeta_adjoint(R, H(f)[s0:e0]))
+
+
 # ------------------------------------------------------------ error handling
 def test_argument_errors_and_nonfinite(px, cfg0):
     import torch
