@@ -1795,11 +1795,13 @@ px_status px_poset_set_layout(px_poset* p, uint32_t layout) {
       }
     }
     p->dp.node_of_row = p->d_iota;
+    p->dp.ident = 1;
     // the uniform level solve's level-ordered ids: the rows themselves
     p->dp.lev_node[0] = p->d_lev_node[0] ? p->d_lev_down : nullptr;
     p->dp.lev_node[1] = p->d_lev_node[1] ? p->d_lev_up : nullptr;
   } else {
     p->dp.node_of_row = p->d_node_of_row;
+    p->dp.ident = 0;
     p->dp.lev_node[0] = p->d_lev_node[0];
     p->dp.lev_node[1] = p->d_lev_node[1];
   }
@@ -2159,8 +2161,10 @@ px_status px_batch_set_layout(px_batch* b, uint32_t layout) {
       }
     }
     b->dp.node_of_row = b->d_iota;
+    b->dp.ident = 1;
   } else {
     b->dp.node_of_row = b->d_node_of_row;
+    b->dp.ident = 0;
   }
   b->layout = layout;
   return PX_OK;

@@ -83,6 +83,9 @@ struct SegTables {
 struct DevPoset {
   int32_t n = 0, k = 0;           // for a batch: total rows; k = 0 (per-poset k)
   const int32_t* node_of_row = nullptr;
+  // 1: node_of_row is the identity (matrices in row order): kernels use the
+  // row itself and skip the table loads
+  int32_t ident = 0;
   const int32_t* chain_of_row = nullptr;
   const int32_t* chain_off = nullptr;   // chains+1
   int32_t nchains = 0;

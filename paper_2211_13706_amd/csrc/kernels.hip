@@ -43,6 +43,14 @@ int seg_index(int cw) {
 }
 int seg_rows(int cw) { return (WG / cw) * RPT; }
 
+// Every byte offset of a buffer of `bytes` fits an unsigned 32-bit offset
+// (POSETX_O32=0, read on every call, takes 64-bit offsets everywhere).
+bool fits32(int64_t bytes) {
+  const char* e = std::getenv("POSETX_O32");
+  if (e && e[0] == '0') return false;
+  return bytes >= 0 && bytes <= (int64_t)0xffffffffu;
+}
+
 namespace {
 
 constexpr int reduce_tiles(int cwt) { return cwt == 64 ? 1 : 2; }
@@ -119,6 +127,22 @@ __device__ inline int find_chain(const int32_t* so, int nchains, int t) {
   return lo;
 }
 
+// Address of element (row, col) of a matrix with leading dimension ld.  With
+// O32 (the launcher checked that every offset of the matrix fits 32 bits) the
+// offset is a 32-bit lane value from a scalar base: one register per address
+// and no 64-bit multiply.
+template <bool O32, typename T>
+__device__ inline T* elem(T* base, int64_t row, int64_t ld, int64_t col) {
+  if constexpr (O32)
+    return (T*)((char*)base + ((uint32_t)row * (uint32_t)ld + (uint32_t)col) * (uint32_t)sizeof(T));
+  else
+    return base + row * ld + col;
+}
+
+// Matrix row of chain-major row r: the node, or r itself in the row layout
+// (d.ident, uniform), where the table load is skipped.
+__device__ inline int node_at(const DevPoset& d, int64_t r) { return d.ident ? (int)r : d.node_of_row[r]; }
+
 // Phase 1: per tile and column, the compensated total of the tile's rows.  A
 // workgroup reduces reduce_tiles(CWT) tiles: two for narrow column blocks, so
 // that each thread has 2*RPT loads in flight; one for 64-column blocks, whose
@@ -133,7 +157,7 @@ __device__ inline int find_chain(const int32_t* so, int nchains, int t) {
 // first MK marked rows in LDS; after the barrier each of them is combined with
 // the sum of the row groups before it.  A wavefront with more marks (rare)
 // sums its rows again for the rest.
-template <typename Tin, typename Tout, int CWT, bool MARK>
+template <typename Tin, typename Tout, int CWT, bool MARK, bool O32 = false>
 __global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw_rt, const Tin* __restrict__ x,
                                                     int64_t ldx, int64_t B, int64_t ntiles,
                                                     typename ScanTraits<Tin, Tout>::St* __restrict__ A, int dir,
@@ -179,14 +203,14 @@ __global__ __launch_bounds__(WG) void k_scan_reduce(DevPoset d, int segi, int cw
   for (int q = 0; q < NT; ++q)
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      nodes[q][i] = d.node_of_row[min(r0[q] + i, end[q] - 1)];
+      nodes[q][i] = node_at(d, min(r0[q] + i, end[q] - 1));
       if (CWT == 64) nodes[q][i] = __builtin_amdgcn_readfirstlane(nodes[q][i]);
     }
   Tin v[NT][RPT];
 #pragma unroll
   for (int q = 0; q < NT; ++q)
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) v[q][i] = x[(int64_t)nodes[q][i] * ldx + colc];
+    for (int i = 0; i < RPT; ++i) v[q][i] = *elem<O32>(x, nodes[q][i], ldx, colc);
   // MARK: this wavefront's marked rows (bits of its RPT rows, scalar)
   constexpr int MK = 4;
   __shared__ St lm[MARK ? NT * MK : 1][WG];
@@ -432,7 +456,7 @@ __global__ __launch_bounds__(WG) void k_scan_carry_short(DevPoset d, int segi, i
 // the other chains' sum S[snap_of_row[r]] (from the walk) and write the zeta
 // value out[node(r)] = P[r] + S (MODE 1), or the refinement residual
 // out[node(r)] = res[node(r)] - (P[r] + S) (MODE 2).
-template <typename Tin, typename Tout, int CWT, int MODE, typename Tres>
+template <typename Tin, typename Tout, int CWT, int MODE, typename Tres, bool O32 = false>
 __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_rt, int dir,
                                                    const Tin* __restrict__ x, int64_t ldx, int64_t B,
                                                    const typename ScanTraits<Tin, Tout>::St* __restrict__ C,
@@ -468,12 +492,12 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
   int32_t nodes[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    nodes[i] = d.node_of_row[min(r0 + i, end - 1)];
+    nodes[i] = node_at(d, min(r0 + i, end - 1));
     if (CWT == 64) nodes[i] = __builtin_amdgcn_readfirstlane(nodes[i]);
   }
   Tin raw[RPT];
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) raw[i] = __builtin_nontemporal_load(&x[(int64_t)nodes[i] * ldx + colc]);
+  for (int i = 0; i < RPT; ++i) raw[i] = __builtin_nontemporal_load(elem<O32>(x, nodes[i], ldx, colc));
   // MODE != 0: the rows' snapshots; consecutive rows mostly share one, which
   // is loaded once (scalar tests) and copied once the loads have returned
   Tout sv[MODE ? RPT : 1];
@@ -499,7 +523,7 @@ __global__ __launch_bounds__(WG) void k_scan_apply(DevPoset d, int segi, int cw_
       if (CWT == 64)
         __builtin_nontemporal_store(Tr::out(st.value()), &P[r * B + col]);
       else
-        P[r * B + col] = Tr::out(st.value());
+        *elem<O32>(P, r, B, col) = Tr::out(st.value());
     } else if constexpr (MODE == 1) {
       __builtin_nontemporal_store((Tout)((W)Tr::out(st.value()) + (W)sv[i]), &P[(int64_t)nodes[i] * ldo + col]);
     } else {
@@ -609,16 +633,17 @@ struct FlatRows {
   Tv v[RPT];
   bool seg[RPT];
   // the RPT rows of row group rg of tile t: values (zero beyond n) and segment starts
+  template <bool O32>
   __device__ void load(const DevPoset& d, int64_t t, int H, int rg, int dir, const Tin* __restrict__ x, int64_t ldx,
                        int64_t colc) {
     const int64_t n = d.n;
     const int64_t r0 = t * H + (int64_t)rg * RPT;
     int32_t nodes[RPT];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) nodes[i] = d.node_of_row[min(r0 + i, n - 1)];
+    for (int i = 0; i < RPT; ++i) nodes[i] = node_at(d, min(r0 + i, n - 1));
     Tin raw[RPT];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) raw[i] = __builtin_nontemporal_load(&x[(int64_t)nodes[i] * ldx + colc]);
+    for (int i = 0; i < RPT; ++i) raw[i] = __builtin_nontemporal_load(elem<O32>(x, nodes[i], ldx, colc));
 #pragma unroll
     for (int i = 0; i < RPT; ++i) seg[i] = r0 + i < n && flat_seg_start(d.chain_of_row, n, r0 + i, dir);
 #pragma unroll
@@ -646,7 +671,7 @@ struct FlatRows {
   }
 };
 
-template <typename Tin, typename Tout>
+template <typename Tin, typename Tout, bool O32>
 __global__ __launch_bounds__(WG) void k_scan_reduce_flat(DevPoset d, int cw, int dir, const Tin* __restrict__ x,
                                                          int64_t ldx, int64_t B,
                                                          typename ScanTraits<Tin, Tout>::St* __restrict__ A) {
@@ -658,7 +683,7 @@ __global__ __launch_bounds__(WG) void k_scan_reduce_flat(DevPoset d, int cw, int
   const int lane = threadIdx.x % cw, rg = threadIdx.x / cw;
   const int64_t col = (int64_t)blockIdx.y * cw + lane;
   FlatRows<Tin, Tout> fr;
-  fr.load(d, t, H, rg, dir, x, ldx, col < B ? col : 0);
+  fr.template load<O32>(d, t, H, rg, dir, x, ldx, col < B ? col : 0);
   bool seen;
   St st;
   fr.local(dir, seen, st);
@@ -700,7 +725,7 @@ __global__ __launch_bounds__(WG) void k_scan_carry_flat(DevPoset d, int H, int64
   C[t * B + col] = acc;
 }
 
-template <typename Tin, typename Tout>
+template <typename Tin, typename Tout, bool O32>
 __global__ __launch_bounds__(WG) void k_scan_apply_flat(DevPoset d, int cw, int dir, const Tin* __restrict__ x,
                                                         int64_t ldx, int64_t B,
                                                         const typename ScanTraits<Tin, Tout>::St* __restrict__ C,
@@ -714,7 +739,7 @@ __global__ __launch_bounds__(WG) void k_scan_apply_flat(DevPoset d, int cw, int 
   const int lane = threadIdx.x % cw, rg = threadIdx.x / cw;
   const int64_t col = (int64_t)blockIdx.y * cw + lane;
   FlatRows<Tin, Tout> fr;
-  fr.load(d, t, H, rg, dir, x, ldx, col < B ? col : 0);
+  fr.template load<O32>(d, t, H, rg, dir, x, ldx, col < B ? col : 0);
   bool seen;
   St loc;
   fr.local(dir, seen, loc);
@@ -747,7 +772,7 @@ __global__ __launch_bounds__(WG) void k_scan_apply_flat(DevPoset d, int cw, int 
   auto step = [&](int i) {
     if (fr.seg[i]) st.zero();
     st.add(fr.v[i]);
-    if (r0 + i < d.n) P[(r0 + i) * B + col] = Tr::out(st.value());
+    if (r0 + i < d.n) *elem<O32>(P, r0 + i, B, col) = Tr::out(st.value());
   };
   if (dir > 0) {
 #pragma unroll
@@ -865,7 +890,7 @@ __global__ __launch_bounds__(WG) void k_scan_onepass(DevPoset d, int segi, int c
   int32_t nodes[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    nodes[i] = d.node_of_row[min(r0 + i, end - 1)];
+    nodes[i] = node_at(d, min(r0 + i, end - 1));
     if (CWT == 64) nodes[i] = __builtin_amdgcn_readfirstlane(nodes[i]);
   }
   Tin raw[RPT];
@@ -1580,7 +1605,7 @@ __global__ __launch_bounds__(WG) void k_walk_events_vec(DevPoset d, const int32_
 // P is read here for the last time and g is written once: both streams are
 // non-temporal, so that they do not evict f and P's gathered rows from the
 // caches (f stays in the 256 MB MALL between its two reads by the scan).
-template <typename TP, typename Tres, bool RESID, bool UNI>
+template <typename TP, typename Tres, bool RESID, bool UNI, bool O32 = false>
 __global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* __restrict__ snap_of_row, int cw_rt,
                                                      const TP* __restrict__ P, const TP* __restrict__ S, int64_t B,
                                                      TP* __restrict__ out, int64_t ldo, const Tres* __restrict__ res,
@@ -1603,7 +1628,7 @@ __global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* 
 #pragma unroll
   for (int i = 0; i < RPC; ++i) {
     const int r = min(rb + i * rs, d.n - 1);
-    nd[i] = uni(d.node_of_row[r]);
+    nd[i] = uni(node_at(d, r));
     sm[i] = uni(snap_of_row[r]);
   }
   TP pv[RPC], sv[RPC];
@@ -1611,8 +1636,8 @@ __global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* 
 #pragma unroll
   for (int i = 0; i < RPC; ++i) {
     const int r = min(rb + i * rs, d.n - 1);
-    pv[i] = __builtin_nontemporal_load(&(P + (int64_t)r * B)[colc]);
-    sv[i] = (S + (int64_t)sm[i] * B)[colc];
+    pv[i] = __builtin_nontemporal_load(elem<O32>(P, r, B, colc));
+    sv[i] = *elem<O32>(S, sm[i], B, colc);
     if constexpr (RESID) rv[i] = (res + (int64_t)nd[i] * ldr)[colc];
   }
   if (col >= B) return;
@@ -1624,7 +1649,7 @@ __global__ __launch_bounds__(WG) void k_walk_combine(DevPoset d, const int32_t* 
       else if (UNI)
         __builtin_nontemporal_store((TP)((W)pv[i] + (W)sv[i]), &(out + (int64_t)nd[i] * ldo)[col]);
       else
-        (out + (int64_t)nd[i] * ldo)[col] = (TP)((W)pv[i] + (W)sv[i]);
+        *elem<O32>(out, nd[i], ldo, col) = (TP)((W)pv[i] + (W)sv[i]);
     }
   }
 }
@@ -1700,6 +1725,10 @@ hipError_t walk_typed(const DevPoset& d, const int32_t* nv, const WalkTables& w,
     else if (resid)
       hipLaunchKernelGGL((k_walk_combine<TP, double, true, false>), gc, dim3(WG), 0, s, d, w.snap_of_row, ccw,
                          (const TP*)P, (const TP*)snaps, B, (TP*)out, ldo, (const double*)resid, ldr);
+    else if (fits32(((int64_t)d.n + 1) * B * (int64_t)sizeof(TP)) && fits32((int64_t)w.nsnap * B * (int64_t)sizeof(TP)) &&
+             fits32((int64_t)d.n * ldo * (int64_t)sizeof(TP)))
+      hipLaunchKernelGGL((k_walk_combine<TP, TP, false, false, true>), gc, dim3(WG), 0, s, d, w.snap_of_row, ccw,
+                         (const TP*)P, (const TP*)snaps, B, (TP*)out, ldo, (const TP*)nullptr, 0);
     else
       hipLaunchKernelGGL((k_walk_combine<TP, TP, false, false>), gc, dim3(WG), 0, s, d, w.snap_of_row, ccw,
                          (const TP*)P, (const TP*)snaps, B, (TP*)out, ldo, (const TP*)nullptr, 0);
@@ -2473,7 +2502,7 @@ __global__ __launch_bounds__(WG) void k_scan_chains(DevPoset d, int dir, int cw,
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int64_t i = min(i0 + u, len - 1);
-      nodes[u] = d.node_of_row[dir > 0 ? r0 + i : r1 - 1 - i];
+      nodes[u] = node_at(d, dir > 0 ? r0 + i : r1 - 1 - i);
     }
     Tin raw[16];
 #pragma unroll
@@ -2504,6 +2533,9 @@ hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int6
   const int cw = col_width(B);
   const int segi = seg_index(cw);
   St* A = (St*)aux;
+  // 32-bit offsets for f (node order, n rows of ldx) and P (n + 1 rows of B)
+  const bool o32 = fits32((int64_t)d.n * ldx * (int64_t)sizeof(Tin)) &&
+                   fits32(((int64_t)d.n + 1) * B * (int64_t)sizeof(Tout));
   if (cw < 64 && flat_scan(d, segi)) {  // flat tiles (see k_scan_reduce_flat)
     const int H = seg_rows(cw);
     const int64_t nft = ((int64_t)d.n + H - 1) / H;
@@ -2511,13 +2543,20 @@ hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int6
     St* Cf = A + ntiles * B;
     const dim3 gf((unsigned)nft, (unsigned)((B + cw - 1) / cw));
     if (phase == 0) {
-      hipLaunchKernelGGL((k_scan_reduce_flat<Tin, Tout>), gf, dim3(WG), 0, s, d, cw, dir, (const Tin*)x, ldx, B, A);
+      if (o32)
+        hipLaunchKernelGGL((k_scan_reduce_flat<Tin, Tout, true>), gf, dim3(WG), 0, s, d, cw, dir, (const Tin*)x, ldx, B, A);
+      else
+        hipLaunchKernelGGL((k_scan_reduce_flat<Tin, Tout, false>), gf, dim3(WG), 0, s, d, cw, dir, (const Tin*)x, ldx, B,
+                           A);
     } else if (phase == 1) {
       const int64_t threads = nft * B;
       hipLaunchKernelGGL((k_scan_carry_flat<St, Tout>), dim3((unsigned)((threads + WG - 1) / WG)), dim3(WG), 0, s, d,
                          H, nft, dir, B, (const St*)A, Cf, (Tout*)P);
+    } else if (o32) {
+      hipLaunchKernelGGL((k_scan_apply_flat<Tin, Tout, true>), gf, dim3(WG), 0, s, d, cw, dir, (const Tin*)x, ldx, B,
+                         (const St*)Cf, (Tout*)P);
     } else {
-      hipLaunchKernelGGL((k_scan_apply_flat<Tin, Tout>), gf, dim3(WG), 0, s, d, cw, dir, (const Tin*)x, ldx, B,
+      hipLaunchKernelGGL((k_scan_apply_flat<Tin, Tout, false>), gf, dim3(WG), 0, s, d, cw, dir, (const Tin*)x, ldx, B,
                          (const St*)Cf, (Tout*)P);
     }
     return hipGetLastError();
@@ -2539,6 +2578,9 @@ hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int6
     if (cw == 64)
       hipLaunchKernelGGL((k_scan_reduce<Tin, Tout, 64, false>), g2, dim3(WG), 0, s, d, segi, cw, (const Tin*)x,
                          ldx, B, ntiles, A, dir, (const uint64_t*)nullptr, (const int32_t*)nullptr, (Tout*)nullptr);
+    else if (o32)
+      hipLaunchKernelGGL((k_scan_reduce<Tin, Tout, 0, false, true>), g2, dim3(WG), 0, s, d, segi, cw, (const Tin*)x,
+                         ldx, B, ntiles, A, dir, (const uint64_t*)nullptr, (const int32_t*)nullptr, (Tout*)nullptr);
     else
       hipLaunchKernelGGL((k_scan_reduce<Tin, Tout, 0, false>), g2, dim3(WG), 0, s, d, segi, cw, (const Tin*)x,
                          ldx, B, ntiles, A, dir, (const uint64_t*)nullptr, (const int32_t*)nullptr, (Tout*)nullptr);
@@ -2554,6 +2596,10 @@ hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int6
     }
   } else if (cw == 64) {
     hipLaunchKernelGGL((k_scan_apply<Tin, Tout, 64, 0, Tout>), g, dim3(WG), 0, s, d, segi, cw, dir, (const Tin*)x,
+                       ldx, B, (const St*)C, (Tout*)P, (const int32_t*)nullptr, (const Tout*)nullptr, 0,
+                       (const Tout*)nullptr, 0);
+  } else if (o32) {
+    hipLaunchKernelGGL((k_scan_apply<Tin, Tout, 0, 0, Tout, true>), g, dim3(WG), 0, s, d, segi, cw, dir, (const Tin*)x,
                        ldx, B, (const St*)C, (Tout*)P, (const int32_t*)nullptr, (const Tout*)nullptr, 0,
                        (const Tout*)nullptr, 0);
   } else {

@@ -802,6 +802,37 @@ def test_vector_lane_walk(px, B, monkeypatch):
                     assert np.array_equal(a[s0:e0], O.zeta_adjoint(R, H(f)[s0:e0]))
 
 
+@pytest.mark.parametrize("B", [4, 16])
+def test_offsets_32_and_64_bit(px, B, monkeypatch):
+    """The narrow scans, flat scans and combine address matrices with 32-bit offsets when
+    every offset fits (the usual case) and with 64-bit offsets otherwise; both forms give
+    the same values bit for bit (POSETX_O32=0 forces 64-bit), in node and row layout, and
+    equal the closure oracle."""
+    import torch
+    p = W.chain_poset(3000, 30, 3, seed=40 + B)
+    P = build(px, p)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    f = W.functions(p.n, B, "int", seed=B, lo=-10**6, hi=10**6)
+    perm = torch.from_numpy(P.rows()).to(dev())
+    res = {}
+    for o32 in ("1", "0"):
+        monkeypatch.setenv("POSETX_O32", o32)
+        for flat in ("1", "0"):
+            monkeypatch.setenv("POSETX_SCAN_FLAT", flat)
+            P.set_layout("nodes")
+            g, a = px.zeta(P, T(f)), px.zeta_adjoint(P, T(f))
+            P.set_layout("rows")
+            fr = torch.empty_like(T(f))
+            fr[perm] = T(f)
+            gr, ar = px.zeta(P, fr), px.zeta_adjoint(P, fr)
+            P.set_layout("nodes")
+            assert torch.equal(gr[perm], g) and torch.equal(ar[perm], a)
+            res[o32 + flat] = (H(g), H(a))
+    for key, (g, a) in res.items():
+        assert np.array_equal(g, O.zeta(R, f)), key
+        assert np.array_equal(a, O.zeta_adjoint(R, f)), key
+
+
 # ------------------------------------------------------------ error handling
 def test_argument_errors_and_nonfinite(px, cfg0):
     import torch
