@@ -616,6 +616,26 @@ def main():
     torch.cuda.synchronize()
     dt_rot = time.perf_counter() - t1
     del fs, gs
+    # the same K steps with the matrices in the kernels' chain-major row order
+    # (px_poset_set_layout): same values bit for bit, permuted; node order stays `value`
+    rows_np = P.rows()
+    row_idx = torch.from_numpy(rows_np).to(dev)
+    fr = torch.empty_like(f)
+    fr[row_idx] = f
+    gr = torch.empty_like(g)
+    P.set_layout("rows")
+    for _ in range(max(1, args.warmup)):
+        px.zeta(P, fr, out=gr)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        px.zeta(P, fr, out=gr)
+    torch.cuda.synchronize()
+    dt_rows = time.perf_counter() - t1
+    P.set_layout("nodes")
+    px.zeta(P, f, out=g)
+    rows_equal = bool(torch.equal(gr[row_idx], g))
+    del fr, gr, row_idx
     copy_gbps = measured_copy_gbps(dev)
 
     ms_step = dt * 1e3 / args.steps
@@ -678,6 +698,10 @@ def main():
         "rotating_inputs": {"buffers": NROT, "ms_per_step": dt_rot * 1e3 / args.steps,
                             "node_rhs_per_s": p.n * B / (dt_rot / args.steps),
                             "step_frac": round(step_bytes / (dt_rot / args.steps) / 1e9 / HBM_PEAK_GBS, 4)},
+        "rows_layout": {"ms_per_step": dt_rows * 1e3 / args.steps,
+                        "node_rhs_per_s": p.n * B / (dt_rows / args.steps),
+                        "step_frac": round(step_bytes / (dt_rows / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+                        "equal_to_node_order": rows_equal},
         "phases": phases,
         "preprocess_s": {"total": round(t_prep, 3), **{k: round(v, 3) for k, v in P.info.items()
                                                       if k.startswith("t_")},
