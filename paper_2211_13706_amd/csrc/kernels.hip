@@ -783,6 +783,154 @@ __global__ __launch_bounds__(WG) void k_scan_apply_flat(DevPoset d, int cw, int 
   }
 }
 
+// Compact walk for narrow column blocks (8 <= cw <= 32): the scan kernels of
+// the compact walk with cw-column blocks.  A workgroup covers TPW = WG / (4 cw)
+// consecutive 64-row tiles of the compact tables (which may belong to
+// different chains), 4 row groups of RPT = 16 rows per tile; a row group's
+// marks are a 16-bit slice of its tile's mask.  The tile totals and the
+// tile-local prefixes are those of the 64-column kernels, combined in the
+// same order, so the carry kernel and the tables are shared.
+template <typename Tin, typename Tout, bool O32>
+__global__ __launch_bounds__(WG) void k_scan_reduce_cn(DevPoset d, int cw, int dir, const Tin* __restrict__ x,
+                                                       int64_t ldx, int64_t B, int64_t ntiles,
+                                                       typename ScanTraits<Tin, Tout>::St* __restrict__ A,
+                                                       const uint64_t* __restrict__ tmask,
+                                                       const int32_t* __restrict__ qoff, Tout* __restrict__ L) {
+  using Tr = ScanTraits<Tin, Tout>;
+  using St = typename Tr::St;
+  using Tv = decltype(Tr::in(Tin()));
+  __shared__ St sm[WG];
+  const int RG = WG / cw, TPW = RG / 4;
+  const int lane = threadIdx.x % cw, rg = threadIdx.x / cw;
+  const int tq = rg >> 2, q = rg & 3;
+  const int64_t t = (int64_t)blockIdx.x * TPW + tq;
+  const bool tok = t < ntiles;
+  const int64_t tc = tok ? t : ntiles - 1;
+  const int2 tr = d.tiles[6][tc];  // 64-row tiles: {first row, end row of its chain}
+  const int64_t r0 = tr.x + (int64_t)q * RPT, end = tr.y;
+  const int64_t col = (int64_t)blockIdx.y * cw + lane;
+  const int64_t colc = col < B ? col : 0;
+  const uint64_t tm = tmask[tc];
+  int32_t nodes[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) nodes[i] = node_at(d, min(r0 + i, end - 1));
+  Tin raw[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) raw[i] = *elem<O32>(x, nodes[i], ldx, colc);
+  Tv v[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) v[i] = (tok && r0 + i < end) ? Tr::in(raw[i]) : Tv(0);
+  St st;
+  st.zero();
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) st.add(v[dir > 0 ? i : RPT - 1 - i]);
+  sm[threadIdx.x] = st;
+  __syncthreads();
+  const int g0 = tq * 4;  // this tile's first row group
+  if (q == 0 && tok && col < B) {
+    St tot;
+    tot.zero();
+    for (int u = 0; u < 4; ++u) tot.combine(sm[(g0 + (dir > 0 ? u : 3 - u)) * cw + lane]);
+    A[t * B + col] = tot;
+  }
+  const uint32_t m16 = tok ? (uint32_t)(tm >> (q * RPT)) & 0xffffu : 0u;
+  if (m16 == 0 || col >= B) return;
+  // the row groups of this tile before this one in scan order, then this one's rows
+  St pre;
+  pre.zero();
+  if (dir > 0) {
+    for (int u = 0; u < q; ++u) pre.combine(sm[(g0 + u) * cw + lane]);
+  } else {
+    for (int u = 3; u > q; --u) pre.combine(sm[(g0 + u) * cw + lane]);
+  }
+  const int32_t qo = qoff[tc];
+  auto step = [&](int i) {
+    pre.add(v[i]);
+    if ((m16 >> i) & 1u) {
+      const int b = q * RPT + i;  // the row's bit in its tile; slots run in row order
+      const int slot = qo + __popcll(tm & ((uint64_t(1) << b) - 1));
+      L[(int64_t)slot * B + col] = Tr::out(pre.value());
+    }
+  };
+  if (dir > 0) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) step(i);
+  } else {
+#pragma unroll
+    for (int i = RPT - 1; i >= 0; --i) step(i);
+  }
+}
+
+// The last pass of the narrow compact walk: the scan inside each 64-row tile
+// from its carry, fused with the combine out[node(r)] = P[r] + S[snap_of_row[r]].
+template <typename Tin, typename Tout, bool O32>
+__global__ __launch_bounds__(WG) void k_scan_apply_cn(DevPoset d, int cw, int dir, const Tin* __restrict__ x,
+                                                      int64_t ldx, int64_t B, int64_t ntiles,
+                                                      const typename ScanTraits<Tin, Tout>::St* __restrict__ C,
+                                                      Tout* __restrict__ out, int64_t ldo,
+                                                      const int32_t* __restrict__ snap_of_row,
+                                                      const Tout* __restrict__ S) {
+  using Tr = ScanTraits<Tin, Tout>;
+  using St = typename Tr::St;
+  using Tv = decltype(Tr::in(Tin()));
+  using W = typename Wide<Tout>::W;
+  __shared__ St sm[WG];
+  const int RG = WG / cw, TPW = RG / 4;
+  const int lane = threadIdx.x % cw, rg = threadIdx.x / cw;
+  const int tq = rg >> 2, q = rg & 3;
+  const int64_t t = (int64_t)blockIdx.x * TPW + tq;
+  const bool tok = t < ntiles;
+  const int64_t tc = tok ? t : ntiles - 1;
+  const int2 tr = d.tiles[6][tc];
+  const int64_t r0 = tr.x + (int64_t)q * RPT, end = tr.y;
+  const int64_t col = (int64_t)blockIdx.y * cw + lane;
+  const int64_t colc = col < B ? col : 0;
+  int32_t nodes[RPT], sn[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    nodes[i] = node_at(d, min(r0 + i, end - 1));
+    sn[i] = snap_of_row[min(r0 + i, end - 1)];
+  }
+  Tin raw[RPT];
+  Tout sv[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    raw[i] = __builtin_nontemporal_load(elem<O32>(x, nodes[i], ldx, colc));
+    sv[i] = *elem<O32>(S, sn[i], B, colc);
+  }
+  Tv v[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) v[i] = (tok && r0 + i < end) ? Tr::in(raw[i]) : Tv(0);
+  St loc;
+  loc.zero();
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) loc.add(v[dir > 0 ? i : RPT - 1 - i]);
+  sm[threadIdx.x] = loc;
+  __syncthreads();
+  if (!tok || col >= B) return;
+  const int g0 = tq * 4;
+  St pre;
+  pre.zero();
+  if (dir > 0) {
+    for (int u = 0; u < q; ++u) pre.combine(sm[(g0 + u) * cw + lane]);
+  } else {
+    for (int u = 3; u > q; --u) pre.combine(sm[(g0 + u) * cw + lane]);
+  }
+  St st = C[t * B + col];
+  st.combine(pre);
+  auto step = [&](int i) {
+    st.add(v[i]);
+    if (r0 + i < end) *elem<O32>(out, nodes[i], ldo, col) = (Tout)((W)Tr::out(st.value()) + (W)sv[i]);
+  };
+  if (dir > 0) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) step(i);
+  } else {
+#pragma unroll
+    for (int i = RPT - 1; i >= 0; --i) step(i);
+  }
+}
+
 // Single-pass chain scan with a deterministic multi-level look-back.
 //
 // Workgroups take tiles (and column blocks) in scan-position-major order of
@@ -1281,11 +1429,14 @@ __global__ __launch_bounds__(WG) void k_walk_events(DevPoset d, const int32_t* _
 // uniform form, XCD x takes a contiguous slice of the runs: for a batch, whose
 // runs are poset after poset, each XCD's L2 then holds the P rows of the few
 // posets it is working on instead of all of them.
-template <typename TP>
+// COMPACT (one poset, k <= 64, cw >= 8): P is the compact Q, as in the
+// vector-lane form.
+template <typename TP, bool COMPACT = false>
 __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int32_t* __restrict__ nv, WalkTables w,
                                                           int cw, const TP* __restrict__ P, int64_t B,
                                                           TP* __restrict__ S) {
   using W = typename Wide<TP>::W;
+  if (COMPACT && cw < 8) return;  // not launched: the compact form needs cw >= 8
   const int lane = threadIdx.x & 63;
   const int nsub = 64 / cw;
   const int nblk = (int)gridDim.x, q8 = nblk >> 3, r8 = nblk & 7;
@@ -1300,7 +1451,10 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
   const int r0 = w.runs[runc].x;
   int k;
   const int32_t* nr;
-  if (d.poset_of_row) {
+  if (COMPACT) {
+    k = d.k;
+    nr = w.init + runc * k;
+  } else if (d.poset_of_row) {
     const int p = d.poset_of_row[r0];
     k = d.k_of_poset[p];
     nr = nv + d.niv_off[p] + (int64_t)(r0 - d.row_off[p]) * k;
@@ -1308,6 +1462,7 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
     k = d.k;
     nr = nv + (int64_t)r0 * k;
   }
+  const int zrow = COMPACT ? w.nslots : r0;  // a row to load for masked entries
   const int klast = k - 1;  // entries load from nr[min(j, klast)] (k >= 1) and are masked after
   if (!active) k = 0;
   int kmax = k;
@@ -1333,8 +1488,8 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
-        ok[u] = t[u] >= 0 && t[u] != r0;
-        v[u] = P[(int64_t)(ok[u] ? t[u] : r0) * B + colc];
+        ok[u] = t[u] >= 0 && (COMPACT || t[u] != r0);
+        v[u] = P[(int64_t)(ok[u] ? t[u] : zrow) * B + colc];
       }
 #pragma unroll
       for (int u = 0; u < 16; ++u)
@@ -1376,8 +1531,9 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
     // of the next group.  Record indices clamp to the run's end: the tables
     // keep one padding record after the last run.
     const int sub = lane % cw, base = lane - sub, s8 = sub & 7;
+    const int4* __restrict__ evs = COMPACT ? w.evq : w.ev;
     auto rec = [&](int i) {  // OR-ing the mask keeps the load unconditional (no branch)
-      const int4 r = w.ev[e0 + min(i, ne)];
+      const int4 r = evs[e0 + min(i, ne)];
       const int no = i < ne ? 0 : -1;
       return make_int4(r.x | no, r.y | no, r.z | no, 0);
     };
@@ -1400,8 +1556,8 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
       for (int q = 0; q < 16; ++q) {
         okn[q] = ex[q] >= 0;
         oko[q] = ey[q] >= 0;
-        vn[q] = P[(int64_t)(okn[q] ? ex[q] : r0) * B + colc];
-        vo[q] = P[(int64_t)(oko[q] ? ey[q] : r0) * B + colc];
+        vn[q] = P[(int64_t)(okn[q] ? ex[q] : zrow) * B + colc];
+        vo[q] = P[(int64_t)(oko[q] ? ey[q] : zrow) * B + colc];
       }
       ra = rec(g0 + 16 + s8);
       rb = rec(g0 + 24 + s8);
@@ -1465,7 +1621,11 @@ __global__ __launch_bounds__(WG) void k_walk_events_split(DevPoset d, const int3
 // of a compute unit spends its time per row touched, so narrow blocks gather
 // several times faster this way.  Events and first-row entries are shared by
 // the run's L lanes as in the lane-split form; EG events per group.
-template <typename TP, int L, int EG>
+//
+// COMPACT (one poset, k <= 64): P is the compact Q of the gathered rows; the
+// first row's entries come from w.init and the events from w.evq, as slots
+// (slot nslots, a zero row, for the own chain and "no element").
+template <typename TP, int L, int EG, bool COMPACT = false>
 __global__ __launch_bounds__(WG) void k_walk_events_vec(DevPoset d, const int32_t* __restrict__ nv, WalkTables w,
                                                         const TP* __restrict__ P, int64_t B, TP* __restrict__ S) {
   using W = typename Wide<TP>::W;
@@ -1487,7 +1647,10 @@ __global__ __launch_bounds__(WG) void k_walk_events_vec(DevPoset d, const int32_
   const int r0 = w.runs[runc].x;
   int k;
   const int32_t* nr;
-  if (d.poset_of_row) {
+  if (COMPACT) {
+    k = d.k;
+    nr = w.init + runc * k;
+  } else if (d.poset_of_row) {
     const int p = d.poset_of_row[r0];
     k = d.k_of_poset[p];
     nr = nv + d.niv_off[p] + (int64_t)(r0 - d.row_off[p]) * k;
@@ -1495,6 +1658,7 @@ __global__ __launch_bounds__(WG) void k_walk_events_vec(DevPoset d, const int32_
     k = d.k;
     nr = nv + (int64_t)r0 * k;
   }
+  const int4* __restrict__ evs = COMPACT ? w.evq : w.ev;
   const int klast = k - 1;
   if (!active) k = 0;
   int kmax = k;
@@ -1522,8 +1686,9 @@ __global__ __launch_bounds__(WG) void k_walk_events_vec(DevPoset d, const int32_
     bool ok[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      ok[u] = t[u] >= 0 && t[u] != r0;
-      vv[u] = row(ok[u] ? t[u] : r0);
+      // compact slots name the zero row for the own chain; masked entries are -1
+      ok[u] = t[u] >= 0 && (COMPACT || t[u] != r0);
+      vv[u] = row(ok[u] ? t[u] : (COMPACT ? w.nslots : r0));
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u)
@@ -1548,7 +1713,7 @@ __global__ __launch_bounds__(WG) void k_walk_events_vec(DevPoset d, const int32_
   for (int off = 32; off >= 1; off >>= 1) nemax = max(nemax, __shfl_xor(nemax, off));
   // record i of this run (clamped to the padding record after the last run)
   auto rec = [&](int i) {
-    const int4 r = w.ev[e0 + min(i, ne)];
+    const int4 r = evs[e0 + min(i, ne)];
     const int no = i < ne ? 0 : -1;
     return make_int4(r.x | no, r.y | no, r.z | no, 0);
   };
@@ -1572,8 +1737,8 @@ __global__ __launch_bounds__(WG) void k_walk_events_vec(DevPoset d, const int32_
     for (int q = 0; q < EG; ++q) {
       okn[q] = ex[q] >= 0;
       oko[q] = ey[q] >= 0;
-      vn[q] = row(okn[q] ? ex[q] : r0);
-      vo[q] = row(oko[q] ? ey[q] : r0);
+      vn[q] = row(okn[q] ? ex[q] : (COMPACT ? w.nslots : r0));
+      vo[q] = row(oko[q] ? ey[q] : (COMPACT ? w.nslots : r0));
     }
 #pragma unroll
     for (int i = 0; i < RL; ++i) ra[i] = rec(g0 + EG + sub + L * i);
@@ -2614,6 +2779,66 @@ hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int6
 // quarter of the chain's gathered rows.
 constexpr int kCarrySplit = 4;
 
+// The narrow compact walk (8 <= cw <= 32, zeta values): k_scan_reduce_cn, the
+// shared carry, the vector-lane or lane-split walk on Q, k_scan_apply_cn.
+template <typename Tin, typename Tout>
+hipError_t compact_narrow_typed(const DevPoset& d, int dir, const void* x, int64_t ldx, void* out, int64_t ldo,
+                                int64_t B, void* aux, int64_t ntiles, void* lq, void* snaps, LaunchHook* hook,
+                                hipStream_t s) {
+  using St = typename ScanTraits<Tin, Tout>::St;
+  const WalkTables& w = d.walk[dir > 0 ? 0 : 1];
+  const int cw = col_width(B);
+  St* A = (St*)aux;
+  St* C = A + ntiles * B;
+  Tout* L = (Tout*)lq;
+  Tout* Q = L + (int64_t)w.nslots * B;
+  const int tpw = WG / cw / 4;
+  const dim3 g((unsigned)((ntiles + tpw - 1) / tpw));
+  const bool o32 = fits32((int64_t)d.n * ldx * (int64_t)sizeof(Tin)) &&
+                   fits32((int64_t)d.n * ldo * (int64_t)sizeof(Tout)) &&
+                   fits32((int64_t)w.nsnap * B * (int64_t)sizeof(Tout));
+  if (hook) hook->before(0, s);
+  if (o32)
+    hipLaunchKernelGGL((k_scan_reduce_cn<Tin, Tout, true>), g, dim3(WG), 0, s, d, cw, dir, (const Tin*)x, ldx, B,
+                       ntiles, A, w.tmask, w.qoff, L);
+  else
+    hipLaunchKernelGGL((k_scan_reduce_cn<Tin, Tout, false>), g, dim3(WG), 0, s, d, cw, dir, (const Tin*)x, ldx, B,
+                       ntiles, A, w.tmask, w.qoff, L);
+  if (hook) hook->after(0, s);
+  if (hook) hook->before(1, s);
+  hipLaunchKernelGGL((k_scan_carry<St, Tout, true>),
+                     dim3((unsigned)d.nchains, (unsigned)((B + 15) / 16), (unsigned)kCarrySplit), dim3(WG), 0, s, d,
+                     seg_index(64), dir, B, (const St*)A, C, Q, w.qoff, w.tile_of_slot, (const Tout*)L, w.nslots);
+  if (hook) hook->after(1, s);
+  if (hook) hook->before(2, s);
+  if (walk_vec_ok<Tout>(cw, B, w.nruns)) {
+    constexpr int V = 16 / sizeof(Tout);
+    const int Lr = cw / V;
+    const int64_t waves = (w.nruns + (64 / Lr) - 1) / (64 / Lr);
+    const dim3 gw((unsigned)((waves + (WG / 64) - 1) / (WG / 64)));
+    const Tout* q = Q;
+    Tout* sn = (Tout*)snaps;
+    if (Lr == 2) hipLaunchKernelGGL((k_walk_events_vec<Tout, 2, 16, true>), gw, dim3(WG), 0, s, d, nullptr, w, q, B, sn);
+    else if (Lr == 4) hipLaunchKernelGGL((k_walk_events_vec<Tout, 4, 16, true>), gw, dim3(WG), 0, s, d, nullptr, w, q, B, sn);
+    else if (Lr == 8) hipLaunchKernelGGL((k_walk_events_vec<Tout, 8, 16, true>), gw, dim3(WG), 0, s, d, nullptr, w, q, B, sn);
+    else hipLaunchKernelGGL((k_walk_events_vec<Tout, 16, 16, true>), gw, dim3(WG), 0, s, d, nullptr, w, q, B, sn);
+  } else {
+    const int64_t waves = (w.nruns + (64 / cw) - 1) / (64 / cw);
+    hipLaunchKernelGGL((k_walk_events_split<Tout, true>), dim3((unsigned)((waves + (WG / 64) - 1) / (WG / 64))),
+                       dim3(WG), 0, s, d, nullptr, w, cw, (const Tout*)Q, B, (Tout*)snaps);
+  }
+  if (hook) hook->after(2, s);
+  if (hook) hook->before(3, s);
+  if (o32)
+    hipLaunchKernelGGL((k_scan_apply_cn<Tin, Tout, true>), g, dim3(WG), 0, s, d, cw, dir, (const Tin*)x, ldx, B,
+                       ntiles, (const St*)C, (Tout*)out, ldo, w.snap_of_row, (const Tout*)snaps);
+  else
+    hipLaunchKernelGGL((k_scan_apply_cn<Tin, Tout, false>), g, dim3(WG), 0, s, d, cw, dir, (const Tin*)x, ldx, B,
+                       ntiles, (const St*)C, (Tout*)out, ldo, w.snap_of_row, (const Tout*)snaps);
+  if (hook) hook->after(3, s);
+  return hipGetLastError();
+}
+
 template <typename Tin, typename Tout, int MODE, typename Tres>
 hipError_t compact_typed(const DevPoset& d, int dir, const void* x, int64_t ldx, void* out, int64_t ldo,
                          const void* resid, int64_t ldr, int64_t B, void* aux, int64_t ntiles, void* lq,
@@ -2621,6 +2846,11 @@ hipError_t compact_typed(const DevPoset& d, int dir, const void* x, int64_t ldx,
   using St = typename ScanTraits<Tin, Tout>::St;
   const WalkTables& w = d.walk[dir > 0 ? 0 : 1];
   const int segi = seg_index(64);
+  if constexpr (MODE == 1) {
+    const int cw = col_width(B);
+    if (cw >= 8 && cw <= 32)
+      return compact_narrow_typed<Tin, Tout>(d, dir, x, ldx, out, ldo, B, aux, ntiles, lq, snaps, hook, s);
+  }
   St* A = (St*)aux;
   St* C = A + ntiles * B;
   Tout* L = (Tout*)lq;

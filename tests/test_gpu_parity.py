@@ -489,6 +489,7 @@ def test_masked_compact_walk_for_narrow_blocks(px, cfg0, B, monkeypatch):
     fi = W.functions(p.n, B, "int", seed=20 + B, lo=-1000, hi=1000)
     ff = W.functions(p.n, B, "normal", seed=20 + B)
     g = O.zeta(R, fi).astype(np.float32)        # exact in float32 (|g| < 2**24)
+    monkeypatch.setenv("POSETX_COMPACT_NARROW", "0")   # the scan over P
     base = [H(px.zeta(P, T(fi))), H(px.zeta_adjoint(P, T(fi))), H(px.zeta(P, T(ff))),
             H(px.mobius(P, T(g), max_refine=3))]
     monkeypatch.setenv("POSETX_COMPACT_NARROW", "1")
@@ -499,6 +500,36 @@ def test_masked_compact_walk_for_narrow_blocks(px, cfg0, B, monkeypatch):
     check_f32_zeta(got[2], O.zeta(R, ff, exact=False), O.zeta(R, np.abs(ff).astype(np.float64), exact=False))
     # the refinement's residual through the masked compact walk converges as through P
     assert rel(got[3], fi) <= max(2 * rel(base[3], fi), 1e-6)
+
+
+@pytest.mark.parametrize("B", [5, 8, 12, 16, 24, 32])
+def test_narrow_compact_walk(px, B, monkeypatch):
+    """Blocks of 8 to 32 columns take the compact walk with narrow kernels by default
+    (k_scan_reduce_cn, the shared carry, the walk on Q, k_scan_apply_cn: P is never
+    formed).  Zeta and its adjoint equal the scan over P (POSETX_COMPACT_NARROW=0) and
+    the closure oracle: int64 bit for bit, float32 within the compensated bound, float64
+    to rounding; with the walk on Q in both its vector-lane and lane-split forms.
+    Chains of about 167 rows put chain ends inside the 64-row tiles a workgroup spans."""
+    p = W.chain_poset(4000, 24, 3, seed=B)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = build(px, p)
+    fi = W.functions(p.n, B, "int", seed=B, lo=-10**6, hi=10**6)
+    ff = W.functions(p.n, B, "normal", seed=B + 1)
+    fd = W.functions(p.n, B, "normal64", seed=B + 2)
+    za = O.zeta(R, np.abs(ff).astype(np.float64), exact=False)
+    zta = O.zeta_adjoint(R, np.abs(ff).astype(np.float64), exact=False)
+    monkeypatch.setenv("POSETX_COMPACT_NARROW", "0")
+    base = (H(px.zeta(P, T(fi))), H(px.zeta_adjoint(P, T(fi))))
+    monkeypatch.delenv("POSETX_COMPACT_NARROW")
+    for vec in ("0", "1"):
+        monkeypatch.setenv("POSETX_WALK_VEC", vec)
+        g, a = H(px.zeta(P, T(fi))), H(px.zeta_adjoint(P, T(fi)))
+        assert np.array_equal(g, O.zeta(R, fi)) and np.array_equal(a, O.zeta_adjoint(R, fi))
+        assert np.array_equal(g, base[0]) and np.array_equal(a, base[1])
+        check_f32_zeta(H(px.zeta(P, T(ff))), O.zeta(R, ff, exact=False), za)
+        check_f32_zeta(H(px.zeta_adjoint(P, T(ff))), O.zeta_adjoint(R, ff, exact=False), zta)
+        assert rel(H(px.zeta(P, T(fd))), O.zeta(R, fd, exact=False)) <= 1e-12
+        assert rel(H(px.zeta_adjoint(P, T(fd))), O.zeta_adjoint(R, fd, exact=False)) <= 1e-12
 
 
 @pytest.mark.parametrize("case", ["cfg0", "er", "grid"])

@@ -77,10 +77,11 @@ def test_noalloc_matches_oracle_small(px):
     assert np.array_equal(out.cpu().numpy(), O.zeta(R, f))
 
 
-def test_noalloc_refuses_oversized_scratch(px):
+def test_noalloc_refuses_oversized_scratch(px, monkeypatch):
     import torch
-    # int64, B = 32 (the scan over P) over 300,000 rows: the prefix matrix alone
-    # is 76.8 MB > 64 MiB
+    # int64, B = 32 through the scan over P (narrow blocks kept off the compact
+    # walk) over 300,000 rows: the prefix matrix alone is 76.8 MB > 64 MiB
+    monkeypatch.setenv("POSETX_COMPACT_NARROW", "0")
     p, P = _poset(px, 300000, 32, 5)
     x = torch.ones((p.n, 32), dtype=torch.int64, device="cuda:0")
     out = torch.full_like(x, 3)
