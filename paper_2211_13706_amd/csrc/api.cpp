@@ -870,13 +870,13 @@ int64_t flow_ints(const px_poset* p, int64_t B) {
   return 1 + ncb * std::max<int64_t>(p->prep.n + 1, nch);
 }
 
-// Narrow blocks (B <= 32).  With 8 to 32 columns per block, zeta values take
-// the compact walk with narrow kernels (k_scan_reduce_cn, k_scan_apply_cn and
-// the walks on Q).  POSETX_COMPACT_NARROW (read on every call): 0 never takes
-// the compact walk for narrow blocks; 1 takes it for every narrow block and
-// the refinement residual too, in 64-column tiles with the columns beyond B
-// masked where the narrow kernels do not apply (slower: a masked tile spends a
-// 64-lane wavefront on each row however narrow it is).
+// Narrow blocks (B <= 32).  With 8 to 32 columns per block, zeta values and
+// refinement residuals take the compact walk with narrow kernels
+// (k_scan_reduce_cn, k_scan_apply_cn and the walks on Q).
+// POSETX_COMPACT_NARROW (read on every call): 0 never takes the compact walk
+// for narrow blocks; 1 takes it for every narrow block, with 1 to 4 columns in
+// 64-column tiles with the columns beyond B masked (slower: a masked tile
+// spends a 64-lane wavefront on each row however narrow it is).
 int compact_narrow_mode() {
   const char* v = std::getenv("POSETX_COMPACT_NARROW");
   if (v && v[0] == '0') return 0;
@@ -884,13 +884,12 @@ int compact_narrow_mode() {
   return 1;
 }
 
-// resid: the call computes a refinement residual (float64 values).
-bool use_compact(const px_poset* p, bool up, int64_t B, bool resid = false) {
+bool use_compact(const px_poset* p, bool up, int64_t B) {
   if (p->nslots[up ? 1 : 0] < 0 || !compact_enabled() || !px::compact_ok(p->dp, up, B)) return false;
   const int cw = px::col_width(B);
   if (cw == 64) return true;
   const int mode = compact_narrow_mode();
-  return mode == 2 || (mode == 1 && !resid && cw >= 8);
+  return mode == 2 || (mode == 1 && cw >= 8);
 }
 
 // Tiles of the compact walk's scan (64-row tiles whatever B is), and the tile
@@ -1117,7 +1116,7 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   };
   // r = g - zeta(f), zeta applied in float64 to the float32 iterate.
   auto residual = [&]() -> hipError_t {
-    if (use_compact(p, up, B, true))
+    if (use_compact(p, up, B))
       return run_compact(p->dp, dir, px::E_F32, f, ldf, px::E_F64, r64, B, px::E_F32, g, ldg, B, w + L.aux,
                          compact_tiles(p), w + L.lq, w + L.snaps, s);
     hipError_t e2 = run_scan(p->dp, dir, px::E_F32, f, ldf, px::E_F64, w + L.p64, B, w + L.aux, nt, (int*)(w + L.sync), s);

@@ -862,14 +862,16 @@ __global__ __launch_bounds__(WG) void k_scan_reduce_cn(DevPoset d, int cw, int d
 }
 
 // The last pass of the narrow compact walk: the scan inside each 64-row tile
-// from its carry, fused with the combine out[node(r)] = P[r] + S[snap_of_row[r]].
-template <typename Tin, typename Tout, bool O32>
+// from its carry, fused with the combine: out[node(r)] = P[r] + S[snap_of_row[r]]
+// (MODE 1), or the refinement residual res[node(r)] - (P[r] + S[...]) (MODE 2).
+template <typename Tin, typename Tout, int MODE, typename Tres, bool O32>
 __global__ __launch_bounds__(WG) void k_scan_apply_cn(DevPoset d, int cw, int dir, const Tin* __restrict__ x,
                                                       int64_t ldx, int64_t B, int64_t ntiles,
                                                       const typename ScanTraits<Tin, Tout>::St* __restrict__ C,
                                                       Tout* __restrict__ out, int64_t ldo,
                                                       const int32_t* __restrict__ snap_of_row,
-                                                      const Tout* __restrict__ S) {
+                                                      const Tout* __restrict__ S, const Tres* __restrict__ res,
+                                                      int64_t ldr) {
   using Tr = ScanTraits<Tin, Tout>;
   using St = typename Tr::St;
   using Tv = decltype(Tr::in(Tin()));
@@ -893,10 +895,12 @@ __global__ __launch_bounds__(WG) void k_scan_apply_cn(DevPoset d, int cw, int di
   }
   Tin raw[RPT];
   Tout sv[RPT];
+  Tres rv[MODE == 2 ? RPT : 1];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     raw[i] = __builtin_nontemporal_load(elem<O32>(x, nodes[i], ldx, colc));
     sv[i] = *elem<O32>(S, sn[i], B, colc);
+    if constexpr (MODE == 2) rv[i] = *elem<O32>(res, nodes[i], ldr, colc);
   }
   Tv v[RPT];
 #pragma unroll
@@ -920,7 +924,12 @@ __global__ __launch_bounds__(WG) void k_scan_apply_cn(DevPoset d, int cw, int di
   st.combine(pre);
   auto step = [&](int i) {
     st.add(v[i]);
-    if (r0 + i < end) *elem<O32>(out, nodes[i], ldo, col) = (Tout)((W)Tr::out(st.value()) + (W)sv[i]);
+    if (r0 + i < end) {
+      if constexpr (MODE == 2)
+        *elem<O32>(out, nodes[i], ldo, col) = (Tout)((double)rv[i] - ((W)Tr::out(st.value()) + (W)sv[i]));
+      else
+        *elem<O32>(out, nodes[i], ldo, col) = (Tout)((W)Tr::out(st.value()) + (W)sv[i]);
+    }
   };
   if (dir > 0) {
 #pragma unroll
@@ -2779,12 +2788,13 @@ hipError_t scan_typed(int phase, const DevPoset& d, int dir, const void* x, int6
 // quarter of the chain's gathered rows.
 constexpr int kCarrySplit = 4;
 
-// The narrow compact walk (8 <= cw <= 32, zeta values): k_scan_reduce_cn, the
-// shared carry, the vector-lane or lane-split walk on Q, k_scan_apply_cn.
-template <typename Tin, typename Tout>
+// The narrow compact walk (8 <= cw <= 32): k_scan_reduce_cn, the shared
+// carry, the vector-lane or lane-split walk on Q, k_scan_apply_cn (MODE 1: zeta
+// values; MODE 2: refinement residuals against resid, type Tres).
+template <typename Tin, typename Tout, int MODE, typename Tres>
 hipError_t compact_narrow_typed(const DevPoset& d, int dir, const void* x, int64_t ldx, void* out, int64_t ldo,
-                                int64_t B, void* aux, int64_t ntiles, void* lq, void* snaps, LaunchHook* hook,
-                                hipStream_t s) {
+                                const void* resid, int64_t ldr, int64_t B, void* aux, int64_t ntiles, void* lq,
+                                void* snaps, LaunchHook* hook, hipStream_t s) {
   using St = typename ScanTraits<Tin, Tout>::St;
   const WalkTables& w = d.walk[dir > 0 ? 0 : 1];
   const int cw = col_width(B);
@@ -2796,7 +2806,8 @@ hipError_t compact_narrow_typed(const DevPoset& d, int dir, const void* x, int64
   const dim3 g((unsigned)((ntiles + tpw - 1) / tpw));
   const bool o32 = fits32((int64_t)d.n * ldx * (int64_t)sizeof(Tin)) &&
                    fits32((int64_t)d.n * ldo * (int64_t)sizeof(Tout)) &&
-                   fits32((int64_t)w.nsnap * B * (int64_t)sizeof(Tout));
+                   fits32((int64_t)w.nsnap * B * (int64_t)sizeof(Tout)) &&
+                   (MODE != 2 || fits32((int64_t)d.n * ldr * (int64_t)sizeof(Tres)));
   if (hook) hook->before(0, s);
   if (o32)
     hipLaunchKernelGGL((k_scan_reduce_cn<Tin, Tout, true>), g, dim3(WG), 0, s, d, cw, dir, (const Tin*)x, ldx, B,
@@ -2830,11 +2841,13 @@ hipError_t compact_narrow_typed(const DevPoset& d, int dir, const void* x, int64
   if (hook) hook->after(2, s);
   if (hook) hook->before(3, s);
   if (o32)
-    hipLaunchKernelGGL((k_scan_apply_cn<Tin, Tout, true>), g, dim3(WG), 0, s, d, cw, dir, (const Tin*)x, ldx, B,
-                       ntiles, (const St*)C, (Tout*)out, ldo, w.snap_of_row, (const Tout*)snaps);
+    hipLaunchKernelGGL((k_scan_apply_cn<Tin, Tout, MODE, Tres, true>), g, dim3(WG), 0, s, d, cw, dir, (const Tin*)x,
+                       ldx, B, ntiles, (const St*)C, (Tout*)out, ldo, w.snap_of_row, (const Tout*)snaps,
+                       (const Tres*)resid, ldr);
   else
-    hipLaunchKernelGGL((k_scan_apply_cn<Tin, Tout, false>), g, dim3(WG), 0, s, d, cw, dir, (const Tin*)x, ldx, B,
-                       ntiles, (const St*)C, (Tout*)out, ldo, w.snap_of_row, (const Tout*)snaps);
+    hipLaunchKernelGGL((k_scan_apply_cn<Tin, Tout, MODE, Tres, false>), g, dim3(WG), 0, s, d, cw, dir, (const Tin*)x,
+                       ldx, B, ntiles, (const St*)C, (Tout*)out, ldo, w.snap_of_row, (const Tout*)snaps,
+                       (const Tres*)resid, ldr);
   if (hook) hook->after(3, s);
   return hipGetLastError();
 }
@@ -2846,10 +2859,11 @@ hipError_t compact_typed(const DevPoset& d, int dir, const void* x, int64_t ldx,
   using St = typename ScanTraits<Tin, Tout>::St;
   const WalkTables& w = d.walk[dir > 0 ? 0 : 1];
   const int segi = seg_index(64);
-  if constexpr (MODE == 1) {
+  {
     const int cw = col_width(B);
     if (cw >= 8 && cw <= 32)
-      return compact_narrow_typed<Tin, Tout>(d, dir, x, ldx, out, ldo, B, aux, ntiles, lq, snaps, hook, s);
+      return compact_narrow_typed<Tin, Tout, MODE, Tres>(d, dir, x, ldx, out, ldo, resid, ldr, B, aux, ntiles, lq,
+                                                         snaps, hook, s);
   }
   St* A = (St*)aux;
   St* C = A + ntiles * B;

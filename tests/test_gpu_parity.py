@@ -508,7 +508,8 @@ def test_narrow_compact_walk(px, B, monkeypatch):
     (k_scan_reduce_cn, the shared carry, the walk on Q, k_scan_apply_cn: P is never
     formed).  Zeta and its adjoint equal the scan over P (POSETX_COMPACT_NARROW=0) and
     the closure oracle: int64 bit for bit, float32 within the compensated bound, float64
-    to rounding; with the walk on Q in both its vector-lane and lane-split forms.
+    to rounding; with the walk on Q in both its vector-lane and lane-split forms.  The
+    refined float32 Möbius, whose float64 residuals take the same path, recovers f.
     Chains of about 167 rows put chain ends inside the 64-row tiles a workgroup spans."""
     p = W.chain_poset(4000, 24, 3, seed=B)
     R = O.reachability(p.n, p.indptr, p.indices)
@@ -518,9 +519,15 @@ def test_narrow_compact_walk(px, B, monkeypatch):
     fd = W.functions(p.n, B, "normal64", seed=B + 2)
     za = O.zeta(R, np.abs(ff).astype(np.float64), exact=False)
     zta = O.zeta_adjoint(R, np.abs(ff).astype(np.float64), exact=False)
+    fs = W.functions(p.n, B, "int", seed=B + 3, lo=-1000, hi=1000)
+    gs = O.zeta(R, fs).astype(np.float32)       # exact in float32 (|g| < 2**24)
     monkeypatch.setenv("POSETX_COMPACT_NARROW", "0")
     base = (H(px.zeta(P, T(fi))), H(px.zeta_adjoint(P, T(fi))))
+    mob0 = H(px.mobius(P, T(gs), max_refine=3))
     monkeypatch.delenv("POSETX_COMPACT_NARROW")
+    # the refined float32 Möbius, whose residuals now run through the narrow compact walk
+    mob = H(px.mobius(P, T(gs), max_refine=3))
+    assert rel(mob, fs) <= max(2 * rel(mob0, fs), 1e-6)
     for vec in ("0", "1"):
         monkeypatch.setenv("POSETX_WALK_VEC", vec)
         g, a = H(px.zeta(P, T(fi))), H(px.zeta_adjoint(P, T(fi)))
