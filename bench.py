@@ -368,6 +368,20 @@ def leg_batched(px, dev, steps, count=512):
     t_graph_r = _time(graph_r.replay, steps, sync)
     rows_equal = bool(torch.equal(gr[perm], g) and torch.equal(gwr[perm], gw))
     bt.set_layout("nodes")
+    # load balance of the walk (its dominant kernel): workgroups take the runs in 8
+    # contiguous slices, one per XCD, poset after poset; events per slice, from each
+    # poset's run and event counts (events spread evenly over a poset's runs)
+    infos = [P.info_dict() for P in Ps]
+    runs = np.array([i["walk_runs"] for i in infos], np.float64)
+    evs = np.array([i["walk_events"] for i in infos], np.float64)
+    edges = np.linspace(0, runs.sum(), 9)
+    cum = np.concatenate([[0], np.cumsum(runs)])
+    per_xcd = []
+    for a, b in zip(edges[:-1], edges[1:]):
+        lo = np.clip(np.minimum(cum[1:], b) - np.maximum(cum[:-1], a), 0, None)
+        per_xcd.append(float((lo / np.maximum(runs, 1) * evs).sum()))
+    balance = {"walk_events_per_xcd_max_over_mean": round(max(per_xcd) / (sum(per_xcd) / 8), 3),
+               "walk_runs": int(runs.sum()), "walk_events": int(evs.sum())}
     # compulsory bytes of forward + adjoint: per direction the niv map (4k B per row)
     # and f, P written, P read and g (4 B per row and RHS each)
     nk = sum(int(P.n) * int(P.k) for P in Ps)
@@ -380,7 +394,7 @@ def leg_batched(px, dev, steps, count=512):
             "alg_bytes": alg, "hbm_floor_ms": round(floor_ms, 4),
             "frac_of_floor": round(floor_ms / (t_graph * 1e3), 4),
             "graph_fwd_adj_rows_layout_ms": round(t_graph_r * 1e3, 4), "rows_layout_equal": rows_equal,
-            "frac_of_floor_rows_layout": round(floor_ms / (t_graph_r * 1e3), 4)}
+            "frac_of_floor_rows_layout": round(floor_ms / (t_graph_r * 1e3), 4), "load_balance": balance}
 
 
 def leg_large(px, dev, steps):
