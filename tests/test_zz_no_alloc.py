@@ -56,9 +56,10 @@ def _poset(px, n, k, seed):
 def test_noalloc_matches_px_zeta_on_two_calls(px, kind):
     import torch
     dtype = torch.float32 if kind == "normal" else torch.int64
-    # first call: the compact walk (k <= 64, B = 64) over 2^17 rows; second: a
-    # smaller poset and B = 8 (the scan over P and the lane-split walk)
-    for n, k, B, seed in ((1 << 17, 64, 64, 11), (3000, 24, 8, 12)):
+    # first call: the compact walk (k <= 64, B = 64) over 2^17 rows; then smaller
+    # ones: B = 8 (the narrow compact walk) and B = 4 (the scan over P and the
+    # lane-split walk)
+    for n, k, B, seed in ((1 << 17, 64, 64, 11), (3000, 24, 8, 12), (2000, 24, 4, 13)):
         p, P = _poset(px, n, k, seed)
         f = W.functions(n, B, kind, seed=seed + 100, lo=-1000, hi=1000)
         x = torch.from_numpy(f).cuda()
