@@ -1,7 +1,7 @@
 """Benchmark of the fast zeta transform on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--legs none|default|all|sparse|batched|chains]
+                    [--legs none|default|all|sparse|batched|chains|large]
 
 Workload (the headline configuration): a random-height poset with
 n = 2^20 elements, k = 64 planted chains of 16,384 elements, 3 cross edges
@@ -555,9 +555,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
-    ap.add_argument("--legs", default="default", choices=["none", "default", "all", "sparse", "batched", "chains"],
+    ap.add_argument("--legs", default="default", choices=["none", "default", "all", "sparse", "batched", "chains",
+                                                          "large"],
                     help="extra measurements of the other hot-path rows (all: also the batched, n=2^23 and "
-                         "Erdős–Rényi configs; sparse / batched: that config alone)")
+                         "Erdős–Rényi configs; sparse / batched / large: that config alone)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for counter scaling)")
     args = ap.parse_args()
@@ -738,6 +739,9 @@ def main():
     elif args.legs == "batched":
         del P
         out["legs"] = {"batched": leg_batched(px, dev, args.steps)}
+    elif args.legs == "large":
+        del P
+        out["legs"] = {"large": leg_large(px, dev, max(2, args.steps // 4))}
     elif args.legs != "none":
         def note(msg):
             print(f"[bench] {msg}", file=sys.stderr, flush=True)
