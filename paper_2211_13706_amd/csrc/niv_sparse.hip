@@ -197,9 +197,11 @@ __global__ __launch_bounds__(SWG) void k_udep_level(int64_t cnt, const int32_t* 
 // Each thread takes up to SEQ_PP (row, entry) pairs of a height, the rows'
 // maxima meet in LDS (two buffers, alternating by height), and a workgroup
 // barrier orders one height's level stores before the next height's loads
-// (all wavefronts share one compute unit and its cache).  One launch per
-// height costs about 4.7 us, one height here about a microsecond.
-constexpr int SEQ_WG = 1024, SEQ_PP = 8, SEQ_ROWS = 128;
+// (all wavefronts share one compute unit and its cache).  Measured per height:
+// one launch about 3.4 to 4.7 us, this loop 1.9 us with 1,024 pairs (n = 2^23,
+// k = 32) but 4.2 us with 4,096 (n = 2^20, k = 64: 64 atomics on each row's
+// maximum), so heights of more than SEQ_WG * SEQ_PP pairs take a launch each.
+constexpr int SEQ_WG = 1024, SEQ_PP = 2, SEQ_ROWS = 128;
 __global__ __launch_bounds__(SEQ_WG) void k_udep_levels_seq(int64_t h0, int64_t h1, const int64_t* __restrict__ hptr,
                                                            const int32_t* __restrict__ R, int k,
                                                            const int32_t* __restrict__ E, int32_t* lev) {
