@@ -863,7 +863,7 @@ int flow_spin_limit() {
 // the error word and a ready flag per row and column block.
 int64_t flow_ints(const px_poset* p, int64_t B) {
   if (!p->d_run_chunks[0]) return 0;
-  const int cw = px::col_width(B);
+  const int cw = px::flow_col_width(B);
   const int64_t ncb = (B + cw - 1) / cw;
   const int64_t nch = std::max(p->run_cptr[0].empty() ? 0 : p->run_cptr[0].back(),
                                p->run_cptr[1].empty() ? 0 : p->run_cptr[1].back());
@@ -933,10 +933,11 @@ hipError_t solve_levels(const px_poset* p, bool up, px::ElemType tin, const void
       prof::Scope sc(prof::USOLVE, s);
       const char* wv = std::getenv("POSETX_FLOW_WAIT");
       const char* gv = std::getenv("POSETX_FLOW_GRID");
-      // measured: at n = 2^20, k = 64, B = 64 waiting on the chunks read from took 3.3 ms against
-      // 4.4 ms on the rows read; at n = 2^23, k = 32, B = 16 the rows took 9.1 ms against 12.0 ms
-      // (the row groups of a narrow tile proceed as soon as their own rows are ready)
-      int wait = px::col_width(B) == 64 ? px::kWaitDeps : px::kWaitRows;
+      // measured: with 64-column tiles (n = 2^20, k = 64, B = 64) waiting on the chunks read from
+      // took 3.3 ms against 4.4 ms on the rows read; with narrower tiles the rows win: 3.0 against
+      // 3.4 ms there at 32 columns, 9.1 against 12.0 ms at n = 2^23, k = 32, B = 16 (the row groups
+      // of a narrow tile proceed as soon as their own rows are ready)
+      int wait = px::flow_col_width(B) == 64 ? px::kWaitDeps : px::kWaitRows;
       if (wv && std::strcmp(wv, "rows") == 0) wait = px::kWaitRows;
       if (wv && std::strcmp(wv, "level") == 0) wait = px::kWaitLevel;
       if (wv && std::strcmp(wv, "deps") == 0) wait = px::kWaitDeps;

@@ -127,6 +127,9 @@ struct DevPoset {
 int col_width(int64_t B);
 int seg_index(int cw);     // 0..6
 int seg_rows(int cw);      // rows of one scan tile
+// Column tile of the persistent int64 solve (launch_usolve_flow): col_width(B)
+// up to 32, or a narrower power of two from POSETX_FLOW_CW (read on every call).
+int flow_col_width(int64_t B);
 
 // Chain scan V x (forward, dir=+1, prefix from the bottom) or V^T x (dir=-1,
 // suffix from the top), three deterministic phases.  x is node order

@@ -43,6 +43,20 @@ int seg_index(int cw) {
 }
 int seg_rows(int cw) { return (WG / cw) * RPT; }
 
+// 32 columns at most: at n = 2^20, k = 64, B = 64 two 32-column halves of each
+// chunk, each waiting on the rows it reads, took 3.0 ms against 3.3 ms for one
+// 64-column workgroup waiting on the chunks it reads (16 columns: 3.3 ms, 8:
+// 5.2 ms); a chunk's half moves half the bytes between its wait and its flag.
+int flow_col_width(int64_t B) {
+  const int cw = std::min(col_width(B), 32);
+  const char* e = std::getenv("POSETX_FLOW_CW");
+  if (e && *e) {
+    const int v = std::atoi(e);
+    if ((v == 8 || v == 16 || v == 32 || v == 64) && v <= cw) return v;
+  }
+  return cw;
+}
+
 // Every byte offset of a buffer of `bytes` fits an unsigned 32-bit offset
 // (POSETX_O32=0, read on every call, takes 64-bit offsets everywhere).
 bool fits32(int64_t bytes) {
@@ -3247,7 +3261,7 @@ hipError_t launch_usolve_flow(const DevPoset& d, bool up, const int4* chunks, in
   if (nchunks == 0) return hipSuccess;
   const int32_t* nv = up ? d.niv_up : d.niv;
   const SegTables& t = d.seg[up ? 1 : 0];
-  const int cw = col_width(B);
+  const int cw = flow_col_width(B);
   const int64_t ncb = (B + cw - 1) / cw;
   if (!nv || !t.ev || !lev_off || (wait == kWaitDeps && (!dep_ptr || !deps)) || nchunks * ncb >= INT32_MAX ||
       (int64_t)d.n + 1 >= INT32_MAX || cw < 8 || wait < kWaitRows || wait > kWaitDeps)
