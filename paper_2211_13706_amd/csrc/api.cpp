@@ -1397,18 +1397,24 @@ static px_status finish_poset(px_poset* p, int device, px_poset** out) {
     }
     if (e == hipSuccess) e = upload(&p->d_lev_down, P.lev_down_rows.data(), P.lev_down_rows.size(), b);
     if (e == hipSuccess && p->has_up) e = upload(&p->d_lev_up, P.lev_up_rows.data(), P.lev_up_rows.size(), b);
-    // level-ordered niv rows and node ids for the uniform level solve
+    // level-ordered niv rows and node ids for the uniform level solve, gathered
+    // on the device from the maps and level orders already there
     for (int dir = 0; dir < 2 && e == hipSuccess && P.k <= 64 && !P.sparse; ++dir) {
       if (dir == 1 && !p->has_up) break;
-      const std::vector<int32_t>& lr = dir ? P.lev_up_rows : P.lev_down_rows;
-      const std::vector<int32_t>& nv = dir ? P.niv_up : P.niv;
-      std::vector<int32_t> lnv(lr.size() * P.k), lnode(lr.size());
-      for (size_t i = 0; i < lr.size(); ++i) {
-        std::copy_n(&nv[(size_t)lr[i] * P.k], P.k, &lnv[i * P.k]);
-        lnode[i] = P.node_of_row[lr[i]];
+      const int32_t* d_lr = dir ? p->d_lev_up : p->d_lev_down;
+      const int32_t* d_nv = dir ? p->d_niv_up : p->d_niv;
+      const int64_t cnt = (int64_t)(dir ? P.lev_up_rows.size() : P.lev_down_rows.size());
+      if (!d_lr || !d_nv) {
+        e = hipErrorInvalidValue;
+        break;
       }
-      e = upload(&p->d_lev_niv[dir], lnv.data(), lnv.size(), b);
-      if (e == hipSuccess) e = upload(&p->d_lev_node[dir], lnode.data(), lnode.size(), b);
+      e = hipMalloc((void**)&p->d_lev_niv[dir], std::max<int64_t>(cnt * P.k, 1) * sizeof(int32_t));
+      if (e == hipSuccess) e = hipMalloc((void**)&p->d_lev_node[dir], std::max<int64_t>(cnt, 1) * sizeof(int32_t));
+      if (e == hipSuccess) {
+        b += (cnt * P.k + cnt) * (int64_t)sizeof(int32_t);
+        e = px::device_gather_rows(d_nv, (int)P.k, d_lr, cnt, p->d_node_of_row, p->d_lev_niv[dir],
+                                   p->d_lev_node[dir]);
+      }
       p->dp.lev_niv[dir] = p->d_lev_niv[dir];
       p->dp.lev_node[dir] = p->d_lev_node[dir];
     }

@@ -1,6 +1,8 @@
 // The niv maps computed on the device (dense rows); see niv_device.hip.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -34,10 +36,17 @@ int device_niv_sparse(Prep& P, const int64_t* indptr, const int32_t* indices, co
                       int32_t* out_rows[2], std::string& msg);
 
 // The U-dependency levels of one map on the current device from the map's
-// device rows (dense [n, k] nv, or sparse ep / er), one launch per height
-// (hptr / hnodes), copied into lev.  Returns PX_OK, or -1 on any HIP error
-// (the caller computes them on the host instead).
+// device rows (dense [n, k] nv, or sparse ep / er), height after height
+// (hptr / hnodes: runs of narrow heights in one single-workgroup launch, wider
+// heights a launch each), copied into lev.  Returns PX_OK, or -1 on any HIP
+// error (the caller computes them on the host instead).
 int device_udep_levels(const Prep& P, const std::vector<int64_t>& hptr, const std::vector<int32_t>& hnodes,
                        const int32_t* nv, const int64_t* ep, const int32_t* er, std::vector<int32_t>& lev);
+
+// Rows of a dense device map in a given order, on the current device (all
+// pointers device memory): dst[i * k + j] = src[rows[i] * k + j] and
+// nodes[i] = node_of_row[rows[i]] for i < cnt.  Returns the launch status.
+hipError_t device_gather_rows(const int32_t* src, int k, const int32_t* rows, int64_t cnt,
+                              const int32_t* node_of_row, int32_t* dst, int32_t* nodes);
 
 }  // namespace px

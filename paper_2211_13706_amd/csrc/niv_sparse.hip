@@ -478,4 +478,24 @@ int device_udep_levels(const Prep& P, const std::vector<int64_t>& hptr, const st
   return PX_OK;
 }
 
+__global__ __launch_bounds__(SWG) void k_gather_rows(const int32_t* __restrict__ src, int k,
+                                                     const int32_t* __restrict__ rows, int64_t cnt,
+                                                     const int32_t* __restrict__ node_of_row,
+                                                     int32_t* __restrict__ dst, int32_t* __restrict__ nodes) {
+  const int64_t q = (int64_t)blockIdx.x * SWG + threadIdx.x;
+  if (q >= cnt * k) return;
+  const int64_t i = q / k, j = q % k;
+  const int r = rows[i];
+  dst[q] = src[(int64_t)r * k + j];
+  if (j == 0) nodes[i] = node_of_row[r];
+}
+
+hipError_t device_gather_rows(const int32_t* src, int k, const int32_t* rows, int64_t cnt,
+                              const int32_t* node_of_row, int32_t* dst, int32_t* nodes) {
+  if (cnt == 0 || k == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rows, dim3(nblocks(cnt * k, SWG)), dim3(SWG), 0, 0, src, k, rows, cnt, node_of_row,
+                     dst, nodes);
+  return hipGetLastError();
+}
+
 }  // namespace px
