@@ -14,6 +14,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.h"
@@ -150,6 +151,57 @@ std::vector<int32_t> tile_tables(const std::vector<int32_t>& chain_off, int64_t 
 constexpr int kWalkT = 128;
 constexpr int kWalkEvents = 96;
 
+// Host threads of the table builders (walk, compact and run tables): up to 16
+// for posets of 2^15 rows or more; POSETX_PREP_THREADS overrides (1..64).
+// The tables do not depend on the thread count.
+int table_threads(int64_t n) {
+  if (const char* v = std::getenv("POSETX_PREP_THREADS")) {
+    const int t = std::atoi(v);
+    if (t >= 1) return std::min(t, 64);
+  }
+  if (n < (1 << 15)) return 1;
+  const unsigned hc = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(16u, hc ? hc : 1u));
+}
+
+// fn(t, lo, hi) over [0, count) in nt contiguous ascending parts, part t on
+// thread t (part 0 on the caller's thread).
+template <typename F>
+void parallel_for(int64_t count, int nt, const F& fn) {
+  nt = (int)std::max<int64_t>(1, std::min<int64_t>(nt, count));
+  if (nt <= 1) {
+    if (count > 0) fn(0, (int64_t)0, count);
+    return;
+  }
+  const int64_t part = (count + nt - 1) / nt;
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) {
+    const int64_t lo = t * part, hi = std::min(count, lo + part);
+    if (lo < hi) th.emplace_back([&fn, t, lo, hi] { fn(t, lo, hi); });
+  }
+  fn(0, (int64_t)0, std::min(count, part));
+  for (auto& x : th) x.join();
+}
+
+// The other-chain entries of every row that differ from the row below it in
+// its chain (0 for a chain's first row).
+std::vector<int32_t> row_changes(const px::Prep& P, const std::vector<int32_t>& nv, int nt) {
+  const int64_t n = P.n, k = P.k;
+  std::vector<int32_t> cnt(n, 0);
+  parallel_for(n, nt, [&](int, int64_t lo, int64_t hi) {
+    for (int64_t r = lo; r < hi; ++r) {
+      const int32_t c = P.chain_of_row[r];
+      if (r == P.chain_off[c]) continue;
+      const int32_t* a = &nv[(size_t)r * k];
+      const int32_t* b = a - k;
+      int e = 0;
+      for (int64_t j = 0; j < k; ++j) e += (j != c && a[j] != b[j]);
+      cnt[r] = e;
+    }
+  });
+  return cnt;
+}
+
 struct HostWalk {
   std::vector<int32_t> runs;  // pairs (r0, r1)
   std::vector<int32_t> ev;    // quadruples (new row, old row, (u << 8) | chain, 0), -1 = none
@@ -160,66 +212,74 @@ struct HostWalk {
 
 void build_walk(const px::Prep& P, const std::vector<int32_t>& nv, HostWalk& W, int T, int emax) {
   const int64_t k = P.k, n = P.n;
-  auto nchanges = [&](int32_t r) {  // other-chain entries of row r that differ from row r-1
-    const int32_t c = P.chain_of_row[r];
-    const int32_t* a = &nv[(size_t)r * k];
-    const int32_t* b = &nv[(size_t)(r - 1) * k];
-    int cnt = 0;
-    for (int64_t j = 0; j < k; ++j) cnt += (j != c && a[j] != b[j]);
-    return cnt;
-  };
+  const int nt = table_threads(n);
+  const std::vector<int32_t> ch = row_changes(P, nv, nt);
   struct Run {
     double h;
     int32_t c, r0, r1;
   };
-  std::vector<Run> runs;
-  for (int64_t c = 0; c < k; ++c) {
-    const int32_t lo = P.chain_off[c], hi = P.chain_off[c + 1];
-    int32_t r = lo;
-    while (r < hi) {
-      const int32_t r0 = r++;
-      int ev = 0;
-      while (r < hi && r - r0 < T) {
-        const int e = nchanges(r);
-        if (ev + e > emax && r > r0 + 1) break;
-        ev += e;
-        ++r;
-      }
-      runs.push_back({(0.5 * (r0 + r) - lo) / (double)(hi - lo), (int32_t)c, r0, r});
-    }
-  }
-  std::stable_sort(runs.begin(), runs.end(), [](const Run& x, const Run& y) { return x.h < y.h; });
-  W.runs.resize(2 * runs.size());
-  W.ev.clear();
-  W.ev_off.assign(runs.size() + 1, 0);
-  W.snap_off.assign(runs.size() + 1, 0);
-  W.snap_of_row.assign(n, 0);
-  int32_t m = 0;
-  for (size_t s = 0; s < runs.size(); ++s) {
-    const Run& R = runs[s];
-    W.runs[2 * s] = R.r0;
-    W.runs[2 * s + 1] = R.r1;
-    W.snap_off[s] = m;
-    int32_t cur = m++;
-    W.snap_of_row[R.r0] = cur;
-    for (int32_t r = R.r0 + 1; r < R.r1; ++r) {
-      const int32_t* a = &nv[(size_t)r * k];
-      const int32_t* b = &nv[(size_t)(r - 1) * k];
-      bool any = false;
-      for (int64_t j = 0; j < k; ++j)
-        if (j != R.c && a[j] != b[j]) {
-          W.ev.push_back(a[j]);
-          W.ev.push_back(b[j]);
-          W.ev.push_back(((r - R.r0) << 8) | (int32_t)std::min<int64_t>(j, 255));
-          W.ev.push_back(0);
-          any = true;
+  // runs chain by chain (each thread a contiguous range of chains, joined in order)
+  std::vector<std::vector<Run>> part(std::max(1, nt));
+  parallel_for(k, nt, [&](int t, int64_t c0, int64_t c1) {
+    for (int64_t c = c0; c < c1; ++c) {
+      const int32_t lo = P.chain_off[c], hi = P.chain_off[c + 1];
+      int32_t r = lo;
+      while (r < hi) {
+        const int32_t r0 = r++;
+        int ev = 0;
+        while (r < hi && r - r0 < T) {
+          const int e = ch[r];
+          if (ev + e > emax && r > r0 + 1) break;
+          ev += e;
+          ++r;
         }
-      if (any) cur = m++;
-      W.snap_of_row[r] = cur;
+        part[t].push_back({(0.5 * (r0 + r) - lo) / (double)(hi - lo), (int32_t)c, r0, r});
+      }
     }
-    W.ev_off[s + 1] = (int32_t)(W.ev.size() / 4);
+  });
+  std::vector<Run> runs;
+  for (auto& v : part) runs.insert(runs.end(), v.begin(), v.end());
+  std::stable_sort(runs.begin(), runs.end(), [](const Run& x, const Run& y) { return x.h < y.h; });
+  const size_t nr = runs.size();
+  W.runs.resize(2 * nr);
+  W.ev_off.assign(nr + 1, 0);
+  W.snap_off.assign(nr + 1, 0);
+  W.snap_of_row.assign(n, 0);
+  // events and snapshots per run, then their offsets
+  for (size_t s = 0; s < nr; ++s) {
+    int64_t e = 0, m = 1;  // the first row's snapshot, then one per row with events
+    for (int32_t r = runs[s].r0 + 1; r < runs[s].r1; ++r) {
+      e += ch[r];
+      m += ch[r] > 0;
+    }
+    W.ev_off[s + 1] = (int32_t)(W.ev_off[s] + e);
+    W.snap_off[s + 1] = (int32_t)(W.snap_off[s] + m);
   }
-  W.snap_off[runs.size()] = m;
+  W.ev.assign(4 * (size_t)W.ev_off[nr], 0);
+  parallel_for((int64_t)nr, nt, [&](int, int64_t s0, int64_t s1) {
+    for (int64_t s = s0; s < s1; ++s) {
+      const Run& R = runs[s];
+      W.runs[2 * s] = R.r0;
+      W.runs[2 * s + 1] = R.r1;
+      int32_t cur = W.snap_off[s];
+      size_t o = 4 * (size_t)W.ev_off[s];
+      W.snap_of_row[R.r0] = cur;
+      for (int32_t r = R.r0 + 1; r < R.r1; ++r) {
+        const int32_t* a = &nv[(size_t)r * k];
+        const int32_t* b = &nv[(size_t)(r - 1) * k];
+        for (int64_t j = 0; j < k; ++j)
+          if (j != R.c && a[j] != b[j]) {
+            W.ev[o++] = a[j];
+            W.ev[o++] = b[j];
+            W.ev[o++] = ((r - R.r0) << 8) | (int32_t)std::min<int64_t>(j, 255);
+            W.ev[o++] = 0;
+          }
+        if (ch[r] > 0) ++cur;
+        W.snap_of_row[r] = cur;
+      }
+    }
+  });
+  const int32_t m = W.snap_off[nr];
   W.nsnap = m;
   // P rows read by the event kernel: the other-chain entries of every run's
   // first row, and the new and old rows of every event
@@ -777,20 +837,27 @@ bool build_runs(const px::Prep& P, bool up, std::vector<int4>& ev, std::vector<i
   const std::vector<int32_t>& nv = up ? P.niv_up : P.niv;
   const std::vector<int32_t>& ptr = up ? P.lev_up_ptr : P.lev_down_ptr;
   const std::vector<int32_t>& rows = up ? P.lev_up_rows : P.lev_down_rows;
+  const int nt = table_threads(n);
+  const std::vector<int32_t> ch = row_changes(P, nv, nt);
   std::vector<int32_t> ev_ptr(n + 1, 0);
-  ev.clear();
+  int64_t nev = 0;
   for (int64_t r = 0; r < n; ++r) {
-    const int32_t c = P.chain_of_row[r];
-    if (r > P.chain_off[c]) {
+    nev += ch[r];
+    if (nev >= (int64_t)INT32_MAX) return false;
+    ev_ptr[r + 1] = (int32_t)nev;
+  }
+  ev.assign((size_t)nev, make_int4(0, 0, 0, 0));
+  parallel_for(n, nt, [&](int, int64_t lo, int64_t hi) {
+    for (int64_t r = lo; r < hi; ++r) {
+      if (ch[r] == 0) continue;
+      const int32_t c = P.chain_of_row[r];
       const int32_t* a = &nv[(size_t)r * k];
       const int32_t* b = a - k;
+      int64_t o = ev_ptr[r];
       for (int64_t j = 0; j < k; ++j)
-        if (j != c && a[j] != b[j])
-          ev.push_back(make_int4(a[j] < 0 ? (int)n : a[j], b[j] < 0 ? (int)n : b[j], (int)r, 0));
+        if (j != c && a[j] != b[j]) ev[o++] = make_int4(a[j] < 0 ? (int)n : a[j], b[j] < 0 ? (int)n : b[j], (int)r, 0);
     }
-    if (ev.size() >= (size_t)INT32_MAX) return false;
-    ev_ptr[r + 1] = (int32_t)ev.size();
-  }
+  });
   // deltas read two rows per event against k - 1 for a full sum: only worth it
   // where they read at most half as much (not on a grid, where row i of chain j
   // changes all j entries below it)
@@ -813,32 +880,49 @@ bool build_runs(const px::Prep& P, bool up, std::vector<int4>& ev, std::vector<i
   }
   if (chunks.size() >= (size_t)INT32_MAX) return false;
   // the chunks that each chunk reads from: those holding its first row's
-  // other-chain entries and its events' rows (all at lower levels)
-  std::vector<int32_t> chunk_of(n, -1), seen(chunks.size(), -1);
-  for (size_t c = 0; c < chunks.size(); ++c)
+  // other-chain entries and its events' rows (all at lower levels); each thread
+  // a contiguous range of chunks, joined in order
+  const int64_t nch = (int64_t)chunks.size();
+  std::vector<int32_t> chunk_of(n, -1);
+  for (int64_t c = 0; c < nch; ++c)
     for (int32_t r = chunks[c].x; r < chunks[c].x + (chunks[c].y & 63); ++r) chunk_of[r] = (int32_t)c;
-  dep_ptr.assign(1, 0);
-  deps.clear();
-  auto add = [&](int32_t row, int32_t c) {
-    if (row < 0 || row >= n) return;
-    const int32_t q = chunk_of[row];
-    if (q >= 0 && q != c && seen[q] != c) {
-      seen[q] = c;
-      deps.push_back(q);
+  const int ntd = (int)std::max<int64_t>(1, std::min<int64_t>(nt, nch));
+  std::vector<std::vector<int32_t>> dpart(ntd);
+  std::vector<int32_t> dcnt(nch, 0);
+  parallel_for(nch, ntd, [&](int t, int64_t c0, int64_t c1) {
+    std::vector<int32_t> seen(nch, -1);
+    std::vector<int32_t>& out = dpart[t];
+    for (int64_t c = c0; c < c1; ++c) {
+      const size_t before = out.size();
+      auto add = [&](int32_t row) {
+        if (row < 0 || row >= n) return;
+        const int32_t q = chunk_of[row];
+        if (q >= 0 && q != c && seen[q] != c) {
+          seen[q] = (int32_t)c;
+          out.push_back(q);
+        }
+      };
+      const int4 chk = chunks[c];
+      const int32_t* a = &nv[(size_t)chk.x * k];
+      for (int64_t j = 0; j < k; ++j)
+        if (a[j] != chk.x) add(a[j]);
+      for (int32_t e = chk.z; e < chk.w; ++e) {
+        add(ev[e].x);
+        add(ev[e].y);
+      }
+      dcnt[c] = (int32_t)(out.size() - before);
     }
-  };
-  for (size_t c = 0; c < chunks.size(); ++c) {
-    const int4 ch = chunks[c];
-    const int32_t* a = &nv[(size_t)ch.x * k];
-    for (int64_t j = 0; j < k; ++j)
-      if (a[j] != ch.x) add(a[j], (int32_t)c);
-    for (int32_t e = ch.z; e < ch.w; ++e) {
-      add(ev[e].x, (int32_t)c);
-      add(ev[e].y, (int32_t)c);
-    }
-    if (deps.size() >= (size_t)INT32_MAX) return false;
-    dep_ptr.push_back((int32_t)deps.size());
+  });
+  dep_ptr.assign(nch + 1, 0);
+  int64_t nd = 0;
+  for (int64_t c = 0; c < nch; ++c) {
+    nd += dcnt[c];
+    if (nd >= (int64_t)INT32_MAX) return false;
+    dep_ptr[c + 1] = (int32_t)nd;
   }
+  deps.clear();
+  deps.reserve((size_t)nd);
+  for (auto& v : dpart) deps.insert(deps.end(), v.begin(), v.end());
   return true;
 }
 

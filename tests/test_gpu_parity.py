@@ -871,6 +871,30 @@ def test_offsets_32_and_64_bit(px, B, monkeypatch):
         assert np.array_equal(a, O.zeta_adjoint(R, f)), key
 
 
+def test_table_builders_thread_count_independent(px, monkeypatch):
+    """The walk, compact and run tables (built on host threads) are the same for one
+    thread and for several: equal table statistics and bit-equal int64 zeta, adjoint and
+    Möbius results, which also match the oracle on sampled elements."""
+    import torch
+    p = W.chain_poset(1 << 16, 24, 3, seed=31)
+    f = W.functions(p.n, 8, "int", seed=32, lo=-1000, hi=1000)
+    keys = ("walk_runs", "walk_events", "walk_snapshots", "walk_rows_distinct", "walk_row_loads", "run_chunks",
+            "run_events")
+    res = {}
+    for thr in ("1", "5"):
+        monkeypatch.setenv("POSETX_PREP_THREADS", thr)
+        P = build(px, p)
+        info = P.info_dict()
+        res[thr] = ({k: info[k] for k in keys}, H(px.zeta(P, T(f))), H(px.zeta_adjoint(P, T(f))),
+                    H(px.mobius(P, px.zeta(P, T(f)))))
+    assert res["1"][0] == res["5"][0]
+    for a, b in zip(res["1"][1:], res["5"][1:]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(res["5"][3], f)
+    nodes = np.random.default_rng(33).choice(p.n, 8, replace=False)
+    assert np.array_equal(res["5"][1][nodes], O.zeta_at(p.n, p.indptr, p.indices, f, nodes))
+
+
 # ------------------------------------------------------------ error handling
 def test_argument_errors_and_nonfinite(px, cfg0):
     import torch
