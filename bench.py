@@ -321,7 +321,8 @@ def leg_batched(px, dev, steps, count=512):
     sync = torch.cuda.synchronize
     t0 = time.perf_counter()
     posets = W.batched_posets(count, seed=40)
-    Ps = [px.poset_build(q.n, q.indptr, q.indices, q.chain_of, q.chain_pos, device=0) for q in posets]
+    # the posets are independent: built on several host threads at once
+    Ps = px.poset_build_many([(q.n, q.indptr, q.indices, q.chain_of, q.chain_pos) for q in posets], device=0)
     bt = px.batch_build(Ps)
     t_prep = time.perf_counter() - t0
     Bb = 8

@@ -40,9 +40,10 @@
  *    crosses this interface.
  *  - Execution paths (results agree to rounding; int64 bit for bit), read from
  *    the environment on every call: for a single poset with at most 64 chains
- *    and B > 32, zeta and its adjoint complete the chain prefixes only at the
- *    rows the gather reads and never form the full prefix matrix;
- *    POSETX_WALK=rows forms it instead.  POSETX_SCAN=onepass selects the
+ *    and B >= 5, zeta, its adjoint and the residual of the refined Mobius
+ *    transform complete the chain prefixes only at the rows the gather reads
+ *    and never form the full prefix matrix (POSETX_COMPACT_NARROW=0 keeps that
+ *    to B > 32, =2 extends it to every B); POSETX_WALK=rows forms it instead.  POSETX_SCAN=onepass selects the
  *    single-pass chain scan for the paths that form it, with POSETX_LB_SPIN
  *    bounding its waits (polls; 0 makes every wait give up and sum its
  *    predecessors from the input).  POSETX_TUNE_CACHE: see px_autotune.
@@ -159,7 +160,9 @@ typedef struct {
  *   flags      PX_BUILD_* bits
  *   device     HIP device ordinal (ignored with PX_BUILD_HOST_ONLY)
  *   out        receives the handle; free it with px_poset_free
- * Host arrays are copied.  Synchronous.
+ * Host arrays are copied.  Synchronous.  Builds share no state: calls on
+ * several host threads may run at once, each returning its own handle, with
+ * the same result as one call after another.
  */
 px_status px_poset_build(int64_t n, const int64_t* indptr, const int32_t* indices,
                          const int32_t* chain_of, const int32_t* chain_pos, uint32_t flags,
@@ -240,7 +243,7 @@ px_status px_zeta_adjoint(px_poset* p, int dtype, const void* w, int64_t ldw, vo
  * the first call there.
  *   Returns PX_EINVAL, before launching anything, when the call needs more than
  *   64 MiB of scratch (the message says how much).  The scratch of the compact
- *   walk (one poset, k <= 64, B > 32) is small: at n = 2^20, k = 64, B = 64 float32
+ *   walk (one poset, k <= 64, B >= 5) is small: at n = 2^20, k = 64, B = 64 float32
  *   it needs about 97 MiB, so that size is rejected while n = 2^19 fits; the scan
  *   over P (other shapes) needs (n + 1) * B * elem bytes for P and fits while
  *   n * B * elem stays below about 60 MiB.

@@ -13,12 +13,12 @@ hand-written HIP kernels behind a C ABI (include/posetx.h, libposetx.so).
 
 from ._lib import (PX_BUILD_HOST_ONLY, PX_BUILD_LEVELS_MIRSKY, PX_BUILD_MIN_CHAINS, PX_BUILD_NO_ADJOINT,
                    PX_BUILD_SPARSE_NIV, PX_F32, PX_F64, PX_I64, PosetxError, lib)
-from .poset import (Batch, Poset, batch_build, mobius, mobius_adjoint, poset_build, poset_load, zeta,
-                    zeta_adjoint, zeta_adjoint_batched, zeta_batched, zeta_noalloc)
+from .poset import (Batch, Poset, batch_build, mobius, mobius_adjoint, poset_build, poset_build_many, poset_load,
+                    zeta, zeta_adjoint, zeta_adjoint_batched, zeta_batched, zeta_noalloc)
 
 __all__ = [
-    "Poset", "Batch", "PosetxError", "poset_build", "poset_load", "batch_build", "zeta", "zeta_adjoint", "mobius",
-    "mobius_adjoint", "zeta_batched", "zeta_adjoint_batched", "zeta_noalloc", "lib",
+    "Poset", "Batch", "PosetxError", "poset_build", "poset_build_many", "poset_load", "batch_build", "zeta",
+    "zeta_adjoint", "mobius", "mobius_adjoint", "zeta_batched", "zeta_adjoint_batched", "zeta_noalloc", "lib",
     "PX_I64", "PX_F32", "PX_F64", "PX_BUILD_HOST_ONLY", "PX_BUILD_NO_ADJOINT", "PX_BUILD_LEVELS_MIRSKY",
     "PX_BUILD_SPARSE_NIV", "PX_BUILD_MIN_CHAINS",
 ]

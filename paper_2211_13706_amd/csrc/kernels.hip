@@ -17,6 +17,7 @@
 // lanes of a wavefront read contiguous bytes of a row; B is padded to cw.
 // Everything here is a scan or an integer-indexed gather: VALU + HBM work, no
 // MFMA.
+#include <atomic>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -3209,18 +3210,19 @@ namespace {
 // Workgroups of k_usolve_flow<TY, CW> the device holds resident at once.
 template <int CW, int WAIT>
 int flow_resident() {
-  static int cached[64] = {0};  // per device
+  static std::atomic<int> cached[64];  // per device; builds may run on several threads
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-  if (cached[dev] > 0) return cached[dev];
+  if (int c = cached[dev].load(std::memory_order_relaxed); c > 0) return c;
   int per_cu = 0, cus = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_usolve_flow<int64_t, CW, WAIT>, WG, 0) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
     (void)hipGetLastError();
     return 0;
   }
-  cached[dev] = std::max(1, per_cu) * std::max(1, cus);
-  return cached[dev];
+  const int r = std::max(1, per_cu) * std::max(1, cus);
+  cached[dev].store(r, std::memory_order_relaxed);
+  return r;
 }
 
 template <int CW, int WAIT>

@@ -199,6 +199,26 @@ def poset_build(n, indptr, indices, chain_of=None, chain_pos=None, flags: int = 
     return Poset(h, n, device)
 
 
+def poset_build_many(specs, flags: int = 0, device: int = 0, threads: int = 0):
+    """Many posets preprocessed at once, e.g. for a batch: specs is a sequence of
+    (n, indptr, indices, chain_of, chain_pos) tuples (chains may be None).  The builds run
+    on up to `threads` host threads (0: min(16, CPUs)); px_poset_build calls are
+    independent, so concurrent builds give the same handles as one after another."""
+    from concurrent.futures import ThreadPoolExecutor
+    specs = list(specs)
+    nt = threads if threads > 0 else min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                                           else (os.cpu_count() or 1))
+    nt = max(1, min(nt, len(specs)))
+
+    def one(sp):
+        n, ip, ix, co, cp = sp
+        return poset_build(n, ip, ix, co, cp, flags=flags, device=device)
+    if nt == 1:
+        return [one(sp) for sp in specs]
+    with ThreadPoolExecutor(max_workers=nt) as ex:
+        return list(ex.map(one, specs))
+
+
 def poset_load(path, flags: int = 0, device: int = 0) -> Poset:
     """A handle from a file written by Poset.save, without preprocessing again (px_poset_load)."""
     h = ctypes.c_void_p()

@@ -806,6 +806,26 @@ def test_batched_row_layout(px, B):
         assert torch.equal(px.zeta_batched(b, f), g)
 
 
+def test_batch_from_concurrent_builds(px):
+    """Device handles built on several host threads at once (poset_build_many) form a batch
+    whose zeta and adjoint equal those of a batch built one poset after another, bit for
+    bit (int64), and the closure oracle."""
+    import torch
+    posets = W.batched_posets(16, seed=98, nmin=200, nmax=4000)
+    specs = [(q.n, q.indptr, q.indices, None if i % 3 == 0 else q.chain_of, None if i % 3 == 0 else q.chain_pos)
+             for i, q in enumerate(posets)]
+    many = px.batch_build(px.poset_build_many(specs, device=0, threads=8))
+    one = px.batch_build([px.poset_build(*s, device=0) for s in specs])
+    f = T(W.functions(one.rows, 8, "int", seed=99, lo=-1000, hi=1000))
+    g, a = px.zeta_batched(many, f), px.zeta_adjoint_batched(many, f)
+    assert torch.equal(g, px.zeta_batched(one, f)) and torch.equal(a, px.zeta_adjoint_batched(one, f))
+    fh, gh = f.cpu().numpy(), g.cpu().numpy()
+    for i, q in enumerate(posets[:4]):
+        lo, hi = int(one.offsets[i]), int(one.offsets[i + 1])
+        R = O.reachability(q.n, q.indptr, q.indices)
+        assert np.array_equal(gh[lo:hi], O.zeta(R, fh[lo:hi]))
+
+
 @pytest.mark.parametrize("B", [2, 4, 8, 12, 16, 24, 32, 64])
 def test_vector_lane_walk(px, B, monkeypatch):
     """The vector-lane walk (each lane gathers 16 bytes of a row: 4 float32 or 2 int64 /

@@ -342,3 +342,20 @@ def test_load_recounts_sizes(px, tmp_path):
     Bq = px.poset_load(path, flags=px.PX_BUILD_HOST_ONLY)
     assert Bq.info_dict()["nnz_niv"] == A.info_dict()["nnz_niv"]
     assert Bq.info_dict()["nnz_niv_up"] == A.info_dict()["nnz_niv_up"]
+
+
+def test_concurrent_builds_match_serial(px):
+    """px_poset_build calls on several threads at once (poset_build_many) give the same
+    chains, niv maps and level schedules as one build after another."""
+    posets = W.batched_posets(24, seed=61, nmin=200, nmax=3000)
+    specs = [(q.n, q.indptr, q.indices, None if i % 2 else q.chain_of, None if i % 2 else q.chain_pos)
+             for i, q in enumerate(posets)]
+    many = px.poset_build_many(specs, flags=px.PX_BUILD_HOST_ONLY, threads=6)
+    for (n, ip, ix, co, cp), P in zip(specs, many):
+        S = px.poset_build(n, ip, ix, co, cp, flags=px.PX_BUILD_HOST_ONLY)
+        assert P.k == S.k
+        for a, b in zip(P.chains(), S.chains()):
+            assert np.array_equal(a, b)
+        for up in (False, True):
+            assert np.array_equal(P.niv(up), S.niv(up))
+            assert np.array_equal(P.levels(up), S.levels(up))
