@@ -1021,7 +1021,8 @@ hipError_t solve_levels(const px_poset* p, bool up, px::ElemType tin, const void
       // took 3.3 ms against 4.4 ms on the rows read; with narrower tiles the rows win: 3.0 against
       // 3.4 ms there at 32 columns, 9.1 against 12.0 ms at n = 2^23, k = 32, B = 16 (the row groups
       // of a narrow tile proceed as soon as their own rows are ready)
-      int wait = px::flow_col_width(B) == 64 ? px::kWaitDeps : px::kWaitRows;
+      int wait = px::flow_col_width(B) == 64 ? px::kWaitDeps : px::kWaitValues;
+      if (wv && std::strcmp(wv, "values") == 0) wait = px::kWaitValues;
       if (wv && std::strcmp(wv, "rows") == 0) wait = px::kWaitRows;
       if (wv && std::strcmp(wv, "level") == 0) wait = px::kWaitLevel;
       if (wv && std::strcmp(wv, "deps") == 0) wait = px::kWaitDeps;

@@ -206,12 +206,16 @@ hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_ro
 // wait: what a chunk waits for before it reads Y:
 //   kWaitRows   a ready flag of every row it reads;
 //   kWaitLevel  every chunk of the level below (one done flag per chunk);
-//   kWaitDeps   every chunk it reads from (one done flag per chunk).
-// sync: 1 + ceil(B / col_width(B)) * (n + 1) ints of scratch (chunk flags:
-// nchunks instead of n + 1), cleared by the launch.  spin_limit bounds each
-// wait (polls); a wait that gives up makes the fallback recompute the solve in
-// one workgroup.  max_grid > 0 caps the workgroups.  B >= 5.
-constexpr int kWaitRows = 0, kWaitLevel = 1, kWaitDeps = 2;
+//   kWaitDeps   every chunk it reads from (one done flag per chunk);
+//   kWaitValues nothing: it reads the rows' values themselves until none is
+//               the unwritten mark (rows 0 .. n-1 of Y are filled with it
+//               first), a value equal to the mark being taken once the
+//               row's ready flag is set.
+// sync: 1 + ceil(B / flow_col_width(B)) * (n + 1) ints of scratch (chunk
+// flags: nchunks instead of n + 1), cleared by the launch.  spin_limit bounds
+// each wait (polls); a wait that gives up makes the fallback recompute the
+// solve in one workgroup.  max_grid > 0 caps the workgroups.  B >= 5.
+constexpr int kWaitRows = 0, kWaitLevel = 1, kWaitDeps = 2, kWaitValues = 3;
 hipError_t launch_usolve_flow(const DevPoset& d, bool up, const int4* chunks, int64_t nchunks, const int32_t* lev_off,
                               const int32_t* dep_ptr, const int32_t* deps, int wait, const void* g, int64_t ldg, void* Y,
                               int64_t B, int* sync, int spin_limit, int max_grid, hipStream_t s);

@@ -1240,6 +1240,18 @@ __global__ void k_fill_i32(int* p, int64_t cnt, int v) {
   if (i < cnt) p[i] = v;
 }
 
+// cnt 64-bit words set to v, two per thread (16-byte stores when p is 16-byte
+// aligned).
+__global__ void k_fill_i64x2(int64_t* __restrict__ p, int64_t cnt, int64_t v) {
+  const int64_t i = ((int64_t)blockIdx.x * WG + threadIdx.x) * 2;
+  if (i + 1 < cnt && (uintptr_t)p % 16 == 0) {
+    reinterpret_cast<longlong2*>(p + i)[0] = make_longlong2(v, v);
+  } else {
+    if (i < cnt) p[i] = v;
+    if (i + 1 < cnt) p[i + 1] = v;
+  }
+}
+
 // ------------------------------------------------------------ gather-reduce
 
 __device__ inline double fmax_(double a, double b) { return a > b ? a : b; }
@@ -2266,6 +2278,94 @@ __device__ inline bool await_rows(const int* __restrict__ fl, const int32_t (&ro
   return await_idx<M>(fl, mine, err, spin_limit);
 }
 
+// The ready flags of the rows of Q lists of N rows each at once (all polls of
+// one round in flight together rather than one list after another).
+template <int CW, int N, int Q>
+__device__ inline bool await_rows_n(const int* __restrict__ fl, const int32_t* const (&lists)[Q], int lane,
+                                    const int* __restrict__ err, int spin_limit) {
+  constexpr int M = (N + CW - 1) / CW;
+  int mine[Q * M];
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      int r = -1;
+#pragma unroll
+      for (int u = 0; u < N; ++u)
+        if (u == lane + m * CW) r = lists[q][u];
+      mine[q * M + m] = r;
+    }
+  return await_idx<Q * M>(fl, mine, err, spin_limit);
+}
+
+// Rows of Y not yet written by the persistent solve hold this mark.
+constexpr int64_t kUnwritten = INT64_MIN;
+
+// Reads the values of the lane's column in Q lists of N rows of Y (-1 = the
+// zero row zr) into vals, polling until none is kUnwritten.  Each round reads
+// every value again (a written value never changes, so settled entries just
+// read the same word; the loads of a round are all in flight together).  A
+// row's value can equal the mark legitimately: every fourth round the ready
+// flags of the rows still pending are read, and the round after a flag read as
+// set (issued once that flag has arrived) takes the value as it is; the flag
+// is set only after the row's stores completed.  Exits are uniform over the
+// active lanes; false when the wait gives up.
+template <int N, int Q>
+__device__ inline bool await_vals(const int64_t* __restrict__ Y, int64_t B, int64_t colc, int zr,
+                                  const int32_t* const (&rows)[Q], int64_t* const (&vals)[Q],
+                                  const int* __restrict__ fl, const int* __restrict__ err, int spin_limit) {
+  uint32_t pend[Q], seen[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    pend[q] = 0;
+    seen[q] = 0;
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+      if (rows[q][u] >= 0) pend[q] |= 1u << u;
+  }
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  for (int spin = 0;; ++spin) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int u = 0; u < N; ++u) {
+        int r = rows[q][u] >= 0 ? rows[q][u] : zr;
+        asm volatile("" : "+v"(r));  // addresses formed in each round, not held across rounds
+        vals[q][u] = ld_dev(&Y[(int64_t)r * B + colc]);
+      }
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+#pragma unroll
+      for (int u = 0; u < N; ++u)
+        if (((seen[q] >> u) & 1) || vals[q][u] != kUnwritten) pend[q] &= ~(1u << u);
+      any = any || pend[q] != 0;
+    }
+    if (!__any(any)) return true;
+    if (spin >= spin_limit) return false;
+    if ((spin & 15) == 15) {
+      if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0)
+        return false;
+      if (__builtin_amdgcn_s_memrealtime() - t0 > kFlowWaitTicks) return false;
+    }
+    if ((spin & 3) == 3) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        int f[N];
+#pragma unroll
+        for (int u = 0; u < N; ++u)
+          f[u] = __hip_atomic_load(fl + (((pend[q] >> u) & 1) ? rows[q][u] : zr), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        wait_vmem();  // the flags have arrived before the next round's reads are issued
+#pragma unroll
+        for (int u = 0; u < N; ++u)
+          if (((pend[q] >> u) & 1) && f[u] != 0) seen[q] |= 1u << u;
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
 // One wavefront (all lanes active): the flags fl[a .. b), 512 at a time.
 __device__ inline bool await_range(const int* __restrict__ fl, int a, int b, const int* __restrict__ err,
                                    int spin_limit) {
@@ -2316,7 +2416,11 @@ __global__ __launch_bounds__(WG) void k_usolve_flow(DevPoset d, const int32_t* _
   using W = typename Wide<TY>::W;
   constexpr int RG = WG / CW;
   constexpr int SR = kSegRows / RG;
-  constexpr bool LEVEL = WAIT != kWaitRows;  // chunk done flags (level or dependency waits)
+  constexpr bool LEVEL = WAIT == kWaitLevel || WAIT == kWaitDeps;  // chunk done flags
+  constexpr bool VALS = WAIT == kWaitValues;  // polls the values (no flag waits before the reads)
+  // entries and events per row group and batch: 16; polling the values, 64 per
+  // workgroup (fewer registers in flight, so that two workgroups fit per CU)
+  constexpr int NB = !VALS ? 16 : 64 / RG < 2 ? 2 : 64 / RG > 16 ? 16 : 64 / RG;
   static_assert(SR >= 1 && SR * RG == kSegRows, "kSegRows must be a multiple of the row groups");
   __shared__ W s_d[kSegRows][CW];
   __shared__ W s_t[RG][CW];
@@ -2352,16 +2456,16 @@ __global__ __launch_bounds__(WG) void k_usolve_flow(DevPoset d, const int32_t* _
     // and -1 skipped) and of the events (e0 + rg, e0 + rg + RG, ...), loaded
     // before the wait like g
     const int32_t* __restrict__ nr0 = nv + (int64_t)r0 * k;
-    int32_t t[16], a[16], b[16], rr[16];
+    int32_t t[NB], a[NB], b[NB], rr[NB];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < NB; ++u) {
       const int j = rg + u * RG;
       const int tt = j < k ? uni(nr0[j]) : -1;
       t[u] = tt != r0 ? tt : -1;
     }
     auto load_events = [&](int eb) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < NB; ++u) {
         const int e = eb + u * RG;
         const int4 q = e < e1 ? ev[e] : make_int4(zr, zr, r0, 0);
         a[u] = uni(q.x) != zr ? uni(q.x) : -1;
@@ -2400,54 +2504,80 @@ __global__ __launch_bounds__(WG) void k_usolve_flow(DevPoset d, const int32_t* _
         if (threadIdx.x == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
-    } else {
-      ok = await_rows<CW, 16>(fl, t, lane, err, spin_limit) && await_rows<CW, 16>(fl, a, lane, err, spin_limit) &&
-           await_rows<CW, 16>(fl, b, lane, err, spin_limit);
+    } else if (!VALS) {
+      const int32_t* const lists[3] = {t, a, b};
+      ok = await_rows_n<CW, NB, 3>(fl, lists, lane, err, spin_limit);
     }
     W part = W(0);
     if (ok) {  // the first batches' rows of Y, all in flight together
-      TY v[16], vn[16], vo[16];
+      TY v[NB], vn[NB], vo[NB];
+      if (VALS) {
+        const int32_t* const lists[3] = {t, a, b};
+        int64_t* const outs[3] = {v, vn, vo};
+        ok = await_vals<NB, 3>(Y, B, colc, zr, lists, outs, fl, err, spin_limit);
+      } else {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        v[u] = ld_dev(&Y[(int64_t)(t[u] >= 0 ? t[u] : zr) * B + colc]);
-        vn[u] = ld_dev(&Y[(int64_t)(a[u] >= 0 ? a[u] : zr) * B + colc]);
-        vo[u] = ld_dev(&Y[(int64_t)(b[u] >= 0 ? b[u] : zr) * B + colc]);
+        for (int u = 0; u < NB; ++u) {
+          v[u] = ld_dev(&Y[(int64_t)(t[u] >= 0 ? t[u] : zr) * B + colc]);
+          vn[u] = ld_dev(&Y[(int64_t)(a[u] >= 0 ? a[u] : zr) * B + colc]);
+          vo[u] = ld_dev(&Y[(int64_t)(b[u] >= 0 ? b[u] : zr) * B + colc]);
+        }
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u) part += (W)v[u];
+      for (int u = 0; u < NB; ++u) part += (W)v[u];
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
+      for (int u = 0; u < NB; ++u)
         if (e0 + rg + u * RG < e1) atomicAdd(&s_d[rr[u] - r0][lane], (W)vn[u] - (W)vo[u]);
     }
-    // later batches (k > 16 * RG, or more than 16 events per row group)
-    for (int jb = rg + 16 * RG; jb < k && ok; jb += RG * 16) {
+    // later batches (k > NB * RG, or more than NB events per row group)
+    for (int jb = rg + NB * RG; jb < k && ok; jb += RG * NB) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < NB; ++u) {
         const int j = jb + u * RG;
         const int tt = j < k ? uni(nr0[j]) : -1;
         t[u] = tt != r0 ? tt : -1;
       }
-      if (!LEVEL) ok = await_rows<CW, 16>(fl, t, lane, err, spin_limit);
+      if (!LEVEL && !VALS) ok = await_rows<CW, NB>(fl, t, lane, err, spin_limit);
       if (!ok) break;
-      TY v[16];
+      TY v[NB];
+      if (VALS) {
+        const int32_t* const lists[1] = {t};
+        int64_t* const outs[1] = {v};
+        if (!await_vals<NB, 1>(Y, B, colc, zr, lists, outs, fl, err, spin_limit)) {
+          ok = false;
+          break;
+        }
+      } else {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) v[u] = ld_dev(&Y[(int64_t)(t[u] >= 0 ? t[u] : zr) * B + colc]);
-#pragma unroll
-      for (int u = 0; u < 16; ++u) part += (W)v[u];
-    }
-    for (int eb = e0 + rg + 16 * RG; eb < e1 && ok; eb += RG * 16) {
-      load_events(eb);
-      if (!LEVEL)
-        ok = await_rows<CW, 16>(fl, a, lane, err, spin_limit) && await_rows<CW, 16>(fl, b, lane, err, spin_limit);
-      if (!ok) break;
-      TY vn[16], vo[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        vn[u] = ld_dev(&Y[(int64_t)(a[u] >= 0 ? a[u] : zr) * B + colc]);
-        vo[u] = ld_dev(&Y[(int64_t)(b[u] >= 0 ? b[u] : zr) * B + colc]);
+        for (int u = 0; u < NB; ++u) v[u] = ld_dev(&Y[(int64_t)(t[u] >= 0 ? t[u] : zr) * B + colc]);
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
+      for (int u = 0; u < NB; ++u) part += (W)v[u];
+    }
+    for (int eb = e0 + rg + NB * RG; eb < e1 && ok; eb += RG * NB) {
+      load_events(eb);
+      if (!LEVEL && !VALS) {
+        const int32_t* const lists[2] = {a, b};
+        ok = await_rows_n<CW, NB, 2>(fl, lists, lane, err, spin_limit);
+      }
+      if (!ok) break;
+      TY vn[NB], vo[NB];
+      if (VALS) {
+        const int32_t* const lists[2] = {a, b};
+        int64_t* const outs[2] = {vn, vo};
+        if (!await_vals<NB, 2>(Y, B, colc, zr, lists, outs, fl, err, spin_limit)) {
+          ok = false;
+          break;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+          vn[u] = ld_dev(&Y[(int64_t)(a[u] >= 0 ? a[u] : zr) * B + colc]);
+          vo[u] = ld_dev(&Y[(int64_t)(b[u] >= 0 ? b[u] : zr) * B + colc]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
         if (eb + u * RG < e1) atomicAdd(&s_d[rr[u] - r0][lane], (W)vn[u] - (W)vo[u]);
     }
     if (ok)
@@ -3250,9 +3380,12 @@ hipError_t flow_wait(int wait, const DevPoset& d, const int32_t* nv, const int4*
     case kWaitLevel:
       return flow_typed<CW, kWaitLevel>(d, nv, chunks, nchunks, lev_off, dep_ptr, deps, ev, g, ldg, Y, B, flags, err,
                                         spin_limit, total, max_grid, s);
-    default:
+    case kWaitDeps:
       return flow_typed<CW, kWaitDeps>(d, nv, chunks, nchunks, lev_off, dep_ptr, deps, ev, g, ldg, Y, B, flags, err,
                                        spin_limit, total, max_grid, s);
+    default:
+      return flow_typed<CW, kWaitValues>(d, nv, chunks, nchunks, lev_off, dep_ptr, deps, ev, g, ldg, Y, B, flags, err,
+                                         spin_limit, total, max_grid, s);
   }
 }
 }  // namespace
@@ -3266,12 +3399,18 @@ hipError_t launch_usolve_flow(const DevPoset& d, bool up, const int4* chunks, in
   const int cw = flow_col_width(B);
   const int64_t ncb = (B + cw - 1) / cw;
   if (!nv || !t.ev || !lev_off || (wait == kWaitDeps && (!dep_ptr || !deps)) || nchunks * ncb >= INT32_MAX ||
-      (int64_t)d.n + 1 >= INT32_MAX || cw < 8 || wait < kWaitRows || wait > kWaitDeps)
+      (int64_t)d.n + 1 >= INT32_MAX || cw < 8 || wait < kWaitRows || wait > kWaitValues)
     return hipErrorInvalidValue;
   int* err = sync;
   int* flags = sync + 1;
-  const int64_t nsync = 1 + ncb * (wait != kWaitRows ? nchunks : (int64_t)d.n + 1);
+  const bool chunk_flags = wait == kWaitLevel || wait == kWaitDeps;
+  const int64_t nsync = 1 + ncb * (chunk_flags ? nchunks : (int64_t)d.n + 1);
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nsync + WG - 1) / WG)), dim3(WG), 0, s, sync, nsync, 0);
+  if (wait == kWaitValues) {  // rows 0 .. n-1 of Y unwritten (row n, the zero row, stays 0)
+    const int64_t words = (int64_t)d.n * B;
+    hipLaunchKernelGGL(k_fill_i64x2, dim3((unsigned)((words + 2 * WG - 1) / (2 * WG))), dim3(WG), 0, s, (int64_t*)Y,
+                       words, kUnwritten);
+  }
   const int nc = (int)nchunks;
   const int64_t* gi = (const int64_t*)g;
   int64_t* Yi = (int64_t*)Y;

@@ -436,7 +436,38 @@ def test_int64_solve_by_runs_matches_oracle_and_direct(px, B, mirsky, monkeypatc
         assert np.array_equal(runs[0], other[0]) and np.array_equal(runs[1], other[1]), mode
 
 
-@pytest.mark.parametrize("wait", ["deps", "level", "rows"])
+@pytest.mark.parametrize("wait", ["values", "rows"])
+@pytest.mark.parametrize("B", [8, 40])
+def test_int64_solve_values_equal_to_unwritten_mark(px, B, wait, monkeypatch):
+    """The persistent int64 solve polling the values marks unwritten rows with the
+    int64 minimum; rows whose solution is that very value (columns 0 and 1: chain
+    prefix sums of f pinned to it, downward and upward) are taken once their ready
+    flags are set.  Zeta against the closure oracle (wrapping int64), and both
+    Möbius round trips exact."""
+    p = W.chain_poset(3000, 8, 3, seed=88)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = build(px, p)
+    assert P.info["run_chunks"] > 0
+    lo = np.iinfo(np.int64).min
+    f = W.functions(p.n, B, "int", seed=89, lo=-1000, hi=1000)
+    f[:, :2] = 0
+    ends = np.zeros(int(p.chain_of.max()) + 1, dtype=np.int64)
+    np.maximum.at(ends, p.chain_of, p.chain_pos)
+    f[p.chain_pos == 0, 0] = lo                   # prefixes from the bottom: every row of a chain
+    f[p.chain_pos == ends[p.chain_of], 1] = lo    # suffixes from the top
+    f[::7, 1] += 1                                # some rows off the mark
+    monkeypatch.setenv("POSETX_FLOW_WAIT", wait)
+    with np.errstate(over="ignore"):
+        gz, ga = O.zeta(R, f), O.zeta_adjoint(R, f)
+    g = px.zeta(P, T(f))
+    assert np.array_equal(H(g), gz)
+    a = px.zeta_adjoint(P, T(f))
+    assert np.array_equal(H(a), ga)
+    assert np.array_equal(H(px.mobius(P, g)), f)
+    assert np.array_equal(H(px.mobius_adjoint(P, a)), f)
+
+
+@pytest.mark.parametrize("wait", ["deps", "level", "rows", "values"])
 @pytest.mark.parametrize("B", [8, 64])
 def test_int64_persistent_solve_fallback(px, B, wait, monkeypatch):
     """With a spin limit of 0 polls every wait of the persistent solve gives up at
