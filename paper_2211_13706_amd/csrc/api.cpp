@@ -1017,16 +1017,19 @@ hipError_t solve_levels(const px_poset* p, bool up, px::ElemType tin, const void
       prof::Scope sc(prof::USOLVE, s);
       const char* wv = std::getenv("POSETX_FLOW_WAIT");
       const char* gv = std::getenv("POSETX_FLOW_GRID");
-      // measured: with 64-column tiles (n = 2^20, k = 64, B = 64) waiting on the chunks read from
-      // took 3.3 ms against 4.4 ms on the rows read; with narrower tiles the rows win: 3.0 against
-      // 3.4 ms there at 32 columns, 9.1 against 12.0 ms at n = 2^23, k = 32, B = 16 (the row groups
-      // of a narrow tile proceed as soon as their own rows are ready)
+      // measured (n = 2^20, k = 64, B = 64): 64-column items waiting on the chunks read from
+      // 3.3 ms, against 4.4 ms waiting on the rows read; with narrower items the row waits win
+      // (32 columns: 3.0 against 3.4 ms; n = 2^23, k = 32, B = 16: 9.1 against 12.0 ms), and
+      // polling the values read instead of flags is faster still (32 columns: 2.46 ms; 16: 2.04;
+      // n = 2^23: 5.7 ms): no store acknowledgement, flag store and flag poll per level
       int wait = px::flow_col_width(B) == 64 ? px::kWaitDeps : px::kWaitValues;
       if (wv && std::strcmp(wv, "values") == 0) wait = px::kWaitValues;
       if (wv && std::strcmp(wv, "rows") == 0) wait = px::kWaitRows;
       if (wv && std::strcmp(wv, "level") == 0) wait = px::kWaitLevel;
       if (wv && std::strcmp(wv, "deps") == 0) wait = px::kWaitDeps;
-      // 512 workgroups (two per compute unit) poll less than the full resident count: 3.3 against 3.5 ms
+      // 512 workgroups (two per compute unit) poll less than the full resident count; polling the
+      // values in 16-column items, 512 to 768 are equally fast (2.02-2.04 ms) and 1024 slower
+      // (2.22 ms; at n = 2^23, 8.7 against 5.7 ms)
       return px::launch_usolve_flow(p->dp, up, p->d_run_chunks[m], cp.back(), p->d_run_levn[m], p->d_run_dep_ptr[m],
                                     p->d_run_deps[m], wait, g, ldg, Y, B, (int*)flow, flow_spin_limit(),
                                     gv ? std::atoi(gv) : 512, s);

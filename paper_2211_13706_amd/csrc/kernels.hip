@@ -44,12 +44,13 @@ int seg_index(int cw) {
 }
 int seg_rows(int cw) { return (WG / cw) * RPT; }
 
-// 32 columns at most: at n = 2^20, k = 64, B = 64 two 32-column halves of each
-// chunk, each waiting on the rows it reads, took 3.0 ms against 3.3 ms for one
-// 64-column workgroup waiting on the chunks it reads (16 columns: 3.3 ms, 8:
-// 5.2 ms); a chunk's half moves half the bytes between its wait and its flag.
+// 16 columns at most.  Polling the values it reads (n = 2^20, k = 64, B = 64,
+// 512 workgroups) the solve took 2.04 ms in 16-column items against 2.46 ms in
+// 32-column ones (8: 2.54 ms; at n = 2^23, k = 32, B = 16, 16 columns 5.70 ms,
+// 8 columns 5.64): a narrow item moves fewer bytes between its reads and its
+// stores, and more items of a level run at once.
 int flow_col_width(int64_t B) {
-  const int cw = std::min(col_width(B), 32);
+  const int cw = std::min(col_width(B), 16);
   const char* e = std::getenv("POSETX_FLOW_CW");
   if (e && *e) {
     const int v = std::atoi(e);
