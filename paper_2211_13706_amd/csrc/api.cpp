@@ -622,6 +622,8 @@ struct px_poset {
   std::vector<int64_t> run_cptr[2];  // per level: offsets into d_run_chunks
   int64_t run_events[2] = {0, 0};
   int32_t* d_run_levn[2] = {nullptr, nullptr};  // per level: its first chunk (levels + 1 entries)
+  // per level: its first position in d_lev_down / d_lev_up (levels + 1 entries; dense rows)
+  int32_t* d_lev_ptr[2] = {nullptr, nullptr};
   int32_t* d_run_dep_ptr[2] = {nullptr, nullptr};  // per chunk: the chunks it reads from
   int32_t* d_run_deps[2] = {nullptr, nullptr};
   int64_t* d_nivp[2] = {nullptr, nullptr};
@@ -682,7 +684,7 @@ void free_poset_device(px_poset* p) {
   int32_t* bufs[] = {p->d_node_of_row, p->d_chain_of_row, p->d_chain_off, p->d_niv, p->d_niv_up,
                      p->d_lev_down,     p->d_lev_up,       p->d_segoff,    p->d_order, p->d_tiles,
                      p->d_lev_niv[0],   p->d_lev_niv[1],   p->d_lev_node[0], p->d_lev_node[1], p->d_iota,
-                     p->d_nivr[0],      p->d_nivr[1]};
+                     p->d_nivr[0],      p->d_nivr[1],      p->d_lev_ptr[0], p->d_lev_ptr[1]};
   for (int32_t* b : bufs)
     if (b) (void)hipFree(b);
   for (int64_t* b : p->d_nivp)
@@ -943,15 +945,34 @@ int flow_spin_limit() {
   return v ? std::max(0, std::atoi(v)) : 1 << 20;
 }
 
-// Ints of the persistent solve's scratch for B columns (0 where it is not used):
-// the error word and a ready flag per row and column block.
+// Ints of the persistent solves' scratch for B columns (0 where neither is
+// used): the error word and a ready flag per row and column block.
 int64_t flow_ints(const px_poset* p, int64_t B) {
-  if (!p->d_run_chunks[0]) return 0;
+  const int64_t poll = p->d_lev_ptr[0] ? px::usolve_poll_ints(p->prep.n, B) : 0;
+  if (!p->d_run_chunks[0]) return poll;
   const int cw = px::flow_col_width(B);
   const int64_t ncb = (B + cw - 1) / cw;
   const int64_t nch = std::max(p->run_cptr[0].empty() ? 0 : p->run_cptr[0].back(),
                                p->run_cptr[1].empty() ? 0 : p->run_cptr[1].back());
-  return 1 + ncb * std::max<int64_t>(p->prep.n + 1, nch);
+  return std::max(poll, 1 + ncb * std::max<int64_t>(p->prep.n + 1, nch));
+}
+
+// Row-by-row level solves (floating point, and int64 without runs) run every
+// level in one persistent launch polling the values they read
+// (px::launch_usolve_poll) where the rows are dense, there are at least two
+// levels and the average level fits the resident wavefronts at one row (and
+// 64-column block) each: n = 2^20, k = 64, 568 levels of 1,846 rows, float64
+// B = 64: 3.9 ms against 5.4 ms with a launch per level; the 4096 x 64 grid,
+// 64 levels of 4,096 rows: 0.83 against 0.46 ms (int64, B = 16), since each
+// wavefront then takes two rows a level, one after the other.
+// POSETX_LEVEL_POLL (read on every call): 0 launches one kernel per level,
+// 2 takes the persistent launch whatever the level widths; POSETX_POLL_GRID
+// caps its workgroups.
+int level_poll_mode() {
+  const char* v = std::getenv("POSETX_LEVEL_POLL");
+  if (v && v[0] == '0') return 0;
+  if (v && v[0] == '2') return 2;
+  return 1;
 }
 
 // Narrow blocks (B <= 32).  With 8 to 32 columns per block, zeta values and
@@ -983,8 +1004,9 @@ int64_t ws_tiles(const px_poset* p, int64_t B) {
   return std::max(p->ntiles[px::seg_index(px::col_width(B))], p->nslots[0] >= 0 ? compact_tiles(p) : (int64_t)0);
 }
 
-// Level-scheduled solve U y' = g (Alg. 4, first loop; Alg. 5 schedule), one
-// launch per level so that every level sees the previous one complete.
+// Level-scheduled solve U y' = g (Alg. 4, first loop; Alg. 5 schedule): each
+// level sees the levels below it complete, by one launch per level or by the
+// waits of a persistent launch.
 hipError_t solve_levels(const px_poset* p, bool up, px::ElemType tin, const void* g, int64_t ldg, px::ElemType ty,
                         void* Y, int64_t B, void* part, void* flow, hipStream_t s) {
   const std::vector<int32_t>& ptr = up ? p->prep.lev_up_ptr : p->prep.lev_down_ptr;
@@ -1040,6 +1062,15 @@ hipError_t solve_levels(const px_poset* p, bool up, px::ElemType tin, const void
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
+  }
+  const int poll = level_poll_mode();
+  const int64_t nlev = (int64_t)ptr.size() - 1;
+  if (flow && p->d_lev_ptr[m] && nlev >= 2 && poll > 0 &&
+      (poll == 2 || (int64_t)ptr.back() * ((B + 63) / 64) <= nlev * px::usolve_poll_waves(tin, ty, p->prep.n, B))) {
+    prof::Scope sc(prof::USOLVE, s);
+    const char* gv = std::getenv("POSETX_POLL_GRID");
+    return px::launch_usolve_poll(p->dp, up, rows, p->d_lev_ptr[m], (int)ptr.size() - 1, ptr.back(), tin, g, ldg, ty,
+                                  Y, B, (int*)flow, flow_spin_limit(), gv ? std::atoi(gv) : 0, s);
   }
   for (size_t l = 0; l + 1 < ptr.size(); ++l) {
     prof::Scope sc(prof::USOLVE, s);
@@ -1153,7 +1184,7 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   const int cw = px::col_width(B);
   const int64_t nt = p->ntiles[px::seg_index(cw)];
   Layout L = layout(n, B, dtype, refine, ws_tiles(p, B), std::max(p->nsnap[0], p->nsnap[1]), max_slots(p),
-                    max_parts(p), dtype == PX_I64 ? flow_ints(p, B) : 0);
+                    max_parts(p), flow_ints(p, B));
   if ((st = p->ws.ensure(L.total)) != PX_OK) return st;
   char* w = (char*)p->ws.p;
   hipStream_t s = (hipStream_t)stream;
@@ -1220,7 +1251,7 @@ px_status mobius_impl(px_poset* p, bool up, int dtype, const void* g, int64_t ld
   while (it < max_refine) {
     const bool last_check = check_end && it + 1 == max_refine;
     e = residual();
-    if (e == hipSuccess) e = solve_levels(p, up, px::E_F64, r64, B, px::E_F32, w + L.y, B, w + L.part, nullptr, s);
+    if (e == hipSuccess) e = solve_levels(p, up, px::E_F64, r64, B, px::E_F32, w + L.y, B, w + L.part, w + L.flow, s);
     if (e == hipSuccess)
       e = run_chain_diff(p->dp, dir, px::E_F32, w + L.y, B, px::E_F32, f, ldf, true,
                          check_steps || last_check ? dstats : nullptr, s);
@@ -1485,6 +1516,9 @@ static px_status finish_poset(px_poset* p, int device, px_poset** out) {
     }
     if (e == hipSuccess) e = upload(&p->d_lev_down, P.lev_down_rows.data(), P.lev_down_rows.size(), b);
     if (e == hipSuccess && p->has_up) e = upload(&p->d_lev_up, P.lev_up_rows.data(), P.lev_up_rows.size(), b);
+    if (e == hipSuccess && !P.sparse) e = upload(&p->d_lev_ptr[0], P.lev_down_ptr.data(), P.lev_down_ptr.size(), b);
+    if (e == hipSuccess && !P.sparse && p->has_up)
+      e = upload(&p->d_lev_ptr[1], P.lev_up_ptr.data(), P.lev_up_ptr.size(), b);
     // level-ordered niv rows and node ids for the uniform level solve, gathered
     // on the device from the maps and level orders already there
     for (int dir = 0; dir < 2 && e == hipSuccess && P.k <= 64 && !P.sparse; ++dir) {
@@ -1979,7 +2013,7 @@ px_status px_reserve(px_poset* p, int dtype, int64_t B) {
   DeviceGuard dg(p->device);
   return p->ws.ensure(
       layout(p->prep.n, B, dtype, dtype == PX_F32, ws_tiles(p, B), std::max(p->nsnap[0], p->nsnap[1]), max_slots(p),
-             max_parts(p), dtype == PX_I64 ? flow_ints(p, B) : 0).total);
+             max_parts(p), flow_ints(p, B)).total);
 }
 
 px_status px_zeta(px_poset* p, int dtype, const void* f, int64_t ldf, void* g, int64_t ldg, int64_t B, void* stream) {

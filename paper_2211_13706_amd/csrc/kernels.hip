@@ -18,6 +18,7 @@
 // Everything here is a scan or an integer-indexed gather: VALU + HBM work, no
 // MFMA.
 #include <atomic>
+#include <cstring>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -3428,6 +3429,313 @@ hipError_t launch_usolve_flow(const DevPoset& d, bool up, const int4* chunks, in
   hipLaunchKernelGGL((k_usolve_flow_fix<int64_t>), dim3(1), dim3(WG), 0, s, d, nv, chunks, nc, gi, ldg, Yi, B,
                      (const int*)err);
   return hipGetLastError();
+}
+
+// ------------------------------------------- row-by-row solve in one launch
+
+// Bit pattern of an unwritten value of Y in the value-polling row solve: the
+// int64 minimum, and signalling NaNs with a payload for float32 and float64
+// (arithmetic returns quiet NaNs).  A legitimate value equal to the mark is
+// handled through the row's ready flag.
+template <typename T> struct PollMark;
+template <> struct PollMark<int64_t> { using U = uint64_t; static constexpr U bits = 0x8000000000000000ull; };
+template <> struct PollMark<double> { using U = uint64_t; static constexpr U bits = 0x7FF4A5A5A5A5A5A5ull; };
+template <> struct PollMark<float> { using U = uint32_t; static constexpr U bits = 0x7FA5A5A5u; };
+
+template <typename T>
+__device__ inline typename PollMark<T>::U ld_bits(const T* p) {
+  using U = typename PollMark<T>::U;
+  return __hip_atomic_load(reinterpret_cast<const U*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ inline void st_bits(T* p, T v) {
+  using U = typename PollMark<T>::U;
+  U w;
+  __builtin_memcpy(&w, &v, sizeof(U));
+  __hip_atomic_store(reinterpret_cast<U*>(p), w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One wavefront, one row: lane j < KB holds entry j of a batch (-1: none or
+// the own chain).  Reads Y at those rows, column colc of each lane, into v,
+// until no value is the mark.  A round reads all KB entries (unconditional
+// loads, all in flight together; a written value never changes, so settled
+// entries just read the same word).  While some entry is still marked, the
+// wavefront polls only the lowest such entry (one load per poll, so waiting
+// wavefronts add little traffic) and reads all again once it has been
+// written.  With FLAGS (int64, whose results can equal the mark) every fourth
+// poll also reads that row's ready flag; once the flag reads as set, the next
+// round's read of it (issued after the flag arrived) is taken as it is.
+// Without FLAGS (floating point: arithmetic never yields the signalling-NaN
+// mark) a wait for such a value would end at the spin limit and the fallback.
+// Exits are wave-uniform; false when it gives up.
+template <typename TY, int KB, bool FLAGS, bool O32>
+__device__ inline bool poll_row(const TY* __restrict__ Y, int64_t B, int64_t colc, int zr, int cur, TY (&v)[KB],
+                                const int* __restrict__ fl, const int* __restrict__ err, int spin_limit) {
+  using U = typename PollMark<TY>::U;
+  // O32: Y spans less than 4 GiB, so each load is Y plus a 32-bit byte offset
+  auto at = [&](int t) -> const TY* {
+    if (O32)
+      return reinterpret_cast<const TY*>(reinterpret_cast<const char*>(Y) +
+                                         (uint32_t)(((uint32_t)t * (uint32_t)B + (uint32_t)colc) * sizeof(TY)));
+    return Y + (int64_t)t * B + colc;
+  };
+  U b[KB];
+  uint64_t seen = 0;
+  int spin = 0;
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  for (;;) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int t = __builtin_amdgcn_readlane(cur, j);
+      b[j] = ld_bits(at(t >= 0 ? t : zr));
+    }
+    uint64_t pend = 0;  // wave-uniform: entries still marked in some lane
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+      if (__any(b[j] == PollMark<TY>::bits) && !((seen >> j) & 1) && __builtin_amdgcn_readlane(cur, j) >= 0)
+        pend |= 1ull << j;
+    if (pend == 0) break;
+    const int js = __builtin_amdgcn_readfirstlane(__builtin_ctzll(pend));
+    const int ts = __builtin_amdgcn_readlane(cur, js);
+    for (int poll = 0;; ++poll, ++spin) {
+      if (spin >= spin_limit) return false;
+      if ((spin & 15) == 15) {
+        if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0)
+          return false;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > kFlowWaitTicks) return false;
+      }
+      __builtin_amdgcn_s_sleep(2);
+      if (FLAGS && (poll & 3) == 3) {
+        const int f = __hip_atomic_load(fl + ts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        wait_vmem();  // the flag has arrived before the next round's reads are issued
+        if (__builtin_amdgcn_readfirstlane(f) != 0) {
+          seen |= 1ull << js;
+          break;
+        }
+      }
+      if (!__any(ld_bits(at(ts)) == PollMark<TY>::bits)) break;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < KB; ++j) __builtin_memcpy(&v[j], &b[j], sizeof(U));
+  return true;
+}
+
+// The row-by-row level solve (k_usolve_uni's sums: g minus one entry at a time
+// in chain order, the own and missing entries reading the zero row n) for all
+// levels in one launch.  Each wavefront takes the items gw, gw + W, ... (gw its
+// index over the grid, W the wavefronts of the grid) of the level-ordered list
+// of (row, 64-column block) items; it reads the Y rows it needs by polling
+// their values (rows 0 .. n-1 of Y hold the mark until written), stores its
+// row's values and (int64) once they have completed sets the row's ready flag.  A row
+// reads only rows of lower levels, which come earlier in the list; a
+// wavefront takes its items in order, so with every wavefront resident the
+// unfinished item of lowest index has all it reads and every wait ends.  One
+// row per wavefront: a wavefront never holds a row and one of its readers.
+// Waits are bounded; a wavefront that gives up stores the error word and
+// stops, and k_usolve_poll_fix then solves again level by level.  Results
+// equal the per-level kernels' bit for bit.
+template <typename Tin, typename TY, bool O32>
+__global__ __launch_bounds__(WG) void k_usolve_poll(DevPoset d, const int32_t* __restrict__ nv,
+                                                    const int32_t* __restrict__ rows, const int32_t* __restrict__ lnv,
+                                                    const int32_t* __restrict__ lnode, int cnt,
+                                                    const Tin* __restrict__ g, int64_t ldg, TY* __restrict__ Y,
+                                                    int64_t B, int* __restrict__ flags, int* __restrict__ err,
+                                                    int spin_limit) {
+  using W = typename Wide<TY>::W;
+  constexpr bool FLAGS = std::is_same<TY, int64_t>::value;  // integer results can equal the mark
+  constexpr int KB = sizeof(TY) == 4 ? 64 : 32;               // entries per batch (registers in flight)
+  const int lane = threadIdx.x & 63;
+  const int ncb = (int)((B + 63) / 64);
+  const int64_t total = (int64_t)cnt * ncb;
+  const int64_t nw = (int64_t)gridDim.x * (WG / 64);
+  const int k = d.k, zr = d.n;
+  for (int64_t it = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6); it < total; it += nw) {
+    const int i = __builtin_amdgcn_readfirstlane((int)(it / ncb));
+    const int cb = __builtin_amdgcn_readfirstlane((int)(it - (int64_t)i * ncb));
+    int* const fl = flags + (int64_t)cb * (zr + 1);
+    const int64_t col = (int64_t)cb * 64 + lane;
+    const bool colok = col < B;
+    const int64_t colc = colok ? col : 0;
+    const int r = __builtin_amdgcn_readfirstlane(rows[i]);
+    const int node = __builtin_amdgcn_readfirstlane(lnode ? lnode[i] : d.node_of_row[r]);
+    const int32_t* __restrict__ nr = lnv ? lnv + (int64_t)i * k : nv + (int64_t)r * k;
+    W acc = (W)g[(int64_t)node * ldg + colc];
+    bool ok = true;
+    for (int j0 = 0; j0 < k; j0 += KB) {
+      int cur = lane < KB && j0 + lane < k ? nr[j0 + lane] : -1;
+      if (cur == r) cur = -1;
+      TY v[KB];
+      if (!poll_row<TY, KB, FLAGS, O32>(Y, B, colc, zr, cur, v, fl, err, spin_limit)) {
+        ok = false;
+        break;
+      }
+#pragma unroll
+      for (int j = 0; j < KB; ++j) acc -= (W)v[j];
+    }
+    if (!ok) {
+      if (lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    if (colok) st_bits(&Y[(int64_t)r * B + col], (TY)acc);
+    if (FLAGS) {
+      wait_vmem();
+      if (lane == 0) __hip_atomic_store(&fl[r], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// Fallback of k_usolve_poll: when its error word is set, one workgroup solves
+// again, level after level with a barrier in between, a row per wavefront with
+// the same sums; otherwise it returns at once.  Reads and writes are
+// device-scope, so nothing stale from the persistent launch is seen.
+template <typename Tin, typename TY>
+__global__ __launch_bounds__(WG) void k_usolve_poll_fix(DevPoset d, const int32_t* __restrict__ nv,
+                                                        const int32_t* __restrict__ rows,
+                                                        const int32_t* __restrict__ lev_ptr, int nlev,
+                                                        const Tin* __restrict__ g, int64_t ldg, TY* __restrict__ Y,
+                                                        int64_t B, const int* __restrict__ err) {
+  using W = typename Wide<TY>::W;
+  if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int k = d.k, zr = d.n;
+  for (int l = 0; l < nlev; ++l) {
+    const int a = lev_ptr[l], b = lev_ptr[l + 1];
+    for (int i = a + wv; i < b; i += WG / 64) {
+      const int r = __builtin_amdgcn_readfirstlane(rows[i]);
+      const int node = __builtin_amdgcn_readfirstlane(d.node_of_row[r]);
+      for (int64_t c0 = 0; c0 < B; c0 += 64) {
+        const int64_t col = c0 + lane;
+        const bool colok = col < B;
+        const int64_t colc = colok ? col : 0;
+        W acc = (W)g[(int64_t)node * ldg + colc];
+        for (int j0 = 0; j0 < k; j0 += 64) {  // 64 entries in flight at a time
+          int cur = j0 + lane < k ? nv[(int64_t)r * k + j0 + lane] : -1;
+          if (cur == r) cur = -1;
+          typename PollMark<TY>::U w[64];
+#pragma unroll
+          for (int j = 0; j < 64; ++j) {
+            const int t = __builtin_amdgcn_readlane(cur, j);
+            w[j] = ld_bits(Y + (int64_t)(t >= 0 ? t : zr) * B + colc);
+          }
+#pragma unroll
+          for (int j = 0; j < 64; ++j) {
+            TY v;
+            __builtin_memcpy(&v, &w[j], sizeof(v));
+            acc -= (W)v;
+          }
+        }
+        if (colok) st_bits(&Y[(int64_t)r * B + col], (TY)acc);
+      }
+    }
+    wait_vmem();
+    __syncthreads();
+  }
+}
+
+namespace {
+template <typename Tin, typename TY, bool O32>
+int poll_resident() {
+  static std::atomic<int> cached[64];  // per device; builds may run on several threads
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (int c = cached[dev].load(std::memory_order_relaxed); c > 0) return c;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_usolve_poll<Tin, TY, O32>, WG, 0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  const int r = std::max(1, per_cu) * std::max(1, cus);
+  cached[dev].store(r, std::memory_order_relaxed);
+  return r;
+}
+
+template <typename Tin, typename TY>
+hipError_t poll_typed(const DevPoset& d, const int32_t* nv, const int32_t* rows, const int32_t* lnv,
+                      const int32_t* lnode, const int32_t* lev_ptr, int nlev, int cnt, const void* g, int64_t ldg,
+                      void* Y, int64_t B, int* sync, int spin_limit, int max_grid, hipStream_t s) {
+  using U = typename PollMark<TY>::U;
+  const int64_t ncb = (B + 63) / 64;
+  const int64_t nsync = 1 + ncb * ((int64_t)d.n + 1);
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nsync + WG - 1) / WG)), dim3(WG), 0, s, sync, nsync, 0);
+  const int64_t words = (int64_t)d.n * B;  // rows 0 .. n-1 unwritten; row n, the zero row, stays 0
+  if (sizeof(U) == 8) {
+    int64_t m;
+    const U bits = PollMark<TY>::bits;
+    std::memcpy(&m, &bits, 8);
+    hipLaunchKernelGGL(k_fill_i64x2, dim3((unsigned)((words + 2 * WG - 1) / (2 * WG))), dim3(WG), 0, s, (int64_t*)Y,
+                       words, m);
+  } else {
+    int m;
+    const U bits = PollMark<TY>::bits;
+    std::memcpy(&m, &bits, 4);
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((words + WG - 1) / WG)), dim3(WG), 0, s, (int*)Y, words, m);
+  }
+  const bool o32 = ((int64_t)d.n + 1) * B * (int64_t)sizeof(TY) < ((int64_t)1 << 32);
+  const int res = o32 ? poll_resident<Tin, TY, true>() : poll_resident<Tin, TY, false>();
+  if (res <= 0) return hipErrorInvalidValue;
+  const int64_t waves = (int64_t)cnt * ncb;
+  const int64_t need = (waves + (WG / 64) - 1) / (WG / 64);
+  const unsigned grid =
+      (unsigned)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(need, res), max_grid > 0 ? max_grid : res));
+  if (o32)
+    hipLaunchKernelGGL((k_usolve_poll<Tin, TY, true>), dim3(grid), dim3(WG), 0, s, d, nv, rows, lnv, lnode, cnt,
+                       (const Tin*)g, ldg, (TY*)Y, B, sync + 1, sync, spin_limit);
+  else
+    hipLaunchKernelGGL((k_usolve_poll<Tin, TY, false>), dim3(grid), dim3(WG), 0, s, d, nv, rows, lnv, lnode, cnt,
+                       (const Tin*)g, ldg, (TY*)Y, B, sync + 1, sync, spin_limit);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_usolve_poll_fix<Tin, TY>), dim3(1), dim3(WG), 0, s, d, nv, rows, lev_ptr, nlev,
+                     (const Tin*)g, ldg, (TY*)Y, B, (const int*)sync);
+  return hipGetLastError();
+}
+}  // namespace
+
+int64_t usolve_poll_ints(int64_t n, int64_t B) { return 1 + (B + 63) / 64 * (n + 1); }
+
+int64_t usolve_poll_waves(ElemType tin, ElemType ty, int64_t n, int64_t B) {
+  const int64_t span = ((int64_t)n + 1) * B * (ty == E_F32 ? 4 : 8);
+  const bool o32 = span < ((int64_t)1 << 32);
+  int res = 0;
+  if (tin == E_I64 && ty == E_I64)
+    res = o32 ? poll_resident<int64_t, int64_t, true>() : poll_resident<int64_t, int64_t, false>();
+  else if (tin == E_F32 && ty == E_F32)
+    res = o32 ? poll_resident<float, float, true>() : poll_resident<float, float, false>();
+  else if (tin == E_F64 && ty == E_F32)
+    res = o32 ? poll_resident<double, float, true>() : poll_resident<double, float, false>();
+  else if (tin == E_F64 && ty == E_F64)
+    res = o32 ? poll_resident<double, double, true>() : poll_resident<double, double, false>();
+  return (int64_t)res * (WG / 64);
+}
+
+hipError_t launch_usolve_poll(const DevPoset& d, bool up, const int32_t* rows, const int32_t* lev_ptr, int nlev,
+                              int64_t cnt, ElemType tin, const void* g, int64_t ldg, ElemType ty, void* Y, int64_t B,
+                              int* sync, int spin_limit, int max_grid, hipStream_t s) {
+  if (cnt == 0) return hipSuccess;
+  const int32_t* nv = up ? d.niv_up : d.niv;
+  if (!nv || !rows || !lev_ptr || !sync || d.nivp[up ? 1 : 0] || cnt >= INT32_MAX || (int64_t)d.n + 1 >= INT32_MAX ||
+      (int64_t)d.n * ((B + 63) / 64) >= INT32_MAX || d.poset_of_row)
+    return hipErrorInvalidValue;
+  const int32_t* lnv = d.lev_niv[up ? 1 : 0];
+  const int32_t* lnode = d.lev_node[up ? 1 : 0];
+  if (!lnv || !lnode) lnv = lnode = nullptr;
+  const int c = (int)cnt;
+  if (tin == E_I64 && ty == E_I64)
+    return poll_typed<int64_t, int64_t>(d, nv, rows, lnv, lnode, lev_ptr, nlev, c, g, ldg, Y, B, sync, spin_limit,
+                                        max_grid, s);
+  if (tin == E_F32 && ty == E_F32)
+    return poll_typed<float, float>(d, nv, rows, lnv, lnode, lev_ptr, nlev, c, g, ldg, Y, B, sync, spin_limit,
+                                    max_grid, s);
+  if (tin == E_F64 && ty == E_F32)
+    return poll_typed<double, float>(d, nv, rows, lnv, lnode, lev_ptr, nlev, c, g, ldg, Y, B, sync, spin_limit,
+                                     max_grid, s);
+  if (tin == E_F64 && ty == E_F64)
+    return poll_typed<double, double>(d, nv, rows, lnv, lnode, lev_ptr, nlev, c, g, ldg, Y, B, sync, spin_limit,
+                                      max_grid, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_usolve_level(const DevPoset& d, bool up, const int32_t* lev_rows, int64_t i0, int64_t cnt,

@@ -467,6 +467,83 @@ def test_int64_solve_values_equal_to_unwritten_mark(px, B, wait, monkeypatch):
     assert np.array_equal(H(px.mobius_adjoint(P, a)), f)
 
 
+def _level_poll_shape(shape):
+    if shape == "cfg0":
+        return W.chain_poset(2000, 16, 4, seed=71)
+    if shape == "grid":
+        return W.grid_poset(96, 24)
+    return W.chain_poset(3000, 130, 3, seed=72)  # k > 64: dense rows read in two batches
+
+
+@pytest.mark.parametrize("shape", ["cfg0", "grid", "k130"])
+def test_level_poll_solve_matches_per_level_launches(px, shape, monkeypatch):
+    """The row-by-row level solve in one persistent launch that polls the values it
+    reads (the default for floating point, and for int64 rows without runs) equals one
+    launch per level (POSETX_LEVEL_POLL=2 forces the one, 0 the other) bit for bit: float32 Möbius with its
+    float64-residual refinement, float64 Möbius and both adjoints, at B = 1, 16, 64 and
+    100 (two 64-column blocks); int64 row by row against the substitution oracle."""
+    import torch
+    p = _level_poll_shape(shape)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = build(px, p)
+    assert P.info["levels_down"] >= 2
+    for B in (1, 16, 64, 100):
+        f = W.functions(p.n, B, "int", seed=73 + B, lo=-100, hi=100)
+        g32 = T(O.zeta(R, f).astype(np.float32))
+        g64 = T(O.zeta(R, f).astype(np.float64))
+        got = {}
+        for poll in ("2", "0"):
+            monkeypatch.setenv("POSETX_LEVEL_POLL", poll)
+            got[poll] = (px.mobius(P, g32, tol=-1), px.mobius_adjoint(P, g32, tol=-1),
+                         px.mobius(P, g64, tol=-1), px.mobius_adjoint(P, g64, tol=-1))
+        for a, b in zip(got["2"], got["0"]):
+            assert torch.equal(a, b), (shape, B)
+        assert rel(H(got["2"][2]), f) <= 1e-9
+        monkeypatch.setenv("POSETX_LEVEL_POLL", "2")
+        monkeypatch.setenv("POSETX_USOLVE", "direct")
+        gi = W.functions(p.n, B, "int", seed=74 + B, lo=-(2 ** 40), hi=2 ** 40)
+        assert np.array_equal(H(px.mobius(P, T(gi))), O.mobius_by_substitution(R, gi))
+        assert np.array_equal(H(px.mobius_adjoint(P, T(gi))), O.mobius_adjoint_by_substitution(R, gi))
+        monkeypatch.delenv("POSETX_USOLVE")
+
+
+@pytest.mark.parametrize("spin", ["0", "default"])
+def test_level_poll_solve_marks_and_fallback(px, spin, monkeypatch):
+    """int64 row by row in the persistent launch with solutions equal to its
+    unwritten mark (every row of column 0 downward, of column 1 upward): taken once
+    the rows' ready flags are set; and with a spin limit of 0 every wait gives up, the
+    fallback solves level by level, and float32, float64 and int64 results still equal
+    the per-level launches (the give-up path forced from the host)."""
+    import torch
+    monkeypatch.setenv("POSETX_LEVEL_POLL", "2")
+    p = W.chain_poset(2500, 8, 3, seed=75)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = build(px, p)
+    if spin == "0":
+        monkeypatch.setenv("POSETX_FLOW_SPIN", "0")
+    monkeypatch.setenv("POSETX_USOLVE", "direct")
+    B = 6
+    lo = np.iinfo(np.int64).min
+    f = W.functions(p.n, B, "int", seed=76, lo=-1000, hi=1000)
+    f[:, :2] = 0
+    ends = np.zeros(int(p.chain_of.max()) + 1, dtype=np.int64)
+    np.maximum.at(ends, p.chain_of, p.chain_pos)
+    f[p.chain_pos == 0, 0] = lo
+    f[p.chain_pos == ends[p.chain_of], 1] = lo
+    g, a = px.zeta(P, T(f)), px.zeta_adjoint(P, T(f))
+    assert np.array_equal(H(px.mobius(P, g)), f)
+    assert np.array_equal(H(px.mobius_adjoint(P, a)), f)
+    fl = W.functions(p.n, 16, "int", seed=77, lo=-100, hi=100)
+    g32 = T(O.zeta(R, fl).astype(np.float32))
+    g64 = T(O.zeta(R, fl).astype(np.float64))
+    res = {}
+    for poll in ("2", "0"):
+        monkeypatch.setenv("POSETX_LEVEL_POLL", poll)
+        res[poll] = (px.mobius(P, g32, tol=-1), px.mobius(P, g64, tol=-1), px.mobius_adjoint(P, g32, tol=-1))
+    for x, y in zip(res["2"], res["0"]):
+        assert torch.equal(x, y)
+
+
 @pytest.mark.parametrize("wait", ["deps", "level", "rows", "values"])
 @pytest.mark.parametrize("B", [8, 64])
 def test_int64_persistent_solve_fallback(px, B, wait, monkeypatch):
