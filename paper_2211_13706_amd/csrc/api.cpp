@@ -624,6 +624,7 @@ struct px_poset {
   int32_t* d_run_levn[2] = {nullptr, nullptr};  // per level: its first chunk (levels + 1 entries)
   // per level: its first position in d_lev_down / d_lev_up (levels + 1 entries; dense rows)
   int32_t* d_lev_ptr[2] = {nullptr, nullptr};
+  uint64_t* d_lev_bits[2] = {nullptr, nullptr};  // bit p: position p starts a level
   int32_t* d_run_dep_ptr[2] = {nullptr, nullptr};  // per chunk: the chunks it reads from
   int32_t* d_run_deps[2] = {nullptr, nullptr};
   int64_t* d_nivp[2] = {nullptr, nullptr};
@@ -689,6 +690,10 @@ void free_poset_device(px_poset* p) {
     if (b) (void)hipFree(b);
   for (int64_t* b : p->d_nivp)
     if (b) (void)hipFree(b);
+  for (uint64_t*& b : p->d_lev_bits) {
+    if (b) (void)hipFree(b);
+    b = nullptr;
+  }
   for (int m = 0; m < 2; ++m) {
     if (p->d_run_ev[m]) (void)hipFree(p->d_run_ev[m]);
     if (p->d_run_chunks[m]) (void)hipFree(p->d_run_chunks[m]);
@@ -1065,12 +1070,14 @@ hipError_t solve_levels(const px_poset* p, bool up, px::ElemType tin, const void
   }
   const int poll = level_poll_mode();
   const int64_t nlev = (int64_t)ptr.size() - 1;
-  if (flow && p->d_lev_ptr[m] && nlev >= 2 && poll > 0 &&
-      (poll == 2 || (int64_t)ptr.back() * ((B + 63) / 64) <= nlev * px::usolve_poll_waves(tin, ty, p->prep.n, B))) {
+  const int cwp = 64 / px::usolve_poll_rows_per_wave(B);
+  const int64_t wave_items = ((int64_t)ptr.back() + 64 / cwp - 1) / (64 / cwp) * ((B + cwp - 1) / cwp);
+  if (flow && p->d_lev_ptr[m] && p->d_lev_bits[m] && nlev >= 2 && poll > 0 &&
+      (poll == 2 || wave_items <= nlev * px::usolve_poll_waves(tin, ty, p->prep.n, B))) {
     prof::Scope sc(prof::USOLVE, s);
     const char* gv = std::getenv("POSETX_POLL_GRID");
-    return px::launch_usolve_poll(p->dp, up, rows, p->d_lev_ptr[m], (int)ptr.size() - 1, ptr.back(), tin, g, ldg, ty,
-                                  Y, B, (int*)flow, flow_spin_limit(), gv ? std::atoi(gv) : 0, s);
+    return px::launch_usolve_poll(p->dp, up, rows, p->d_lev_ptr[m], p->d_lev_bits[m], (int)nlev, ptr.back(), tin, g,
+                                  ldg, ty, Y, B, (int*)flow, flow_spin_limit(), gv ? std::atoi(gv) : 0, s);
   }
   for (size_t l = 0; l + 1 < ptr.size(); ++l) {
     prof::Scope sc(prof::USOLVE, s);
@@ -1516,9 +1523,13 @@ static px_status finish_poset(px_poset* p, int device, px_poset** out) {
     }
     if (e == hipSuccess) e = upload(&p->d_lev_down, P.lev_down_rows.data(), P.lev_down_rows.size(), b);
     if (e == hipSuccess && p->has_up) e = upload(&p->d_lev_up, P.lev_up_rows.data(), P.lev_up_rows.size(), b);
-    if (e == hipSuccess && !P.sparse) e = upload(&p->d_lev_ptr[0], P.lev_down_ptr.data(), P.lev_down_ptr.size(), b);
-    if (e == hipSuccess && !P.sparse && p->has_up)
-      e = upload(&p->d_lev_ptr[1], P.lev_up_ptr.data(), P.lev_up_ptr.size(), b);
+    for (int dir = 0; dir < (p->has_up ? 2 : 1) && e == hipSuccess && !P.sparse; ++dir) {
+      const std::vector<int32_t>& lp = dir ? P.lev_up_ptr : P.lev_down_ptr;
+      std::vector<uint64_t> bits((size_t)(n + 64) / 64 + 1, 0);
+      for (int32_t q : lp) bits[(size_t)q >> 6] |= 1ull << (q & 63);
+      e = upload(&p->d_lev_ptr[dir], lp.data(), lp.size(), b);
+      if (e == hipSuccess) e = upload(&p->d_lev_bits[dir], bits.data(), bits.size(), b);
+    }
     // level-ordered niv rows and node ids for the uniform level solve, gathered
     // on the device from the maps and level orders already there
     for (int dir = 0; dir < 2 && e == hipSuccess && P.k <= 64 && !P.sparse; ++dir) {

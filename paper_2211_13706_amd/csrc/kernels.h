@@ -220,22 +220,28 @@ hipError_t launch_usolve_flow(const DevPoset& d, bool up, const int4* chunks, in
                               const int32_t* dep_ptr, const int32_t* deps, int wait, const void* g, int64_t ldg, void* Y,
                               int64_t B, int* sync, int spin_limit, int max_grid, hipStream_t s);
 
-// The row-by-row level solve (dense niv rows, k_usolve_uni's sums, so results
-// equal the per-level launches bit for bit) for every level in one persistent
-// launch: rows, the level-ordered rows (cnt), lev_ptr (device, nlev + 1
-// entries) the first position of every level.  Rows 0 .. n-1 of Y are first
-// filled with a mark; a row's wavefront reads the rows it needs until none
-// holds the mark (a legitimate value equal to it is taken once that row's
-// ready flag is set).  sync: usolve_poll_ints(n, B) ints of scratch, cleared
-// by the launch.  spin_limit bounds each wait (polls); a wait that gives up
-// makes a one-workgroup fallback solve again level by level.  max_grid > 0
-// caps the workgroups.  Row n of Y must be zero (launch_usolve_begin).
+// The row-by-row level solve (dense niv rows, the per-level kernels' sums, so
+// results equal them bit for bit) for every level in one persistent launch:
+// rows, the level-ordered rows (cnt), lev_ptr (device, nlev + 1 entries) the
+// first position of every level, lev_bits (device, one bit per position,
+// ceil((cnt + 1) / 64) words) set at those first positions.  Rows 0 .. n-1 of
+// Y are first filled with a mark; a row's lanes read the rows it needs until
+// none holds the mark (int64: a legitimate value equal to it is taken once
+// that row's ready flag is set).  One row per wavefront for B > 32, else 8,
+// 16 or 32 columns per row and several rows per wavefront.  sync:
+// usolve_poll_ints(n, B) ints of scratch, cleared by the launch.  spin_limit
+// bounds each wait (polls); a wait that gives up makes a one-workgroup
+// fallback solve again level by level.  max_grid > 0 caps the workgroups.
+// Row n of Y must be zero (launch_usolve_begin).
 int64_t usolve_poll_ints(int64_t n, int64_t B);
-// Wavefronts of that launch the device holds resident at once (0: none).
+// Wavefronts of that launch the device holds resident at once (0: none), and
+// the rows each takes at a time.
 int64_t usolve_poll_waves(ElemType tin, ElemType ty, int64_t n, int64_t B);
-hipError_t launch_usolve_poll(const DevPoset& d, bool up, const int32_t* rows, const int32_t* lev_ptr, int nlev,
-                              int64_t cnt, ElemType tin, const void* g, int64_t ldg, ElemType ty, void* Y, int64_t B,
-                              int* sync, int spin_limit, int max_grid, hipStream_t s);
+int usolve_poll_rows_per_wave(int64_t B);
+hipError_t launch_usolve_poll(const DevPoset& d, bool up, const int32_t* rows, const int32_t* lev_ptr,
+                              const uint64_t* lev_bits, int nlev, int64_t cnt, ElemType tin, const void* g,
+                              int64_t ldg, ElemType ty, void* Y, int64_t B, int* sync, int spin_limit, int max_grid,
+                              hipStream_t s);
 
 // One level of the int64 solve by runs (dense niv rows, B >= 5): the chunks
 // of that level (see SegTables).

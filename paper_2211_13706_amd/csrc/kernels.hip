@@ -3585,6 +3585,138 @@ __global__ __launch_bounds__(WG) void k_usolve_poll(DevPoset d, const int32_t* _
   }
 }
 
+// The same poll for row groups of fewer than 64 lanes: every lane holds its
+// row's entries t[0 .. KB) (-1: none), so rows differ across the wavefront.
+// The lowest entry still marked in some lane is polled (lanes whose row has
+// no such entry read the zero row); with FLAGS a lane that reads its entry's
+// ready flag as set takes that entry's next read as it is.
+template <typename TY, int KB, bool FLAGS, bool O32>
+__device__ inline bool poll_lanes(const TY* __restrict__ Y, int64_t B, int64_t colc, int zr, const int32_t (&t)[KB],
+                                  TY (&v)[KB], const int* __restrict__ fl, const int* __restrict__ err,
+                                  int spin_limit) {
+  using U = typename PollMark<TY>::U;
+  auto at = [&](int r) -> const TY* {
+    if (O32)
+      return reinterpret_cast<const TY*>(reinterpret_cast<const char*>(Y) +
+                                         (uint32_t)(((uint32_t)r * (uint32_t)B + (uint32_t)colc) * sizeof(TY)));
+    return Y + (int64_t)r * B + colc;
+  };
+  U b[KB];
+  uint64_t seen = 0;  // per lane
+  int spin = 0;
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  for (;;) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) b[j] = ld_bits(at(t[j] >= 0 ? t[j] : zr));
+    uint64_t pend = 0;  // wave-uniform
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+      if (__any(b[j] == PollMark<TY>::bits && t[j] >= 0 && !((seen >> j) & 1))) pend |= 1ull << j;
+    if (pend == 0) break;
+    const int js = __builtin_amdgcn_readfirstlane(__builtin_ctzll(pend));
+    int ts = -1;
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+      if (j == js) ts = t[j];
+    const bool mine = ts >= 0 && !((seen >> js) & 1);
+    for (int poll = 0;; ++poll, ++spin) {
+      if (spin >= spin_limit) return false;
+      if ((spin & 15) == 15) {
+        if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0)
+          return false;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > kFlowWaitTicks) return false;
+      }
+      __builtin_amdgcn_s_sleep(2);
+      if (FLAGS && (poll & 3) == 3) {
+        const int f = __hip_atomic_load(fl + (mine ? ts : zr), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        wait_vmem();  // the flag has arrived before the next round's reads are issued
+        if (mine && f != 0) seen |= 1ull << js;
+        if (__any(mine && f != 0)) break;
+      }
+      if (!__any(mine && ld_bits(at(mine ? ts : zr)) == PollMark<TY>::bits)) break;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < KB; ++j) __builtin_memcpy(&v[j], &b[j], sizeof(U));
+  return true;
+}
+
+// k_usolve_poll for narrow blocks (CW = 8, 16 or 32 columns): a wavefront
+// takes 64 / CW consecutive positions of the level-ordered list at a time, one
+// row per group of CW lanes, and a block of CW columns.  Rows of one
+// wavefront item that lie in different levels are solved one level after the
+// other (sub-batches; lev_bits marks the first position of every level), so a
+// wavefront never waits on a row it holds itself.  Same sums as the per-level
+// kernels.
+template <typename Tin, typename TY, int CW, bool O32>
+__global__ __launch_bounds__(WG) void k_usolve_poll_n(DevPoset d, const int32_t* __restrict__ nv,
+                                                      const int32_t* __restrict__ rows,
+                                                      const int32_t* __restrict__ lnv,
+                                                      const int32_t* __restrict__ lnode,
+                                                      const uint64_t* __restrict__ lev_bits, int cnt,
+                                                      const Tin* __restrict__ g, int64_t ldg, TY* __restrict__ Y,
+                                                      int64_t B, int* __restrict__ flags, int* __restrict__ err,
+                                                      int spin_limit) {
+  using W = typename Wide<TY>::W;
+  constexpr bool FLAGS = std::is_same<TY, int64_t>::value;
+  constexpr int KB = 32;
+  constexpr int RPW = 64 / CW;  // rows per wavefront item
+  const int lane = threadIdx.x % CW;
+  const int rgw = (threadIdx.x & 63) / CW;
+  const int ncb = (int)((B + CW - 1) / CW);
+  const int64_t nwi = ((int64_t)cnt + RPW - 1) / RPW;
+  const int64_t total = nwi * ncb;
+  const int64_t nw = (int64_t)gridDim.x * (WG / 64);
+  const int k = d.k, zr = d.n;
+  for (int64_t it = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6); it < total; it += nw) {
+    const int wi = __builtin_amdgcn_readfirstlane((int)(it / ncb));
+    const int cb = __builtin_amdgcn_readfirstlane((int)(it - (int64_t)wi * ncb));
+    const int p0 = wi * RPW;  // a multiple of RPW: the item's positions share one 64-bit word of lev_bits
+    const int pos = p0 + rgw;
+    const bool act = pos < cnt;
+    int* const fl = flags + (int64_t)cb * (zr + 1);
+    const int64_t col = (int64_t)cb * CW + lane;
+    const bool colok = col < B;
+    const int64_t colc = colok ? col : 0;
+    // level of each position relative to the item's first: the level starts in (p0, pos]
+    const uint64_t word = lev_bits[p0 >> 6];
+    const int sh = p0 & 63;
+    const uint64_t within = RPW == 64 ? word : (word >> sh) & ((1ull << RPW) - 1);
+    const int sub = __builtin_popcountll(within & ((2ull << rgw) - 1) & ~1ull);
+    const int nsub = __builtin_popcountll(within & ~1ull);
+    const int r = act ? rows[pos] : 0;
+    const int node = act ? (lnode ? lnode[pos] : d.node_of_row[r]) : 0;
+    const int32_t* __restrict__ nr = lnv ? lnv + (int64_t)(act ? pos : 0) * k : nv + (int64_t)r * k;
+    W acc = act ? (W)g[(int64_t)node * ldg + colc] : W(0);
+    for (int sb = 0; sb <= nsub; ++sb) {
+      if (!act || sub != sb) continue;
+      bool ok = true;
+      for (int j0 = 0; j0 < k; j0 += KB) {
+        int32_t t[KB];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+          const int e = j0 + u < k ? nr[j0 + u] : -1;
+          t[u] = e != r ? e : -1;
+        }
+        TY v[KB];
+        if (!poll_lanes<TY, KB, FLAGS, O32>(Y, B, colc, zr, t, v, fl, err, spin_limit)) {
+          ok = false;
+          break;
+        }
+#pragma unroll
+        for (int u = 0; u < KB; ++u) acc -= (W)v[u];
+      }
+      if (!ok) {
+        if (lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+      }
+      if (colok) st_bits(&Y[(int64_t)r * B + col], (TY)acc);
+      if (FLAGS || nsub > 0) wait_vmem();  // (the next sub-batch may read these rows)
+      if (FLAGS && lane == 0) __hip_atomic_store(&fl[r], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 // Fallback of k_usolve_poll: when its error word is set, one workgroup solves
 // again, level after level with a barrier in between, a row per wavefront with
 // the same sums; otherwise it returns at once.  Reads and writes are
@@ -3635,14 +3767,26 @@ __global__ __launch_bounds__(WG) void k_usolve_poll_fix(DevPoset d, const int32_
 }
 
 namespace {
-template <typename Tin, typename TY, bool O32>
+// Columns per row group of the persistent row solve: 64 (one row per
+// wavefront) for B > 32, else 8, 16 or 32 (several rows per wavefront).
+int poll_col_width(int64_t B) { return std::max(8, col_width(B)); }
+
+template <typename Tin, typename TY, int CW, bool O32>
+const void* poll_kernel() {
+  if constexpr (CW == 64)
+    return reinterpret_cast<const void*>(&k_usolve_poll<Tin, TY, O32>);
+  else
+    return reinterpret_cast<const void*>(&k_usolve_poll_n<Tin, TY, CW, O32>);
+}
+
+template <typename Tin, typename TY, int CW, bool O32>
 int poll_resident() {
   static std::atomic<int> cached[64];  // per device; builds may run on several threads
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
   if (int c = cached[dev].load(std::memory_order_relaxed); c > 0) return c;
   int per_cu = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_usolve_poll<Tin, TY, O32>, WG, 0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, poll_kernel<Tin, TY, CW, O32>(), WG, 0) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
     (void)hipGetLastError();
     return 0;
@@ -3652,12 +3796,50 @@ int poll_resident() {
   return r;
 }
 
+template <typename Tin, typename TY, bool O32>
+int poll_resident_cw(int cw) {
+  switch (cw) {
+    case 64: return poll_resident<Tin, TY, 64, O32>();
+    case 32: return poll_resident<Tin, TY, 32, O32>();
+    case 16: return poll_resident<Tin, TY, 16, O32>();
+    default: return poll_resident<Tin, TY, 8, O32>();
+  }
+}
+
+template <typename Tin, typename TY, bool O32>
+void poll_launch(int cw, unsigned grid, hipStream_t s, const DevPoset& d, const int32_t* nv, const int32_t* rows,
+                 const int32_t* lnv, const int32_t* lnode, const uint64_t* lev_bits, int cnt, const void* g,
+                 int64_t ldg, void* Y, int64_t B, int* sync, int spin_limit) {
+  const Tin* gt = (const Tin*)g;
+  TY* Yt = (TY*)Y;
+  switch (cw) {
+    case 64:
+      hipLaunchKernelGGL((k_usolve_poll<Tin, TY, O32>), dim3(grid), dim3(WG), 0, s, d, nv, rows, lnv, lnode, cnt, gt,
+                         ldg, Yt, B, sync + 1, sync, spin_limit);
+      break;
+    case 32:
+      hipLaunchKernelGGL((k_usolve_poll_n<Tin, TY, 32, O32>), dim3(grid), dim3(WG), 0, s, d, nv, rows, lnv, lnode,
+                         lev_bits, cnt, gt, ldg, Yt, B, sync + 1, sync, spin_limit);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_usolve_poll_n<Tin, TY, 16, O32>), dim3(grid), dim3(WG), 0, s, d, nv, rows, lnv, lnode,
+                         lev_bits, cnt, gt, ldg, Yt, B, sync + 1, sync, spin_limit);
+      break;
+    default:
+      hipLaunchKernelGGL((k_usolve_poll_n<Tin, TY, 8, O32>), dim3(grid), dim3(WG), 0, s, d, nv, rows, lnv, lnode,
+                         lev_bits, cnt, gt, ldg, Yt, B, sync + 1, sync, spin_limit);
+      break;
+  }
+}
+
 template <typename Tin, typename TY>
 hipError_t poll_typed(const DevPoset& d, const int32_t* nv, const int32_t* rows, const int32_t* lnv,
-                      const int32_t* lnode, const int32_t* lev_ptr, int nlev, int cnt, const void* g, int64_t ldg,
-                      void* Y, int64_t B, int* sync, int spin_limit, int max_grid, hipStream_t s) {
+                      const int32_t* lnode, const uint64_t* lev_bits, const int32_t* lev_ptr, int nlev, int cnt,
+                      const void* g, int64_t ldg, void* Y, int64_t B, int* sync, int spin_limit, int max_grid,
+                      hipStream_t s) {
   using U = typename PollMark<TY>::U;
-  const int64_t ncb = (B + 63) / 64;
+  const int cw = poll_col_width(B);
+  const int64_t ncb = (B + cw - 1) / cw;
   const int64_t nsync = 1 + ncb * ((int64_t)d.n + 1);
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((nsync + WG - 1) / WG)), dim3(WG), 0, s, sync, nsync, 0);
   const int64_t words = (int64_t)d.n * B;  // rows 0 .. n-1 unwritten; row n, the zero row, stays 0
@@ -3674,18 +3856,16 @@ hipError_t poll_typed(const DevPoset& d, const int32_t* nv, const int32_t* rows,
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((words + WG - 1) / WG)), dim3(WG), 0, s, (int*)Y, words, m);
   }
   const bool o32 = ((int64_t)d.n + 1) * B * (int64_t)sizeof(TY) < ((int64_t)1 << 32);
-  const int res = o32 ? poll_resident<Tin, TY, true>() : poll_resident<Tin, TY, false>();
+  const int res = o32 ? poll_resident_cw<Tin, TY, true>(cw) : poll_resident_cw<Tin, TY, false>(cw);
   if (res <= 0) return hipErrorInvalidValue;
-  const int64_t waves = (int64_t)cnt * ncb;
+  const int64_t waves = ((int64_t)cnt + 64 / cw - 1) / (64 / cw) * ncb;
   const int64_t need = (waves + (WG / 64) - 1) / (WG / 64);
   const unsigned grid =
       (unsigned)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(need, res), max_grid > 0 ? max_grid : res));
   if (o32)
-    hipLaunchKernelGGL((k_usolve_poll<Tin, TY, true>), dim3(grid), dim3(WG), 0, s, d, nv, rows, lnv, lnode, cnt,
-                       (const Tin*)g, ldg, (TY*)Y, B, sync + 1, sync, spin_limit);
+    poll_launch<Tin, TY, true>(cw, grid, s, d, nv, rows, lnv, lnode, lev_bits, cnt, g, ldg, Y, B, sync, spin_limit);
   else
-    hipLaunchKernelGGL((k_usolve_poll<Tin, TY, false>), dim3(grid), dim3(WG), 0, s, d, nv, rows, lnv, lnode, cnt,
-                       (const Tin*)g, ldg, (TY*)Y, B, sync + 1, sync, spin_limit);
+    poll_launch<Tin, TY, false>(cw, grid, s, d, nv, rows, lnv, lnode, lev_bits, cnt, g, ldg, Y, B, sync, spin_limit);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_usolve_poll_fix<Tin, TY>), dim3(1), dim3(WG), 0, s, d, nv, rows, lev_ptr, nlev,
@@ -3694,47 +3874,54 @@ hipError_t poll_typed(const DevPoset& d, const int32_t* nv, const int32_t* rows,
 }
 }  // namespace
 
-int64_t usolve_poll_ints(int64_t n, int64_t B) { return 1 + (B + 63) / 64 * (n + 1); }
+int64_t usolve_poll_ints(int64_t n, int64_t B) {
+  const int cw = poll_col_width(B);
+  return 1 + (B + cw - 1) / cw * (n + 1);
+}
 
 int64_t usolve_poll_waves(ElemType tin, ElemType ty, int64_t n, int64_t B) {
   const int64_t span = ((int64_t)n + 1) * B * (ty == E_F32 ? 4 : 8);
   const bool o32 = span < ((int64_t)1 << 32);
+  const int cw = poll_col_width(B);
   int res = 0;
   if (tin == E_I64 && ty == E_I64)
-    res = o32 ? poll_resident<int64_t, int64_t, true>() : poll_resident<int64_t, int64_t, false>();
+    res = o32 ? poll_resident_cw<int64_t, int64_t, true>(cw) : poll_resident_cw<int64_t, int64_t, false>(cw);
   else if (tin == E_F32 && ty == E_F32)
-    res = o32 ? poll_resident<float, float, true>() : poll_resident<float, float, false>();
+    res = o32 ? poll_resident_cw<float, float, true>(cw) : poll_resident_cw<float, float, false>(cw);
   else if (tin == E_F64 && ty == E_F32)
-    res = o32 ? poll_resident<double, float, true>() : poll_resident<double, float, false>();
+    res = o32 ? poll_resident_cw<double, float, true>(cw) : poll_resident_cw<double, float, false>(cw);
   else if (tin == E_F64 && ty == E_F64)
-    res = o32 ? poll_resident<double, double, true>() : poll_resident<double, double, false>();
+    res = o32 ? poll_resident_cw<double, double, true>(cw) : poll_resident_cw<double, double, false>(cw);
   return (int64_t)res * (WG / 64);
 }
 
-hipError_t launch_usolve_poll(const DevPoset& d, bool up, const int32_t* rows, const int32_t* lev_ptr, int nlev,
-                              int64_t cnt, ElemType tin, const void* g, int64_t ldg, ElemType ty, void* Y, int64_t B,
-                              int* sync, int spin_limit, int max_grid, hipStream_t s) {
+int usolve_poll_rows_per_wave(int64_t B) { return 64 / poll_col_width(B); }
+
+hipError_t launch_usolve_poll(const DevPoset& d, bool up, const int32_t* rows, const int32_t* lev_ptr,
+                              const uint64_t* lev_bits, int nlev, int64_t cnt, ElemType tin, const void* g,
+                              int64_t ldg, ElemType ty, void* Y, int64_t B, int* sync, int spin_limit, int max_grid,
+                              hipStream_t s) {
   if (cnt == 0) return hipSuccess;
   const int32_t* nv = up ? d.niv_up : d.niv;
-  if (!nv || !rows || !lev_ptr || !sync || d.nivp[up ? 1 : 0] || cnt >= INT32_MAX || (int64_t)d.n + 1 >= INT32_MAX ||
-      (int64_t)d.n * ((B + 63) / 64) >= INT32_MAX || d.poset_of_row)
+  if (!nv || !rows || !lev_ptr || !lev_bits || !sync || d.nivp[up ? 1 : 0] || cnt >= INT32_MAX ||
+      (int64_t)d.n + 1 >= INT32_MAX || (int64_t)d.n * ((B + 7) / 8) >= INT32_MAX || d.poset_of_row)
     return hipErrorInvalidValue;
   const int32_t* lnv = d.lev_niv[up ? 1 : 0];
   const int32_t* lnode = d.lev_node[up ? 1 : 0];
   if (!lnv || !lnode) lnv = lnode = nullptr;
   const int c = (int)cnt;
   if (tin == E_I64 && ty == E_I64)
-    return poll_typed<int64_t, int64_t>(d, nv, rows, lnv, lnode, lev_ptr, nlev, c, g, ldg, Y, B, sync, spin_limit,
-                                        max_grid, s);
+    return poll_typed<int64_t, int64_t>(d, nv, rows, lnv, lnode, lev_bits, lev_ptr, nlev, c, g, ldg, Y, B, sync,
+                                        spin_limit, max_grid, s);
   if (tin == E_F32 && ty == E_F32)
-    return poll_typed<float, float>(d, nv, rows, lnv, lnode, lev_ptr, nlev, c, g, ldg, Y, B, sync, spin_limit,
-                                    max_grid, s);
+    return poll_typed<float, float>(d, nv, rows, lnv, lnode, lev_bits, lev_ptr, nlev, c, g, ldg, Y, B, sync,
+                                    spin_limit, max_grid, s);
   if (tin == E_F64 && ty == E_F32)
-    return poll_typed<double, float>(d, nv, rows, lnv, lnode, lev_ptr, nlev, c, g, ldg, Y, B, sync, spin_limit,
-                                     max_grid, s);
+    return poll_typed<double, float>(d, nv, rows, lnv, lnode, lev_bits, lev_ptr, nlev, c, g, ldg, Y, B, sync,
+                                     spin_limit, max_grid, s);
   if (tin == E_F64 && ty == E_F64)
-    return poll_typed<double, double>(d, nv, rows, lnv, lnode, lev_ptr, nlev, c, g, ldg, Y, B, sync, spin_limit,
-                                      max_grid, s);
+    return poll_typed<double, double>(d, nv, rows, lnv, lnode, lev_bits, lev_ptr, nlev, c, g, ldg, Y, B, sync,
+                                      spin_limit, max_grid, s);
   return hipErrorInvalidValue;
 }
 

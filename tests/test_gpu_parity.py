@@ -480,14 +480,16 @@ def test_level_poll_solve_matches_per_level_launches(px, shape, monkeypatch):
     """The row-by-row level solve in one persistent launch that polls the values it
     reads (the default for floating point, and for int64 rows without runs) equals one
     launch per level (POSETX_LEVEL_POLL=2 forces the one, 0 the other) bit for bit: float32 Möbius with its
-    float64-residual refinement, float64 Möbius and both adjoints, at B = 1, 16, 64 and
-    100 (two 64-column blocks); int64 row by row against the substitution oracle."""
+    float64-residual refinement, float64 Möbius and both adjoints, at B = 1, 16, 24 (8,
+    4 and 2 rows per wavefront, whose rows of different levels go one level after the
+    other), 64 and 100 (one row per wavefront, two 64-column blocks); int64 row by row
+    against the substitution oracle."""
     import torch
     p = _level_poll_shape(shape)
     R = O.reachability(p.n, p.indptr, p.indices)
     P = build(px, p)
     assert P.info["levels_down"] >= 2
-    for B in (1, 16, 64, 100):
+    for B in (1, 16, 24, 64, 100):
         f = W.functions(p.n, B, "int", seed=73 + B, lo=-100, hi=100)
         g32 = T(O.zeta(R, f).astype(np.float32))
         g64 = T(O.zeta(R, f).astype(np.float64))
