@@ -304,13 +304,27 @@ def leg_grid(px, dev, steps, refine=3):
     fi = torch.empty_like(gi)
     G.reserve(torch.int64, Bg)
     ti = _time(lambda: px.mobius(G, gi, out=fi), steps, sync)
+    # both forms again with one launch per level instead of the persistent level solve
+    prev = os.environ.get("POSETX_LEVEL_POLL")
+    os.environ["POSETX_LEVEL_POLL"] = "0"
+    try:
+        t32l = _time(lambda: px.mobius(G, g, out=f, max_refine=refine, tol=-1.0), steps, sync)
+        t64l = _time(lambda: [px.mobius(G, c, out=o, tol=-1.0) for c, o in zip(cols, f64)], max(2, steps // 4), sync)
+    finally:
+        if prev is None:
+            os.environ.pop("POSETX_LEVEL_POLL", None)
+        else:
+            os.environ["POSETX_LEVEL_POLL"] = prev
     return {"workload": "grid 4096x64 (n=262144, k=64), B=16 float32 U(-1,1)",
             "levels": G.info["levels_down"], "mirsky_levels": G.info["mirsky_levels"],
             "int64_mobius_ms": round(ti * 1e3, 4),
             "us_per_level": round(ti * 1e6 / max(1, G.info["levels_down"]), 2),
             "f32_refined_ms": round(t32 * 1e3, 4), "refine_steps": refine,
             "f64_single_rhs_x16_ms": round(t64 * 1e3, 4), "speedup": round(t64 / t32, 2),
-            "rel_err_vs_f64": err, "report": rep}
+            "rel_err_vs_f64": err, "report": rep,
+            "launch_per_level": {"f32_refined_ms": round(t32l * 1e3, 4),
+                                 "f64_single_rhs_x16_ms": round(t64l * 1e3, 4),
+                                 "speedup": round(t64l / t32l, 2)}}
 
 
 def leg_batched(px, dev, steps, count=512):
