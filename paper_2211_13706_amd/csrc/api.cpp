@@ -1054,12 +1054,13 @@ hipError_t solve_levels(const px_poset* p, bool up, px::ElemType tin, const void
       if (wv && std::strcmp(wv, "rows") == 0) wait = px::kWaitRows;
       if (wv && std::strcmp(wv, "level") == 0) wait = px::kWaitLevel;
       if (wv && std::strcmp(wv, "deps") == 0) wait = px::kWaitDeps;
-      // 512 workgroups (two per compute unit) poll less than the full resident count; polling the
-      // values in 16-column items, 512 to 768 are equally fast (2.02-2.04 ms) and 1024 slower
-      // (2.22 ms; at n = 2^23, 8.7 against 5.7 ms)
+      // workgroups: 256 per column block plus 256, at most 1024 (polling the values in 16-column
+      // items: n = 2^20, B = 64, four blocks: 512 2.09 ms, 768 1.90, 1024 1.88; n = 2^23, B = 16,
+      // one block: 384 5.76, 512 5.59, 640 5.69, 768 5.81); capped by the resident count
+      const int64_t ncb = (B + px::flow_col_width(B) - 1) / px::flow_col_width(B);
+      const int grid = gv ? std::atoi(gv) : (int)(256 * std::min<int64_t>(ncb + 1, 4));
       return px::launch_usolve_flow(p->dp, up, p->d_run_chunks[m], cp.back(), p->d_run_levn[m], p->d_run_dep_ptr[m],
-                                    p->d_run_deps[m], wait, g, ldg, Y, B, (int*)flow, flow_spin_limit(),
-                                    gv ? std::atoi(gv) : 512, s);
+                                    p->d_run_deps[m], wait, g, ldg, Y, B, (int*)flow, flow_spin_limit(), grid, s);
     }
     for (size_t l = 0; l + 1 < cp.size(); ++l) {
       prof::Scope sc(prof::USOLVE, s);

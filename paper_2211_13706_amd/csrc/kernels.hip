@@ -2304,29 +2304,26 @@ __device__ inline bool await_rows_n(const int* __restrict__ fl, const int32_t* c
 constexpr int64_t kUnwritten = INT64_MIN;
 
 // Reads the values of the lane's column in Q lists of N rows of Y (-1 = the
-// zero row zr) into vals, polling until none is kUnwritten.  Each round reads
-// every value again (a written value never changes, so settled entries just
-// read the same word; the loads of a round are all in flight together).  A
-// row's value can equal the mark legitimately: every fourth round the ready
-// flags of the rows still pending are read, and the round after a flag read as
-// set (issued once that flag has arrived) takes the value as it is; the flag
-// is set only after the row's stores completed.  Exits are uniform over the
-// active lanes; false when the wait gives up.
+// zero row zr) into vals, until none is kUnwritten.  A round reads every value
+// (a written value never changes, so settled entries just read the same word;
+// the loads of a round are all in flight together).  While some entry is
+// still marked, the wavefront polls only the first such entry (one load per
+// lane and poll, so waiting workgroups add little traffic) and reads all
+// again once it has been written.  A row's value can equal the mark
+// legitimately: every fourth poll also reads the polled row's ready flag (set
+// after the row's stores completed), and once it reads as set the next
+// round's read of that entry, issued after the flag arrived, is taken as it
+// is.  Exits are uniform over the active lanes; false when the wait gives up.
 template <int N, int Q>
 __device__ inline bool await_vals(const int64_t* __restrict__ Y, int64_t B, int64_t colc, int zr,
                                   const int32_t* const (&rows)[Q], int64_t* const (&vals)[Q],
                                   const int* __restrict__ fl, const int* __restrict__ err, int spin_limit) {
-  uint32_t pend[Q], seen[Q];
+  uint32_t seen[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    pend[q] = 0;
-    seen[q] = 0;
-#pragma unroll
-    for (int u = 0; u < N; ++u)
-      if (rows[q][u] >= 0) pend[q] |= 1u << u;
-  }
+  for (int q = 0; q < Q; ++q) seen[q] = 0;
+  int spin = 0;
   const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-  for (int spin = 0;; ++spin) {
+  for (;;) {
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -2335,36 +2332,56 @@ __device__ inline bool await_vals(const int64_t* __restrict__ Y, int64_t B, int6
         asm volatile("" : "+v"(r));  // addresses formed in each round, not held across rounds
         vals[q][u] = ld_dev(&Y[(int64_t)r * B + colc]);
       }
+    uint32_t pend[Q];
     bool any = false;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
+      pend[q] = 0;
 #pragma unroll
       for (int u = 0; u < N; ++u)
-        if (((seen[q] >> u) & 1) || vals[q][u] != kUnwritten) pend[q] &= ~(1u << u);
+        if (rows[q][u] >= 0 && !((seen[q] >> u) & 1) && vals[q][u] == kUnwritten) pend[q] |= 1u << u;
       any = any || pend[q] != 0;
     }
     if (!__any(any)) return true;
-    if (spin >= spin_limit) return false;
-    if ((spin & 15) == 15) {
-      if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0)
-        return false;
-      if (__builtin_amdgcn_s_memrealtime() - t0 > kFlowWaitTicks) return false;
-    }
-    if ((spin & 3) == 3) {
+    // the first entry still pending in some lane (the same for the whole wavefront)
+    int qs = -1, us = -1;
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        int f[N];
+    for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int u = 0; u < N; ++u)
-          f[u] = __hip_atomic_load(fl + (((pend[q] >> u) & 1) ? rows[q][u] : zr), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        wait_vmem();  // the flags have arrived before the next round's reads are issued
+      for (int u = 0; u < N; ++u)
+        if (qs < 0 && __any((pend[q] >> u) & 1)) {
+          qs = q;
+          us = u;
+        }
+    int rs = zr;
+    bool mine = false;
 #pragma unroll
-        for (int u = 0; u < N; ++u)
-          if (((pend[q] >> u) & 1) && f[u] != 0) seen[q] |= 1u << u;
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int u = 0; u < N; ++u)
+        if (q == qs && u == us && ((pend[q] >> u) & 1)) {
+          rs = rows[q][u];
+          mine = true;
+        }
+    for (int poll = 0;; ++poll, ++spin) {
+      if (spin >= spin_limit) return false;
+      if ((spin & 15) == 15) {
+        if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0)
+          return false;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > kFlowWaitTicks) return false;
       }
+      __builtin_amdgcn_s_sleep(1);
+      if ((poll & 3) == 3) {
+        const int f = __hip_atomic_load(fl + rs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        wait_vmem();  // the flag has arrived before the next round's reads are issued
+        const bool set = mine && f != 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+          if (q == qs && set) seen[q] |= 1u << us;
+        if (__any(set)) break;
+      }
+      if (!__any(mine && ld_dev(&Y[(int64_t)rs * B + colc]) == kUnwritten)) break;
     }
-    __builtin_amdgcn_s_sleep(1);
   }
 }
 
