@@ -43,13 +43,23 @@
  *    and B >= 5, zeta, its adjoint and the residual of the refined Mobius
  *    transform complete the chain prefixes only at the rows the gather reads
  *    and never form the full prefix matrix (POSETX_COMPACT_NARROW=0 keeps that
- *    to B > 32, =2 extends it to every B); POSETX_WALK=rows forms it instead.  POSETX_SCAN=onepass selects the
- *    single-pass chain scan for the paths that form it, with POSETX_LB_SPIN
- *    bounding its waits (polls; 0 makes every wait give up and sum its
- *    predecessors from the input).  POSETX_TUNE_CACHE: see px_autotune.
+ *    to B > 32, =2 extends it to every B); POSETX_WALK=rows forms it
+ *    instead.  POSETX_SCAN=onepass selects the single-pass chain scan for the
+ *    paths that form it, with POSETX_LB_SPIN bounding its waits (polls; 0
+ *    makes every wait give up and sum its predecessors from the input).
+ *    POSETX_TUNE_CACHE: see px_autotune.  The Möbius level solve runs every
+ *    level in one persistent launch whose workgroups poll the values they
+ *    read (bounded waits; a wait that gives up makes a one-workgroup fallback
+ *    solve again): int64 with dense rows and B >= 5 by runs of rows
+ *    (POSETX_USOLVE=levels: a launch per level, =direct: row by row), other
+ *    dense solves row by row where the average level fits the resident
+ *    wavefronts (POSETX_LEVEL_POLL=0: a launch per level, =2: always
+ *    persistent); floating-point results do not depend on the choice.
+ *    POSETX_FLOW_SPIN bounds the polls of each wait.
  *    Posets with sparse niv rows (PX_BUILD_SPARSE_NIV, or more than 256
- *    chains) take the chain scan, a gather over their rows and a level solve,
- *    rows of more than 256 entries summed in fixed chunks.  Preprocessing:
+ *    chains) take the chain scan, a gather over their rows and a level solve
+ *    with a launch per level, rows of more than 256 entries summed in fixed
+ *    chunks.  Preprocessing:
  *    POSETX_PREP (see px_poset_build) and POSETX_PREP_THREADS (host threads of
  *    the recursion, default up to 16 for posets with wide levels).
  */
