@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -186,6 +187,51 @@ __global__ __launch_bounds__(SWG) void k_udep_level(int64_t cnt, const int32_t* 
   }
   m = wave_max(m);
   if (lane == 0) lev[r] = m;
+}
+
+// All U-dependency levels in one persistent launch.  lev starts at -1
+// (unknown).  Wavefront w takes the positions w, w + W, ... of the height
+// order (W the wavefronts of the grid), one row each: its lanes read the row's
+// other-chain entries (64 at a time), poll their levels until none is -1, and
+// lane 0 stores 1 + the largest (0 without entries).  An entry lies at a
+// lower height, so earlier in the order; a wavefront takes its positions in
+// order, so with every wavefront resident the unfinished position of lowest
+// index has all it reads and every wait ends.  Levels travel as relaxed
+// device-scope loads and stores (coherent across the per-XCD caches).  A
+// wait is bounded by spin_limit polls and about 2 s; one that gives up stores
+// err and stops, and the caller computes the levels height by height instead.
+__global__ __launch_bounds__(SWG) void k_udep_poll(int64_t n, const int32_t* __restrict__ hn,
+                                                   const int32_t* __restrict__ row_of_node, int k,
+                                                   const int32_t* __restrict__ nv, const int64_t* __restrict__ ep,
+                                                   const int32_t* __restrict__ er, int32_t* lev, int* err,
+                                                   int spin_limit) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t nw = (int64_t)gridDim.x * (SWG / 64);
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  for (int64_t i = (int64_t)blockIdx.x * (SWG / 64) + (threadIdx.x >> 6); i < n; i += nw) {
+    const int r = __builtin_amdgcn_readfirstlane(row_of_node[hn[i]]);
+    const int32_t* row = nv ? nv + (int64_t)r * k : er + ep[r];
+    const int64_t len = nv ? k : ep[r + 1] - ep[r];
+    int m = 0;
+    for (int64_t j0 = 0; j0 < len; j0 += 64) {
+      int t = j0 + lane < len ? row[j0 + lane] : -1;
+      if (t == r) t = -1;
+      int v = __hip_atomic_load(lev + (t >= 0 ? t : r), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int spin = 0; __any(t >= 0 && v < 0); ++spin) {
+        if (spin >= spin_limit || ((spin & 15) == 15 && (__hip_atomic_load(err, __ATOMIC_RELAXED,
+                                                                             __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                                                          __builtin_amdgcn_s_memrealtime() - t0 > 200000000ull))) {
+          if (lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          return;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        if (t >= 0 && v < 0) v = __hip_atomic_load(lev + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (t >= 0) m = max(m, v + 1);
+    }
+    m = wave_max(m);
+    if (lane == 0) __hip_atomic_store(lev + r, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // A run of narrow heights (few rows each, such as the one row per chain of a
@@ -440,9 +486,36 @@ int device_udep_levels(const Prep& P, const std::vector<int64_t>& hptr, const st
   // dense rows: heights of at most SEQ_ROWS rows and SEQ_WG * SEQ_PP entries go
   // in runs through k_udep_levels_seq, wider ones (and sparse rows) one launch each
   const int64_t nh = (int64_t)hptr.size() - 1;
+  // all levels in one persistent launch, unless POSETX_UDEP=heights; if a wait
+  // gave up there, height by height below
+  bool done = false;
+  const char* mode = std::getenv("POSETX_UDEP");
+  if (e == hipSuccess && !(mode && std::string(mode) == "heights")) {
+    int* d_err = hb.get<int>(1);
+    int per_cu = 0, cus = 0, dev = 0;
+    e = hb.err;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_udep_poll, SWG, 0);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipMemset(d_lev, 0xFF, n * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemset(d_err, 0, sizeof(int));
+    if (e == hipSuccess) {
+      const int64_t res = (int64_t)std::max(1, per_cu) * std::max(1, cus);
+      const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(res, (n + SWG / 64 - 1) / (SWG / 64)));
+      const char* sv = std::getenv("POSETX_FLOW_SPIN");
+      const int spin = sv ? std::max(0, std::atoi(sv)) : 1 << 20;
+      hipLaunchKernelGGL(k_udep_poll, dim3(grid), dim3(SWG), 0, 0, n, d_hn, d_ron, (int)P.k, nv, ep, er, d_lev, d_err,
+                         spin);
+      e = hipGetLastError();
+    }
+    int herr = 1;
+    if (e == hipSuccess) e = hipMemcpy(&herr, d_err, sizeof(int), hipMemcpyDeviceToHost);
+    done = e == hipSuccess && herr == 0;
+    if (e == hipSuccess && !done) e = hipMemset(d_lev, 0, n * sizeof(int32_t));
+  }
   int32_t* d_R = nullptr;
   int32_t* d_E = nullptr;
-  if (nv && e == hipSuccess) {
+  if (nv && e == hipSuccess && !done) {
     d_R = hb.get<int32_t>((size_t)n);
     d_E = hb.get<int32_t>((size_t)(n * P.k));
     e = hb.err;
@@ -453,7 +526,7 @@ int device_udep_levels(const Prep& P, const std::vector<int64_t>& hptr, const st
     }
   }
   int64_t h0 = 0;  // first height of the pending run of narrow heights
-  for (int64_t h = 0; h <= nh && e == hipSuccess; ++h) {
+  for (int64_t h = 0; h <= nh && e == hipSuccess && !done; ++h) {
     const int64_t c = h < nh ? hptr[h + 1] - hptr[h] : 0;
     const bool narrow = h < nh && d_E && c <= SEQ_ROWS && c * P.k <= (int64_t)SEQ_WG * SEQ_PP;
     if (narrow) continue;

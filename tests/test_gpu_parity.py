@@ -1280,6 +1280,30 @@ def test_device_niv_equals_host_recursion(px, case, monkeypatch):
     assert info["nnz_niv"] == int((want[False] >= 0).sum()) and info["nnz_niv_up"] == int((want[True] >= 0).sum())
 
 
+@pytest.mark.parametrize("case", ["cfg0", "grid", "er_d4"])
+def test_device_levels_persistent_and_by_height(px, case, monkeypatch):
+    """The U-dependency levels computed on the device in one persistent launch (the
+    default), height by height (POSETX_UDEP=heights), and height by height after every
+    wait of the persistent launch gave up (a spin limit of 0) all equal the host's, for
+    dense rows and for sparse rows, both maps."""
+    monkeypatch.setenv("POSETX_PREP", "device")
+    p, flags = {"cfg0": (W.chain_poset(3000, 16, 4, seed=8), 0), "grid": (W.grid_poset(120, 24), 0),
+                "er_d4": (W.er_dag(2000, 4, seed=9), px.PX_BUILD_SPARSE_NIV)}[case]
+    planted = p.chain_of is not None
+    co = p.chain_of if planted else None
+    cp = p.chain_pos if planted else None
+    Hh = px.poset_build(p.n, p.indptr, p.indices, co, cp, flags=flags | px.PX_BUILD_HOST_ONLY)
+    for env in ({}, {"POSETX_UDEP": "heights"}, {"POSETX_FLOW_SPIN": "0"}):
+        for key in ("POSETX_UDEP", "POSETX_FLOW_SPIN"):
+            monkeypatch.delenv(key, raising=False)
+        for key, val in env.items():
+            monkeypatch.setenv(key, val)
+        D = px.poset_build(p.n, p.indptr, p.indices, co, cp, flags=flags, device=0)
+        assert D.info_dict()["niv_device_rounds"] >= 1
+        for up in (False, True):
+            assert np.array_equal(D.levels(up), Hh.levels(up)), (case, env, up)
+
+
 @pytest.mark.parametrize("case", ["er_d4", "er_d6", "example", "lattice", "cfg0", "random", "antichain", "chain"])
 def test_device_sparse_niv_rows_match_oracle(px, case, monkeypatch):
     """The sparse niv rows merged on the device, height after height (both maps),
