@@ -36,10 +36,12 @@ int device_niv_sparse(Prep& P, const int64_t* indptr, const int32_t* indices, co
                       int32_t* out_rows[2], std::string& msg);
 
 // The U-dependency levels of one map on the current device from the map's
-// device rows (dense [n, k] nv, or sparse ep / er), height after height
-// (hptr / hnodes: runs of narrow heights in one single-workgroup launch, wider
-// heights a launch each), copied into lev.  Returns PX_OK, or -1 on any HIP
-// error (the caller computes them on the host instead).
+// device rows (dense [n, k] nv, or sparse ep / er), copied into lev: in one
+// persistent launch over the rows in height order (hnodes) polling the levels
+// they read; if a wait gives up there (or POSETX_UDEP=heights), height after
+// height (hptr: runs of narrow heights in one single-workgroup launch, wider
+// heights a launch each).  Returns PX_OK, or -1 on any HIP error (the caller
+// computes them on the host instead).
 int device_udep_levels(const Prep& P, const std::vector<int64_t>& hptr, const std::vector<int32_t>& hnodes,
                        const int32_t* nv, const int64_t* ep, const int32_t* er, std::vector<int32_t>& lev);
 

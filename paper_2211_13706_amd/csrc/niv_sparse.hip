@@ -483,8 +483,6 @@ int device_udep_levels(const Prep& P, const std::vector<int64_t>& hptr, const st
   int32_t* d_lev = hb.get<int32_t>((size_t)n);
   hipError_t e = hb.err;
   if (e == hipSuccess) e = hipMemset(d_lev, 0, n * sizeof(int32_t));
-  // dense rows: heights of at most SEQ_ROWS rows and SEQ_WG * SEQ_PP entries go
-  // in runs through k_udep_levels_seq, wider ones (and sparse rows) one launch each
   const int64_t nh = (int64_t)hptr.size() - 1;
   // all levels in one persistent launch, unless POSETX_UDEP=heights; if a wait
   // gave up there, height by height below
@@ -513,6 +511,9 @@ int device_udep_levels(const Prep& P, const std::vector<int64_t>& hptr, const st
     done = e == hipSuccess && herr == 0;
     if (e == hipSuccess && !done) e = hipMemset(d_lev, 0, n * sizeof(int32_t));
   }
+  // height by height: for dense rows, heights of at most SEQ_ROWS rows and
+  // SEQ_WG * SEQ_PP entries go in runs through k_udep_levels_seq, wider ones
+  // (and sparse rows) one launch each
   int32_t* d_R = nullptr;
   int32_t* d_E = nullptr;
   if (nv && e == hipSuccess && !done) {
