@@ -546,6 +546,55 @@ def test_level_poll_solve_marks_and_fallback(px, spin, monkeypatch):
         assert torch.equal(x, y)
 
 
+def test_persistent_solves_in_a_hip_graph(px):
+    """The persistent Möbius solves captured in one HIP graph (after px_reserve; tol < 0,
+    so no host synchronisation): the int64 solve by runs, and the float32 (refined) and
+    float64 row-by-row solves.  Each of three replays, with new inputs copied in and eager
+    work between them, equals the eager calls bit for bit, and int64 equals the oracle."""
+    import torch
+    p = W.chain_poset(3000, 16, 3, seed=81)
+    R = O.reachability(p.n, p.indptr, p.indices)
+    P = build(px, p)
+    assert P.info["run_chunks"] > 0
+    B = 8
+    gi = torch.empty(p.n, B, dtype=torch.int64, device=dev())
+    g32 = torch.empty(p.n, B, dtype=torch.float32, device=dev())
+    g64 = torch.empty(p.n, B, dtype=torch.float64, device=dev())
+    oi, o32, o64 = torch.empty_like(gi), torch.empty_like(g32), torch.empty_like(g64)
+    for dt in (torch.int64, torch.float32, torch.float64):
+        P.reserve(dt, B)
+
+    def calls():
+        px.mobius(P, gi, out=oi)
+        px.mobius(P, g32, out=o32, tol=-1)
+        px.mobius_adjoint(P, g64, out=o64, tol=-1)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm-up off the capture
+        calls()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        calls()
+    for rep in range(3):
+        print(f"graph replay {rep}", flush=True)
+        f = W.functions(p.n, B, "int", seed=82 + rep, lo=-1000, hi=1000)
+        gi.copy_(T(O.zeta(R, f)))
+        g32.copy_(T(O.zeta(R, f).astype(np.float32)))
+        g64.copy_(T(O.zeta_adjoint(R, f).astype(np.float64)))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = (oi.clone(), o32.clone(), o64.clone())
+        calls()  # eager, between the replays
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], oi) and torch.equal(got[1], o32) and torch.equal(got[2], o64)
+        assert np.array_equal(H(got[0]), f)
+        assert rel(H(got[2]), f) <= 1e-9
+
+
 @pytest.mark.parametrize("wait", ["deps", "level", "rows", "values"])
 @pytest.mark.parametrize("B", [8, 64])
 def test_int64_persistent_solve_fallback(px, B, wait, monkeypatch):
