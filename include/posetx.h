@@ -55,7 +55,12 @@
  *    dense solves row by row where the average level fits the resident
  *    wavefronts (POSETX_LEVEL_POLL=0: a launch per level, =2: always
  *    persistent); floating-point results do not depend on the choice.
- *    POSETX_FLOW_SPIN bounds the polls of each wait.
+ *    POSETX_FLOW_SPIN bounds the polls of each wait.  A persistent launch
+ *    sizes its grid to what the device holds resident; other work running
+ *    at the same time on other streams (another persistent solve, say) can
+ *    keep some of its workgroups from starting, and its waits then give up
+ *    after about 2 s and the fallback solves again: results stay the same,
+ *    only slower.
  *    Posets with sparse niv rows (PX_BUILD_SPARSE_NIV, or more than 256
  *    chains) take the chain scan, a gather over their rows and a level solve
  *    with a launch per level, rows of more than 256 entries summed in fixed
