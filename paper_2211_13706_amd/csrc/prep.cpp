@@ -391,8 +391,22 @@ int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const i
   if (P.sparse && hook_rc == PX_OK) {
     // rows computed elsewhere
   } else if (!P.sparse && hook_rc == PX_OK) {
-    for (size_t i = 0; i < P.niv.size(); ++i) P.nnz_niv += P.niv[i] >= 0;
-    for (size_t i = 0; i < P.niv_up.size(); ++i) P.nnz_niv_up += P.niv_up[i] >= 0;
+    // finite entries of the maps computed elsewhere, counted on a team of threads
+    // (n = 2^23, k = 32: two maps of 2^28 entries)
+    const unsigned hc = std::thread::hardware_concurrency();
+    Workers team(P.niv.size() >= ((size_t)1 << 24) ? (int)std::max(1u, std::min(16u, hc ? hc : 1u)) : 1);
+    for (int m = 0; m < 2; ++m) {
+      const std::vector<int32_t>& v = m ? P.niv_up : P.niv;
+      std::vector<int64_t> part(team.size(), 0);
+      team.run((int64_t)v.size(), (int64_t)1 << 20, [&](int t, int64_t lo, int64_t hi) {
+        int64_t c = 0;
+        for (int64_t i = lo; i < hi; ++i) c += v[(size_t)i] >= 0;
+        part[t] += c;
+      });
+      int64_t total = 0;
+      for (int64_t c : part) total += c;
+      (m ? P.nnz_niv_up : P.nnz_niv) = total;
+    }
   } else if (!P.sparse) {
     // Rows of one height (the longest path down to a leaf; up to a root for
     // the dual map) depend only on lower ones, so a team of threads takes the

@@ -1429,6 +1429,10 @@ def test_device_niv_config1_and_host_switch(px, cfg1, monkeypatch):
     Hh = _host_only(px, p, True)
     assert np.array_equal(D.niv(), Hh.niv())
     assert np.array_equal(D.niv(True), Hh.niv(True))
+    # finite entries counted on host threads from the device maps
+    di, hi = D.info_dict(), Hh.info_dict()
+    assert di["nnz_niv"] == hi["nnz_niv"] == int((Hh.niv() >= 0).sum())
+    assert di["nnz_niv_up"] == hi["nnz_niv_up"]
     monkeypatch.setenv("POSETX_PREP", "host")
     assert build(px, W.chain_poset(2000, 16, 4, seed=0)).info_dict()["niv_device_rounds"] == 0
     monkeypatch.delenv("POSETX_PREP")
