@@ -2401,12 +2401,15 @@ __device__ inline bool await_range(const int* __restrict__ fl, int a, int b, con
 // The int64 solve by runs in one persistent launch: a dataflow over the chunks
 // instead of one launch per level.  Workgroup b takes the (chunk, column
 // block) items b, b + G, b + 2G, ... of the level-ordered list, G workgroups
-// being at most what the device holds resident at once.  Before it reads a row
-// of Y a row group waits for that row's ready flag (one per row and column
-// block), set by the chunk that wrote it (LEVEL: instead one wavefront waits
-// for the done flags of every chunk of the level below, which are contiguous;
-// those chunks waited for their own level below, so all lower levels are then
-// complete).  A chunk reads only rows of lower levels, which come earlier in
+// being at most what the device holds resident at once.  VALS (the default):
+// a row group reads the rows of Y it needs until none holds the unwritten mark
+// (await_vals; rows 0 .. n-1 of Y are filled with it before the launch).
+// Otherwise, before it reads a row of Y a row group waits for that row's
+// ready flag (one per row and column block), set by the chunk that wrote it
+// (LEVEL: instead one wavefront waits for the done flags of every chunk of the
+// level below, which are contiguous; those chunks waited for their own level
+// below, so all lower levels are then complete; DEPS: for the done flags of
+// the chunks it reads from).  A chunk reads only rows of lower levels, which come earlier in
 // the list; a workgroup takes its items in order, so the unfinished item of
 // lowest index always has every row it reads finished, and with all
 // workgroups resident every wait ends.  Everything that does not depend on Y
@@ -2421,8 +2424,9 @@ __device__ inline bool await_range(const int* __restrict__ fl, int a, int b, con
 // Waits are bounded (spin_limit polls, and 2 s of real time).  A workgroup
 // that gives up (also when some workgroups could not be resident) stores the
 // error word and stops, and so does every waiter that sees it; then
-// k_usolve_flow_fix recomputes the whole solve in one workgroup.  flags: ncb * (n + 1) ints and err, cleared
-// before the launch.
+// k_usolve_flow_fix recomputes the whole solve in one workgroup.  flags:
+// ncb * (n + 1) ints (chunk flags: ncb * nchunks) and err, cleared before the
+// launch; the row flags are set in VALS mode too, for values equal to the mark.
 template <typename TY, int CW, int WAIT>
 __global__ __launch_bounds__(WG) void k_usolve_flow(DevPoset d, const int32_t* __restrict__ nv,
                                                     const int4* __restrict__ chunks, int nchunks,
