@@ -359,3 +359,15 @@ def test_concurrent_builds_match_serial(px):
         for up in (False, True):
             assert np.array_equal(P.niv(up), S.niv(up))
             assert np.array_equal(P.levels(up), S.levels(up))
+
+
+def test_concurrent_builds_report_a_failing_spec(px):
+    """A spec that cannot be built (here a 2-cycle) among concurrent builds raises its own
+    error (PX_ECYCLE) from poset_build_many; the other specs build as usual alone."""
+    posets = W.batched_posets(6, seed=62, nmin=200, nmax=800)
+    specs = [(q.n, q.indptr, q.indices, None, None) for q in posets]
+    specs.insert(3, (2, np.array([0, 1, 2], dtype=np.int64), np.array([1, 0], dtype=np.int32), None, None))
+    assert _err(px, lambda: px.poset_build_many(specs, flags=px.PX_BUILD_HOST_ONLY, threads=4)) == "PX_ECYCLE"
+    good = specs[:3] + specs[4:]
+    assert [P.n for P in px.poset_build_many(good, flags=px.PX_BUILD_HOST_ONLY, threads=4)] == [q.n for q in posets]
+    assert px.poset_build_many([], flags=px.PX_BUILD_HOST_ONLY) == []
