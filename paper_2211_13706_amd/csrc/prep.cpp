@@ -134,17 +134,50 @@ void by_height(int64_t n, const int64_t* indptr, const int32_t* indices, const s
   for (int64_t x = 0; x < n; ++x) hnodes[fill[height[x]]++] = (int32_t)x;
 }
 
-// Parent lists (reversed CSR) of the child lists.
+// Parent lists (reversed CSR) of the child lists, each in ascending parent
+// order.  Graphs of 2^22 edges or more (or any, with POSETX_PREP_THREADS)
+// split the targets into ranges, one per thread: every thread reads all edges
+// in order and handles those into its range, so the lists are the same for any
+// thread count.
 void reverse_csr(int64_t n, const int64_t* indptr, const int32_t* indices, std::vector<int64_t>& rptr,
                  std::vector<int32_t>& ridx) {
   rptr.assign(n + 1, 0);
   const int64_t m = indptr[n];
-  for (int64_t e = 0; e < m; ++e) rptr[indices[e] + 1]++;
+  const unsigned hc = std::thread::hardware_concurrency();
+  int nt = m >= ((int64_t)1 << 22) ? (int)std::max(1u, std::min(16u, hc ? hc : 1u)) : 1;
+  if (const char* v = std::getenv("POSETX_PREP_THREADS"))
+    if (std::atoi(v) >= 1) nt = std::min(std::atoi(v), 64);
+  auto each = [&](const std::function<void(int32_t, int32_t)>& fn) {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+      th.emplace_back([&, t] { fn((int32_t)(n * t / nt), (int32_t)(n * (t + 1) / nt)); });
+    for (auto& x : th) x.join();
+  };
+  if (nt == 1) {
+    for (int64_t e = 0; e < m; ++e) rptr[indices[e] + 1]++;
+  } else {
+    each([&](int32_t v0, int32_t v1) {
+      for (int64_t e = 0; e < m; ++e) {
+        const int32_t v = indices[e];
+        if (v >= v0 && v < v1) rptr[v + 1]++;
+      }
+    });
+  }
   for (int64_t i = 0; i < n; ++i) rptr[i + 1] += rptr[i];
   ridx.resize(m);
   std::vector<int64_t> fill(rptr.begin(), rptr.end() - 1);
-  for (int64_t u = 0; u < n; ++u)
-    for (int64_t e = indptr[u]; e < indptr[u + 1]; ++e) ridx[fill[indices[e]]++] = (int32_t)u;
+  if (nt == 1) {
+    for (int64_t u = 0; u < n; ++u)
+      for (int64_t e = indptr[u]; e < indptr[u + 1]; ++e) ridx[fill[indices[e]]++] = (int32_t)u;
+  } else {
+    each([&](int32_t v0, int32_t v1) {
+      for (int64_t u = 0; u < n; ++u)
+        for (int64_t e = indptr[u]; e < indptr[u + 1]; ++e) {
+          const int32_t v = indices[e];
+          if (v >= v0 && v < v1) ridx[fill[v]++] = (int32_t)u;
+        }
+    });
+  }
 }
 
 // Maximum matching of the bipartite graph with an edge (v1, u2) per DAG edge v -> u
@@ -275,25 +308,36 @@ int preprocess(int64_t n, const int64_t* indptr, const int32_t* indices, const i
   reverse_csr(n, indptr, indices, rptr, ridx);
   std::vector<int32_t> order;
   order.reserve(n);
-  std::vector<int64_t> outdeg(n);
+  // a node's remaining out-degree and its longest path down to a leaf (Mirsky
+  // level) side by side: one cache line per visit of a parent
+  struct alignas(16) KahnState {
+    int64_t deg;
+    int32_t mir;
+  };
+  std::vector<KahnState> st(n);
   for (int64_t u = 0; u < n; ++u) {
-    outdeg[u] = indptr[u + 1] - indptr[u];
-    if (outdeg[u] == 0) order.push_back((int32_t)u);
+    st[u] = {indptr[u + 1] - indptr[u], 0};
+    if (st[u].deg == 0) order.push_back((int32_t)u);
   }
-  std::vector<int32_t> mir(n, 0);  // longest path down to a leaf (Mirsky level)
   for (size_t h = 0; h < order.size(); ++h) {
-    int32_t v = order[h];
+    const int32_t v = order[h];
+    const int32_t up = st[v].mir + 1;
     for (int64_t e = rptr[v]; e < rptr[v + 1]; ++e) {
-      int32_t p = ridx[e];
-      mir[p] = std::max(mir[p], mir[v] + 1);
-      if (--outdeg[p] == 0) order.push_back(p);
+      KahnState& s = st[ridx[e]];
+      s.mir = std::max(s.mir, up);
+      if (--s.deg == 0) order.push_back(ridx[e]);
     }
   }
   if ((int64_t)order.size() != n) {
     msg = "the graph has a directed cycle";
     return PX_ECYCLE;
   }
-  for (int64_t v = 0; v < n; ++v) P.mirsky = std::max<int64_t>(P.mirsky, mir[v] + 1);
+  std::vector<int32_t> mir(n);
+  for (int64_t v = 0; v < n; ++v) {
+    mir[v] = st[v].mir;
+    P.mirsky = std::max<int64_t>(P.mirsky, mir[v] + 1);
+  }
+  std::vector<KahnState>().swap(st);
   double t1 = now_s();
   P.t_validate = t1 - t0;
 

@@ -242,9 +242,9 @@ def test_config1_preprocessing_scale(px):
 
 
 def test_threaded_recursion_matches_serial(px, monkeypatch):
-    """The host recursion merges the rows of one height on several threads; the maps and
-    level schedules do not depend on the thread count (sparse rows of a wide ER DAG, and
-    dense rows with the chain check)."""
+    """The host recursion merges the rows of one height on several threads, and the parent
+    lists are built on several threads; the maps and level schedules do not depend on the
+    thread count (sparse rows of a wide ER DAG, and dense rows with the chain check)."""
     for p, planted in ((W.er_dag(1 << 15, 4, seed=9), False), (W.chain_poset(1 << 15, 16, 3, seed=9), True)):
         got = []
         for t in ("1", "6"):
